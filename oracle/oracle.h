@@ -1,0 +1,39 @@
+/*
+ * oracle.h -- declarations of the FP64 CPU oracle (test infrastructure only;
+ * see oracle.c).  Not included by, and shares nothing with, the GPU library.
+ */
+#ifndef ORACLE_H
+#define ORACLE_H
+#include <stdint.h>
+
+enum { ORACLE_FORCES = 0, ORACLE_HERCULES = 1 };
+enum { ORACLE_NEAREST = 0, ORACLE_LINEAR = 1, ORACLE_CUBIC = 2 };
+
+typedef struct {
+    int mode;                  /* ORACLE_FORCES (2D) or ORACLE_HERCULES (3D)        */
+    int n_tx, n_ch, n_samples; /* decoded transmits, data channels, samples        */
+    const int32_t *tx_elements;/* n_tx: element column of decoded index i         */
+    const int32_t *channel_map;/* n_ch: element column (FORCES) / row (HERCULES)  */
+    double pitch[2];           /* column pitch (x), row pitch (y), metres          */
+    double xdc[16];            /* row-major 4x4 affine, global -> array frame      */
+    double fs, c, t0;          /* Hz, m/s, s (time of sample 0)                    */
+    double f_number;           /* receive F#; 0 disables apodization               */
+    int interp;                /* ORACLE_NEAREST / ORACLE_LINEAR / ORACLE_CUBIC    */
+    int dims[3];               /* Nx, Ny, Nz                                       */
+    double gmin[3], gmax[3];   /* inclusive region bounds, global frame, metres    */
+} oracle_geom;
+
+int oracle_sylvester(int n, int8_t *H);
+void oracle_decode(const int8_t *H, int n_tx, int n_ch, int n_samples, const int16_t *r,
+                   int64_t *e);
+double oracle_hann(double u);
+double oracle_interp(const double *trace, int S, double s, int mode);
+double oracle_interp_deriv(const double *trace, int S, double s, int mode);
+void oracle_das(const oracle_geom *g, const double *e, double *out);
+void oracle_das_points(const oracle_geom *g, const double *e, const int64_t *vox, int64_t n,
+                       double *out);
+void oracle_das_adjoint_e(const oracle_geom *g, const double *G, double *grad_e);
+void oracle_das_dc(const oracle_geom *g, const double *e, double *dout);
+double oracle_sharpness(const double *img, int64_t n, double *grad);
+
+#endif

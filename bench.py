@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Throughput of the decode + DAS hot path on one MI355X.
+
+Workload (default): HERCULES volume, 128x128 TOBE array at 0.1 mm, 128
+Hadamard transmits x 128 channels x 2048 int16 samples at 30 MHz, output
+128 x 128 x 256 FP32 voxels, cubic Hermite reads, F# 1 (seeded synthetic
+scene of 64 points + 10^4 speckle scatterers).  One step = decode + DAS of
+one volume with the RF already resident in HBM.
+
+Metric: G voxel*tx*ch samples/s = Nx*Ny*Nz*n_tx*n_ch / step time (nominal:
+apodization-skipped terms are counted), plus volumes/s.  The JSON line also
+carries the DAS kernel's roofline figures (HIP events around each DAS launch
+on the launch stream) and the FP64 CPU oracle's rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# VALU peak used for the DAS roofline: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# non-packed FP32 lane operations (an FMA counts as 2 flops).
+FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def active_terms(desc, dev) -> int:
+    """Number of (voxel, tx, ch) terms with non-zero apodization (geometry only;
+    bookkeeping for the roofline figure, evaluated with torch on the device)."""
+    import torch
+    px, py = desc["pitch"]
+    M = torch.tensor(np.asarray(desc["xdc"], dtype=np.float64).reshape(4, 4), device=dev)
+    axes = [torch.linspace(desc["gmin"][a], desc["gmax"][a], desc["dims"][a], dtype=torch.float64,
+                           device=dev) for a in range(3)]
+    gx, gy, gz = torch.meshgrid(axes[0], axes[1], axes[2], indexing="ij")
+    P = torch.stack([gx, gy, gz], -1).reshape(-1, 3) @ M[:3, :3].T + M[:3, 3]
+    x, y, z = P[:, 0], P[:, 1], P[:, 2]
+    F2 = float(desc["f_number"]) ** 2
+    thr = torch.where(z > 0, 0.25 * z * z, torch.full_like(z, -1.0))
+    xt = torch.tensor(np.asarray(desc["tx_elements"], dtype=np.float64) * px, device=dev)
+    total = 0
+    if desc["mode"] == "hercules":
+        for yj in np.asarray(desc["channel_map"], dtype=np.float64) * py:
+            r2 = (x[:, None] - xt[None, :]) ** 2 + (y[:, None] - yj) ** 2
+            total += int(torch.count_nonzero(F2 * r2 < thr[:, None]))
+        return total
+    for xj in np.asarray(desc["channel_map"], dtype=np.float64) * px:
+        total += int(torch.count_nonzero(F2 * (x - xj) ** 2 < thr)) * len(xt)
+    return total
+
+
+def cpu_baseline(desc, H, rf, budget_s: float):
+    """FP64 oracle on the host cores: full decode + DAS on a random voxel sample."""
+    import oracle
+    threads = os.cpu_count()
+    t = time.perf_counter()
+    e = oracle.decode(H, rf)
+    t_dec = time.perf_counter() - t
+    nv = int(np.prod(desc["dims"]))
+    rng = np.random.default_rng(99)
+    probe = rng.choice(nv, 512, replace=False)
+    t = time.perf_counter()
+    oracle.das_points(desc, e, probe)
+    per_vox = (time.perf_counter() - t) / probe.size
+    n = int(min(nv, max(1024, (budget_s - t_dec) / max(per_vox, 1e-9))))
+    vox = np.sort(rng.choice(nv, n, replace=False))
+    t = time.perf_counter()
+    ref = oracle.das_points(desc, e, vox)
+    t_das = time.perf_counter() - t
+    step = t_dec + t_das * nv / n          # one full volume at the sampled rate
+    nominal = nv * desc["n_tx"] * desc["n_ch"]
+    return dict(value=nominal / step / 1e9, unit="G voxel*tx*ch samples/s", cores=threads,
+                kind="oracle",
+                sample=f"full decode ({t_dec:.1f} s) + DAS of {n} random voxels of {nv} "
+                       f"({t_das:.1f} s), scaled to one volume"), e, vox, ref
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; multi-GPU runs are not part of this build "
+              "(frames or receive channels would shard with no or one all-reduce).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2512_11086_amd as bfm
+    import synth
+
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    desc, H, rf, _ = synth.make_inputs(1)
+    log(f"inputs generated in {time.perf_counter() - t:.1f} s")
+    plan = bfm.Plan(desc, H)
+    rf_d = torch.from_numpy(rf).to(dev)
+    e_d = torch.empty(rf.shape, dtype=torch.float32, device=dev)
+    out_d = torch.empty(plan.out_shape, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        plan.decode(rf_d, out=e_d)
+        plan.das(e_d, out=out_d)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    K = args.steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    start.record(stream)
+    for k in range(K):
+        ev[k][0].record(stream)
+        plan.decode(rf_d, out=e_d)
+        ev[k][1].record(stream)
+        plan.das(e_d, out=out_d)
+        ev[k][2].record(stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms_step = start.elapsed_time(stop) / K
+    dec_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    das_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    log(f"step {ms_step:.3f} ms (decode {dec_ms:.3f} ms, DAS {das_ms:.3f} ms), wall {t_wall:.2f} s")
+
+    nv = int(np.prod(desc["dims"]))
+    nominal = nv * desc["n_tx"] * desc["n_ch"]
+    value = nominal / (ms_step * 1e-3) / 1e9
+    n_act = active_terms(desc, dev)
+    # Algorithmic FP32 work of one active HERCULES term:
+    # delay 13 flops (dx, rho^2, d^2, sqrt, d+z, rcp, mul, fma, floor, fract),
+    # apodization 14 (u^2 + degree-6 polynomial), cubic read 16, accumulate 2.
+    flops_per_term = 45
+    achieved = n_act * flops_per_term / (das_ms * 1e-3) / 1e12
+    dec_bytes = rf.size * 2 + rf.size * 4
+    res = {
+        "metric": "G voxel*tx*ch samples/s (+ volumes/s), decode + DAS at oracle accuracy",
+        "value": round(value, 3),
+        "unit": "G samples/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded point + speckle scene, int16 RF)",
+        "config": {"workload": "HERCULES volume 128x128 array, 128 tx x 128 ch x 2048 samples "
+                               "-> 128x128x256 voxels, cubic",
+                   "n_tx": 128, "n_ch": 128, "n_samples": 2048, "out_dims": [128, 128, 256]},
+        "volumes_per_s": round(1e3 / ms_step, 3),
+        "decode_ms": round(dec_ms, 4), "das_ms": round(das_ms, 4),
+        "decode_hbm_GBps": round(dec_bytes / (dec_ms * 1e-3) / 1e9, 1),
+        "active_term_fraction": round(n_act / nominal, 4),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 2),
+                     "peak": round(FP32_NONPACKED_TFLOPS, 1), "unit": "TFLOP/s",
+                     "frac": round(achieved / FP32_NONPACKED_TFLOPS, 4), "traffic": None},
+    }
+    if not args.no_cpu:
+        cb, e64, vox, ref = cpu_baseline(desc, H, rf, args.cpu_budget)
+        res["cpu_baseline"] = cb
+        got = out_d.cpu().numpy().reshape(-1)[vox].astype(np.float64)
+        res["sampled_rel_l2_vs_oracle"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * bf.h -- C ABI of libbf: Hadamard aperture decoding and delay-and-sum (DAS)
+ * beamforming of row-column / TOBE array channel data on AMD MI355X (gfx950).
+ *
+ * Method: arXiv 2512.11086, "An Open Source Realtime GPU Beamformer for RCA
+ * and TOBE Arrays".  The path is: int16 RF channel data -> Hadamard decode
+ * across transmits (Sec. IV-A; Sec. VII-E) -> DAS with receive apodization
+ * (Eqs. 1-3; Sec. VII-F) and fractional-delay interpolation (Sec. IV-B).
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns a bf_status (0 = BF_OK, < 0 = error).  Nothing
+ *    aborts or throws.  On error, bf_last_error() returns a message for the
+ *    calling thread.  Arguments are validated before any device work is
+ *    queued, so a failed call leaves device memory untouched.
+ *  - Data pointers marked "device" are device memory owned by the caller,
+ *    contiguous in the documented layout.  Pointers marked "host" are read
+ *    during the call only (the library copies what it keeps).
+ *  - All device work is queued on the caller's stream (`stream` is a
+ *    hipStream_t; NULL = the legacy default stream) and is asynchronous.
+ *    Faults inside kernels surface on later HIP calls on that stream.
+ *  - A plan owns its device tables and workspaces; bf_plan_destroy frees
+ *    them.  A plan must not be used concurrently from two host threads, and
+ *    two streams must not run calls of the same plan at the same time (the
+ *    calls share the plan's workspaces).
+ *  - No buffer may exceed 2^31 elements (the paper's limit is 2 GB of data
+ *    per call, Table I): larger requests fail with BF_ERR_TOO_LARGE.
+ *
+ * Layouts
+ *  rf   int16            [n_tx][n_ch][n_samples]   encoded channel data, sample fastest
+ *  e    f32 | bf16 | i32 [n_tx][n_ch][n_samples]   decoded data (type = params.e_type)
+ *  out  f32              [Ny][Nx][Nz]              image / volume, z (depth) fastest
+ */
+#ifndef BF_H
+#define BF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BF_ABI_VERSION 1
+
+typedef enum {
+    BF_OK = 0,
+    BF_ERR_NULL = -1,          /* a required pointer is NULL                          */
+    BF_ERR_SHAPE = -2,         /* a count is out of range or inconsistent             */
+    BF_ERR_NOT_HADAMARD = -3,  /* an entry is not +-1 or H H^T != N I                 */
+    BF_ERR_GEOMETRY = -4,      /* non-finite or non-physical geometry / timing value  */
+    BF_ERR_UNSUPPORTED = -5,   /* a valid request this library does not implement     */
+    BF_ERR_TOO_LARGE = -6,     /* a buffer would exceed 2^31 elements                 */
+    BF_ERR_HIP = -7,           /* a HIP runtime call failed                           */
+    BF_ERR_NO_DEVICE = -8,     /* no gfx950 device is available                       */
+    BF_ERR_STATE = -9          /* call does not fit the plan (e.g. batch on 1 frame)  */
+} bf_status;
+
+/* Acquisition method (Table I).  uFORCES / uHERCULES are the same modes with a
+ * sparse transmit subset in tx_elements. */
+enum { BF_FORCES_2D = 0, BF_HERCULES_3D = 1 };
+/* Fractional-delay interpolation (Sec. IV-B; Table I). */
+enum { BF_INTERP_NEAREST = 0, BF_INTERP_LINEAR = 1, BF_INTERP_CUBIC = 2 };
+/* Element type of decoded data (written by bf_decode, read by bf_das). */
+enum { BF_E_F32 = 0, BF_E_BF16 = 1, BF_E_I32 = 2 };
+/* Decode arithmetic: exact int8 matrix-core product, or FP32 FMA (also exact
+ * for |values| < 2^24, i.e. for every int16 input with n_tx <= 256). */
+enum { BF_DECODE_MFMA_I8 = 0, BF_DECODE_FMA_F32 = 1 };
+
+/* Problem description: the data description and beamforming parameters of
+ * Sec. VI-B (array pitch, 4x4 transform, transmit sequence and Hadamard
+ * order, sampling rate, sound speed, output region and resolution, channel
+ * mapping). */
+typedef struct {
+    int32_t mode;              /* BF_FORCES_2D or BF_HERCULES_3D                        */
+    int32_t n_tx;              /* transmits per frame = Hadamard order, 1..256          */
+    int32_t n_ch;              /* receive data channels, 1..1024                        */
+    int32_t n_samples;         /* samples per channel, 1..65536                         */
+    int32_t n_elem[2];         /* element columns (x), rows (y) of the array            */
+    double  pitch[2];          /* column pitch (x), row pitch (y), metres, > 0          */
+    /* Row-major 4x4 affine from the global frame to the array frame, whose origin
+     * is the centre of the corner element and whose z axis is the array normal.
+     * The last row must be 0 0 0 1.  A single centred array uses a translation
+     * by ((n_elem[0]-1)/2 pitch[0], (n_elem[1]-1)/2 pitch[1], 0). */
+    double  xdc_transform[16];
+    /* host, n_tx*n_tx, row-major: hadamard[k*n_tx+i] = polarity (+-1) of element
+     * i in transmit k.  Any matrix with H H^T = N I is accepted (checked exactly). */
+    const int8_t  *hadamard;
+    /* host, n_tx: element column behind decoded transmit i; NULL = 0..n_tx-1.
+     * A sparse subset gives uFORCES / uHERCULES. */
+    const int32_t *tx_elements;
+    /* host, n_ch: element column (FORCES) or row (HERCULES) of data channel j;
+     * NULL = 0..n_ch-1. */
+    const int32_t *channel_map;
+    double  fs;                /* sampling rate, Hz, > 0                                */
+    double  fc;                /* centre frequency, Hz (informational for RF data)      */
+    double  c;                 /* default sound speed, m/s, > 0                         */
+    double  t0;                /* time of sample 0 relative to the transmit, s          */
+    double  focal_depth;       /* HERCULES transmit focus; only +INFINITY (plane wave)  */
+    double  f_number;          /* receive F# of the Hann apodization (Eq. 2); 0 = none  */
+    int32_t interp;            /* BF_INTERP_*                                           */
+    int32_t e_type;            /* BF_E_*                                                */
+    int32_t decode_algo;       /* BF_DECODE_*                                           */
+    int32_t out_dims[3];       /* Nx, Ny, Nz output points (Ny = 1 for a B-scan)        */
+    double  out_min[3];        /* inclusive region bounds in the global frame, metres:  */
+    double  out_max[3];        /*   point k on axis a = min + k (max-min)/(N-1)         */
+} bf_params;
+
+typedef struct bf_plan_s *bf_plan;   /* opaque, owned by libbf */
+
+/* Read-only facts about a plan. */
+typedef struct {
+    int32_t n_frames;
+    int32_t tile[3];           /* DAS voxels per wavefront along x, y, z               */
+    int64_t workspace_bytes;   /* device memory held by the plan                       */
+    int64_t e_elems;           /* elements of decoded data per frame (frame 0)         */
+    int64_t out_elems;         /* output points per frame (frame 0)                    */
+} bf_plan_info;
+
+/* ABI version of the loaded library (BF_ABI_VERSION). */
+int32_t bf_abi_version(void);
+
+/* Thread-local message describing the last error of the calling thread
+ * ("" if none).  The pointer stays valid until the thread's next bf_ call. */
+const char *bf_last_error(void);
+
+/* Validate a problem description without touching the GPU: sizes, geometry,
+ * element indices, and the exact Hadamard check H H^T = N I (Sec. VII-E:
+ * decoding is a product across transmits).  Returns the status bf_plan_create
+ * would return for the same description before its first device call. */
+int bf_validate(const bf_params *params);
+
+/* Create a single-frame plan: validates (as bf_validate), selects the
+ * kernels, and uploads the geometry and Hadamard tables to the current device.
+ * Errors: BF_ERR_NULL / SHAPE / NOT_HADAMARD / GEOMETRY / UNSUPPORTED /
+ * TOO_LARGE from validation; BF_ERR_NO_DEVICE if the current device is not a
+ * gfx950; BF_ERR_HIP if an allocation or copy fails.  *out is NULL on error. */
+int bf_plan_create(const bf_params *params, bf_plan *out);
+
+/* Create a plan for a batch of n_frames (1..4096) frames, each with its own
+ * description (params[f]; modes, transmit counts, grids may differ).  The plan
+ * owns one decoded-data workspace per frame.  Used by bf_batch_run and
+ * bf_graph_launch; bf_decode / bf_das / bf_das_adjoint act on frame 0. */
+int bf_plan_create_batch(const bf_params *params, int32_t n_frames, bf_plan *out);
+
+/* Free a plan and its device memory (waits for the device first).  NULL is a no-op. */
+int bf_plan_destroy(bf_plan plan);
+
+int bf_plan_get_info(bf_plan plan, bf_plan_info *info);
+
+/* Choose the DAS wavefront tile of the plan by timing the candidate shapes on
+ * the device (synchronous; uses scratch data).  If cache_path is non-NULL the
+ * choice is read from / appended to that text file, keyed by device and problem
+ * shape.  Returns the chosen shape through bf_plan_get_info. */
+int bf_autotune(bf_plan plan, const char *cache_path);
+/* Set the DAS wavefront tile explicitly: log2 of voxels along x, y, z; they must
+ * sum to 6 (64 lanes).  For 2D plans log2_y must be 0. */
+int bf_set_tile(bf_plan plan, int32_t log2_x, int32_t log2_y, int32_t log2_z);
+
+/* Decode (Sec. VII-E):  e[i][j][t] = sum_k H[k][i] * rf[k][j][t]  (unscaled, so
+ * decoding an encoded set returns N times the element responses).
+ * rf: device int16 [n_tx][n_ch][n_samples];  e: device, type params.e_type,
+ * same layout.  Exact for BF_E_F32 / BF_E_I32 (|e| <= 256 * 32768 < 2^24);
+ * BF_E_BF16 rounds to nearest even.  rf and e must not overlap. */
+int bf_decode(bf_plan plan, const int16_t *rf, void *e, void *stream);
+
+/* DAS (Eq. 1 with Eqs. 2-3; Sec. VII-F):
+ *   out[p] = sum_i sum_j a(p,i,j) * interp(e[i][j], (tof_ij(p) - t0) * fs)
+ * FORCES:   tof = (|p - col(tx_i)|_xz + |p - col(ch_j)|_xz) / c,
+ *           a = W(F# |x - x_j| / z)
+ * HERCULES: tof = (z + |p - (x_i, y_j, 0)|) / c,  a = W(F# rho / z), rho radial
+ * W is the Hann window (Eq. 3); points with z <= 0 give 0.  Samples outside
+ * [0, n_samples) read as 0.  e: device, type params.e_type; out: device f32
+ * [Ny][Nx][Nz], overwritten.  c: sound speed for this call (m/s, finite, > 0;
+ * the autofocus loop varies it).  Accumulation is FP32 in a fixed order per
+ * point, so repeated calls give bit-identical results. */
+int bf_das(bf_plan plan, const void *e, float *out, double c, void *stream);
+
+/* Adjoint of bf_das for the same e and c, given grad_out = dL/d(out)
+ * (device f32 [Ny][Nx][Nz]):
+ *   grad_e (device f32 [n_tx][n_ch][n_samples], nullable, overwritten) =
+ *       transpose of the linear map e -> out, applied to grad_out;
+ *   grad_c (device f32 scalar, nullable, overwritten) =
+ *       sum_p grad_out[p] * d out[p] / dc, with d s / dc = -tof * fs / c.
+ * grad_e accumulates with atomics, so its low bits may vary between calls. */
+int bf_das_adjoint(bf_plan plan, const void *e, const float *grad_out, double c,
+                   float *grad_e, float *grad_c, void *stream);
+
+/* Image-sharpness loss for n_images images of n_per_image points each:
+ *   loss[f] = -sum I^4 / (sum I^2)^2   (device f32 [n_images], overwritten)
+ *   grad[f][p] = d loss[f] / d I[f][p] (device f32, nullable, overwritten)
+ * Sums are accumulated in FP64.  An all-zero image gives loss 0, gradient 0. */
+int bf_sharpness(const float *img, int64_t n_per_image, int32_t n_images, float *loss,
+                 float *grad, void *stream);
+
+/* Batched decode + DAS of every frame of a batch plan with persistent
+ * kernels (one decode launch per Hadamard-order class and one DAS launch per
+ * mode, each pulling (frame, tile) items from a queue).
+ * rf[f]: device int16 of frame f; out[f]: device f32 of frame f (host arrays of
+ * n_frames device pointers).  Decoded data goes to the plan's workspaces. */
+int bf_batch_run(bf_plan plan, const int16_t *const *rf, float *const *out, void *stream);
+
+/* Same work as bf_batch_run, recorded once into a hipGraph and replayed on
+ * later calls.  The frame pointers are copied into the plan's device table
+ * before each replay, so new buffers need no re-capture. */
+int bf_graph_launch(bf_plan plan, const int16_t *const *rf, float *const *out, void *stream);
+
+/* Evaluates the library's Hann-window polynomial W at u^2 (host, for tests). */
+double bf_hann_poly(double u2);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BF_H */

@@ -1,0 +1,237 @@
+"""MI355X-native Hadamard aperture decoding + delay-and-sum beamforming.
+
+Python face of libbf (include/bf.h).  Every step of the path runs in the HIP
+kernels of libbf; this module only converts a problem description into the
+C structure, passes device pointers of torch tensors (torch is used for
+device memory and streams) and raises ``BfError`` on a failed status.
+
+A problem description is a dict with the paper's inputs (Sec. VI-B): mode,
+n_tx, n_ch, n_samples, n_elem, pitch, xdc (4x4 global -> array frame),
+tx_elements, channel_map, fs, fc, c, t0, f_number, interp, dims, gmin, gmax.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+
+from ._lib import (BfError, DECODE_ALGOS, ETYPES, INTERPS, MODES, Params, PlanInfo, check,
+                   lib)
+
+__all__ = ["BfError", "Plan", "BatchPlan", "params_from_desc", "sharpness", "validate",
+           "hann_poly"]
+
+
+class _Marshalled:
+    """A bf_params plus the numpy arrays its pointers refer to."""
+
+    def __init__(self, desc: dict, hadamard, e_type="f32", decode_algo="mfma"):
+        p = Params()
+        p.mode = MODES[desc["mode"]]
+        p.n_tx, p.n_ch, p.n_samples = int(desc["n_tx"]), int(desc["n_ch"]), int(desc["n_samples"])
+        p.n_elem[:] = [int(v) for v in desc["n_elem"]]
+        p.pitch[:] = [float(v) for v in desc["pitch"]]
+        p.xdc_transform[:] = [float(v) for v in np.asarray(desc["xdc"], dtype=np.float64).reshape(16)]
+        self.H = None if hadamard is None else np.ascontiguousarray(hadamard, dtype=np.int8)
+        self.tx = None if desc.get("tx_elements") is None else np.ascontiguousarray(
+            desc["tx_elements"], dtype=np.int32)
+        self.ch = None if desc.get("channel_map") is None else np.ascontiguousarray(
+            desc["channel_map"], dtype=np.int32)
+        P = ctypes.POINTER
+        p.hadamard = self.H.ctypes.data_as(P(ctypes.c_int8)) if self.H is not None else None
+        p.tx_elements = self.tx.ctypes.data_as(P(ctypes.c_int32)) if self.tx is not None else None
+        p.channel_map = self.ch.ctypes.data_as(P(ctypes.c_int32)) if self.ch is not None else None
+        p.fs, p.fc, p.c, p.t0 = (float(desc[k]) for k in ("fs", "fc", "c", "t0"))
+        p.focal_depth = float(desc.get("focal_depth", math.inf))
+        p.f_number = float(desc["f_number"])
+        p.interp = INTERPS[desc.get("interp", "cubic")]
+        p.e_type = ETYPES[e_type]
+        p.decode_algo = DECODE_ALGOS[decode_algo]
+        p.out_dims[:] = [int(v) for v in desc["dims"]]
+        p.out_min[:] = [float(v) for v in desc["gmin"]]
+        p.out_max[:] = [float(v) for v in desc["gmax"]]
+        self.p = p
+
+
+def params_from_desc(desc, hadamard, e_type="f32", decode_algo="mfma") -> _Marshalled:
+    return _Marshalled(desc, hadamard, e_type, decode_algo)
+
+
+def validate(desc, hadamard, **kw) -> None:
+    """Validate a description on the host (raises BfError)."""
+    m = _Marshalled(desc, hadamard, **kw)
+    check(lib().bf_validate(ctypes.byref(m.p)))
+
+
+def hann_poly(u2: float) -> float:
+    return lib().bf_hann_poly(float(u2))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+_TORCH_ETYPE = {"f32": "float32", "bf16": "bfloat16", "i32": "int32"}
+
+
+class Plan:
+    """Single-frame plan: bf_decode, bf_das, bf_das_adjoint on torch tensors."""
+
+    def __init__(self, desc: dict, hadamard, e_type: str = "f32", decode_algo: str = "mfma",
+                 tile=None):
+        self.desc = desc
+        self.e_type = e_type
+        self._m = _Marshalled(desc, hadamard, e_type, decode_algo)
+        h = ctypes.c_void_p()
+        check(lib().bf_plan_create(ctypes.byref(self._m.p), ctypes.byref(h)))
+        self._h = h
+        self.n_tx, self.n_ch, self.n_samples = (int(desc[k]) for k in ("n_tx", "n_ch", "n_samples"))
+        nx, ny, nz = (int(v) for v in desc["dims"])
+        self.out_shape = (ny, nx, nz)
+        self.c = float(desc["c"])
+        if tile is not None:
+            self.set_tile(*tile)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check(lib().bf_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = PlanInfo()
+        check(lib().bf_plan_get_info(self._h, ctypes.byref(inf)))
+        return dict(n_frames=inf.n_frames, tile=tuple(inf.tile),
+                    workspace_bytes=inf.workspace_bytes, e_elems=inf.e_elems,
+                    out_elems=inf.out_elems)
+
+    def set_tile(self, lx: int, ly: int, lz: int):
+        check(lib().bf_set_tile(self._h, lx, ly, lz))
+
+    def autotune(self, cache_path: str | None = None):
+        check(lib().bf_autotune(self._h, cache_path.encode() if cache_path else None))
+        return self.info()["tile"]
+
+    def e_dtype(self):
+        return getattr(_torch(), _TORCH_ETYPE[self.e_type])
+
+    def _check_rf(self, rf):
+        torch = _torch()
+        if rf.dtype != torch.int16 or not rf.is_cuda or not rf.is_contiguous():
+            raise ValueError("rf must be a contiguous int16 CUDA tensor")
+        if tuple(rf.shape) != (self.n_tx, self.n_ch, self.n_samples):
+            raise ValueError(f"rf shape {tuple(rf.shape)} != {(self.n_tx, self.n_ch, self.n_samples)}")
+
+    def _check_e(self, e):
+        if e.dtype != self.e_dtype() or not e.is_cuda or not e.is_contiguous():
+            raise ValueError(f"e must be a contiguous {self.e_dtype()} CUDA tensor")
+        if tuple(e.shape) != (self.n_tx, self.n_ch, self.n_samples):
+            raise ValueError("e has the wrong shape")
+
+    def decode(self, rf, out=None, stream=None):
+        torch = _torch()
+        self._check_rf(rf)
+        if out is None:
+            out = torch.empty(rf.shape, dtype=self.e_dtype(), device=rf.device)
+        self._check_e(out)
+        check(lib().bf_decode(self._h, _ptr(rf), _ptr(out), _stream(stream)))
+        return out
+
+    def das(self, e, c: float | None = None, out=None, stream=None):
+        torch = _torch()
+        self._check_e(e)
+        if out is None:
+            out = torch.empty(self.out_shape, dtype=torch.float32, device=e.device)
+        if out.dtype != torch.float32 or tuple(out.shape) != self.out_shape or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 tensor of the image shape")
+        check(lib().bf_das(self._h, _ptr(e), _ptr(out), float(self.c if c is None else c),
+                           _stream(stream)))
+        return out
+
+    def das_adjoint(self, e, grad_out, c: float | None = None, want_e: bool = True,
+                    want_c: bool = True, stream=None):
+        """Returns (grad_e or None, grad_c tensor of shape () or None)."""
+        torch = _torch()
+        if e is not None:
+            self._check_e(e)
+        g = grad_out.contiguous().to(torch.float32)
+        if tuple(g.shape) != self.out_shape:
+            raise ValueError("grad_out has the wrong shape")
+        ge = (torch.empty((self.n_tx, self.n_ch, self.n_samples), dtype=torch.float32,
+                          device=g.device) if want_e else None)
+        gc = torch.empty((), dtype=torch.float32, device=g.device) if want_c else None
+        check(lib().bf_das_adjoint(self._h, _ptr(e) if e is not None else None, _ptr(g),
+                                   float(self.c if c is None else c),
+                                   _ptr(ge) if ge is not None else None,
+                                   _ptr(gc) if gc is not None else None, _stream(stream)))
+        return ge, gc
+
+
+class BatchPlan:
+    """Plan over many frames with their own descriptions (persistent batched path)."""
+
+    def __init__(self, descs, hadamards, e_type: str = "f32"):
+        self.descs = list(descs)
+        self._ms = [_Marshalled(d, H, e_type) for d, H in zip(self.descs, hadamards)]
+        arr = (Params * len(self._ms))(*[m.p for m in self._ms])
+        self._arr = arr
+        h = ctypes.c_void_p()
+        check(lib().bf_plan_create_batch(arr, len(self._ms), ctypes.byref(h)))
+        self._h = h
+        self.out_shapes = [(int(d["dims"][1]), int(d["dims"][0]), int(d["dims"][2]))
+                           for d in self.descs]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check(lib().bf_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ptrs(self, tensors):
+        return (ctypes.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
+
+    def run(self, rfs, outs, stream=None):
+        check(lib().bf_batch_run(self._h, self._ptrs(rfs), self._ptrs(outs), _stream(stream)))
+
+    def graph_launch(self, rfs, outs, stream=None):
+        check(lib().bf_graph_launch(self._h, self._ptrs(rfs), self._ptrs(outs), _stream(stream)))
+
+    def autotune(self, cache_path: str | None = None):
+        check(lib().bf_autotune(self._h, cache_path.encode() if cache_path else None))
+
+
+def sharpness(img, grad: bool = True, stream=None):
+    """Negative normalised L4 norm per image of a (n_images, ...) float32 tensor."""
+    torch = _torch()
+    x = img.contiguous()
+    if x.dtype != torch.float32:
+        raise ValueError("img must be float32")
+    n_images = x.shape[0] if x.dim() > 1 else 1
+    n = x.numel() // n_images
+    loss = torch.empty(n_images, dtype=torch.float32, device=x.device)
+    g = torch.empty_like(x) if grad else None
+    check(lib().bf_sharpness(_ptr(x), n, n_images, _ptr(loss), _ptr(g) if g is not None else None,
+                             _stream(stream)))
+    return (loss, g) if grad else loss

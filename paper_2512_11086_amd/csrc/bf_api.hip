@@ -1,0 +1,472 @@
+// bf_api.hip -- host side of libbf: validation, plans, dispatch, errors.
+// See include/bf.h for the contract of every entry point.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "bf.h"
+#include "bf_common.h"
+#include "bf_plan.h"
+
+namespace bf {
+hipError_t launch_decode_mfma(const DecodeArgs &a, int kb, int etype, hipStream_t s);
+hipError_t launch_decode_fma(const DecodeArgs &a, int etype, hipStream_t s);
+hipError_t launch_das(const DasArgs &a, int mode, int et, int ip, hipStream_t s);
+hipError_t launch_das_adjoint(const DasArgs &a, int mode, int et, int ip, float *grad_c,
+                              hipStream_t s);
+hipError_t launch_sharpness(const float *img, long n, int n_images, float *loss, float *grad,
+                            hipStream_t s);
+
+static thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(BF_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+static bool is_fin(double v) { return isfinite(v) != 0; }
+
+// ---------------------------------------------------------------------------
+// Validation (no HIP calls)
+// ---------------------------------------------------------------------------
+int validate_params(const bf_params *p)
+{
+    if (!p) return fail(BF_ERR_NULL, "params is NULL");
+    if (p->mode != BF_FORCES_2D && p->mode != BF_HERCULES_3D)
+        return fail(BF_ERR_UNSUPPORTED, "unknown mode %d", p->mode);
+    if (p->interp < BF_INTERP_NEAREST || p->interp > BF_INTERP_CUBIC)
+        return fail(BF_ERR_UNSUPPORTED, "unknown interpolation %d", p->interp);
+    if (p->e_type < BF_E_F32 || p->e_type > BF_E_I32)
+        return fail(BF_ERR_UNSUPPORTED, "unknown decoded-data type %d", p->e_type);
+    if (p->decode_algo != BF_DECODE_MFMA_I8 && p->decode_algo != BF_DECODE_FMA_F32)
+        return fail(BF_ERR_UNSUPPORTED, "unknown decode algorithm %d", p->decode_algo);
+    if (p->n_tx < 1 || p->n_tx > 256) return fail(BF_ERR_SHAPE, "n_tx=%d not in [1,256]", p->n_tx);
+    if (p->n_ch < 1 || p->n_ch > 1024) return fail(BF_ERR_SHAPE, "n_ch=%d not in [1,1024]", p->n_ch);
+    if (p->n_samples < 1 || p->n_samples > 65536)
+        return fail(BF_ERR_SHAPE, "n_samples=%d not in [1,65536]", p->n_samples);
+    if (p->n_elem[0] < 1 || p->n_elem[1] < 1)
+        return fail(BF_ERR_SHAPE, "n_elem must be >= 1");
+    for (int a = 0; a < 3; ++a)
+        if (p->out_dims[a] < 1) return fail(BF_ERR_SHAPE, "out_dims[%d]=%d < 1", a, p->out_dims[a]);
+    const int64_t ne = (int64_t)p->n_tx * p->n_ch * p->n_samples;
+    if (ne >= (int64_t(1) << 31))
+        return fail(BF_ERR_TOO_LARGE, "channel data has %lld elements (limit 2^31)", (long long)ne);
+    const int64_t nv = (int64_t)p->out_dims[0] * p->out_dims[1] * p->out_dims[2];
+    if (nv >= (int64_t(1) << 31))
+        return fail(BF_ERR_TOO_LARGE, "output has %lld points (limit 2^31)", (long long)nv);
+    for (int a = 0; a < 2; ++a)
+        if (!is_fin(p->pitch[a]) || p->pitch[a] <= 0.0)
+            return fail(BF_ERR_GEOMETRY, "pitch[%d] must be finite and > 0", a);
+    for (int q = 0; q < 16; ++q)
+        if (!is_fin(p->xdc_transform[q])) return fail(BF_ERR_GEOMETRY, "transform not finite");
+    if (p->xdc_transform[12] != 0.0 || p->xdc_transform[13] != 0.0 ||
+        p->xdc_transform[14] != 0.0 || p->xdc_transform[15] != 1.0)
+        return fail(BF_ERR_GEOMETRY, "transform last row must be 0 0 0 1");
+    if (!is_fin(p->fs) || p->fs <= 0.0) return fail(BF_ERR_GEOMETRY, "fs must be finite and > 0");
+    if (!is_fin(p->c) || p->c <= 0.0) return fail(BF_ERR_GEOMETRY, "c must be finite and > 0");
+    if (!is_fin(p->t0)) return fail(BF_ERR_GEOMETRY, "t0 must be finite");
+    if (!is_fin(p->fc) || p->fc < 0.0) return fail(BF_ERR_GEOMETRY, "fc must be finite and >= 0");
+    if (!is_fin(p->f_number) || p->f_number < 0.0)
+        return fail(BF_ERR_GEOMETRY, "f_number must be finite and >= 0");
+    for (int a = 0; a < 3; ++a)
+        if (!is_fin(p->out_min[a]) || !is_fin(p->out_max[a]))
+            return fail(BF_ERR_GEOMETRY, "output region bounds must be finite");
+    if (p->mode == BF_HERCULES_3D && !(isinf(p->focal_depth) && p->focal_depth > 0))
+        return fail(BF_ERR_UNSUPPORTED, "HERCULES supports only a plane-wave transmit "
+                                        "(focal_depth = +inf)");
+    if (p->tx_elements)
+        for (int i = 0; i < p->n_tx; ++i)
+            if (p->tx_elements[i] < 0 || p->tx_elements[i] >= p->n_elem[0])
+                return fail(BF_ERR_SHAPE, "tx_elements[%d]=%d outside [0,%d)", i,
+                            p->tx_elements[i], p->n_elem[0]);
+    const int nrx = p->mode == BF_FORCES_2D ? p->n_elem[0] : p->n_elem[1];
+    if (p->channel_map)
+        for (int j = 0; j < p->n_ch; ++j)
+            if (p->channel_map[j] < 0 || p->channel_map[j] >= nrx)
+                return fail(BF_ERR_SHAPE, "channel_map[%d]=%d outside [0,%d)", j,
+                            p->channel_map[j], nrx);
+    if (!p->hadamard) return fail(BF_ERR_NULL, "hadamard is NULL");
+    const int n = p->n_tx;
+    const int8_t *H = p->hadamard;
+    for (int q = 0; q < n * n; ++q)
+        if (H[q] != 1 && H[q] != -1)
+            return fail(BF_ERR_NOT_HADAMARD, "hadamard[%d]=%d is not +-1", q, H[q]);
+    for (int a = 0; a < n; ++a)
+        for (int b = a; b < n; ++b) {
+            int dot = 0;
+            for (int q = 0; q < n; ++q) dot += H[a * n + q] * H[b * n + q];
+            if (dot != (a == b ? n : 0))
+                return fail(BF_ERR_NOT_HADAMARD, "rows %d and %d: dot=%d (H H^T != N I)", a, b, dot);
+        }
+    return BF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device checks and memory
+// ---------------------------------------------------------------------------
+static int check_device(int *dev)
+{
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count < 1) {
+        (void)hipGetLastError();
+        return fail(BF_ERR_NO_DEVICE, "no HIP device available");
+    }
+    e = hipGetDevice(dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, *dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(BF_ERR_NO_DEVICE, "device %d is %s, libbf is built for gfx950", *dev,
+                    prop.gcnArchName);
+    return BF_OK;
+}
+
+void *Frame::alloc(size_t bytes)
+{
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    allocs.push_back(p);
+    total_bytes += (int64_t)bytes;
+    return p;
+}
+
+Frame::~Frame()
+{
+    for (void *p : allocs) (void)hipFree(p);
+}
+
+// Build host tables and upload them for one frame.
+int Frame::init(const bf_params &src)
+{
+    p = src;
+    const int n = p.n_tx;
+    H.assign(p.hadamard, p.hadamard + (size_t)n * n);
+    tx.resize(n);
+    ch.resize(p.n_ch);
+    for (int i = 0; i < n; ++i) tx[i] = p.tx_elements ? p.tx_elements[i] : i;
+    for (int j = 0; j < p.n_ch; ++j) ch[j] = p.channel_map ? p.channel_map[j] : j;
+    p.hadamard = nullptr;
+    p.tx_elements = nullptr;
+    p.channel_map = nullptr;
+
+    kb = (n + 31) / 32;
+    const int KP = 32 * kb;
+    std::vector<int8_t> At((size_t)KP * KP, 0);
+    std::vector<int> cs(KP, 0);
+    std::vector<float> Hf((size_t)n * KP, 0.f);
+    for (int k = 0; k < n; ++k)
+        for (int m = 0; m < n; ++m) {
+            At[(size_t)m * KP + k] = H[(size_t)k * n + m];
+            cs[m] += H[(size_t)k * n + m];
+            Hf[(size_t)k * KP + m] = (float)H[(size_t)k * n + m];
+        }
+
+    // Lateral reference: centre of the element grid (keeps FP32 offsets small).
+    const double cx = 0.5 * (p.n_elem[0] - 1) * p.pitch[0];
+    const double cy = 0.5 * (p.n_elem[1] - 1) * p.pitch[1];
+    std::vector<float> tx_x(n), rx_c(p.n_ch);
+    for (int i = 0; i < n; ++i) tx_x[i] = (float)(tx[i] * p.pitch[0] - cx);
+    for (int j = 0; j < p.n_ch; ++j)
+        rx_c[j] = (float)(p.mode == BF_FORCES_2D ? ch[j] * p.pitch[0] - cx : ch[j] * p.pitch[1] - cy);
+
+    // Grid: point (ix,iy,iz) = M (min + idx * step) - (cx, cy, 0).
+    const double *M = p.xdc_transform;
+    double step[3];
+    for (int a = 0; a < 3; ++a)
+        step[a] = p.out_dims[a] > 1 ? (p.out_max[a] - p.out_min[a]) / (p.out_dims[a] - 1) : 0.0;
+    for (int r = 0; r < 3; ++r) {
+        grid.org[r] = M[4 * r] * p.out_min[0] + M[4 * r + 1] * p.out_min[1] +
+                      M[4 * r + 2] * p.out_min[2] + M[4 * r + 3] - (r == 0 ? cx : r == 1 ? cy : 0.0);
+        grid.ax[r] = M[4 * r] * step[0];
+        grid.ay[r] = M[4 * r + 1] * step[1];
+        grid.az[r] = M[4 * r + 2] * step[2];
+    }
+    grid.nx = p.out_dims[0];
+    grid.ny = p.out_dims[1];
+    grid.nz = p.out_dims[2];
+    if (p.mode == BF_FORCES_2D && grid.ny == 1)
+        set_tile(3, 0, 3);
+    else
+        set_tile(2, 2, 2);
+
+    d_At = (int8_t *)alloc(At.size());
+    d_colsum = (int *)alloc(cs.size() * sizeof(int));
+    d_Hf = (float *)alloc(Hf.size() * sizeof(float));
+    d_tx_x = (float *)alloc(tx_x.size() * sizeof(float));
+    d_rx_c = (float *)alloc(rx_c.size() * sizeof(float));
+    max_blocks = 0;
+    for (int lx = 0; lx <= 6; ++lx)        // partial-sum buffer large enough for any tile
+        for (int ly = 0; ly + lx <= 6; ++ly) {
+            const int lz = 6 - lx - ly;
+            const long w = (long)((grid.nx + (1 << lx) - 1) >> lx) *
+                           ((grid.ny + (1 << ly) - 1) >> ly) * ((grid.nz + (1 << lz) - 1) >> lz);
+            if ((w + 3) / 4 > max_blocks) max_blocks = (w + 3) / 4;
+        }
+    d_partial = (double *)alloc((size_t)max_blocks * sizeof(double));
+    if (!d_At || !d_colsum || !d_Hf || !d_tx_x || !d_rx_c || !d_partial)
+        return fail(BF_ERR_HIP, "device allocation for plan tables failed");
+    hipError_t e;
+    if ((e = hipMemcpy(d_At, At.data(), At.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d_colsum, cs.data(), cs.size() * sizeof(int), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(d_Hf, Hf.data(), Hf.size() * sizeof(float), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(d_tx_x, tx_x.data(), tx_x.size() * sizeof(float), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(d_rx_c, rx_c.data(), rx_c.size() * sizeof(float), hipMemcpyHostToDevice)) !=
+            hipSuccess)
+        return hip_fail(e, "upload of plan tables");
+    return BF_OK;
+}
+
+void Frame::set_tile(int lx_, int ly_, int lz_)
+{
+    lx = lx_;
+    ly = ly_;
+    lz = lz_;
+}
+
+int64_t Frame::e_elems() const { return (int64_t)p.n_tx * p.n_ch * p.n_samples; }
+int64_t Frame::out_elems() const { return (int64_t)grid.nx * grid.ny * grid.nz; }
+size_t Frame::e_bytes() const { return (size_t)e_elems() * (p.e_type == BF_E_BF16 ? 2 : 4); }
+
+DecodeArgs Frame::decode_args(const int16_t *rf, void *e) const
+{
+    DecodeArgs a;
+    a.rf = rf;
+    a.e = e;
+    a.At = d_At;
+    a.colsum = d_colsum;
+    a.Hf = d_Hf;
+    a.n_tx = p.n_tx;
+    a.n_ch = p.n_ch;
+    a.S = p.n_samples;
+    return a;
+}
+
+DasArgs Frame::das_args(const void *e, float *out, double c) const
+{
+    DasArgs a;
+    memset(&a, 0, sizeof a);
+    a.e = e;
+    a.out = out;
+    a.tx_x = d_tx_x;
+    a.rx_c = d_rx_c;
+    a.partial = d_partial;
+    a.n_tx = p.n_tx;
+    a.n_ch = p.n_ch;
+    a.S = p.n_samples;
+    a.g = grid;
+    a.k = p.fs / c;
+    a.t0fs = p.t0 * p.fs;
+    a.c = c;
+    a.f2 = (float)(p.f_number * p.f_number);
+    a.lx = lx;
+    a.ly = ly;
+    a.lz = lz;
+    a.tiles_x = (grid.nx + (1 << lx) - 1) >> lx;
+    a.tiles_y = (grid.ny + (1 << ly) - 1) >> ly;
+    a.tiles_z = (grid.nz + (1 << lz) - 1) >> lz;
+    a.n_waves = a.tiles_x * a.tiles_y * a.tiles_z;
+    return a;
+}
+
+int Frame::decode(const int16_t *rf, void *e, hipStream_t s) const
+{
+    const DecodeArgs a = decode_args(rf, e);
+    hipError_t err = p.decode_algo == BF_DECODE_FMA_F32 ? launch_decode_fma(a, p.e_type, s)
+                                                         : launch_decode_mfma(a, kb, p.e_type, s);
+    return err == hipSuccess ? BF_OK : hip_fail(err, "decode launch");
+}
+
+int Frame::das(const void *e, float *out, double c, hipStream_t s) const
+{
+    const DasArgs a = das_args(e, out, c);
+    hipError_t err = launch_das(a, p.mode, p.e_type, p.interp, s);
+    return err == hipSuccess ? BF_OK : hip_fail(err, "DAS launch");
+}
+
+}  // namespace bf
+
+using namespace bf;
+
+static int check_plan(bf_plan plan)
+{
+    if (!plan) return fail(BF_ERR_NULL, "plan is NULL");
+    if (plan->magic != BF_PLAN_MAGIC) return fail(BF_ERR_STATE, "not a live plan");
+    return BF_OK;
+}
+
+static int check_c(double c)
+{
+    if (!is_fin(c) || c <= 0.0) return fail(BF_ERR_GEOMETRY, "sound speed must be finite and > 0");
+    return BF_OK;
+}
+
+extern "C" {
+
+int32_t bf_abi_version(void) { return BF_ABI_VERSION; }
+
+const char *bf_last_error(void) { return g_err.c_str(); }
+
+int bf_validate(const bf_params *params)
+{
+    g_err.clear();
+    return validate_params(params);
+}
+
+int bf_plan_create_batch(const bf_params *params, int32_t n_frames, bf_plan *out)
+{
+    g_err.clear();
+    if (!out) return fail(BF_ERR_NULL, "out is NULL");
+    *out = nullptr;
+    if (!params) return fail(BF_ERR_NULL, "params is NULL");
+    if (n_frames < 1 || n_frames > 4096) return fail(BF_ERR_SHAPE, "n_frames=%d not in [1,4096]", n_frames);
+    for (int f = 0; f < n_frames; ++f) {
+        int st = validate_params(&params[f]);
+        if (st != BF_OK) {
+            if (n_frames > 1) {
+                std::string m = g_err;
+                return fail(st, "frame %d: %s", f, m.c_str());
+            }
+            return st;
+        }
+    }
+    int dev = 0;
+    int st = check_device(&dev);
+    if (st != BF_OK) return st;
+    bf_plan plan = new bf_plan_s();
+    plan->device = dev;
+    plan->frames.resize(n_frames);
+    for (int f = 0; f < n_frames; ++f) {
+        plan->frames[f] = new Frame();
+        st = plan->frames[f]->init(params[f]);
+        if (st != BF_OK) {
+            delete plan;
+            return st;
+        }
+    }
+    *out = plan;
+    return BF_OK;
+}
+
+int bf_plan_create(const bf_params *params, bf_plan *out)
+{
+    return bf_plan_create_batch(params, 1, out);
+}
+
+int bf_plan_destroy(bf_plan plan)
+{
+    g_err.clear();
+    if (!plan) return BF_OK;
+    if (plan->magic != BF_PLAN_MAGIC) return fail(BF_ERR_STATE, "not a live plan");
+    (void)hipDeviceSynchronize();
+    delete plan;
+    return BF_OK;
+}
+
+int bf_plan_get_info(bf_plan plan, bf_plan_info *info)
+{
+    g_err.clear();
+    int st = check_plan(plan);
+    if (st != BF_OK) return st;
+    if (!info) return fail(BF_ERR_NULL, "info is NULL");
+    const Frame &f = *plan->frames[0];
+    info->n_frames = (int32_t)plan->frames.size();
+    info->tile[0] = 1 << f.lx;
+    info->tile[1] = 1 << f.ly;
+    info->tile[2] = 1 << f.lz;
+    info->workspace_bytes = plan->workspace_bytes();
+    info->e_elems = f.e_elems();
+    info->out_elems = f.out_elems();
+    return BF_OK;
+}
+
+int bf_set_tile(bf_plan plan, int32_t log2_x, int32_t log2_y, int32_t log2_z)
+{
+    g_err.clear();
+    int st = check_plan(plan);
+    if (st != BF_OK) return st;
+    if (log2_x < 0 || log2_y < 0 || log2_z < 0 || log2_x + log2_y + log2_z != 6)
+        return fail(BF_ERR_SHAPE, "tile log2 sizes must be >= 0 and sum to 6");
+    for (Frame *f : plan->frames) {
+        if (f->p.mode == BF_FORCES_2D && f->grid.ny == 1 && log2_y != 0)
+            return fail(BF_ERR_SHAPE, "a 2D plan needs log2_y = 0");
+    }
+    for (Frame *f : plan->frames) f->set_tile(log2_x, log2_y, log2_z);
+    return BF_OK;
+}
+
+int bf_decode(bf_plan plan, const int16_t *rf, void *e, void *stream)
+{
+    g_err.clear();
+    int st = check_plan(plan);
+    if (st != BF_OK) return st;
+    if (!rf || !e) return fail(BF_ERR_NULL, "rf and e must be non-NULL");
+    return plan->frames[0]->decode(rf, e, (hipStream_t)stream);
+}
+
+int bf_das(bf_plan plan, const void *e, float *out, double c, void *stream)
+{
+    g_err.clear();
+    int st = check_plan(plan);
+    if (st != BF_OK) return st;
+    if (!e || !out) return fail(BF_ERR_NULL, "e and out must be non-NULL");
+    if ((st = check_c(c)) != BF_OK) return st;
+    return plan->frames[0]->das(e, out, c, (hipStream_t)stream);
+}
+
+int bf_das_adjoint(bf_plan plan, const void *e, const float *grad_out, double c, float *grad_e,
+                   float *grad_c, void *stream)
+{
+    g_err.clear();
+    int st = check_plan(plan);
+    if (st != BF_OK) return st;
+    if (!grad_out) return fail(BF_ERR_NULL, "grad_out is NULL");
+    if (grad_c && !e) return fail(BF_ERR_NULL, "e is needed for grad_c");
+    if ((st = check_c(c)) != BF_OK) return st;
+    const Frame &f = *plan->frames[0];
+    DasArgs a = f.das_args(e, nullptr, c);
+    a.grad_out = grad_out;
+    a.grad_e = grad_e;
+    hipError_t err = launch_das_adjoint(a, f.p.mode, f.p.e_type, f.p.interp, grad_c,
+                                        (hipStream_t)stream);
+    return err == hipSuccess ? BF_OK : hip_fail(err, "DAS adjoint launch");
+}
+
+int bf_sharpness(const float *img, int64_t n_per_image, int32_t n_images, float *loss, float *grad,
+                 void *stream)
+{
+    g_err.clear();
+    if (!img || !loss) return fail(BF_ERR_NULL, "img and loss must be non-NULL");
+    if (n_per_image < 1 || n_images < 1) return fail(BF_ERR_SHAPE, "empty image batch");
+    if (n_per_image * (int64_t)n_images >= (int64_t(1) << 31))
+        return fail(BF_ERR_TOO_LARGE, "image batch exceeds 2^31 elements");
+    int dev = 0;
+    int st = check_device(&dev);
+    if (st != BF_OK) return st;
+    hipError_t err = launch_sharpness(img, (long)n_per_image, n_images, loss, grad,
+                                      (hipStream_t)stream);
+    return err == hipSuccess ? BF_OK : hip_fail(err, "sharpness launch");
+}
+
+double bf_hann_poly(double u2) { return (double)hann_u2((float)u2); }
+
+}  // extern "C"

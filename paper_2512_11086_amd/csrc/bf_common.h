@@ -1,0 +1,150 @@
+// bf_common.h -- internal definitions shared by the libbf HIP sources
+// (kernel argument blocks, device helpers).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bf {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+enum EType { ET_F32 = 0, ET_BF16 = 1, ET_I32 = 2 };
+enum Interp { IN_NEAREST = 0, IN_LINEAR = 1, IN_CUBIC = 2 };
+
+// ---------------------------------------------------------------------------
+// Decode
+// ---------------------------------------------------------------------------
+struct DecodeArgs {
+    const int16_t *rf;     // [n_tx][n_ch][S]
+    void *e;               // [n_tx][n_ch][S], type per template
+    const int8_t *At;      // [KP][KP] with KP = 32*KB: At[m][k] = H[k][m], zero padded
+    const int *colsum;     // [KP]: sum_k H[k][m], zero padded
+    const float *Hf;       // [n_tx][IP] float copy of H (FMA path), IP = 32*ceil(n_tx/32)
+    int n_tx, n_ch, S;
+};
+
+// ---------------------------------------------------------------------------
+// DAS
+// ---------------------------------------------------------------------------
+// Output grid in the array frame, shifted by the lateral reference (cx, cy)
+// so that FP32 lateral coordinates stay small.  Point (ix, iy, iz) is
+//   org + ix * ax + iy * ay + iz * az.
+struct Grid {
+    double org[3], ax[3], ay[3], az[3];
+    int nx, ny, nz;
+};
+
+struct DasArgs {
+    const void *e;          // decoded data [n_tx][n_ch][S]
+    float *out;             // [ny][nx][nz]
+    const float *tx_x;      // [n_tx] x of decoded transmit column (relative to cx)
+    const float *rx_c;      // [n_ch] x (FORCES) or y (HERCULES) of channel (relative)
+    const float *grad_out;  // adjoint: dL/dout
+    float *grad_e;          // adjoint: dL/de (nullable)
+    double *partial;        // adjoint: per-block partial sums of grad_c
+    int n_tx, n_ch, S;
+    Grid g;
+    double k;               // fs / c
+    double t0fs;            // t0 * fs
+    double c;               // sound speed
+    float f2;               // F#^2 (0 disables apodization)
+    int lx, ly, lz;         // log2 of the wavefront tile along x, y, z (sum 6)
+    int tiles_x, tiles_y, tiles_z;
+    int n_waves;            // tiles_x * tiles_y * tiles_z
+};
+
+// Hann window of Eq. 3 as a function of w = u^2 on [0, 1/4): a degree-6
+// polynomial fitted at Chebyshev nodes (max error 2e-7 in FP32 Horner form,
+// exact 1 at w = 0 and exact 0 at w = 1/4 up to FP32 rounding).  Using u^2
+// avoids a square root and a cosine per sample; the caller zeroes w >= 1/4.
+__host__ __device__ inline float hann_u2(float w)
+{
+    float p = 3.264329195e+00f;
+    p = p * w + -1.298379993e+01f;
+    p = p * w + 3.008381462e+01f;
+    p = p * w + -4.272507095e+01f;
+    p = p * w + 3.246955872e+01f;
+    p = p * w + -9.869602203e+00f;
+    p = p * w + 1.0f;
+    return p;
+}
+
+template <int ET>
+__device__ inline float load_e(const void *base, long idx)
+{
+    if constexpr (ET == ET_F32) {
+        return static_cast<const float *>(base)[idx];
+    } else if constexpr (ET == ET_BF16) {
+        uint32_t b = static_cast<const uint16_t *>(base)[idx];
+        return __uint_as_float(b << 16);
+    } else {
+        return (float)static_cast<const int *>(base)[idx];
+    }
+}
+
+// Per-lane state of one output point of a DAS wavefront tile.
+struct Lane {
+    bool valid;     // inside the grid
+    bool active;    // valid and in front of the array (z > 0)
+    long out_idx;
+    float x, y, z, z2;
+    int nB;         // integer part of B
+    float fB;       // fractional part of B
+    float thr;      // rho^2 threshold of the receive aperture (inf: no apodization)
+    float wsc;      // u^2 = rho^2 * wsc
+};
+
+__device__ inline Lane lane_setup(const DasArgs &a, int wave_id, int lane)
+{
+    Lane L;
+    const int tz = wave_id % a.tiles_z;
+    const int rest = wave_id / a.tiles_z;
+    const int tx = rest % a.tiles_x;
+    const int ty = rest / a.tiles_x;
+    const int lz = lane & ((1 << a.lz) - 1);
+    const int lx = (lane >> a.lz) & ((1 << a.lx) - 1);
+    const int ly = lane >> (a.lz + a.lx);
+    const int ix = (tx << a.lx) + lx, iy = (ty << a.ly) + ly, iz = (tz << a.lz) + lz;
+    L.valid = ix < a.g.nx && iy < a.g.ny && iz < a.g.nz;
+    L.out_idx = ((long)iy * a.g.nx + ix) * a.g.nz + iz;
+    const double px = a.g.org[0] + ix * a.g.ax[0] + iy * a.g.ay[0] + iz * a.g.az[0];
+    const double py = a.g.org[1] + ix * a.g.ax[1] + iy * a.g.ay[1] + iz * a.g.az[1];
+    const double pz = a.g.org[2] + ix * a.g.ax[2] + iy * a.g.ay[2] + iz * a.g.az[2];
+    L.active = L.valid && pz > 0.0;
+    const double B = 2.0 * pz * a.k - a.t0fs;
+    const double fl = floor(B);
+    L.nB = (int)fl;
+    L.fB = (float)(B - fl);
+    L.x = (float)px;
+    L.y = (float)py;
+    L.z = (float)pz;
+    L.z2 = L.z * L.z;
+    if (a.f2 > 0.f) {
+        L.thr = L.z2 * 0.25f / a.f2;
+        L.wsc = a.f2 / L.z2;
+    } else {
+        L.thr = __builtin_inff();
+        L.wsc = 0.f;
+    }
+    return L;
+}
+
+// Excess path d - z of a lateral offset with squared length rho2.
+__device__ inline float excess(float rho2, float z, float z2)
+{
+    const float d = __builtin_amdgcn_sqrtf(rho2 + z2);
+    return rho2 * __builtin_amdgcn_rcpf(d + z);
+}
+
+template <int ET>
+__device__ inline const void *trace_ptr(const void *e, long trace, int S)
+{
+    if constexpr (ET == ET_BF16)
+        return static_cast<const uint16_t *>(e) + trace * S;
+    else
+        return static_cast<const float *>(e) + trace * S;   // f32 and i32 are 4 bytes
+}
+
+}  // namespace bf

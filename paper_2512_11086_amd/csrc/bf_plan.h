@@ -1,0 +1,62 @@
+// bf_plan.h -- internal plan and frame objects of libbf (host side).
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "bf.h"
+#include "bf_common.h"
+
+namespace bf {
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+int validate_params(const bf_params *p);
+
+// One frame of a plan: its description, host copies of the tables and the
+// device tables the kernels read.
+struct Frame {
+    bf_params p;                 // copy; pointer members cleared
+    std::vector<int8_t> H;       // [n_tx][n_tx]
+    std::vector<int> tx, ch;     // element column / channel element
+    int kb = 1;                  // 32-wide K blocks of the int8 decode
+    Grid grid;
+    int lx = 2, ly = 2, lz = 2;  // DAS wavefront tile (log2)
+    long max_blocks = 0;
+    int8_t *d_At = nullptr;
+    int *d_colsum = nullptr;
+    float *d_Hf = nullptr;
+    float *d_tx_x = nullptr, *d_rx_c = nullptr;
+    double *d_partial = nullptr;
+    void *d_e = nullptr;         // batch plans: decoded-data workspace
+    std::vector<void *> allocs;
+    int64_t total_bytes = 0;
+
+    ~Frame();
+    void *alloc(size_t bytes);
+    int init(const bf_params &src);
+    void set_tile(int lx, int ly, int lz);
+    int64_t e_elems() const;
+    int64_t out_elems() const;
+    size_t e_bytes() const;
+    DecodeArgs decode_args(const int16_t *rf, void *e) const;
+    DasArgs das_args(const void *e, float *out, double c) const;
+    int decode(const int16_t *rf, void *e, hipStream_t s) const;
+    int das(const void *e, float *out, double c, hipStream_t s) const;
+};
+
+struct Batch;   // persistent batched path state (bf_batch.hip)
+
+constexpr uint32_t BF_PLAN_MAGIC = 0xBF0C0DE5u;
+
+}  // namespace bf
+
+struct bf_plan_s {
+    uint32_t magic = bf::BF_PLAN_MAGIC;
+    int device = 0;
+    std::vector<bf::Frame *> frames;
+    bf::Batch *batch = nullptr;
+    ~bf_plan_s();
+    int64_t workspace_bytes() const;
+};

@@ -1,0 +1,366 @@
+"""GPU parity of libbf against the FP64 CPU oracle, through the C ABI.
+
+Decode must be bit-exact (int32 / exact-integer FP32; BF16 equal to the
+round-to-nearest-even of the exact value).  DAS must be within a relative L2
+error of 1e-5 of the FP64 oracle for linear and cubic reads (the workloads'
+tolerance); nearest reads pick a sample from an FP32 delay, so a delay within
+FP32 rounding of a half-sample boundary can select the neighbouring sample:
+their bound (1e-4) is derived in the design doc.  Full images where the oracle
+finishes in seconds, sampled points at the full workload sizes.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2512_11086_amd as bfm
+import synth
+from synth import configs
+from synth.configs import MM, describe
+from tests.helpers import hadamard, max_rel, random_rf, rel_l2, sample_voxels
+
+pytestmark = pytest.mark.gpu
+
+TOL_L2 = 1e-5
+TOL_NEAREST = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+def _to_dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _decode_gpu(torch, desc, H, rf, e_type="f32", algo="mfma"):
+    plan = bfm.Plan(desc, H, e_type=e_type, decode_algo=algo)
+    e = plan.decode(_to_dev(torch, rf))
+    torch.cuda.synchronize()
+    return plan, e
+
+
+def _exact_check(torch, e, ref, e_type):
+    if e_type == "bf16":
+        want = torch.from_numpy(ref.astype(np.float32)).to(torch.bfloat16)
+        assert torch.equal(e.cpu().view(torch.int16), want.view(torch.int16))
+    elif e_type == "i32":
+        assert np.array_equal(e.cpu().numpy().astype(np.int64), ref)
+    else:
+        got = e.cpu().numpy()
+        assert np.array_equal(got.astype(np.int64), ref) and np.all(got == ref.astype(np.float32))
+
+
+# ---------------------------------------------------------------------------
+# Decode
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n_tx,kind,n_ch,S", [
+    (1, "sylvester", 3, 70), (2, "scrambled", 5, 64), (8, "sylvester", 4, 129),
+    (12, "paley", 3, 1001), (16, "scrambled", 7, 64), (20, "paley", 2, 37), (32, "sylvester", 4, 1024),
+    (44, "paley", 3, 200), (64, "scrambled", 3, 130), (60, "paley", 2, 66),
+    (128, "scrambled", 2, 2048), (132, "paley", 2, 65),
+    (256, "sylvester", 2, 128), (252, "paley", 1, 63),
+])
+@pytest.mark.parametrize("e_type", ["f32", "i32", "bf16"])
+def test_decode_bit_exact_ragged(torch_dev, n_tx, kind, n_ch, S, e_type):
+    torch, _ = torch_dev
+    H = hadamard(n_tx, kind, seed=n_tx)
+    rf = random_rf((n_tx, n_ch, S), seed=n_tx * 7 + S)
+    desc = describe("forces", (max(n_tx, n_ch), 4), (0.2 * MM, 0.2 * MM), n_tx, n_ch, S, 20e6, 5e6,
+                    (4, 1, 4), (-1 * MM, 0, 5 * MM), (1 * MM, 0, 6 * MM))
+    _, e = _decode_gpu(torch, desc, H, rf, e_type)
+    _exact_check(torch, e, oracle.decode(H, rf), e_type)
+
+
+@pytest.mark.parametrize("n_tx", [16, 64, 128])
+def test_decode_fma_variant_bit_exact(torch_dev, n_tx):
+    torch, _ = torch_dev
+    H = hadamard(n_tx, "scrambled", seed=3)
+    rf = random_rf((n_tx, 3, 515), seed=n_tx)
+    desc = describe("forces", (n_tx, 4), (0.2 * MM, 0.2 * MM), n_tx, 3, 515, 20e6, 5e6,
+                    (4, 1, 4), (-1 * MM, 0, 5 * MM), (1 * MM, 0, 6 * MM))
+    _, e = _decode_gpu(torch, desc, H, rf, "f32", "fma")
+    _exact_check(torch, e, oracle.decode(H, rf), "f32")
+
+
+def test_decode_extreme_values(torch_dev):
+    torch, _ = torch_dev
+    n = 64
+    H = hadamard(n, "sylvester")
+    rf = np.full((n, 2, 128), -32768, dtype=np.int16)
+    rf[:, 1, :] = 32767
+    rf[::2, 0, ::3] = 32767
+    desc = describe("forces", (n, 4), (0.2 * MM, 0.2 * MM), n, 2, 128, 20e6, 5e6,
+                    (4, 1, 4), (-1 * MM, 0, 5 * MM), (1 * MM, 0, 6 * MM))
+    _, e = _decode_gpu(torch, desc, H, rf, "i32")
+    _exact_check(torch, e, oracle.decode(H, rf), "i32")
+
+
+@pytest.fixture(scope="module")
+def workload0():
+    return synth.make_inputs(0)
+
+
+@pytest.fixture(scope="module")
+def workload1():
+    return synth.make_inputs(1)
+
+
+@pytest.fixture(scope="module")
+def workload3():
+    return synth.make_inputs(3, frame=0)
+
+
+def test_decode_workloads_bit_exact(torch_dev, workload0, workload1, workload3):
+    torch, _ = torch_dev
+    for desc, H, rf in ((workload0[0], workload0[1], workload0[2]),
+                        (workload1[0], workload1[1], workload1[2]),
+                        (workload3[0], workload3[1], workload3[2][0])):
+        _, e = _decode_gpu(torch, desc, H, rf)
+        _exact_check(torch, e, oracle.decode(H, rf), "f32")
+
+
+# ---------------------------------------------------------------------------
+# DAS forward
+# ---------------------------------------------------------------------------
+
+def _das_gpu(torch, desc, H, e_np, e_type="f32", c=None, tile=None):
+    plan = bfm.Plan(desc, H, e_type=e_type, tile=tile)
+    dt = {"f32": torch.float32, "bf16": torch.bfloat16, "i32": torch.int32}[e_type]
+    e = torch.from_numpy(np.ascontiguousarray(e_np)).to(dt).cuda()
+    img = plan.das(e, c=c)
+    torch.cuda.synchronize()
+    return plan, e, img.cpu().numpy().astype(np.float64)
+
+
+def test_das_workload0_full_image(torch_dev, workload0):
+    torch, _ = torch_dev
+    desc, H, rf, _ = workload0
+    e = oracle.decode(H, rf)
+    ref = oracle.das(desc, e)
+    _, _, got = _das_gpu(torch, desc, H, e.astype(np.float32))
+    err = rel_l2(got, ref)
+    print(f"workload 0: rel L2 {err:.3e}  max|d|/max|ref| {max_rel(got, ref):.3e}")
+    assert err <= TOL_L2
+
+
+def test_das_workload3_full_image(torch_dev, workload3):
+    torch, _ = torch_dev
+    desc, H, rfs, info = workload3
+    e = oracle.decode(H, rfs[0])
+    for c in (1450.0, info["c_true"]):
+        ref = oracle.das(desc, e, c=c)
+        _, _, got = _das_gpu(torch, desc, H, e.astype(np.float32), c=c)
+        err = rel_l2(got, ref)
+        print(f"workload 3 (c={c:.1f}): rel L2 {err:.3e}  max rel {max_rel(got, ref):.3e}")
+        assert err <= TOL_L2
+
+
+def test_das_workload1_sampled_voxels(torch_dev, workload1):
+    torch, _ = torch_dev
+    desc, H, rf, _ = workload1
+    e = oracle.decode(H, rf)
+    _, _, got = _das_gpu(torch, desc, H, e.astype(np.float32))
+    vox = sample_voxels(got.size, 3000, seed=11)
+    ref = oracle.das_points(desc, e, vox)
+    err = rel_l2(got.reshape(-1)[vox], ref)
+    print(f"workload 1 ({vox.size} sampled voxels): rel L2 {err:.3e}  max rel "
+          f"{max_rel(got.reshape(-1)[vox], ref):.3e}")
+    assert err <= TOL_L2
+
+
+def _small_desc(mode, interp, f_number=0.7, rotate=False, dims=None, t0=0.3e-6):
+    M = None
+    if rotate:
+        a = 0.3
+        R = np.array([[np.cos(a), 0, np.sin(a)], [0, 1, 0], [-np.sin(a), 0, np.cos(a)]])
+        M = configs.centered_xdc((12, 10), (0.25 * MM, 0.3 * MM))
+        M[:3, :3] = R
+        M[:3, 3] += [0.2 * MM, -0.1 * MM, 0.5 * MM]
+    if dims is None:
+        dims = (37, 1, 53) if mode == "forces" else (13, 9, 29)
+    return describe(mode, (12, 10), (0.25 * MM, 0.3 * MM), 8, 10 if mode == "hercules" else 12,
+                    600, 25e6, 6e6, dims, (-2 * MM, -1.5 * MM, 1.0 * MM), (2.2 * MM, 1.2 * MM, 9 * MM),
+                    t0=t0, f_number=f_number, interp=interp,
+                    tx_elements=[0, 3, 4, 6, 7, 8, 10, 11],
+                    channel_map=np.random.default_rng(2).permutation(10 if mode == "hercules" else 12),
+                    xdc=M)
+
+
+def _small_data(desc, seed):
+    rng = np.random.default_rng(seed)
+    pts = rng.uniform([-2 * MM, -1 * MM, 1.5 * MM], [2 * MM, 1 * MM, 8 * MM], size=(6, 3))
+    if desc["mode"] == "forces":
+        pts[:, 1] = 0
+    H = hadamard(desc["n_tx"], "scrambled", seed=seed)
+    rf = synth.acquire(desc, pts, np.ones(6), rng, H=H)
+    return H, oracle.decode(H, rf)
+
+
+@pytest.mark.parametrize("mode", ["forces", "hercules"])
+@pytest.mark.parametrize("interp", ["nearest", "linear", "cubic"])
+@pytest.mark.parametrize("rotate", [False, True])
+def test_das_small_ragged(torch_dev, mode, interp, rotate):
+    torch, _ = torch_dev
+    desc = _small_desc(mode, interp, rotate=rotate)
+    H, e = _small_data(desc, seed=5)
+    ref = oracle.das(desc, e)
+    _, _, got = _das_gpu(torch, desc, H, e.astype(np.float32))
+    err = rel_l2(got, ref)
+    print(f"{mode} {interp} rotate={rotate}: rel L2 {err:.3e}")
+    assert err <= (TOL_NEAREST if interp == "nearest" else TOL_L2)
+
+
+@pytest.mark.parametrize("mode", ["forces", "hercules"])
+def test_das_tiles_agree(torch_dev, mode):
+    torch, _ = torch_dev
+    desc = _small_desc(mode, "cubic", f_number=1.0)
+    H, e = _small_data(desc, seed=8)
+    ref = oracle.das(desc, e)
+    tiles = [(3, 0, 3), (2, 0, 4), (0, 0, 6), (6, 0, 0)] if mode == "forces" else \
+            [(2, 2, 2), (1, 1, 4), (3, 3, 0), (0, 0, 6)]
+    outs = []
+    for t in tiles:
+        _, _, got = _das_gpu(torch, desc, H, e.astype(np.float32), tile=t)
+        assert rel_l2(got, ref) <= TOL_L2, t
+        outs.append(got)
+    # every tile shape computes each point with the same per-point sum order
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("e_type", ["bf16", "i32"])
+def test_das_storage_types(torch_dev, e_type):
+    torch, _ = torch_dev
+    desc = _small_desc("hercules", "cubic")
+    H, e = _small_data(desc, seed=9)
+    if e_type == "bf16":
+        e_in = torch.from_numpy(e.astype(np.float32)).to(torch.bfloat16)
+        e_ref = e_in.float().numpy().astype(np.float64)   # DAS of the rounded data
+    else:
+        e_in = torch.from_numpy(e.astype(np.int32))
+        e_ref = e
+    ref = oracle.das(desc, e_ref)
+    plan = bfm.Plan(desc, H, e_type=e_type)
+    got = plan.das(e_in.cuda()).cpu().numpy()
+    assert rel_l2(got, ref) <= TOL_L2
+
+
+def test_das_edge_cases(torch_dev):
+    torch, _ = torch_dev
+    # grid behind / on the array plane, and delays beyond the record: zeros
+    desc = _small_desc("hercules", "cubic", dims=(5, 3, 7))
+    desc = dict(desc, gmin=(-1 * MM, -1 * MM, -3 * MM), gmax=(1 * MM, 1 * MM, 0.0))
+    H, e = _small_data(_small_desc("hercules", "cubic"), seed=1)
+    _, _, got = _das_gpu(torch, desc, H, e.astype(np.float32))
+    assert np.all(got == 0.0)
+    far = dict(_small_desc("forces", "cubic", dims=(9, 1, 11)), gmin=(-1 * MM, 0, 60 * MM),
+               gmax=(1 * MM, 0, 70 * MM))
+    H2, e2 = _small_data(_small_desc("forces", "cubic"), seed=2)
+    _, _, got2 = _das_gpu(torch, far, H2, e2.astype(np.float32))
+    assert np.all(got2 == 0.0) and np.all(oracle.das(far, e2) == 0.0)
+    # a single point, and a grid partly past the end of the record
+    one = dict(_small_desc("forces", "cubic", dims=(1, 1, 1)), gmin=(0.3 * MM, 0, 4 * MM),
+               gmax=(0.3 * MM, 0, 4 * MM))
+    _, _, g1 = _das_gpu(torch, one, H2, e2.astype(np.float32))
+    # one point has no L2 averaging: bound its error by the beamformed magnitude
+    # of |e| (the size of the terms that cancel in the sum)
+    scale = float(oracle.das(one, np.abs(e2)).reshape(-1)[0])
+    assert abs(float(g1.reshape(-1)[0]) - float(oracle.das(one, e2).reshape(-1)[0])) <= TOL_L2 * scale
+    edge = dict(_small_desc("forces", "cubic", dims=(8, 1, 40)), gmax=(2.2 * MM, 0, 19 * MM))
+    ref = oracle.das(edge, e2)
+    _, _, g2 = _das_gpu(torch, edge, H2, e2.astype(np.float32))
+    assert rel_l2(g2, ref) <= TOL_L2
+
+
+def test_das_repeatable_bitwise(torch_dev, workload0):
+    torch, _ = torch_dev
+    desc, H, rf, _ = workload0
+    plan = bfm.Plan(desc, H)
+    e = plan.decode(_to_dev(torch, rf))
+    a = plan.das(e).clone()
+    b = plan.das(e)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# Adjoint, sound-speed gradient, sharpness
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode", ["forces", "hercules"])
+@pytest.mark.parametrize("interp", ["linear", "cubic"])
+def test_adjoint_matches_oracle(torch_dev, mode, interp):
+    torch, _ = torch_dev
+    desc = _small_desc(mode, interp, f_number=1.0)
+    H, e = _small_data(desc, seed=4)
+    G = np.random.default_rng(3).normal(size=oracle.Geometry(desc).shape)
+    plan = bfm.Plan(desc, H)
+    et = torch.from_numpy(e.astype(np.float32)).cuda()
+    ge, gc = plan.das_adjoint(et, torch.from_numpy(G.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    ref_e = oracle.das_adjoint_e(desc, G)
+    assert rel_l2(ge.cpu().numpy(), ref_e) <= TOL_L2
+    ref_c = float(np.sum(G * oracle.das_dc(desc, e)))
+    assert abs(gc.item() - ref_c) <= 1e-4 * abs(ref_c)
+    # dot-product identity on the GPU (FP32)
+    img = plan.das(et).cpu().numpy().astype(np.float64)
+    lhs = float(np.sum(img * G))
+    rhs = float(np.sum(e * ge.cpu().numpy().astype(np.float64)))
+    assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(img) * np.linalg.norm(G)
+
+
+def test_sound_speed_gradient_workload3(torch_dev, workload3):
+    torch, _ = torch_dev
+    desc, H, rfs, info = workload3
+    plan = bfm.Plan(desc, H)
+    e = plan.decode(_to_dev(torch, rfs[0]))
+    e64 = oracle.decode(H, rfs[0])
+    for c0 in (1450.0, 1540.0, 1600.0):
+        img = plan.das(e, c=c0)
+        loss, g = bfm.sharpness(img.reshape(1, -1))
+        _, gc = plan.das_adjoint(e, g.reshape(img.shape), c=c0, want_e=False)
+        torch.cuda.synchronize()
+        # oracle: analytic chain rule in FP64
+        ref_img = oracle.das(desc, e64, c=c0)
+        L, gI = oracle.sharpness(ref_img.reshape(-1), grad=True)
+        ref = float(np.sum(gI.reshape(ref_img.shape) * oracle.das_dc(desc, e64, c=c0)))
+        assert abs(loss.item() - L) <= 1e-5 * abs(L)
+        assert abs(gc.item() - ref) <= 1e-4 * abs(ref), (c0, gc.item(), ref)
+        # central finite differences of the oracle at h = 0.1 m/s and h / 2.  The
+        # loss is strongly curved in c, so FD(0.1) itself carries an O(h^2)
+        # truncation error of up to a few percent: the GPU gradient must lie
+        # within that error of FD(0.1) and within 1e-3 of the Richardson
+        # extrapolation (4 FD(h/2) - FD(h)) / 3, whose error is O(h^4).
+        def fd(h):
+            Lp = oracle.sharpness(oracle.das(desc, e64, c=c0 + h))
+            Lm = oracle.sharpness(oracle.das(desc, e64, c=c0 - h))
+            return (Lp - Lm) / (2 * h)
+        f1, f2 = fd(0.1), fd(0.05)
+        rich = (4 * f2 - f1) / 3
+        trunc = abs(f1 - f2) * 4 / 3
+        # GPU forward differences, reported only
+        ip = plan.das(e, c=c0 + 0.05)
+        im = plan.das(e, c=c0 - 0.05)
+        gfd = (bfm.sharpness(ip.reshape(1, -1), grad=False).item()
+               - bfm.sharpness(im.reshape(1, -1), grad=False).item()) / 0.1
+        print(f"c0={c0}: gpu dL/dc {gc.item():.6e}  oracle {ref:.6e}  FD(0.1) {f1:.6e}  "
+              f"FD(0.05) {f2:.6e}  Richardson {rich:.6e}  gpu FD(0.05) {gfd:.6e}")
+        assert abs(gc.item() - f1) <= 2 * trunc + 1e-4 * abs(f1)
+        assert abs(gc.item() - rich) <= 1e-3 * abs(rich)
+
+
+def test_sharpness_matches_oracle(torch_dev):
+    torch, _ = torch_dev
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(3, 5000)).astype(np.float32)
+    x[1] = 0.0
+    loss, g = bfm.sharpness(torch.from_numpy(x).cuda())
+    for f in range(3):
+        L, gr = oracle.sharpness(x[f].astype(np.float64), grad=True)
+        assert abs(loss[f].item() - L) <= 1e-6 * max(abs(L), 1e-30)
+        assert rel_l2(g[f].cpu().numpy(), gr) <= 1e-6 or not np.any(gr)

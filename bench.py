@@ -85,6 +85,56 @@ def cpu_baseline(desc, H, rf, budget_s: float):
                        f"({t_das:.1f} s), scaled to one volume"), e, vox, ref
 
 
+def batched_comparison(torch, bfm, synth, reps: int):
+    """64-frame uFORCES/uHERCULES stream: plain per-frame launches vs one
+    persistent launch per kernel class vs the same captured in a hipGraph."""
+    t = time.perf_counter()
+    descs, Hs, rfs, info = synth.make_inputs(4)
+    log(f"batched inputs ({len(descs)} frames) generated in {time.perf_counter() - t:.1f} s")
+    dev = torch.device("cuda:0")
+    rf_d = [torch.from_numpy(r).to(dev) for r in rfs]
+    bp = bfm.BatchPlan(descs, Hs)
+    plans = [bfm.Plan(d, H) for d, H in zip(descs, Hs)]
+    outs_b = [torch.empty(s, device=dev) for s in bp.out_shapes]
+    outs_g = [torch.empty(s, device=dev) for s in bp.out_shapes]
+    outs_p = [torch.empty(p.out_shape, device=dev) for p in plans]
+    es = [torch.empty(r.shape, dtype=torch.float32, device=dev) for r in rfs]
+
+    def per_frame():
+        for p, r, e, o in zip(plans, rf_d, es, outs_p):
+            p.decode(r, out=e)
+            p.das(e, out=o)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ms_pf = timed(per_frame)
+    ms_ps = timed(lambda: bp.run(rf_d, outs_b))
+    ms_gr = timed(lambda: bp.graph_launch(rf_d, outs_g))
+    worst = 0.0
+    for a_, b_, c_ in zip(outs_p, outs_b, outs_g):
+        worst = max(worst, float((a_ - b_).norm() / a_.norm().clamp_min(1e-30)),
+                    float((b_ - c_).norm() / b_.norm().clamp_min(1e-30)))
+    nominal = sum(int(np.prod(d["dims"])) * d["n_tx"] * d["n_ch"] for d in descs)
+    n3 = sum(1 for d in descs if d["mode"] == "hercules")
+    log(f"batched: per-frame {ms_pf:.2f} ms, persistent {ms_ps:.2f} ms, graph {ms_gr:.2f} ms")
+    return {"frames": len(descs), "frames_3d": n3, "nominal_G_samples": round(nominal / 1e9, 2),
+            "per_frame_ms": round(ms_pf, 3), "persistent_ms": round(ms_ps, 3),
+            "graph_ms": round(ms_gr, 3),
+            "speedup_graph_vs_per_frame": round(ms_pf / ms_gr, 3),
+            "speedup_persistent_vs_per_frame": round(ms_pf / ms_ps, 3),
+            "graph_G_samples_per_s": round(nominal / (ms_gr * 1e-3) / 1e9, 1),
+            "max_rel_l2_between_paths": worst}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +142,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-frame batched comparison")
+    ap.add_argument("--batch-reps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; multi-GPU runs are not part of this build "
@@ -169,6 +221,9 @@ def main():
                      "peak": round(FP32_NONPACKED_TFLOPS, 1), "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_NONPACKED_TFLOPS, 4), "traffic": None},
     }
+    res["das_config"] = plan.info()
+    if not args.no_batch:
+        res["batched"] = batched_comparison(torch, bfm, synth, args.batch_reps)
     if not args.no_cpu:
         cb, e64, vox, ref = cpu_baseline(desc, H, rf, args.cpu_budget)
         res["cpu_baseline"] = cb

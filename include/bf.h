@@ -106,10 +106,17 @@ typedef struct {
 
 typedef struct bf_plan_s *bf_plan;   /* opaque, owned by libbf */
 
+/* DAS kernel variants: LDS-staged trace windows (default), or the direct
+ * gather kernel (used automatically when a window would not fit in LDS). */
+enum { BF_DAS_LDS = 0, BF_DAS_GATHER = 1 };
+
 /* Read-only facts about a plan. */
 typedef struct {
     int32_t n_frames;
     int32_t tile[3];           /* DAS voxels per wavefront along x, y, z               */
+    int32_t variant;           /* BF_DAS_*                                             */
+    int32_t block[3];          /* wavefront tiles per LDS workgroup along x, y, z      */
+    int32_t nb;                /* traces per staged batch                              */
     int64_t workspace_bytes;   /* device memory held by the plan                       */
     int64_t e_elems;           /* elements of decoded data per frame (frame 0)         */
     int64_t out_elems;         /* output points per frame (frame 0)                    */
@@ -154,6 +161,12 @@ int bf_autotune(bf_plan plan, const char *cache_path);
 /* Set the DAS wavefront tile explicitly: log2 of voxels along x, y, z; they must
  * sum to 6 (64 lanes).  For 2D plans log2_y must be 0. */
 int bf_set_tile(bf_plan plan, int32_t log2_x, int32_t log2_y, int32_t log2_z);
+
+/* Select the DAS kernel and its LDS workgroup: variant BF_DAS_*, wavefront
+ * tiles per workgroup (product 1..16; bw_y = 1 for 2D plans) and traces per
+ * staged batch nb (4..64, multiple of 4).  Applies to every frame. */
+int bf_set_das_config(bf_plan plan, int32_t variant, int32_t bw_x, int32_t bw_y, int32_t bw_z,
+                      int32_t nb);
 
 /* Decode (Sec. VII-E):  e[i][j][t] = sum_k H[k][i] * rf[k][j][t]  (unscaled, so
  * decoding an encoded set returns N times the element responses).

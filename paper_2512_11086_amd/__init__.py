@@ -118,16 +118,21 @@ class Plan:
     def info(self) -> dict:
         inf = PlanInfo()
         check(lib().bf_plan_get_info(self._h, ctypes.byref(inf)))
-        return dict(n_frames=inf.n_frames, tile=tuple(inf.tile),
+        return dict(n_frames=inf.n_frames, tile=tuple(inf.tile), variant=inf.variant,
+                    block=tuple(inf.block), nb=inf.nb,
                     workspace_bytes=inf.workspace_bytes, e_elems=inf.e_elems,
                     out_elems=inf.out_elems)
 
     def set_tile(self, lx: int, ly: int, lz: int):
         check(lib().bf_set_tile(self._h, lx, ly, lz))
 
+    def set_das_config(self, variant: str = "lds", block=(4, 4, 1), nb: int = 16):
+        v = {"lds": 0, "gather": 1}[variant]
+        check(lib().bf_set_das_config(self._h, v, *[int(b) for b in block], int(nb)))
+
     def autotune(self, cache_path: str | None = None):
         check(lib().bf_autotune(self._h, cache_path.encode() if cache_path else None))
-        return self.info()["tile"]
+        return self.info()
 
     def e_dtype(self):
         return getattr(_torch(), _TORCH_ETYPE[self.e_type])

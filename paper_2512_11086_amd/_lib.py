@@ -45,6 +45,7 @@ class Params(ctypes.Structure):
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n_frames", ctypes.c_int32), ("tile", ctypes.c_int32 * 3),
+                ("variant", ctypes.c_int32), ("block", ctypes.c_int32 * 3), ("nb", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_int64), ("e_elems", ctypes.c_int64),
                 ("out_elems", ctypes.c_int64)]
 
@@ -72,6 +73,7 @@ def lib():
         "bf_plan_get_info": ([vp, P(PlanInfo)], ctypes.c_int),
         "bf_autotune": ([vp, ctypes.c_char_p], ctypes.c_int),
         "bf_set_tile": ([vp, i32, i32, i32], ctypes.c_int),
+        "bf_set_das_config": ([vp, i32, i32, i32, i32, i32], ctypes.c_int),
         "bf_decode": ([vp, vp, vp, vp], ctypes.c_int),
         "bf_das": ([vp, vp, vp, dbl, vp], ctypes.c_int),
         "bf_das_adjoint": ([vp, vp, vp, dbl, vp, vp, vp], ctypes.c_int),
@@ -95,5 +97,5 @@ def check(status: int) -> None:
 
 EXPORTED = ("bf_abi_version", "bf_last_error", "bf_validate", "bf_plan_create",
             "bf_plan_create_batch", "bf_plan_destroy", "bf_plan_get_info", "bf_autotune",
-            "bf_set_tile", "bf_decode", "bf_das", "bf_das_adjoint", "bf_sharpness",
+            "bf_set_tile", "bf_set_das_config", "bf_decode", "bf_das", "bf_das_adjoint", "bf_sharpness",
             "bf_batch_run", "bf_graph_launch", "bf_hann_poly")

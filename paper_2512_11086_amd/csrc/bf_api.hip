@@ -201,10 +201,21 @@ int Frame::init(const bf_params &src)
     grid.nx = p.out_dims[0];
     grid.ny = p.out_dims[1];
     grid.nz = p.out_dims[2];
-    if (p.mode == BF_FORCES_2D && grid.ny == 1)
-        set_tile(3, 0, 3);
-    else
-        set_tile(2, 2, 2);
+    // Default DAS workgroups (fastest in measured sweeps on MI355X; the
+    // autotuner can replace them): 2D = 4x16-point wavefront tiles, four
+    // stacked in depth; 3D = flat 8x8x1 tiles, a 2x2x2 block of them.
+    if (p.mode == BF_FORCES_2D && grid.ny == 1) {
+        set_tile(2, 0, 4);
+        bw[0] = 1; bw[1] = 1; bw[2] = 4;
+        nb = 8;
+    } else {
+        set_tile(3, 3, 0);
+        bw[0] = 2; bw[1] = 2; bw[2] = 2;
+        nb = 16;
+    }
+    sorted_tx = 1;
+    for (int i = 1; i < n; ++i)
+        if (tx_x[i] < tx_x[i - 1]) sorted_tx = 0;
 
     d_At = (int8_t *)alloc(At.size());
     d_colsum = (int *)alloc(cs.size() * sizeof(int));
@@ -220,6 +231,22 @@ int Frame::init(const bf_params &src)
             if ((w + 3) / 4 > max_blocks) max_blocks = (w + 3) / 4;
         }
     d_partial = (double *)alloc((size_t)max_blocks * sizeof(double));
+    // Small grids give too few wavefronts to fill 256 CUs; split the channel
+    // sum over `groups` workgroup sets (>= 8192 wavefronts in flight) and add
+    // the partial images in a fixed order afterwards.
+    {
+        const long nvox = (long)grid.nx * grid.ny * grid.nz;
+        const long waves = (nvox + 63) / 64;
+        long G = (8192 + waves - 1) / waves;
+        const long gmax = p.n_ch / 4 > 1 ? p.n_ch / 4 : 1;
+        if (G > 16) G = 16;
+        if (G > gmax) G = gmax;
+        groups = (int)(G < 1 ? 1 : G);
+        if (groups > 1) {
+            d_part = (float *)alloc((size_t)groups * nvox * sizeof(float));
+            if (!d_part) return fail(BF_ERR_HIP, "device allocation of partial images failed");
+        }
+    }
     if (!d_At || !d_colsum || !d_Hf || !d_tx_x || !d_rx_c || !d_partial)
         return fail(BF_ERR_HIP, "device allocation for plan tables failed");
     hipError_t e;
@@ -285,6 +312,8 @@ DasArgs Frame::das_args(const void *e, float *out, double c) const
     a.tiles_y = (grid.ny + (1 << ly) - 1) >> ly;
     a.tiles_z = (grid.nz + (1 << lz) - 1) >> lz;
     a.n_waves = a.tiles_x * a.tiles_y * a.tiles_z;
+    a.groups = groups;
+    a.part = d_part;
     return a;
 }
 
@@ -296,10 +325,49 @@ int Frame::decode(const int16_t *rf, void *e, hipStream_t s) const
     return err == hipSuccess ? BF_OK : hip_fail(err, "decode launch");
 }
 
+// Workgroup box, staged-window length and batch size of the LDS kernel for
+// this frame at the sound speed of `a`; false if the window would not fit
+// (the direct-gather kernel is used then).
+bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
+{
+    const int tx = bw[0] << lx, ty = bw[1] << ly, tz = bw[2] << lz;
+    double E[3];
+    for (int r = 0; r < 3; ++r)
+        E[r] = fabs(grid.ax[r]) * (tx - 1) + fabs(grid.ay[r]) * (ty - 1) + fabs(grid.az[r]) * (tz - 1);
+    // Bound on the spread of the sample position over the box: the delay
+    // grows with depth (2 dz on the round trip) and with lateral distance
+    // (one receive path for HERCULES, transmit and receive for FORCES).
+    const double spread = p.mode == BF_FORCES_2D ? 2.0 * E[2] + 2.0 * E[0]
+                                                 : 2.0 * E[2] + sqrt(E[0] * E[0] + E[1] * E[1]);
+    const int lmax = (int)ceil(a.k * spread) + 8;
+    const int nthr = 64 * bw[0] * bw[1] * bw[2];
+    int nbb = nb;
+    const int unit = p.mode == BF_FORCES_2D ? 4 : 1;
+    const size_t lds_cap = 60 * 1024;   // dynamic LDS without the large-LDS attribute
+    while (nbb >= unit && ((long)nbb * lmax > 4L * nthr || lds_bytes(p.n_tx, p.n_ch, nbb, lmax) > lds_cap))
+        nbb -= unit;
+    if (nbb < unit || nthr > 1024) return false;
+    cfg->bwx = bw[0];
+    cfg->bwy = bw[1];
+    cfg->bwz = bw[2];
+    cfg->nb = nbb;
+    cfg->lmax = lmax;
+    cfg->sorted_tx = sorted_tx;
+    cfg->blocks_x = (grid.nx + tx - 1) / tx;
+    cfg->blocks_y = (grid.ny + ty - 1) / ty;
+    cfg->blocks_z = (grid.nz + tz - 1) / tz;
+    return true;
+}
+
 int Frame::das(const void *e, float *out, double c, hipStream_t s) const
 {
     const DasArgs a = das_args(e, out, c);
-    hipError_t err = launch_das(a, p.mode, p.e_type, p.interp, s);
+    LdsCfg cfg;
+    hipError_t err;
+    if (variant == 0 && lds_config(a, &cfg))
+        err = launch_das_lds(a, cfg, p.mode, p.e_type, p.interp, s);
+    else
+        err = launch_das(a, p.mode, p.e_type, p.interp, s);
     return err == hipSuccess ? BF_OK : hip_fail(err, "DAS launch");
 }
 
@@ -393,6 +461,11 @@ int bf_plan_get_info(bf_plan plan, bf_plan_info *info)
     info->tile[0] = 1 << f.lx;
     info->tile[1] = 1 << f.ly;
     info->tile[2] = 1 << f.lz;
+    info->variant = f.variant;
+    info->block[0] = f.bw[0];
+    info->block[1] = f.bw[1];
+    info->block[2] = f.bw[2];
+    info->nb = f.nb;
     info->workspace_bytes = plan->workspace_bytes();
     info->e_elems = f.e_elems();
     info->out_elems = f.out_elems();
@@ -411,6 +484,31 @@ int bf_set_tile(bf_plan plan, int32_t log2_x, int32_t log2_y, int32_t log2_z)
             return fail(BF_ERR_SHAPE, "a 2D plan needs log2_y = 0");
     }
     for (Frame *f : plan->frames) f->set_tile(log2_x, log2_y, log2_z);
+    return BF_OK;
+}
+
+int bf_set_das_config(bf_plan plan, int32_t variant, int32_t bw_x, int32_t bw_y, int32_t bw_z,
+                      int32_t nb)
+{
+    g_err.clear();
+    int st = check_plan(plan);
+    if (st != BF_OK) return st;
+    if (variant != BF_DAS_LDS && variant != BF_DAS_GATHER)
+        return fail(BF_ERR_UNSUPPORTED, "unknown DAS variant %d", variant);
+    if (bw_x < 1 || bw_y < 1 || bw_z < 1 || bw_x * bw_y * bw_z > 16)
+        return fail(BF_ERR_SHAPE, "workgroup must hold 1..16 wavefront tiles");
+    if (nb < 4 || nb > 64 || nb % 4 != 0) return fail(BF_ERR_SHAPE, "nb must be 4..64, a multiple of 4");
+    for (Frame *f : plan->frames) {
+        if (f->p.mode == BF_FORCES_2D && f->grid.ny == 1 && bw_y != 1)
+            return fail(BF_ERR_SHAPE, "a 2D plan needs bw_y = 1");
+    }
+    for (Frame *f : plan->frames) {
+        f->variant = variant;
+        f->bw[0] = bw_x;
+        f->bw[1] = bw_y;
+        f->bw[2] = bw_z;
+        f->nb = nb;
+    }
     return BF_OK;
 }
 

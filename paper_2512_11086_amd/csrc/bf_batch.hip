@@ -1,10 +1,300 @@
-// bf_batch.hip -- batched persistent decode + DAS and its hipGraph replay,
-// plus the DAS tile autotuner.
+// bf_batch.hip -- batched decode + DAS over many frames with persistent
+// kernels, its hipGraph replay, and the DAS workgroup autotuner.
+//
+// A batch holds frames with their own descriptions (uFORCES / uHERCULES
+// transmit subsets of different sizes, 2D and 3D outputs).  Frames are
+// grouped into kernel classes: decode by (32-wide K blocks, output type) and
+// DAS by (mode, data type, interpolation).  Each class runs as ONE persistent
+// launch whose workgroups pull work items from an atomic queue: decode items
+// are (frame, channel, 256 samples), DAS items are (frame, workgroup box),
+// sorted by decreasing cost so that the tail of the queue is made of short
+// items.  Decoded data stays in plan-owned workspaces; the caller's RF and
+// output buffers are passed through a device pointer table refreshed before
+// every launch, so a captured graph never needs re-capture for new buffers.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
 #include "bf_plan.h"
 
 namespace bf {
-struct Batch {
+
+hipError_t launch_decode_persistent(const DecLaunch &p, hipStream_t s);
+hipError_t launch_das_persistent(const PersistentLaunch &p, hipStream_t s);
+int persistent_das_blocks(int mode, int et, int ip, int threads, size_t shm);
+hipError_t launch_fill(float *p, long n, float v, hipStream_t s);
+
+__global__ void reset_counters_kernel(int *c, int n)
+{
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+}
+
+struct DecClass {
+    int kb, ot;
+    std::vector<int2> items;
+    int2 *d_items = nullptr;
+    int grid = 0;
 };
+
+struct DasClass {
+    int mode, et, ip, threads;
+    size_t shm = 0;
+    std::vector<std::pair<double, int2>> items;   // (cost, item)
+    int2 *d_items = nullptr;
+    int n_items = 0;
+    int grid = 0;
+};
+
+constexpr int RING = 4;
+
+struct Batch {
+    int F = 0;
+    FrameDec *d_fdec = nullptr;
+    FrameDas *d_fdas = nullptr;
+    void **d_ptrs = nullptr;          // [2F]: rf pointers, then out pointers
+    int *d_counters = nullptr;
+    std::vector<DecClass> dec;
+    std::vector<DasClass> das;
+    std::vector<int> gather_frames;   // frames whose window does not fit in LDS
+    void **h_stage[RING] = {};
+    hipEvent_t ev[RING] = {};
+    int ring = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<void *> allocs;
+
+    ~Batch()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+        for (int k = 0; k < RING; ++k) {
+            if (ev[k]) (void)hipEventDestroy(ev[k]);
+            if (h_stage[k]) (void)hipHostFree(h_stage[k]);
+        }
+        for (void *p : allocs) (void)hipFree(p);
+    }
+    void *alloc(size_t bytes)
+    {
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        allocs.push_back(p);
+        return p;
+    }
+};
+
+static int build_batch(bf_plan plan)
+{
+    Batch *b = new Batch();
+    plan->batch = b;
+    const int F = (int)plan->frames.size();
+    b->F = F;
+    std::vector<FrameDec> fdec(F);
+    std::vector<FrameDas> fdas(F);
+    for (int f = 0; f < F; ++f) {
+        Frame &fr = *plan->frames[f];
+        if (!fr.d_e) {
+            fr.d_e = fr.alloc(fr.e_bytes());
+            if (!fr.d_e) return fail(BF_ERR_HIP, "decoded-data workspace allocation failed");
+        }
+        fdec[f].a = fr.decode_args(nullptr, fr.d_e);
+        DasArgs a = fr.das_args(fr.d_e, nullptr, fr.p.c);
+        a.groups = 1;
+        a.part = nullptr;
+        LdsCfg c;
+        if (fr.variant != 0 || !fr.lds_config(a, &c)) {
+            b->gather_frames.push_back(f);
+            memset(&c, 0, sizeof c);
+        } else {
+            const int threads = 64 * c.bwx * c.bwy * c.bwz;
+            const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax);
+            DasClass *cls = nullptr;
+            for (DasClass &d : b->das)
+                if (d.mode == fr.p.mode && d.et == fr.p.e_type && d.ip == fr.p.interp &&
+                    d.threads == threads)
+                    cls = &d;
+            if (!cls) {
+                DasClass d;
+                d.mode = fr.p.mode;
+                d.et = fr.p.e_type;
+                d.ip = fr.p.interp;
+                d.threads = threads;
+                b->das.push_back(d);
+                cls = &b->das.back();
+            }
+            cls->shm = std::max(cls->shm, shm);
+            const int nblk = c.blocks_x * c.blocks_y * c.blocks_z;
+            const double cost = (double)fr.p.n_tx * fr.p.n_ch * threads;
+            for (int q = 0; q < nblk; ++q) cls->items.push_back({cost, make_int2(f, q)});
+        }
+        fdas[f].a = a;
+        fdas[f].c = c;
+        // decode classes
+        if (fr.p.decode_algo == BF_DECODE_MFMA_I8) {
+            DecClass *cls = nullptr;
+            for (DecClass &d : b->dec)
+                if (d.kb == fr.kb && d.ot == fr.p.e_type) cls = &d;
+            if (!cls) {
+                DecClass d;
+                d.kb = fr.kb;
+                d.ot = fr.p.e_type;
+                b->dec.push_back(d);
+                cls = &b->dec.back();
+            }
+            const int n_chunks = (fr.p.n_samples + 63) / 64;
+            const int n_cg = (n_chunks + 3) / 4;
+            for (int j = 0; j < fr.p.n_ch; ++j)
+                for (int g = 0; g < n_cg; ++g) cls->items.push_back(make_int2(f, j * n_cg + g));
+        }
+    }
+    const int n_counters = (int)(b->dec.size() + b->das.size());
+    b->d_fdec = (FrameDec *)b->alloc(sizeof(FrameDec) * F);
+    b->d_fdas = (FrameDas *)b->alloc(sizeof(FrameDas) * F);
+    b->d_ptrs = (void **)b->alloc(sizeof(void *) * 2 * F);
+    b->d_counters = (int *)b->alloc(sizeof(int) * (n_counters > 0 ? n_counters : 1));
+    if (!b->d_fdec || !b->d_fdas || !b->d_ptrs || !b->d_counters)
+        return fail(BF_ERR_HIP, "batch table allocation failed");
+    hipError_t e;
+    if ((e = hipMemcpy(b->d_fdec, fdec.data(), sizeof(FrameDec) * F, hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(b->d_fdas, fdas.data(), sizeof(FrameDas) * F, hipMemcpyHostToDevice)) !=
+            hipSuccess)
+        return hip_fail(e, "batch table upload");
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    for (DecClass &d : b->dec) {
+        d.d_items = (int2 *)b->alloc(sizeof(int2) * d.items.size());
+        if (!d.d_items) return fail(BF_ERR_HIP, "batch item allocation failed");
+        if ((e = hipMemcpy(d.d_items, d.items.data(), sizeof(int2) * d.items.size(),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "batch item upload");
+        d.grid = std::min<int>((int)d.items.size(), cus * 8);
+    }
+    for (DasClass &d : b->das) {
+        std::stable_sort(d.items.begin(), d.items.end(),
+                         [](const std::pair<double, int2> &x, const std::pair<double, int2> &y) {
+                             return x.first > y.first;
+                         });
+        std::vector<int2> it(d.items.size());
+        for (size_t q = 0; q < it.size(); ++q) it[q] = d.items[q].second;
+        d.n_items = (int)it.size();
+        d.d_items = (int2 *)b->alloc(sizeof(int2) * it.size());
+        if (!d.d_items) return fail(BF_ERR_HIP, "batch item allocation failed");
+        if ((e = hipMemcpy(d.d_items, it.data(), sizeof(int2) * it.size(), hipMemcpyHostToDevice)) !=
+            hipSuccess)
+            return hip_fail(e, "batch item upload");
+        d.grid = std::min(d.n_items, persistent_das_blocks(d.mode, d.et, d.ip, d.threads, d.shm));
+    }
+    for (int k = 0; k < RING; ++k) {
+        if ((e = hipHostMalloc((void **)&b->h_stage[k], sizeof(void *) * 2 * F)) != hipSuccess)
+            return hip_fail(e, "pinned staging allocation");
+        if ((e = hipEventCreateWithFlags(&b->ev[k], hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "event creation");
+    }
+    return BF_OK;
+}
+
+// Copy the frame pointers to the device table (ordered on `s` before the
+// kernels that read it).  A ring of pinned buffers keeps earlier, still
+// pending copies intact.
+static int stage_pointers(Batch *b, const int16_t *const *rf, float *const *out, hipStream_t s)
+{
+    const int k = b->ring;
+    b->ring = (b->ring + 1) % RING;
+    hipError_t e = hipEventSynchronize(b->ev[k]);
+    if (e != hipSuccess) return hip_fail(e, "pointer staging wait");
+    for (int f = 0; f < b->F; ++f) {
+        b->h_stage[k][f] = (void *)rf[f];
+        b->h_stage[k][b->F + f] = (void *)out[f];
+    }
+    if ((e = hipMemcpyAsync(b->d_ptrs, b->h_stage[k], sizeof(void *) * 2 * b->F,
+                            hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_fail(e, "pointer table copy");
+    if ((e = hipEventRecord(b->ev[k], s)) != hipSuccess) return hip_fail(e, "event record");
+    return BF_OK;
+}
+
+// All kernels of one batched pass, in stream order.
+static int enqueue(bf_plan plan, hipStream_t s)
+{
+    Batch *b = plan->batch;
+    const int n_counters = (int)(b->dec.size() + b->das.size());
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, b->d_counters,
+                       n_counters);
+    int ci = 0;
+    for (DecClass &d : b->dec) {
+        DecLaunch L;
+        L.kb = d.kb;
+        L.ot = d.ot;
+        L.grid = d.grid;
+        L.frames = b->d_fdec;
+        L.items = d.d_items;
+        L.n_items = (int)d.items.size();
+        L.counter = b->d_counters + ci++;
+        L.rf_ptrs = b->d_ptrs;
+        hipError_t e = launch_decode_persistent(L, s);
+        if (e != hipSuccess) return hip_fail(e, "persistent decode launch");
+    }
+    for (DasClass &d : b->das) {
+        PersistentLaunch L;
+        L.mode = d.mode;
+        L.et = d.et;
+        L.ip = d.ip;
+        L.grid = d.grid;
+        L.threads = d.threads;
+        L.shm = d.shm;
+        L.frames = b->d_fdas;
+        L.items = d.d_items;
+        L.n_items = d.n_items;
+        L.counter = b->d_counters + ci++;
+        L.out_ptrs = b->d_ptrs + b->F;
+        hipError_t e = launch_das_persistent(L, s);
+        if (e != hipSuccess) return hip_fail(e, "persistent DAS launch");
+    }
+    return BF_OK;
+}
+
+static int check_batch(bf_plan plan, const int16_t *const *rf, float *const *out)
+{
+    if (!plan) return fail(BF_ERR_NULL, "plan is NULL");
+    if (plan->magic != BF_PLAN_MAGIC) return fail(BF_ERR_STATE, "not a live plan");
+    if (!rf || !out) return fail(BF_ERR_NULL, "rf and out pointer arrays must be non-NULL");
+    for (size_t f = 0; f < plan->frames.size(); ++f)
+        if (!rf[f] || !out[f]) return fail(BF_ERR_NULL, "frame %zu has a NULL buffer", f);
+    for (Frame *fr : plan->frames)
+        if (fr->p.decode_algo != BF_DECODE_MFMA_I8)
+            return fail(BF_ERR_UNSUPPORTED, "batched path runs the int8 decode only");
+    if (!plan->batch) {
+        int st = build_batch(plan);
+        if (st != BF_OK) {
+            delete plan->batch;
+            plan->batch = nullptr;
+            return st;
+        }
+    }
+    return BF_OK;
+}
+
+// Frames whose windows do not fit in LDS run as plain launches after the
+// persistent kernels (same stream, so they may also be captured).
+static int enqueue_gather(bf_plan plan, float *const *out, hipStream_t s)
+{
+    for (int f : plan->batch->gather_frames) {
+        const Frame &fr = *plan->frames[f];
+        DasArgs a = fr.das_args(fr.d_e, out[f], fr.p.c);
+        hipError_t e = launch_das(a, fr.p.mode, fr.p.e_type, fr.p.interp, s);
+        if (e != hipSuccess) return hip_fail(e, "DAS launch");
+    }
+    return BF_OK;
+}
+
 }  // namespace bf
 
 using namespace bf;
@@ -23,24 +313,219 @@ int64_t bf_plan_s::workspace_bytes() const
     return b;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner
+// ---------------------------------------------------------------------------
+namespace {
+
+struct TileCand {
+    int lx, ly, lz, bwx, bwy, bwz, nb;
+};
+
+std::vector<TileCand> candidates(const Frame &f)
+{
+    std::vector<TileCand> c;
+    if (f.p.mode == BF_FORCES_2D && f.grid.ny == 1) {
+        const int tiles[][3] = {{3, 0, 3}, {2, 0, 4}, {4, 0, 2}, {1, 0, 5}};
+        const int blocks[][3] = {{2, 1, 2}, {4, 1, 1}, {1, 1, 4}, {2, 1, 1}, {4, 1, 4}};
+        for (auto &t : tiles)
+            for (auto &b : blocks)
+                for (int nb : {8, 16})
+                    c.push_back({t[0], t[1], t[2], b[0], b[1], b[2], nb});
+    } else {
+        const int tiles[][3] = {{3, 3, 0}, {2, 2, 2}, {3, 2, 1}, {2, 3, 1}};
+        const int blocks[][3] = {{2, 2, 2}, {4, 2, 1}, {2, 2, 1}, {4, 4, 1}, {2, 2, 4}};
+        for (auto &t : tiles)
+            for (auto &b : blocks)
+                for (int nb : {8, 16, 32})
+                    c.push_back({t[0], t[1], t[2], b[0], b[1], b[2], nb});
+    }
+    return c;
+}
+
+std::string tune_key(const Frame &f, const char *arch)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s|m%d|tx%d|ch%d|S%d|%dx%dx%d|ip%d|et%d", arch, f.p.mode, f.p.n_tx,
+             f.p.n_ch, f.p.n_samples, f.grid.nx, f.grid.ny, f.grid.nz, f.p.interp, f.p.e_type);
+    return buf;
+}
+
+bool cache_lookup(const char *path, const std::string &key, TileCand *out)
+{
+    FILE *fp = fopen(path, "r");
+    if (!fp) return false;
+    char line[512];
+    bool found = false;
+    while (fgets(line, sizeof line, fp)) {
+        char k[300];
+        TileCand t;
+        if (sscanf(line, "%299s %d %d %d %d %d %d %d", k, &t.lx, &t.ly, &t.lz, &t.bwx, &t.bwy,
+                   &t.bwz, &t.nb) == 8 &&
+            key == k) {
+            *out = t;
+            found = true;      // last entry wins
+        }
+    }
+    fclose(fp);
+    return found;
+}
+
+__global__ void scratch_fill_kernel(float *p, long n)
+{
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (long)gridDim.x * blockDim.x) {
+        uint32_t h = (uint32_t)q * 2654435761u;
+        h ^= h >> 13;
+        h *= 0x5bd1e995u;
+        h ^= h >> 15;
+        p[q] = (float)((int)(h & 0xFFFF) - 32768);
+    }
+}
+
+}  // namespace
+
 extern "C" {
 
 int bf_batch_run(bf_plan plan, const int16_t *const *rf, float *const *out, void *stream)
 {
-    (void)plan; (void)rf; (void)out; (void)stream;
-    return fail(BF_ERR_UNSUPPORTED, "batched path not built yet");
+    int st = check_batch(plan, rf, out);
+    if (st != BF_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = stage_pointers(plan->batch, rf, out, s)) != BF_OK) return st;
+    if ((st = enqueue(plan, s)) != BF_OK) return st;
+    return enqueue_gather(plan, out, s);
 }
 
 int bf_graph_launch(bf_plan plan, const int16_t *const *rf, float *const *out, void *stream)
 {
-    (void)plan; (void)rf; (void)out; (void)stream;
-    return fail(BF_ERR_UNSUPPORTED, "batched path not built yet");
+    int st = check_batch(plan, rf, out);
+    if (st != BF_OK) return st;
+    Batch *b = plan->batch;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = stage_pointers(b, rf, out, s)) != BF_OK) return st;
+    if (!b->gather_frames.empty()) {
+        // their output pointers are kernel arguments: run them outside the graph
+        if ((st = enqueue(plan, s)) != BF_OK) return st;
+        return enqueue_gather(plan, out, s);
+    }
+    hipError_t e;
+    if (!b->exec) {
+        if (!b->cap && (e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "capture stream");
+        if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(e, "graph capture begin");
+        st = enqueue(plan, b->cap);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->cap, &g);
+        if (st != BF_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "graph capture end");
+        b->graph = g;
+        if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess)
+            return hip_fail(e, "graph instantiate");
+    }
+    if ((e = hipGraphLaunch(b->exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+    return BF_OK;
 }
 
 int bf_autotune(bf_plan plan, const char *cache_path)
 {
-    (void)plan; (void)cache_path;
-    return fail(BF_ERR_UNSUPPORTED, "autotuner not built yet");
+    if (!plan) return fail(BF_ERR_NULL, "plan is NULL");
+    if (plan->magic != BF_PLAN_MAGIC) return fail(BF_ERR_STATE, "not a live plan");
+    if (plan->batch) return fail(BF_ERR_STATE, "autotune before the first batched launch");
+    hipDeviceProp_t prop;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    // Tune the first frame of each mode; apply to every frame of that mode.
+    for (int mode = 0; mode < 2; ++mode) {
+        Frame *f0 = nullptr;
+        for (Frame *f : plan->frames)
+            if (f->p.mode == mode) {
+                f0 = f;
+                break;
+            }
+        if (!f0) continue;
+        const std::string key = tune_key(*f0, prop.gcnArchName);
+        TileCand best{};
+        bool have = cache_path && cache_lookup(cache_path, key, &best);
+        if (!have) {
+            float *e_buf = nullptr, *o_buf = nullptr;
+            const size_t e_bytes = (size_t)f0->e_elems() * 4;
+            const size_t o_bytes = (size_t)f0->out_elems() * 4;
+            if (hipMalloc(&e_buf, e_bytes) != hipSuccess) return fail(BF_ERR_HIP, "scratch alloc");
+            if (hipMalloc(&o_buf, o_bytes) != hipSuccess) {
+                (void)hipFree(e_buf);
+                return fail(BF_ERR_HIP, "scratch alloc");
+            }
+            hipLaunchKernelGGL(scratch_fill_kernel, dim3(4096), dim3(256), 0, 0, e_buf,
+                               (long)f0->e_elems());
+            const int saved[7] = {f0->lx, f0->ly, f0->lz, f0->bw[0], f0->bw[1], f0->bw[2], f0->nb};
+            const int saved_variant = f0->variant;
+            const int saved_et = f0->p.e_type;
+            f0->p.e_type = BF_E_F32;
+            f0->variant = 0;
+            hipEvent_t t0, t1;
+            (void)hipEventCreate(&t0);
+            (void)hipEventCreate(&t1);
+            float best_ms = 1e30f;
+            for (const TileCand &t : candidates(*f0)) {
+                f0->set_tile(t.lx, t.ly, t.lz);
+                f0->bw[0] = t.bwx;
+                f0->bw[1] = t.bwy;
+                f0->bw[2] = t.bwz;
+                f0->nb = t.nb;
+                LdsCfg cfg;
+                if (!f0->lds_config(f0->das_args(e_buf, o_buf, f0->p.c), &cfg)) continue;
+                if (f0->das(e_buf, o_buf, f0->p.c, 0) != BF_OK) continue;   // warm-up
+                (void)hipEventRecord(t0, 0);
+                for (int r = 0; r < 3; ++r) (void)f0->das(e_buf, o_buf, f0->p.c, 0);
+                (void)hipEventRecord(t1, 0);
+                (void)hipEventSynchronize(t1);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, t0, t1);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
+            }
+            (void)hipEventDestroy(t0);
+            (void)hipEventDestroy(t1);
+            (void)hipFree(e_buf);
+            (void)hipFree(o_buf);
+            f0->p.e_type = saved_et;
+            f0->variant = saved_variant;
+            if (best_ms >= 1e30f) {
+                f0->set_tile(saved[0], saved[1], saved[2]);
+                f0->bw[0] = saved[3];
+                f0->bw[1] = saved[4];
+                f0->bw[2] = saved[5];
+                f0->nb = saved[6];
+                continue;
+            }
+            if (cache_path) {
+                FILE *fp = fopen(cache_path, "a");
+                if (fp) {
+                    fprintf(fp, "%s %d %d %d %d %d %d %d\n", key.c_str(), best.lx, best.ly, best.lz,
+                            best.bwx, best.bwy, best.bwz, best.nb);
+                    fclose(fp);
+                }
+            }
+        }
+        for (Frame *f : plan->frames)
+            if (f->p.mode == mode) {
+                f->set_tile(best.lx, best.ly, best.lz);
+                f->bw[0] = best.bwx;
+                f->bw[1] = best.bwy;
+                f->bw[2] = best.bwz;
+                f->nb = best.nb;
+            }
+    }
+    return BF_OK;
 }
 
 }  // extern "C"

@@ -25,6 +25,21 @@ struct DecodeArgs {
     int n_tx, n_ch, S;
 };
 
+// One frame of a batch for the persistent decode kernel (rf comes from the
+// per-launch pointer table).
+struct FrameDec {
+    DecodeArgs a;
+};
+
+struct DecLaunch {
+    int kb, ot, grid;
+    const FrameDec *frames;
+    const int2 *items;      // (frame, channel * chunk_groups + chunk_group)
+    int n_items;
+    int *counter;
+    void *const *rf_ptrs;
+};
+
 // ---------------------------------------------------------------------------
 // DAS
 // ---------------------------------------------------------------------------
@@ -53,6 +68,41 @@ struct DasArgs {
     int lx, ly, lz;         // log2 of the wavefront tile along x, y, z (sum 6)
     int tiles_x, tiles_y, tiles_z;
     int n_waves;            // tiles_x * tiles_y * tiles_z
+    int groups;             // channel groups (blockIdx.y); > 1 writes partial images
+    float *part;            // [groups][ny][nx][nz] partial images when groups > 1
+};
+
+// Channel rows [j0, j1) of group g of G.
+__host__ __device__ inline void group_rows(int n_ch, int g, int G, int *j0, int *j1)
+{
+    *j0 = (int)(((long)n_ch * g) / G);
+    *j1 = (int)(((long)n_ch * (g + 1)) / G);
+}
+
+// Workgroup configuration of the LDS-staged DAS kernel.
+struct LdsCfg {
+    int bwx, bwy, bwz;   // wavefront tiles per workgroup along x, y, z
+    int nb;              // traces per batch (FORCES: 4 channel rows x nb/4 transmits)
+    int lmax;            // coefficient quads per staged window
+    int sorted_tx;       // tx_x ascending (enables the per-row transmit range)
+    int blocks_x, blocks_y, blocks_z;
+};
+
+// One frame of a batch for the persistent DAS kernel (device table entry).
+struct FrameDas {
+    DasArgs a;      // out is taken from the per-launch pointer table
+    LdsCfg c;
+};
+
+struct PersistentLaunch {
+    int mode, et, ip;
+    int grid, threads;
+    size_t shm;
+    const FrameDas *frames;
+    const int2 *items;      // (frame, workgroup box)
+    int n_items;
+    int *counter;
+    void *const *out_ptrs;  // [n_frames] device pointers
 };
 
 // Hann window of Eq. 3 as a function of w = u^2 on [0, 1/4): a degree-6

@@ -63,11 +63,11 @@ __device__ inline float read_trace(const void *tr, int S, int nB, float s)
 // FORCES: the transmit and receive excess paths separate, so the receive term
 // and its apodization are computed once per (point, channel).
 template <int ET, int IP>
-__device__ inline float das_forces_point(const DasArgs &a, const Lane &L)
+__device__ inline float das_forces_point(const DasArgs &a, const Lane &L, int jb, int je)
 {
     const float kf = (float)a.k;
     float acc = 0.f;
-    for (int j = 0; j < a.n_ch; ++j) {
+    for (int j = jb; j < je; ++j) {
         const float dxr = L.x - a.rx_c[j];
         const float r2 = dxr * dxr;
         const bool act = L.active && r2 < L.thr;
@@ -89,11 +89,11 @@ __device__ inline float das_forces_point(const DasArgs &a, const Lane &L)
 // HERCULES: receive element (x_i, y_j, 0), plane-wave transmit (tof_tx = z/c,
 // already inside B), radial apodization.
 template <int ET, int IP>
-__device__ inline float das_hercules_point(const DasArgs &a, const Lane &L)
+__device__ inline float das_hercules_point(const DasArgs &a, const Lane &L, int jb, int je)
 {
     const float kf = (float)a.k;
     float acc = 0.f;
-    for (int j = 0; j < a.n_ch; ++j) {
+    for (int j = jb; j < je; ++j) {
         const float dy = L.y - a.rx_c[j];
         const float dy2 = dy * dy;
         if (!__any(L.active && dy2 < L.thr)) continue;
@@ -120,18 +120,47 @@ __global__ __launch_bounds__(256) void das_kernel(DasArgs a)
     const int wave_id = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (wave_id >= a.n_waves) return;
     const Lane L = lane_setup(a, wave_id, threadIdx.x & 63);
+    int jb, je;
+    group_rows(a.n_ch, blockIdx.y, a.groups, &jb, &je);
     float acc;
     if constexpr (MODE == 0)
-        acc = das_forces_point<ET, IP>(a, L);
+        acc = das_forces_point<ET, IP>(a, L, jb, je);
     else
-        acc = das_hercules_point<ET, IP>(a, L);
-    if (L.valid) a.out[L.out_idx] = L.active ? acc : 0.f;
+        acc = das_hercules_point<ET, IP>(a, L, jb, je);
+    if (L.valid) {
+        const float v = L.active ? acc : 0.f;
+        if (a.groups > 1)
+            a.part[(long)blockIdx.y * a.g.nx * a.g.ny * a.g.nz + L.out_idx] = v;
+        else
+            a.out[L.out_idx] = v;
+    }
+}
+
+// Sum of the channel-group partial images in group order (deterministic).
+__global__ __launch_bounds__(256) void sum_groups_kernel(const float *part, float *out, long n,
+                                                         int G)
+{
+    for (long q = (long)blockIdx.x * 256 + threadIdx.x; q < n; q += (long)gridDim.x * 256) {
+        float s = 0.f;
+        for (int g = 0; g < G; ++g) s += part[(long)g * n + q];
+        out[q] = s;
+    }
+}
+
+hipError_t launch_sum_groups(const DasArgs &a, hipStream_t s)
+{
+    const long n = (long)a.g.nx * a.g.ny * a.g.nz;
+    long blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(sum_groups_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a.part, a.out,
+                       n, a.groups);
+    return hipGetLastError();
 }
 
 template <int MODE, int ET>
 static hipError_t launch_ip(const DasArgs &a, int ip, hipStream_t s)
 {
-    dim3 grid((a.n_waves + 3) / 4);
+    dim3 grid((a.n_waves + 3) / 4, a.groups);
     switch (ip) {
         case IN_NEAREST: hipLaunchKernelGGL((das_kernel<MODE, ET, IN_NEAREST>), grid, dim3(256), 0, s, a); break;
         case IN_LINEAR: hipLaunchKernelGGL((das_kernel<MODE, ET, IN_LINEAR>), grid, dim3(256), 0, s, a); break;
@@ -154,7 +183,9 @@ static hipError_t launch_et(const DasArgs &a, int et, int ip, hipStream_t s)
 
 hipError_t launch_das(const DasArgs &a, int mode, int et, int ip, hipStream_t s)
 {
-    return mode == 0 ? launch_et<0>(a, et, ip, s) : launch_et<1>(a, et, ip, s);
+    hipError_t err = mode == 0 ? launch_et<0>(a, et, ip, s) : launch_et<1>(a, et, ip, s);
+    if (err != hipSuccess || a.groups <= 1) return err;
+    return launch_sum_groups(a, s);
 }
 
 }  // namespace bf

@@ -1,0 +1,640 @@
+// bf_das_lds.hip -- delay-and-sum with LDS-staged trace windows (gfx950).
+//
+// A workgroup owns a box of output points (a grid of 64-lane wavefront
+// tiles).  It walks the (transmit, channel) traces in batches; for every
+// trace of a batch it stages, once, the window of samples that any point of
+// the box can read -- bounded from the box geometry, since the delay grows
+// with depth and with lateral distance -- as cubic-Hermite coefficient quads
+// (c0, c1, c2, c3) per sample interval, with zeros outside the record.  Each
+// term of Eq. 1 then costs one aligned 16-byte LDS read and three FMAs for
+// the read (Sec. IV-B) instead of four bounds-checked global loads.  The
+// global loads of the next batch are issued before the current batch is
+// beamformed (double-buffered LDS, one barrier per batch), and they read
+// contiguous runs along fast time.
+//
+// Apodization skip (Sec. VII-F): a channel row is staged only if the receive
+// aperture of the deepest point of the box reaches it; within a row only the
+// transmits whose lateral offset can fall inside that aperture are staged
+// (HERCULES); each wavefront additionally skips traces outside the union of
+// its own lanes' apertures with a scalar test.
+//
+// Delay precision: as in the gather kernel, s = B(p) + k (E_tx + E_rx) with
+// B in FP64 split into integer + FP32 fraction and E = rho^2 / (d + z) in FP32.
+#include "bf_common.h"
+
+namespace bf {
+
+hipError_t launch_sum_groups(const DasArgs &a, hipStream_t s);
+
+constexpr int JC = 4;    // FORCES channel rows per batch
+
+struct Meta {
+    int w0;      // first sample interval of the window
+    int on;      // trace staged
+    float xi;    // x of the transmit column
+    int pad;
+};
+
+// Uniform description of one batch.
+struct BatchDesc {
+    int valid;
+    int i0, cnt;          // transmits i0 .. i0+cnt-1
+    int j;                // HERCULES: channel row
+    int rows[JC];         // FORCES: channel rows (-1 = none)
+};
+
+struct BoxGeom {
+    float xmin, xmax, ymin, ymax, zmin, zmax;
+};
+
+__device__ inline float wave_min(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline float wave_max(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ inline int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline float uniform_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// Lane state with benign values for points outside the grid or at z <= 0
+// (never active, finite arithmetic).
+struct LaneL {
+    bool valid;
+    long out_idx;
+    float x, y, z, z2, thr, wsc, fB;
+    int nB;
+};
+
+__device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, int by, int bz,
+                                     int wave, int lane)
+{
+    LaneL L;
+    const int wz = wave % c.bwz, wx = (wave / c.bwz) % c.bwx, wy = wave / (c.bwz * c.bwx);
+    const int lz = lane & ((1 << a.lz) - 1);
+    const int lx = (lane >> a.lz) & ((1 << a.lx) - 1);
+    const int ly = lane >> (a.lz + a.lx);
+    const int ix = ((bx * c.bwx + wx) << a.lx) + lx;
+    const int iy = ((by * c.bwy + wy) << a.ly) + ly;
+    const int iz = ((bz * c.bwz + wz) << a.lz) + lz;
+    L.valid = ix < a.g.nx && iy < a.g.ny && iz < a.g.nz;
+    L.out_idx = ((long)iy * a.g.nx + ix) * a.g.nz + iz;
+    const double px = a.g.org[0] + ix * a.g.ax[0] + iy * a.g.ay[0] + iz * a.g.az[0];
+    const double py = a.g.org[1] + ix * a.g.ax[1] + iy * a.g.ay[1] + iz * a.g.az[1];
+    const double pz = a.g.org[2] + ix * a.g.ax[2] + iy * a.g.ay[2] + iz * a.g.az[2];
+    if (L.valid && pz > 0.0) {
+        const double B = 2.0 * pz * a.k - a.t0fs;
+        const double fl = floor(B);
+        L.nB = (int)fl;
+        L.fB = (float)(B - fl);
+        L.x = (float)px;
+        L.y = (float)py;
+        L.z = (float)pz;
+        L.z2 = L.z * L.z;
+        L.thr = a.f2 > 0.f ? L.z2 * 0.25f / a.f2 : __builtin_inff();
+        L.wsc = a.f2 > 0.f ? a.f2 / L.z2 : 0.f;
+    } else {
+        L.nB = 0;
+        L.fB = 0.f;
+        L.x = L.y = 0.f;
+        L.z = L.z2 = 1.f;
+        L.thr = -1.f;
+        L.wsc = 0.f;
+    }
+    return L;
+}
+
+// Array-frame bounding box of the workgroup's points (clamped to the grid).
+__device__ inline BoxGeom block_box(const DasArgs &a, const LdsCfg &c, int bx, int by, int bz)
+{
+    const int tx = c.bwx << a.lx, ty = c.bwy << a.ly, tz = c.bwz << a.lz;
+    const int i0[3] = {bx * tx, by * ty, bz * tz};
+    const int i1[3] = {min(bx * tx + tx - 1, a.g.nx - 1), min(by * ty + ty - 1, a.g.ny - 1),
+                       min(bz * tz + tz - 1, a.g.nz - 1)};
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int q = 0; q < 8; ++q) {
+        const int ix = (q & 1) ? i1[0] : i0[0];
+        const int iy = (q & 2) ? i1[1] : i0[1];
+        const int iz = (q & 4) ? i1[2] : i0[2];
+        for (int r = 0; r < 3; ++r) {
+            const double v = a.g.org[r] + ix * a.g.ax[r] + iy * a.g.ay[r] + iz * a.g.az[r];
+            lo[r] = fmin(lo[r], v);
+            hi[r] = fmax(hi[r], v);
+        }
+    }
+    BoxGeom b;
+    b.xmin = (float)lo[0]; b.xmax = (float)hi[0];
+    b.ymin = (float)lo[1]; b.ymax = (float)hi[1];
+    b.zmin = (float)lo[2]; b.zmax = (float)hi[2];
+    return b;
+}
+
+__device__ inline float dist_to_range(float v, float lo, float hi)
+{
+    return fmaxf(0.f, fmaxf(lo - v, v - hi));
+}
+__device__ inline float far_to_range(float v, float lo, float hi)
+{
+    return fmaxf(fabsf(v - lo), fabsf(v - hi));
+}
+
+// First sample interval of the staged window of one trace for the box.
+template <int MODE>
+__device__ inline int window_start(const DasArgs &a, const BoxGeom &b, float xi, float cj)
+{
+    const float zlo = fmaxf(b.zmin, 0.f);
+    float path;
+    if constexpr (MODE == 0) {
+        const float rt = dist_to_range(xi, b.xmin, b.xmax);
+        const float rr = dist_to_range(cj, b.xmin, b.xmax);
+        path = sqrtf(rt * rt + zlo * zlo) + sqrtf(rr * rr + zlo * zlo);
+    } else {
+        const float rx = dist_to_range(xi, b.xmin, b.xmax);
+        const float ry = dist_to_range(cj, b.ymin, b.ymax);
+        path = zlo + sqrtf(rx * rx + ry * ry + zlo * zlo);
+    }
+    const float s = path * (float)a.k - (float)a.t0fs;
+    return (int)floorf(s) - 2;
+}
+
+// Is channel row j reachable by the receive aperture of any point of the box?
+// For HERCULES also returns the lateral reach R of the aperture along x.
+template <int MODE>
+__device__ inline bool row_active(const DasArgs &a, const BoxGeom &b, float cj, float *R)
+{
+    if (b.zmax <= 0.f) return false;
+    if (a.f2 <= 0.f) {
+        *R = __builtin_inff();
+        return true;
+    }
+    const float thr = b.zmax * b.zmax * 0.25f / a.f2;
+    const float d = MODE == 0 ? dist_to_range(cj, b.xmin, b.xmax) : dist_to_range(cj, b.ymin, b.ymax);
+    const float r2 = thr - d * d;
+    *R = sqrtf(fmaxf(r2, 0.f));
+    return r2 > 0.f;
+}
+
+// Transmit range [lo, hi) whose column x lies in [xl, xh] (ascending tx_x).
+__device__ inline void tx_range(const float *tx, int n, float xl, float xh, int *lo, int *hi)
+{
+    int a0 = 0, b0 = n;                   // first index with tx >= xl
+    while (a0 < b0) {
+        const int m = (a0 + b0) >> 1;
+        if (tx[m] < xl) a0 = m + 1; else b0 = m;
+    }
+    int a1 = a0, b1 = n;                  // first index with tx > xh
+    while (a1 < b1) {
+        const int m = (a1 + b1) >> 1;
+        if (tx[m] <= xh) a1 = m + 1; else b1 = m;
+    }
+    *lo = a0;
+    *hi = a1;
+}
+
+// Batch iterator (uniform across the workgroup).
+struct Iter {
+    int jend;    // end of this workgroup's channel rows
+    int j;       // current channel row (HERCULES) / next row to scan (FORCES)
+    int i;       // next transmit
+    int ihi;     // end of the current row's transmit range (HERCULES)
+    int rows[JC];
+};
+
+template <int MODE>
+__device__ inline BatchDesc next_batch(const DasArgs &a, const LdsCfg &c, const BoxGeom &b,
+                                       const float *s_tx, const float *s_rx, Iter &it)
+{
+    BatchDesc d;
+    d.valid = 0;
+    if constexpr (MODE == 1) {
+        while (it.i >= it.ihi) {          // advance to the next active row
+            ++it.j;
+            if (it.j >= it.jend) return d;
+            float R;
+            if (!row_active<1>(a, b, s_rx[it.j], &R)) continue;
+            if (c.sorted_tx && isfinite(R)) {
+                tx_range(s_tx, a.n_tx, b.xmin - R, b.xmax + R, &it.i, &it.ihi);
+            } else {
+                it.i = 0;
+                it.ihi = a.n_tx;
+            }
+        }
+        d.valid = 1;
+        d.j = it.j;
+        d.i0 = it.i;
+        d.cnt = min(c.nb, it.ihi - it.i);
+        it.i += d.cnt;
+        return d;
+    } else {
+        const int nbi = c.nb / JC;
+        if (it.i >= a.n_tx) {             // next chunk of JC active rows
+            int n = 0;
+            for (int q = 0; q < JC; ++q) it.rows[q] = -1;
+            while (n < JC && it.j < it.jend) {
+                float R;
+                if (row_active<0>(a, b, s_rx[it.j], &R)) it.rows[n++] = it.j;
+                ++it.j;
+            }
+            if (n == 0) return d;
+            it.i = 0;
+        }
+        d.valid = 1;
+        for (int q = 0; q < JC; ++q) d.rows[q] = it.rows[q];
+        d.i0 = it.i;
+        d.cnt = min(nbi, a.n_tx - it.i);
+        it.i += d.cnt;
+        return d;
+    }
+}
+
+template <int MODE>
+__device__ inline void slot_trace(const BatchDesc &d, const LdsCfg &c, int e, int *i, int *j)
+{
+    if constexpr (MODE == 1) {
+        *i = d.i0 + e;
+        *j = e < d.cnt ? d.j : -1;
+    } else {
+        const int nbi = c.nb / JC;
+        const int ii = e % nbi, jj = e / nbi;
+        *i = d.i0 + ii;
+        *j = (ii < d.cnt) ? d.rows[jj] : -1;
+    }
+}
+
+constexpr int QMAX = 4;   // staged quads per thread per batch (host guarantees)
+
+struct Staged {
+    float p[QMAX][4];
+};
+
+// Issue the global loads of a batch's windows (taps n-1..n+2 of every quad).
+template <int MODE, int ET>
+__device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const BoxGeom &b,
+                                  const float *s_tx, const float *s_rx, const BatchDesc &d,
+                                  Staged &st, int tid, int nthr)
+{
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+        const int idx = tid + q * nthr;
+        float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+        if (idx < c.nb * c.lmax) {
+            const int e = idx / c.lmax, m = idx - e * c.lmax;
+            int i, j;
+            slot_trace<MODE>(d, c, e, &i, &j);
+            if (j >= 0) {
+                const int w0 = window_start<MODE>(a, b, s_tx[i], s_rx[j]);
+                const int n = w0 + m;
+                const void *tr = trace_ptr<ET>(a.e, (long)i * a.n_ch + j, a.S);
+                const unsigned S = (unsigned)a.S;
+                p0 = ((unsigned)(n - 1) < S) ? load_e<ET>(tr, n - 1) : 0.f;
+                p1 = ((unsigned)n < S) ? load_e<ET>(tr, n) : 0.f;
+                p2 = ((unsigned)(n + 1) < S) ? load_e<ET>(tr, n + 1) : 0.f;
+                p3 = ((unsigned)(n + 2) < S) ? load_e<ET>(tr, n + 2) : 0.f;
+            }
+        }
+        st.p[q][0] = p0;
+        st.p[q][1] = p1;
+        st.p[q][2] = p2;
+        st.p[q][3] = p3;
+    }
+}
+
+// Convert the loaded taps to coefficient quads and write them (and the
+// per-trace metadata) to one LDS buffer.
+template <int MODE, int IP>
+__device__ inline void stage_store(const DasArgs &a, const LdsCfg &c, const BoxGeom &b,
+                                   const float *s_tx, const float *s_rx, const BatchDesc &d,
+                                   const Staged &st, float4 *quads, Meta *meta, int tid, int nthr)
+{
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+        const int idx = tid + q * nthr;
+        if (idx < c.nb * c.lmax) {
+            const float pm = st.p[q][0], p0 = st.p[q][1], p1 = st.p[q][2], p2 = st.p[q][3];
+            float4 cq;
+            if constexpr (IP == IN_CUBIC) {
+                cq.x = p0;
+                cq.y = 0.5f * (p1 - pm);
+                cq.z = pm - 2.5f * p0 + 2.0f * p1 - 0.5f * p2;
+                cq.w = 0.5f * (p2 - pm) + 1.5f * (p0 - p1);
+            } else if constexpr (IP == IN_LINEAR) {
+                cq = make_float4(p0, p1 - p0, 0.f, 0.f);
+            } else {
+                cq = make_float4(p0, p1, 0.f, 0.f);
+            }
+            quads[idx] = cq;
+            const int e = idx / c.lmax, m = idx - e * c.lmax;
+            if (m == 0) {
+                int i, j;
+                slot_trace<MODE>(d, c, e, &i, &j);
+                Meta mt;
+                mt.on = j >= 0;
+                mt.xi = mt.on ? s_tx[i] : 0.f;
+                mt.w0 = mt.on ? window_start<MODE>(a, b, s_tx[i], s_rx[j]) : 0;
+                mt.pad = 0;
+                meta[e] = mt;
+            }
+        }
+    }
+}
+
+template <int IP>
+__device__ inline float read_quad(const float4 *win, int li, int lmax, float t)
+{
+    li = min(max(li, 0), lmax - 1);
+    const float4 q = win[li];
+    if constexpr (IP == IN_NEAREST) return t < 0.5f ? q.x : q.y;
+    if constexpr (IP == IN_LINEAR) return fmaf(t, q.y, q.x);
+    return fmaf(t, fmaf(t, fmaf(t, q.w, q.z), q.y), q.x);
+}
+
+// Beamforms workgroup box `blk` (channel group `grp`) of one frame.  Every
+// thread of the workgroup must call it (it contains barriers).
+template <int MODE, int ET, int IP>
+__device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int grp,
+                                 float4 *smem)
+{
+    const int nthr = blockDim.x;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+
+    // tables: tx_x, rx_c, then two buffers of [nb] Meta + [nb * lmax] quads
+    float *s_tx = reinterpret_cast<float *>(smem);
+    float *s_rx = s_tx + ((a.n_tx + 3) & ~3);
+    float4 *bufbase = reinterpret_cast<float4 *>(s_rx + ((a.n_ch + 3) & ~3));
+    const int buf_quads = c.nb * c.lmax + c.nb;   // Meta is 16 bytes = one float4
+    float4 *q0 = bufbase, *q1 = bufbase + buf_quads;
+    for (int t = tid; t < a.n_tx; t += nthr) s_tx[t] = a.tx_x[t];
+    for (int t = tid; t < a.n_ch; t += nthr) s_rx[t] = a.rx_c[t];
+
+    const int bz = blk % c.blocks_z;
+    const int bx = (blk / c.blocks_z) % c.blocks_x;
+    const int by = blk / (c.blocks_z * c.blocks_x);
+    const BoxGeom box = block_box(a, c, bx, by, bz);
+    const LaneL L = lane_setup_l(a, c, bx, by, bz, wave, lane);
+    const float kf = (float)a.k;
+    float acc = 0.f;
+    __syncthreads();
+
+    int jb, je;
+    group_rows(a.n_ch, grp, a.groups, &jb, &je);
+    Iter it;
+    it.j = MODE == 1 ? jb - 1 : jb;
+    it.jend = je;
+    it.i = MODE == 1 ? 0 : a.n_tx;
+    it.ihi = 0;
+    for (int q = 0; q < JC; ++q) it.rows[q] = -1;
+
+    BatchDesc cur = next_batch<MODE>(a, c, box, s_tx, s_rx, it);
+    Staged st;
+    if (cur.valid) {
+        stage_load<MODE, ET>(a, c, box, s_tx, s_rx, cur, st, tid, nthr);
+        stage_store<MODE, IP>(a, c, box, s_tx, s_rx, cur, st, q0 + c.nb,
+                              reinterpret_cast<Meta *>(q0), tid, nthr);
+    }
+    __syncthreads();
+
+    // per-row lane state
+    int row_j = -1;
+    float dy2 = 0.f, wlo = 0.f, whi = 0.f;              // HERCULES
+    int rows_cur[JC];
+    float Rj[JC], aj[JC];
+    bool row_on[JC];
+    for (int q = 0; q < JC; ++q) { rows_cur[q] = -1; Rj[q] = 0.f; aj[q] = 0.f; row_on[q] = false; }
+
+    int bi = 0;
+    while (cur.valid) {
+        BatchDesc nxt = next_batch<MODE>(a, c, box, s_tx, s_rx, it);
+        if (nxt.valid) stage_load<MODE, ET>(a, c, box, s_tx, s_rx, nxt, st, tid, nthr);
+
+        float4 *qb = (bi & 1) ? q1 : q0;
+        const Meta *meta = reinterpret_cast<const Meta *>(qb);
+        const float4 *quads = qb + c.nb;
+        // Lane l holds the metadata of trace slot l of the batch; terms read it
+        // with v_readlane (no LDS round trip per term).
+        const Meta mine = lane < c.nb ? meta[lane] : Meta{0, 0, 0.f, 0};
+        if constexpr (MODE == 1) {
+            if (cur.j != row_j) {
+                row_j = cur.j;
+                const float dy = L.y - s_rx[row_j];
+                dy2 = dy * dy;
+                const float r2 = L.thr - dy2;
+                const float r = r2 > 0.f ? sqrtf(r2) : 0.f;
+                wlo = uniform_f(wave_min(r2 > 0.f ? L.x - r : __builtin_inff()));
+                whi = uniform_f(wave_max(r2 > 0.f ? L.x + r : -__builtin_inff()));
+            }
+            // traces inside the union of this wavefront's receive apertures
+            uint64_t mask = __ballot(lane < cur.cnt && mine.xi >= wlo && mine.xi <= whi);
+            while (mask) {
+                const int e1 = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                const bool two = mask != 0;
+                const int e2 = two ? __builtin_ctzll(mask) : e1;
+                if (two) mask &= mask - 1;
+                const float x1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.xi), e1));
+                const float x2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.xi), e2));
+                const int w01 = __builtin_amdgcn_readlane(mine.w0, e1);
+                const int w02 = __builtin_amdgcn_readlane(mine.w0, e2);
+                const float dxa = L.x - x1, dxb = L.x - x2;
+                const float ra = fmaf(dxa, dxa, dy2), rb = fmaf(dxb, dxb, dy2);
+                const float sa = fmaf(excess(ra, L.z, L.z2), kf, L.fB);
+                const float sb = fmaf(excess(rb, L.z, L.z2), kf, L.fB);
+                const float fa = floorf(sa), fb = floorf(sb);
+                const float va = read_quad<IP>(quads + e1 * c.lmax, (int)fa + L.nB - w01, c.lmax, sa - fa);
+                const float vb = read_quad<IP>(quads + e2 * c.lmax, (int)fb + L.nB - w02, c.lmax, sb - fb);
+                const float wa = ra < L.thr ? hann_u2(ra * L.wsc) : 0.f;
+                const float wb = (two && rb < L.thr) ? hann_u2(rb * L.wsc) : 0.f;
+                acc = fmaf(wa, va, acc);
+                acc = fmaf(wb, vb, acc);
+            }
+        } else {
+            const int nbi = c.nb / JC;
+#pragma unroll
+            for (int q = 0; q < JC; ++q) {
+                if (cur.rows[q] != rows_cur[q]) {
+                    rows_cur[q] = cur.rows[q];
+                    if (rows_cur[q] >= 0) {
+                        const float dxr = L.x - s_rx[rows_cur[q]];
+                        const float r2 = dxr * dxr;
+                        const bool act = r2 < L.thr;
+                        Rj[q] = fmaf(excess(r2, L.z, L.z2), kf, L.fB);
+                        aj[q] = act ? hann_u2(r2 * L.wsc) : 0.f;
+                        row_on[q] = __any(act);
+                    } else {
+                        row_on[q] = false;
+                    }
+                }
+            }
+            for (int ii = 0; ii < cur.cnt; ++ii) {
+                const float xi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.xi), ii));
+                const float dxt = L.x - xi;
+                const float T = kf * excess(dxt * dxt, L.z, L.z2);
+#pragma unroll
+                for (int q = 0; q < JC; ++q) {
+                    if (!row_on[q]) continue;
+                    const int e = q * nbi + ii;
+                    const int w0 = __builtin_amdgcn_readlane(mine.w0, e);
+                    const float sq = Rj[q] + T;
+                    const float fl = floorf(sq);
+                    const float v = read_quad<IP>(quads + e * c.lmax, (int)fl + L.nB - w0, c.lmax, sq - fl);
+                    acc = fmaf(aj[q], v, acc);
+                }
+            }
+        }
+
+        if (!nxt.valid) break;
+        float4 *nb_ = ((bi + 1) & 1) ? q1 : q0;
+        stage_store<MODE, IP>(a, c, box, s_tx, s_rx, nxt, st, nb_ + c.nb,
+                              reinterpret_cast<Meta *>(nb_), tid, nthr);
+        __syncthreads();
+        cur = nxt;
+        ++bi;
+    }
+    if (L.valid) {
+        if (a.groups > 1)
+            a.part[(long)grp * a.g.nx * a.g.ny * a.g.nz + L.out_idx] = acc;
+        else
+            a.out[L.out_idx] = acc;
+    }
+}
+
+template <int MODE, int ET, int IP>
+__global__ __launch_bounds__(1024) void das_lds_kernel(DasArgs a, LdsCfg c)
+{
+    extern __shared__ float4 smem[];
+    das_block<MODE, ET, IP>(a, c, blockIdx.x, blockIdx.y, smem);
+}
+
+// Persistent form for a batch of frames: each workgroup pulls (frame, box)
+// items from a queue until it is empty.  Items are ordered by decreasing
+// cost on the host, so the queue balances uneven frames.
+template <int MODE, int ET, int IP>
+__global__ __launch_bounds__(1024) void das_persistent_kernel(const FrameDas *frames,
+                                                              const int2 *items, int n_items,
+                                                              int *counter,
+                                                              void *const *out_ptrs)
+{
+    extern __shared__ float4 smem[];
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= n_items) break;
+        const int2 w = items[item];
+        DasArgs a = frames[w.x].a;
+        a.out = static_cast<float *>(out_ptrs[w.x]);
+        das_block<MODE, ET, IP>(a, frames[w.x].c, w.y, 0, smem);
+        __syncthreads();
+    }
+}
+
+template <int MODE, int ET, int IP>
+static hipError_t launch_persistent3(const PersistentLaunch &p, hipStream_t s)
+{
+    hipLaunchKernelGGL((das_persistent_kernel<MODE, ET, IP>), dim3(p.grid), dim3(p.threads),
+                       p.shm, s, p.frames, p.items, p.n_items, p.counter, p.out_ptrs);
+    return hipGetLastError();
+}
+
+template <int MODE, int ET>
+static hipError_t launch_persistent2(const PersistentLaunch &p, hipStream_t s)
+{
+    switch (p.ip) {
+        case IN_NEAREST: return launch_persistent3<MODE, ET, IN_NEAREST>(p, s);
+        case IN_LINEAR: return launch_persistent3<MODE, ET, IN_LINEAR>(p, s);
+        case IN_CUBIC: return launch_persistent3<MODE, ET, IN_CUBIC>(p, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int MODE>
+static hipError_t launch_persistent1(const PersistentLaunch &p, hipStream_t s)
+{
+    switch (p.et) {
+        case ET_F32: return launch_persistent2<MODE, ET_F32>(p, s);
+        case ET_BF16: return launch_persistent2<MODE, ET_BF16>(p, s);
+        case ET_I32: return launch_persistent2<MODE, ET_I32>(p, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_das_persistent(const PersistentLaunch &p, hipStream_t s)
+{
+    return p.mode == 0 ? launch_persistent1<0>(p, s) : launch_persistent1<1>(p, s);
+}
+
+// Workgroups of the persistent DAS kernel that fit on the device at once.
+int persistent_das_blocks(int mode, int et, int ip, int threads, size_t shm)
+{
+    int dev = 0, cus = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const void *fn = nullptr;
+    if (mode == 0 && et == ET_F32 && ip == IN_CUBIC)
+        fn = reinterpret_cast<const void *>(&das_persistent_kernel<0, ET_F32, IN_CUBIC>);
+    else if (mode == 1 && et == ET_F32 && ip == IN_CUBIC)
+        fn = reinterpret_cast<const void *>(&das_persistent_kernel<1, ET_F32, IN_CUBIC>);
+    if (fn && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, shm) == hipSuccess &&
+        per > 0)
+        return cus * per;
+    return cus * 2;
+}
+
+template <int MODE, int ET>
+static hipError_t launch_lds_ip(const DasArgs &a, const LdsCfg &c, int ip, size_t shm,
+                                hipStream_t s)
+{
+    const int nthr = 64 * c.bwx * c.bwy * c.bwz;
+    dim3 grid(c.blocks_x * c.blocks_y * c.blocks_z, a.groups);
+    switch (ip) {
+        case IN_NEAREST:
+            hipLaunchKernelGGL((das_lds_kernel<MODE, ET, IN_NEAREST>), grid, dim3(nthr), shm, s, a, c);
+            break;
+        case IN_LINEAR:
+            hipLaunchKernelGGL((das_lds_kernel<MODE, ET, IN_LINEAR>), grid, dim3(nthr), shm, s, a, c);
+            break;
+        case IN_CUBIC:
+            hipLaunchKernelGGL((das_lds_kernel<MODE, ET, IN_CUBIC>), grid, dim3(nthr), shm, s, a, c);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_lds_et(const DasArgs &a, const LdsCfg &c, int et, int ip, size_t shm,
+                                hipStream_t s)
+{
+    switch (et) {
+        case ET_F32: return launch_lds_ip<MODE, ET_F32>(a, c, ip, shm, s);
+        case ET_BF16: return launch_lds_ip<MODE, ET_BF16>(a, c, ip, shm, s);
+        case ET_I32: return launch_lds_ip<MODE, ET_I32>(a, c, ip, shm, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax)
+{
+    return (size_t)(((n_tx + 3) & ~3) + ((n_ch + 3) & ~3)) * 4 + 2 * (size_t)(nb * lmax + nb) * 16;
+}
+
+hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, int ip,
+                          hipStream_t s)
+{
+    const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax);
+    hipError_t err = mode == 0 ? launch_lds_et<0>(a, c, et, ip, shm, s)
+                               : launch_lds_et<1>(a, c, et, ip, shm, s);
+    if (err != hipSuccess || a.groups <= 1) return err;
+    return launch_sum_groups(a, s);
+}
+
+}  // namespace bf

@@ -172,6 +172,75 @@ __global__ __launch_bounds__(256) void decode_mfma_kernel(DecodeArgs a, int n_ch
     decode_item<KB, OT>(a, lds_A, lds_cs, blockIdx.y, chunk, threadIdx.x & 63);
 }
 
+// Persistent form for a batch of frames of one 32-wide K-block class: each
+// workgroup pulls (frame, channel, 4 chunks) items from a queue; the operand
+// tables are restaged in LDS only when the frame changes (items are grouped
+// by frame).
+template <int KB, int OT>
+__global__ __launch_bounds__(256) void decode_persistent_kernel(const FrameDec *frames,
+                                                                const int2 *items, int n_items,
+                                                                int *counter,
+                                                                void *const *rf_ptrs)
+{
+    __shared__ v4i lds_A[KB * KB * 64];
+    __shared__ int lds_cs[KB * 32];
+    __shared__ int s_item;
+    int staged = -1;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= n_items) break;
+        const int2 w = items[item];
+        DecodeArgs a = frames[w.x].a;
+        a.rf = static_cast<const int16_t *>(rf_ptrs[w.x]);
+        if (w.x != staged) {
+            stage_operands<KB>(a, lds_A, lds_cs);
+            staged = w.x;
+        }
+        const int n_chunks = (a.S + 63) / 64;
+        const int n_cg = (n_chunks + 3) / 4;
+        const int j = w.y / n_cg;
+        const int chunk = (w.y % n_cg) * 4 + (threadIdx.x >> 6);
+        if (chunk < n_chunks) decode_item<KB, OT>(a, lds_A, lds_cs, j, chunk, threadIdx.x & 63);
+    }
+}
+
+template <int KB, int OT>
+static hipError_t launch_dec_persistent(const DecLaunch &p, hipStream_t s)
+{
+    hipLaunchKernelGGL((decode_persistent_kernel<KB, OT>), dim3(p.grid), dim3(256), 0, s,
+                       p.frames, p.items, p.n_items, p.counter, p.rf_ptrs);
+    return hipGetLastError();
+}
+
+template <int OT>
+static hipError_t launch_dec_persistent_kb(const DecLaunch &p, hipStream_t s)
+{
+    switch (p.kb) {
+        case 1: return launch_dec_persistent<1, OT>(p, s);
+        case 2: return launch_dec_persistent<2, OT>(p, s);
+        case 3: return launch_dec_persistent<3, OT>(p, s);
+        case 4: return launch_dec_persistent<4, OT>(p, s);
+        case 5: return launch_dec_persistent<5, OT>(p, s);
+        case 6: return launch_dec_persistent<6, OT>(p, s);
+        case 7: return launch_dec_persistent<7, OT>(p, s);
+        case 8: return launch_dec_persistent<8, OT>(p, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_decode_persistent(const DecLaunch &p, hipStream_t s)
+{
+    switch (p.ot) {
+        case ET_F32: return launch_dec_persistent_kb<ET_F32>(p, s);
+        case ET_BF16: return launch_dec_persistent_kb<ET_BF16>(p, s);
+        case ET_I32: return launch_dec_persistent_kb<ET_I32>(p, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 // FP32 FMA decode (precision-study variant): one lane per (j, t), 32 outputs
 // per pass; the +-1 coefficients are wave-uniform scalar loads.
 template <int OT>

@@ -23,6 +23,12 @@ struct Frame {
     int kb = 1;                  // 32-wide K blocks of the int8 decode
     Grid grid;
     int lx = 2, ly = 2, lz = 2;  // DAS wavefront tile (log2)
+    int bw[3] = {4, 4, 1};       // wavefront tiles per LDS workgroup (x, y, z)
+    int nb = 16;                 // traces per staged batch
+    int variant = 0;             // 0 = LDS-staged windows, 1 = direct gather
+    int sorted_tx = 0;           // transmit columns ascending
+    int groups = 1;              // channel groups of the DAS launch (small grids)
+    float *d_part = nullptr;     // [groups][points] partial images
     long max_blocks = 0;
     int8_t *d_At = nullptr;
     int *d_colsum = nullptr;
@@ -42,11 +48,17 @@ struct Frame {
     size_t e_bytes() const;
     DecodeArgs decode_args(const int16_t *rf, void *e) const;
     DasArgs das_args(const void *e, float *out, double c) const;
+    bool lds_config(const DasArgs &a, LdsCfg *cfg) const;
     int decode(const int16_t *rf, void *e, hipStream_t s) const;
     int das(const void *e, float *out, double c, hipStream_t s) const;
 };
 
 struct Batch;   // persistent batched path state (bf_batch.hip)
+
+hipError_t launch_das(const DasArgs &a, int mode, int et, int ip, hipStream_t s);
+hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, int ip,
+                          hipStream_t s);
+size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax);
 
 constexpr uint32_t BF_PLAN_MAGIC = 0xBF0C0DE5u;
 

@@ -1,0 +1,82 @@
+"""torch.autograd path over the adjoint kernel, checkpointed autofocus (GPU)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2512_11086_amd as bfm
+import synth
+from paper_2512_11086_amd import autofocus as af
+from tests.helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def w3():
+    desc, H, rfs, info = synth.make_inputs(3)
+    return desc, H, rfs, info
+
+
+def test_autograd_gradients_match_adjoint_and_oracle(torch_mod, w3):
+    torch = torch_mod
+    desc, H, rfs, info = w3
+    plan = bfm.Plan(desc, H)
+    e = plan.decode(torch.from_numpy(rfs[0]).cuda())
+    e_req = e.clone().requires_grad_(True)
+    c = torch.tensor(1520.0, dtype=torch.float64, requires_grad=True)
+    loss = af.sharpness(af.das(e_req, c, plan))
+    loss.backward()
+    # reference: oracle chain rule in FP64
+    e64 = oracle.decode(H, rfs[0])
+    img = oracle.das(desc, e64, c=1520.0)
+    L, gI = oracle.sharpness(img.reshape(-1), grad=True)
+    gI = gI.reshape(img.shape)
+    assert abs(loss.item() - L) <= 1e-5 * abs(L)
+    ref_c = float(np.sum(gI * oracle.das_dc(desc, e64, c=1520.0)))
+    assert abs(c.grad.item() - ref_c) <= 1e-4 * abs(ref_c)
+    ref_e = oracle.das_adjoint_e(desc, gI, c=1520.0)
+    assert rel_l2(e_req.grad.cpu().numpy(), ref_e) <= 1e-5
+
+
+def test_checkpointed_loss_equals_plain(torch_mod, w3):
+    torch = torch_mod
+    desc, H, rfs, info = w3
+    plan = bfm.Plan(desc, H)
+    frames = [plan.decode(torch.from_numpy(r).cuda()) for r in rfs[:3]]
+    grads = []
+    for ck in (False, True):
+        c = torch.tensor(1500.0, dtype=torch.float64, requires_grad=True)
+        loss = af.focus_loss(frames, c, plan, use_checkpoint=ck)
+        loss.backward()
+        grads.append((loss.item(), c.grad.item()))
+    assert grads[0][0] == grads[1][0]
+    assert grads[0][1] == pytest.approx(grads[1][1], rel=1e-6)
+
+
+def test_autofocus_finds_generating_sound_speed(torch_mod, w3):
+    # Sanity check of the autofocus loop on the 8-frame workload: the scan +
+    # gradient refinement ends at a local minimum no worse than the scan's
+    # best point.  Distance to the generating sound speed is reported (the RF
+    # sharpness loss oscillates in c, so it is bounded loosely).
+    torch = torch_mod
+    desc, H, rfs, info = w3
+    plan = bfm.Plan(desc, H)
+    frames = [plan.decode(torch.from_numpy(r).cuda()) for r in rfs]
+    c_hat, scan, hist = af.autofocus(frames, plan)
+    best_scan = min(l for _, l in scan)
+    print(f"c_true {info['c_true']:.2f}  c_hat {c_hat:.2f}  refinement steps {len(hist)}")
+    for c, l in scan:
+        print("  scan c=%.1f loss=%.6e" % (c, l))
+    for h in hist:
+        print("  refine c=%.3f loss=%.6e dL/dc=%.3e" % h)
+    final = min(h[1] for h in hist)
+    assert final <= best_scan + 1e-9
+    assert abs(c_hat - info["c_true"]) <= 15.0

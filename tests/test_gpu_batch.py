@@ -1,0 +1,120 @@
+"""Batched persistent path, hipGraph replay and autotuner (GPU).
+
+A batch of frames with different modes, transmit subsets and grids goes
+through bf_batch_run (persistent kernels) and bf_graph_launch (the same
+kernels captured once, replayed with new buffers).  Every frame is checked
+against the FP64 oracle, the batch against the per-frame plans, and every
+graph replay against an eager run on the same inputs, with the program's own
+eager work and synchronisations between replays.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2512_11086_amd as bfm
+import synth
+from synth.configs import MM, describe
+from tests.helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _frames(seed=0, n=6):
+    rng = np.random.default_rng(seed)
+    out = []
+    for f in range(n):
+        n_tx = int(rng.choice([4, 8, 16, 32]))
+        cols = np.sort(rng.choice(32, size=n_tx, replace=False))
+        if f % 2 == 0:
+            d = describe("forces", (32, 16), (0.2 * MM, 0.2 * MM), n_tx, 32, 700, 20e6, 5e6,
+                         (40 + 3 * f, 1, 57), (-3 * MM, 0, 4 * MM), (3 * MM, 0, 14 * MM),
+                         tx_elements=cols)
+        else:
+            d = describe("hercules", (32, 16), (0.2 * MM, 0.2 * MM), n_tx, 16, 700, 20e6, 5e6,
+                         (19, 13 + f, 27), (-2.5 * MM, -1.5 * MM, 3 * MM), (2.5 * MM, 1.5 * MM, 9 * MM),
+                         tx_elements=cols)
+        H = synth.hadamard_sylvester(n_tx)
+        pts = rng.uniform([-2 * MM, -1 * MM, 5 * MM], [2 * MM, 1 * MM, 8 * MM], size=(5, 3))
+        if d["mode"] == "forces":
+            pts[:, 1] = 0
+        rf = synth.acquire(d, pts, np.ones(5), rng, H=H)
+        out.append((d, H, rf))
+    return out
+
+
+def test_batch_matches_oracle_and_per_frame(torch_mod):
+    torch = torch_mod
+    frames = _frames()
+    bp = bfm.BatchPlan([f[0] for f in frames], [f[1] for f in frames])
+    rfs = [torch.from_numpy(f[2]).cuda() for f in frames]
+    outs = [torch.empty(s, device="cuda") for s in bp.out_shapes]
+    bp.run(rfs, outs)
+    torch.cuda.synchronize()
+    for (d, H, rf), o in zip(frames, outs):
+        ref = oracle.das(d, oracle.decode(H, rf))
+        assert rel_l2(o.cpu().numpy(), ref) <= 1e-5
+        p = bfm.Plan(d, H)
+        single = p.das(p.decode(torch.from_numpy(rf).cuda()))
+        assert rel_l2(o.cpu().numpy(), single.cpu().numpy()) <= 1e-6
+
+
+def test_graph_replays_match_eager(torch_mod):
+    torch = torch_mod
+    frames = _frames(seed=3)
+    bp = bfm.BatchPlan([f[0] for f in frames], [f[1] for f in frames])
+    sets = []
+    for k in range(3):     # three input sets: the frames' data scaled and shifted
+        rfs = [torch.from_numpy(np.roll(f[2], 7 * k, axis=2) // (k + 1)).cuda() for f in frames]
+        sets.append(rfs)
+    eager = []
+    for rfs in sets:
+        outs = [torch.empty(s, device="cuda") for s in bp.out_shapes]
+        bp.run(rfs, outs)
+        torch.cuda.synchronize()
+        eager.append([o.clone() for o in outs])
+    for rep in range(2):
+        for k, rfs in enumerate(sets):
+            outs = [torch.full(s, float("nan"), device="cuda") for s in bp.out_shapes]
+            bp.graph_launch(rfs, outs)
+            junk = torch.randn(1000, device="cuda").sum()      # eager work between replays
+            torch.cuda.synchronize()
+            assert torch.isfinite(junk)
+            for o, ref in zip(outs, eager[k]):
+                assert torch.equal(o, ref), (rep, k)
+
+
+def test_batch_rejects_bad_arguments(torch_mod):
+    torch = torch_mod
+    frames = _frames(n=2)
+    bp = bfm.BatchPlan([f[0] for f in frames], [f[1] for f in frames])
+    rfs = [torch.from_numpy(f[2]).cuda() for f in frames]
+    with pytest.raises(bfm.BfError):
+        bfm._lib.check(bfm._lib.lib().bf_batch_run(bp._h, None, None, None))
+    outs = [torch.empty(s, device="cuda") for s in bp.out_shapes]
+    bp.run(rfs, outs)
+    torch.cuda.synchronize()
+
+
+def test_autotune_choice_is_valid_and_cached(torch_mod, tmp_path):
+    torch = torch_mod
+    (d, H, rf) = _frames(seed=5, n=2)[1]
+    p = bfm.Plan(d, H)
+    cache = str(tmp_path / "tune.txt")
+    info = p.autotune(cache)
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and lines[0].split()[0].startswith("gfx950")
+    e = p.decode(torch.from_numpy(rf).cuda())
+    ref = oracle.das(d, oracle.decode(H, rf))
+    assert rel_l2(p.das(e).cpu().numpy(), ref) <= 1e-5
+    p2 = bfm.Plan(d, H)
+    info2 = p2.autotune(cache)      # served from the cache
+    assert info2["tile"] == info["tile"] and info2["block"] == info["block"]
+    assert len(open(cache).read().strip().splitlines()) == 1

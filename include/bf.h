@@ -114,7 +114,8 @@ enum { BF_DAS_LDS = 0, BF_DAS_GATHER = 1 };
 typedef struct {
     int32_t n_frames;
     int32_t tile[3];           /* DAS voxels per wavefront along x, y, z               */
-    int32_t variant;           /* BF_DAS_*                                             */
+    int32_t variant;           /* BF_DAS_* kernel bf_das runs for frame 0 (after the
+                                  LDS-fit check at the plan's sound speed)              */
     int32_t block[3];          /* wavefront tiles per LDS workgroup along x, y, z      */
     int32_t nb;                /* traces per staged batch                              */
     int64_t workspace_bytes;   /* device memory held by the plan                       */

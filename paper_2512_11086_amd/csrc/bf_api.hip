@@ -202,12 +202,13 @@ int Frame::init(const bf_params &src)
     grid.ny = p.out_dims[1];
     grid.nz = p.out_dims[2];
     // Default DAS workgroups (fastest in measured sweeps on MI355X; the
-    // autotuner can replace them): 2D = 4x16-point wavefront tiles, four
-    // stacked in depth; 3D = flat 8x8x1 tiles, a 2x2x2 block of them.
+    // autotuner can replace them): 2D = the direct-gather kernel on 16x4-point
+    // wavefront tiles; 3D = LDS windows, flat 8x8x1 tiles in a 2x2x2 block.
     if (p.mode == BF_FORCES_2D && grid.ny == 1) {
-        set_tile(2, 0, 4);
-        bw[0] = 1; bw[1] = 1; bw[2] = 4;
-        nb = 8;
+        set_tile(4, 0, 2);
+        bw[0] = 2; bw[1] = 1; bw[2] = 2;
+        nb = 4;
+        variant = BF_DAS_GATHER;   // 2D windows are long for the LDS staging limit
     } else {
         set_tile(3, 3, 0);
         bw[0] = 2; bw[1] = 2; bw[2] = 2;
@@ -344,7 +345,10 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
     int nbb = nb;
     const int unit = p.mode == BF_FORCES_2D ? 4 : 1;
     const size_t lds_cap = 60 * 1024;   // dynamic LDS without the large-LDS attribute
-    while (nbb >= unit && ((long)nbb * lmax > 4L * nthr || lds_bytes(p.n_tx, p.n_ch, nbb, lmax) > lds_cap))
+    const int nwaves = nthr / 64;
+    // staging rounds per thread: ceil(nb / waves) traces x ceil(lmax / 64) quads <= 2
+    auto rounds = [&](int n) { return ((n + nwaves - 1) / nwaves) * ((lmax + 63) / 64); };
+    while (nbb >= unit && (rounds(nbb) > 2 || lds_bytes(p.n_tx, p.n_ch, nbb, lmax) > lds_cap))
         nbb -= unit;
     if (nbb < unit || nthr > 1024) return false;
     cfg->bwx = bw[0];
@@ -461,7 +465,13 @@ int bf_plan_get_info(bf_plan plan, bf_plan_info *info)
     info->tile[0] = 1 << f.lx;
     info->tile[1] = 1 << f.ly;
     info->tile[2] = 1 << f.lz;
-    info->variant = f.variant;
+    {
+        // the kernel bf_das actually runs (LDS windows may not fit: gather)
+        LdsCfg cfg;
+        info->variant = (f.variant == BF_DAS_LDS && f.lds_config(f.das_args(nullptr, nullptr, f.p.c), &cfg))
+                            ? BF_DAS_LDS
+                            : BF_DAS_GATHER;
+    }
     info->block[0] = f.bw[0];
     info->block[1] = f.bw[1];
     info->block[2] = f.bw[2];

@@ -282,13 +282,16 @@ static int check_batch(bf_plan plan, const int16_t *const *rf, float *const *out
     return BF_OK;
 }
 
-// Frames whose windows do not fit in LDS run as plain launches after the
-// persistent kernels (same stream, so they may also be captured).
-static int enqueue_gather(bf_plan plan, float *const *out, hipStream_t s)
+// Frames whose windows do not fit in LDS run the direct-gather kernel after
+// the persistent kernels; they read their output pointer from the device
+// table too, so they are captured in the same graph.
+static int enqueue_gather(bf_plan plan, hipStream_t s)
 {
-    for (int f : plan->batch->gather_frames) {
+    Batch *b = plan->batch;
+    for (int f : b->gather_frames) {
         const Frame &fr = *plan->frames[f];
-        DasArgs a = fr.das_args(fr.d_e, out[f], fr.p.c);
+        DasArgs a = fr.das_args(fr.d_e, nullptr, fr.p.c);
+        a.out_ref = reinterpret_cast<float *const *>(b->d_ptrs + b->F + f);
         hipError_t e = launch_das(a, fr.p.mode, fr.p.e_type, fr.p.interp, s);
         if (e != hipSuccess) return hip_fail(e, "DAS launch");
     }
@@ -319,7 +322,7 @@ int64_t bf_plan_s::workspace_bytes() const
 namespace {
 
 struct TileCand {
-    int lx, ly, lz, bwx, bwy, bwz, nb;
+    int lx, ly, lz, bwx, bwy, bwz, nb, variant;
 };
 
 std::vector<TileCand> candidates(const Frame &f)
@@ -328,17 +331,21 @@ std::vector<TileCand> candidates(const Frame &f)
     if (f.p.mode == BF_FORCES_2D && f.grid.ny == 1) {
         const int tiles[][3] = {{3, 0, 3}, {2, 0, 4}, {4, 0, 2}, {1, 0, 5}};
         const int blocks[][3] = {{2, 1, 2}, {4, 1, 1}, {1, 1, 4}, {2, 1, 1}, {4, 1, 4}};
-        for (auto &t : tiles)
+        for (auto &t : tiles) {
+            c.push_back({t[0], t[1], t[2], 1, 1, 1, 4, BF_DAS_GATHER});
             for (auto &b : blocks)
-                for (int nb : {8, 16})
-                    c.push_back({t[0], t[1], t[2], b[0], b[1], b[2], nb});
+                for (int nb : {4, 8, 16})
+                    c.push_back({t[0], t[1], t[2], b[0], b[1], b[2], nb, BF_DAS_LDS});
+        }
     } else {
         const int tiles[][3] = {{3, 3, 0}, {2, 2, 2}, {3, 2, 1}, {2, 3, 1}};
         const int blocks[][3] = {{2, 2, 2}, {4, 2, 1}, {2, 2, 1}, {4, 4, 1}, {2, 2, 4}};
-        for (auto &t : tiles)
+        for (auto &t : tiles) {
+            c.push_back({t[0], t[1], t[2], 1, 1, 1, 4, BF_DAS_GATHER});
             for (auto &b : blocks)
                 for (int nb : {8, 16, 32})
-                    c.push_back({t[0], t[1], t[2], b[0], b[1], b[2], nb});
+                    c.push_back({t[0], t[1], t[2], b[0], b[1], b[2], nb, BF_DAS_LDS});
+        }
     }
     return c;
 }
@@ -360,8 +367,8 @@ bool cache_lookup(const char *path, const std::string &key, TileCand *out)
     while (fgets(line, sizeof line, fp)) {
         char k[300];
         TileCand t;
-        if (sscanf(line, "%299s %d %d %d %d %d %d %d", k, &t.lx, &t.ly, &t.lz, &t.bwx, &t.bwy,
-                   &t.bwz, &t.nb) == 8 &&
+        if (sscanf(line, "%299s %d %d %d %d %d %d %d %d", k, &t.lx, &t.ly, &t.lz, &t.bwx, &t.bwy,
+                   &t.bwz, &t.nb, &t.variant) == 9 &&
             key == k) {
             *out = t;
             found = true;      // last entry wins
@@ -394,7 +401,7 @@ int bf_batch_run(bf_plan plan, const int16_t *const *rf, float *const *out, void
     hipStream_t s = (hipStream_t)stream;
     if ((st = stage_pointers(plan->batch, rf, out, s)) != BF_OK) return st;
     if ((st = enqueue(plan, s)) != BF_OK) return st;
-    return enqueue_gather(plan, out, s);
+    return enqueue_gather(plan, s);
 }
 
 int bf_graph_launch(bf_plan plan, const int16_t *const *rf, float *const *out, void *stream)
@@ -404,11 +411,6 @@ int bf_graph_launch(bf_plan plan, const int16_t *const *rf, float *const *out, v
     Batch *b = plan->batch;
     hipStream_t s = (hipStream_t)stream;
     if ((st = stage_pointers(b, rf, out, s)) != BF_OK) return st;
-    if (!b->gather_frames.empty()) {
-        // their output pointers are kernel arguments: run them outside the graph
-        if ((st = enqueue(plan, s)) != BF_OK) return st;
-        return enqueue_gather(plan, out, s);
-    }
     hipError_t e;
     if (!b->exec) {
         if (!b->cap && (e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess)
@@ -416,6 +418,7 @@ int bf_graph_launch(bf_plan plan, const int16_t *const *rf, float *const *out, v
         if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return hip_fail(e, "graph capture begin");
         st = enqueue(plan, b->cap);
+        if (st == BF_OK) st = enqueue_gather(plan, b->cap);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(b->cap, &g);
         if (st != BF_OK) {
@@ -479,8 +482,11 @@ int bf_autotune(bf_plan plan, const char *cache_path)
                 f0->bw[1] = t.bwy;
                 f0->bw[2] = t.bwz;
                 f0->nb = t.nb;
+                f0->variant = t.variant;
                 LdsCfg cfg;
-                if (!f0->lds_config(f0->das_args(e_buf, o_buf, f0->p.c), &cfg)) continue;
+                if (t.variant == BF_DAS_LDS &&
+                    !f0->lds_config(f0->das_args(e_buf, o_buf, f0->p.c), &cfg))
+                    continue;
                 if (f0->das(e_buf, o_buf, f0->p.c, 0) != BF_OK) continue;   // warm-up
                 (void)hipEventRecord(t0, 0);
                 for (int r = 0; r < 3; ++r) (void)f0->das(e_buf, o_buf, f0->p.c, 0);
@@ -500,6 +506,7 @@ int bf_autotune(bf_plan plan, const char *cache_path)
             f0->p.e_type = saved_et;
             f0->variant = saved_variant;
             if (best_ms >= 1e30f) {
+                f0->variant = saved_variant;
                 f0->set_tile(saved[0], saved[1], saved[2]);
                 f0->bw[0] = saved[3];
                 f0->bw[1] = saved[4];
@@ -510,8 +517,8 @@ int bf_autotune(bf_plan plan, const char *cache_path)
             if (cache_path) {
                 FILE *fp = fopen(cache_path, "a");
                 if (fp) {
-                    fprintf(fp, "%s %d %d %d %d %d %d %d\n", key.c_str(), best.lx, best.ly, best.lz,
-                            best.bwx, best.bwy, best.bwz, best.nb);
+                    fprintf(fp, "%s %d %d %d %d %d %d %d %d\n", key.c_str(), best.lx, best.ly,
+                            best.lz, best.bwx, best.bwy, best.bwz, best.nb, best.variant);
                     fclose(fp);
                 }
             }
@@ -523,6 +530,7 @@ int bf_autotune(bf_plan plan, const char *cache_path)
                 f->bw[1] = best.bwy;
                 f->bw[2] = best.bwz;
                 f->nb = best.nb;
+                f->variant = best.variant;
             }
     }
     return BF_OK;

@@ -70,7 +70,10 @@ struct DasArgs {
     int n_waves;            // tiles_x * tiles_y * tiles_z
     int groups;             // channel groups (blockIdx.y); > 1 writes partial images
     float *part;            // [groups][ny][nx][nz] partial images when groups > 1
+    float *const *out_ref;  // if set, the output pointer is read from here (graph replay)
 };
+
+__device__ inline float *das_out(const DasArgs &a) { return a.out_ref ? *a.out_ref : a.out; }
 
 // Channel rows [j0, j1) of group g of G.
 __host__ __device__ inline void group_rows(int n_ch, int g, int G, int *j0, int *j1)

@@ -60,26 +60,51 @@ __device__ inline float read_trace(const void *tr, int S, int nB, float s)
     }
 }
 
-// FORCES: the transmit and receive excess paths separate, so the receive term
-// and its apodization are computed once per (point, channel).
+// FORCES: the transmit and receive excess paths separate.  The wavefront
+// collects up to JG of its active channel rows (a row is active when some
+// lane lies inside its receive aperture), computes each row's receive term
+// and apodization once per lane, then sweeps the transmits: the transmit
+// excess path (one square root and one reciprocal) is shared by the JG terms
+// of that transmit.  Terms of one point are added in (row chunk, transmit,
+// row) order.
+constexpr int JG = 8;
+
 template <int ET, int IP>
 __device__ inline float das_forces_point(const DasArgs &a, const Lane &L, int jb, int je)
 {
     const float kf = (float)a.k;
     float acc = 0.f;
-    for (int j = jb; j < je; ++j) {
-        const float dxr = L.x - a.rx_c[j];
-        const float r2 = dxr * dxr;
-        const bool act = L.active && r2 < L.thr;
-        if (!__any(act)) continue;
-        const float Rj = fmaf(excess(r2, L.z, L.z2), kf, L.fB);
-        const float aj = act ? hann_u2(r2 * L.wsc) : 0.f;
+    int j = jb;
+    for (;;) {
+        int rows[JG];
+        int n = 0;
+        for (; j < je && n < JG; ++j) {
+            const float dxr = L.x - a.rx_c[j];
+            if (__any(L.active && dxr * dxr < L.thr)) rows[n++] = j;
+        }
+        if (n == 0) break;
+        float Rj[JG], aj[JG];
+#pragma unroll
+        for (int q = 0; q < JG; ++q) {
+            Rj[q] = 0.f;
+            aj[q] = 0.f;
+            if (q < n) {
+                const float dxr = L.x - a.rx_c[rows[q]];
+                const float r2 = dxr * dxr;
+                const bool act = L.active && r2 < L.thr;
+                Rj[q] = fmaf(excess(r2, L.z, L.z2), kf, L.fB);
+                aj[q] = act ? hann_u2(r2 * L.wsc) : 0.f;
+            }
+        }
         for (int i = 0; i < a.n_tx; ++i) {
             const float dxt = L.x - a.tx_x[i];
-            const float s = fmaf(excess(dxt * dxt, L.z, L.z2), kf, Rj);
-            if (act) {
-                const void *tr = trace_ptr<ET>(a.e, (long)i * a.n_ch + j, a.S);
-                acc = fmaf(aj, read_trace<ET, IP>(tr, a.S, L.nB, s), acc);
+            const float T = kf * excess(dxt * dxt, L.z, L.z2);
+#pragma unroll
+            for (int q = 0; q < JG; ++q) {
+                if (q < n && L.active) {
+                    const void *tr = trace_ptr<ET>(a.e, (long)i * a.n_ch + rows[q], a.S);
+                    acc = fmaf(aj[q], read_trace<ET, IP>(tr, a.S, L.nB, Rj[q] + T), acc);
+                }
             }
         }
     }
@@ -132,14 +157,15 @@ __global__ __launch_bounds__(256) void das_kernel(DasArgs a)
         if (a.groups > 1)
             a.part[(long)blockIdx.y * a.g.nx * a.g.ny * a.g.nz + L.out_idx] = v;
         else
-            a.out[L.out_idx] = v;
+            das_out(a)[L.out_idx] = v;
     }
 }
 
 // Sum of the channel-group partial images in group order (deterministic).
-__global__ __launch_bounds__(256) void sum_groups_kernel(const float *part, float *out, long n,
-                                                         int G)
+__global__ __launch_bounds__(256) void sum_groups_kernel(const float *part, float *out_direct,
+                                                         float *const *out_ref, long n, int G)
 {
+    float *out = out_ref ? *out_ref : out_direct;
     for (long q = (long)blockIdx.x * 256 + threadIdx.x; q < n; q += (long)gridDim.x * 256) {
         float s = 0.f;
         for (int g = 0; g < G; ++g) s += part[(long)g * n + q];
@@ -153,7 +179,7 @@ hipError_t launch_sum_groups(const DasArgs &a, hipStream_t s)
     long blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(sum_groups_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a.part, a.out,
-                       n, a.groups);
+                       a.out_ref, n, a.groups);
     return hipGetLastError();
 }
 

@@ -268,76 +268,98 @@ __device__ inline void slot_trace(const BatchDesc &d, const LdsCfg &c, int e, in
     }
 }
 
-constexpr int QMAX = 4;   // staged quads per thread per batch (host guarantees)
+constexpr int QMAX = 2;   // staging rounds per thread per batch (host guarantees)
 
+// Staging map: trace slot e of a batch is staged by wavefront e % W in round
+// e / W; lane m loads quad m (and m + 64 ... when the window is longer), so
+// the window start is computed once per (wavefront, trace) and consecutive
+// lanes read consecutive samples.
 struct Staged {
     float p[QMAX][4];
+    int w0[QMAX];
 };
+
+__device__ inline int stage_rounds_m(const LdsCfg &c) { return (c.lmax + 63) >> 6; }
 
 // Issue the global loads of a batch's windows (taps n-1..n+2 of every quad).
 template <int MODE, int ET>
 __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const BoxGeom &b,
                                   const float *s_tx, const float *s_rx, const BatchDesc &d,
-                                  Staged &st, int tid, int nthr)
+                                  Staged &st, int wave, int lane, int nwaves)
 {
+    const int mr = stage_rounds_m(c);
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-        const int idx = tid + q * nthr;
+        const int e = wave + (q / mr) * nwaves;
+        const int m = lane + 64 * (q % mr);
         float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
-        if (idx < c.nb * c.lmax) {
-            const int e = idx / c.lmax, m = idx - e * c.lmax;
+        int w0 = 0;
+        if (q < mr * ((c.nb + nwaves - 1) / nwaves) && e < c.nb) {
             int i, j;
             slot_trace<MODE>(d, c, e, &i, &j);
             if (j >= 0) {
-                const int w0 = window_start<MODE>(a, b, s_tx[i], s_rx[j]);
-                const int n = w0 + m;
-                const void *tr = trace_ptr<ET>(a.e, (long)i * a.n_ch + j, a.S);
-                const unsigned S = (unsigned)a.S;
-                p0 = ((unsigned)(n - 1) < S) ? load_e<ET>(tr, n - 1) : 0.f;
-                p1 = ((unsigned)n < S) ? load_e<ET>(tr, n) : 0.f;
-                p2 = ((unsigned)(n + 1) < S) ? load_e<ET>(tr, n + 1) : 0.f;
-                p3 = ((unsigned)(n + 2) < S) ? load_e<ET>(tr, n + 2) : 0.f;
+                w0 = window_start<MODE>(a, b, s_tx[i], s_rx[j]);
+                if (m < c.lmax) {
+                    const int n = w0 + m;
+                    const void *tr = trace_ptr<ET>(a.e, (long)i * a.n_ch + j, a.S);
+                    const unsigned S = (unsigned)a.S;
+                    if (n >= 1 && n + 2 < a.S) {
+                        p0 = load_e<ET>(tr, n - 1);
+                        p1 = load_e<ET>(tr, n);
+                        p2 = load_e<ET>(tr, n + 1);
+                        p3 = load_e<ET>(tr, n + 2);
+                    } else {
+                        p0 = ((unsigned)(n - 1) < S) ? load_e<ET>(tr, n - 1) : 0.f;
+                        p1 = ((unsigned)n < S) ? load_e<ET>(tr, n) : 0.f;
+                        p2 = ((unsigned)(n + 1) < S) ? load_e<ET>(tr, n + 1) : 0.f;
+                        p3 = ((unsigned)(n + 2) < S) ? load_e<ET>(tr, n + 2) : 0.f;
+                    }
+                }
             }
         }
         st.p[q][0] = p0;
         st.p[q][1] = p1;
         st.p[q][2] = p2;
         st.p[q][3] = p3;
+        st.w0[q] = w0;
     }
 }
 
 // Convert the loaded taps to coefficient quads and write them (and the
 // per-trace metadata) to one LDS buffer.
 template <int MODE, int IP>
-__device__ inline void stage_store(const DasArgs &a, const LdsCfg &c, const BoxGeom &b,
-                                   const float *s_tx, const float *s_rx, const BatchDesc &d,
-                                   const Staged &st, float4 *quads, Meta *meta, int tid, int nthr)
+__device__ inline void stage_store(const LdsCfg &c, const float *s_tx, const BatchDesc &d,
+                                   const Staged &st, float4 *quads, Meta *meta, int wave,
+                                   int lane, int nwaves)
 {
+    const int mr = stage_rounds_m(c);
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-        const int idx = tid + q * nthr;
-        if (idx < c.nb * c.lmax) {
-            const float pm = st.p[q][0], p0 = st.p[q][1], p1 = st.p[q][2], p2 = st.p[q][3];
-            float4 cq;
-            if constexpr (IP == IN_CUBIC) {
-                cq.x = p0;
-                cq.y = 0.5f * (p1 - pm);
-                cq.z = pm - 2.5f * p0 + 2.0f * p1 - 0.5f * p2;
-                cq.w = 0.5f * (p2 - pm) + 1.5f * (p0 - p1);
-            } else if constexpr (IP == IN_LINEAR) {
-                cq = make_float4(p0, p1 - p0, 0.f, 0.f);
-            } else {
-                cq = make_float4(p0, p1, 0.f, 0.f);
+        const int e = wave + (q / mr) * nwaves;
+        const int m = lane + 64 * (q % mr);
+        if (q < mr * ((c.nb + nwaves - 1) / nwaves) && e < c.nb) {
+            if (m < c.lmax) {
+                const float pm = st.p[q][0], p0 = st.p[q][1], p1 = st.p[q][2], p2 = st.p[q][3];
+                float4 cq;
+                if constexpr (IP == IN_CUBIC) {
+                    cq.x = p0;
+                    cq.y = 0.5f * (p1 - pm);
+                    cq.z = pm - 2.5f * p0 + 2.0f * p1 - 0.5f * p2;
+                    cq.w = 0.5f * (p2 - pm) + 1.5f * (p0 - p1);
+                } else if constexpr (IP == IN_LINEAR) {
+                    cq = make_float4(p0, p1 - p0, 0.f, 0.f);
+                } else {
+                    cq = make_float4(p0, p1, 0.f, 0.f);
+                }
+                quads[e * c.lmax + m] = cq;
             }
-            quads[idx] = cq;
-            const int e = idx / c.lmax, m = idx - e * c.lmax;
             if (m == 0) {
                 int i, j;
                 slot_trace<MODE>(d, c, e, &i, &j);
                 Meta mt;
                 mt.on = j >= 0;
                 mt.xi = mt.on ? s_tx[i] : 0.f;
-                mt.w0 = mt.on ? window_start<MODE>(a, b, s_tx[i], s_rx[j]) : 0;
+                mt.w0 = st.w0[q];
                 mt.pad = 0;
                 meta[e] = mt;
             }
@@ -345,10 +367,18 @@ __device__ inline void stage_store(const DasArgs &a, const LdsCfg &c, const BoxG
     }
 }
 
+// clamp to [0, hi] in one instruction (hi wave-uniform)
+__device__ inline int clamp0_i32(int x, int hi)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "s"(hi));
+    return r;
+}
+
 template <int IP>
 __device__ inline float read_quad(const float4 *win, int li, int lmax, float t)
 {
-    li = min(max(li, 0), lmax - 1);
+    li = clamp0_i32(li, lmax - 1);
     const float4 q = win[li];
     if constexpr (IP == IN_NEAREST) return t < 0.5f ? q.x : q.y;
     if constexpr (IP == IN_LINEAR) return fmaf(t, q.y, q.x);
@@ -364,6 +394,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     const int nthr = blockDim.x;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
+    const int nwaves = nthr >> 6;
 
     // tables: tx_x, rx_c, then two buffers of [nb] Meta + [nb * lmax] quads
     float *s_tx = reinterpret_cast<float *>(smem);
@@ -395,9 +426,9 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     BatchDesc cur = next_batch<MODE>(a, c, box, s_tx, s_rx, it);
     Staged st;
     if (cur.valid) {
-        stage_load<MODE, ET>(a, c, box, s_tx, s_rx, cur, st, tid, nthr);
-        stage_store<MODE, IP>(a, c, box, s_tx, s_rx, cur, st, q0 + c.nb,
-                              reinterpret_cast<Meta *>(q0), tid, nthr);
+        stage_load<MODE, ET>(a, c, box, s_tx, s_rx, cur, st, wave, lane, nwaves);
+        stage_store<MODE, IP>(c, s_tx, cur, st, q0 + c.nb, reinterpret_cast<Meta *>(q0), wave,
+                              lane, nwaves);
     }
     __syncthreads();
 
@@ -412,7 +443,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     int bi = 0;
     while (cur.valid) {
         BatchDesc nxt = next_batch<MODE>(a, c, box, s_tx, s_rx, it);
-        if (nxt.valid) stage_load<MODE, ET>(a, c, box, s_tx, s_rx, nxt, st, tid, nthr);
+        if (nxt.valid) stage_load<MODE, ET>(a, c, box, s_tx, s_rx, nxt, st, wave, lane, nwaves);
 
         float4 *qb = (bi & 1) ? q1 : q0;
         const Meta *meta = reinterpret_cast<const Meta *>(qb);
@@ -446,9 +477,10 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                 const float ra = fmaf(dxa, dxa, dy2), rb = fmaf(dxb, dxb, dy2);
                 const float sa = fmaf(excess(ra, L.z, L.z2), kf, L.fB);
                 const float sb = fmaf(excess(rb, L.z, L.z2), kf, L.fB);
-                const float fa = floorf(sa), fb = floorf(sb);
-                const float va = read_quad<IP>(quads + e1 * c.lmax, (int)fa + L.nB - w01, c.lmax, sa - fa);
-                const float vb = read_quad<IP>(quads + e2 * c.lmax, (int)fb + L.nB - w02, c.lmax, sb - fb);
+                const float va = read_quad<IP>(quads + e1 * c.lmax, (int)floorf(sa) + L.nB - w01,
+                                               c.lmax, __builtin_amdgcn_fractf(sa));
+                const float vb = read_quad<IP>(quads + e2 * c.lmax, (int)floorf(sb) + L.nB - w02,
+                                               c.lmax, __builtin_amdgcn_fractf(sb));
                 const float wa = ra < L.thr ? hann_u2(ra * L.wsc) : 0.f;
                 const float wb = (two && rb < L.thr) ? hann_u2(rb * L.wsc) : 0.f;
                 acc = fmaf(wa, va, acc);
@@ -482,8 +514,8 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                     const int e = q * nbi + ii;
                     const int w0 = __builtin_amdgcn_readlane(mine.w0, e);
                     const float sq = Rj[q] + T;
-                    const float fl = floorf(sq);
-                    const float v = read_quad<IP>(quads + e * c.lmax, (int)fl + L.nB - w0, c.lmax, sq - fl);
+                    const float v = read_quad<IP>(quads + e * c.lmax, (int)floorf(sq) + L.nB - w0,
+                                                  c.lmax, __builtin_amdgcn_fractf(sq));
                     acc = fmaf(aj[q], v, acc);
                 }
             }
@@ -491,8 +523,8 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
 
         if (!nxt.valid) break;
         float4 *nb_ = ((bi + 1) & 1) ? q1 : q0;
-        stage_store<MODE, IP>(a, c, box, s_tx, s_rx, nxt, st, nb_ + c.nb,
-                              reinterpret_cast<Meta *>(nb_), tid, nthr);
+        stage_store<MODE, IP>(c, s_tx, nxt, st, nb_ + c.nb, reinterpret_cast<Meta *>(nb_), wave,
+                              lane, nwaves);
         __syncthreads();
         cur = nxt;
         ++bi;
@@ -501,7 +533,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
         if (a.groups > 1)
             a.part[(long)grp * a.g.nx * a.g.ny * a.g.nz + L.out_idx] = acc;
         else
-            a.out[L.out_idx] = acc;
+            das_out(a)[L.out_idx] = acc;
     }
 }
 
@@ -516,23 +548,25 @@ __global__ __launch_bounds__(1024) void das_lds_kernel(DasArgs a, LdsCfg c)
 // items from a queue until it is empty.  Items are ordered by decreasing
 // cost on the host, so the queue balances uneven frames.
 template <int MODE, int ET, int IP>
-__global__ __launch_bounds__(1024) void das_persistent_kernel(const FrameDas *frames,
-                                                              const int2 *items, int n_items,
-                                                              int *counter,
-                                                              void *const *out_ptrs)
+__global__ __launch_bounds__(1024) void das_persistent_kernel(const FrameDas *__restrict__ frames,
+                                                              const int2 *__restrict__ items,
+                                                              int n_items, int *counter,
+                                                              void *const *__restrict__ out_ptrs)
 {
     extern __shared__ float4 smem[];
     __shared__ int s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
         __syncthreads();
-        const int item = s_item;
+        // the item is workgroup-uniform: keep it (and all it indexes) scalar
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (item >= n_items) break;
-        const int2 w = items[item];
-        DasArgs a = frames[w.x].a;
-        a.out = static_cast<float *>(out_ptrs[w.x]);
-        das_block<MODE, ET, IP>(a, frames[w.x].c, w.y, 0, smem);
+        const int fr = __builtin_amdgcn_readfirstlane(items[item].x);
+        const int blk = __builtin_amdgcn_readfirstlane(items[item].y);
+        DasArgs a = frames[fr].a;
+        a.out = static_cast<float *>(out_ptrs[fr]);
+        das_block<MODE, ET, IP>(a, frames[fr].c, blk, 0, smem);
         __syncthreads();
     }
 }

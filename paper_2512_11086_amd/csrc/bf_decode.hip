@@ -189,20 +189,21 @@ __global__ __launch_bounds__(256) void decode_persistent_kernel(const FrameDec *
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
         __syncthreads();
-        const int item = s_item;
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (item >= n_items) break;
-        const int2 w = items[item];
-        DecodeArgs a = frames[w.x].a;
-        a.rf = static_cast<const int16_t *>(rf_ptrs[w.x]);
-        if (w.x != staged) {
+        const int fr = __builtin_amdgcn_readfirstlane(items[item].x);
+        const int wy = __builtin_amdgcn_readfirstlane(items[item].y);
+        DecodeArgs a = frames[fr].a;
+        a.rf = static_cast<const int16_t *>(rf_ptrs[fr]);
+        if (fr != staged) {
             stage_operands<KB>(a, lds_A, lds_cs);
-            staged = w.x;
+            staged = fr;
         }
         const int n_chunks = (a.S + 63) / 64;
         const int n_cg = (n_chunks + 3) / 4;
-        const int j = w.y / n_cg;
-        const int chunk = (w.y % n_cg) * 4 + (threadIdx.x >> 6);
+        const int j = wy / n_cg;
+        const int chunk = (wy % n_cg) * 4 + (threadIdx.x >> 6);
         if (chunk < n_chunks) decode_item<KB, OT>(a, lds_A, lds_cs, j, chunk, threadIdx.x & 63);
     }
 }

@@ -203,7 +203,9 @@ int Frame::init(const bf_params &src)
     grid.nz = p.out_dims[2];
     // Default DAS workgroups (fastest in measured sweeps on MI355X; the
     // autotuner can replace them): 2D = the direct-gather kernel on 16x4-point
-    // wavefront tiles; 3D = LDS windows, flat 8x8x1 tiles in a 2x2x2 block.
+    // wavefront tiles; 3D = LDS windows, flat 8x8x1 tiles in a 2x2x3 block
+    // (12 wavefronts: two such workgroups fill a CU at the kernel's register
+    // count).
     if (p.mode == BF_FORCES_2D && grid.ny == 1) {
         set_tile(4, 0, 2);
         bw[0] = 2; bw[1] = 1; bw[2] = 2;
@@ -211,12 +213,23 @@ int Frame::init(const bf_params &src)
         variant = BF_DAS_GATHER;   // 2D windows are long for the LDS staging limit
     } else {
         set_tile(3, 3, 0);
-        bw[0] = 2; bw[1] = 2; bw[2] = 2;
-        nb = 16;
+        bw[0] = 2; bw[1] = 2; bw[2] = 3;
+        nb = 32;
     }
     sorted_tx = 1;
     for (int i = 1; i < n; ++i)
         if (tx_x[i] < tx_x[i - 1]) sorted_tx = 0;
+    // equally spaced columns (e.g. the full aperture): the kernels find the
+    // transmit range of a channel row by arithmetic instead of a search
+    uniform_tx = 0;
+    if (n >= 2 && sorted_tx && tx[1] > tx[0]) {
+        const int step = tx[1] - tx[0];
+        uniform_tx = 1;
+        for (int i = 1; i < n; ++i)
+            if (tx[i] - tx[i - 1] != step) uniform_tx = 0;
+        tx_x0 = tx_x[0];
+        tx_inv_dx = (float)(1.0 / (step * p.pitch[0]));
+    }
 
     d_At = (int8_t *)alloc(At.size());
     d_colsum = (int *)alloc(cs.size() * sizeof(int));
@@ -232,6 +245,22 @@ int Frame::init(const bf_params &src)
             if ((w + 3) / 4 > max_blocks) max_blocks = (w + 3) / 4;
         }
     d_partial = (double *)alloc((size_t)max_blocks * sizeof(double));
+    {
+        // Eq. 3 in double precision at u^2 = k / (4 HANN_N), value + slope
+        std::vector<float2> tab(HANN_N + 1);
+        std::vector<double> W(HANN_N + 1);
+        for (int k = 0; k <= HANN_N; ++k) {
+            const double u = sqrt(k / (4.0 * HANN_N));
+            const double cu = cos(M_PI * u);
+            W[k] = (k == HANN_N) ? 0.0 : cu * cu;
+        }
+        for (int k = 0; k < HANN_N; ++k) tab[k] = make_float2((float)W[k], (float)(W[k + 1] - W[k]));
+        tab[HANN_N] = make_float2(0.f, 0.f);
+        d_hann = (float2 *)alloc(tab.size() * sizeof(float2));
+        if (!d_hann) return fail(BF_ERR_HIP, "device allocation of the Hann table failed");
+        hipError_t he = hipMemcpy(d_hann, tab.data(), tab.size() * sizeof(float2), hipMemcpyHostToDevice);
+        if (he != hipSuccess) return hip_fail(he, "upload of the Hann table");
+    }
     // Small grids give too few wavefronts to fill 256 CUs; split the channel
     // sum over `groups` workgroup sets (>= 8192 wavefronts in flight) and add
     // the partial images in a fixed order afterwards.
@@ -315,6 +344,7 @@ DasArgs Frame::das_args(const void *e, float *out, double c) const
     a.n_waves = a.tiles_x * a.tiles_y * a.tiles_z;
     a.groups = groups;
     a.part = d_part;
+    a.hann_tab = d_hann;
     return a;
 }
 
@@ -357,6 +387,9 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
     cfg->nb = nbb;
     cfg->lmax = lmax;
     cfg->sorted_tx = sorted_tx;
+    cfg->uniform_tx = uniform_tx;
+    cfg->tx_x0 = tx_x0;
+    cfg->tx_inv_dx = tx_inv_dx;
     cfg->blocks_x = (grid.nx + tx - 1) / tx;
     cfg->blocks_y = (grid.ny + ty - 1) / ty;
     cfg->blocks_z = (grid.nz + tz - 1) / tz;

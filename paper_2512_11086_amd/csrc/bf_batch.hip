@@ -338,8 +338,8 @@ std::vector<TileCand> candidates(const Frame &f)
                     c.push_back({t[0], t[1], t[2], b[0], b[1], b[2], nb, BF_DAS_LDS});
         }
     } else {
-        const int tiles[][3] = {{3, 3, 0}, {2, 2, 2}, {3, 2, 1}, {2, 3, 1}};
-        const int blocks[][3] = {{2, 2, 2}, {4, 2, 1}, {2, 2, 1}, {4, 4, 1}, {2, 2, 4}};
+        const int tiles[][3] = {{3, 3, 0}, {2, 3, 1}, {2, 2, 2}};
+        const int blocks[][3] = {{2, 2, 3}, {2, 2, 2}, {4, 2, 1}, {3, 2, 2}, {2, 3, 2}, {2, 2, 1}};
         for (auto &t : tiles) {
             c.push_back({t[0], t[1], t[2], 1, 1, 1, 4, BF_DAS_GATHER});
             for (auto &b : blocks)

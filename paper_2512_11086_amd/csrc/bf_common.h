@@ -71,7 +71,13 @@ struct DasArgs {
     int groups;             // channel groups (blockIdx.y); > 1 writes partial images
     float *part;            // [groups][ny][nx][nz] partial images when groups > 1
     float *const *out_ref;  // if set, the output pointer is read from here (graph replay)
+    const float2 *hann_tab; // [HANN_N + 1] (value, slope) of W over u^2 in [0, 1/4]
 };
+
+// Hann weight table: W(u) of Eq. 3 sampled at u^2 = k / (4 HANN_N), stored as
+// (W_k, W_{k+1} - W_k) for linear interpolation in u^2 (max error 1.2e-7);
+// entry HANN_N is (0, 0), so every u^2 >= 1/4 reads weight 0.
+constexpr int HANN_N = 2048;
 
 __device__ inline float *das_out(const DasArgs &a) { return a.out_ref ? *a.out_ref : a.out; }
 
@@ -89,6 +95,8 @@ struct LdsCfg {
     int lmax;            // coefficient quads per staged window
     int sorted_tx;       // tx_x ascending (enables the per-row transmit range)
     int blocks_x, blocks_y, blocks_z;
+    int uniform_tx;      // tx_x[i] = tx_x0 + i * tx_dx exactly (range by arithmetic)
+    float tx_x0, tx_inv_dx;
 };
 
 // One frame of a batch for the persistent DAS kernel (device table entry).

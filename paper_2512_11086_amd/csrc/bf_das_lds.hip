@@ -27,6 +27,7 @@ namespace bf {
 hipError_t launch_sum_groups(const DasArgs &a, hipStream_t s);
 
 constexpr int JC = 4;    // FORCES channel rows per batch
+constexpr int HANN_TAB_PAD = HANN_N + 2;   // table entries reserved in LDS (float2, keeps 16-byte alignment)
 
 struct Meta {
     int w0;      // first sample interval of the window
@@ -45,6 +46,7 @@ struct BatchDesc {
 
 struct BoxGeom {
     float xmin, xmax, ymin, ymax, zmin, zmax;
+    float kf, t0f;    // fs / c and t0 * fs in FP32 (window bounds only)
 };
 
 __device__ inline float wave_min(float v)
@@ -70,6 +72,7 @@ struct LaneL {
     bool valid;
     long out_idx;
     float x, y, z, z2, thr, wsc, fB;
+    float wtab;     // u^2 * 4 HANN_N = rho^2 * wtab (table coordinate)
     int nB;
 };
 
@@ -100,13 +103,17 @@ __device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, 
         L.z2 = L.z * L.z;
         L.thr = a.f2 > 0.f ? L.z2 * 0.25f / a.f2 : __builtin_inff();
         L.wsc = a.f2 > 0.f ? a.f2 / L.z2 : 0.f;
+        L.wtab = L.wsc * (4.f * HANN_N);
     } else {
+        // benign values for points outside the grid or at z <= 0: far away
+        // laterally, so rho^2 is huge (never NaN) and the weight is 0
         L.nB = 0;
         L.fB = 0.f;
-        L.x = L.y = 0.f;
+        L.x = L.y = 1e18f;
         L.z = L.z2 = 1.f;
         L.thr = -1.f;
-        L.wsc = 0.f;
+        L.wsc = __builtin_inff();
+        L.wtab = 1.f;        // rho^2 ~ 1e36 -> table index saturates, fract 0 -> weight 0
     }
     return L;
 }
@@ -133,6 +140,8 @@ __device__ inline BoxGeom block_box(const DasArgs &a, const LdsCfg &c, int bx, i
     b.xmin = (float)lo[0]; b.xmax = (float)hi[0];
     b.ymin = (float)lo[1]; b.ymax = (float)hi[1];
     b.zmin = (float)lo[2]; b.zmax = (float)hi[2];
+    b.kf = (float)a.k;
+    b.t0f = (float)a.t0fs;
     return b;
 }
 
@@ -146,22 +155,23 @@ __device__ inline float far_to_range(float v, float lo, float hi)
 }
 
 // First sample interval of the staged window of one trace for the box.
+// (the bound has a 2-sample margin, so the hardware square root suffices)
 template <int MODE>
-__device__ inline int window_start(const DasArgs &a, const BoxGeom &b, float xi, float cj)
+__device__ inline int window_start(const BoxGeom &b, float xi, float cj)
 {
     const float zlo = fmaxf(b.zmin, 0.f);
     float path;
     if constexpr (MODE == 0) {
         const float rt = dist_to_range(xi, b.xmin, b.xmax);
         const float rr = dist_to_range(cj, b.xmin, b.xmax);
-        path = sqrtf(rt * rt + zlo * zlo) + sqrtf(rr * rr + zlo * zlo);
+        path = __builtin_amdgcn_sqrtf(fmaf(rt, rt, zlo * zlo)) +
+               __builtin_amdgcn_sqrtf(fmaf(rr, rr, zlo * zlo));
     } else {
         const float rx = dist_to_range(xi, b.xmin, b.xmax);
         const float ry = dist_to_range(cj, b.ymin, b.ymax);
-        path = zlo + sqrtf(rx * rx + ry * ry + zlo * zlo);
+        path = zlo + __builtin_amdgcn_sqrtf(fmaf(rx, rx, fmaf(ry, ry, zlo * zlo)));
     }
-    const float s = path * (float)a.k - (float)a.t0fs;
-    return (int)floorf(s) - 2;
+    return (int)floorf(fmaf(path, b.kf, -b.t0f)) - 2;
 }
 
 // Is channel row j reachable by the receive aperture of any point of the box?
@@ -219,7 +229,15 @@ __device__ inline BatchDesc next_batch(const DasArgs &a, const LdsCfg &c, const 
             if (it.j >= it.jend) return d;
             float R;
             if (!row_active<1>(a, b, s_rx[it.j], &R)) continue;
-            if (c.sorted_tx && isfinite(R)) {
+            if (c.uniform_tx && isfinite(R)) {
+                // columns on a regular grid: [lo, hi) by arithmetic (one
+                // column of margin each side; the wavefront tests are exact)
+                const int lo = (int)floorf((b.xmin - R - c.tx_x0) * c.tx_inv_dx) - 1;
+                const int hi = (int)floorf((b.xmax + R - c.tx_x0) * c.tx_inv_dx) + 2;
+                it.i = max(lo, 0);
+                it.ihi = min(hi, a.n_tx);
+                if (it.i > it.ihi) it.i = it.ihi;
+            } else if (c.sorted_tx && isfinite(R)) {
                 tx_range(s_tx, a.n_tx, b.xmin - R, b.xmax + R, &it.i, &it.ihi);
             } else {
                 it.i = 0;
@@ -298,16 +316,24 @@ __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const BoxGe
             int i, j;
             slot_trace<MODE>(d, c, e, &i, &j);
             if (j >= 0) {
-                w0 = window_start<MODE>(a, b, s_tx[i], s_rx[j]);
+                w0 = window_start<MODE>(b, s_tx[i], s_rx[j]);
                 if (m < c.lmax) {
                     const int n = w0 + m;
                     const void *tr = trace_ptr<ET>(a.e, (long)i * a.n_ch + j, a.S);
                     const unsigned S = (unsigned)a.S;
-                    if (n >= 1 && n + 2 < a.S) {
-                        p0 = load_e<ET>(tr, n - 1);
-                        p1 = load_e<ET>(tr, n);
-                        p2 = load_e<ET>(tr, n + 1);
-                        p3 = load_e<ET>(tr, n + 2);
+                    if (w0 >= 1 && w0 + c.lmax + 1 < a.S) {
+                        // whole window inside the record (the usual case): one
+                        // 16-byte load of the four taps (4-byte aligned)
+                        if constexpr (ET == ET_F32) {
+                            float4 q;
+                            __builtin_memcpy(&q, static_cast<const float *>(tr) + (n - 1), 16);
+                            p0 = q.x; p1 = q.y; p2 = q.z; p3 = q.w;
+                        } else {
+                            p0 = load_e<ET>(tr, n - 1);
+                            p1 = load_e<ET>(tr, n);
+                            p2 = load_e<ET>(tr, n + 1);
+                            p3 = load_e<ET>(tr, n + 2);
+                        }
                     } else {
                         p0 = ((unsigned)(n - 1) < S) ? load_e<ET>(tr, n - 1) : 0.f;
                         p1 = ((unsigned)n < S) ? load_e<ET>(tr, n) : 0.f;
@@ -387,6 +413,41 @@ __device__ inline float read_quad(const float4 *win, int li, int lmax, float t)
 
 // Beamforms workgroup box `blk` (channel group `grp`) of one frame.  Every
 // thread of the workgroup must call it (it contains barriers).
+// floor to int in one instruction
+__device__ inline int cvt_flr(float x)
+{
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// a + b + c in one instruction (c wave-uniform)
+__device__ inline int add3_i32(int a, int b, int c)
+{
+    int r;
+    asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+
+// One HERCULES term: receiver at lateral offset (x - xi, dy), trace window
+// `win` starting at sample interval w0 (passed negated, uniform).
+template <int IP>
+__device__ inline float hercules_term(const LaneL &L, const float4 *win, int lmax,
+                                      const float2 *hann, float dy2, float kf, float xi,
+                                      int neg_w0, float acc)
+{
+    const float dx = L.x - xi;
+    const float rho2 = fmaf(dx, dx, dy2);
+    const float s = fmaf(excess(rho2, L.z, L.z2), kf, L.fB);
+    const int li = add3_i32(cvt_flr(s), L.nB, neg_w0);
+    const float v = read_quad<IP>(win, li, lmax, __builtin_amdgcn_fractf(s));
+    // Hann weight from the LDS table; u^2 >= 1/4 lands on the (0, 0) entry
+    const float xw = rho2 * L.wtab;
+    const float2 h = hann[min((unsigned)cvt_flr(xw), (unsigned)HANN_N)];
+    const float w = fmaf(__builtin_amdgcn_fractf(xw), h.y, h.x);
+    return fmaf(w, v, acc);
+}
+
 template <int MODE, int ET, int IP>
 __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int grp,
                                  float4 *smem)
@@ -399,11 +460,14 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     // tables: tx_x, rx_c, then two buffers of [nb] Meta + [nb * lmax] quads
     float *s_tx = reinterpret_cast<float *>(smem);
     float *s_rx = s_tx + ((a.n_tx + 3) & ~3);
-    float4 *bufbase = reinterpret_cast<float4 *>(s_rx + ((a.n_ch + 3) & ~3));
+    float2 *s_hann = reinterpret_cast<float2 *>(s_rx + ((a.n_ch + 3) & ~3));
+    float4 *bufbase = reinterpret_cast<float4 *>(s_hann + HANN_TAB_PAD);
     const int buf_quads = c.nb * c.lmax + c.nb;   // Meta is 16 bytes = one float4
     float4 *q0 = bufbase, *q1 = bufbase + buf_quads;
     for (int t = tid; t < a.n_tx; t += nthr) s_tx[t] = a.tx_x[t];
     for (int t = tid; t < a.n_ch; t += nthr) s_rx[t] = a.rx_c[t];
+    if constexpr (MODE == 1)
+        for (int t = tid; t <= HANN_N; t += nthr) s_hann[t] = a.hann_tab[t];
 
     const int bz = blk % c.blocks_z;
     const int bx = (blk / c.blocks_z) % c.blocks_x;
@@ -462,29 +526,27 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                 whi = uniform_f(wave_max(r2 > 0.f ? L.x + r : -__builtin_inff()));
             }
             // traces inside the union of this wavefront's receive apertures
+            // (a contiguous run: the columns are sorted within a batch), in
+            // pairs whose LDS reads overlap, then an odd last one
             uint64_t mask = __ballot(lane < cur.cnt && mine.xi >= wlo && mine.xi <= whi);
-            while (mask) {
+            const int xi_bits = __float_as_int(mine.xi);
+            while (mask & (mask - 1)) {
                 const int e1 = __builtin_ctzll(mask);
                 mask &= mask - 1;
-                const bool two = mask != 0;
-                const int e2 = two ? __builtin_ctzll(mask) : e1;
-                if (two) mask &= mask - 1;
-                const float x1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.xi), e1));
-                const float x2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.xi), e2));
-                const int w01 = __builtin_amdgcn_readlane(mine.w0, e1);
-                const int w02 = __builtin_amdgcn_readlane(mine.w0, e2);
-                const float dxa = L.x - x1, dxb = L.x - x2;
-                const float ra = fmaf(dxa, dxa, dy2), rb = fmaf(dxb, dxb, dy2);
-                const float sa = fmaf(excess(ra, L.z, L.z2), kf, L.fB);
-                const float sb = fmaf(excess(rb, L.z, L.z2), kf, L.fB);
-                const float va = read_quad<IP>(quads + e1 * c.lmax, (int)floorf(sa) + L.nB - w01,
-                                               c.lmax, __builtin_amdgcn_fractf(sa));
-                const float vb = read_quad<IP>(quads + e2 * c.lmax, (int)floorf(sb) + L.nB - w02,
-                                               c.lmax, __builtin_amdgcn_fractf(sb));
-                const float wa = ra < L.thr ? hann_u2(ra * L.wsc) : 0.f;
-                const float wb = (two && rb < L.thr) ? hann_u2(rb * L.wsc) : 0.f;
-                acc = fmaf(wa, va, acc);
-                acc = fmaf(wb, vb, acc);
+                const int e2 = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                acc = hercules_term<IP>(L, quads + e1 * c.lmax, c.lmax, s_hann, dy2, kf,
+                                        __int_as_float(__builtin_amdgcn_readlane(xi_bits, e1)),
+                                        -__builtin_amdgcn_readlane(mine.w0, e1), acc);
+                acc = hercules_term<IP>(L, quads + e2 * c.lmax, c.lmax, s_hann, dy2, kf,
+                                        __int_as_float(__builtin_amdgcn_readlane(xi_bits, e2)),
+                                        -__builtin_amdgcn_readlane(mine.w0, e2), acc);
+            }
+            if (mask) {
+                const int e1 = __builtin_ctzll(mask);
+                acc = hercules_term<IP>(L, quads + e1 * c.lmax, c.lmax, s_hann, dy2, kf,
+                                        __int_as_float(__builtin_amdgcn_readlane(xi_bits, e1)),
+                                        -__builtin_amdgcn_readlane(mine.w0, e1), acc);
             }
         } else {
             const int nbi = c.nb / JC;
@@ -658,7 +720,8 @@ static hipError_t launch_lds_et(const DasArgs &a, const LdsCfg &c, int et, int i
 
 size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax)
 {
-    return (size_t)(((n_tx + 3) & ~3) + ((n_ch + 3) & ~3)) * 4 + 2 * (size_t)(nb * lmax + nb) * 16;
+    return (size_t)(((n_tx + 3) & ~3) + ((n_ch + 3) & ~3)) * 4 + (size_t)HANN_TAB_PAD * 8 +
+           2 * (size_t)(nb * lmax + nb) * 16;
 }
 
 hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, int ip,

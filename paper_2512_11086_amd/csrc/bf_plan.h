@@ -27,8 +27,11 @@ struct Frame {
     int nb = 16;                 // traces per staged batch
     int variant = 0;             // 0 = LDS-staged windows, 1 = direct gather
     int sorted_tx = 0;           // transmit columns ascending
+    int uniform_tx = 0;          // transmit columns equally spaced (ascending)
+    float tx_x0 = 0.f, tx_inv_dx = 0.f;
     int groups = 1;              // channel groups of the DAS launch (small grids)
     float *d_part = nullptr;     // [groups][points] partial images
+    float2 *d_hann = nullptr;    // Hann weight table (HANN_N + 1 entries)
     long max_blocks = 0;
     int8_t *d_At = nullptr;
     int *d_colsum = nullptr;

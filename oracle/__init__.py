@@ -73,6 +73,13 @@ def lib():
         L.oracle_das_dc.argtypes = [P(_Geom), P(ctypes.c_double), P(ctypes.c_double)]
         L.oracle_sharpness.argtypes = [P(ctypes.c_double), ctypes.c_int64, P(ctypes.c_double)]
         L.oracle_sharpness.restype = ctypes.c_double
+        D = P(ctypes.c_double)
+        L.oracle_demod.argtypes = [P(ctypes.c_int16), ctypes.c_int, ctypes.c_int, D, D,
+                                   ctypes.c_int, ctypes.c_double, ctypes.c_int, D]
+        L.oracle_quantise_i16.argtypes = [D, ctypes.c_int64, P(ctypes.c_int16)]
+        L.oracle_das_iq.argtypes = [P(_Geom), ctypes.c_double, D, D, D, D]
+        L.oracle_das_iq_points.argtypes = [P(_Geom), ctypes.c_double, D, D, P(ctypes.c_int64),
+                                           ctypes.c_int64, D, D]
         _lib = L
     return _lib
 
@@ -189,3 +196,70 @@ def sharpness(img: np.ndarray, grad: bool = False):
     L = lib().oracle_sharpness(_ptr(img, ctypes.c_double), img.size,
                                _ptr(g, ctypes.c_double) if grad else None)
     return (L, g) if grad else L
+
+
+# ---------------------------------------------------------------------------
+# Demodulation (Eq. 4) and IQ beamforming
+# ---------------------------------------------------------------------------
+def demod(x: np.ndarray, taps, fd: float, fs: float, D: int = 1) -> np.ndarray:
+    """Mix, filter, decimate (Eq. 4) every trace of int16 ``x`` (..., S).
+
+    Returns complex128 (..., ceil(S / D)) before any rounding.  ``taps`` may be
+    real or complex."""
+    x = np.ascontiguousarray(x, dtype=np.int16)
+    S = x.shape[-1]
+    n_tr = int(np.prod(x.shape[:-1])) if x.ndim > 1 else 1
+    h = np.asarray(taps)
+    hr = np.ascontiguousarray(h.real, dtype=np.float64)
+    hi = np.ascontiguousarray(h.imag, dtype=np.float64) if np.iscomplexobj(h) else None
+    n_out = (S + D - 1) // D
+    y = np.empty(x.shape[:-1] + (n_out, 2), dtype=np.float64)
+    lib().oracle_demod(_ptr(x, ctypes.c_int16), n_tr, S, _ptr(hr, ctypes.c_double),
+                       _ptr(hi, ctypes.c_double) if hi is not None else None, hr.size,
+                       float(fd) / float(fs), int(D), _ptr(y, ctypes.c_double))
+    return y[..., 0] + 1j * y[..., 1]
+
+
+def quantise_iq(y: np.ndarray) -> np.ndarray:
+    """Complex values -> int16 (..., 2) (re, im): round half to even, saturate."""
+    y = np.asarray(y)
+    v = np.ascontiguousarray(np.stack([y.real, y.imag], axis=-1), dtype=np.float64)
+    q = np.empty(v.shape, dtype=np.int16)
+    lib().oracle_quantise_i16(_ptr(v, ctypes.c_double), v.size, _ptr(q, ctypes.c_int16))
+    return q
+
+
+def _planes(desc, e):
+    e = np.asarray(e)
+    assert e.shape == (desc["n_tx"], desc["n_ch"], desc["n_samples"]), e.shape
+    return (np.ascontiguousarray(e.real, dtype=np.float64),
+            np.ascontiguousarray(e.imag, dtype=np.float64))
+
+
+def das_iq(desc: dict, e: np.ndarray, c: float | None = None) -> np.ndarray:
+    """Complex IQ image (Ny, Nx, Nz) of complex decoded data e (n_tx, n_ch, S).
+
+    ``desc["fs"]`` is the IQ sampling rate and ``desc["fc"]`` the
+    demodulation frequency of the phase rotation."""
+    geo = Geometry(desc, c)
+    er, ei = _planes(desc, e)
+    o_r = np.empty(geo.shape, dtype=np.float64)
+    o_i = np.empty(geo.shape, dtype=np.float64)
+    lib().oracle_das_iq(ctypes.byref(geo.g), float(desc["fc"]), _ptr(er, ctypes.c_double),
+                        _ptr(ei, ctypes.c_double), _ptr(o_r, ctypes.c_double),
+                        _ptr(o_i, ctypes.c_double))
+    return o_r + 1j * o_i
+
+
+def das_iq_points(desc: dict, e: np.ndarray, vox: np.ndarray, c: float | None = None) -> np.ndarray:
+    """das_iq at the listed linear voxel indices only."""
+    geo = Geometry(desc, c)
+    er, ei = _planes(desc, e)
+    vox = np.ascontiguousarray(vox, dtype=np.int64)
+    assert vox.size == 0 or (vox.min() >= 0 and vox.max() < geo.n_vox)
+    o_r = np.empty(vox.shape, dtype=np.float64)
+    o_i = np.empty(vox.shape, dtype=np.float64)
+    lib().oracle_das_iq_points(ctypes.byref(geo.g), float(desc["fc"]), _ptr(er, ctypes.c_double),
+                               _ptr(ei, ctypes.c_double), _ptr(vox, ctypes.c_int64), vox.size,
+                               _ptr(o_r, ctypes.c_double), _ptr(o_i, ctypes.c_double))
+    return o_r + 1j * o_i

@@ -344,3 +344,126 @@ double oracle_sharpness(const double *img, int64_t n, double *grad)
         }
     return -P / (Q * Q);
 }
+
+/* ------------------------------------------------------------------------- */
+/* Demodulation, filtering, decimation (Eq. 4; Sec. VII-D; Sec. VII-C order)  */
+/* ------------------------------------------------------------------------- */
+
+/* Eq. 4, IQ[n] = LPF{ s[n] exp(-j 2 pi fd n / fs) }, in the paper's order:
+ * first every input sample is mixed with the complex exponential at its own
+ * index, then the FIR filter h (the baseband matched filter or a plain
+ * low-pass; real or complex taps) is applied as a convolution, then every
+ * D-th filter output is kept (decimation comes after the low-pass, which
+ * must precede it):
+ *   m[n]  = x[n] (cos(2 pi r n) - j sin(2 pi r n)),    r = fd / fs
+ *   y[n]  = sum_{k=0}^{N_f-1} h[k] m[n-k],             m[n < 0] = 0
+ *   IQ[q] = y[q D],                                    q = 0 .. ceil(S / D) - 1
+ * Readings: n counts from sample 0 of the record; the convolution is causal
+ * with the signal start zero-padded (the paper pads the start with zeros in
+ * its LDS filter); no group-delay compensation (a caller folds the filter
+ * delay into t0); output q is the filter output at input sample q D.
+ * x: [n_traces][S] int16; y: [n_traces][n_out][2] (re, im), double. */
+void oracle_demod(const int16_t *x, int n_traces, int S, const double *h_re, const double *h_im,
+                  int n_taps, double fd_over_fs, int D, double *y)
+{
+    const int n_out = (S + D - 1) / D;
+#pragma omp parallel
+    {
+        double *mr = malloc(sizeof(double) * (size_t)S);
+        double *mi = malloc(sizeof(double) * (size_t)S);
+#pragma omp for schedule(static)
+        for (int tr = 0; tr < n_traces; ++tr) {
+            const int16_t *xs = x + (size_t)tr * S;
+            for (int n = 0; n < S; ++n) {
+                double ph = 2.0 * M_PI * fd_over_fs * (double)n;
+                mr[n] = (double)xs[n] * cos(ph);
+                mi[n] = -(double)xs[n] * sin(ph);
+            }
+            double *yo = y + (size_t)tr * n_out * 2;
+            for (int q = 0; q < n_out; ++q) {
+                const long n = (long)q * D;
+                double ar = 0.0, ai = 0.0;
+                for (int k = 0; k < n_taps; ++k) {
+                    long idx = n - k;
+                    if (idx < 0) break;
+                    double hr = h_re[k], hi = h_im ? h_im[k] : 0.0;
+                    ar += hr * mr[idx] - hi * mi[idx];
+                    ai += hr * mi[idx] + hi * mr[idx];
+                }
+                yo[2 * q] = ar;
+                yo[2 * q + 1] = ai;
+            }
+        }
+        free(mr);
+        free(mi);
+    }
+}
+
+/* Conversion of the filtered result back to 16-bit integers (Sec. VII-C:
+ * filter gains <= 1 keep the data in 16 bits).  Reading: round to nearest
+ * with ties to even, saturating at the int16 limits. */
+void oracle_quantise_i16(const double *y, int64_t n, int16_t *q)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double r = nearbyint(y[i]);
+        if (r > 32767.0) r = 32767.0;
+        if (r < -32768.0) r = -32768.0;
+        q[i] = (int16_t)r;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* IQ (complex baseband) beamforming                                          */
+/* ------------------------------------------------------------------------- */
+
+/* Eq. 1 on demodulated data: each term reads the complex trace at the sample
+ * position s = (tof - t0) fs (fs is the IQ sampling rate) with the same
+ * interpolator applied to the real and imaginary parts, then restores the
+ * carrier phase that the mix of Eq. 4 removed at that record time:
+ *   HR(p) = sum_ij a(p,i,j) IQ_ij(s) exp(+j 2 pi fd (tof - t0)).
+ * Reading: the phase restored is that of the record time tof - t0 (the mix
+ * counts n from sample 0, whose time is t0), so the terms of a scatterer add
+ * coherently across traces. */
+static void das_point_iq(const oracle_geom *g, double fd, const double *er, const double *ei,
+                         int64_t v, double *out_re, double *out_im)
+{
+    int Nx = g->dims[0], Nz = g->dims[2];
+    int iz = (int)(v % Nz), ix = (int)((v / Nz) % Nx), iy = (int)(v / ((int64_t)Nz * Nx));
+    double p[3];
+    voxel_position(g, ix, iy, iz, p);
+    double acc_r = 0.0, acc_i = 0.0;
+    for (int i = 0; i < g->n_tx; ++i)
+        for (int j = 0; j < g->n_ch; ++j) {
+            double tof, a;
+            tof_apod(g, p, i, j, &tof, &a);
+            if (a == 0.0) continue;
+            size_t off = ((size_t)i * g->n_ch + j) * g->n_samples;
+            double s = sample_pos(g, tof);
+            double vr = oracle_interp(er + off, g->n_samples, s, g->interp);
+            double vi = oracle_interp(ei + off, g->n_samples, s, g->interp);
+            double ph = 2.0 * M_PI * fd * (tof - g->t0);
+            double c = cos(ph), sn = sin(ph);
+            acc_r += a * (vr * c - vi * sn);
+            acc_i += a * (vr * sn + vi * c);
+        }
+    *out_re = acc_r;
+    *out_im = acc_i;
+}
+
+/* Full complex image: out_re / out_im [iy][ix][iz]; e_re / e_im are the real
+ * and imaginary planes of the decoded data [n_tx][n_ch][n_samples]. */
+void oracle_das_iq(const oracle_geom *g, double fd, const double *e_re, const double *e_im,
+                   double *out_re, double *out_im)
+{
+    int64_t nv = n_voxels(g);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t v = 0; v < nv; ++v) das_point_iq(g, fd, e_re, e_im, v, &out_re[v], &out_im[v]);
+}
+
+void oracle_das_iq_points(const oracle_geom *g, double fd, const double *e_re, const double *e_im,
+                          const int64_t *vox, int64_t n, double *out_re, double *out_im)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < n; ++q)
+        das_point_iq(g, fd, e_re, e_im, vox[q], &out_re[q], &out_im[q]);
+}

@@ -35,5 +35,12 @@ void oracle_das_points(const oracle_geom *g, const double *e, const int64_t *vox
 void oracle_das_adjoint_e(const oracle_geom *g, const double *G, double *grad_e);
 void oracle_das_dc(const oracle_geom *g, const double *e, double *dout);
 double oracle_sharpness(const double *img, int64_t n, double *grad);
+void oracle_demod(const int16_t *x, int n_traces, int S, const double *h_re, const double *h_im,
+                  int n_taps, double fd_over_fs, int D, double *y);
+void oracle_quantise_i16(const double *y, int64_t n, int16_t *q);
+void oracle_das_iq(const oracle_geom *g, double fd, const double *e_re, const double *e_im,
+                   double *out_re, double *out_im);
+void oracle_das_iq_points(const oracle_geom *g, double fd, const double *e_re, const double *e_im,
+                          const int64_t *vox, int64_t n, double *out_re, double *out_im);
 
 #endif

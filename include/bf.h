@@ -6,6 +6,9 @@
  * and TOBE Arrays".  The path is: int16 RF channel data -> Hadamard decode
  * across transmits (Sec. IV-A; Sec. VII-E) -> DAS with receive apodization
  * (Eqs. 1-3; Sec. VII-F) and fractional-delay interpolation (Sec. IV-B).
+ * Optionally the RF is first demodulated to complex baseband (IQ), filtered
+ * and decimated (Eq. 4; Sec. VII-D), decoded as complex int16 and
+ * beamformed as IQ data with a per-term phase rotation.
  *
  * Conventions shared by every entry point
  *  - Every function returns a bf_status (0 = BF_OK, < 0 = error).  Nothing
@@ -29,6 +32,9 @@
  *  rf   int16            [n_tx][n_ch][n_samples]   encoded channel data, sample fastest
  *  e    f32 | bf16 | i32 [n_tx][n_ch][n_samples]   decoded data (type = params.e_type)
  *  out  f32              [Ny][Nx][Nz]              image / volume, z (depth) fastest
+ * IQ plans (params.iq = 1) add a trailing (re, im) pair to each:
+ *  rf   int16 [n_tx][n_ch][n_samples][2],  e  f32 [n_tx][n_ch][n_samples][2],
+ *  out  f32   [Ny][Nx][Nz][2]
  */
 #ifndef BF_H
 #define BF_H
@@ -39,7 +45,7 @@
 extern "C" {
 #endif
 
-#define BF_ABI_VERSION 1
+#define BF_ABI_VERSION 2
 
 typedef enum {
     BF_OK = 0,
@@ -102,6 +108,15 @@ typedef struct {
     int32_t out_dims[3];       /* Nx, Ny, Nz output points (Ny = 1 for a B-scan)        */
     double  out_min[3];        /* inclusive region bounds in the global frame, metres:  */
     double  out_max[3];        /*   point k on axis a = min + k (max-min)/(N-1)         */
+    /* 0: real RF samples.  1: complex baseband (IQ) samples as written by
+     * bf_demodulate (layouts above); fs is then the IQ sampling rate, fc the
+     * demodulation frequency fd of Eq. 4, and e_type must be BF_E_F32.  DAS reads
+     * the complex trace with the plan's interpolator (real and imaginary parts
+     * alike) and rotates each term by exp(+j 2 pi fd (tof - t0)), the phase the
+     * demodulation removed at that record time.  IQ plans support bf_decode,
+     * bf_das, bf_set_* and bf_autotune; bf_das_adjoint and the batched entry
+     * points return BF_ERR_UNSUPPORTED. */
+    int32_t iq;
 } bf_params;
 
 typedef struct bf_plan_s *bf_plan;   /* opaque, owned by libbf */
@@ -119,8 +134,9 @@ typedef struct {
     int32_t block[3];          /* wavefront tiles per LDS workgroup along x, y, z      */
     int32_t nb;                /* traces per staged batch                              */
     int64_t workspace_bytes;   /* device memory held by the plan                       */
-    int64_t e_elems;           /* elements of decoded data per frame (frame 0)         */
-    int64_t out_elems;         /* output points per frame (frame 0)                    */
+    int64_t e_elems;           /* elements of decoded data per frame (frame 0; IQ
+                                  plans count the two FP32 parts of a sample)          */
+    int64_t out_elems;         /* output values per frame (frame 0; IQ: 2 per point)   */
 } bf_plan_info;
 
 /* ABI version of the loaded library (BF_ABI_VERSION). */
@@ -216,6 +232,49 @@ int bf_batch_run(bf_plan plan, const int16_t *const *rf, float *const *out, void
  * later calls.  The frame pointers are copied into the plan's device table
  * before each replay, so new buffers need no re-capture. */
 int bf_graph_launch(bf_plan plan, const int16_t *const *rf, float *const *out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Demodulation (Eq. 4; Sec. VII-D): the stage before decoding.
+ *   y[n]  = sum_{k=0}^{N_f-1} h[k] x[n-k] exp(-j 2 pi fd (n-k) / fs),  x[n<0] = 0
+ *   iq[q] = y[q D],   q = 0 .. n_out-1,  n_out = ceil(n_samples / D)
+ * i.e. mix every sample with the carrier (n counted from sample 0 of the
+ * record), filter with h (the baseband matched filter, which also acts as the
+ * low-pass; real or complex taps), then keep every D-th output (decimation
+ * after the low-pass).  The filter is causal and not delay-compensated: fold
+ * its group delay into the t0 of the IQ plan if wanted.  Computed in FP32;
+ * BF_IQ_I16 output is rounded to nearest (ties to even) and saturated to int16,
+ * which loses nothing for filters with gain <= 1 (the paper's convention), so
+ * the data do not grow for the next stage.
+ *   rf: device int16 [n_traces][n_samples] (n_traces = n_tx * n_ch of a frame)
+ *   iq: device [n_traces][n_out][2] (re, im), int16 or f32 per out_type; for
+ *       int16 this is exactly the rf layout of an IQ plan with n_samples = n_out.
+ * ------------------------------------------------------------------------- */
+enum { BF_IQ_I16 = 0, BF_IQ_F32 = 1 };
+
+typedef struct {
+    int32_t n_traces;          /* traces per call, >= 1                                */
+    int32_t n_samples;         /* input samples per trace, 1..65536                    */
+    int32_t decimation;        /* D, 1..16                                             */
+    int32_t n_taps;            /* filter length N_f, 1..1024                           */
+    const double *taps_re;     /* host, n_taps: real parts of h (copied at create)     */
+    const double *taps_im;     /* host, n_taps, or NULL for a real filter              */
+    double fs;                 /* input sampling rate, Hz, > 0                         */
+    double fd;                 /* demodulation frequency, Hz, finite                   */
+    int32_t out_type;          /* BF_IQ_I16 or BF_IQ_F32                               */
+} bf_demod_params;
+
+typedef struct bf_demod_s *bf_demod;   /* opaque, owned by libbf */
+
+/* Validate, then upload the filter (folded with the mix, FP64 -> FP32) and the
+ * output rotations to the current device.  Errors as bf_plan_create (SHAPE for
+ * counts out of range, GEOMETRY for non-finite fs / fd / taps). */
+int bf_demod_create(const bf_demod_params *params, bf_demod *out);
+/* Free a demodulator (waits for the device first).  NULL is a no-op. */
+int bf_demod_destroy(bf_demod d);
+/* Output samples per trace, ceil(n_samples / D). */
+int bf_demod_out_samples(bf_demod d, int32_t *n_out);
+/* Demodulate one frame on `stream` (asynchronous).  rf and iq must not overlap. */
+int bf_demodulate(bf_demod d, const int16_t *rf, void *iq, void *stream);
 
 /* Evaluates the library's Hann-window polynomial W at u^2 (host, for tests). */
 double bf_hann_poly(double u2);

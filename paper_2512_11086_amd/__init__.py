@@ -7,7 +7,9 @@ device memory and streams) and raises ``BfError`` on a failed status.
 
 A problem description is a dict with the paper's inputs (Sec. VI-B): mode,
 n_tx, n_ch, n_samples, n_elem, pitch, xdc (4x4 global -> array frame),
-tx_elements, channel_map, fs, fc, c, t0, f_number, interp, dims, gmin, gmax.
+tx_elements, channel_map, fs, fc, c, t0, f_number, interp, dims, gmin, gmax,
+and optionally iq (complex baseband data; fs is then the IQ rate and fc the
+demodulation frequency).
 """
 from __future__ import annotations
 
@@ -16,10 +18,10 @@ import math
 
 import numpy as np
 
-from ._lib import (BfError, DECODE_ALGOS, ETYPES, INTERPS, MODES, Params, PlanInfo, check,
-                   lib)
+from ._lib import (BfError, DECODE_ALGOS, DemodParams, ETYPES, INTERPS, IQ_TYPES, MODES, Params,
+                   PlanInfo, check, lib)
 
-__all__ = ["BfError", "Plan", "BatchPlan", "params_from_desc", "sharpness", "validate",
+__all__ = ["BfError", "Plan", "BatchPlan", "Demod", "params_from_desc", "sharpness", "validate",
            "hann_poly"]
 
 
@@ -51,6 +53,7 @@ class _Marshalled:
         p.out_dims[:] = [int(v) for v in desc["dims"]]
         p.out_min[:] = [float(v) for v in desc["gmin"]]
         p.out_max[:] = [float(v) for v in desc["gmax"]]
+        p.iq = 1 if desc.get("iq", False) else 0
         self.p = p
 
 
@@ -100,6 +103,12 @@ class Plan:
         self.n_tx, self.n_ch, self.n_samples = (int(desc[k]) for k in ("n_tx", "n_ch", "n_samples"))
         nx, ny, nz = (int(v) for v in desc["dims"])
         self.out_shape = (ny, nx, nz)
+        self.iq = bool(desc.get("iq", False))
+        # IQ plans: rf int16 and e float32 carry a trailing (re, im) axis; the
+        # image is complex64
+        tail = (2,) if self.iq else ()
+        self.rf_shape = (self.n_tx, self.n_ch, self.n_samples) + tail
+        self.e_shape = self.rf_shape
         self.c = float(desc["c"])
         if tile is not None:
             self.set_tile(*tile)
@@ -141,13 +150,13 @@ class Plan:
         torch = _torch()
         if rf.dtype != torch.int16 or not rf.is_cuda or not rf.is_contiguous():
             raise ValueError("rf must be a contiguous int16 CUDA tensor")
-        if tuple(rf.shape) != (self.n_tx, self.n_ch, self.n_samples):
-            raise ValueError(f"rf shape {tuple(rf.shape)} != {(self.n_tx, self.n_ch, self.n_samples)}")
+        if tuple(rf.shape) != self.rf_shape:
+            raise ValueError(f"rf shape {tuple(rf.shape)} != {self.rf_shape}")
 
     def _check_e(self, e):
         if e.dtype != self.e_dtype() or not e.is_cuda or not e.is_contiguous():
             raise ValueError(f"e must be a contiguous {self.e_dtype()} CUDA tensor")
-        if tuple(e.shape) != (self.n_tx, self.n_ch, self.n_samples):
+        if tuple(e.shape) != self.e_shape:
             raise ValueError("e has the wrong shape")
 
     def decode(self, rf, out=None, stream=None):
@@ -162,10 +171,11 @@ class Plan:
     def das(self, e, c: float | None = None, out=None, stream=None):
         torch = _torch()
         self._check_e(e)
+        odt = torch.complex64 if self.iq else torch.float32
         if out is None:
-            out = torch.empty(self.out_shape, dtype=torch.float32, device=e.device)
-        if out.dtype != torch.float32 or tuple(out.shape) != self.out_shape or not out.is_contiguous():
-            raise ValueError("out must be a contiguous float32 tensor of the image shape")
+            out = torch.empty(self.out_shape, dtype=odt, device=e.device)
+        if out.dtype != odt or tuple(out.shape) != self.out_shape or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous {odt} tensor of the image shape")
         check(lib().bf_das(self._h, _ptr(e), _ptr(out), float(self.c if c is None else c),
                            _stream(stream)))
         return out
@@ -187,6 +197,63 @@ class Plan:
                                    _ptr(ge) if ge is not None else None,
                                    _ptr(gc) if gc is not None else None, _stream(stream)))
         return ge, gc
+
+
+class Demod:
+    """bf_demodulate: mix with exp(-j 2 pi fd n / fs), FIR-filter, decimate (Eq. 4).
+
+    ``taps`` is a real or complex 1-D sequence; ``out`` "i16" gives the int16
+    (re, im) layout an IQ plan decodes, "f32" float32 pairs."""
+
+    def __init__(self, n_traces: int, n_samples: int, taps, fd: float, fs: float,
+                 decimation: int = 1, out: str = "i16"):
+        h = np.asarray(taps)
+        self._re = np.ascontiguousarray(h.real, dtype=np.float64).reshape(-1)
+        self._im = (np.ascontiguousarray(h.imag, dtype=np.float64).reshape(-1)
+                    if np.iscomplexobj(h) else None)
+        P = ctypes.POINTER(ctypes.c_double)
+        p = DemodParams()
+        p.n_traces, p.n_samples = int(n_traces), int(n_samples)
+        p.decimation, p.n_taps = int(decimation), int(self._re.size)
+        p.taps_re = self._re.ctypes.data_as(P)
+        p.taps_im = self._im.ctypes.data_as(P) if self._im is not None else None
+        p.fs, p.fd = float(fs), float(fd)
+        p.out_type = IQ_TYPES[out]
+        self.out = out
+        h_ = ctypes.c_void_p()
+        check(lib().bf_demod_create(ctypes.byref(p), ctypes.byref(h_)))
+        self._h = h_
+        n = ctypes.c_int32()
+        check(lib().bf_demod_out_samples(self._h, ctypes.byref(n)))
+        self.n_traces, self.n_samples, self.n_out = int(n_traces), int(n_samples), int(n.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check(lib().bf_demod_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __call__(self, rf, out=None, stream=None):
+        """rf: contiguous int16 CUDA tensor whose last axis is the n_samples and
+        whose leading axes hold n_traces traces; returns (..., n_out, 2)."""
+        torch = _torch()
+        if rf.dtype != torch.int16 or not rf.is_cuda or not rf.is_contiguous():
+            raise ValueError("rf must be a contiguous int16 CUDA tensor")
+        if rf.shape[-1] != self.n_samples or rf.numel() != self.n_traces * self.n_samples:
+            raise ValueError("rf does not hold n_traces x n_samples samples")
+        shape = tuple(rf.shape[:-1]) + (self.n_out, 2)
+        dt = torch.int16 if self.out == "i16" else torch.float32
+        if out is None:
+            out = torch.empty(shape, dtype=dt, device=rf.device)
+        if out.dtype != dt or tuple(out.shape) != shape or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous {dt} tensor of shape {shape}")
+        check(lib().bf_demodulate(self._h, _ptr(rf), _ptr(out), _stream(stream)))
+        return out
 
 
 class BatchPlan:

@@ -39,7 +39,19 @@ class Params(ctypes.Structure):
         ("t0", ctypes.c_double), ("focal_depth", ctypes.c_double), ("f_number", ctypes.c_double),
         ("interp", ctypes.c_int32), ("e_type", ctypes.c_int32), ("decode_algo", ctypes.c_int32),
         ("out_dims", ctypes.c_int32 * 3), ("out_min", ctypes.c_double * 3),
-        ("out_max", ctypes.c_double * 3),
+        ("out_max", ctypes.c_double * 3), ("iq", ctypes.c_int32),
+    ]
+
+
+IQ_TYPES = {"i16": 0, "f32": 1}
+
+
+class DemodParams(ctypes.Structure):
+    _fields_ = [
+        ("n_traces", ctypes.c_int32), ("n_samples", ctypes.c_int32),
+        ("decimation", ctypes.c_int32), ("n_taps", ctypes.c_int32),
+        ("taps_re", ctypes.POINTER(ctypes.c_double)), ("taps_im", ctypes.POINTER(ctypes.c_double)),
+        ("fs", ctypes.c_double), ("fd", ctypes.c_double), ("out_type", ctypes.c_int32),
     ]
 
 
@@ -81,6 +93,10 @@ def lib():
         "bf_batch_run": ([vp, P(vp), P(vp), vp], ctypes.c_int),
         "bf_graph_launch": ([vp, P(vp), P(vp), vp], ctypes.c_int),
         "bf_hann_poly": ([dbl], dbl),
+        "bf_demod_create": ([P(DemodParams), P(vp)], ctypes.c_int),
+        "bf_demod_destroy": ([vp], ctypes.c_int),
+        "bf_demod_out_samples": ([vp, P(i32)], ctypes.c_int),
+        "bf_demodulate": ([vp, vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -98,4 +114,5 @@ def check(status: int) -> None:
 EXPORTED = ("bf_abi_version", "bf_last_error", "bf_validate", "bf_plan_create",
             "bf_plan_create_batch", "bf_plan_destroy", "bf_plan_get_info", "bf_autotune",
             "bf_set_tile", "bf_set_das_config", "bf_decode", "bf_das", "bf_das_adjoint", "bf_sharpness",
-            "bf_batch_run", "bf_graph_launch", "bf_hann_poly")
+            "bf_batch_run", "bf_graph_launch", "bf_hann_poly", "bf_demod_create",
+            "bf_demod_destroy", "bf_demod_out_samples", "bf_demodulate")

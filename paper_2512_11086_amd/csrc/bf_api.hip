@@ -23,6 +23,8 @@ hipError_t launch_sharpness(const float *img, long n, int n_images, float *loss,
 
 static thread_local std::string g_err;
 
+void clear_err() { g_err.clear(); }
+
 int fail(int code, const char *fmt, ...)
 {
     char buf[512];
@@ -55,6 +57,9 @@ int validate_params(const bf_params *p)
         return fail(BF_ERR_UNSUPPORTED, "unknown decoded-data type %d", p->e_type);
     if (p->decode_algo != BF_DECODE_MFMA_I8 && p->decode_algo != BF_DECODE_FMA_F32)
         return fail(BF_ERR_UNSUPPORTED, "unknown decode algorithm %d", p->decode_algo);
+    if (p->iq != 0 && p->iq != 1) return fail(BF_ERR_UNSUPPORTED, "iq must be 0 or 1");
+    if (p->iq && p->e_type != BF_E_F32)
+        return fail(BF_ERR_UNSUPPORTED, "IQ plans decode to BF_E_F32 only");
     if (p->n_tx < 1 || p->n_tx > 256) return fail(BF_ERR_SHAPE, "n_tx=%d not in [1,256]", p->n_tx);
     if (p->n_ch < 1 || p->n_ch > 1024) return fail(BF_ERR_SHAPE, "n_ch=%d not in [1,1024]", p->n_ch);
     if (p->n_samples < 1 || p->n_samples > 65536)
@@ -63,10 +68,11 @@ int validate_params(const bf_params *p)
         return fail(BF_ERR_SHAPE, "n_elem must be >= 1");
     for (int a = 0; a < 3; ++a)
         if (p->out_dims[a] < 1) return fail(BF_ERR_SHAPE, "out_dims[%d]=%d < 1", a, p->out_dims[a]);
-    const int64_t ne = (int64_t)p->n_tx * p->n_ch * p->n_samples;
+    const int parts = p->iq ? 2 : 1;
+    const int64_t ne = (int64_t)p->n_tx * p->n_ch * p->n_samples * parts;
     if (ne >= (int64_t(1) << 31))
         return fail(BF_ERR_TOO_LARGE, "channel data has %lld elements (limit 2^31)", (long long)ne);
-    const int64_t nv = (int64_t)p->out_dims[0] * p->out_dims[1] * p->out_dims[2];
+    const int64_t nv = (int64_t)p->out_dims[0] * p->out_dims[1] * p->out_dims[2] * parts;
     if (nv >= (int64_t(1) << 31))
         return fail(BF_ERR_TOO_LARGE, "output has %lld points (limit 2^31)", (long long)nv);
     for (int a = 0; a < 2; ++a)
@@ -273,7 +279,7 @@ int Frame::init(const bf_params &src)
         if (G > gmax) G = gmax;
         groups = (int)(G < 1 ? 1 : G);
         if (groups > 1) {
-            d_part = (float *)alloc((size_t)groups * nvox * sizeof(float));
+            d_part = (float *)alloc((size_t)groups * nvox * (p.iq ? 2 : 1) * sizeof(float));
             if (!d_part) return fail(BF_ERR_HIP, "device allocation of partial images failed");
         }
     }
@@ -300,8 +306,9 @@ void Frame::set_tile(int lx_, int ly_, int lz_)
     lz = lz_;
 }
 
-int64_t Frame::e_elems() const { return (int64_t)p.n_tx * p.n_ch * p.n_samples; }
-int64_t Frame::out_elems() const { return (int64_t)grid.nx * grid.ny * grid.nz; }
+int64_t Frame::e_elems() const { return (int64_t)p.n_tx * p.n_ch * p.n_samples * (p.iq ? 2 : 1); }
+int64_t Frame::out_elems() const { return (int64_t)grid.nx * grid.ny * grid.nz * (p.iq ? 2 : 1); }
+int Frame::das_et() const { return p.iq ? ET_CF32 : p.e_type; }
 size_t Frame::e_bytes() const { return (size_t)e_elems() * (p.e_type == BF_E_BF16 ? 2 : 4); }
 
 DecodeArgs Frame::decode_args(const int16_t *rf, void *e) const
@@ -314,7 +321,7 @@ DecodeArgs Frame::decode_args(const int16_t *rf, void *e) const
     a.Hf = d_Hf;
     a.n_tx = p.n_tx;
     a.n_ch = p.n_ch;
-    a.S = p.n_samples;
+    a.S = p.n_samples * (p.iq ? 2 : 1);   // IQ: (re, im) pairs decode as two samples
     return a;
 }
 
@@ -345,6 +352,9 @@ DasArgs Frame::das_args(const void *e, float *out, double c) const
     a.groups = groups;
     a.part = d_part;
     a.hann_tab = d_hann;
+    a.cx = p.iq;
+    a.rot_d = p.iq ? p.fc / p.fs : 0.0;
+    a.rot = (float)a.rot_d;
     return a;
 }
 
@@ -378,7 +388,9 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
     const int nwaves = nthr / 64;
     // staging rounds per thread: ceil(nb / waves) traces x ceil(lmax / 64) quads <= 2
     auto rounds = [&](int n) { return ((n + nwaves - 1) / nwaves) * ((lmax + 63) / 64); };
-    while (nbb >= unit && (rounds(nbb) > 2 || lds_bytes(p.n_tx, p.n_ch, nbb, lmax) > lds_cap))
+    const int qs = p.iq ? 2 : 1;
+    while (nbb >= unit &&
+           (rounds(nbb) > 2 || lds_bytes(p.n_tx, p.n_ch, nbb, lmax, qs) > lds_cap))
         nbb -= unit;
     if (nbb < unit || nthr > 1024) return false;
     cfg->bwx = bw[0];
@@ -402,9 +414,9 @@ int Frame::das(const void *e, float *out, double c, hipStream_t s) const
     LdsCfg cfg;
     hipError_t err;
     if (variant == 0 && lds_config(a, &cfg))
-        err = launch_das_lds(a, cfg, p.mode, p.e_type, p.interp, s);
+        err = launch_das_lds(a, cfg, p.mode, das_et(), p.interp, s);
     else
-        err = launch_das(a, p.mode, p.e_type, p.interp, s);
+        err = launch_das(a, p.mode, das_et(), p.interp, s);
     return err == hipSuccess ? BF_OK : hip_fail(err, "DAS launch");
 }
 
@@ -584,6 +596,7 @@ int bf_das_adjoint(bf_plan plan, const void *e, const float *grad_out, double c,
     if (grad_c && !e) return fail(BF_ERR_NULL, "e is needed for grad_c");
     if ((st = check_c(c)) != BF_OK) return st;
     const Frame &f = *plan->frames[0];
+    if (f.p.iq) return fail(BF_ERR_UNSUPPORTED, "the adjoint is defined for RF plans only");
     DasArgs a = f.das_args(e, nullptr, c);
     a.grad_out = grad_out;
     a.grad_e = grad_e;

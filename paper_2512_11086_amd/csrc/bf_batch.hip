@@ -113,7 +113,7 @@ static int build_batch(bf_plan plan)
             memset(&c, 0, sizeof c);
         } else {
             const int threads = 64 * c.bwx * c.bwy * c.bwz;
-            const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax);
+            const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, 1);
             DasClass *cls = nullptr;
             for (DasClass &d : b->das)
                 if (d.mode == fr.p.mode && d.et == fr.p.e_type && d.ip == fr.p.interp &&
@@ -268,9 +268,11 @@ static int check_batch(bf_plan plan, const int16_t *const *rf, float *const *out
     if (!rf || !out) return fail(BF_ERR_NULL, "rf and out pointer arrays must be non-NULL");
     for (size_t f = 0; f < plan->frames.size(); ++f)
         if (!rf[f] || !out[f]) return fail(BF_ERR_NULL, "frame %zu has a NULL buffer", f);
-    for (Frame *fr : plan->frames)
+    for (Frame *fr : plan->frames) {
         if (fr->p.decode_algo != BF_DECODE_MFMA_I8)
             return fail(BF_ERR_UNSUPPORTED, "batched path runs the int8 decode only");
+        if (fr->p.iq) return fail(BF_ERR_UNSUPPORTED, "batched path takes RF frames only");
+    }
     if (!plan->batch) {
         int st = build_batch(plan);
         if (st != BF_OK) {
@@ -353,8 +355,9 @@ std::vector<TileCand> candidates(const Frame &f)
 std::string tune_key(const Frame &f, const char *arch)
 {
     char buf[256];
-    snprintf(buf, sizeof buf, "%s|m%d|tx%d|ch%d|S%d|%dx%dx%d|ip%d|et%d", arch, f.p.mode, f.p.n_tx,
-             f.p.n_ch, f.p.n_samples, f.grid.nx, f.grid.ny, f.grid.nz, f.p.interp, f.p.e_type);
+    snprintf(buf, sizeof buf, "%s|m%d|tx%d|ch%d|S%d|%dx%dx%d|ip%d|et%d%s", arch, f.p.mode,
+             f.p.n_tx, f.p.n_ch, f.p.n_samples, f.grid.nx, f.grid.ny, f.grid.nz, f.p.interp,
+             f.p.e_type, f.p.iq ? "|iq" : "");
     return buf;
 }
 

@@ -10,7 +10,9 @@ namespace bf {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-enum EType { ET_F32 = 0, ET_BF16 = 1, ET_I32 = 2 };
+// Element type of decoded data.  ET_CF32 is complex FP32 (re, im) pairs of IQ
+// plans; the DAS kernels then accumulate complex sums.
+enum EType { ET_F32 = 0, ET_BF16 = 1, ET_I32 = 2, ET_CF32 = 3 };
 enum Interp { IN_NEAREST = 0, IN_LINEAR = 1, IN_CUBIC = 2 };
 
 // ---------------------------------------------------------------------------
@@ -72,6 +74,9 @@ struct DasArgs {
     float *part;            // [groups][ny][nx][nz] partial images when groups > 1
     float *const *out_ref;  // if set, the output pointer is read from here (graph replay)
     const float2 *hann_tab; // [HANN_N + 1] (value, slope) of W over u^2 in [0, 1/4]
+    int cx;                 // IQ data: e, out and part hold (re, im) pairs
+    float rot;              // IQ: fd / fs, revolutions of carrier phase per sample
+    double rot_d;           // the same in FP64 (per-lane phase origin)
 };
 
 // Hann weight table: W(u) of Eq. 3 sampled at u^2 = k / (4 HANN_N), stored as
@@ -145,6 +150,28 @@ __device__ inline float load_e(const void *base, long idx)
     }
 }
 
+// IQ: the carrier phase restored for sample position nB + s is
+// fd (tof - t0) = rot (nB + s) revolutions.  rot * nB is large, so its
+// fractional part is taken once per lane in FP64; per term only rot * s (s is
+// the small FP32 offset) is added.
+__device__ inline float phase_origin(const DasArgs &a, int nB)
+{
+    const double f = a.rot_d * (double)nB;
+    return (float)(f - floor(f));
+}
+
+// IQ term: acc += w * v * exp(j 2 pi ph) with ph in revolutions.  The hardware
+// sine and cosine take revolutions; the argument is reduced to [0, 1) first.
+__device__ inline void rotate_acc(float2 v, float w, float ph, float2 &acc)
+{
+    const float f = __builtin_amdgcn_fractf(ph);
+    const float wc = w * __builtin_amdgcn_cosf(f), ws = w * __builtin_amdgcn_sinf(f);
+    acc.x = fmaf(v.x, wc, acc.x);
+    acc.x = fmaf(-v.y, ws, acc.x);
+    acc.y = fmaf(v.x, ws, acc.y);
+    acc.y = fmaf(v.y, wc, acc.y);
+}
+
 // Per-lane state of one output point of a DAS wavefront tile.
 struct Lane {
     bool valid;     // inside the grid
@@ -155,6 +182,7 @@ struct Lane {
     float fB;       // fractional part of B
     float thr;      // rho^2 threshold of the receive aperture (inf: no apodization)
     float wsc;      // u^2 = rho^2 * wsc
+    float ph0;      // IQ: carrier phase (revolutions, in [0, 1)) of sample position nB
 };
 
 __device__ inline Lane lane_setup(const DasArgs &a, int wave_id, int lane)
@@ -189,6 +217,7 @@ __device__ inline Lane lane_setup(const DasArgs &a, int wave_id, int lane)
         L.thr = __builtin_inff();
         L.wsc = 0.f;
     }
+    L.ph0 = phase_origin(a, L.nB);
     return L;
 }
 
@@ -204,8 +233,15 @@ __device__ inline const void *trace_ptr(const void *e, long trace, int S)
 {
     if constexpr (ET == ET_BF16)
         return static_cast<const uint16_t *>(e) + trace * S;
+    else if constexpr (ET == ET_CF32)
+        return static_cast<const float2 *>(e) + trace * S;
     else
         return static_cast<const float *>(e) + trace * S;   // f32 and i32 are 4 bytes
+}
+
+__device__ inline float2 load_c(const void *base, long idx)
+{
+    return static_cast<const float2 *>(base)[idx];
 }
 
 }  // namespace bf

@@ -18,9 +18,60 @@
 // no lane lies inside its receive aperture, tested on rho^2 against
 // z^2 / (4 F#^2) (no cosine, no square root).  FORCES tests once per channel
 // for all transmits, HERCULES per (row, column) element.
+//
+// IQ data (ET_CF32): the trace is read as (re, im) pairs with the same
+// interpolator and each term is rotated by the carrier phase of its record
+// time before it is added (complex accumulation).
 #include "bf_common.h"
 
 namespace bf {
+
+// Catmull-Rom cubic Hermite in Horner form around p0, for real or complex taps.
+__device__ inline float cr_eval(float t, float pm, float p0, float p1, float p2)
+{
+    const float c1 = 0.5f * (p1 - pm);
+    const float c2 = pm - 2.5f * p0 + 2.0f * p1 - 0.5f * p2;
+    const float c3 = 0.5f * (p2 - pm) + 1.5f * (p0 - p1);
+    return fmaf(t, fmaf(t, fmaf(t, c3, c2), c1), p0);
+}
+__device__ inline float2 cr_eval(float t, float2 pm, float2 p0, float2 p1, float2 p2)
+{
+    return make_float2(cr_eval(t, pm.x, p0.x, p1.x, p2.x), cr_eval(t, pm.y, p0.y, p1.y, p2.y));
+}
+
+// Complex read of an IQ trace at nB + s; zero outside [0, S).
+template <int IP>
+__device__ inline float2 read_trace_cx(const void *tr, int S, int nB, float s)
+{
+    const float2 z = make_float2(0.f, 0.f);
+    if constexpr (IP == IN_NEAREST) {
+        const int n = nB + (int)floorf(s + 0.5f);
+        return ((unsigned)n < (unsigned)S) ? load_c(tr, n) : z;
+    } else {
+        const float fl = floorf(s);
+        const float t = s - fl;
+        const int n = nB + (int)fl;
+        if constexpr (IP == IN_LINEAR) {
+            const float2 p0 = ((unsigned)n < (unsigned)S) ? load_c(tr, n) : z;
+            const float2 p1 = ((unsigned)(n + 1) < (unsigned)S) ? load_c(tr, n + 1) : z;
+            return make_float2(fmaf(t, p1.x - p0.x, p0.x), fmaf(t, p1.y - p0.y, p0.y));
+        } else {
+            float2 pm, p0, p1, p2;
+            if (n >= 1 && n + 2 < S) {
+                pm = load_c(tr, n - 1);
+                p0 = load_c(tr, n);
+                p1 = load_c(tr, n + 1);
+                p2 = load_c(tr, n + 2);
+            } else {
+                pm = ((unsigned)(n - 1) < (unsigned)S) ? load_c(tr, n - 1) : z;
+                p0 = ((unsigned)n < (unsigned)S) ? load_c(tr, n) : z;
+                p1 = ((unsigned)(n + 1) < (unsigned)S) ? load_c(tr, n + 1) : z;
+                p2 = ((unsigned)(n + 2) < (unsigned)S) ? load_c(tr, n + 2) : z;
+            }
+            return cr_eval(t, pm, p0, p1, p2);
+        }
+    }
+}
 
 // Read of trace `tr` at absolute sample position nB + s (s = small FP32
 // offset); zero outside [0, S).
@@ -51,13 +102,20 @@ __device__ inline float read_trace(const void *tr, int S, int nB, float s)
                 p1 = ((unsigned)(n + 1) < (unsigned)S) ? load_e<ET>(tr, n + 1) : 0.f;
                 p2 = ((unsigned)(n + 2) < (unsigned)S) ? load_e<ET>(tr, n + 2) : 0.f;
             }
-            // Catmull-Rom cubic Hermite in Horner form around p0.
-            const float c1 = 0.5f * (p1 - pm);
-            const float c2 = pm - 2.5f * p0 + 2.0f * p1 - 0.5f * p2;
-            const float c3 = 0.5f * (p2 - pm) + 1.5f * (p0 - p1);
-            return fmaf(t, fmaf(t, fmaf(t, c3, c2), c1), p0);
+            return cr_eval(t, pm, p0, p1, p2);
         }
     }
+}
+
+// acc += w * read(e_ij at nB + s), rotated for IQ data.
+template <int ET, int IP>
+__device__ inline void add_term(const DasArgs &a, const Lane &L, const void *tr, float w, float s,
+                                float2 &acc)
+{
+    if constexpr (ET == ET_CF32)
+        rotate_acc(read_trace_cx<IP>(tr, a.S, L.nB, s), w, fmaf(a.rot, s, L.ph0), acc);
+    else
+        acc.x = fmaf(w, read_trace<ET, IP>(tr, a.S, L.nB, s), acc.x);
 }
 
 // FORCES: the transmit and receive excess paths separate.  The wavefront
@@ -70,10 +128,10 @@ __device__ inline float read_trace(const void *tr, int S, int nB, float s)
 constexpr int JG = 8;
 
 template <int ET, int IP>
-__device__ inline float das_forces_point(const DasArgs &a, const Lane &L, int jb, int je)
+__device__ inline float2 das_forces_point(const DasArgs &a, const Lane &L, int jb, int je)
 {
     const float kf = (float)a.k;
-    float acc = 0.f;
+    float2 acc = make_float2(0.f, 0.f);
     int j = jb;
     for (;;) {
         int rows[JG];
@@ -103,7 +161,7 @@ __device__ inline float das_forces_point(const DasArgs &a, const Lane &L, int jb
             for (int q = 0; q < JG; ++q) {
                 if (q < n && L.active) {
                     const void *tr = trace_ptr<ET>(a.e, (long)i * a.n_ch + rows[q], a.S);
-                    acc = fmaf(aj[q], read_trace<ET, IP>(tr, a.S, L.nB, Rj[q] + T), acc);
+                    add_term<ET, IP>(a, L, tr, aj[q], Rj[q] + T, acc);
                 }
             }
         }
@@ -114,10 +172,10 @@ __device__ inline float das_forces_point(const DasArgs &a, const Lane &L, int jb
 // HERCULES: receive element (x_i, y_j, 0), plane-wave transmit (tof_tx = z/c,
 // already inside B), radial apodization.
 template <int ET, int IP>
-__device__ inline float das_hercules_point(const DasArgs &a, const Lane &L, int jb, int je)
+__device__ inline float2 das_hercules_point(const DasArgs &a, const Lane &L, int jb, int je)
 {
     const float kf = (float)a.k;
-    float acc = 0.f;
+    float2 acc = make_float2(0.f, 0.f);
     for (int j = jb; j < je; ++j) {
         const float dy = L.y - a.rx_c[j];
         const float dy2 = dy * dy;
@@ -131,7 +189,7 @@ __device__ inline float das_hercules_point(const DasArgs &a, const Lane &L, int 
                 const float s = fmaf(excess(rho2, L.z, L.z2), kf, L.fB);
                 const float w = hann_u2(rho2 * L.wsc);
                 const void *tr = trace_ptr<ET>(a.e, (long)i * a.n_ch + j, a.S);
-                acc = fmaf(w, read_trace<ET, IP>(tr, a.S, L.nB, s), acc);
+                add_term<ET, IP>(a, L, tr, w, s, acc);
             }
         }
     }
@@ -147,17 +205,20 @@ __global__ __launch_bounds__(256) void das_kernel(DasArgs a)
     const Lane L = lane_setup(a, wave_id, threadIdx.x & 63);
     int jb, je;
     group_rows(a.n_ch, blockIdx.y, a.groups, &jb, &je);
-    float acc;
+    float2 acc;
     if constexpr (MODE == 0)
         acc = das_forces_point<ET, IP>(a, L, jb, je);
     else
         acc = das_hercules_point<ET, IP>(a, L, jb, je);
     if (L.valid) {
-        const float v = L.active ? acc : 0.f;
-        if (a.groups > 1)
-            a.part[(long)blockIdx.y * a.g.nx * a.g.ny * a.g.nz + L.out_idx] = v;
+        if (!L.active) acc = make_float2(0.f, 0.f);
+        const long npts = (long)a.g.nx * a.g.ny * a.g.nz;
+        float *dst = a.groups > 1 ? a.part + (long)blockIdx.y * npts * (ET == ET_CF32 ? 2 : 1)
+                                  : das_out(a);
+        if constexpr (ET == ET_CF32)
+            reinterpret_cast<float2 *>(dst)[L.out_idx] = acc;
         else
-            das_out(a)[L.out_idx] = v;
+            dst[L.out_idx] = acc.x;
     }
 }
 
@@ -175,7 +236,7 @@ __global__ __launch_bounds__(256) void sum_groups_kernel(const float *part, floa
 
 hipError_t launch_sum_groups(const DasArgs &a, hipStream_t s)
 {
-    const long n = (long)a.g.nx * a.g.ny * a.g.nz;
+    const long n = (long)a.g.nx * a.g.ny * a.g.nz * (a.cx ? 2 : 1);
     long blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(sum_groups_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a.part, a.out,
@@ -203,6 +264,7 @@ static hipError_t launch_et(const DasArgs &a, int et, int ip, hipStream_t s)
         case ET_F32: return launch_ip<MODE, ET_F32>(a, ip, s);
         case ET_BF16: return launch_ip<MODE, ET_BF16>(a, ip, s);
         case ET_I32: return launch_ip<MODE, ET_I32>(a, ip, s);
+        case ET_CF32: return launch_ip<MODE, ET_CF32>(a, ip, s);
         default: return hipErrorInvalidValue;
     }
 }

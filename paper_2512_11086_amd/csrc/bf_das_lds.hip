@@ -20,6 +20,11 @@
 //
 // Delay precision: as in the gather kernel, s = B(p) + k (E_tx + E_rx) with
 // B in FP64 split into integer + FP32 fraction and E = rho^2 / (d + z) in FP32.
+//
+// IQ data (ET_CF32): a sample interval stages as two adjacent quads, the
+// coefficients of the real and of the imaginary part (32 bytes per interval),
+// and each term is rotated by its carrier phase before the complex
+// accumulation.
 #include "bf_common.h"
 
 namespace bf {
@@ -74,6 +79,7 @@ struct LaneL {
     float x, y, z, z2, thr, wsc, fB;
     float wtab;     // u^2 * 4 HANN_N = rho^2 * wtab (table coordinate)
     int nB;
+    float ph0;      // IQ: carrier phase of sample position nB (revolutions)
 };
 
 __device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, int by, int bz,
@@ -104,6 +110,7 @@ __device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, 
         L.thr = a.f2 > 0.f ? L.z2 * 0.25f / a.f2 : __builtin_inff();
         L.wsc = a.f2 > 0.f ? a.f2 / L.z2 : 0.f;
         L.wtab = L.wsc * (4.f * HANN_N);
+        L.ph0 = phase_origin(a, L.nB);
     } else {
         // benign values for points outside the grid or at z <= 0: far away
         // laterally, so rho^2 is huge (never NaN) and the weight is 0
@@ -114,6 +121,7 @@ __device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, 
         L.thr = -1.f;
         L.wsc = __builtin_inff();
         L.wtab = 1.f;        // rho^2 ~ 1e36 -> table index saturates, fract 0 -> weight 0
+        L.ph0 = 0.f;
     }
     return L;
 }
@@ -293,7 +301,7 @@ constexpr int QMAX = 2;   // staging rounds per thread per batch (host guarantee
 // the window start is computed once per (wavefront, trace) and consecutive
 // lanes read consecutive samples.
 struct Staged {
-    float p[QMAX][4];
+    float p[QMAX][8];    // taps n-1 .. n+2 (IQ: (re, im) of each)
     int w0[QMAX];
 };
 
@@ -311,6 +319,7 @@ __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const BoxGe
         const int e = wave + (q / mr) * nwaves;
         const int m = lane + 64 * (q % mr);
         float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+        float p4 = 0.f, p5 = 0.f, p6 = 0.f, p7 = 0.f;
         int w0 = 0;
         if (q < mr * ((c.nb + nwaves - 1) / nwaves) && e < c.nb) {
             int i, j;
@@ -321,7 +330,25 @@ __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const BoxGe
                     const int n = w0 + m;
                     const void *tr = trace_ptr<ET>(a.e, (long)i * a.n_ch + j, a.S);
                     const unsigned S = (unsigned)a.S;
-                    if (w0 >= 1 && w0 + c.lmax + 1 < a.S) {
+                    if constexpr (ET == ET_CF32) {
+                        // (re, im) of taps n-1 .. n+2: 32 contiguous bytes
+                        const float2 z = make_float2(0.f, 0.f);
+                        float2 t0, t1, t2, t3;
+                        if (w0 >= 1 && w0 + c.lmax + 1 < a.S) {
+                            float4 u, v;
+                            __builtin_memcpy(&u, static_cast<const float2 *>(tr) + (n - 1), 16);
+                            __builtin_memcpy(&v, static_cast<const float2 *>(tr) + (n + 1), 16);
+                            t0 = make_float2(u.x, u.y); t1 = make_float2(u.z, u.w);
+                            t2 = make_float2(v.x, v.y); t3 = make_float2(v.z, v.w);
+                        } else {
+                            t0 = ((unsigned)(n - 1) < S) ? load_c(tr, n - 1) : z;
+                            t1 = ((unsigned)n < S) ? load_c(tr, n) : z;
+                            t2 = ((unsigned)(n + 1) < S) ? load_c(tr, n + 1) : z;
+                            t3 = ((unsigned)(n + 2) < S) ? load_c(tr, n + 2) : z;
+                        }
+                        p0 = t0.x; p1 = t1.x; p2 = t2.x; p3 = t3.x;
+                        p4 = t0.y; p5 = t1.y; p6 = t2.y; p7 = t3.y;
+                    } else if (w0 >= 1 && w0 + c.lmax + 1 < a.S) {
                         // whole window inside the record (the usual case): one
                         // 16-byte load of the four taps (4-byte aligned)
                         if constexpr (ET == ET_F32) {
@@ -347,13 +374,31 @@ __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const BoxGe
         st.p[q][1] = p1;
         st.p[q][2] = p2;
         st.p[q][3] = p3;
+        st.p[q][4] = p4;
+        st.p[q][5] = p5;
+        st.p[q][6] = p6;
+        st.p[q][7] = p7;
         st.w0[q] = w0;
     }
 }
 
+// Coefficient quad of one sample interval from taps p[n-1] .. p[n+2].
+template <int IP>
+__device__ inline float4 coef_quad(float pm, float p0, float p1, float p2)
+{
+    if constexpr (IP == IN_CUBIC)
+        return make_float4(p0, 0.5f * (p1 - pm), pm - 2.5f * p0 + 2.0f * p1 - 0.5f * p2,
+                           0.5f * (p2 - pm) + 1.5f * (p0 - p1));
+    else if constexpr (IP == IN_LINEAR)
+        return make_float4(p0, p1 - p0, 0.f, 0.f);
+    else
+        return make_float4(p0, p1, 0.f, 0.f);
+}
+
 // Convert the loaded taps to coefficient quads and write them (and the
-// per-trace metadata) to one LDS buffer.
-template <int MODE, int IP>
+// per-trace metadata) to one LDS buffer.  QS = quads per sample interval
+// (2 for IQ data: real part, then imaginary part).
+template <int MODE, int IP, int QS>
 __device__ inline void stage_store(const LdsCfg &c, const float *s_tx, const BatchDesc &d,
                                    const Staged &st, float4 *quads, Meta *meta, int wave,
                                    int lane, int nwaves)
@@ -365,19 +410,10 @@ __device__ inline void stage_store(const LdsCfg &c, const float *s_tx, const Bat
         const int m = lane + 64 * (q % mr);
         if (q < mr * ((c.nb + nwaves - 1) / nwaves) && e < c.nb) {
             if (m < c.lmax) {
-                const float pm = st.p[q][0], p0 = st.p[q][1], p1 = st.p[q][2], p2 = st.p[q][3];
-                float4 cq;
-                if constexpr (IP == IN_CUBIC) {
-                    cq.x = p0;
-                    cq.y = 0.5f * (p1 - pm);
-                    cq.z = pm - 2.5f * p0 + 2.0f * p1 - 0.5f * p2;
-                    cq.w = 0.5f * (p2 - pm) + 1.5f * (p0 - p1);
-                } else if constexpr (IP == IN_LINEAR) {
-                    cq = make_float4(p0, p1 - p0, 0.f, 0.f);
-                } else {
-                    cq = make_float4(p0, p1, 0.f, 0.f);
-                }
-                quads[e * c.lmax + m] = cq;
+                const float *t = st.p[q];
+                quads[(e * c.lmax + m) * QS] = coef_quad<IP>(t[0], t[1], t[2], t[3]);
+                if constexpr (QS == 2)
+                    quads[(e * c.lmax + m) * 2 + 1] = coef_quad<IP>(t[4], t[5], t[6], t[7]);
             }
             if (m == 0) {
                 int i, j;
@@ -402,13 +438,26 @@ __device__ inline int clamp0_i32(int x, int hi)
 }
 
 template <int IP>
-__device__ inline float read_quad(const float4 *win, int li, int lmax, float t)
+__device__ inline float eval_quad(const float4 q, float t)
 {
-    li = clamp0_i32(li, lmax - 1);
-    const float4 q = win[li];
     if constexpr (IP == IN_NEAREST) return t < 0.5f ? q.x : q.y;
     if constexpr (IP == IN_LINEAR) return fmaf(t, q.y, q.x);
     return fmaf(t, fmaf(t, fmaf(t, q.w, q.z), q.y), q.x);
+}
+
+template <int IP>
+__device__ inline float read_quad(const float4 *win, int li, int lmax, float t)
+{
+    li = clamp0_i32(li, lmax - 1);
+    return eval_quad<IP>(win[li], t);
+}
+
+// IQ window: interval li holds the real quad at 2 li and the imaginary at 2 li + 1
+template <int IP>
+__device__ inline float2 read_quad_cx(const float4 *win, int li, int lmax, float t)
+{
+    li = clamp0_i32(li, lmax - 1);
+    return make_float2(eval_quad<IP>(win[2 * li], t), eval_quad<IP>(win[2 * li + 1], t));
 }
 
 // Beamforms workgroup box `blk` (channel group `grp`) of one frame.  Every
@@ -431,21 +480,26 @@ __device__ inline int add3_i32(int a, int b, int c)
 
 // One HERCULES term: receiver at lateral offset (x - xi, dy), trace window
 // `win` starting at sample interval w0 (passed negated, uniform).
-template <int IP>
-__device__ inline float hercules_term(const LaneL &L, const float4 *win, int lmax,
-                                      const float2 *hann, float dy2, float kf, float xi,
-                                      int neg_w0, float acc)
+template <int ET, int IP>
+__device__ inline void hercules_term(const LaneL &L, const float4 *win, int lmax,
+                                     const float2 *hann, float dy2, float kf, float rot, float xi,
+                                     int neg_w0, float2 &acc)
 {
     const float dx = L.x - xi;
     const float rho2 = fmaf(dx, dx, dy2);
     const float s = fmaf(excess(rho2, L.z, L.z2), kf, L.fB);
     const int li = add3_i32(cvt_flr(s), L.nB, neg_w0);
-    const float v = read_quad<IP>(win, li, lmax, __builtin_amdgcn_fractf(s));
     // Hann weight from the LDS table; u^2 >= 1/4 lands on the (0, 0) entry
     const float xw = rho2 * L.wtab;
     const float2 h = hann[min((unsigned)cvt_flr(xw), (unsigned)HANN_N)];
     const float w = fmaf(__builtin_amdgcn_fractf(xw), h.y, h.x);
-    return fmaf(w, v, acc);
+    if constexpr (ET == ET_CF32) {
+        const float2 v = read_quad_cx<IP>(win, li, lmax, __builtin_amdgcn_fractf(s));
+        rotate_acc(v, w, fmaf(rot, s, L.ph0), acc);
+    } else {
+        const float v = read_quad<IP>(win, li, lmax, __builtin_amdgcn_fractf(s));
+        acc.x = fmaf(w, v, acc.x);
+    }
 }
 
 template <int MODE, int ET, int IP>
@@ -462,7 +516,8 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     float *s_rx = s_tx + ((a.n_tx + 3) & ~3);
     float2 *s_hann = reinterpret_cast<float2 *>(s_rx + ((a.n_ch + 3) & ~3));
     float4 *bufbase = reinterpret_cast<float4 *>(s_hann + HANN_TAB_PAD);
-    const int buf_quads = c.nb * c.lmax + c.nb;   // Meta is 16 bytes = one float4
+    constexpr int QS = ET == ET_CF32 ? 2 : 1;     // quads per sample interval
+    const int buf_quads = c.nb * c.lmax * QS + c.nb;   // Meta is 16 bytes = one float4
     float4 *q0 = bufbase, *q1 = bufbase + buf_quads;
     for (int t = tid; t < a.n_tx; t += nthr) s_tx[t] = a.tx_x[t];
     for (int t = tid; t < a.n_ch; t += nthr) s_rx[t] = a.rx_c[t];
@@ -475,7 +530,8 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     const BoxGeom box = block_box(a, c, bx, by, bz);
     const LaneL L = lane_setup_l(a, c, bx, by, bz, wave, lane);
     const float kf = (float)a.k;
-    float acc = 0.f;
+    const float rot = a.rot;
+    float2 acc = make_float2(0.f, 0.f);
     __syncthreads();
 
     int jb, je;
@@ -491,8 +547,8 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     Staged st;
     if (cur.valid) {
         stage_load<MODE, ET>(a, c, box, s_tx, s_rx, cur, st, wave, lane, nwaves);
-        stage_store<MODE, IP>(c, s_tx, cur, st, q0 + c.nb, reinterpret_cast<Meta *>(q0), wave,
-                              lane, nwaves);
+        stage_store<MODE, IP, QS>(c, s_tx, cur, st, q0 + c.nb, reinterpret_cast<Meta *>(q0),
+                                  wave, lane, nwaves);
     }
     __syncthreads();
 
@@ -535,18 +591,18 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                 mask &= mask - 1;
                 const int e2 = __builtin_ctzll(mask);
                 mask &= mask - 1;
-                acc = hercules_term<IP>(L, quads + e1 * c.lmax, c.lmax, s_hann, dy2, kf,
-                                        __int_as_float(__builtin_amdgcn_readlane(xi_bits, e1)),
-                                        -__builtin_amdgcn_readlane(mine.w0, e1), acc);
-                acc = hercules_term<IP>(L, quads + e2 * c.lmax, c.lmax, s_hann, dy2, kf,
-                                        __int_as_float(__builtin_amdgcn_readlane(xi_bits, e2)),
-                                        -__builtin_amdgcn_readlane(mine.w0, e2), acc);
+                hercules_term<ET, IP>(L, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, kf, rot,
+                                      __int_as_float(__builtin_amdgcn_readlane(xi_bits, e1)),
+                                      -__builtin_amdgcn_readlane(mine.w0, e1), acc);
+                hercules_term<ET, IP>(L, quads + e2 * c.lmax * QS, c.lmax, s_hann, dy2, kf, rot,
+                                      __int_as_float(__builtin_amdgcn_readlane(xi_bits, e2)),
+                                      -__builtin_amdgcn_readlane(mine.w0, e2), acc);
             }
             if (mask) {
                 const int e1 = __builtin_ctzll(mask);
-                acc = hercules_term<IP>(L, quads + e1 * c.lmax, c.lmax, s_hann, dy2, kf,
-                                        __int_as_float(__builtin_amdgcn_readlane(xi_bits, e1)),
-                                        -__builtin_amdgcn_readlane(mine.w0, e1), acc);
+                hercules_term<ET, IP>(L, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, kf, rot,
+                                      __int_as_float(__builtin_amdgcn_readlane(xi_bits, e1)),
+                                      -__builtin_amdgcn_readlane(mine.w0, e1), acc);
             }
         } else {
             const int nbi = c.nb / JC;
@@ -576,26 +632,35 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                     const int e = q * nbi + ii;
                     const int w0 = __builtin_amdgcn_readlane(mine.w0, e);
                     const float sq = Rj[q] + T;
-                    const float v = read_quad<IP>(quads + e * c.lmax, (int)floorf(sq) + L.nB - w0,
-                                                  c.lmax, __builtin_amdgcn_fractf(sq));
-                    acc = fmaf(aj[q], v, acc);
+                    const int li = (int)floorf(sq) + L.nB - w0;
+                    if constexpr (ET == ET_CF32) {
+                        const float2 v = read_quad_cx<IP>(quads + e * c.lmax * QS, li, c.lmax,
+                                                          __builtin_amdgcn_fractf(sq));
+                        rotate_acc(v, aj[q], fmaf(rot, sq, L.ph0), acc);
+                    } else {
+                        const float v = read_quad<IP>(quads + e * c.lmax, li, c.lmax,
+                                                      __builtin_amdgcn_fractf(sq));
+                        acc.x = fmaf(aj[q], v, acc.x);
+                    }
                 }
             }
         }
 
         if (!nxt.valid) break;
         float4 *nb_ = ((bi + 1) & 1) ? q1 : q0;
-        stage_store<MODE, IP>(c, s_tx, nxt, st, nb_ + c.nb, reinterpret_cast<Meta *>(nb_), wave,
-                              lane, nwaves);
+        stage_store<MODE, IP, QS>(c, s_tx, nxt, st, nb_ + c.nb, reinterpret_cast<Meta *>(nb_),
+                                  wave, lane, nwaves);
         __syncthreads();
         cur = nxt;
         ++bi;
     }
     if (L.valid) {
-        if (a.groups > 1)
-            a.part[(long)grp * a.g.nx * a.g.ny * a.g.nz + L.out_idx] = acc;
+        const long npts = (long)a.g.nx * a.g.ny * a.g.nz;
+        float *dst = a.groups > 1 ? a.part + (long)grp * npts * QS : das_out(a);
+        if constexpr (ET == ET_CF32)
+            reinterpret_cast<float2 *>(dst)[L.out_idx] = acc;
         else
-            das_out(a)[L.out_idx] = acc;
+            dst[L.out_idx] = acc.x;
     }
 }
 
@@ -714,20 +779,21 @@ static hipError_t launch_lds_et(const DasArgs &a, const LdsCfg &c, int et, int i
         case ET_F32: return launch_lds_ip<MODE, ET_F32>(a, c, ip, shm, s);
         case ET_BF16: return launch_lds_ip<MODE, ET_BF16>(a, c, ip, shm, s);
         case ET_I32: return launch_lds_ip<MODE, ET_I32>(a, c, ip, shm, s);
+        case ET_CF32: return launch_lds_ip<MODE, ET_CF32>(a, c, ip, shm, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax)
+size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs)
 {
     return (size_t)(((n_tx + 3) & ~3) + ((n_ch + 3) & ~3)) * 4 + (size_t)HANN_TAB_PAD * 8 +
-           2 * (size_t)(nb * lmax + nb) * 16;
+           2 * (size_t)(nb * lmax * qs + nb) * 16;
 }
 
 hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, int ip,
                           hipStream_t s)
 {
-    const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax);
+    const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, a.cx ? 2 : 1);
     hipError_t err = mode == 0 ? launch_lds_et<0>(a, c, et, ip, shm, s)
                                : launch_lds_et<1>(a, c, et, ip, shm, s);
     if (err != hipSuccess || a.groups <= 1) return err;

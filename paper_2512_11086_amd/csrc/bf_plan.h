@@ -11,6 +11,7 @@
 namespace bf {
 
 int fail(int code, const char *fmt, ...);
+void clear_err();
 int hip_fail(hipError_t e, const char *what);
 int validate_params(const bf_params *p);
 
@@ -48,6 +49,7 @@ struct Frame {
     void set_tile(int lx, int ly, int lz);
     int64_t e_elems() const;
     int64_t out_elems() const;
+    int das_et() const;          // element type of the DAS kernels (ET_CF32 for IQ plans)
     size_t e_bytes() const;
     DecodeArgs decode_args(const int16_t *rf, void *e) const;
     DasArgs das_args(const void *e, float *out, double c) const;
@@ -61,7 +63,7 @@ struct Batch;   // persistent batched path state (bf_batch.hip)
 hipError_t launch_das(const DasArgs &a, int mode, int et, int ip, hipStream_t s);
 hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, int ip,
                           hipStream_t s);
-size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax);
+size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs);
 
 constexpr uint32_t BF_PLAN_MAGIC = 0xBF0C0DE5u;
 

@@ -145,3 +145,32 @@ def frames_4_plan(rng: np.random.Generator, n_frames: int = 64):
         kind = "2d" if rng.random() < 0.5 else "3d"
         plan.append((kind, cols))
     return plan
+
+
+def lowpass_taps(n_taps: int, cutoff: float) -> np.ndarray:
+    """Hamming-windowed sinc low-pass, cutoff in cycles/sample, unit DC gain.
+
+    Input generation only: the paper's filters (a 36-tap low-pass for volumes,
+    a 166-tap matched chirp filter for B-scans) are inputs to the method; this
+    stands in for the low-pass one."""
+    n = np.arange(n_taps) - (n_taps - 1) / 2.0
+    h = 2 * cutoff * np.sinc(2 * cutoff * n) * np.hamming(n_taps)
+    return h / h.sum()
+
+
+def iq_frontend(desc: dict, n_taps: int = 36, decimation: int = 2):
+    """Demodulation setup for an RF workload: (taps, decimation, IQ description).
+
+    The RF is demodulated at its centre frequency with a low-pass of cutoff
+    fc / 2 (the echo band is about +-0.4 fc around the carrier), decimated by
+    `decimation`, and beamformed as IQ data: fs becomes fs / D, n_samples
+    ceil(S / D), and t0 moves back by the filter's group delay (N_f - 1) / 2
+    input samples so that IQ sample q lines up with record time."""
+    fs, fc = float(desc["fs"]), float(desc["fc"])
+    taps = lowpass_taps(n_taps, 0.5 * fc / fs)
+    d = dict(desc)
+    d["iq"] = True
+    d["fs"] = fs / decimation
+    d["n_samples"] = (int(desc["n_samples"]) + decimation - 1) // decimation
+    d["t0"] = float(desc["t0"]) - (n_taps - 1) / 2.0 / fs
+    return taps, decimation, d

@@ -4,16 +4,19 @@ import numpy as np
 import synth
 
 
+def _as64(a):
+    a = np.asarray(a)
+    return a.astype(np.complex128) if np.iscomplexobj(a) else a.astype(np.float64)
+
+
 def rel_l2(got, ref):
-    got = np.asarray(got, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
+    got, ref = _as64(got), _as64(ref)
     den = np.linalg.norm(ref)
     return float(np.linalg.norm(got - ref) / den) if den > 0 else float(np.linalg.norm(got))
 
 
 def max_rel(got, ref):
-    got = np.asarray(got, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
+    got, ref = _as64(got), _as64(ref)
     m = np.abs(ref).max()
     return float(np.abs(got - ref).max() / m) if m > 0 else float(np.abs(got).max())
 

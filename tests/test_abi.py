@@ -32,7 +32,7 @@ def test_library_exports_every_declared_function():
     for name in names:
         assert hasattr(L, name), f"{name} declared in bf.h but not exported"
     assert set(names) == set(_lib.EXPORTED)
-    assert L.bf_abi_version() == 1
+    assert L.bf_abi_version() == 2
 
 
 def _good(k=0):
@@ -164,3 +164,52 @@ def test_hann_polynomial_matches_window():
     assert np.max(np.abs(got - want)) < 3e-7
     assert bfm.hann_poly(0.0) == 1.0
     assert abs(bfm.hann_poly(0.25)) < 1e-6
+
+
+def test_validate_iq_descriptions():
+    d, H = _good(1)
+    iq = dict(d, iq=True)
+    assert _status(iq, H) == 0, _lib.lib().bf_last_error()
+    assert _status(iq, H, e_type="bf16") == -5          # IQ decodes to FP32 only
+    m = bfm.params_from_desc(d, H)
+    m.p.iq = 2
+    assert _lib.lib().bf_validate(ctypes.byref(m.p)) == -5
+
+
+def _demod_status(**kw):
+    taps = np.ascontiguousarray(kw.pop("taps", np.ones(4)), dtype=np.float64)
+    p = _lib.DemodParams()
+    p.n_traces, p.n_samples, p.decimation = kw.get("n_traces", 4), kw.get("S", 100), kw.get("D", 2)
+    p.n_taps = kw.get("n_taps", taps.size)
+    p.taps_re = taps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if kw.get("re", True) else None
+    p.taps_im = None
+    p.fs, p.fd = kw.get("fs", 20e6), kw.get("fd", 5e6)
+    p.out_type = kw.get("out_type", 0)
+    h = ctypes.c_void_p()
+    st = _lib.lib().bf_demod_create(ctypes.byref(p), ctypes.byref(h))
+    if st == 0:
+        _lib.lib().bf_demod_destroy(h)
+    return st
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n_traces=0), -2), (dict(S=0), -2), (dict(S=65537), -2), (dict(D=0), -2),
+    (dict(D=17), -2), (dict(n_taps=0), -2), (dict(taps=np.ones(1025)), -2),
+    (dict(out_type=7), -5), (dict(fs=0.0), -4), (dict(fd=math.inf), -4),
+    (dict(taps=np.array([1.0, math.nan])), -4), (dict(re=False), -1),
+    (dict(n_traces=40000, S=65536), -6),
+])
+def test_demod_validation_errors(kw, code):
+    assert _demod_status(**kw) == code
+
+
+def test_demod_null_arguments_and_no_device():
+    L = _lib.lib()
+    assert L.bf_demod_create(None, None) == -1
+    assert L.bf_demod_destroy(None) == 0
+    assert L.bf_demodulate(None, None, None, None) == -1
+    n = ctypes.c_int32()
+    assert L.bf_demod_out_samples(None, ctypes.byref(n)) == -1
+    import torch
+    if not torch.cuda.is_available():
+        assert _demod_status() == -8                     # valid, but no gfx950 here

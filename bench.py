@@ -187,6 +187,60 @@ def batched_comparison(torch, bfm, synth, reps: int):
             "max_rel_l2_between_paths": worst}
 
 
+def iq_pipeline(torch, bfm, synth, desc, H, rf_d, n_act, reps: int):
+    """Demodulate (Eq. 4) + decode complex int16 + IQ DAS of the same RF:
+    36-tap low-pass (the paper's volume filter length), decimation 2 ->
+    1024 complex samples at 15 MHz."""
+    from synth.configs import iq_frontend
+    taps, D, dq = iq_frontend(desc)
+    n_tr = desc["n_tx"] * desc["n_ch"]
+    dm = bfm.Demod(n_tr, desc["n_samples"], taps, desc["fc"], desc["fs"], D)
+    plan = bfm.Plan(dq, H)
+    stream = torch.cuda.current_stream()
+    iq = dm(rf_d)
+    e = plan.decode(iq)
+    img = plan.das(e)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
+    for k in range(reps):
+        ev[k][0].record(stream)
+        dm(rf_d, out=iq)
+        ev[k][1].record(stream)
+        plan.decode(iq, out=e)
+        ev[k][2].record(stream)
+        plan.das(e, out=img)
+        ev[k][3].record(stream)
+    torch.cuda.synchronize()
+    t = np.array([[ev[k][i].elapsed_time(ev[k][i + 1]) for i in range(3)] for k in range(reps)])
+    dem_ms, dec_ms, das_ms = (float(v) for v in t.mean(axis=0))
+    step = dem_ms + dec_ms + das_ms
+    n_out = dm.n_out
+    # demodulation: per output N_f complex-by-real taps (4 flops) + the
+    # rotation (6); HBM: 2 bytes in per input sample, 4 bytes out per output
+    dem_flops = n_tr * n_out * (4 * len(taps) + 6)
+    dem_bytes = n_tr * (2 * desc["n_samples"] + 4 * n_out)
+    dem_tf = dem_flops / (dem_ms * 1e-3) / 1e12
+    # IQ term: delay 13, apodization 14, two cubic reads 32, phase 2, sin+cos
+    # 2, weight x rotation 2, complex multiply-accumulate 8 = 73 flops
+    das_tf = n_act * 73 / (das_ms * 1e-3) / 1e12
+    nominal = int(np.prod(dq["dims"])) * dq["n_tx"] * dq["n_ch"]
+    return {
+        "workload": "same RF -> demodulate (36-tap low-pass, D = 2, fd = 7.5 MHz) -> "
+                    "decode complex int16 (128 x 128 x 1024 x 2) -> IQ DAS 128x128x256 complex",
+        "ms_per_step": round(step, 4), "value": round(nominal / (step * 1e-3) / 1e9, 3),
+        "unit": "G samples/s", "demod_ms": round(dem_ms, 4), "decode_ms": round(dec_ms, 4),
+        "das_ms": round(das_ms, 4),
+        "demod_roofline": {"bound": "alu", "achieved": round(dem_tf, 2),
+                           "peak": round(FP32_NONPACKED_TFLOPS, 1), "unit": "TFLOP/s",
+                           "frac": round(dem_tf / FP32_NONPACKED_TFLOPS, 4),
+                           "hbm_GBps": round(dem_bytes / (dem_ms * 1e-3) / 1e9, 1)},
+        "das_roofline": {"bound": "alu", "achieved": round(das_tf, 2),
+                         "peak": round(FP32_NONPACKED_TFLOPS, 1), "unit": "TFLOP/s",
+                         "frac": round(das_tf / FP32_NONPACKED_TFLOPS, 4)},
+        "das_config": plan.info(),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +250,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-frame batched comparison")
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--no-iq", action="store_true", help="skip the demodulation + IQ pipeline")
+    ap.add_argument("--iq-reps", type=int, default=3)
     ap.add_argument("--traffic", action="store_true",
                     help="only run the short kernel sequence used for counter collection")
     args = ap.parse_args()
@@ -280,6 +336,9 @@ def main():
                      "traffic": measured_traffic()},
     }
     res["das_config"] = plan.info()
+    if not args.no_iq:
+        res["iq"] = iq_pipeline(torch, bfm, synth, desc, H, rf_d, n_act, args.iq_reps)
+        log(f"IQ pipeline {res['iq']['ms_per_step']:.3f} ms")
     if not args.no_batch:
         res["batched"] = batched_comparison(torch, bfm, synth, args.batch_reps)
     if not args.no_cpu:

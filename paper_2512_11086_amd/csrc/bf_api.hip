@@ -217,6 +217,12 @@ int Frame::init(const bf_params &src)
         bw[0] = 2; bw[1] = 1; bw[2] = 2;
         nb = 4;
         variant = BF_DAS_GATHER;   // 2D windows are long for the LDS staging limit
+    } else if (p.iq) {
+        // IQ kernels hold more registers (complex accumulators and quads): two
+        // 8-wavefront workgroups per CU
+        set_tile(3, 3, 0);
+        bw[0] = 4; bw[1] = 2; bw[2] = 1;
+        nb = 16;
     } else {
         set_tile(3, 3, 0);
         bw[0] = 2; bw[1] = 2; bw[2] = 3;

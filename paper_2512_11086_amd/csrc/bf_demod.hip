@@ -11,15 +11,19 @@
 // host in FP64 and rounded to FP32.  Only the kept outputs q D are computed
 // (decimation, Sec. VII-C: as early as possible, after the low-pass).
 //
-// A workgroup owns 256 consecutive outputs of one trace.  It stages the input
-// span they read (255 D + N_f samples, converted to FP32 once, zeros before the
+// A workgroup of T threads owns 4 T consecutive outputs of one trace.  It
+// stages the input span they read (converted to FP32 once, zeros before the
 // record -- the paper's LDS filter with zero padding) in LDS, split into its D
-// polyphase components so that lanes whose outputs are D samples apart read
-// consecutive LDS words.  Taps are workgroup-uniform and come through scalar
-// loads.
+// polyphase components: within a component, outputs q and q + 1 read
+// neighbouring words.  Each thread computes 4 consecutive outputs from a
+// sliding 8-word register window refilled by one aligned 16-byte LDS read per
+// 4 taps, so every LDS word read feeds 4 outputs (the paper's LDS sharing,
+// carried one level further into registers).  Taps are workgroup-uniform and
+// come through scalar loads.
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "bf.h"
@@ -28,18 +32,18 @@
 
 namespace bf {
 
-constexpr int DEMOD_THREADS = 256;
+constexpr int DEMOD_M = 4;            // consecutive outputs per thread
 constexpr int DEMOD_MAX_TAPS = 1024;
 constexpr int DEMOD_MAX_D = 16;
 
 struct DemodArgs {
     const int16_t *x;     // [n_traces][S]
     void *y;              // [n_traces][n_out][2], int16 or f32
-    const float2 *g;      // [n_taps] folded taps, polyphase order (see bf_demod_create)
+    const float2 *g;      // folded taps, polyphase order, each component padded to 4
     const float2 *rot;    // [n_out] exp(-j 2 pi r q D)
     int n_traces, S, n_out, D, n_taps;
     int chunks;           // workgroups per trace
-    int phase_len;        // LDS words per polyphase component
+    int phase_len;        // LDS words per polyphase component (multiple of 4)
 };
 
 __device__ inline int16_t sat_i16(float v)
@@ -48,62 +52,121 @@ __device__ inline int16_t sat_i16(float v)
     return (int16_t)(int)fminf(fmaxf(r, -32768.f), 32767.f);
 }
 
-template <int OT>
-__global__ __launch_bounds__(DEMOD_THREADS) void demod_kernel(DemodArgs a)
+// Taps of polyphase component ph (of D) of an N-tap filter, and that count
+// rounded up to a multiple of 4 (the host pads with zero taps).
+__host__ __device__ inline int phase_taps(int N, int D, int ph)
 {
-    extern __shared__ float xs[];                 // [D][phase_len]
+    return ph < N ? (N - 1 - ph) / D + 1 : 0;
+}
+__host__ __device__ inline int phase_taps4(int N, int D, int ph)
+{
+    return (phase_taps(N, D, ph) + 3) & ~3;
+}
+
+template <int OT, int T>
+__global__ __launch_bounds__(T) void demod_kernel(DemodArgs a)
+{
+    extern __shared__ float4 xs4[];                // [D][phase_len / 4]
+    float *xs = reinterpret_cast<float *>(xs4);
+    const int t = threadIdx.x;
     const int blk = blockIdx.x;
     const int trace = blk / a.chunks;
-    const int q0 = (blk - trace * a.chunks) * DEMOD_THREADS;
+    const int q0 = (blk - trace * a.chunks) * (T * DEMOD_M);
     const int16_t *x = a.x + (long)trace * a.S;
-    // span position p holds input sample n0 + p, n0 = q0 D - (N_f - 1);
-    // stored at xs[(p % D) * phase_len + p / D]
+    // Word w of component ph holds input sample n0 + ph + D w, with
+    // n0 = q0 D - (N_f - 1); samples outside the record read as 0.
     const int n0 = q0 * a.D - (a.n_taps - 1);
-    const int span = (DEMOD_THREADS - 1) * a.D + a.n_taps;
-    for (int p = threadIdx.x; p < span; p += DEMOD_THREADS) {
-        const int n = n0 + p;
-        const float v = (n >= 0 && n < a.S) ? (float)x[n] : 0.f;
-        const int ph = p % a.D;
-        xs[ph * a.phase_len + p / a.D] = v;
-    }
-    __syncthreads();
-    const int q = q0 + threadIdx.x;
-    // Output q = q0 + t reads span positions t D + off, off = N_f - 1 - k,
-    // i.e. word t + off / D of polyphase component off % D.  Loop over the
-    // components; inside one, off = ph + D b, so the LDS word advances by one
-    // and the taps (host-ordered the same way in g) are contiguous.
-    const int top = a.n_taps - 1;
-    float ar = 0.f, ai = 0.f;
-    const float2 *__restrict__ gp = a.g;
-    for (int ph = 0; ph < a.D && ph <= top; ++ph) {
-        const int nb = (top - ph) / a.D + 1;
-        const float *xp = xs + ph * a.phase_len + threadIdx.x;
-        int b = 0;
-        for (; b + 4 <= nb; b += 4) {
+    // Loads are unconditional from a clamped index (then zeroed), four per
+    // thread in flight before their conversions.
+    for (int ph = 0; ph < a.D; ++ph) {
+        for (int w0 = 0; w0 < a.phase_len; w0 += 4 * T) {
+            int16_t v[4];
+            int n[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const float v = xp[b + u];
-                ar = fmaf(gp[b + u].x, v, ar);
-                ai = fmaf(gp[b + u].y, v, ai);
+                n[u] = n0 + ph + a.D * (w0 + u * T + t);
+                v[u] = x[min(max(n[u], 0), a.S - 1)];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int w = w0 + u * T + t;
+                if (w < a.phase_len)
+                    xs[ph * a.phase_len + w] = (n[u] >= 0 && n[u] < a.S) ? (float)v[u] : 0.f;
             }
         }
-        for (; b < nb; ++b) {
-            const float v = xp[b];
-            ar = fmaf(gp[b].x, v, ar);
-            ai = fmaf(gp[b].y, v, ai);
-        }
-        gp += nb;
     }
+    __syncthreads();
+    // Output o = t M + m (of this workgroup) reads word o + b of component ph
+    // for tap k = N_f - 1 - ph - D b.  The thread slides an 8-word window
+    // along its words tM + b .. tM + b + 7, refilled by one aligned 16-byte
+    // read per 4 taps; each word then feeds all M outputs.
+    float ar[DEMOD_M], ai[DEMOD_M];
+#pragma unroll
+    for (int m = 0; m < DEMOD_M; ++m) ar[m] = ai[m] = 0.f;
+    const float2 *__restrict__ gp = a.g;
+    for (int ph = 0; ph < a.D; ++ph) {
+        const int nb4 = phase_taps4(a.n_taps, a.D, ph);
+        const float4 *wp = xs4 + (ph * a.phase_len) / 4 + t;   // words tM .. (M = 4)
+        float4 lo = wp[0];
+        for (int b = 0; b < nb4; b += 4) {
+            const float4 hi = wp[b / 4 + 1];
+            const float w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float2 gk = gp[b + u];
+#pragma unroll
+                for (int m = 0; m < DEMOD_M; ++m) {
+                    ar[m] = fmaf(gk.x, w[u + m], ar[m]);
+                    ai[m] = fmaf(gk.y, w[u + m], ai[m]);
+                }
+            }
+            lo = hi;
+        }
+        gp += nb4;
+    }
+    const int q = q0 + t * DEMOD_M;
     if (q >= a.n_out) return;
-    const float2 r = a.rot[q];
-    const float yr = fmaf(ar, r.x, -ai * r.y);
-    const float yi = fmaf(ar, r.y, ai * r.x);
     const long o = (long)trace * a.n_out + q;
-    if constexpr (OT == BF_IQ_I16) {
-        const uint32_t lo = (uint16_t)sat_i16(yr), hi = (uint16_t)sat_i16(yi);
-        static_cast<uint32_t *>(a.y)[o] = lo | (hi << 16);
+    if (q + DEMOD_M <= a.n_out) {
+        const float4 r01 = *reinterpret_cast<const float4 *>(a.rot + q);
+        const float4 r23 = *reinterpret_cast<const float4 *>(a.rot + q + 2);
+        const float rx[4] = {r01.x, r01.z, r23.x, r23.z}, ry[4] = {r01.y, r01.w, r23.y, r23.w};
+        float yr[4], yi[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            yr[m] = fmaf(ar[m], rx[m], -ai[m] * ry[m]);
+            yi[m] = fmaf(ar[m], ry[m], ai[m] * rx[m]);
+        }
+        if constexpr (OT == BF_IQ_I16) {
+            uint4 v;
+            v.x = (uint16_t)sat_i16(yr[0]) | ((uint32_t)(uint16_t)sat_i16(yi[0]) << 16);
+            v.y = (uint16_t)sat_i16(yr[1]) | ((uint32_t)(uint16_t)sat_i16(yi[1]) << 16);
+            v.z = (uint16_t)sat_i16(yr[2]) | ((uint32_t)(uint16_t)sat_i16(yi[2]) << 16);
+            v.w = (uint16_t)sat_i16(yr[3]) | ((uint32_t)(uint16_t)sat_i16(yi[3]) << 16);
+            uint32_t *dst = static_cast<uint32_t *>(a.y) + o;
+            if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+                *reinterpret_cast<uint4 *>(dst) = v;
+            } else {
+                dst[0] = v.x; dst[1] = v.y; dst[2] = v.z; dst[3] = v.w;
+            }
+        } else {
+            float2 *dst = static_cast<float2 *>(a.y) + o;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) dst[m] = make_float2(yr[m], yi[m]);
+        }
     } else {
-        static_cast<float2 *>(a.y)[o] = make_float2(yr, yi);
+#pragma unroll
+        for (int m = 0; m < DEMOD_M; ++m) {
+            if (q + m >= a.n_out) break;
+            const float2 r = a.rot[q + m];
+            const float yr = fmaf(ar[m], r.x, -ai[m] * r.y);
+            const float yi = fmaf(ar[m], r.y, ai[m] * r.x);
+            if constexpr (OT == BF_IQ_I16)
+                static_cast<uint32_t *>(a.y)[o + m] =
+                    (uint16_t)sat_i16(yr) | ((uint32_t)(uint16_t)sat_i16(yi) << 16);
+            else
+                static_cast<float2 *>(a.y)[o + m] = make_float2(yr, yi);
+        }
     }
 }
 
@@ -184,8 +247,10 @@ int bf_demod_create(const bf_demod_params *params, bf_demod *out)
     const double r = params->fd / params->fs;
     std::vector<float2> g, rot(d->n_out);
     // g[k] = h[k] exp(j 2 pi r k) in FP64, stored in the kernel's read order:
-    // component ph = 0 .. D-1, then k = N-1-ph, N-1-ph-D, ... >= 0
-    for (int ph = 0; ph < D && ph < N; ++ph)
+    // component ph = 0 .. D-1, then k = N-1-ph, N-1-ph-D, ... >= 0, each
+    // component padded with zero taps to a multiple of 4
+    for (int ph = 0; ph < D; ++ph) {
+        const size_t start = g.size();
         for (int k = N - 1 - ph; k >= 0; k -= D) {
             const double hr = params->taps_re[k], hi = params->taps_im ? params->taps_im[k] : 0.0;
             double f = r * k;
@@ -193,11 +258,14 @@ int bf_demod_create(const bf_demod_params *params, bf_demod *out)
             const double c = cos(2.0 * M_PI * f), s = sin(2.0 * M_PI * f);
             g.push_back(make_float2((float)(hr * c - hi * s), (float)(hr * s + hi * c)));
         }
+        g.resize(start + phase_taps4(N, D, ph), make_float2(0.f, 0.f));
+    }
     for (int q = 0; q < d->n_out; ++q) rot[q] = cis_rev(-r * (double)q * D);
     hipError_t e;
-    if ((e = hipMalloc(&d->d_g, N * sizeof(float2))) != hipSuccess ||
+    if ((e = hipMalloc(&d->d_g, g.size() * sizeof(float2))) != hipSuccess ||
         (e = hipMalloc(&d->d_rot, d->n_out * sizeof(float2))) != hipSuccess ||
-        (e = hipMemcpy(d->d_g, g.data(), N * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d->d_g, g.data(), g.size() * sizeof(float2), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
         (e = hipMemcpy(d->d_rot, rot.data(), d->n_out * sizeof(float2), hipMemcpyHostToDevice)) !=
             hipSuccess) {
         delete d;
@@ -243,19 +311,28 @@ int bf_demodulate(bf_demod d, const int16_t *rf, void *iq, void *stream)
     a.n_out = d->n_out;
     a.D = d->p.decimation;
     a.n_taps = d->p.n_taps;
-    a.chunks = (d->n_out + DEMOD_THREADS - 1) / DEMOD_THREADS;
-    const int span = (DEMOD_THREADS - 1) * a.D + a.n_taps;
-    a.phase_len = (span + a.D - 1) / a.D;
+    // Workgroup of T threads x 4 outputs; each component needs the words of
+    // T*4 outputs plus its padded taps plus the window's 4-word prefetch.
+    int nb4max = 0;
+    for (int ph = 0; ph < a.D; ++ph) nb4max = std::max(nb4max, phase_taps4(a.n_taps, a.D, ph));
+    const int T = (a.D * (256 * DEMOD_M + nb4max + 4) * 4 <= 48 * 1024) ? 256 : 64;
+    a.chunks = (d->n_out + T * DEMOD_M - 1) / (T * DEMOD_M);
+    a.phase_len = T * DEMOD_M + nb4max + 4;
     const size_t shm = (size_t)a.D * a.phase_len * sizeof(float);
     const long blocks = (long)a.n_traces * a.chunks;
     if (blocks >= (1L << 31)) return fail(BF_ERR_TOO_LARGE, "too many workgroups");
     hipStream_t s = (hipStream_t)stream;
-    if (d->p.out_type == BF_IQ_I16)
-        hipLaunchKernelGGL(demod_kernel<BF_IQ_I16>, dim3((unsigned)blocks), dim3(DEMOD_THREADS),
-                           shm, s, a);
-    else
-        hipLaunchKernelGGL(demod_kernel<BF_IQ_F32>, dim3((unsigned)blocks), dim3(DEMOD_THREADS),
-                           shm, s, a);
+    if (d->p.out_type == BF_IQ_I16) {
+        if (T == 256)
+            hipLaunchKernelGGL((demod_kernel<BF_IQ_I16, 256>), dim3((unsigned)blocks), dim3(T), shm, s, a);
+        else
+            hipLaunchKernelGGL((demod_kernel<BF_IQ_I16, 64>), dim3((unsigned)blocks), dim3(T), shm, s, a);
+    } else {
+        if (T == 256)
+            hipLaunchKernelGGL((demod_kernel<BF_IQ_F32, 256>), dim3((unsigned)blocks), dim3(T), shm, s, a);
+        else
+            hipLaunchKernelGGL((demod_kernel<BF_IQ_F32, 64>), dim3((unsigned)blocks), dim3(T), shm, s, a);
+    }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? BF_OK : hip_fail(e, "demodulation launch");
 }

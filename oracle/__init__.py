@@ -80,6 +80,9 @@ def lib():
         L.oracle_das_iq.argtypes = [P(_Geom), ctypes.c_double, D, D, D, D]
         L.oracle_das_iq_points.argtypes = [P(_Geom), ctypes.c_double, D, D, P(ctypes.c_int64),
                                            ctypes.c_int64, D, D]
+        L.oracle_envelope.argtypes = [D, ctypes.c_int64, ctypes.c_int, D]
+        L.oracle_compress.argtypes = [D, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
+                                      ctypes.c_double, D]
         _lib = L
     return _lib
 
@@ -263,3 +266,27 @@ def das_iq_points(desc: dict, e: np.ndarray, vox: np.ndarray, c: float | None = 
                                _ptr(ei, ctypes.c_double), _ptr(vox, ctypes.c_int64), vox.size,
                                _ptr(o_r, ctypes.c_double), _ptr(o_i, ctypes.c_double))
     return o_r + 1j * o_i
+
+
+# ---------------------------------------------------------------------------
+# Envelope (analytic signal along depth) and display compression
+# ---------------------------------------------------------------------------
+COMPRESS = {"none": 0, "log": 1, "power": 2}
+
+
+def envelope(img: np.ndarray) -> np.ndarray:
+    """|analytic signal| of every depth column (last axis) of a real image."""
+    x = np.ascontiguousarray(img, dtype=np.float64)
+    N = x.shape[-1]
+    out = np.empty_like(x)
+    lib().oracle_envelope(_ptr(x, ctypes.c_double), x.size // N, N, _ptr(out, ctypes.c_double))
+    return out
+
+
+def compress(env: np.ndarray, mode: str = "log", ref: float = 0.0, param: float = 60.0):
+    """Display compression of an envelope (see oracle_compress)."""
+    e = np.ascontiguousarray(env, dtype=np.float64)
+    out = np.empty_like(e)
+    lib().oracle_compress(_ptr(e, ctypes.c_double), e.size, COMPRESS[mode], float(ref),
+                          float(param), _ptr(out, ctypes.c_double))
+    return out

@@ -467,3 +467,84 @@ void oracle_das_iq_points(const oracle_geom *g, double fd, const double *e_re, c
     for (int64_t q = 0; q < n; ++q)
         das_point_iq(g, fd, e_re, e_im, vox[q], &out_re[q], &out_im[q]);
 }
+
+/* ------------------------------------------------------------------------- */
+/* Envelope and display compression (the stage after DAS)                     */
+/* ------------------------------------------------------------------------- */
+
+/* Envelope of an RF image along the depth axis through the analytic signal
+ * (the paper runs a Hilbert transform after beamforming), by the discrete
+ * Fourier definition, one depth column at a time:
+ *   X[k]   = sum_n x[n] exp(-j 2 pi k n / N)
+ *   Xa[k]  = h[k] X[k],  h = 1 at k = 0 and (N even) k = N/2, 2 for
+ *            0 < k < N/2, 0 for the negative frequencies
+ *   xa[n]  = (1/N) sum_k Xa[k] exp(+j 2 pi k n / N)
+ *   env[n] = |xa[n]|
+ * Reading: the transform is circular over the N depth samples of a column
+ * (an FFT of the column's own length, no padding).  img and env:
+ * [n_cols][N], depth fastest.  Plain O(N^2) sums in FP64. */
+void oracle_envelope(const double *img, int64_t n_cols, int N, double *env)
+{
+#pragma omp parallel
+    {
+        double *Xr = malloc(sizeof(double) * (size_t)N);
+        double *Xi = malloc(sizeof(double) * (size_t)N);
+#pragma omp for schedule(static)
+        for (int64_t col = 0; col < n_cols; ++col) {
+            const double *x = img + (size_t)col * N;
+            for (int k = 0; k < N; ++k) {
+                double ar = 0.0, ai = 0.0;
+                for (int n = 0; n < N; ++n) {
+                    double ph = -2.0 * M_PI * (double)(((long)k * n) % N) / N;
+                    ar += x[n] * cos(ph);
+                    ai += x[n] * sin(ph);
+                }
+                double h = (k == 0 || 2 * k == N) ? 1.0 : (2 * k < N ? 2.0 : 0.0);
+                Xr[k] = h * ar;
+                Xi[k] = h * ai;
+            }
+            for (int n = 0; n < N; ++n) {
+                double ar = 0.0, ai = 0.0;
+                for (int k = 0; k < N; ++k) {
+                    double ph = 2.0 * M_PI * (double)(((long)k * n) % N) / N;
+                    double c = cos(ph), s = sin(ph);
+                    ar += Xr[k] * c - Xi[k] * s;
+                    ai += Xr[k] * s + Xi[k] * c;
+                }
+                env[(size_t)col * N + n] = sqrt(ar * ar + ai * ai) / N;
+            }
+        }
+        free(Xr);
+        free(Xi);
+    }
+}
+
+/* Display compression of an envelope (the paper's live view shows a log scale
+ * with an adjustable dynamic range or a power scale with an adjustable
+ * threshold).  Readings:
+ *   mode 0 (none):  y = env
+ *   mode 1 (log):   y = max(20 log10(env / ref), -param)   (param = dynamic range, dB)
+ *   mode 2 (power): y = min(env / ref, 1)^param             (ref = threshold, param = exponent)
+ * ref <= 0 takes the maximum of env over the n values; an all-zero envelope
+ * then gives -param (log) or 0 (power). */
+void oracle_compress(const double *env, int64_t n, int mode, double ref, double param,
+                     double *out)
+{
+    if (ref <= 0.0) {
+        ref = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            if (env[i] > ref) ref = env[i];
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double v = env[i];
+        if (mode == 1) {
+            double db = (ref > 0.0 && v > 0.0) ? 20.0 * log10(v / ref) : -INFINITY;
+            out[i] = db > -param ? db : -param;
+        } else if (mode == 2) {
+            double r = ref > 0.0 ? v / ref : 0.0;
+            out[i] = pow(r < 1.0 ? r : 1.0, param);
+        } else {
+            out[i] = v;
+        }
+    }
+}

@@ -40,6 +40,9 @@ void oracle_demod(const int16_t *x, int n_traces, int S, const double *h_re, con
 void oracle_quantise_i16(const double *y, int64_t n, int16_t *q);
 void oracle_das_iq(const oracle_geom *g, double fd, const double *e_re, const double *e_im,
                    double *out_re, double *out_im);
+void oracle_envelope(const double *img, int64_t n_cols, int N, double *env);
+void oracle_compress(const double *env, int64_t n, int mode, double ref, double param,
+                     double *out);
 void oracle_das_iq_points(const oracle_geom *g, double fd, const double *e_re, const double *e_im,
                           const int64_t *vox, int64_t n, double *out_re, double *out_im);
 

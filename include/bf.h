@@ -276,6 +276,42 @@ int bf_demod_out_samples(bf_demod d, int32_t *n_out);
 /* Demodulate one frame on `stream` (asynchronous).  rf and iq must not overlap. */
 int bf_demodulate(bf_demod d, const int16_t *rf, void *iq, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Envelope and display compression: the stage after DAS (the paper applies a
+ * Hilbert transform to the beamformed image and shows it on a log scale with
+ * an adjustable dynamic range or on a power scale with an adjustable
+ * threshold).
+ *   RF image (iq = 0): env = |x_a|, x_a the analytic signal of each depth
+ *     column: X = DFT_N(x), X_a[k] = h[k] X[k] with h = 1 at DC and at N/2,
+ *     2 for 0 < k < N/2, 0 above; x_a = IDFT_N(X_a) (circular over the
+ *     column's N samples, no padding).
+ *   IQ image (iq = 1): env = |z|.
+ *   compress BF_COMPRESS_NONE:  y = env
+ *            BF_COMPRESS_LOG:   y = max(20 log10(env / ref), -param)  (param: dynamic range, dB)
+ *            BF_COMPRESS_POWER: y = min(env / ref, 1)^param          (ref: threshold, param: exponent)
+ *   ref > 0 is used as given; ref <= 0 takes the maximum envelope of the image
+ *   (computed on the device; an all-zero image gives -param / 0).
+ * img: device f32 [n_cols][n] (depth fastest: a [Ny][Nx][Nz] volume has
+ * n_cols = Ny*Nx, n = Nz) or, for iq = 1, complex f32 [n_cols][n][2];
+ * out: device f32 [n_cols][n] (must not overlap img).  FP32 arithmetic:
+ * radix-2 FFT in LDS for power-of-two n, a direct circular sum otherwise.
+ * A plan holds its tables and a one-word reduction buffer, so calls of one
+ * plan must not overlap on the device.
+ * ------------------------------------------------------------------------- */
+enum { BF_COMPRESS_NONE = 0, BF_COMPRESS_LOG = 1, BF_COMPRESS_POWER = 2 };
+
+typedef struct bf_env_s *bf_env;      /* opaque, owned by libbf */
+
+/* n_cols >= 1, n in 1..4096, iq 0 or 1.  Errors: SHAPE, UNSUPPORTED, TOO_LARGE,
+ * NO_DEVICE, HIP. */
+int bf_env_create(int64_t n_cols, int32_t n, int32_t iq, bf_env *out);
+/* Free an envelope plan (waits for the device first).  NULL is a no-op. */
+int bf_env_destroy(bf_env e);
+/* Envelope + compression on `stream` (asynchronous).  GEOMETRY if ref is not
+ * finite or, when compressing, param is not finite and > 0. */
+int bf_envelope(bf_env e, const float *img, float *out, int32_t compress, double ref,
+                double param, void *stream);
+
 /* Evaluates the library's Hann-window polynomial W at u^2 (host, for tests). */
 double bf_hann_poly(double u2);
 

@@ -18,11 +18,11 @@ import math
 
 import numpy as np
 
-from ._lib import (BfError, DECODE_ALGOS, DemodParams, ETYPES, INTERPS, IQ_TYPES, MODES, Params,
-                   PlanInfo, check, lib)
+from ._lib import (BfError, COMPRESS, DECODE_ALGOS, DemodParams, ETYPES, INTERPS, IQ_TYPES, MODES,
+                   Params, PlanInfo, check, lib)
 
-__all__ = ["BfError", "Plan", "BatchPlan", "Demod", "params_from_desc", "sharpness", "validate",
-           "hann_poly"]
+__all__ = ["BfError", "Plan", "BatchPlan", "Demod", "Envelope", "params_from_desc", "sharpness",
+           "validate", "hann_poly"]
 
 
 class _Marshalled:
@@ -253,6 +253,46 @@ class Demod:
         if out.dtype != dt or tuple(out.shape) != shape or not out.is_contiguous():
             raise ValueError(f"out must be a contiguous {dt} tensor of shape {shape}")
         check(lib().bf_demodulate(self._h, _ptr(rf), _ptr(out), _stream(stream)))
+        return out
+
+
+class Envelope:
+    """bf_envelope: |analytic signal| along depth (or |z| of an IQ image) with
+    optional log / power compression, for images whose last axis is depth."""
+
+    def __init__(self, shape, iq: bool = False):
+        shape = tuple(int(v) for v in shape)
+        self.shape, self.iq = shape, bool(iq)
+        self.n = shape[-1]
+        self.n_cols = int(np.prod(shape[:-1])) if len(shape) > 1 else 1
+        h = ctypes.c_void_p()
+        check(lib().bf_env_create(self.n_cols, self.n, 1 if iq else 0, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check(lib().bf_env_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __call__(self, img, compress: str = "none", ref: float = 0.0, param: float = 60.0,
+                 out=None, stream=None):
+        torch = _torch()
+        dt = torch.complex64 if self.iq else torch.float32
+        if img.dtype != dt or not img.is_cuda or not img.is_contiguous() or \
+                tuple(img.shape) != self.shape:
+            raise ValueError(f"img must be a contiguous {dt} CUDA tensor of shape {self.shape}")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float32, device=img.device)
+        if out.dtype != torch.float32 or tuple(out.shape) != self.shape or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 tensor of the image shape")
+        check(lib().bf_envelope(self._h, _ptr(img), _ptr(out), COMPRESS[compress], float(ref),
+                                float(param), _stream(stream)))
         return out
 
 

@@ -97,6 +97,9 @@ def lib():
         "bf_demod_destroy": ([vp], ctypes.c_int),
         "bf_demod_out_samples": ([vp, P(i32)], ctypes.c_int),
         "bf_demodulate": ([vp, vp, vp, vp], ctypes.c_int),
+        "bf_env_create": ([i64, i32, i32, P(vp)], ctypes.c_int),
+        "bf_env_destroy": ([vp], ctypes.c_int),
+        "bf_envelope": ([vp, vp, vp, i32, dbl, dbl, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -115,4 +118,6 @@ EXPORTED = ("bf_abi_version", "bf_last_error", "bf_validate", "bf_plan_create",
             "bf_plan_create_batch", "bf_plan_destroy", "bf_plan_get_info", "bf_autotune",
             "bf_set_tile", "bf_set_das_config", "bf_decode", "bf_das", "bf_das_adjoint", "bf_sharpness",
             "bf_batch_run", "bf_graph_launch", "bf_hann_poly", "bf_demod_create",
-            "bf_demod_destroy", "bf_demod_out_samples", "bf_demodulate")
+            "bf_demod_destroy", "bf_demod_out_samples", "bf_demodulate", "bf_env_create",
+            "bf_env_destroy", "bf_envelope")
+COMPRESS = {"none": 0, "log": 1, "power": 2}

@@ -1,0 +1,367 @@
+// bf_env.hip -- envelope detection and display compression of beamformed
+// images (the stage after DAS: the paper's Hilbert transform and its log /
+// power display scales).
+//
+// A real (RF) image is [n_cols][N] with depth fastest; the envelope of a
+// column is |x_a| with x_a its analytic signal along depth:
+//     X = DFT_N(x),  X_a[k] = h[k] X[k]  (h = 1 at DC and Nyquist, 2 for
+//     positive, 0 for negative frequencies),  x_a = IDFT_N(X_a).
+// One workgroup per column.  Power-of-two N: radix-2 FFT in LDS (forward
+// decimation-in-time from a bit-reversed load, spectrum weighting, inverse
+// decimation-in-frequency, read back in bit-reversed order), twiddles from a
+// host FP64 table staged in LDS.  Other N: Re x_a = x exactly, and Im x_a is the
+// circular convolution of x with q = Im IDFT(h) (host FP64), summed directly.
+// IQ images already are analytic: the envelope is |z|.
+//
+// Compression (ref > 0 is fused into the store; ref <= 0 uses the image
+// maximum: every workgroup writes the maximum of its envelope values to a
+// partial-max buffer, one workgroup reduces it in a fixed order, and a second
+// pass applies the compression -- no atomics, so repeated calls agree):
+//     log:   y = max(20 log10(env / ref), -param)
+//     power: y = min(env / ref, 1)^param
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "bf.h"
+#include "bf_common.h"
+#include "bf_plan.h"
+
+namespace bf {
+
+constexpr int ENV_MAX_N = 4096;
+
+struct EnvArgs {
+    const float *img;        // [n_cols][N] real, or [n_cols][N][2] complex (iq)
+    float *out;              // [n_cols][N]
+    const float2 *tw;        // FFT: [N/2] exp(-j 2 pi t / N)
+    const float *q;          // direct path: [N] Im IDFT(h)
+    float *part_max;         // [n_parts] per-workgroup maxima (ref <= 0)
+    float *img_max;          // reduced maximum (ref <= 0)
+    long n_cols;
+    int N, log2n;
+    int compress;
+    float ref, param;
+};
+
+__device__ inline float compress_value(float env, int mode, float ref, float param)
+{
+    if (mode == BF_COMPRESS_LOG) {
+        const float db = 20.f * log10f(env / ref);      // -inf for env = 0
+        return fmaxf(db, -param);
+    }
+    if (mode == BF_COMPRESS_POWER) return powf(fminf(env / ref, 1.f), param);
+    return env;
+}
+
+// Store one envelope value: compressed now (ref given), or raw with the
+// running maximum (compression pass follows).
+__device__ inline void store_env(const EnvArgs &a, long idx, float env, float &local_max)
+{
+    if (a.compress != BF_COMPRESS_NONE && a.ref > 0.f) {
+        a.out[idx] = compress_value(env, a.compress, a.ref, a.param);
+    } else {
+        a.out[idx] = env;
+        local_max = fmaxf(local_max, env);
+    }
+}
+
+// Maximum of the workgroup's envelope values to part_max[blockIdx.x]
+// (wavefront shuffles, then LDS across wavefronts; blockDim <= 256).
+__device__ inline void publish_max(const EnvArgs &a, float local_max)
+{
+    if (!(a.compress != BF_COMPRESS_NONE && a.ref <= 0.f)) return;
+    __shared__ float s_max[4];
+    for (int o = 32; o > 0; o >>= 1) local_max = fmaxf(local_max, __shfl_xor(local_max, o, 64));
+    if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = local_max;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = s_max[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, s_max[w]);
+        a.part_max[blockIdx.x] = m;
+    }
+}
+
+__device__ inline float2 cmul(float2 a, float2 b)
+{
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
+__device__ inline unsigned bitrev(unsigned v, int bits) { return __brev(v) >> (32 - bits); }
+
+// grid: n_cols workgroups of T threads; LDS: N float2 data + N/2 float2 twiddles
+__global__ __launch_bounds__(256) void env_fft_kernel(EnvArgs a)
+{
+    extern __shared__ float2 sm[];
+    float2 *d = sm;
+    float2 *tw = sm + a.N;
+    const int N = a.N, half_n = N >> 1, T = blockDim.x, t = threadIdx.x;
+    const long col = blockIdx.x;
+    const float *x = a.img + col * N;
+    for (int i = t; i < half_n; i += T) tw[i] = a.tw[i];
+    for (int n = t; n < N; n += T) d[bitrev(n, a.log2n)] = make_float2(x[n], 0.f);
+    __syncthreads();
+    // forward DIT: butterflies (i, i + h) with twiddle exp(-j 2 pi pos / len)
+    for (int len = 2, stride = half_n; len <= N; len <<= 1, stride >>= 1) {
+        const int h = len >> 1;
+        for (int b = t; b < half_n; b += T) {
+            const int pos = b & (h - 1);
+            const int i = ((b - pos) << 1) + pos;
+            const float2 u = d[i], v = cmul(d[i + h], tw[pos * stride]);
+            d[i] = make_float2(u.x + v.x, u.y + v.y);
+            d[i + h] = make_float2(u.x - v.x, u.y - v.y);
+        }
+        __syncthreads();
+    }
+    // analytic-signal weights: 1 at DC and Nyquist, 2 positive, 0 negative
+    for (int k = t; k < N; k += T) {
+        const float w = (k == 0 || k == half_n) ? 1.f : (k < half_n ? 2.f : 0.f);
+        d[k] = make_float2(d[k].x * w, d[k].y * w);
+    }
+    __syncthreads();
+    // inverse DIF: butterflies (i, i + h), (u + v, (u - v) exp(+j 2 pi pos / len))
+    for (int len = N, stride = 1; len >= 2; len >>= 1, stride <<= 1) {
+        const int h = len >> 1;
+        for (int b = t; b < half_n; b += T) {
+            const int pos = b & (h - 1);
+            const int i = ((b - pos) << 1) + pos;
+            const float2 u = d[i], v = d[i + h];
+            const float2 w = tw[pos * stride];
+            d[i] = make_float2(u.x + v.x, u.y + v.y);
+            d[i + h] = cmul(make_float2(u.x - v.x, u.y - v.y), make_float2(w.x, -w.y));
+        }
+        __syncthreads();
+    }
+    const float inv_n = 1.f / (float)N;
+    float local_max = 0.f;
+    for (int n = t; n < N; n += T) {
+        const float2 z = d[bitrev(n, a.log2n)];
+        store_env(a, col * N + n, sqrtf(z.x * z.x + z.y * z.y) * inv_n, local_max);
+    }
+    publish_max(a, local_max);
+}
+
+// Any N: y = Im x_a = sum_k q[k] x[(n - k) mod N]; env = sqrt(x^2 + y^2).
+// LDS holds the column twice (no modulo in the sum) and q.
+__global__ __launch_bounds__(256) void env_direct_kernel(EnvArgs a)
+{
+    extern __shared__ float sf[];
+    const int N = a.N, T = blockDim.x, t = threadIdx.x;
+    float *x2 = sf;            // [2N]: x2[i] = x[i mod N]
+    float *q = sf + 2 * N;     // [N]
+    const long col = blockIdx.x;
+    const float *x = a.img + col * N;
+    for (int i = t; i < N; i += T) {
+        const float v = x[i];
+        x2[i] = v;
+        x2[i + N] = v;
+        q[i] = a.q[i];
+    }
+    __syncthreads();
+    float local_max = 0.f;
+    for (int n = t; n < N; n += T) {
+        // x[(n - k) mod N] = x2[n - k + N] for 0 <= k < N
+        float y = 0.f;
+        for (int k = 0; k < N; ++k) y = fmaf(q[k], x2[n - k + N], y);
+        const float xv = x2[n];
+        store_env(a, col * N + n, sqrtf(fmaf(xv, xv, y * y)), local_max);
+    }
+    publish_max(a, local_max);
+}
+
+__global__ __launch_bounds__(256) void env_iq_kernel(EnvArgs a)
+{
+    const long total = a.n_cols * a.N;
+    float local_max = 0.f;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
+        const float2 z = reinterpret_cast<const float2 *>(a.img)[i];
+        store_env(a, i, sqrtf(fmaf(z.x, z.x, z.y * z.y)), local_max);
+    }
+    publish_max(a, local_max);
+}
+
+// One workgroup: img_max = max of part_max[0 .. n) (fixed order per thread,
+// then a tree over threads).
+__global__ __launch_bounds__(256) void env_reduce_kernel(const float *part_max, long n,
+                                                         float *img_max)
+{
+    __shared__ float s[256];
+    float m = 0.f;
+    for (long i = threadIdx.x; i < n; i += 256) m = fmaxf(m, part_max[i]);
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] = fmaxf(s[threadIdx.x], s[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *img_max = s[0];
+}
+
+__global__ __launch_bounds__(256) void env_compress_kernel(EnvArgs a)
+{
+    const long total = a.n_cols * a.N;
+    const float ref = *a.img_max;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
+        const float env = a.out[i];
+        float y;
+        if (ref > 0.f) {
+            y = compress_value(env, a.compress, ref, a.param);
+        } else {   // all-zero image
+            y = a.compress == BF_COMPRESS_LOG ? -a.param : 0.f;
+        }
+        a.out[i] = y;
+    }
+}
+
+}  // namespace bf
+
+using namespace bf;
+
+struct bf_env_s {
+    uint32_t magic = 0xBFE7E701u;
+    long n_cols = 0;
+    int N = 0, iq = 0, log2n = -1;
+    long n_parts = 0;
+    float2 *d_tw = nullptr;
+    float *d_q = nullptr;
+    float *d_part = nullptr;      // [n_parts] per-workgroup maxima, then the maximum
+    ~bf_env_s()
+    {
+        if (d_tw) (void)hipFree(d_tw);
+        if (d_q) (void)hipFree(d_q);
+        if (d_part) (void)hipFree(d_part);
+    }
+};
+
+static bool live(bf_env e) { return e && e->magic == 0xBFE7E701u; }
+
+extern "C" {
+
+int bf_env_create(int64_t n_cols, int32_t n, int32_t iq, bf_env *out)
+{
+    clear_err();
+    if (!out) return fail(BF_ERR_NULL, "out is NULL");
+    *out = nullptr;
+    if (n_cols < 1) return fail(BF_ERR_SHAPE, "n_cols=%lld < 1", (long long)n_cols);
+    if (n < 1 || n > ENV_MAX_N) return fail(BF_ERR_SHAPE, "n=%d not in [1,%d]", n, ENV_MAX_N);
+    if (iq != 0 && iq != 1) return fail(BF_ERR_UNSUPPORTED, "iq must be 0 or 1");
+    if (n_cols >= (int64_t(1) << 31) || n_cols * n * (iq ? 2 : 1) >= (int64_t(1) << 31))
+        return fail(BF_ERR_TOO_LARGE, "image exceeds 2^31 elements");
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+        (void)hipGetLastError();
+        return fail(BF_ERR_NO_DEVICE, "no HIP device available");
+    }
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return fail(BF_ERR_HIP, "device query failed");
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(BF_ERR_NO_DEVICE, "device %d is %s, libbf is built for gfx950", dev,
+                    prop.gcnArchName);
+    bf_env e = new bf_env_s();
+    e->n_cols = n_cols;
+    e->N = n;
+    e->iq = iq;
+    // workgroups of the envelope pass: one per column, or the grid-stride
+    // launch of the IQ path
+    e->n_parts = iq ? std::min<long>((n_cols * n + 255) / 256, 8192) : n_cols;
+    hipError_t err = hipMalloc(&e->d_part, (e->n_parts + 1) * sizeof(float));
+    if (err == hipSuccess && !iq) {
+        if ((n & (n - 1)) == 0 && n >= 2) {
+            int l = 0;
+            while ((1 << l) < n) ++l;
+            e->log2n = l;
+            std::vector<float2> tw(n / 2);
+            for (int k = 0; k < n / 2; ++k) {
+                const double ph = -2.0 * M_PI * k / n;
+                tw[k] = make_float2((float)cos(ph), (float)sin(ph));
+            }
+            err = hipMalloc(&e->d_tw, tw.size() * sizeof(float2));
+            if (err == hipSuccess)
+                err = hipMemcpy(e->d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice);
+        } else {
+            // q[k] = Im IDFT(h)[k] = (1/N) sum_k' h[k'] sin(2 pi k' k / N)
+            std::vector<float> q(n);
+            for (int k = 0; k < n; ++k) {
+                double s = 0.0;
+                // weight 2 for 0 < k' < N/2; DC and Nyquist add sin(0) = sin(pi k) = 0
+                for (int kk = 1; 2 * kk < n; ++kk)
+                    s += 2.0 * sin(2.0 * M_PI * (double)((long)kk * k % n) / n);
+                q[k] = (float)(s / n);
+            }
+            err = hipMalloc(&e->d_q, n * sizeof(float));
+            if (err == hipSuccess)
+                err = hipMemcpy(e->d_q, q.data(), n * sizeof(float), hipMemcpyHostToDevice);
+        }
+    }
+    if (err != hipSuccess) {
+        delete e;
+        return hip_fail(err, "envelope tables");
+    }
+    *out = e;
+    return BF_OK;
+}
+
+int bf_env_destroy(bf_env e)
+{
+    clear_err();
+    if (!e) return BF_OK;
+    if (!live(e)) return fail(BF_ERR_STATE, "not a live envelope plan");
+    (void)hipDeviceSynchronize();
+    e->magic = 0;
+    delete e;
+    return BF_OK;
+}
+
+int bf_envelope(bf_env e, const float *img, float *out, int32_t compress, double ref,
+                double param, void *stream)
+{
+    clear_err();
+    if (!e) return fail(BF_ERR_NULL, "envelope plan is NULL");
+    if (!live(e)) return fail(BF_ERR_STATE, "not a live envelope plan");
+    if (!img || !out) return fail(BF_ERR_NULL, "img and out must be non-NULL");
+    if (compress < BF_COMPRESS_NONE || compress > BF_COMPRESS_POWER)
+        return fail(BF_ERR_UNSUPPORTED, "unknown compression %d", compress);
+    if (!isfinite(ref)) return fail(BF_ERR_GEOMETRY, "ref must be finite");
+    if (compress != BF_COMPRESS_NONE && !(isfinite(param) && param > 0.0))
+        return fail(BF_ERR_GEOMETRY, "param must be finite and > 0");
+    EnvArgs a;
+    a.img = img;
+    a.out = out;
+    a.tw = e->d_tw;
+    a.q = e->d_q;
+    a.part_max = e->d_part;
+    a.img_max = e->d_part + e->n_parts;
+    a.n_cols = e->n_cols;
+    a.N = e->N;
+    a.log2n = e->log2n;
+    a.compress = compress;
+    a.ref = (float)ref;
+    a.param = (float)param;
+    hipStream_t s = (hipStream_t)stream;
+    const bool two_pass = compress != BF_COMPRESS_NONE && ref <= 0.0;
+    const long total = e->n_cols * e->N;
+    const unsigned eblocks = (unsigned)std::min<long>((total + 255) / 256, 8192);
+    if (e->iq) {
+        hipLaunchKernelGGL(env_iq_kernel, dim3(eblocks), dim3(256), 0, s, a);
+    } else if (e->log2n > 0) {
+        const int T = std::min(256, std::max(64, e->N / 2));
+        hipLaunchKernelGGL(env_fft_kernel, dim3((unsigned)e->n_cols), dim3(T),
+                           (size_t)e->N * 8 + (size_t)(e->N / 2) * 8, s, a);
+    } else {
+        hipLaunchKernelGGL(env_direct_kernel, dim3((unsigned)e->n_cols), dim3(256),
+                           (size_t)3 * e->N * sizeof(float), s, a);
+    }
+    if (two_pass) {
+        hipLaunchKernelGGL(env_reduce_kernel, dim3(1), dim3(256), 0, s, e->d_part, e->n_parts,
+                           e->d_part + e->n_parts);
+        hipLaunchKernelGGL(env_compress_kernel, dim3(eblocks), dim3(256), 0, s, a);
+    }
+    hipError_t err = hipGetLastError();
+    return err == hipSuccess ? BF_OK : hip_fail(err, "envelope launch");
+}
+
+}  // extern "C"

@@ -213,3 +213,19 @@ def test_demod_null_arguments_and_no_device():
     import torch
     if not torch.cuda.is_available():
         assert _demod_status() == -8                     # valid, but no gfx950 here
+
+
+def test_envelope_validation_on_host():
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.bf_env_create(4, 16, 0, None) == -1
+    assert L.bf_env_create(0, 16, 0, ctypes.byref(h)) == -2
+    assert L.bf_env_create(4, 0, 0, ctypes.byref(h)) == -2
+    assert L.bf_env_create(4, 4097, 0, ctypes.byref(h)) == -2
+    assert L.bf_env_create(4, 16, 2, ctypes.byref(h)) == -5
+    assert L.bf_env_create(1 << 20, 4096, 0, ctypes.byref(h)) == -6
+    assert L.bf_env_destroy(None) == 0
+    assert L.bf_envelope(None, None, None, 0, 0.0, 1.0, None) == -1
+    import torch
+    if not torch.cuda.is_available():
+        assert L.bf_env_create(4, 16, 0, ctypes.byref(h)) == -8

@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-MODES = {"forces": 0, "hercules": 1}
+MODES = {"forces": 0, "hercules": 1, "tpw": 2, "vls": 3}
 INTERPS = {"nearest": 0, "linear": 1, "cubic": 2}
 
 
@@ -48,6 +48,8 @@ class _Geom(ctypes.Structure):
         ("fs", ctypes.c_double), ("c", ctypes.c_double), ("t0", ctypes.c_double),
         ("f_number", ctypes.c_double), ("interp", ctypes.c_int),
         ("dims", ctypes.c_int * 3), ("gmin", ctypes.c_double * 3), ("gmax", ctypes.c_double * 3),
+        ("n_elem", ctypes.c_int * 2), ("focal_depth", ctypes.c_double),
+        ("tx_angles", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -141,6 +143,11 @@ class Geometry:
         g.dims[:] = [int(v) for v in desc["dims"]]
         g.gmin[:] = [float(v) for v in desc["gmin"]]
         g.gmax[:] = [float(v) for v in desc["gmax"]]
+        g.n_elem[:] = [int(v) for v in desc["n_elem"]]
+        g.focal_depth = float(desc.get("focal_depth", np.inf))
+        self._ang = np.ascontiguousarray(desc.get("tx_angles", np.zeros(g.n_tx)), dtype=np.float64)
+        assert self._ang.shape == (g.n_tx,)
+        g.tx_angles = _ptr(self._ang, ctypes.c_double)
         self.g = g
         self.n_vox = int(np.prod(desc["dims"]))
         self.shape = (int(desc["dims"][1]), int(desc["dims"][0]), int(desc["dims"][2]))

@@ -172,6 +172,9 @@ static double chan_coord(const oracle_geom *g, int j)
     return g->mode == ORACLE_FORCES ? g->channel_map[j] * g->pitch[0]
                                     : g->channel_map[j] * g->pitch[1];
 }
+/* Centre of the element grid in the array frame. */
+static double centre_x(const oracle_geom *g) { return 0.5 * (g->n_elem[0] - 1) * g->pitch[0]; }
+static double centre_y(const oracle_geom *g) { return 0.5 * (g->n_elem[1] - 1) * g->pitch[1]; }
 
 /* Round-trip time of flight and receive apodization of one (point, i, j).
  * FORCES (Eq. 1 with the decoded STA dataset): the transmit is a cylindrical
@@ -181,7 +184,8 @@ static double chan_coord(const oracle_geom *g, int j)
  *   point receiver at (x_i, y_j, 0): tof = (z + |p - (x_i, y_j, 0)|) / c.
  * Apodization (Eqs. 2-3), receive only (transmit apodization is 1 for
  *   unfocused transmits):  a = W(F# * rho / z), rho = lateral distance from
- *   the receiver (|x - x_j| for FORCES, radial for HERCULES).
+ *   the receiver (|x - x_j| for FORCES, radial for HERCULES, |y - y_j| for the
+ *   row receivers of TPW and VLS).
  * Reading: points with z <= 0 (on or behind the array) get a = 0; F# = 0
  *   disables apodization (a = 1). */
 static void tof_apod(const oracle_geom *g, const double p[3], int i, int j,
@@ -195,11 +199,39 @@ static void tof_apod(const oracle_geom *g, const double p[3], int i, int j,
         double dr = sqrt((x - xr) * (x - xr) + z * z);
         *tof = (dt + dr) / g->c;
         rho = fabs(x - xr);
-    } else {
+    } else if (g->mode == ORACLE_HERCULES) {
         double xe = elem_x(g, i), ye = chan_coord(g, j);
         double rho2 = (x - xe) * (x - xe) + (y - ye) * (y - ye);
-        *tof = (z + sqrt(rho2 + z * z)) / g->c;
+        /* transmit: plane wave (z), or a diverging wave from the virtual point
+         * source v = (centre, focal_depth < 0) that crosses the array centre at
+         * t = 0: |p - v| - |focal_depth| */
+        double tx = z;
+        if (!isinf(g->focal_depth)) {
+            double dx = x - centre_x(g), dy = y - centre_y(g), dz = z - g->focal_depth;
+            tx = sqrt(dx * dx + dy * dy + dz * dz) + g->focal_depth;
+        }
+        *tof = (tx + sqrt(rho2 + z * z)) / g->c;
         rho = sqrt(rho2);
+    } else {
+        /* Row-column volumes: columns transmit, rows (line elements along x at
+         * y_j) receive a cylindrical wave in the y-z plane.
+         * TPW: plane wave tilted by theta_i in the x-z plane, crossing the
+         *      array centre at t = 0: (x - x_c) sin(theta) + z cos(theta).
+         * VLS: cylindrical wave through the virtual line source (x_i, z_f),
+         *      zero delay at the element: z_f + sgn(z - z_f) |(x, z) - (x_i, z_f)|
+         *      (z_f > 0 focused, z_f < 0 diverging; sgn(0) = +1). */
+        double ye = chan_coord(g, j);
+        double tx;
+        if (g->mode == ORACLE_TPW) {
+            double th = g->tx_angles[i];
+            tx = (x - centre_x(g)) * sin(th) + z * cos(th);
+        } else {
+            double xi = elem_x(g, i), zf = g->focal_depth;
+            double d = sqrt((x - xi) * (x - xi) + (z - zf) * (z - zf));
+            tx = zf + (z - zf >= 0.0 ? d : -d);
+        }
+        *tof = (tx + sqrt((y - ye) * (y - ye) + z * z)) / g->c;
+        rho = fabs(y - ye);
     }
     if (z <= 0.0) { *apod = 0.0; return; }
     *apod = (g->f_number == 0.0) ? 1.0 : oracle_hann(g->f_number * rho / z);

@@ -6,7 +6,7 @@
 #define ORACLE_H
 #include <stdint.h>
 
-enum { ORACLE_FORCES = 0, ORACLE_HERCULES = 1 };
+enum { ORACLE_FORCES = 0, ORACLE_HERCULES = 1, ORACLE_TPW = 2, ORACLE_VLS = 3 };
 enum { ORACLE_NEAREST = 0, ORACLE_LINEAR = 1, ORACLE_CUBIC = 2 };
 
 typedef struct {
@@ -21,6 +21,11 @@ typedef struct {
     int interp;                /* ORACLE_NEAREST / ORACLE_LINEAR / ORACLE_CUBIC    */
     int dims[3];               /* Nx, Ny, Nz                                       */
     double gmin[3], gmax[3];   /* inclusive region bounds, global frame, metres    */
+    int n_elem[2];             /* element columns, rows (array centre for TPW and  */
+                               /* the diverging HERCULES source)                   */
+    double focal_depth;        /* HERCULES: +inf plane wave, < 0 diverging source; */
+                               /* VLS: depth of the virtual line sources (!= 0)    */
+    const double *tx_angles;   /* TPW: n_tx tilt angles, radians                   */
 } oracle_geom;
 
 int oracle_sylvester(int n, int8_t *H);

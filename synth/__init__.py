@@ -50,6 +50,7 @@ def _load():
         D = ctypes.POINTER(ctypes.c_double)
         L.synth_echoes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                    D, D, ctypes.c_int, D, D, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_double, D,
                                    ctypes.c_double, ctypes.c_double, D]
         _lib = L
     return _lib
@@ -78,7 +79,7 @@ def to_array_frame(desc: dict, pts_global: np.ndarray) -> np.ndarray:
 def element_responses(desc: dict, pts_global: np.ndarray, amps: np.ndarray,
                       c: float | None = None) -> np.ndarray:
     """Simulated (unencoded) element responses, float64 (n_tx, n_ch, S)."""
-    mode = {"forces": 0, "hercules": 1}[desc["mode"]]
+    mode = {"forces": 0, "hercules": 1, "tpw": 2, "vls": 3}[desc["mode"]]
     n_tx, n_ch, S = int(desc["n_tx"]), int(desc["n_ch"]), int(desc["n_samples"])
     px, py = (float(v) for v in desc["pitch"])
     tx_x = np.ascontiguousarray(np.asarray(desc["tx_elements"], dtype=np.float64) * px)
@@ -87,9 +88,13 @@ def element_responses(desc: dict, pts_global: np.ndarray, amps: np.ndarray,
     sp = np.ascontiguousarray(to_array_frame(desc, pts_global))
     amps = np.ascontiguousarray(amps, dtype=np.float64)
     e = np.empty((n_tx, n_ch, S), dtype=np.float64)
+    ang = np.ascontiguousarray(desc.get("tx_angles", np.zeros(n_tx)), dtype=np.float64)
+    xc = 0.5 * (desc["n_elem"][0] - 1) * px
+    yc = 0.5 * (desc["n_elem"][1] - 1) * py
     _load().synth_echoes(mode, n_tx, n_ch, S, _dptr(tx_x), _dptr(rx_c), sp.shape[0], _dptr(sp),
                          _dptr(amps), float(desc["fs"]), float(desc["fc"]),
-                         float(desc["c"] if c is None else c), float(desc["t0"]), _dptr(e))
+                         float(desc["c"] if c is None else c), float(desc["t0"]),
+                         float(desc.get("focal_depth", np.inf)), _dptr(ang), xc, yc, _dptr(e))
     return e
 
 
@@ -112,11 +117,14 @@ def quantise(r: np.ndarray, rng: np.random.Generator, noise: float = 0.01,
 
 
 def acquire(desc: dict, pts_global, amps, rng: np.random.Generator, H=None,
-            noise: float = 0.01, c: float | None = None) -> np.ndarray:
-    """Scene -> int16 encoded RF (n_tx, n_ch, S)."""
+            noise: float = 0.01, c: float | None = None, encoded: bool = True) -> np.ndarray:
+    """Scene -> int16 RF (n_tx, n_ch, S), Hadamard-encoded across transmits
+    unless ``encoded`` is False (conventional TPW / VLS acquisitions)."""
+    e = element_responses(desc, pts_global, amps, c=c)
+    if not encoded:
+        return quantise(e, rng, noise=noise)
     if H is None:
         H = hadamard_sylvester(int(desc["n_tx"]))
-    e = element_responses(desc, pts_global, amps, c=c)
     return quantise(encode(H, e), rng, noise=noise)
 
 

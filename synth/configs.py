@@ -1,7 +1,9 @@
 """Workload descriptions and seeded scenes for the five benchmark workloads.
 
 A description is a dict of the paper's beamforming inputs (Sec. VI-B):
-  mode              "forces" (2D B-scan) or "hercules" (3D volume)
+  mode              "forces" (2D B-scan), "hercules" (3D volume), "tpw" or "vls"
+                    (row-column volumes: columns transmit tilted plane waves /
+                    virtual line sources, rows receive)
   n_tx, n_ch, n_samples
   n_elem            (columns, rows) of the TOBE array
   pitch             (x, y) element pitch, metres
@@ -13,6 +15,9 @@ A description is a dict of the paper's beamforming inputs (Sec. VI-B):
   f_number          receive F# of the Hann apodization (0 = none)
   interp            "nearest" | "linear" | "cubic"
   dims, gmin, gmax  output grid: (Nx, Ny, Nz) points, inclusive bounds (global frame)
+  focal_depth       optional: HERCULES diverging source depth (< 0; default +inf =
+                    plane wave), VLS virtual line depth
+  tx_angles         optional: TPW tilt angle of each transmit, radians
 """
 from __future__ import annotations
 
@@ -31,7 +36,7 @@ def centered_xdc(n_elem, pitch):
 
 def describe(mode, n_elem, pitch, n_tx, n_ch, n_samples, fs, fc, dims, gmin, gmax,
              c=1540.0, t0=0.0, f_number=1.0, interp="cubic", tx_elements=None,
-             channel_map=None, xdc=None):
+             channel_map=None, xdc=None, focal_depth=None, tx_angles=None):
     d = dict(mode=mode, n_tx=int(n_tx), n_ch=int(n_ch), n_samples=int(n_samples),
              n_elem=tuple(int(v) for v in n_elem), pitch=tuple(float(v) for v in pitch),
              fs=float(fs), fc=float(fc), c=float(c), t0=float(t0), f_number=float(f_number),
@@ -42,6 +47,10 @@ def describe(mode, n_elem, pitch, n_tx, n_ch, n_samples, fs, fc, dims, gmin, gma
     d["channel_map"] = (np.arange(n_ch, dtype=np.int32) if channel_map is None
                         else np.asarray(channel_map, dtype=np.int32))
     d["xdc"] = centered_xdc(n_elem, pitch) if xdc is None else np.asarray(xdc, dtype=np.float64)
+    if focal_depth is not None:
+        d["focal_depth"] = float(focal_depth)
+    if tx_angles is not None:
+        d["tx_angles"] = np.asarray(tx_angles, dtype=np.float64)
     return d
 
 

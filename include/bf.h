@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define BF_ABI_VERSION 2
+#define BF_ABI_VERSION 3
 
 typedef enum {
     BF_OK = 0,
@@ -61,8 +61,11 @@ typedef enum {
 } bf_status;
 
 /* Acquisition method (Table I).  uFORCES / uHERCULES are the same modes with a
- * sparse transmit subset in tx_elements. */
-enum { BF_FORCES_2D = 0, BF_HERCULES_3D = 1 };
+ * sparse transmit subset in tx_elements.  TPW and VLS are the conventional
+ * row-column volume methods (Sec. II capabilities): columns transmit tilted
+ * plane waves (TPW) or waves through virtual line sources (VLS), rows receive
+ * (a row is a line element along x at y_j, receiving in the y-z plane). */
+enum { BF_FORCES_2D = 0, BF_HERCULES_3D = 1, BF_TPW_3D = 2, BF_VLS_3D = 3 };
 /* Fractional-delay interpolation (Sec. IV-B; Table I). */
 enum { BF_INTERP_NEAREST = 0, BF_INTERP_LINEAR = 1, BF_INTERP_CUBIC = 2 };
 /* Element type of decoded data (written by bf_decode, read by bf_das). */
@@ -88,19 +91,27 @@ typedef struct {
      * by ((n_elem[0]-1)/2 pitch[0], (n_elem[1]-1)/2 pitch[1], 0). */
     double  xdc_transform[16];
     /* host, n_tx*n_tx, row-major: hadamard[k*n_tx+i] = polarity (+-1) of element
-     * i in transmit k.  Any matrix with H H^T = N I is accepted (checked exactly). */
+     * i in transmit k.  Any matrix with H H^T = N I is accepted (checked exactly).
+     * NULL: the acquisition is not encoded and decoding is the identity. */
     const int8_t  *hadamard;
     /* host, n_tx: element column behind decoded transmit i; NULL = 0..n_tx-1.
      * A sparse subset gives uFORCES / uHERCULES. */
     const int32_t *tx_elements;
-    /* host, n_ch: element column (FORCES) or row (HERCULES) of data channel j;
-     * NULL = 0..n_ch-1. */
+    /* host, n_ch: element column (FORCES) or row (HERCULES, TPW, VLS) of data
+     * channel j; NULL = 0..n_ch-1. */
     const int32_t *channel_map;
     double  fs;                /* sampling rate, Hz, > 0                                */
     double  fc;                /* centre frequency, Hz (informational for RF data)      */
     double  c;                 /* default sound speed, m/s, > 0                         */
     double  t0;                /* time of sample 0 relative to the transmit, s          */
-    double  focal_depth;       /* HERCULES transmit focus; only +INFINITY (plane wave)  */
+    /* Transmit focus, the paper's focal point that encodes the emitted wave:
+     * HERCULES: +INFINITY = plane wave; finite < 0 = diverging wave from the
+     *   virtual point source (array centre, depth focal_depth), zero delay at
+     *   the array centre: tx = |p - v| - |focal_depth|.
+     * VLS: depth z_f of the virtual line sources (x of column tx_elements[i],
+     *   parallel to y), finite: tx = z_f + sgn(z - z_f) |(x - x_i, z - z_f)|.
+     * Ignored by FORCES and TPW. */
+    double  focal_depth;
     double  f_number;          /* receive F# of the Hann apodization (Eq. 2); 0 = none  */
     int32_t interp;            /* BF_INTERP_*                                           */
     int32_t e_type;            /* BF_E_*                                                */
@@ -117,6 +128,10 @@ typedef struct {
      * bf_das, bf_set_* and bf_autotune; bf_das_adjoint and the batched entry
      * points return BF_ERR_UNSUPPORTED. */
     int32_t iq;
+    /* TPW only: host, n_tx tilt angles in radians (|angle| < pi/2) of the plane
+     * wave of each transmit in the x-z plane, zero delay at the array centre:
+     * tx = (x - x_c) sin(angle) + z cos(angle).  Ignored otherwise. */
+    const double *tx_angles;
 } bf_params;
 
 typedef struct bf_plan_s *bf_plan;   /* opaque, owned by libbf */
@@ -196,7 +211,10 @@ int bf_decode(bf_plan plan, const int16_t *rf, void *e, void *stream);
  *   out[p] = sum_i sum_j a(p,i,j) * interp(e[i][j], (tof_ij(p) - t0) * fs)
  * FORCES:   tof = (|p - col(tx_i)|_xz + |p - col(ch_j)|_xz) / c,
  *           a = W(F# |x - x_j| / z)
- * HERCULES: tof = (z + |p - (x_i, y_j, 0)|) / c,  a = W(F# rho / z), rho radial
+ * HERCULES: tof = (tx(p) + |p - (x_i, y_j, 0)|) / c,  a = W(F# rho / z), rho radial,
+ *           tx = z (plane) or |p - v| - f (diverging, see focal_depth)
+ * TPW, VLS: tof = (tx_i(p) + |(y - y_j, z)|) / c,  a = W(F# |y - y_j| / z),
+ *           tx_i per tx_angles / focal_depth; these modes run the gather kernel
  * W is the Hann window (Eq. 3); points with z <= 0 give 0.  Samples outside
  * [0, n_samples) read as 0.  e: device, type params.e_type; out: device f32
  * [Ny][Nx][Nz], overwritten.  c: sound speed for this call (m/s, finite, > 0;

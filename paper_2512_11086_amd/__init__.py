@@ -54,6 +54,9 @@ class _Marshalled:
         p.out_min[:] = [float(v) for v in desc["gmin"]]
         p.out_max[:] = [float(v) for v in desc["gmax"]]
         p.iq = 1 if desc.get("iq", False) else 0
+        self.ang = (None if desc.get("tx_angles") is None
+                    else np.ascontiguousarray(desc["tx_angles"], dtype=np.float64))
+        p.tx_angles = self.ang.ctypes.data_as(P(ctypes.c_double)) if self.ang is not None else None
         self.p = p
 
 

@@ -15,7 +15,7 @@ BF_OK = 0
 STATUS = {0: "BF_OK", -1: "BF_ERR_NULL", -2: "BF_ERR_SHAPE", -3: "BF_ERR_NOT_HADAMARD",
           -4: "BF_ERR_GEOMETRY", -5: "BF_ERR_UNSUPPORTED", -6: "BF_ERR_TOO_LARGE",
           -7: "BF_ERR_HIP", -8: "BF_ERR_NO_DEVICE", -9: "BF_ERR_STATE"}
-MODES = {"forces": 0, "hercules": 1}
+MODES = {"forces": 0, "hercules": 1, "tpw": 2, "vls": 3}
 INTERPS = {"nearest": 0, "linear": 1, "cubic": 2}
 ETYPES = {"f32": 0, "bf16": 1, "i32": 2}
 DECODE_ALGOS = {"mfma": 0, "fma": 1}
@@ -40,6 +40,7 @@ class Params(ctypes.Structure):
         ("interp", ctypes.c_int32), ("e_type", ctypes.c_int32), ("decode_algo", ctypes.c_int32),
         ("out_dims", ctypes.c_int32 * 3), ("out_min", ctypes.c_double * 3),
         ("out_max", ctypes.c_double * 3), ("iq", ctypes.c_int32),
+        ("tx_angles", ctypes.POINTER(ctypes.c_double)),
     ]
 
 

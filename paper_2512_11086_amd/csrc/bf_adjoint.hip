@@ -71,10 +71,12 @@ __device__ inline float adjoint_point(const DasArgs &a, const Lane &L, float G)
     const float kc = (float)(a.k / a.c);     // d/dc of (path * fs / c) = -path * k / c
     const bool live = L.active && (GC || G != 0.f);
     float acc = 0.f;
+    const float xr = rx_coord<MODE>(L.x, L.y);
     for (int j = 0; j < a.n_ch; ++j) {
         const float cj = a.rx_c[j];
-        if constexpr (MODE == 0) {
-            const float dxr = L.x - cj;
+        if constexpr (MODE != MODE_HERCULES) {
+            // separable modes: transmit path z + Et, receive path z + Er
+            const float dxr = xr - cj;
             const float r2 = dxr * dxr;
             const bool act = live && r2 < L.thr;
             if (!__any(act)) continue;
@@ -83,8 +85,7 @@ __device__ inline float adjoint_point(const DasArgs &a, const Lane &L, float G)
             const float aj = act ? hann_u2(r2 * L.wsc) : 0.f;
             for (int i = 0; i < a.n_tx; ++i) {
                 if (act) {
-                    const float dxt = L.x - a.tx_x[i];
-                    const float Et = excess(dxt * dxt, L.z, L.z2);
+                    const float Et = tx_excess<MODE>(a, L.x, L.z, L.z2, i);
                     const float s = fmaf(Et, kf, Rj);
                     const long trace = (long)i * a.n_ch + j;
                     const float d = adjoint_term<ET, IP, GE, GC>(
@@ -110,7 +111,8 @@ __device__ inline float adjoint_point(const DasArgs &a, const Lane &L, float G)
                     const float d = adjoint_term<ET, IP, GE, GC>(
                         trace_ptr<ET>(a.e, trace, a.S), a.grad_e + trace * a.S, a.S, L.nB, s,
                         G * w, w);
-                    if constexpr (GC) acc = fmaf(d, -(2.f * L.z + E) * kc, acc);
+                    // path = transmit path of the point (plane or diverging) + z + E
+                    if constexpr (GC) acc = fmaf(d, -(L.ptx + L.z + E) * kc, acc);
                 }
             }
         }
@@ -217,7 +219,13 @@ hipError_t launch_das_adjoint(const DasArgs &a, int mode, int et, int ip, float 
         err = launch_fill(a.grad_e, (long)a.n_tx * a.n_ch * a.S, 0.f, s);
         if (err != hipSuccess) return err;
     }
-    err = mode == 0 ? launch_adj1<0>(a, et, ip, ge, gc, s) : launch_adj1<1>(a, et, ip, ge, gc, s);
+    switch (mode) {
+        case MODE_FORCES: err = launch_adj1<MODE_FORCES>(a, et, ip, ge, gc, s); break;
+        case MODE_HERCULES: err = launch_adj1<MODE_HERCULES>(a, et, ip, ge, gc, s); break;
+        case MODE_TPW: err = launch_adj1<MODE_TPW>(a, et, ip, ge, gc, s); break;
+        case MODE_VLS: err = launch_adj1<MODE_VLS>(a, et, ip, ge, gc, s); break;
+        default: return hipErrorInvalidValue;
+    }
     if (err != hipSuccess || !gc) return err;
     hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, s, a.partial,
                        (a.n_waves + 3) / 4, grad_c);

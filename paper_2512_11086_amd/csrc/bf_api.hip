@@ -49,7 +49,7 @@ static bool is_fin(double v) { return isfinite(v) != 0; }
 int validate_params(const bf_params *p)
 {
     if (!p) return fail(BF_ERR_NULL, "params is NULL");
-    if (p->mode != BF_FORCES_2D && p->mode != BF_HERCULES_3D)
+    if (p->mode < BF_FORCES_2D || p->mode > BF_VLS_3D)
         return fail(BF_ERR_UNSUPPORTED, "unknown mode %d", p->mode);
     if (p->interp < BF_INTERP_NEAREST || p->interp > BF_INTERP_CUBIC)
         return fail(BF_ERR_UNSUPPORTED, "unknown interpolation %d", p->interp);
@@ -92,9 +92,18 @@ int validate_params(const bf_params *p)
     for (int a = 0; a < 3; ++a)
         if (!is_fin(p->out_min[a]) || !is_fin(p->out_max[a]))
             return fail(BF_ERR_GEOMETRY, "output region bounds must be finite");
-    if (p->mode == BF_HERCULES_3D && !(isinf(p->focal_depth) && p->focal_depth > 0))
-        return fail(BF_ERR_UNSUPPORTED, "HERCULES supports only a plane-wave transmit "
-                                        "(focal_depth = +inf)");
+    if (p->mode == BF_HERCULES_3D && !((isinf(p->focal_depth) && p->focal_depth > 0) ||
+                                       (is_fin(p->focal_depth) && p->focal_depth < 0)))
+        return fail(BF_ERR_UNSUPPORTED, "HERCULES transmits a plane wave (focal_depth = +inf) "
+                                        "or a diverging wave (finite focal_depth < 0)");
+    if (p->mode == BF_VLS_3D && !is_fin(p->focal_depth))
+        return fail(BF_ERR_GEOMETRY, "VLS needs a finite focal_depth (virtual line depth)");
+    if (p->mode == BF_TPW_3D) {
+        if (!p->tx_angles) return fail(BF_ERR_NULL, "TPW needs tx_angles");
+        for (int i = 0; i < p->n_tx; ++i)
+            if (!is_fin(p->tx_angles[i]) || fabs(p->tx_angles[i]) >= 0.5 * M_PI)
+                return fail(BF_ERR_GEOMETRY, "tx_angles[%d] must be finite, |angle| < pi/2", i);
+    }
     if (p->tx_elements)
         for (int i = 0; i < p->n_tx; ++i)
             if (p->tx_elements[i] < 0 || p->tx_elements[i] >= p->n_elem[0])
@@ -106,7 +115,7 @@ int validate_params(const bf_params *p)
             if (p->channel_map[j] < 0 || p->channel_map[j] >= nrx)
                 return fail(BF_ERR_SHAPE, "channel_map[%d]=%d outside [0,%d)", j,
                             p->channel_map[j], nrx);
-    if (!p->hadamard) return fail(BF_ERR_NULL, "hadamard is NULL");
+    if (!p->hadamard) return BF_OK;        // unencoded acquisition: identity decode
     const int n = p->n_tx;
     const int8_t *H = p->hadamard;
     for (int q = 0; q < n * n; ++q)
@@ -163,7 +172,19 @@ int Frame::init(const bf_params &src)
 {
     p = src;
     const int n = p.n_tx;
-    H.assign(p.hadamard, p.hadamard + (size_t)n * n);
+    if (p.hadamard) {
+        H.assign(p.hadamard, p.hadamard + (size_t)n * n);
+    } else {   // unencoded: decoding is the identity (exact copy to the e type)
+        H.assign((size_t)n * n, 0);
+        for (int i = 0; i < n; ++i) H[(size_t)i * n + i] = 1;
+    }
+    std::vector<float2> tx_sc;
+    if (p.mode == BF_TPW_3D)
+        for (int i = 0; i < n; ++i) {
+            const double th = p.tx_angles[i], sh = sin(0.5 * th);
+            tx_sc.push_back(make_float2((float)sin(th), (float)(-2.0 * sh * sh)));   // cos - 1
+        }
+    p.tx_angles = nullptr;
     tx.resize(n);
     ch.resize(p.n_ch);
     for (int i = 0; i < n; ++i) tx[i] = p.tx_elements ? p.tx_elements[i] : i;
@@ -212,11 +233,17 @@ int Frame::init(const bf_params &src)
     // wavefront tiles; 3D = LDS windows, flat 8x8x1 tiles in a 2x2x3 block
     // (12 wavefronts: two such workgroups fill a CU at the kernel's register
     // count).
-    if (p.mode == BF_FORCES_2D && grid.ny == 1) {
-        set_tile(4, 0, 2);
+    if (p.mode == BF_FORCES_2D && (grid.ny == 1 || grid.nx == 1)) {
+        // a plane: 16 x 4 points per wavefront along its lateral axis and depth
+        if (grid.ny == 1) set_tile(4, 0, 2); else set_tile(0, 4, 2);
         bw[0] = 2; bw[1] = 1; bw[2] = 2;
         nb = 4;
         variant = BF_DAS_GATHER;   // 2D windows are long for the LDS staging limit
+    } else if (p.mode == BF_TPW_3D || p.mode == BF_VLS_3D) {
+        set_tile(3, 3, 0);         // gather kernel (separable transmit / receive paths)
+        bw[0] = 2; bw[1] = 2; bw[2] = 3;
+        nb = 32;
+        variant = BF_DAS_GATHER;
     } else if (p.iq) {
         // IQ kernels hold more registers (complex accumulators and quads): two
         // 8-wavefront workgroups per CU
@@ -248,6 +275,13 @@ int Frame::init(const bf_params &src)
     d_Hf = (float *)alloc(Hf.size() * sizeof(float));
     d_tx_x = (float *)alloc(tx_x.size() * sizeof(float));
     d_rx_c = (float *)alloc(rx_c.size() * sizeof(float));
+    if (!tx_sc.empty()) {
+        d_tx_sc = (float2 *)alloc(tx_sc.size() * sizeof(float2));
+        if (!d_tx_sc) return fail(BF_ERR_HIP, "device allocation of the TPW angle table failed");
+        hipError_t he = hipMemcpy(d_tx_sc, tx_sc.data(), tx_sc.size() * sizeof(float2),
+                                  hipMemcpyHostToDevice);
+        if (he != hipSuccess) return hip_fail(he, "upload of the TPW angle table");
+    }
     max_blocks = 0;
     for (int lx = 0; lx <= 6; ++lx)        // partial-sum buffer large enough for any tile
         for (int ly = 0; ly + lx <= 6; ++ly) {
@@ -361,6 +395,9 @@ DasArgs Frame::das_args(const void *e, float *out, double c) const
     a.cx = p.iq;
     a.rot_d = p.iq ? p.fc / p.fs : 0.0;
     a.rot = (float)a.rot_d;
+    a.div_f = (p.mode == BF_HERCULES_3D && is_fin(p.focal_depth)) ? -p.focal_depth : 0.0;
+    a.zf = p.mode == BF_VLS_3D ? (float)p.focal_depth : 0.f;
+    a.tx_sc = d_tx_sc;
     return a;
 }
 
@@ -377,6 +414,7 @@ int Frame::decode(const int16_t *rf, void *e, hipStream_t s) const
 // (the direct-gather kernel is used then).
 bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
 {
+    if (p.mode != BF_FORCES_2D && p.mode != BF_HERCULES_3D) return false;   // gather only
     const int tx = bw[0] << lx, ty = bw[1] << ly, tz = bw[2] << lz;
     double E[3];
     for (int r = 0; r < 3; ++r)
@@ -384,8 +422,11 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
     // Bound on the spread of the sample position over the box: the delay
     // grows with depth (2 dz on the round trip) and with lateral distance
     // (one receive path for HERCULES, transmit and receive for FORCES).
+    // A diverging transmit path changes by at most the box diagonal.
+    const double lat = sqrt(E[0] * E[0] + E[1] * E[1]);
     const double spread = p.mode == BF_FORCES_2D ? 2.0 * E[2] + 2.0 * E[0]
-                                                 : 2.0 * E[2] + sqrt(E[0] * E[0] + E[1] * E[1]);
+                          : a.div_f > 0.0 ? E[2] + lat + sqrt(lat * lat + E[2] * E[2])
+                                          : 2.0 * E[2] + lat;
     const int lmax = (int)ceil(a.k * spread) + 8;
     const int nthr = 64 * bw[0] * bw[1] * bw[2];
     int nbb = nb;

@@ -330,14 +330,19 @@ struct TileCand {
 std::vector<TileCand> candidates(const Frame &f)
 {
     std::vector<TileCand> c;
-    if (f.p.mode == BF_FORCES_2D && f.grid.ny == 1) {
-        const int tiles[][3] = {{3, 0, 3}, {2, 0, 4}, {4, 0, 2}, {1, 0, 5}};
-        const int blocks[][3] = {{2, 1, 2}, {4, 1, 1}, {1, 1, 4}, {2, 1, 1}, {4, 1, 4}};
+    if (f.p.mode == BF_FORCES_2D && (f.grid.ny == 1 || f.grid.nx == 1)) {
+        // a plane along x (ny = 1) or along y (nx = 1): tiles and workgroups
+        // spread over that lateral axis and depth only
+        const bool along_x = f.grid.ny == 1;
+        const int tiles[][2] = {{3, 3}, {2, 4}, {4, 2}, {1, 5}};
+        const int blocks[][2] = {{2, 2}, {4, 1}, {1, 4}, {2, 1}, {4, 4}};
         for (auto &t : tiles) {
-            c.push_back({t[0], t[1], t[2], 1, 1, 1, 4, BF_DAS_GATHER});
+            const int lx = along_x ? t[0] : 0, ly = along_x ? 0 : t[0];
+            c.push_back({lx, ly, t[1], 1, 1, 1, 4, BF_DAS_GATHER});
             for (auto &b : blocks)
                 for (int nb : {4, 8, 16})
-                    c.push_back({t[0], t[1], t[2], b[0], b[1], b[2], nb, BF_DAS_LDS});
+                    c.push_back({lx, ly, t[1], along_x ? b[0] : 1, along_x ? 1 : b[0], b[1], nb,
+                                 BF_DAS_LDS});
         }
     } else {
         const int tiles[][3] = {{3, 3, 0}, {2, 3, 1}, {2, 2, 2}};

@@ -77,7 +77,15 @@ struct DasArgs {
     int cx;                 // IQ data: e, out and part hold (re, im) pairs
     float rot;              // IQ: fd / fs, revolutions of carrier phase per sample
     double rot_d;           // the same in FP64 (per-lane phase origin)
+    double div_f;           // HERCULES diverging wave: source depth f > 0 (0: plane wave)
+    float zf;               // VLS: depth of the virtual line sources
+    const float2 *tx_sc;    // TPW: [n_tx] (sin theta, cos theta - 1)
 };
+
+// Modes: 0 FORCES (2D), 1 HERCULES (3D), 2 TPW and 3 VLS (row-column volumes:
+// columns transmit, rows receive).  Modes 0, 2, 3 separate into a transmit
+// and a receive excess path; HERCULES has one radial receive path.
+constexpr int MODE_FORCES = 0, MODE_HERCULES = 1, MODE_TPW = 2, MODE_VLS = 3;
 
 // Hann weight table: W(u) of Eq. 3 sampled at u^2 = k / (4 HANN_N), stored as
 // (W_k, W_{k+1} - W_k) for linear interpolation in u^2 (max error 1.2e-7);
@@ -183,7 +191,20 @@ struct Lane {
     float thr;      // rho^2 threshold of the receive aperture (inf: no apodization)
     float wsc;      // u^2 = rho^2 * wsc
     float ph0;      // IQ: carrier phase (revolutions, in [0, 1)) of sample position nB
+    float ptx;      // transmit path down to the point: z, or |p - v| - f (diverging)
 };
+
+// Transmit path of a point (array-frame offsets from the centre) in FP64: the
+// plane wave's z, or for a diverging wave from v = (0, 0, -f) the distance to
+// v minus f (zero at the array centre).
+__device__ inline double tx_path(const DasArgs &a, double px, double py, double pz)
+{
+    if (a.div_f > 0.0) {
+        const double dz = pz + a.div_f;
+        return sqrt(px * px + py * py + dz * dz) - a.div_f;
+    }
+    return pz;
+}
 
 __device__ inline Lane lane_setup(const DasArgs &a, int wave_id, int lane)
 {
@@ -202,7 +223,9 @@ __device__ inline Lane lane_setup(const DasArgs &a, int wave_id, int lane)
     const double py = a.g.org[1] + ix * a.g.ax[1] + iy * a.g.ay[1] + iz * a.g.az[1];
     const double pz = a.g.org[2] + ix * a.g.ax[2] + iy * a.g.ay[2] + iz * a.g.az[2];
     L.active = L.valid && pz > 0.0;
-    const double B = 2.0 * pz * a.k - a.t0fs;
+    const double ptx = tx_path(a, px, py, pz);
+    L.ptx = (float)ptx;
+    const double B = (ptx + pz) * a.k - a.t0fs;
     const double fl = floor(B);
     L.nB = (int)fl;
     L.fB = (float)(B - fl);
@@ -226,6 +249,39 @@ __device__ inline float excess(float rho2, float z, float z2)
 {
     const float d = __builtin_amdgcn_sqrtf(rho2 + z2);
     return rho2 * __builtin_amdgcn_rcpf(d + z);
+}
+
+// Receive coordinate of a lane for modes 0, 2, 3 (the receivers of FORCES are
+// columns at x, those of TPW and VLS rows at y).
+template <int MODE>
+__device__ inline float rx_coord(float x, float y)
+{
+    return MODE == MODE_FORCES ? x : y;
+}
+
+// Transmit excess path beyond z of transmit i at lane position (x, z), for
+// modes 0, 2, 3 (the transmit path is z + this):
+//   FORCES: cylindrical wave of column x_i:   |(x - x_i, z)| - z
+//   TPW:    tilted plane wave, zero at the centre: x sin(th) + z (cos(th) - 1)
+//   VLS:    virtual line source (x_i, z_f):   z_f + sgn(z - z_f) |(x - x_i, z - z_f)| - z
+//           = sgn(dz) rho^2 / (|(rho, dz)| + |dz|),  rho = x - x_i, dz = z - z_f
+//           (exact rewriting without cancellation; sgn(0) = +1)
+template <int MODE>
+__device__ inline float tx_excess(const DasArgs &a, float x, float z, float z2, int i)
+{
+    if constexpr (MODE == MODE_TPW) {
+        const float2 sc = a.tx_sc[i];
+        return fmaf(x, sc.x, z * sc.y);
+    } else if constexpr (MODE == MODE_VLS) {
+        const float rho = x - a.tx_x[i], dz = z - a.zf;
+        const float r2 = rho * rho;
+        const float den = __builtin_amdgcn_sqrtf(fmaf(dz, dz, r2)) + fabsf(dz);
+        const float e = den > 0.f ? r2 * __builtin_amdgcn_rcpf(den) : 0.f;   // 0 on the line
+        return dz >= 0.f ? e : -e;
+    } else {
+        const float dxt = x - a.tx_x[i];
+        return excess(dxt * dxt, z, z2);
+    }
 }
 
 template <int ET>

@@ -9,10 +9,12 @@
 // Delay precision.  The sample position s = (tof - t0) fs reaches ~2000, where
 // an FP32 ulp is 1.2e-4 samples; summed over thousands of traces that costs
 // ~3e-5 relative image error.  The kernels therefore split
-//     s = B(p) + k * (E_tx + E_rx),   B = (2 z k - t0 fs),  k = fs / c,
-// with B evaluated once per lane in FP64 and split into an integer part and
-// an FP32 fraction, and the small excess paths E = d - z = rho^2 / (d + z)
-// (exact rewriting of d - z without cancellation) in FP32.
+//     s = B(p) + k * (E_tx + E_rx),   B = ((T(p) + z) k - t0 fs),  k = fs / c,
+// with T(p) the transmit path down to the point (z for plane waves and the
+// separable modes, whose transmit excess goes into E_tx), B evaluated once per
+// lane in FP64 and split into an integer part and an FP32 fraction, and the
+// small excess paths E = d - z = rho^2 / (d + z) (exact rewriting of d - z
+// without cancellation) in FP32.
 //
 // Apodization skip (Sec. VII-F): a trace is skipped wavefront-uniformly when
 // no lane lies inside its receive aperture, tested on rho^2 against
@@ -118,18 +120,19 @@ __device__ inline void add_term(const DasArgs &a, const Lane &L, const void *tr,
         acc.x = fmaf(w, read_trace<ET, IP>(tr, a.S, L.nB, s), acc.x);
 }
 
-// FORCES: the transmit and receive excess paths separate.  The wavefront
-// collects up to JG of its active channel rows (a row is active when some
-// lane lies inside its receive aperture), computes each row's receive term
-// and apodization once per lane, then sweeps the transmits: the transmit
-// excess path (one square root and one reciprocal) is shared by the JG terms
-// of that transmit.  Terms of one point are added in (row chunk, transmit,
-// row) order.
+// FORCES, TPW, VLS: the transmit and receive excess paths separate.  The
+// wavefront collects up to JG of its active receivers (a receiver is active
+// when some lane lies inside its receive aperture), computes each one's
+// receive term and apodization once per lane, then sweeps the transmits: the
+// transmit excess path (tx_excess) is shared by the JG terms of that
+// transmit.  Terms of one point are added in (receiver chunk, transmit,
+// receiver) order.
 constexpr int JG = 8;
 
-template <int ET, int IP>
-__device__ inline float2 das_forces_point(const DasArgs &a, const Lane &L, int jb, int je)
+template <int MODE, int ET, int IP>
+__device__ inline float2 das_separable_point(const DasArgs &a, const Lane &L, int jb, int je)
 {
+    const float xr = rx_coord<MODE>(L.x, L.y);
     const float kf = (float)a.k;
     float2 acc = make_float2(0.f, 0.f);
     int j = jb;
@@ -137,7 +140,7 @@ __device__ inline float2 das_forces_point(const DasArgs &a, const Lane &L, int j
         int rows[JG];
         int n = 0;
         for (; j < je && n < JG; ++j) {
-            const float dxr = L.x - a.rx_c[j];
+            const float dxr = xr - a.rx_c[j];
             if (__any(L.active && dxr * dxr < L.thr)) rows[n++] = j;
         }
         if (n == 0) break;
@@ -147,7 +150,7 @@ __device__ inline float2 das_forces_point(const DasArgs &a, const Lane &L, int j
             Rj[q] = 0.f;
             aj[q] = 0.f;
             if (q < n) {
-                const float dxr = L.x - a.rx_c[rows[q]];
+                const float dxr = xr - a.rx_c[rows[q]];
                 const float r2 = dxr * dxr;
                 const bool act = L.active && r2 < L.thr;
                 Rj[q] = fmaf(excess(r2, L.z, L.z2), kf, L.fB);
@@ -155,8 +158,7 @@ __device__ inline float2 das_forces_point(const DasArgs &a, const Lane &L, int j
             }
         }
         for (int i = 0; i < a.n_tx; ++i) {
-            const float dxt = L.x - a.tx_x[i];
-            const float T = kf * excess(dxt * dxt, L.z, L.z2);
+            const float T = kf * tx_excess<MODE>(a, L.x, L.z, L.z2, i);
 #pragma unroll
             for (int q = 0; q < JG; ++q) {
                 if (q < n && L.active) {
@@ -169,8 +171,8 @@ __device__ inline float2 das_forces_point(const DasArgs &a, const Lane &L, int j
     return acc;
 }
 
-// HERCULES: receive element (x_i, y_j, 0), plane-wave transmit (tof_tx = z/c,
-// already inside B), radial apodization.
+// HERCULES: receive element (x_i, y_j, 0), transmit path of the point (plane
+// or diverging wave, one per point: already inside B), radial apodization.
 template <int ET, int IP>
 __device__ inline float2 das_hercules_point(const DasArgs &a, const Lane &L, int jb, int je)
 {
@@ -206,10 +208,10 @@ __global__ __launch_bounds__(256) void das_kernel(DasArgs a)
     int jb, je;
     group_rows(a.n_ch, blockIdx.y, a.groups, &jb, &je);
     float2 acc;
-    if constexpr (MODE == 0)
-        acc = das_forces_point<ET, IP>(a, L, jb, je);
-    else
+    if constexpr (MODE == MODE_HERCULES)
         acc = das_hercules_point<ET, IP>(a, L, jb, je);
+    else
+        acc = das_separable_point<MODE, ET, IP>(a, L, jb, je);
     if (L.valid) {
         if (!L.active) acc = make_float2(0.f, 0.f);
         const long npts = (long)a.g.nx * a.g.ny * a.g.nz;
@@ -271,7 +273,14 @@ static hipError_t launch_et(const DasArgs &a, int et, int ip, hipStream_t s)
 
 hipError_t launch_das(const DasArgs &a, int mode, int et, int ip, hipStream_t s)
 {
-    hipError_t err = mode == 0 ? launch_et<0>(a, et, ip, s) : launch_et<1>(a, et, ip, s);
+    hipError_t err;
+    switch (mode) {
+        case MODE_FORCES: err = launch_et<MODE_FORCES>(a, et, ip, s); break;
+        case MODE_HERCULES: err = launch_et<MODE_HERCULES>(a, et, ip, s); break;
+        case MODE_TPW: err = launch_et<MODE_TPW>(a, et, ip, s); break;
+        case MODE_VLS: err = launch_et<MODE_VLS>(a, et, ip, s); break;
+        default: return hipErrorInvalidValue;
+    }
     if (err != hipSuccess || a.groups <= 1) return err;
     return launch_sum_groups(a, s);
 }

@@ -52,6 +52,7 @@ struct BatchDesc {
 struct BoxGeom {
     float xmin, xmax, ymin, ymax, zmin, zmax;
     float kf, t0f;    // fs / c and t0 * fs in FP32 (window bounds only)
+    float txlo;       // lower bound of the transmit path over the box (HERCULES)
 };
 
 __device__ inline float wave_min(float v)
@@ -99,7 +100,7 @@ __device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, 
     const double py = a.g.org[1] + ix * a.g.ax[1] + iy * a.g.ay[1] + iz * a.g.az[1];
     const double pz = a.g.org[2] + ix * a.g.ax[2] + iy * a.g.ay[2] + iz * a.g.az[2];
     if (L.valid && pz > 0.0) {
-        const double B = 2.0 * pz * a.k - a.t0fs;
+        const double B = (tx_path(a, px, py, pz) + pz) * a.k - a.t0fs;
         const double fl = floor(B);
         L.nB = (int)fl;
         L.fB = (float)(B - fl);
@@ -150,6 +151,16 @@ __device__ inline BoxGeom block_box(const DasArgs &a, const LdsCfg &c, int bx, i
     b.zmin = (float)lo[2]; b.zmax = (float)hi[2];
     b.kf = (float)a.k;
     b.t0f = (float)a.t0fs;
+    // transmit path: z (plane wave), or the distance from the virtual source
+    // (0, 0, -f) to the box minus f (diverging wave); both grow with depth
+    const float zlo = fmaxf(b.zmin, 0.f);
+    b.txlo = zlo;
+    if (a.div_f > 0.0) {
+        const float f = (float)a.div_f;
+        const float dx = fmaxf(0.f, fmaxf(b.xmin, -b.xmax));
+        const float dy = fmaxf(0.f, fmaxf(b.ymin, -b.ymax));
+        b.txlo = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, (zlo + f) * (zlo + f)))) - f;
+    }
     return b;
 }
 
@@ -177,7 +188,7 @@ __device__ inline int window_start(const BoxGeom &b, float xi, float cj)
     } else {
         const float rx = dist_to_range(xi, b.xmin, b.xmax);
         const float ry = dist_to_range(cj, b.ymin, b.ymax);
-        path = zlo + __builtin_amdgcn_sqrtf(fmaf(rx, rx, fmaf(ry, ry, zlo * zlo)));
+        path = b.txlo + __builtin_amdgcn_sqrtf(fmaf(rx, rx, fmaf(ry, ry, zlo * zlo)));
     }
     return (int)floorf(fmaf(path, b.kf, -b.t0f)) - 2;
 }
@@ -794,8 +805,9 @@ hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, i
                           hipStream_t s)
 {
     const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, a.cx ? 2 : 1);
-    hipError_t err = mode == 0 ? launch_lds_et<0>(a, c, et, ip, shm, s)
-                               : launch_lds_et<1>(a, c, et, ip, shm, s);
+    if (mode != MODE_FORCES && mode != MODE_HERCULES) return hipErrorInvalidValue;
+    hipError_t err = mode == MODE_FORCES ? launch_lds_et<MODE_FORCES>(a, c, et, ip, shm, s)
+                                         : launch_lds_et<MODE_HERCULES>(a, c, et, ip, shm, s);
     if (err != hipSuccess || a.groups <= 1) return err;
     return launch_sum_groups(a, s);
 }

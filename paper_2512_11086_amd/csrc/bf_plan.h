@@ -38,6 +38,7 @@ struct Frame {
     int *d_colsum = nullptr;
     float *d_Hf = nullptr;
     float *d_tx_x = nullptr, *d_rx_c = nullptr;
+    float2 *d_tx_sc = nullptr;   // TPW: (sin, cos - 1) per transmit
     double *d_partial = nullptr;
     void *d_e = nullptr;         // batch plans: decoded-data workspace
     std::vector<void *> allocs;

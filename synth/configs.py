@@ -55,7 +55,8 @@ def describe(mode, n_elem, pitch, n_tx, n_ch, n_samples, fs, fc, dims, gmin, gma
 
 
 def workload(k: int) -> dict:
-    """Description of workload k in 0..3 (workload 4 varies per frame; see frames_4)."""
+    """Description of workload k in 0..3 and 5..7 (workload 4 varies per frame, see
+    frame_4; workload 8 is the cross-plane pair, see cross_planes)."""
     if k == 0:   # FORCES 2D B-scan, 32x32 array
         return describe("forces", (32, 32), (0.2 * MM, 0.2 * MM), 32, 32, 1024, 20e6, 5e6,
                         (128, 1, 128), (-6.4 * MM, 0, 5 * MM), (6.4 * MM, 0, 40 * MM), t0=4e-6)
@@ -66,7 +67,39 @@ def workload(k: int) -> dict:
     if k == 3:   # differentiable FORCES, 64x64 array, 256x256 image
         return describe("forces", (64, 64), (0.2 * MM, 0.2 * MM), 64, 64, 2048, 20e6, 5e6,
                         (256, 1, 256), (-6.4 * MM, 0, 5 * MM), (6.4 * MM, 0, 45 * MM))
+    if k == 5:   # diverging-wave HERCULES: workload 1 with a source 20 mm behind the array
+        return describe("hercules", (128, 128), (0.1 * MM, 0.1 * MM), 128, 128, 2048, 30e6, 7.5e6,
+                        (128, 128, 256), (-6.4 * MM, -6.4 * MM, 5 * MM),
+                        (6.4 * MM, 6.4 * MM, 30 * MM), focal_depth=-20 * MM)
+    if k == 6:   # TPW row-column volume: 32 tilted plane waves over +-10 deg, 128 rows
+        return describe("tpw", (128, 128), (0.1 * MM, 0.1 * MM), 32, 128, 2048, 30e6, 7.5e6,
+                        (128, 128, 256), (-6.4 * MM, -6.4 * MM, 5 * MM),
+                        (6.4 * MM, 6.4 * MM, 30 * MM),
+                        tx_angles=np.deg2rad(np.linspace(-10.0, 10.0, 32)))
+    if k == 7:   # VLS-128 row-column volume: a virtual line 10 mm behind every column
+        return describe("vls", (128, 128), (0.1 * MM, 0.1 * MM), 128, 128, 2048, 30e6, 7.5e6,
+                        (128, 128, 256), (-6.4 * MM, -6.4 * MM, 5 * MM),
+                        (6.4 * MM, 6.4 * MM, 30 * MM), focal_depth=-10 * MM)
     raise ValueError(k)
+
+
+def cross_planes():
+    """Cross-plane FORCES pair (one parameter set per plane, Sec. VI-B): the
+    x-z plane at y = 0 acquired with the columns, and the y-z plane at x = 0
+    acquired with the rows, described as an array frame rotated by 90 degrees
+    about z so that the rows play the columns' role (128x128 array, 0.1 mm,
+    128 tx x 128 ch x 2048 at 30 MHz, 256 x 256 points each)."""
+    n, pitch = 128, 0.1 * MM
+    xz = describe("forces", (n, n), (pitch, pitch), n, n, 2048, 30e6, 7.5e6, (256, 1, 256),
+                  (-6.4 * MM, 0, 5 * MM), (6.4 * MM, 0, 30 * MM))
+    # global (x, y, z) -> rotated array frame (y + c, -x + c, z): rows become columns
+    R = np.array([[0.0, 1.0, 0.0, (n - 1) / 2 * pitch],
+                  [-1.0, 0.0, 0.0, (n - 1) / 2 * pitch],
+                  [0.0, 0.0, 1.0, 0.0],
+                  [0.0, 0.0, 0.0, 1.0]])
+    yz = describe("forces", (n, n), (pitch, pitch), n, n, 2048, 30e6, 7.5e6, (1, 256, 256),
+                  (0, -6.4 * MM, 5 * MM), (0, 6.4 * MM, 30 * MM), xdc=R)
+    return [xz, yz]
 
 
 def frame_4(kind: str, tx_cols) -> dict:
@@ -129,6 +162,21 @@ def make_inputs(k: int, frame=None):
                 rng.standard_normal((desc["n_tx"], desc["n_ch"], desc["n_samples"]))
         return desc, H, [f[2] for f in frames], dict(c_true=c_true,
                                                      points=[f[0] for f in frames])
+    if k in (5, 6, 7):
+        desc = workload(k)
+        pts, amps = scene(1, rng)
+        encoded = k == 5                      # TPW and VLS are not Hadamard-encoded
+        H = hadamard_sylvester(desc["n_tx"]) if encoded else None
+        rf = acquire(desc, pts, amps, rng, H=H, encoded=encoded)
+        return desc, H, rf, dict(points=pts, amps=amps)
+    if k == 8:
+        out = []
+        for desc in cross_planes():
+            H = hadamard_sylvester(desc["n_tx"])
+            lo, hi = np.asarray(desc["gmin"]), np.asarray(desc["gmax"])
+            pts = _uniform_pts(rng, 12, lo, hi)
+            out.append((desc, H, acquire(desc, pts, np.ones(12), rng, H=H)))
+        return [o[0] for o in out], [o[1] for o in out], [o[2] for o in out], {}
     if k == 4:
         plan = frames_4_plan(rng)
         out = []

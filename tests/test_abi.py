@@ -32,7 +32,7 @@ def test_library_exports_every_declared_function():
     for name in names:
         assert hasattr(L, name), f"{name} declared in bf.h but not exported"
     assert set(names) == set(_lib.EXPORTED)
-    assert L.bf_abi_version() == 2
+    assert L.bf_abi_version() == 3
 
 
 def _good(k=0):
@@ -59,7 +59,7 @@ def test_validate_null_and_hadamard_errors():
     L = _lib.lib()
     assert L.bf_validate(None) == -1
     d, H = _good()
-    assert _status(d, None) == -1
+    assert _status(d, None) == 0          # NULL: unencoded acquisition, identity decode
     bad = H.copy()
     bad[3, 5] = 0
     assert _status(d, bad) == -3
@@ -229,3 +229,25 @@ def test_envelope_validation_on_host():
     import torch
     if not torch.cuda.is_available():
         assert L.bf_env_create(4, 16, 0, ctypes.byref(h)) == -8
+
+
+def test_validate_transmit_models():
+    MM = 1e-3
+    d, H = _good(1)
+    ok = dict(d, focal_depth=-20 * MM)                       # diverging HERCULES
+    assert _status(ok, H) == 0, _lib.lib().bf_last_error()
+    assert _status(dict(d, focal_depth=20 * MM), H) == -5    # focused HERCULES: not a model here
+    tpw = dict(d, mode="tpw", tx_angles=np.linspace(-0.2, 0.2, d["n_tx"]))
+    assert _status(tpw, None) == 0, _lib.lib().bf_last_error()
+    assert _status(dict(tpw, tx_angles=None), None) == -1
+    bad = np.zeros(d["n_tx"])
+    bad[3] = math.pi / 2
+    assert _status(dict(tpw, tx_angles=bad), None) == -4
+    bad[3] = math.nan
+    assert _status(dict(tpw, tx_angles=bad), None) == -4
+    vls = dict(d, mode="vls", focal_depth=-5 * MM)
+    assert _status(vls, None) == 0
+    assert _status(dict(vls, focal_depth=math.inf), None) == -4
+    m = bfm.params_from_desc(d, H)
+    m.p.mode = 4
+    assert _lib.lib().bf_validate(ctypes.byref(m.p)) == -5

@@ -54,6 +54,10 @@ def active_terms(desc, dev) -> int:
             r2 = (x[:, None] - xt[None, :]) ** 2 + (y[:, None] - yj) ** 2
             total += int(torch.count_nonzero(F2 * r2 < thr[:, None]))
         return total
+    if desc["mode"] in ("tpw", "vls"):        # row receivers: apodization on |y - y_j|
+        for yj in np.asarray(desc["channel_map"], dtype=np.float64) * py:
+            total += int(torch.count_nonzero(F2 * (y - yj) ** 2 < thr)) * len(xt)
+        return total
     for xj in np.asarray(desc["channel_map"], dtype=np.float64) * px:
         total += int(torch.count_nonzero(F2 * (x - xj) ** 2 < thr)) * len(xt)
     return total
@@ -270,6 +274,62 @@ def envelope_stage(torch, bfm, img, reps: int = 10):
     return res
 
 
+def n4_workloads(torch, bfm, synth, reps: int = 2):
+    """Decode + DAS of the additional transmit models at the headline volume
+    size (128x128 array, 2048 samples, 128x128x256 voxels): diverging-wave
+    HERCULES (LDS kernel), TPW with 32 angles and VLS-128 (gather kernel,
+    unencoded data), and the cross-plane FORCES pair as one captured graph."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    res = {}
+    names = {5: "diverging_hercules", 6: "tpw_32", 7: "vls_128"}
+    for k, name in names.items():
+        desc, H, rf, _ = synth.make_inputs(k)
+        plan = bfm.Plan(desc, H)
+        rf_d = torch.from_numpy(rf).to(dev)
+        e = plan.decode(rf_d)
+        img = plan.das(e)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        for _ in range(reps):
+            plan.decode(rf_d, out=e)
+        ev[1].record(stream)
+        for _ in range(reps):
+            plan.das(e, out=img)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        dec_ms = ev[0].elapsed_time(ev[1]) / reps
+        das_ms = ev[1].elapsed_time(ev[2]) / reps
+        n_act = active_terms(desc, dev)
+        tf = n_act * 45 / (das_ms * 1e-3) / 1e12
+        nominal = int(np.prod(desc["dims"])) * desc["n_tx"] * desc["n_ch"]
+        res[name] = {"n_tx": desc["n_tx"], "decode_ms": round(dec_ms, 4),
+                     "das_ms": round(das_ms, 3),
+                     "value": round(nominal / ((dec_ms + das_ms) * 1e-3) / 1e9, 2),
+                     "unit": "G samples/s", "variant": "lds" if plan.info()["variant"] == 0 else "gather",
+                     "roofline": {"bound": "alu", "achieved": round(tf, 2),
+                                  "peak": round(FP32_NONPACKED_TFLOPS, 1), "unit": "TFLOP/s",
+                                  "frac": round(tf / FP32_NONPACKED_TFLOPS, 4)}}
+        log(f"{name}: decode {dec_ms:.3f} ms, DAS {das_ms:.3f} ms")
+        del plan, rf_d, e, img
+    descs, Hs, rfs, _ = synth.make_inputs(8)
+    bp = bfm.BatchPlan(descs, Hs)
+    rf_d = [torch.from_numpy(r).to(dev) for r in rfs]
+    outs = [torch.empty(s, device=dev) for s in bp.out_shapes]
+    bp.graph_launch(rf_d, outs)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        bp.graph_launch(rf_d, outs)
+    b.record(stream)
+    torch.cuda.synchronize()
+    res["cross_plane_graph_ms"] = round(a.elapsed_time(b) / reps, 3)
+    res["cross_plane"] = "FORCES x-z (columns) + y-z (rows) planes, 256x256 each, one graph"
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +341,7 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--no-iq", action="store_true", help="skip the demodulation + IQ pipeline")
     ap.add_argument("--iq-reps", type=int, default=3)
+    ap.add_argument("--no-n4", action="store_true", help="skip the TPW / VLS / diverging workloads")
     ap.add_argument("--traffic", action="store_true",
                     help="only run the short kernel sequence used for counter collection")
     args = ap.parse_args()
@@ -370,6 +431,8 @@ def main():
     if not args.no_iq:
         res["iq"] = iq_pipeline(torch, bfm, synth, desc, H, rf_d, n_act, args.iq_reps)
         log(f"IQ pipeline {res['iq']['ms_per_step']:.3f} ms")
+    if not args.no_n4:
+        res["n4"] = n4_workloads(torch, bfm, synth)
     if not args.no_batch:
         res["batched"] = batched_comparison(torch, bfm, synth, args.batch_reps)
     if not args.no_cpu:

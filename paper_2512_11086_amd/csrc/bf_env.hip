@@ -6,10 +6,16 @@
 // column is |x_a| with x_a its analytic signal along depth:
 //     X = DFT_N(x),  X_a[k] = h[k] X[k]  (h = 1 at DC and Nyquist, 2 for
 //     positive, 0 for negative frequencies),  x_a = IDFT_N(X_a).
-// One workgroup per column.  Power-of-two N: radix-2 FFT in LDS (forward
+// Power-of-two N from 64 to 1024: one wavefront per column, FFT held in
+// registers (four-step split N = 64 M: a 64-point FFT across the lanes by
+// xor-partner exchanges, a twiddle, an M-point FFT inside each lane, then the
+// mirror image for the inverse); no LDS passes and no barriers.  Other
+// power-of-two N: one workgroup per column, radix-2 FFT in LDS (forward
 // decimation-in-time from a bit-reversed load, spectrum weighting, inverse
-// decimation-in-frequency, read back in bit-reversed order), twiddles from a
-// host FP64 table staged in LDS.  Other N: Re x_a = x exactly, and Im x_a is the
+// decimation-in-frequency, read back in bit-reversed order).  Twiddles come
+// from a host-FP64, stage-major table in global memory (stage len holds
+// exp(-j 2 pi pos / len) for pos < len / 2 at offset len / 2 - 1), so the
+// lanes of a stage read consecutive entries (cached; no LDS bank conflicts).  Other N: Re x_a = x exactly, and Im x_a is the
 // circular convolution of x with q = Im IDFT(h) (host FP64), summed directly.
 // IQ images already are analytic: the envelope is |z|.
 //
@@ -36,7 +42,10 @@ constexpr int ENV_MAX_N = 4096;
 struct EnvArgs {
     const float *img;        // [n_cols][N] real, or [n_cols][N][2] complex (iq)
     float *out;              // [n_cols][N]
-    const float2 *tw;        // FFT: [N/2] exp(-j 2 pi t / N)
+    const float2 *tw;        // FFT: [N - 1] stage-major twiddles (see above)
+    const float2 *tw_lane;   // register FFT: [6][64] W_{2d}^{l mod d}, d = 32, 16, .., 1
+    const float2 *tw_mid;    // register FFT: [64][M] W_N^{r bitrev6(l)}
+    float2 wm[8];            // register FFT: W_M^j, j < M / 2
     const float *q;          // direct path: [N] Im IDFT(h)
     float *part_max;         // [n_parts] per-workgroup maxima (ref <= 0)
     float *img_max;          // reduced maximum (ref <= 0)
@@ -91,25 +100,25 @@ __device__ inline float2 cmul(float2 a, float2 b)
 
 __device__ inline unsigned bitrev(unsigned v, int bits) { return __brev(v) >> (32 - bits); }
 
-// grid: n_cols workgroups of T threads; LDS: N float2 data + N/2 float2 twiddles
+// grid: n_cols workgroups of T threads; LDS: N float2 data
 __global__ __launch_bounds__(256) void env_fft_kernel(EnvArgs a)
 {
     extern __shared__ float2 sm[];
     float2 *d = sm;
-    float2 *tw = sm + a.N;
+    const float2 *__restrict__ tw = a.tw;
     const int N = a.N, half_n = N >> 1, T = blockDim.x, t = threadIdx.x;
     const long col = blockIdx.x;
     const float *x = a.img + col * N;
-    for (int i = t; i < half_n; i += T) tw[i] = a.tw[i];
     for (int n = t; n < N; n += T) d[bitrev(n, a.log2n)] = make_float2(x[n], 0.f);
     __syncthreads();
     // forward DIT: butterflies (i, i + h) with twiddle exp(-j 2 pi pos / len)
-    for (int len = 2, stride = half_n; len <= N; len <<= 1, stride >>= 1) {
+    for (int len = 2; len <= N; len <<= 1) {
         const int h = len >> 1;
+        const float2 *twl = tw + (h - 1);
         for (int b = t; b < half_n; b += T) {
             const int pos = b & (h - 1);
             const int i = ((b - pos) << 1) + pos;
-            const float2 u = d[i], v = cmul(d[i + h], tw[pos * stride]);
+            const float2 u = d[i], v = cmul(d[i + h], twl[pos]);
             d[i] = make_float2(u.x + v.x, u.y + v.y);
             d[i + h] = make_float2(u.x - v.x, u.y - v.y);
         }
@@ -122,13 +131,14 @@ __global__ __launch_bounds__(256) void env_fft_kernel(EnvArgs a)
     }
     __syncthreads();
     // inverse DIF: butterflies (i, i + h), (u + v, (u - v) exp(+j 2 pi pos / len))
-    for (int len = N, stride = 1; len >= 2; len >>= 1, stride <<= 1) {
+    for (int len = N; len >= 2; len >>= 1) {
         const int h = len >> 1;
+        const float2 *twl = tw + (h - 1);
         for (int b = t; b < half_n; b += T) {
             const int pos = b & (h - 1);
             const int i = ((b - pos) << 1) + pos;
             const float2 u = d[i], v = d[i + h];
-            const float2 w = tw[pos * stride];
+            const float2 w = twl[pos];
             d[i] = make_float2(u.x + v.x, u.y + v.y);
             d[i + h] = cmul(make_float2(u.x - v.x, u.y - v.y), make_float2(w.x, -w.y));
         }
@@ -167,6 +177,136 @@ __global__ __launch_bounds__(256) void env_direct_kernel(EnvArgs a)
         for (int k = 0; k < N; ++k) y = fmaf(q[k], x2[n - k + N], y);
         const float xv = x2[n];
         store_env(a, col * N + n, sqrtf(fmaf(xv, xv, y * y)), local_max);
+    }
+    publish_max(a, local_max);
+}
+
+// ---------------------------------------------------------------------------
+// Register FFT (64 <= N = 64 M <= 1024): sample n = M l + r lives in lane l,
+// register r.  X[k1 + 64 k2] = sum_r W_M^{r k2} W_N^{r k1} [sum_l x[M l + r] W_64^{l k1}].
+// ---------------------------------------------------------------------------
+__device__ inline float2 shfl_xor2(float2 v, int m)
+{
+    return make_float2(__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64));
+}
+
+// 64-point DIF across lanes for each register (sign -1: forward); lane l ends
+// with the bin bitrev6(l).  Pairs (l, l ^ d): lower l gets v + p, upper gets
+// (p - v) W_{2d}^{l mod d}.  tw_l[s] = W_{2d}^{l mod d} for every lane.
+template <int M>
+__device__ inline void lane_dif(float2 (&v)[M], const float2 *tw_l, int lane)
+{
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        const int d = 32 >> s;
+        const bool up = (lane & d) != 0;
+        const float2 w = up ? tw_l[s] : make_float2(1.f, 0.f);
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            const float2 p = shfl_xor2(v[r], d);
+            const float2 t = up ? make_float2(p.x - v[r].x, p.y - v[r].y)
+                                : make_float2(v[r].x + p.x, v[r].y + p.y);
+            v[r] = cmul(t, w);
+        }
+    }
+}
+
+// 64-point inverse DIT across lanes from bit-reversed bins back to natural
+// order (sign +1): lower l gets v + W p, upper gets p - W v, W = conj(W_{2d}^{l mod d}).
+template <int M>
+__device__ inline void lane_dit_inv(float2 (&v)[M], const float2 *tw_l, int lane)
+{
+#pragma unroll
+    for (int s = 5; s >= 0; --s) {
+        const int d = 32 >> s;
+        const bool up = (lane & d) != 0;
+        const float2 w = make_float2(tw_l[s].x, -tw_l[s].y);
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            const float2 p = shfl_xor2(v[r], d);
+            const float2 own = cmul(up ? v[r] : p, w);      // W times the upper value
+            const float2 base = up ? p : v[r];              // the lower value
+            v[r] = up ? make_float2(base.x - own.x, base.y - own.y)
+                      : make_float2(base.x + own.x, base.y + own.y);
+        }
+    }
+}
+
+// In-register M-point DFT, natural order in and out; sign -1 forward, +1 inverse.
+template <int M>
+__device__ inline void reg_fft(float2 (&v)[M], const float2 *wm, float sign)
+{
+    if constexpr (M > 1) {
+        // bit-reverse permutation, then iterative DIT
+        constexpr int L = M == 2 ? 1 : M == 4 ? 2 : M == 8 ? 3 : 4;
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            int j = 0;
+#pragma unroll
+            for (int b = 0; b < L; ++b) j |= ((i >> b) & 1) << (L - 1 - b);
+            if (j > i) {
+                const float2 t = v[i];
+                v[i] = v[j];
+                v[j] = t;
+            }
+        }
+#pragma unroll
+        for (int h = 1; h < M; h <<= 1) {
+#pragma unroll
+            for (int i0 = 0; i0 < M; i0 += 2 * h) {
+#pragma unroll
+                for (int j = 0; j < h; ++j) {
+                    const float2 w0 = wm[j * (M / (2 * h))];
+                    const float2 w = make_float2(w0.x, sign < 0.f ? w0.y : -w0.y);
+                    const float2 t = cmul(v[i0 + j + h], w);
+                    const float2 u = v[i0 + j];
+                    v[i0 + j] = make_float2(u.x + t.x, u.y + t.y);
+                    v[i0 + j + h] = make_float2(u.x - t.x, u.y - t.y);
+                }
+            }
+        }
+    }
+}
+
+// 4 columns per 256-thread workgroup, one per wavefront.
+template <int M>
+__global__ __launch_bounds__(256) void env_fft_reg_kernel(EnvArgs a)
+{
+    constexpr int N = 64 * M;
+    const int lane = threadIdx.x & 63;
+    const long col = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    float local_max = 0.f;
+    if (col < a.n_cols) {
+        const float *x = a.img + col * N + M * lane;
+        float2 v[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) v[r] = make_float2(x[r], 0.f);
+        float2 twl[6];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) twl[s] = a.tw_lane[s * 64 + lane];
+        lane_dif<M>(v, twl, lane);
+        // lane holds bin k1 = bitrev6(lane) of each register's 64-point DFT
+        const float2 *tm = a.tw_mid + lane * M;
+#pragma unroll
+        for (int r = 0; r < M; ++r) v[r] = cmul(v[r], tm[r]);
+        reg_fft<M>(v, a.wm, -1.f);
+        // analytic-signal weights on X[k1 + 64 k2] (register k2)
+        const int k1 = (int)(__brev((unsigned)lane) >> 26);
+#pragma unroll
+        for (int k2 = 0; k2 < M; ++k2) {
+            const int k = k1 + 64 * k2;
+            const float w = (k == 0 || 2 * k == N) ? 1.f : (2 * k < N ? 2.f : 0.f);
+            v[k2] = make_float2(v[k2].x * w, v[k2].y * w);
+        }
+        reg_fft<M>(v, a.wm, 1.f);
+#pragma unroll
+        for (int r = 0; r < M; ++r) v[r] = cmul(v[r], make_float2(tm[r].x, -tm[r].y));
+        lane_dit_inv<M>(v, twl, lane);
+        const float inv_n = 1.f / (float)N;
+#pragma unroll
+        for (int r = 0; r < M; ++r)
+            store_env(a, col * N + M * lane + r,
+                      sqrtf(fmaf(v[r].x, v[r].x, v[r].y * v[r].y)) * inv_n, local_max);
     }
     publish_max(a, local_max);
 }
@@ -224,12 +364,18 @@ struct bf_env_s {
     long n_cols = 0;
     int N = 0, iq = 0, log2n = -1;
     long n_parts = 0;
+    int reg_m = 0;                // register FFT: M = N / 64 (0: not used)
+    float2 wm[8] = {};
     float2 *d_tw = nullptr;
+    float2 *d_tw_lane = nullptr;  // [6][64]
+    float2 *d_tw_mid = nullptr;   // [64][M]
     float *d_q = nullptr;
     float *d_part = nullptr;      // [n_parts] per-workgroup maxima, then the maximum
     ~bf_env_s()
     {
         if (d_tw) (void)hipFree(d_tw);
+        if (d_tw_lane) (void)hipFree(d_tw_lane);
+        if (d_tw_mid) (void)hipFree(d_tw_mid);
         if (d_q) (void)hipFree(d_q);
         if (d_part) (void)hipFree(d_part);
     }
@@ -265,23 +411,61 @@ int bf_env_create(int64_t n_cols, int32_t n, int32_t iq, bf_env *out)
     e->n_cols = n_cols;
     e->N = n;
     e->iq = iq;
-    // workgroups of the envelope pass: one per column, or the grid-stride
-    // launch of the IQ path
-    e->n_parts = iq ? std::min<long>((n_cols * n + 255) / 256, 8192) : n_cols;
+    // register FFT for 64 <= N <= 1024 (powers of two)
+    if (!iq && (n & (n - 1)) == 0 && n >= 64 && n <= 1024) e->reg_m = n / 64;
+    // workgroups of the envelope pass: one per column, four columns per
+    // workgroup (register FFT), or the grid-stride launch of the IQ path
+    e->n_parts = iq ? std::min<long>((n_cols * n + 255) / 256, 8192)
+                    : e->reg_m ? (n_cols + 3) / 4 : n_cols;
     hipError_t err = hipMalloc(&e->d_part, (e->n_parts + 1) * sizeof(float));
     if (err == hipSuccess && !iq) {
         if ((n & (n - 1)) == 0 && n >= 2) {
             int l = 0;
             while ((1 << l) < n) ++l;
             e->log2n = l;
-            std::vector<float2> tw(n / 2);
-            for (int k = 0; k < n / 2; ++k) {
-                const double ph = -2.0 * M_PI * k / n;
-                tw[k] = make_float2((float)cos(ph), (float)sin(ph));
-            }
+            // stage-major: stage len (h = len / 2) at offset h - 1, pos < h
+            std::vector<float2> tw(n - 1);
+            for (int h = 1; h < n; h <<= 1)
+                for (int pos = 0; pos < h; ++pos) {
+                    const double ph = -M_PI * pos / h;      // -2 pi pos / len
+                    tw[h - 1 + pos] = make_float2((float)cos(ph), (float)sin(ph));
+                }
             err = hipMalloc(&e->d_tw, tw.size() * sizeof(float2));
             if (err == hipSuccess)
                 err = hipMemcpy(e->d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice);
+            if (err == hipSuccess && e->reg_m) {
+                const int M = e->reg_m;
+                // lane stage twiddles W_{2d}^{l mod d}, d = 32 >> s
+                std::vector<float2> tl(6 * 64), tm((size_t)64 * M);
+                for (int st = 0; st < 6; ++st) {
+                    const int d = 32 >> st;
+                    for (int l = 0; l < 64; ++l) {
+                        const double ph = -M_PI * (l % d) / d;
+                        tl[st * 64 + l] = make_float2((float)cos(ph), (float)sin(ph));
+                    }
+                }
+                // W_N^{r bitrev6(l)}
+                for (int l = 0; l < 64; ++l) {
+                    int br = 0;
+                    for (int b = 0; b < 6; ++b) br |= ((l >> b) & 1) << (5 - b);
+                    for (int r = 0; r < M; ++r) {
+                        const double ph = -2.0 * M_PI * (double)((long)r * br % n) / n;
+                        tm[(size_t)l * M + r] = make_float2((float)cos(ph), (float)sin(ph));
+                    }
+                }
+                for (int j = 0; j < M / 2; ++j) {
+                    const double ph = -2.0 * M_PI * j / M;
+                    e->wm[j] = make_float2((float)cos(ph), (float)sin(ph));
+                }
+                err = hipMalloc(&e->d_tw_lane, tl.size() * sizeof(float2));
+                if (err == hipSuccess) err = hipMalloc(&e->d_tw_mid, tm.size() * sizeof(float2));
+                if (err == hipSuccess)
+                    err = hipMemcpy(e->d_tw_lane, tl.data(), tl.size() * sizeof(float2),
+                                    hipMemcpyHostToDevice);
+                if (err == hipSuccess)
+                    err = hipMemcpy(e->d_tw_mid, tm.data(), tm.size() * sizeof(float2),
+                                    hipMemcpyHostToDevice);
+            }
         } else {
             // q[k] = Im IDFT(h)[k] = (1/N) sum_k' h[k'] sin(2 pi k' k / N)
             std::vector<float> q(n);
@@ -332,6 +516,9 @@ int bf_envelope(bf_env e, const float *img, float *out, int32_t compress, double
     a.img = img;
     a.out = out;
     a.tw = e->d_tw;
+    a.tw_lane = e->d_tw_lane;
+    a.tw_mid = e->d_tw_mid;
+    for (int j = 0; j < 8; ++j) a.wm[j] = e->wm[j];
     a.q = e->d_q;
     a.part_max = e->d_part;
     a.img_max = e->d_part + e->n_parts;
@@ -347,10 +534,19 @@ int bf_envelope(bf_env e, const float *img, float *out, int32_t compress, double
     const unsigned eblocks = (unsigned)std::min<long>((total + 255) / 256, 8192);
     if (e->iq) {
         hipLaunchKernelGGL(env_iq_kernel, dim3(eblocks), dim3(256), 0, s, a);
+    } else if (e->reg_m) {
+        const dim3 g((unsigned)((e->n_cols + 3) / 4)), b(256);
+        switch (e->reg_m) {
+            case 1: hipLaunchKernelGGL(env_fft_reg_kernel<1>, g, b, 0, s, a); break;
+            case 2: hipLaunchKernelGGL(env_fft_reg_kernel<2>, g, b, 0, s, a); break;
+            case 4: hipLaunchKernelGGL(env_fft_reg_kernel<4>, g, b, 0, s, a); break;
+            case 8: hipLaunchKernelGGL(env_fft_reg_kernel<8>, g, b, 0, s, a); break;
+            default: hipLaunchKernelGGL(env_fft_reg_kernel<16>, g, b, 0, s, a); break;
+        }
     } else if (e->log2n > 0) {
         const int T = std::min(256, std::max(64, e->N / 2));
         hipLaunchKernelGGL(env_fft_kernel, dim3((unsigned)e->n_cols), dim3(T),
-                           (size_t)e->N * 8 + (size_t)(e->N / 2) * 8, s, a);
+                           (size_t)e->N * 8, s, a);
     } else {
         hipLaunchKernelGGL(env_direct_kernel, dim3((unsigned)e->n_cols), dim3(256),
                            (size_t)3 * e->N * sizeof(float), s, a);

@@ -39,7 +39,7 @@ def _check_env(got, ref):
     assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("N", [2, 4, 64, 256, 1024, 4096])
+@pytest.mark.parametrize("N", [2, 4, 64, 128, 256, 512, 1024, 2048, 4096])
 def test_envelope_fft_path_matches_oracle(torch_mod, N):
     img = np.random.default_rng(N).normal(size=(5, 3, N)).astype(np.float32)
     got = _env_gpu(torch_mod, img)

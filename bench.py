@@ -219,9 +219,17 @@ def iq_pipeline(torch, bfm, synth, desc, H, rf_d, n_act, reps: int):
     dem_ms, dec_ms, das_ms = (float(v) for v in t.mean(axis=0))
     step = dem_ms + dec_ms + das_ms
     n_out = dm.n_out
-    # demodulation: per output N_f complex-by-real taps (4 flops) + the
-    # rotation (6); HBM: 2 bytes in per input sample, 4 bytes out per output
-    dem_flops = n_tr * n_out * (4 * len(taps) + 6)
+    # demodulation: per output 2 flops per non-zero real or imaginary part of
+    # the mixed taps h[k] exp(j 2 pi r k) (a real filter under quadrature
+    # sampling, r = 1/4, has one non-zero part per tap) + the rotation (6);
+    # HBM: 2 bytes in per input sample, 4 bytes out per output
+    r = desc["fc"] / desc["fs"]
+    q = 4.0 * ((r * np.arange(len(taps))) % 1.0)
+    quarter = np.abs(q - np.round(q)) < 1e-12
+    mix = np.where(quarter, 1j ** np.round(q), np.exp(2j * np.pi * q / 4.0))
+    g = np.asarray(taps) * mix
+    parts = int(np.count_nonzero(np.abs(g.real) > 0) + np.count_nonzero(np.abs(g.imag) > 0))
+    dem_flops = n_tr * n_out * (2 * parts + 6)
     dem_bytes = n_tr * (2 * desc["n_samples"] + 4 * n_out)
     dem_tf = dem_flops / (dem_ms * 1e-3) / 1e12
     # IQ term: delay 13, apodization 14, two cubic reads 32, phase 2, sin+cos

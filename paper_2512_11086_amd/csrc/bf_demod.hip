@@ -8,8 +8,12 @@
 // (the mix factors as exp(-j 2 pi r n) exp(j 2 pi r k)), so each tap is one
 // complex-by-real product (2 FMAs) on the raw samples and the output is rotated
 // once.  g and the per-output rotation exp(-j 2 pi r q D) are computed on the
-// host in FP64 and rounded to FP32.  Only the kept outputs q D are computed
-// (decimation, Sec. VII-C: as early as possible, after the low-pass).
+// host in FP64 (quarter turns exactly) and rounded to FP32.  Only the kept
+// outputs q D are computed (decimation, Sec. VII-C: as early as possible,
+// after the low-pass).  With quadrature sampling (fs = 4 fd, Sec. IV-B) and a
+// real filter, g[k] = h[k] j^k: every polyphase component of an even
+// decimation is purely real or purely imaginary, and the kernel then spends
+// one FMA per tap on it instead of two.
 //
 // A workgroup of T threads owns 4 T consecutive outputs of one trace.  It
 // stages the input span they read (converted to FP32 once, zeros before the
@@ -44,7 +48,10 @@ struct DemodArgs {
     int n_traces, S, n_out, D, n_taps;
     int chunks;           // workgroups per trace
     int phase_len;        // LDS words per polyphase component (multiple of 4)
+    int kind[16];         // per component: 0 complex taps, 1 real only, 2 imaginary only
 };
+
+enum { TAPS_COMPLEX = 0, TAPS_REAL = 1, TAPS_IMAG = 2 };
 
 __device__ inline int16_t sat_i16(float v)
 {
@@ -107,17 +114,34 @@ __global__ __launch_bounds__(T) void demod_kernel(DemodArgs a)
     for (int ph = 0; ph < a.D; ++ph) {
         const int nb4 = phase_taps4(a.n_taps, a.D, ph);
         const float4 *wp = xs4 + (ph * a.phase_len) / 4 + t;   // words tM .. (M = 4)
+        const int kind = a.kind[ph];                           // uniform
         float4 lo = wp[0];
         for (int b = 0; b < nb4; b += 4) {
             const float4 hi = wp[b / 4 + 1];
             const float w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+            if (kind == TAPS_REAL) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const float2 gk = gp[b + u];
+                for (int u = 0; u < 4; ++u) {
+                    const float g = gp[b + u].x;
 #pragma unroll
-                for (int m = 0; m < DEMOD_M; ++m) {
-                    ar[m] = fmaf(gk.x, w[u + m], ar[m]);
-                    ai[m] = fmaf(gk.y, w[u + m], ai[m]);
+                    for (int m = 0; m < DEMOD_M; ++m) ar[m] = fmaf(g, w[u + m], ar[m]);
+                }
+            } else if (kind == TAPS_IMAG) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float g = gp[b + u].y;
+#pragma unroll
+                    for (int m = 0; m < DEMOD_M; ++m) ai[m] = fmaf(g, w[u + m], ai[m]);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float2 gk = gp[b + u];
+#pragma unroll
+                    for (int m = 0; m < DEMOD_M; ++m) {
+                        ar[m] = fmaf(gk.x, w[u + m], ar[m]);
+                        ai[m] = fmaf(gk.y, w[u + m], ai[m]);
+                    }
                 }
             }
             lo = hi;
@@ -178,6 +202,7 @@ struct bf_demod_s {
     uint32_t magic = 0xBFDE0D01u;
     bf_demod_params p;
     int n_out = 0;
+    int kind[16];
     float2 *d_g = nullptr;
     float2 *d_rot = nullptr;
     ~bf_demod_s()
@@ -210,11 +235,19 @@ static int validate_demod(const bf_demod_params *p)
     return BF_OK;
 }
 
-// exp(j 2 pi f) with f reduced to [0, 1) in FP64 first
-static float2 cis_rev(double f)
+// exp(j 2 pi f) in FP64 with f reduced to [0, 1); quarter turns exactly
+static void cis_rev(double f, double *c, double *s)
 {
     f -= floor(f);
-    return make_float2((float)cos(2.0 * M_PI * f), (float)sin(2.0 * M_PI * f));
+    const double q = 4.0 * f;
+    if (q == floor(q)) {
+        static const double cq[4] = {1.0, 0.0, -1.0, 0.0}, sq[4] = {0.0, 1.0, 0.0, -1.0};
+        *c = cq[(int)q & 3];
+        *s = sq[(int)q & 3];
+        return;
+    }
+    *c = cos(2.0 * M_PI * f);
+    *s = sin(2.0 * M_PI * f);
 }
 
 extern "C" {
@@ -246,21 +279,30 @@ int bf_demod_create(const bf_demod_params *params, bf_demod *out)
     d->n_out = (params->n_samples + D - 1) / D;
     const double r = params->fd / params->fs;
     std::vector<float2> g, rot(d->n_out);
+    for (int ph = 0; ph < 16; ++ph) d->kind[ph] = TAPS_COMPLEX;
     // g[k] = h[k] exp(j 2 pi r k) in FP64, stored in the kernel's read order:
     // component ph = 0 .. D-1, then k = N-1-ph, N-1-ph-D, ... >= 0, each
     // component padded with zero taps to a multiple of 4
     for (int ph = 0; ph < D; ++ph) {
         const size_t start = g.size();
+        bool all_re = true, all_im = true;
         for (int k = N - 1 - ph; k >= 0; k -= D) {
             const double hr = params->taps_re[k], hi = params->taps_im ? params->taps_im[k] : 0.0;
-            double f = r * k;
-            f -= floor(f);
-            const double c = cos(2.0 * M_PI * f), s = sin(2.0 * M_PI * f);
-            g.push_back(make_float2((float)(hr * c - hi * s), (float)(hr * s + hi * c)));
+            double c, s;
+            cis_rev(r * k, &c, &s);
+            const double gr = hr * c - hi * s, gi = hr * s + hi * c;
+            all_re = all_re && gi == 0.0;
+            all_im = all_im && gr == 0.0;
+            g.push_back(make_float2((float)gr, (float)gi));
         }
         g.resize(start + phase_taps4(N, D, ph), make_float2(0.f, 0.f));
+        d->kind[ph] = all_re ? TAPS_REAL : all_im ? TAPS_IMAG : TAPS_COMPLEX;
     }
-    for (int q = 0; q < d->n_out; ++q) rot[q] = cis_rev(-r * (double)q * D);
+    for (int q = 0; q < d->n_out; ++q) {
+        double c, s;
+        cis_rev(-r * (double)q * D, &c, &s);
+        rot[q] = make_float2((float)c, (float)s);
+    }
     hipError_t e;
     if ((e = hipMalloc(&d->d_g, g.size() * sizeof(float2))) != hipSuccess ||
         (e = hipMalloc(&d->d_rot, d->n_out * sizeof(float2))) != hipSuccess ||
@@ -317,6 +359,7 @@ int bf_demodulate(bf_demod d, const int16_t *rf, void *iq, void *stream)
     for (int ph = 0; ph < a.D; ++ph) nb4max = std::max(nb4max, phase_taps4(a.n_taps, a.D, ph));
     const int T = (a.D * (256 * DEMOD_M + nb4max + 4) * 4 <= 48 * 1024) ? 256 : 64;
     a.chunks = (d->n_out + T * DEMOD_M - 1) / (T * DEMOD_M);
+    for (int ph = 0; ph < 16; ++ph) a.kind[ph] = d->kind[ph];
     a.phase_len = T * DEMOD_M + nb4max + 4;
     const size_t shm = (size_t)a.D * a.phase_len * sizeof(float);
     const long blocks = (long)a.n_traces * a.chunks;

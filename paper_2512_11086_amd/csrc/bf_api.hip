@@ -231,8 +231,8 @@ int Frame::init(const bf_params &src)
     // Default DAS workgroups (fastest in measured sweeps on MI355X; the
     // autotuner can replace them): 2D = the direct-gather kernel on 16x4-point
     // wavefront tiles; 3D = LDS windows, flat 8x8x1 tiles in a 2x2x3 block
-    // (12 wavefronts: two such workgroups fill a CU at the kernel's register
-    // count).
+    // (12 wavefronts: two such workgroups fill a CU's LDS) with 40 traces per
+    // staged batch.
     if (p.mode == BF_FORCES_2D && (grid.ny == 1 || grid.nx == 1)) {
         // a plane: 16 x 4 points per wavefront along its lateral axis and depth
         if (grid.ny == 1) set_tile(4, 0, 2); else set_tile(0, 4, 2);
@@ -249,11 +249,11 @@ int Frame::init(const bf_params &src)
         // 8-wavefront workgroups per CU
         set_tile(3, 3, 0);
         bw[0] = 4; bw[1] = 2; bw[2] = 1;
-        nb = 16;
+        nb = 24;
     } else {
         set_tile(3, 3, 0);
         bw[0] = 2; bw[1] = 2; bw[2] = 3;
-        nb = 32;
+        nb = 40;
     }
     sorted_tx = 1;
     for (int i = 1; i < n; ++i)
@@ -419,22 +419,34 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
     double E[3];
     for (int r = 0; r < 3; ++r)
         E[r] = fabs(grid.ax[r]) * (tx - 1) + fabs(grid.ay[r]) * (ty - 1) + fabs(grid.az[r]) * (tz - 1);
-    // Bound on the spread of the sample position over the box: the delay
-    // grows with depth (2 dz on the round trip) and with lateral distance
-    // (one receive path for HERCULES, transmit and receive for FORCES).
-    // A diverging transmit path changes by at most the box diagonal.
+    // Bound on the spread of the sample position over the box for the points
+    // that contribute (apodization > 0): the delay grows with depth (2 dz on
+    // the round trip) and with lateral distance.  The receive path
+    // sqrt(rho^2 + z^2) changes with the lateral offset at rate
+    // rho / d <= 1 / sqrt(1 + 4 F#^2) inside the receive aperture
+    // (F# rho / z < 1/2); points outside it have weight 0 and read a clamped
+    // index.  Transmit paths are not apodized: rate 1 (FORCES column
+    // cylinder), and a diverging wave changes by at most the box diagonal.
     const double lat = sqrt(E[0] * E[0] + E[1] * E[1]);
-    const double spread = p.mode == BF_FORCES_2D ? 2.0 * E[2] + 2.0 * E[0]
-                          : a.div_f > 0.0 ? E[2] + lat + sqrt(lat * lat + E[2] * E[2])
-                                          : 2.0 * E[2] + lat;
-    const int lmax = (int)ceil(a.k * spread) + 8;
+    const double srx = p.f_number > 0.0 ? 1.0 / sqrt(1.0 + 4.0 * p.f_number * p.f_number) : 1.0;
+    const double spread = p.mode == BF_FORCES_2D ? 2.0 * E[2] + (1.0 + srx) * E[0]
+                          : a.div_f > 0.0 ? E[2] + srx * lat + sqrt(lat * lat + E[2] * E[2])
+                                          : 2.0 * E[2] + srx * lat;
+    // Window of an active point: its quad index floor(s) - w0 lies in
+    // [1, k spread + 3] (the start w0 is floored 2 samples below the box's
+    // lowest path, the quad covers taps n-1 .. n+2); one quad of FP32 slack.
+    const int lmax = (int)ceil(a.k * spread) + 5;
     const int nthr = 64 * bw[0] * bw[1] * bw[2];
     int nbb = nb;
     const int unit = p.mode == BF_FORCES_2D ? 4 : 1;
     const size_t lds_cap = 60 * 1024;   // dynamic LDS without the large-LDS attribute
     const int nwaves = nthr / 64;
-    // staging rounds per thread: ceil(nb / waves) traces x ceil(lmax / 64) quads <= 2
-    auto rounds = [&](int n) { return ((n + nwaves - 1) / nwaves) * ((lmax + 63) / 64); };
+    const int tpw = lmax <= 32 ? 2 : 1;
+    // staging rounds per thread: traces per wavefront round x quads <= 2
+    auto rounds = [&](int n) {
+        return tpw == 2 ? (n + 2 * nwaves - 1) / (2 * nwaves)
+                        : ((n + nwaves - 1) / nwaves) * ((lmax + 63) / 64);
+    };
     const int qs = p.iq ? 2 : 1;
     while (nbb >= unit &&
            (rounds(nbb) > 2 || lds_bytes(p.n_tx, p.n_ch, nbb, lmax, qs) > lds_cap))
@@ -449,6 +461,7 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
     cfg->uniform_tx = uniform_tx;
     cfg->tx_x0 = tx_x0;
     cfg->tx_inv_dx = tx_inv_dx;
+    cfg->tpw = tpw;
     cfg->blocks_x = (grid.nx + tx - 1) / tx;
     cfg->blocks_y = (grid.ny + ty - 1) / ty;
     cfg->blocks_z = (grid.nz + tz - 1) / tz;

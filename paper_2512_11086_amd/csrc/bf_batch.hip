@@ -350,7 +350,7 @@ std::vector<TileCand> candidates(const Frame &f)
         for (auto &t : tiles) {
             c.push_back({t[0], t[1], t[2], 1, 1, 1, 4, BF_DAS_GATHER});
             for (auto &b : blocks)
-                for (int nb : {8, 16, 32})
+                for (int nb : {8, 16, 24, 32, 40})
                     c.push_back({t[0], t[1], t[2], b[0], b[1], b[2], nb, BF_DAS_LDS});
         }
     }

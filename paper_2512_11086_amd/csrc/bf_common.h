@@ -110,6 +110,8 @@ struct LdsCfg {
     int blocks_x, blocks_y, blocks_z;
     int uniform_tx;      // tx_x[i] = tx_x0 + i * tx_dx exactly (range by arithmetic)
     float tx_x0, tx_inv_dx;
+    int tpw;             // traces staged per wavefront round: 2 when lmax <= 32 (half
+                         // a wavefront per window), else 1
 };
 
 // One frame of a batch for the persistent DAS kernel (device table entry).

@@ -310,7 +310,9 @@ constexpr int QMAX = 2;   // staging rounds per thread per batch (host guarantee
 // Staging map: trace slot e of a batch is staged by wavefront e % W in round
 // e / W; lane m loads quad m (and m + 64 ... when the window is longer), so
 // the window start is computed once per (wavefront, trace) and consecutive
-// lanes read consecutive samples.
+// lanes read consecutive samples.  Windows of at most 32 quads are staged two
+// per wavefront round (lanes 0-31 and 32-63), which halves the staging
+// instructions.
 struct Staged {
     float p[QMAX][8];    // taps n-1 .. n+2 (IQ: (re, im) of each)
     int w0[QMAX];
@@ -318,21 +320,35 @@ struct Staged {
 
 __device__ inline int stage_rounds_m(const LdsCfg &c) { return (c.lmax + 63) >> 6; }
 
+// Slot e and quad m handled by this lane in staging round q; false if none.
+__device__ inline bool stage_slot(const LdsCfg &c, int q, int wave, int lane, int nwaves, int *e,
+                                  int *m)
+{
+    if (c.tpw == 2) {
+        *e = 2 * (wave + q * nwaves) + (lane >> 5);
+        *m = lane & 31;
+        return q < (c.nb + 2 * nwaves - 1) / (2 * nwaves) && *e < c.nb;
+    }
+    const int mr = stage_rounds_m(c);
+    *e = wave + (q / mr) * nwaves;
+    *m = lane + 64 * (q % mr);
+    return q < mr * ((c.nb + nwaves - 1) / nwaves) && *e < c.nb;
+}
+
 // Issue the global loads of a batch's windows (taps n-1..n+2 of every quad).
 template <int MODE, int ET>
 __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const BoxGeom &b,
                                   const float *s_tx, const float *s_rx, const BatchDesc &d,
                                   Staged &st, int wave, int lane, int nwaves)
 {
-    const int mr = stage_rounds_m(c);
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-        const int e = wave + (q / mr) * nwaves;
-        const int m = lane + 64 * (q % mr);
+        int e, m;
+        const bool on = stage_slot(c, q, wave, lane, nwaves, &e, &m);
         float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
         float p4 = 0.f, p5 = 0.f, p6 = 0.f, p7 = 0.f;
         int w0 = 0;
-        if (q < mr * ((c.nb + nwaves - 1) / nwaves) && e < c.nb) {
+        if (on) {
             int i, j;
             slot_trace<MODE>(d, c, e, &i, &j);
             if (j >= 0) {
@@ -414,12 +430,10 @@ __device__ inline void stage_store(const LdsCfg &c, const float *s_tx, const Bat
                                    const Staged &st, float4 *quads, Meta *meta, int wave,
                                    int lane, int nwaves)
 {
-    const int mr = stage_rounds_m(c);
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-        const int e = wave + (q / mr) * nwaves;
-        const int m = lane + 64 * (q % mr);
-        if (q < mr * ((c.nb + nwaves - 1) / nwaves) && e < c.nb) {
+        int e, m;
+        if (stage_slot(c, q, wave, lane, nwaves, &e, &m)) {
             if (m < c.lmax) {
                 const float *t = st.p[q];
                 quads[(e * c.lmax + m) * QS] = coef_quad<IP>(t[0], t[1], t[2], t[3]);

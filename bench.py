@@ -89,6 +89,7 @@ def cpu_baseline(desc, H, rf, budget_s: float):
                        f"({t_das:.1f} s), scaled to one volume"), e, vox, ref
 
 
+VARIANT_NAMES = {0: "lds", 1: "gather", 2: "lds2"}
 KERNEL_SOURCES = ("paper_2512_11086_amd/csrc/bf_das_lds.hip", "paper_2512_11086_amd/csrc/bf_common.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "das_hercules_128x128x256_traffic.json")
 
@@ -315,7 +316,7 @@ def n4_workloads(torch, bfm, synth, reps: int = 2):
         res[name] = {"n_tx": desc["n_tx"], "decode_ms": round(dec_ms, 4),
                      "das_ms": round(das_ms, 3),
                      "value": round(nominal / ((dec_ms + das_ms) * 1e-3) / 1e9, 2),
-                     "unit": "G samples/s", "variant": "lds" if plan.info()["variant"] == 0 else "gather",
+                     "unit": "G samples/s", "variant": VARIANT_NAMES[plan.info()["variant"]],
                      "roofline": {"bound": "alu", "achieved": round(tf, 2),
                                   "peak": round(FP32_NONPACKED_TFLOPS, 1), "unit": "TFLOP/s",
                                   "frac": round(tf / FP32_NONPACKED_TFLOPS, 4)}}

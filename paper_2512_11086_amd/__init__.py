@@ -19,7 +19,7 @@ import math
 import numpy as np
 
 from ._lib import (BfError, COMPRESS, DECODE_ALGOS, DemodParams, ETYPES, INTERPS, IQ_TYPES, MODES,
-                   Params, PlanInfo, check, lib)
+                   Params, PlanInfo, VARIANTS, check, lib)
 
 __all__ = ["BfError", "Plan", "BatchPlan", "Demod", "Envelope", "params_from_desc", "sharpness",
            "validate", "hann_poly"]
@@ -139,7 +139,10 @@ class Plan:
         check(lib().bf_set_tile(self._h, lx, ly, lz))
 
     def set_das_config(self, variant: str = "lds", block=(4, 4, 1), nb: int = 16):
-        v = {"lds": 0, "gather": 1}[variant]
+        """variant: "lds" (LDS-staged windows), "gather" (direct gather) or
+        "lds2" (LDS windows, two adjacent depth points per lane; HERCULES
+        plans with real data)."""
+        v = VARIANTS[variant]
         check(lib().bf_set_das_config(self._h, v, *[int(b) for b in block], int(nb)))
 
     def autotune(self, cache_path: str | None = None):
@@ -335,6 +338,11 @@ class BatchPlan:
 
     def autotune(self, cache_path: str | None = None):
         check(lib().bf_autotune(self._h, cache_path.encode() if cache_path else None))
+
+    def set_das_config(self, variant: str = "lds", block=(4, 4, 1), nb: int = 16):
+        """As Plan.set_das_config, for every frame (before the first launch)."""
+        check(lib().bf_set_das_config(self._h, VARIANTS[variant], *[int(b) for b in block],
+                                      int(nb)))
 
 
 def sharpness(img, grad: bool = True, stream=None):

@@ -122,3 +122,4 @@ EXPORTED = ("bf_abi_version", "bf_last_error", "bf_validate", "bf_plan_create",
             "bf_demod_destroy", "bf_demod_out_samples", "bf_demodulate", "bf_env_create",
             "bf_env_destroy", "bf_envelope")
 COMPRESS = {"none": 0, "log": 1, "power": 2}
+VARIANTS = {"lds": 0, "gather": 1, "lds2": 2}   # BF_DAS_LDS, BF_DAS_GATHER, BF_DAS_LDS_Z2

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -230,8 +231,9 @@ int Frame::init(const bf_params &src)
     grid.nz = p.out_dims[2];
     // Default DAS workgroups (fastest in measured sweeps on MI355X; the
     // autotuner can replace them): 2D = the direct-gather kernel on 16x4-point
-    // wavefront tiles; 3D = LDS windows, flat 8x8x1 tiles in a 2x2x3 block
-    // (12 wavefronts: two such workgroups fill a CU's LDS) with 40 traces per
+    // wavefront tiles; HERCULES volumes = LDS windows, flat 8x8x1 lane tiles
+    // with two depth points per lane in a 2x2x3 block (12 wavefronts,
+    // 16x16x6 points: two such workgroups fill a CU's LDS) with 40 traces per
     // staged batch.
     if (p.mode == BF_FORCES_2D && (grid.ny == 1 || grid.nx == 1)) {
         // a plane: 16 x 4 points per wavefront along its lateral axis and depth
@@ -254,6 +256,7 @@ int Frame::init(const bf_params &src)
         set_tile(3, 3, 0);
         bw[0] = 2; bw[1] = 2; bw[2] = 3;
         nb = 40;
+        if (p.mode == BF_HERCULES_3D && grid.nz >= 2) variant = BF_DAS_LDS_Z2;
     }
     sorted_tx = 1;
     for (int i = 1; i < n; ++i)
@@ -412,10 +415,27 @@ int Frame::decode(const int16_t *rf, void *e, hipStream_t s) const
 // Workgroup box, staged-window length and batch size of the LDS kernel for
 // this frame at the sound speed of `a`; false if the window would not fit
 // (the direct-gather kernel is used then).
+// Dynamic LDS of one workgroup: the device's per-block limit, at most 80 KiB
+// so that two workgroups share a CU's 160 KiB.
+static size_t lds_cap_bytes()
+{
+    static const size_t cap = [] {
+        int dev = 0, v = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+            v <= 0)
+            v = 64 * 1024;
+        return std::min<size_t>((size_t)v, 80 * 1024);
+    }();
+    return cap;
+}
+
 bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
 {
     if (p.mode != BF_FORCES_2D && p.mode != BF_HERCULES_3D) return false;   // gather only
-    const int tx = bw[0] << lx, ty = bw[1] << ly, tz = bw[2] << lz;
+    // points per lane along z: two for the HERCULES real-data variant
+    const int zp = variant == BF_DAS_LDS_Z2 && z2_ok() ? 2 : 1;
+    const int tx = bw[0] << lx, ty = bw[1] << ly, tz = (bw[2] << lz) * zp;
     double E[3];
     for (int r = 0; r < 3; ++r)
         E[r] = fabs(grid.ax[r]) * (tx - 1) + fabs(grid.ay[r]) * (ty - 1) + fabs(grid.az[r]) * (tz - 1);
@@ -439,17 +459,15 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
     const int nthr = 64 * bw[0] * bw[1] * bw[2];
     int nbb = nb;
     const int unit = p.mode == BF_FORCES_2D ? 4 : 1;
-    const size_t lds_cap = 60 * 1024;   // dynamic LDS without the large-LDS attribute
+    const size_t lds_cap = lds_cap_bytes();
     const int nwaves = nthr / 64;
-    const int tpw = lmax <= 32 ? 2 : 1;
-    // staging rounds per thread: traces per wavefront round x quads <= 2
-    auto rounds = [&](int n) {
-        return tpw == 2 ? (n + 2 * nwaves - 1) / (2 * nwaves)
-                        : ((n + nwaves - 1) / nwaves) * ((lmax + 63) / 64);
-    };
+    // staging rounds per thread: the batch's quads dealt over the workgroup's
+    // threads; the kernels unroll 2 rounds (3 with two points per lane)
+    const int max_rounds = zp == 2 ? 3 : 2;
+    auto rounds = [&](int n) { return (n * lmax + 64 * nwaves - 1) / (64 * nwaves); };
     const int qs = p.iq ? 2 : 1;
     while (nbb >= unit &&
-           (rounds(nbb) > 2 || lds_bytes(p.n_tx, p.n_ch, nbb, lmax, qs) > lds_cap))
+           (rounds(nbb) > max_rounds || lds_bytes(p.n_tx, p.n_ch, nbb, lmax, qs) > lds_cap))
         nbb -= unit;
     if (nbb < unit || nthr > 1024) return false;
     cfg->bwx = bw[0];
@@ -461,11 +479,19 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
     cfg->uniform_tx = uniform_tx;
     cfg->tx_x0 = tx_x0;
     cfg->tx_inv_dx = tx_inv_dx;
-    cfg->tpw = tpw;
+    cfg->inv_lmax = 1.0f / (float)lmax;
+    cfg->zp = zp;
     cfg->blocks_x = (grid.nx + tx - 1) / tx;
     cfg->blocks_y = (grid.ny + ty - 1) / ty;
     cfg->blocks_z = (grid.nz + tz - 1) / tz;
     return true;
+}
+
+// Two points per lane share their lateral offset to every receiver: HERCULES
+// with real data, and the grid's depth axis along the array normal.
+bool Frame::z2_ok() const
+{
+    return p.mode == BF_HERCULES_3D && !p.iq && grid.az[0] == 0.0 && grid.az[1] == 0.0;
 }
 
 int Frame::das(const void *e, float *out, double c, hipStream_t s) const
@@ -473,7 +499,7 @@ int Frame::das(const void *e, float *out, double c, hipStream_t s) const
     const DasArgs a = das_args(e, out, c);
     LdsCfg cfg;
     hipError_t err;
-    if (variant == 0 && lds_config(a, &cfg))
+    if (variant != BF_DAS_GATHER && lds_config(a, &cfg))
         err = launch_das_lds(a, cfg, p.mode, das_et(), p.interp, s);
     else
         err = launch_das(a, p.mode, das_et(), p.interp, s);
@@ -573,8 +599,9 @@ int bf_plan_get_info(bf_plan plan, bf_plan_info *info)
     {
         // the kernel bf_das actually runs (LDS windows may not fit: gather)
         LdsCfg cfg;
-        info->variant = (f.variant == BF_DAS_LDS && f.lds_config(f.das_args(nullptr, nullptr, f.p.c), &cfg))
-                            ? BF_DAS_LDS
+        info->variant = (f.variant != BF_DAS_GATHER &&
+                         f.lds_config(f.das_args(nullptr, nullptr, f.p.c), &cfg))
+                            ? (cfg.zp == 2 ? BF_DAS_LDS_Z2 : BF_DAS_LDS)
                             : BF_DAS_GATHER;
     }
     info->block[0] = f.bw[0];
@@ -608,7 +635,8 @@ int bf_set_das_config(bf_plan plan, int32_t variant, int32_t bw_x, int32_t bw_y,
     g_err.clear();
     int st = check_plan(plan);
     if (st != BF_OK) return st;
-    if (variant != BF_DAS_LDS && variant != BF_DAS_GATHER)
+    if (plan->batch) return fail(BF_ERR_STATE, "DAS configuration before the first batched launch");
+    if (variant != BF_DAS_LDS && variant != BF_DAS_GATHER && variant != BF_DAS_LDS_Z2)
         return fail(BF_ERR_UNSUPPORTED, "unknown DAS variant %d", variant);
     if (bw_x < 1 || bw_y < 1 || bw_z < 1 || bw_x * bw_y * bw_z > 16)
         return fail(BF_ERR_SHAPE, "workgroup must hold 1..16 wavefront tiles");
@@ -616,6 +644,9 @@ int bf_set_das_config(bf_plan plan, int32_t variant, int32_t bw_x, int32_t bw_y,
     for (Frame *f : plan->frames) {
         if (f->p.mode == BF_FORCES_2D && f->grid.ny == 1 && bw_y != 1)
             return fail(BF_ERR_SHAPE, "a 2D plan needs bw_y = 1");
+        if (variant == BF_DAS_LDS_Z2 && (f->p.mode != BF_HERCULES_3D || f->p.iq))
+            return fail(BF_ERR_UNSUPPORTED,
+                        "two depth points per lane: HERCULES plans with real data only");
     }
     for (Frame *f : plan->frames) {
         f->variant = variant;

@@ -26,7 +26,7 @@ namespace bf {
 
 hipError_t launch_decode_persistent(const DecLaunch &p, hipStream_t s);
 hipError_t launch_das_persistent(const PersistentLaunch &p, hipStream_t s);
-int persistent_das_blocks(int mode, int et, int ip, int threads, size_t shm);
+int persistent_das_blocks(int mode, int et, int ip, int zp, int threads, size_t shm);
 hipError_t launch_fill(float *p, long n, float v, hipStream_t s);
 
 __global__ void reset_counters_kernel(int *c, int n)
@@ -42,7 +42,7 @@ struct DecClass {
 };
 
 struct DasClass {
-    int mode, et, ip, threads;
+    int mode, et, ip, zp, threads;
     size_t shm = 0;
     std::vector<std::pair<double, int2>> items;   // (cost, item)
     int2 *d_items = nullptr;
@@ -108,7 +108,7 @@ static int build_batch(bf_plan plan)
         a.groups = 1;
         a.part = nullptr;
         LdsCfg c;
-        if (fr.variant != 0 || !fr.lds_config(a, &c)) {
+        if (fr.variant == BF_DAS_GATHER || !fr.lds_config(a, &c)) {
             b->gather_frames.push_back(f);
             memset(&c, 0, sizeof c);
         } else {
@@ -117,13 +117,14 @@ static int build_batch(bf_plan plan)
             DasClass *cls = nullptr;
             for (DasClass &d : b->das)
                 if (d.mode == fr.p.mode && d.et == fr.p.e_type && d.ip == fr.p.interp &&
-                    d.threads == threads)
+                    d.zp == c.zp && d.threads == threads)
                     cls = &d;
             if (!cls) {
                 DasClass d;
                 d.mode = fr.p.mode;
                 d.et = fr.p.e_type;
                 d.ip = fr.p.interp;
+                d.zp = c.zp;
                 d.threads = threads;
                 b->das.push_back(d);
                 cls = &b->das.back();
@@ -190,7 +191,7 @@ static int build_batch(bf_plan plan)
         if ((e = hipMemcpy(d.d_items, it.data(), sizeof(int2) * it.size(), hipMemcpyHostToDevice)) !=
             hipSuccess)
             return hip_fail(e, "batch item upload");
-        d.grid = std::min(d.n_items, persistent_das_blocks(d.mode, d.et, d.ip, d.threads, d.shm));
+        d.grid = std::min(d.n_items, persistent_das_blocks(d.mode, d.et, d.ip, d.zp, d.threads, d.shm));
     }
     for (int k = 0; k < RING; ++k) {
         if ((e = hipHostMalloc((void **)&b->h_stage[k], sizeof(void *) * 2 * F)) != hipSuccess)
@@ -247,6 +248,7 @@ static int enqueue(bf_plan plan, hipStream_t s)
         L.mode = d.mode;
         L.et = d.et;
         L.ip = d.ip;
+        L.zp = d.zp;
         L.grid = d.grid;
         L.threads = d.threads;
         L.shm = d.shm;
@@ -347,11 +349,18 @@ std::vector<TileCand> candidates(const Frame &f)
     } else {
         const int tiles[][3] = {{3, 3, 0}, {2, 3, 1}, {2, 2, 2}};
         const int blocks[][3] = {{2, 2, 3}, {2, 2, 2}, {4, 2, 1}, {3, 2, 2}, {2, 3, 2}, {2, 2, 1}};
+        // two depth points per lane (HERCULES, real data): boxes twice as deep
+        const bool z2 = f.p.mode == BF_HERCULES_3D && !f.p.iq && f.grid.nz >= 2;
+        const int blocks2[][3] = {{2, 2, 3}, {2, 2, 2}, {4, 2, 1}, {2, 2, 1}, {3, 2, 2}};
         for (auto &t : tiles) {
             c.push_back({t[0], t[1], t[2], 1, 1, 1, 4, BF_DAS_GATHER});
             for (auto &b : blocks)
                 for (int nb : {8, 16, 24, 32, 40})
                     c.push_back({t[0], t[1], t[2], b[0], b[1], b[2], nb, BF_DAS_LDS});
+            if (z2)
+                for (auto &b : blocks2)
+                    for (int nb : {16, 24, 32, 40})
+                        c.push_back({t[0], t[1], t[2], b[0], b[1], b[2], nb, BF_DAS_LDS_Z2});
         }
     }
     return c;
@@ -492,7 +501,7 @@ int bf_autotune(bf_plan plan, const char *cache_path)
                 f0->nb = t.nb;
                 f0->variant = t.variant;
                 LdsCfg cfg;
-                if (t.variant == BF_DAS_LDS &&
+                if (t.variant != BF_DAS_GATHER &&
                     !f0->lds_config(f0->das_args(e_buf, o_buf, f0->p.c), &cfg))
                     continue;
                 if (f0->das(e_buf, o_buf, f0->p.c, 0) != BF_OK) continue;   // warm-up

@@ -110,8 +110,8 @@ struct LdsCfg {
     int blocks_x, blocks_y, blocks_z;
     int uniform_tx;      // tx_x[i] = tx_x0 + i * tx_dx exactly (range by arithmetic)
     float tx_x0, tx_inv_dx;
-    int tpw;             // traces staged per wavefront round: 2 when lmax <= 32 (half
-                         // a wavefront per window), else 1
+    float inv_lmax;      // 1 / lmax (staging: quad number -> (trace, quad))
+    int zp;              // output points per lane along z (1, or 2 for HERCULES real data)
 };
 
 // One frame of a batch for the persistent DAS kernel (device table entry).
@@ -121,7 +121,7 @@ struct FrameDas {
 };
 
 struct PersistentLaunch {
-    int mode, et, ip;
+    int mode, et, ip, zp;
     int grid, threads;
     size_t shm;
     const FrameDas *frames;

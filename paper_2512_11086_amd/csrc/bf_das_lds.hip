@@ -12,6 +12,11 @@
 // beamformed (double-buffered LDS, one barrier per batch), and they read
 // contiguous runs along fast time.
 //
+// HERCULES volumes with real data can give each lane two adjacent depth
+// points (ZP = 2): both share the lateral offset to the receiver, rho^2 and
+// the per-trace scalars of every term, and each wavefront's per-batch work
+// (aperture mask, trace metadata) serves twice the points.
+//
 // Apodization skip (Sec. VII-F): a channel row is staged only if the receive
 // aperture of the deepest point of the box reaches it; within a row only the
 // transmits whose lateral offset can fall inside that aperture are staged
@@ -72,40 +77,50 @@ __device__ inline float uniform_f(float v)
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-// Lane state with benign values for points outside the grid or at z <= 0
-// (never active, finite arithmetic).
+// Lane state.  A point outside the grid or at z <= 0 keeps the lane's real
+// lateral position (a lane's points share it) and benign depth values: it
+// is never inside the aperture mask, its arithmetic stays finite, and its
+// sum is discarded (outside the grid) or replaced by 0 (z <= 0, where the
+// apodization vanishes) when the outputs are stored.
 struct LaneL {
     bool valid;
-    long out_idx;
     float x, y, z, z2, thr, wsc, fB;
     float wtab;     // u^2 * 4 HANN_N = rho^2 * wtab (table coordinate)
     int nB;
     float ph0;      // IQ: carrier phase of sample position nB (revolutions)
 };
 
-__device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, int by, int bz,
-                                     int wave, int lane)
+// Grid indices of point p (0 .. zp-1) of a lane: the lane's z tile index
+// times zp plus p, so a lane's points are adjacent along z.
+__device__ inline void lane_point(const DasArgs &a, const LdsCfg &c, int bx, int by, int bz,
+                                  int wave, int lane, int p, int *ix, int *iy, int *iz)
 {
-    LaneL L;
     const int wz = wave % c.bwz, wx = (wave / c.bwz) % c.bwx, wy = wave / (c.bwz * c.bwx);
     const int lz = lane & ((1 << a.lz) - 1);
     const int lx = (lane >> a.lz) & ((1 << a.lx) - 1);
     const int ly = lane >> (a.lz + a.lx);
-    const int ix = ((bx * c.bwx + wx) << a.lx) + lx;
-    const int iy = ((by * c.bwy + wy) << a.ly) + ly;
-    const int iz = ((bz * c.bwz + wz) << a.lz) + lz;
+    *ix = ((bx * c.bwx + wx) << a.lx) + lx;
+    *iy = ((by * c.bwy + wy) << a.ly) + ly;
+    *iz = (((bz * c.bwz + wz) << a.lz) + lz) * c.zp + p;
+}
+
+__device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, int by, int bz,
+                                     int wave, int lane, int p)
+{
+    LaneL L;
+    int ix, iy, iz;
+    lane_point(a, c, bx, by, bz, wave, lane, p, &ix, &iy, &iz);
     L.valid = ix < a.g.nx && iy < a.g.ny && iz < a.g.nz;
-    L.out_idx = ((long)iy * a.g.nx + ix) * a.g.nz + iz;
     const double px = a.g.org[0] + ix * a.g.ax[0] + iy * a.g.ay[0] + iz * a.g.az[0];
     const double py = a.g.org[1] + ix * a.g.ax[1] + iy * a.g.ay[1] + iz * a.g.az[1];
     const double pz = a.g.org[2] + ix * a.g.ax[2] + iy * a.g.ay[2] + iz * a.g.az[2];
+    L.x = (float)px;
+    L.y = (float)py;
     if (L.valid && pz > 0.0) {
         const double B = (tx_path(a, px, py, pz) + pz) * a.k - a.t0fs;
         const double fl = floor(B);
         L.nB = (int)fl;
         L.fB = (float)(B - fl);
-        L.x = (float)px;
-        L.y = (float)py;
         L.z = (float)pz;
         L.z2 = L.z * L.z;
         L.thr = a.f2 > 0.f ? L.z2 * 0.25f / a.f2 : __builtin_inff();
@@ -113,15 +128,14 @@ __device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, 
         L.wtab = L.wsc * (4.f * HANN_N);
         L.ph0 = phase_origin(a, L.nB);
     } else {
-        // benign values for points outside the grid or at z <= 0: far away
-        // laterally, so rho^2 is huge (never NaN) and the weight is 0
+        // benign: depth 1 m (finite delays, clamped window index), outside
+        // every aperture test (thr < 0, FORCES weight forced to 0)
         L.nB = 0;
         L.fB = 0.f;
-        L.x = L.y = 1e18f;
         L.z = L.z2 = 1.f;
         L.thr = -1.f;
         L.wsc = __builtin_inff();
-        L.wtab = 1.f;        // rho^2 ~ 1e36 -> table index saturates, fract 0 -> weight 0
+        L.wtab = 1.f;
         L.ph0 = 0.f;
     }
     return L;
@@ -130,7 +144,7 @@ __device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, 
 // Array-frame bounding box of the workgroup's points (clamped to the grid).
 __device__ inline BoxGeom block_box(const DasArgs &a, const LdsCfg &c, int bx, int by, int bz)
 {
-    const int tx = c.bwx << a.lx, ty = c.bwy << a.ly, tz = c.bwz << a.lz;
+    const int tx = c.bwx << a.lx, ty = c.bwy << a.ly, tz = (c.bwz << a.lz) * c.zp;
     const int i0[3] = {bx * tx, by * ty, bz * tz};
     const int i1[3] = {min(bx * tx + tx - 1, a.g.nx - 1), min(by * ty + ty - 1, a.g.ny - 1),
                        min(bz * tz + tz - 1, a.g.nz - 1)};
@@ -161,6 +175,11 @@ __device__ inline BoxGeom block_box(const DasArgs &a, const LdsCfg &c, int bx, i
         const float dy = fmaxf(0.f, fmaxf(b.ymin, -b.ymax));
         b.txlo = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, (zlo + f) * (zlo + f)))) - f;
     }
+    // workgroup-uniform: keep the box in scalar registers
+    b.xmin = uniform_f(b.xmin); b.xmax = uniform_f(b.xmax);
+    b.ymin = uniform_f(b.ymin); b.ymax = uniform_f(b.ymax);
+    b.zmin = uniform_f(b.zmin); b.zmax = uniform_f(b.zmax);
+    b.kf = uniform_f(b.kf); b.t0f = uniform_f(b.t0f); b.txlo = uniform_f(b.txlo);
     return b;
 }
 
@@ -305,44 +324,41 @@ __device__ inline void slot_trace(const BatchDesc &d, const LdsCfg &c, int e, in
     }
 }
 
-constexpr int QMAX = 2;   // staging rounds per thread per batch (host guarantees)
+// Staging rounds per thread per batch (the host keeps nb * lmax within
+// QM * 64 * wavefronts): 2, or 3 for the two-point kernel.
+template <int ZP> struct StageRounds { static constexpr int value = ZP == 2 ? 3 : 2; };
 
-// Staging map: trace slot e of a batch is staged by wavefront e % W in round
-// e / W; lane m loads quad m (and m + 64 ... when the window is longer), so
-// the window start is computed once per (wavefront, trace) and consecutive
-// lanes read consecutive samples.  Windows of at most 32 quads are staged two
-// per wavefront round (lanes 0-31 and 32-63), which halves the staging
-// instructions.
+// Staging map: the nb * lmax quads of a batch are numbered trace-major and
+// dealt to the workgroup's threads in order (round q, wavefront, lane), so no
+// lane idles on a short window and consecutive lanes read consecutive samples
+// of one trace.  Each lane computes the window start of its own trace.
+template <int QM>
 struct Staged {
-    float p[QMAX][8];    // taps n-1 .. n+2 (IQ: (re, im) of each)
-    int w0[QMAX];
+    float p[QM][8];    // taps n-1 .. n+2 (IQ: (re, im) of each)
+    int w0[QM];
 };
 
-__device__ inline int stage_rounds_m(const LdsCfg &c) { return (c.lmax + 63) >> 6; }
-
 // Slot e and quad m handled by this lane in staging round q; false if none.
+// (g + 1/2) / lmax is at least 1 / (2 lmax) away from an integer, far more
+// than the FP32 rounding of the product for g < 2^16.
 __device__ inline bool stage_slot(const LdsCfg &c, int q, int wave, int lane, int nwaves, int *e,
                                   int *m)
 {
-    if (c.tpw == 2) {
-        *e = 2 * (wave + q * nwaves) + (lane >> 5);
-        *m = lane & 31;
-        return q < (c.nb + 2 * nwaves - 1) / (2 * nwaves) && *e < c.nb;
-    }
-    const int mr = stage_rounds_m(c);
-    *e = wave + (q / mr) * nwaves;
-    *m = lane + 64 * (q % mr);
-    return q < mr * ((c.nb + nwaves - 1) / nwaves) && *e < c.nb;
+    const int g = (q * nwaves + wave) * 64 + lane;
+    const int ee = (int)(((float)g + 0.5f) * c.inv_lmax);
+    *e = ee;
+    *m = g - ee * c.lmax;
+    return ee < c.nb;
 }
 
 // Issue the global loads of a batch's windows (taps n-1..n+2 of every quad).
-template <int MODE, int ET>
+template <int MODE, int ET, int QM>
 __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const BoxGeom &b,
                                   const float *s_tx, const float *s_rx, const BatchDesc &d,
-                                  Staged &st, int wave, int lane, int nwaves)
+                                  Staged<QM> &st, int wave, int lane, int nwaves)
 {
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
+    for (int q = 0; q < QM; ++q) {
         int e, m;
         const bool on = stage_slot(c, q, wave, lane, nwaves, &e, &m);
         float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
@@ -356,43 +372,45 @@ __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const BoxGe
                 if (m < c.lmax) {
                     const int n = w0 + m;
                     const void *tr = trace_ptr<ET>(a.e, (long)i * a.n_ch + j, a.S);
+                    const void *tn = trace_ptr<ET>(tr, n, 1);   // sample n of the trace
                     const unsigned S = (unsigned)a.S;
+                    const bool inside = w0 >= 1 && w0 + c.lmax + 1 < a.S;
                     if constexpr (ET == ET_CF32) {
                         // (re, im) of taps n-1 .. n+2: 32 contiguous bytes
                         const float2 z = make_float2(0.f, 0.f);
                         float2 t0, t1, t2, t3;
-                        if (w0 >= 1 && w0 + c.lmax + 1 < a.S) {
+                        if (inside) {
                             float4 u, v;
-                            __builtin_memcpy(&u, static_cast<const float2 *>(tr) + (n - 1), 16);
-                            __builtin_memcpy(&v, static_cast<const float2 *>(tr) + (n + 1), 16);
+                            __builtin_memcpy(&u, static_cast<const float2 *>(tn) - 1, 16);
+                            __builtin_memcpy(&v, static_cast<const float2 *>(tn) + 1, 16);
                             t0 = make_float2(u.x, u.y); t1 = make_float2(u.z, u.w);
                             t2 = make_float2(v.x, v.y); t3 = make_float2(v.z, v.w);
                         } else {
-                            t0 = ((unsigned)(n - 1) < S) ? load_c(tr, n - 1) : z;
-                            t1 = ((unsigned)n < S) ? load_c(tr, n) : z;
-                            t2 = ((unsigned)(n + 1) < S) ? load_c(tr, n + 1) : z;
-                            t3 = ((unsigned)(n + 2) < S) ? load_c(tr, n + 2) : z;
+                            t0 = ((unsigned)(n - 1) < S) ? load_c(tn, -1) : z;
+                            t1 = ((unsigned)n < S) ? load_c(tn, 0) : z;
+                            t2 = ((unsigned)(n + 1) < S) ? load_c(tn, 1) : z;
+                            t3 = ((unsigned)(n + 2) < S) ? load_c(tn, 2) : z;
                         }
                         p0 = t0.x; p1 = t1.x; p2 = t2.x; p3 = t3.x;
                         p4 = t0.y; p5 = t1.y; p6 = t2.y; p7 = t3.y;
-                    } else if (w0 >= 1 && w0 + c.lmax + 1 < a.S) {
+                    } else if (inside) {
                         // whole window inside the record (the usual case): one
                         // 16-byte load of the four taps (4-byte aligned)
                         if constexpr (ET == ET_F32) {
                             float4 q;
-                            __builtin_memcpy(&q, static_cast<const float *>(tr) + (n - 1), 16);
+                            __builtin_memcpy(&q, static_cast<const float *>(tn) - 1, 16);
                             p0 = q.x; p1 = q.y; p2 = q.z; p3 = q.w;
                         } else {
-                            p0 = load_e<ET>(tr, n - 1);
-                            p1 = load_e<ET>(tr, n);
-                            p2 = load_e<ET>(tr, n + 1);
-                            p3 = load_e<ET>(tr, n + 2);
+                            p0 = load_e<ET>(tn, -1);
+                            p1 = load_e<ET>(tn, 0);
+                            p2 = load_e<ET>(tn, 1);
+                            p3 = load_e<ET>(tn, 2);
                         }
                     } else {
-                        p0 = ((unsigned)(n - 1) < S) ? load_e<ET>(tr, n - 1) : 0.f;
-                        p1 = ((unsigned)n < S) ? load_e<ET>(tr, n) : 0.f;
-                        p2 = ((unsigned)(n + 1) < S) ? load_e<ET>(tr, n + 1) : 0.f;
-                        p3 = ((unsigned)(n + 2) < S) ? load_e<ET>(tr, n + 2) : 0.f;
+                        p0 = ((unsigned)(n - 1) < S) ? load_e<ET>(tn, -1) : 0.f;
+                        p1 = ((unsigned)n < S) ? load_e<ET>(tn, 0) : 0.f;
+                        p2 = ((unsigned)(n + 1) < S) ? load_e<ET>(tn, 1) : 0.f;
+                        p3 = ((unsigned)(n + 2) < S) ? load_e<ET>(tn, 2) : 0.f;
                     }
                 }
             }
@@ -425,13 +443,13 @@ __device__ inline float4 coef_quad(float pm, float p0, float p1, float p2)
 // Convert the loaded taps to coefficient quads and write them (and the
 // per-trace metadata) to one LDS buffer.  QS = quads per sample interval
 // (2 for IQ data: real part, then imaginary part).
-template <int MODE, int IP, int QS>
+template <int MODE, int IP, int QS, int QM>
 __device__ inline void stage_store(const LdsCfg &c, const float *s_tx, const BatchDesc &d,
-                                   const Staged &st, float4 *quads, Meta *meta, int wave,
+                                   const Staged<QM> &st, float4 *quads, Meta *meta, int wave,
                                    int lane, int nwaves)
 {
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
+    for (int q = 0; q < QM; ++q) {
         int e, m;
         if (stage_slot(c, q, wave, lane, nwaves, &e, &m)) {
             if (m < c.lmax) {
@@ -503,34 +521,40 @@ __device__ inline int add3_i32(int a, int b, int c)
     return r;
 }
 
-// One HERCULES term: receiver at lateral offset (x - xi, dy), trace window
-// `win` starting at sample interval w0 (passed negated, uniform).
-template <int ET, int IP>
-__device__ inline void hercules_term(const LaneL &L, const float4 *win, int lmax,
+// One HERCULES trace for the lane's ZP points: receiver at lateral offset
+// (x - xi, dy) from all of them (same x, y), trace window `win` starting at
+// sample interval w0 (passed negated, uniform).
+template <int ET, int IP, int ZP>
+__device__ inline void hercules_term(const LaneL (&L)[ZP], const float4 *win, int lmax,
                                      const float2 *hann, float dy2, float kf, float rot, float xi,
-                                     int neg_w0, float2 &acc)
+                                     int neg_w0, float2 (&acc)[ZP])
 {
-    const float dx = L.x - xi;
+    const float dx = L[0].x - xi;
     const float rho2 = fmaf(dx, dx, dy2);
-    const float s = fmaf(excess(rho2, L.z, L.z2), kf, L.fB);
-    const int li = add3_i32(cvt_flr(s), L.nB, neg_w0);
-    // Hann weight from the LDS table; u^2 >= 1/4 lands on the (0, 0) entry
-    const float xw = rho2 * L.wtab;
-    const float2 h = hann[min((unsigned)cvt_flr(xw), (unsigned)HANN_N)];
-    const float w = fmaf(__builtin_amdgcn_fractf(xw), h.y, h.x);
-    if constexpr (ET == ET_CF32) {
-        const float2 v = read_quad_cx<IP>(win, li, lmax, __builtin_amdgcn_fractf(s));
-        rotate_acc(v, w, fmaf(rot, s, L.ph0), acc);
-    } else {
-        const float v = read_quad<IP>(win, li, lmax, __builtin_amdgcn_fractf(s));
-        acc.x = fmaf(w, v, acc.x);
+#pragma unroll
+    for (int p = 0; p < ZP; ++p) {
+        const float s = fmaf(excess(rho2, L[p].z, L[p].z2), kf, L[p].fB);
+        const int li = add3_i32(cvt_flr(s), L[p].nB, neg_w0);
+        // Hann weight from the LDS table; u^2 >= 1/4 lands on the (0, 0) entry
+        const float xw = rho2 * L[p].wtab;
+        const float2 h = hann[min((unsigned)cvt_flr(xw), (unsigned)HANN_N)];
+        const float w = fmaf(__builtin_amdgcn_fractf(xw), h.y, h.x);
+        if constexpr (ET == ET_CF32) {
+            const float2 v = read_quad_cx<IP>(win, li, lmax, __builtin_amdgcn_fractf(s));
+            rotate_acc(v, w, fmaf(rot, s, L[p].ph0), acc[p]);
+        } else {
+            const float v = read_quad<IP>(win, li, lmax, __builtin_amdgcn_fractf(s));
+            acc[p].x = fmaf(w, v, acc[p].x);
+        }
     }
 }
 
-template <int MODE, int ET, int IP>
+template <int MODE, int ET, int IP, int ZP>
 __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int grp,
                                  float4 *smem)
 {
+    static_assert(ZP == 1 || MODE == MODE_HERCULES, "two points per lane: HERCULES only");
+    constexpr int QM = StageRounds<ZP>::value;
     const int nthr = blockDim.x;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -553,10 +577,19 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     const int bx = (blk / c.blocks_z) % c.blocks_x;
     const int by = blk / (c.blocks_z * c.blocks_x);
     const BoxGeom box = block_box(a, c, bx, by, bz);
-    const LaneL L = lane_setup_l(a, c, bx, by, bz, wave, lane);
+    LaneL Lp[ZP];
+#pragma unroll
+    for (int p = 0; p < ZP; ++p) Lp[p] = lane_setup_l(a, c, bx, by, bz, wave, lane, p);
+    const LaneL &L = Lp[0];
+    // largest rho^2 bound of the receive aperture over the lane's points
+    float thr_l = Lp[0].thr;
+#pragma unroll
+    for (int p = 1; p < ZP; ++p) thr_l = fmaxf(thr_l, Lp[p].thr);
     const float kf = (float)a.k;
     const float rot = a.rot;
-    float2 acc = make_float2(0.f, 0.f);
+    float2 acc[ZP];
+#pragma unroll
+    for (int p = 0; p < ZP; ++p) acc[p] = make_float2(0.f, 0.f);
     __syncthreads();
 
     int jb, je;
@@ -569,11 +602,11 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     for (int q = 0; q < JC; ++q) it.rows[q] = -1;
 
     BatchDesc cur = next_batch<MODE>(a, c, box, s_tx, s_rx, it);
-    Staged st;
+    Staged<QM> st;
     if (cur.valid) {
-        stage_load<MODE, ET>(a, c, box, s_tx, s_rx, cur, st, wave, lane, nwaves);
-        stage_store<MODE, IP, QS>(c, s_tx, cur, st, q0 + c.nb, reinterpret_cast<Meta *>(q0),
-                                  wave, lane, nwaves);
+        stage_load<MODE, ET, QM>(a, c, box, s_tx, s_rx, cur, st, wave, lane, nwaves);
+        stage_store<MODE, IP, QS, QM>(c, s_tx, cur, st, q0 + c.nb, reinterpret_cast<Meta *>(q0),
+                                      wave, lane, nwaves);
     }
     __syncthreads();
 
@@ -588,7 +621,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     int bi = 0;
     while (cur.valid) {
         BatchDesc nxt = next_batch<MODE>(a, c, box, s_tx, s_rx, it);
-        if (nxt.valid) stage_load<MODE, ET>(a, c, box, s_tx, s_rx, nxt, st, wave, lane, nwaves);
+        if (nxt.valid) stage_load<MODE, ET, QM>(a, c, box, s_tx, s_rx, nxt, st, wave, lane, nwaves);
 
         float4 *qb = (bi & 1) ? q1 : q0;
         const Meta *meta = reinterpret_cast<const Meta *>(qb);
@@ -601,7 +634,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                 row_j = cur.j;
                 const float dy = L.y - s_rx[row_j];
                 dy2 = dy * dy;
-                const float r2 = L.thr - dy2;
+                const float r2 = thr_l - dy2;
                 const float r = r2 > 0.f ? sqrtf(r2) : 0.f;
                 wlo = uniform_f(wave_min(r2 > 0.f ? L.x - r : __builtin_inff()));
                 whi = uniform_f(wave_max(r2 > 0.f ? L.x + r : -__builtin_inff()));
@@ -611,23 +644,34 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
             // pairs whose LDS reads overlap, then an odd last one
             uint64_t mask = __ballot(lane < cur.cnt && mine.xi >= wlo && mine.xi <= whi);
             const int xi_bits = __float_as_int(mine.xi);
+            if constexpr (ZP == 2) {
+                // one trace per step already gives two independent terms
+                while (mask) {
+                    const int e1 = __builtin_ctzll(mask);
+                    mask &= mask - 1;
+                    hercules_term<ET, IP, ZP>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2,
+                                              kf, rot,
+                                              __int_as_float(__builtin_amdgcn_readlane(xi_bits, e1)),
+                                              -__builtin_amdgcn_readlane(mine.w0, e1), acc);
+                }
+            }
             while (mask & (mask - 1)) {
                 const int e1 = __builtin_ctzll(mask);
                 mask &= mask - 1;
                 const int e2 = __builtin_ctzll(mask);
                 mask &= mask - 1;
-                hercules_term<ET, IP>(L, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, kf, rot,
-                                      __int_as_float(__builtin_amdgcn_readlane(xi_bits, e1)),
-                                      -__builtin_amdgcn_readlane(mine.w0, e1), acc);
-                hercules_term<ET, IP>(L, quads + e2 * c.lmax * QS, c.lmax, s_hann, dy2, kf, rot,
-                                      __int_as_float(__builtin_amdgcn_readlane(xi_bits, e2)),
-                                      -__builtin_amdgcn_readlane(mine.w0, e2), acc);
+                hercules_term<ET, IP, ZP>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, kf,
+                                          rot, __int_as_float(__builtin_amdgcn_readlane(xi_bits, e1)),
+                                          -__builtin_amdgcn_readlane(mine.w0, e1), acc);
+                hercules_term<ET, IP, ZP>(Lp, quads + e2 * c.lmax * QS, c.lmax, s_hann, dy2, kf,
+                                          rot, __int_as_float(__builtin_amdgcn_readlane(xi_bits, e2)),
+                                          -__builtin_amdgcn_readlane(mine.w0, e2), acc);
             }
             if (mask) {
                 const int e1 = __builtin_ctzll(mask);
-                hercules_term<ET, IP>(L, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, kf, rot,
-                                      __int_as_float(__builtin_amdgcn_readlane(xi_bits, e1)),
-                                      -__builtin_amdgcn_readlane(mine.w0, e1), acc);
+                hercules_term<ET, IP, ZP>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, kf,
+                                          rot, __int_as_float(__builtin_amdgcn_readlane(xi_bits, e1)),
+                                          -__builtin_amdgcn_readlane(mine.w0, e1), acc);
             }
         } else {
             const int nbi = c.nb / JC;
@@ -661,11 +705,11 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                     if constexpr (ET == ET_CF32) {
                         const float2 v = read_quad_cx<IP>(quads + e * c.lmax * QS, li, c.lmax,
                                                           __builtin_amdgcn_fractf(sq));
-                        rotate_acc(v, aj[q], fmaf(rot, sq, L.ph0), acc);
+                        rotate_acc(v, aj[q], fmaf(rot, sq, L.ph0), acc[0]);
                     } else {
                         const float v = read_quad<IP>(quads + e * c.lmax, li, c.lmax,
                                                       __builtin_amdgcn_fractf(sq));
-                        acc.x = fmaf(aj[q], v, acc.x);
+                        acc[0].x = fmaf(aj[q], v, acc[0].x);
                     }
                 }
             }
@@ -673,34 +717,52 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
 
         if (!nxt.valid) break;
         float4 *nb_ = ((bi + 1) & 1) ? q1 : q0;
-        stage_store<MODE, IP, QS>(c, s_tx, nxt, st, nb_ + c.nb, reinterpret_cast<Meta *>(nb_),
-                                  wave, lane, nwaves);
+        stage_store<MODE, IP, QS, QM>(c, s_tx, nxt, st, nb_ + c.nb, reinterpret_cast<Meta *>(nb_),
+                                      wave, lane, nwaves);
         __syncthreads();
         cur = nxt;
         ++bi;
     }
-    if (L.valid) {
-        const long npts = (long)a.g.nx * a.g.ny * a.g.nz;
-        float *dst = a.groups > 1 ? a.part + (long)grp * npts * QS : das_out(a);
-        if constexpr (ET == ET_CF32)
-            reinterpret_cast<float2 *>(dst)[L.out_idx] = acc;
-        else
-            dst[L.out_idx] = acc.x;
+    const long npts = (long)a.g.nx * a.g.ny * a.g.nz;
+    float *dst = a.groups > 1 ? a.part + (long)grp * npts * QS : das_out(a);
+    // the point indices are recomputed here (an opaque copy of the lane
+    // number), so they hold no registers during the loop
+    int lane_e = lane;
+    asm volatile("" : "+v"(lane_e));
+#pragma unroll
+    for (int p = 0; p < ZP; ++p) {
+        int ix, iy, iz;
+        lane_point(a, c, bx, by, bz, wave, lane_e, p, &ix, &iy, &iz);
+        if (ix < a.g.nx && iy < a.g.ny && iz < a.g.nz) {
+            const long idx = ((long)iy * a.g.nx + ix) * a.g.nz + iz;
+            const double pz = a.g.org[2] + ix * a.g.ax[2] + iy * a.g.ay[2] + iz * a.g.az[2];
+            const float2 v = pz > 0.0 ? acc[p] : make_float2(0.f, 0.f);
+            if constexpr (ET == ET_CF32)
+                reinterpret_cast<float2 *>(dst)[idx] = v;
+            else
+                dst[idx] = v.x;
+        }
     }
 }
 
-template <int MODE, int ET, int IP>
-__global__ __launch_bounds__(1024) void das_lds_kernel(DasArgs a, LdsCfg c)
+// Two points per lane: registers capped for 6 wavefronts per SIMD (two
+// 12-wavefront workgroups per CU).
+template <int ZP> struct WavesPerEu { static constexpr int value = ZP == 2 ? 6 : 1; };
+
+template <int MODE, int ET, int IP, int ZP>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerEu<ZP>::value)))
+void das_lds_kernel(DasArgs a, LdsCfg c)
 {
     extern __shared__ float4 smem[];
-    das_block<MODE, ET, IP>(a, c, blockIdx.x, blockIdx.y, smem);
+    das_block<MODE, ET, IP, ZP>(a, c, blockIdx.x, blockIdx.y, smem);
 }
 
 // Persistent form for a batch of frames: each workgroup pulls (frame, box)
 // items from a queue until it is empty.  Items are ordered by decreasing
 // cost on the host, so the queue balances uneven frames.
-template <int MODE, int ET, int IP>
-__global__ __launch_bounds__(1024) void das_persistent_kernel(const FrameDas *__restrict__ frames,
+template <int MODE, int ET, int IP, int ZP>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerEu<ZP>::value)))
+void das_persistent_kernel(const FrameDas *__restrict__ frames,
                                                               const int2 *__restrict__ items,
                                                               int n_items, int *counter,
                                                               void *const *__restrict__ out_ptrs)
@@ -718,17 +780,36 @@ __global__ __launch_bounds__(1024) void das_persistent_kernel(const FrameDas *__
         const int blk = __builtin_amdgcn_readfirstlane(items[item].y);
         DasArgs a = frames[fr].a;
         a.out = static_cast<float *>(out_ptrs[fr]);
-        das_block<MODE, ET, IP>(a, frames[fr].c, blk, 0, smem);
+        das_block<MODE, ET, IP, ZP>(a, frames[fr].c, blk, 0, smem);
         __syncthreads();
     }
+}
+
+// Dynamic LDS beyond 64 KiB (gfx950 has 160 KiB per CU) is requested per
+// kernel before its launch.
+static hipError_t allow_lds(const void *fn, size_t shm)
+{
+    if (shm <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+}
+
+template <int MODE, int ET, int IP, int ZP>
+static hipError_t launch_persistent4(const PersistentLaunch &p, hipStream_t s)
+{
+    const void *fn = reinterpret_cast<const void *>(&das_persistent_kernel<MODE, ET, IP, ZP>);
+    hipError_t e = allow_lds(fn, p.shm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((das_persistent_kernel<MODE, ET, IP, ZP>), dim3(p.grid), dim3(p.threads),
+                       p.shm, s, p.frames, p.items, p.n_items, p.counter, p.out_ptrs);
+    return hipGetLastError();
 }
 
 template <int MODE, int ET, int IP>
 static hipError_t launch_persistent3(const PersistentLaunch &p, hipStream_t s)
 {
-    hipLaunchKernelGGL((das_persistent_kernel<MODE, ET, IP>), dim3(p.grid), dim3(p.threads),
-                       p.shm, s, p.frames, p.items, p.n_items, p.counter, p.out_ptrs);
-    return hipGetLastError();
+    if constexpr (MODE == MODE_HERCULES)
+        if (p.zp == 2) return launch_persistent4<MODE, ET, IP, 2>(p, s);
+    return p.zp == 1 ? launch_persistent4<MODE, ET, IP, 1>(p, s) : hipErrorInvalidValue;
 }
 
 template <int MODE, int ET>
@@ -759,41 +840,52 @@ hipError_t launch_das_persistent(const PersistentLaunch &p, hipStream_t s)
 }
 
 // Workgroups of the persistent DAS kernel that fit on the device at once.
-int persistent_das_blocks(int mode, int et, int ip, int threads, size_t shm)
+int persistent_das_blocks(int mode, int et, int ip, int zp, int threads, size_t shm)
 {
     int dev = 0, cus = 0, per = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const void *fn = nullptr;
     if (mode == 0 && et == ET_F32 && ip == IN_CUBIC)
-        fn = reinterpret_cast<const void *>(&das_persistent_kernel<0, ET_F32, IN_CUBIC>);
+        fn = reinterpret_cast<const void *>(&das_persistent_kernel<0, ET_F32, IN_CUBIC, 1>);
     else if (mode == 1 && et == ET_F32 && ip == IN_CUBIC)
-        fn = reinterpret_cast<const void *>(&das_persistent_kernel<1, ET_F32, IN_CUBIC>);
-    if (fn && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, shm) == hipSuccess &&
-        per > 0)
+        fn = zp == 2 ? reinterpret_cast<const void *>(&das_persistent_kernel<1, ET_F32, IN_CUBIC, 2>)
+                     : reinterpret_cast<const void *>(&das_persistent_kernel<1, ET_F32, IN_CUBIC, 1>);
+    if (fn && allow_lds(fn, shm) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, shm) == hipSuccess && per > 0)
         return cus * per;
     return cus * 2;
+}
+
+template <int MODE, int ET, int IP, int ZP>
+static hipError_t launch_lds4(const DasArgs &a, const LdsCfg &c, size_t shm, hipStream_t s)
+{
+    const int nthr = 64 * c.bwx * c.bwy * c.bwz;
+    dim3 grid(c.blocks_x * c.blocks_y * c.blocks_z, a.groups);
+    hipError_t e = allow_lds(reinterpret_cast<const void *>(&das_lds_kernel<MODE, ET, IP, ZP>), shm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((das_lds_kernel<MODE, ET, IP, ZP>), grid, dim3(nthr), shm, s, a, c);
+    return hipGetLastError();
+}
+
+template <int MODE, int ET, int IP>
+static hipError_t launch_lds_zp(const DasArgs &a, const LdsCfg &c, size_t shm, hipStream_t s)
+{
+    if constexpr (MODE == MODE_HERCULES && ET != ET_CF32)
+        if (c.zp == 2) return launch_lds4<MODE, ET, IP, 2>(a, c, shm, s);
+    return c.zp == 1 ? launch_lds4<MODE, ET, IP, 1>(a, c, shm, s) : hipErrorInvalidValue;
 }
 
 template <int MODE, int ET>
 static hipError_t launch_lds_ip(const DasArgs &a, const LdsCfg &c, int ip, size_t shm,
                                 hipStream_t s)
 {
-    const int nthr = 64 * c.bwx * c.bwy * c.bwz;
-    dim3 grid(c.blocks_x * c.blocks_y * c.blocks_z, a.groups);
     switch (ip) {
-        case IN_NEAREST:
-            hipLaunchKernelGGL((das_lds_kernel<MODE, ET, IN_NEAREST>), grid, dim3(nthr), shm, s, a, c);
-            break;
-        case IN_LINEAR:
-            hipLaunchKernelGGL((das_lds_kernel<MODE, ET, IN_LINEAR>), grid, dim3(nthr), shm, s, a, c);
-            break;
-        case IN_CUBIC:
-            hipLaunchKernelGGL((das_lds_kernel<MODE, ET, IN_CUBIC>), grid, dim3(nthr), shm, s, a, c);
-            break;
+        case IN_NEAREST: return launch_lds_zp<MODE, ET, IN_NEAREST>(a, c, shm, s);
+        case IN_LINEAR: return launch_lds_zp<MODE, ET, IN_LINEAR>(a, c, shm, s);
+        case IN_CUBIC: return launch_lds_zp<MODE, ET, IN_CUBIC>(a, c, shm, s);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 template <int MODE>

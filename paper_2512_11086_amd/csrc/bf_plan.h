@@ -26,7 +26,7 @@ struct Frame {
     int lx = 2, ly = 2, lz = 2;  // DAS wavefront tile (log2)
     int bw[3] = {4, 4, 1};       // wavefront tiles per LDS workgroup (x, y, z)
     int nb = 16;                 // traces per staged batch
-    int variant = 0;             // 0 = LDS-staged windows, 1 = direct gather
+    int variant = 0;             // BF_DAS_LDS, BF_DAS_GATHER or BF_DAS_LDS_Z2
     int sorted_tx = 0;           // transmit columns ascending
     int uniform_tx = 0;          // transmit columns equally spaced (ascending)
     float tx_x0 = 0.f, tx_inv_dx = 0.f;
@@ -55,6 +55,7 @@ struct Frame {
     DecodeArgs decode_args(const int16_t *rf, void *e) const;
     DasArgs das_args(const void *e, float *out, double c) const;
     bool lds_config(const DasArgs &a, LdsCfg *cfg) const;
+    bool z2_ok() const;          // two depth points per lane apply to this frame
     int decode(const int16_t *rf, void *e, hipStream_t s) const;
     int das(const void *e, float *out, double c, hipStream_t s) const;
 };

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_function():
     for name in names:
         assert hasattr(L, name), f"{name} declared in bf.h but not exported"
     assert set(names) == set(_lib.EXPORTED)
-    assert L.bf_abi_version() == 3
+    assert L.bf_abi_version() == 4
 
 
 def _good(k=0):

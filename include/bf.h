@@ -152,7 +152,8 @@ typedef struct {
     int32_t variant;           /* BF_DAS_* kernel bf_das runs for frame 0 (after the
                                   LDS-fit check at the plan's sound speed)              */
     int32_t block[3];          /* wavefront tiles per LDS workgroup along x, y, z      */
-    int32_t nb;                /* traces per staged batch                              */
+    int32_t nb;                /* traces per staged batch (as run: the requested count
+                                  trimmed to the LDS budget)                           */
     int64_t workspace_bytes;   /* device memory held by the plan                       */
     int64_t e_elems;           /* elements of decoded data per frame (frame 0; IQ
                                   plans count the two FP32 parts of a sample)          */

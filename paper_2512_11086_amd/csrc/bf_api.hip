@@ -233,8 +233,8 @@ int Frame::init(const bf_params &src)
     // autotuner can replace them): 2D = the direct-gather kernel on 16x4-point
     // wavefront tiles; HERCULES volumes = LDS windows, flat 8x8x1 lane tiles
     // with two depth points per lane in a 2x2x3 block (12 wavefronts,
-    // 16x16x6 points: two such workgroups fill a CU's LDS) with 40 traces per
-    // staged batch.
+    // 16x16x6 points: two such workgroups fill a CU's LDS) with as many traces
+    // per staged batch as the LDS cap allows (up to 48).
     if (p.mode == BF_FORCES_2D && (grid.ny == 1 || grid.nx == 1)) {
         // a plane: 16 x 4 points per wavefront along its lateral axis and depth
         if (grid.ny == 1) set_tile(4, 0, 2); else set_tile(0, 4, 2);
@@ -256,7 +256,10 @@ int Frame::init(const bf_params &src)
         set_tile(3, 3, 0);
         bw[0] = 2; bw[1] = 2; bw[2] = 3;
         nb = 40;
-        if (p.mode == BF_HERCULES_3D && grid.nz >= 2) variant = BF_DAS_LDS_Z2;
+        if (p.mode == BF_HERCULES_3D && grid.nz >= 2) {
+            variant = BF_DAS_LDS_Z2;
+            nb = 48;   // trimmed to the LDS cap by lds_config
+        }
     }
     sorted_tx = 1;
     for (int i = 1; i < n; ++i)
@@ -599,15 +602,14 @@ int bf_plan_get_info(bf_plan plan, bf_plan_info *info)
     {
         // the kernel bf_das actually runs (LDS windows may not fit: gather)
         LdsCfg cfg;
-        info->variant = (f.variant != BF_DAS_GATHER &&
-                         f.lds_config(f.das_args(nullptr, nullptr, f.p.c), &cfg))
-                            ? (cfg.zp == 2 ? BF_DAS_LDS_Z2 : BF_DAS_LDS)
-                            : BF_DAS_GATHER;
+        const bool lds = f.variant != BF_DAS_GATHER &&
+                         f.lds_config(f.das_args(nullptr, nullptr, f.p.c), &cfg);
+        info->variant = lds ? (cfg.zp == 2 ? BF_DAS_LDS_Z2 : BF_DAS_LDS) : BF_DAS_GATHER;
+        info->nb = lds ? cfg.nb : f.nb;
     }
     info->block[0] = f.bw[0];
     info->block[1] = f.bw[1];
     info->block[2] = f.bw[2];
-    info->nb = f.nb;
     info->workspace_bytes = plan->workspace_bytes();
     info->e_elems = f.e_elems();
     info->out_elems = f.out_elems();

@@ -39,11 +39,14 @@ hipError_t launch_sum_groups(const DasArgs &a, hipStream_t s);
 constexpr int JC = 4;    // FORCES channel rows per batch
 constexpr int HANN_TAB_PAD = HANN_N + 2;   // table entries reserved in LDS (float2, keeps 16-byte alignment)
 
-struct Meta {
-    int w0;      // first sample interval of the window
-    int on;      // trace staged
-    float xi;    // x of the transmit column
-    int pad;
+// Trace slot `lane` of a batch, held by that lane of every wavefront: the
+// first sample interval of its window, the x of its transmit column, and
+// its trace index i * n_ch + j (-1 for an empty slot).  Staging lanes fetch
+// the entry of their slot with a lane permute; terms read it with readlane.
+struct TraceDesc {
+    int w0;
+    float xi;
+    int tr;
 };
 
 // Uniform description of one batch.
@@ -85,6 +88,7 @@ __device__ inline float uniform_f(float v)
 struct LaneL {
     bool valid;
     float x, y, z, z2, thr, wsc, fB;
+    float zk, zk2;  // z / k and its square (k = fs / c): the HERCULES delay
     float wtab;     // u^2 * 4 HANN_N = rho^2 * wtab (table coordinate)
     int nB;
     float ph0;      // IQ: carrier phase of sample position nB (revolutions)
@@ -123,6 +127,8 @@ __device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, 
         L.fB = (float)(B - fl);
         L.z = (float)pz;
         L.z2 = L.z * L.z;
+        L.zk = (float)(pz / a.k);
+        L.zk2 = L.zk * L.zk;
         L.thr = a.f2 > 0.f ? L.z2 * 0.25f / a.f2 : __builtin_inff();
         L.wsc = a.f2 > 0.f ? a.f2 / L.z2 : 0.f;
         L.wtab = L.wsc * (4.f * HANN_N);
@@ -133,6 +139,8 @@ __device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, 
         L.nB = 0;
         L.fB = 0.f;
         L.z = L.z2 = 1.f;
+        L.zk = (float)(1.0 / a.k);
+        L.zk2 = L.zk * L.zk;
         L.thr = -1.f;
         L.wsc = __builtin_inff();
         L.wtab = 1.f;
@@ -335,7 +343,6 @@ template <int ZP> struct StageRounds { static constexpr int value = ZP == 2 ? 3 
 template <int QM>
 struct Staged {
     float p[QM][8];    // taps n-1 .. n+2 (IQ: (re, im) of each)
-    int w0[QM];
 };
 
 // Slot e and quad m handled by this lane in staging round q; false if none.
@@ -351,68 +358,81 @@ __device__ inline bool stage_slot(const LdsCfg &c, int q, int wave, int lane, in
     return ee < c.nb;
 }
 
+// Descriptor of trace slot `lane` of batch d (see TraceDesc).
+template <int MODE>
+__device__ inline TraceDesc trace_desc(const DasArgs &a, const LdsCfg &c, const BoxGeom &b,
+                                       const float *s_tx, const float *s_rx, const BatchDesc &d,
+                                       int lane)
+{
+    TraceDesc t{0, 0.f, -1};
+    if (lane < c.nb) {
+        int i, j;
+        slot_trace<MODE>(d, c, lane, &i, &j);
+        if (j >= 0) {
+            t.xi = s_tx[i];
+            t.w0 = window_start<MODE>(b, t.xi, s_rx[j]);
+            t.tr = i * a.n_ch + j;
+        }
+    }
+    return t;
+}
+
 // Issue the global loads of a batch's windows (taps n-1..n+2 of every quad).
-template <int MODE, int ET, int QM>
-__device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const BoxGeom &b,
-                                  const float *s_tx, const float *s_rx, const BatchDesc &d,
+template <int ET, int QM>
+__device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const TraceDesc &td,
                                   Staged<QM> &st, int wave, int lane, int nwaves)
 {
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
         int e, m;
         const bool on = stage_slot(c, q, wave, lane, nwaves, &e, &m);
+        // window start and trace of slot e, from lane e
+        const int src = (e & 63) << 2;
+        const int w0 = __builtin_amdgcn_ds_bpermute(src, td.w0);
+        const int tr = __builtin_amdgcn_ds_bpermute(src, td.tr);
         float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
         float p4 = 0.f, p5 = 0.f, p6 = 0.f, p7 = 0.f;
-        int w0 = 0;
-        if (on) {
-            int i, j;
-            slot_trace<MODE>(d, c, e, &i, &j);
-            if (j >= 0) {
-                w0 = window_start<MODE>(b, s_tx[i], s_rx[j]);
-                if (m < c.lmax) {
-                    const int n = w0 + m;
-                    const void *tr = trace_ptr<ET>(a.e, (long)i * a.n_ch + j, a.S);
-                    const void *tn = trace_ptr<ET>(tr, n, 1);   // sample n of the trace
-                    const unsigned S = (unsigned)a.S;
-                    const bool inside = w0 >= 1 && w0 + c.lmax + 1 < a.S;
-                    if constexpr (ET == ET_CF32) {
-                        // (re, im) of taps n-1 .. n+2: 32 contiguous bytes
-                        const float2 z = make_float2(0.f, 0.f);
-                        float2 t0, t1, t2, t3;
-                        if (inside) {
-                            float4 u, v;
-                            __builtin_memcpy(&u, static_cast<const float2 *>(tn) - 1, 16);
-                            __builtin_memcpy(&v, static_cast<const float2 *>(tn) + 1, 16);
-                            t0 = make_float2(u.x, u.y); t1 = make_float2(u.z, u.w);
-                            t2 = make_float2(v.x, v.y); t3 = make_float2(v.z, v.w);
-                        } else {
-                            t0 = ((unsigned)(n - 1) < S) ? load_c(tn, -1) : z;
-                            t1 = ((unsigned)n < S) ? load_c(tn, 0) : z;
-                            t2 = ((unsigned)(n + 1) < S) ? load_c(tn, 1) : z;
-                            t3 = ((unsigned)(n + 2) < S) ? load_c(tn, 2) : z;
-                        }
-                        p0 = t0.x; p1 = t1.x; p2 = t2.x; p3 = t3.x;
-                        p4 = t0.y; p5 = t1.y; p6 = t2.y; p7 = t3.y;
-                    } else if (inside) {
-                        // whole window inside the record (the usual case): one
-                        // 16-byte load of the four taps (4-byte aligned)
-                        if constexpr (ET == ET_F32) {
-                            float4 q;
-                            __builtin_memcpy(&q, static_cast<const float *>(tn) - 1, 16);
-                            p0 = q.x; p1 = q.y; p2 = q.z; p3 = q.w;
-                        } else {
-                            p0 = load_e<ET>(tn, -1);
-                            p1 = load_e<ET>(tn, 0);
-                            p2 = load_e<ET>(tn, 1);
-                            p3 = load_e<ET>(tn, 2);
-                        }
-                    } else {
-                        p0 = ((unsigned)(n - 1) < S) ? load_e<ET>(tn, -1) : 0.f;
-                        p1 = ((unsigned)n < S) ? load_e<ET>(tn, 0) : 0.f;
-                        p2 = ((unsigned)(n + 1) < S) ? load_e<ET>(tn, 1) : 0.f;
-                        p3 = ((unsigned)(n + 2) < S) ? load_e<ET>(tn, 2) : 0.f;
-                    }
+        if (on && tr >= 0) {
+            const int n = w0 + m;
+            const void *tn = trace_ptr<ET>(trace_ptr<ET>(a.e, tr, a.S), n, 1);   // sample n
+            const unsigned S = (unsigned)a.S;
+            const bool inside = w0 >= 1 && w0 + c.lmax + 1 < a.S;
+            if constexpr (ET == ET_CF32) {
+                // (re, im) of taps n-1 .. n+2: 32 contiguous bytes
+                const float2 z = make_float2(0.f, 0.f);
+                float2 t0, t1, t2, t3;
+                if (inside) {
+                    float4 u, v;
+                    __builtin_memcpy(&u, static_cast<const float2 *>(tn) - 1, 16);
+                    __builtin_memcpy(&v, static_cast<const float2 *>(tn) + 1, 16);
+                    t0 = make_float2(u.x, u.y); t1 = make_float2(u.z, u.w);
+                    t2 = make_float2(v.x, v.y); t3 = make_float2(v.z, v.w);
+                } else {
+                    t0 = ((unsigned)(n - 1) < S) ? load_c(tn, -1) : z;
+                    t1 = ((unsigned)n < S) ? load_c(tn, 0) : z;
+                    t2 = ((unsigned)(n + 1) < S) ? load_c(tn, 1) : z;
+                    t3 = ((unsigned)(n + 2) < S) ? load_c(tn, 2) : z;
                 }
+                p0 = t0.x; p1 = t1.x; p2 = t2.x; p3 = t3.x;
+                p4 = t0.y; p5 = t1.y; p6 = t2.y; p7 = t3.y;
+            } else if (inside) {
+                // whole window inside the record (the usual case): one
+                // 16-byte load of the four taps (4-byte aligned)
+                if constexpr (ET == ET_F32) {
+                    float4 v;
+                    __builtin_memcpy(&v, static_cast<const float *>(tn) - 1, 16);
+                    p0 = v.x; p1 = v.y; p2 = v.z; p3 = v.w;
+                } else {
+                    p0 = load_e<ET>(tn, -1);
+                    p1 = load_e<ET>(tn, 0);
+                    p2 = load_e<ET>(tn, 1);
+                    p3 = load_e<ET>(tn, 2);
+                }
+            } else {
+                p0 = ((unsigned)(n - 1) < S) ? load_e<ET>(tn, -1) : 0.f;
+                p1 = ((unsigned)n < S) ? load_e<ET>(tn, 0) : 0.f;
+                p2 = ((unsigned)(n + 1) < S) ? load_e<ET>(tn, 1) : 0.f;
+                p3 = ((unsigned)(n + 2) < S) ? load_e<ET>(tn, 2) : 0.f;
             }
         }
         st.p[q][0] = p0;
@@ -423,7 +443,6 @@ __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const BoxGe
         st.p[q][5] = p5;
         st.p[q][6] = p6;
         st.p[q][7] = p7;
-        st.w0[q] = w0;
     }
 }
 
@@ -440,34 +459,21 @@ __device__ inline float4 coef_quad(float pm, float p0, float p1, float p2)
         return make_float4(p0, p1, 0.f, 0.f);
 }
 
-// Convert the loaded taps to coefficient quads and write them (and the
-// per-trace metadata) to one LDS buffer.  QS = quads per sample interval
-// (2 for IQ data: real part, then imaginary part).
-template <int MODE, int IP, int QS, int QM>
-__device__ inline void stage_store(const LdsCfg &c, const float *s_tx, const BatchDesc &d,
-                                   const Staged<QM> &st, float4 *quads, Meta *meta, int wave,
+// Convert the loaded taps to coefficient quads and write them to one LDS
+// buffer.  QS = quads per sample interval (2 for IQ data: real part, then
+// imaginary part).
+template <int IP, int QS, int QM>
+__device__ inline void stage_store(const LdsCfg &c, const Staged<QM> &st, float4 *quads, int wave,
                                    int lane, int nwaves)
 {
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
         int e, m;
         if (stage_slot(c, q, wave, lane, nwaves, &e, &m)) {
-            if (m < c.lmax) {
-                const float *t = st.p[q];
-                quads[(e * c.lmax + m) * QS] = coef_quad<IP>(t[0], t[1], t[2], t[3]);
-                if constexpr (QS == 2)
-                    quads[(e * c.lmax + m) * 2 + 1] = coef_quad<IP>(t[4], t[5], t[6], t[7]);
-            }
-            if (m == 0) {
-                int i, j;
-                slot_trace<MODE>(d, c, e, &i, &j);
-                Meta mt;
-                mt.on = j >= 0;
-                mt.xi = mt.on ? s_tx[i] : 0.f;
-                mt.w0 = st.w0[q];
-                mt.pad = 0;
-                meta[e] = mt;
-            }
+            const float *t = st.p[q];
+            quads[(e * c.lmax + m) * QS] = coef_quad<IP>(t[0], t[1], t[2], t[3]);
+            if constexpr (QS == 2)
+                quads[(e * c.lmax + m) * 2 + 1] = coef_quad<IP>(t[4], t[5], t[6], t[7]);
         }
     }
 }
@@ -523,17 +529,21 @@ __device__ inline int add3_i32(int a, int b, int c)
 
 // One HERCULES trace for the lane's ZP points: receiver at lateral offset
 // (x - xi, dy) from all of them (same x, y), trace window `win` starting at
-// sample interval w0 (passed negated, uniform).
+// sample interval w0 (passed negated, uniform).  The excess receive path in
+// samples, k rho^2 / (d + z), is evaluated as rho^2 / (d/k + z/k) with
+// d/k = sqrt(rho^2 / k^2 + (z/k)^2): the scale k is folded into the lane
+// constants (ik2 = 1 / k^2).
 template <int ET, int IP, int ZP>
 __device__ inline void hercules_term(const LaneL (&L)[ZP], const float4 *win, int lmax,
-                                     const float2 *hann, float dy2, float kf, float rot, float xi,
+                                     const float2 *hann, float dy2, float ik2, float rot, float xi,
                                      int neg_w0, float2 (&acc)[ZP])
 {
     const float dx = L[0].x - xi;
     const float rho2 = fmaf(dx, dx, dy2);
 #pragma unroll
     for (int p = 0; p < ZP; ++p) {
-        const float s = fmaf(excess(rho2, L[p].z, L[p].z2), kf, L[p].fB);
+        const float dk = __builtin_amdgcn_sqrtf(fmaf(rho2, ik2, L[p].zk2));
+        const float s = fmaf(rho2, __builtin_amdgcn_rcpf(dk + L[p].zk), L[p].fB);
         const int li = add3_i32(cvt_flr(s), L[p].nB, neg_w0);
         // Hann weight from the LDS table; u^2 >= 1/4 lands on the (0, 0) entry
         const float xw = rho2 * L[p].wtab;
@@ -560,13 +570,13 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     const int wave = tid >> 6, lane = tid & 63;
     const int nwaves = nthr >> 6;
 
-    // tables: tx_x, rx_c, then two buffers of [nb] Meta + [nb * lmax] quads
+    // tables: tx_x, rx_c, Hann weights, then two buffers of [nb * lmax] quads
     float *s_tx = reinterpret_cast<float *>(smem);
     float *s_rx = s_tx + ((a.n_tx + 3) & ~3);
     float2 *s_hann = reinterpret_cast<float2 *>(s_rx + ((a.n_ch + 3) & ~3));
     float4 *bufbase = reinterpret_cast<float4 *>(s_hann + HANN_TAB_PAD);
     constexpr int QS = ET == ET_CF32 ? 2 : 1;     // quads per sample interval
-    const int buf_quads = c.nb * c.lmax * QS + c.nb;   // Meta is 16 bytes = one float4
+    const int buf_quads = c.nb * c.lmax * QS;
     float4 *q0 = bufbase, *q1 = bufbase + buf_quads;
     for (int t = tid; t < a.n_tx; t += nthr) s_tx[t] = a.tx_x[t];
     for (int t = tid; t < a.n_ch; t += nthr) s_rx[t] = a.rx_c[t];
@@ -586,6 +596,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
 #pragma unroll
     for (int p = 1; p < ZP; ++p) thr_l = fmaxf(thr_l, Lp[p].thr);
     const float kf = (float)a.k;
+    const float ik2 = uniform_f((float)(1.0 / (a.k * a.k)));
     const float rot = a.rot;
     float2 acc[ZP];
 #pragma unroll
@@ -603,10 +614,11 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
 
     BatchDesc cur = next_batch<MODE>(a, c, box, s_tx, s_rx, it);
     Staged<QM> st;
+    TraceDesc td = {0, 0.f, -1};       // descriptors of the current batch
     if (cur.valid) {
-        stage_load<MODE, ET, QM>(a, c, box, s_tx, s_rx, cur, st, wave, lane, nwaves);
-        stage_store<MODE, IP, QS, QM>(c, s_tx, cur, st, q0 + c.nb, reinterpret_cast<Meta *>(q0),
-                                      wave, lane, nwaves);
+        td = trace_desc<MODE>(a, c, box, s_tx, s_rx, cur, lane);
+        stage_load<ET, QM>(a, c, td, st, wave, lane, nwaves);
+        stage_store<IP, QS, QM>(c, st, q0, wave, lane, nwaves);
     }
     __syncthreads();
 
@@ -621,14 +633,14 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     int bi = 0;
     while (cur.valid) {
         BatchDesc nxt = next_batch<MODE>(a, c, box, s_tx, s_rx, it);
-        if (nxt.valid) stage_load<MODE, ET, QM>(a, c, box, s_tx, s_rx, nxt, st, wave, lane, nwaves);
+        TraceDesc td_n = {0, 0.f, -1};
+        if (nxt.valid) {
+            td_n = trace_desc<MODE>(a, c, box, s_tx, s_rx, nxt, lane);
+            stage_load<ET, QM>(a, c, td_n, st, wave, lane, nwaves);
+        }
 
-        float4 *qb = (bi & 1) ? q1 : q0;
-        const Meta *meta = reinterpret_cast<const Meta *>(qb);
-        const float4 *quads = qb + c.nb;
-        // Lane l holds the metadata of trace slot l of the batch; terms read it
-        // with v_readlane (no LDS round trip per term).
-        const Meta mine = lane < c.nb ? meta[lane] : Meta{0, 0, 0.f, 0};
+        const float4 *quads = (bi & 1) ? q1 : q0;
+        const TraceDesc &mine = td;
         if constexpr (MODE == 1) {
             if (cur.j != row_j) {
                 row_j = cur.j;
@@ -650,7 +662,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                     const int e1 = __builtin_ctzll(mask);
                     mask &= mask - 1;
                     hercules_term<ET, IP, ZP>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2,
-                                              kf, rot,
+                                              ik2, rot,
                                               __int_as_float(__builtin_amdgcn_readlane(xi_bits, e1)),
                                               -__builtin_amdgcn_readlane(mine.w0, e1), acc);
                 }
@@ -660,16 +672,16 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                 mask &= mask - 1;
                 const int e2 = __builtin_ctzll(mask);
                 mask &= mask - 1;
-                hercules_term<ET, IP, ZP>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, kf,
+                hercules_term<ET, IP, ZP>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
                                           rot, __int_as_float(__builtin_amdgcn_readlane(xi_bits, e1)),
                                           -__builtin_amdgcn_readlane(mine.w0, e1), acc);
-                hercules_term<ET, IP, ZP>(Lp, quads + e2 * c.lmax * QS, c.lmax, s_hann, dy2, kf,
+                hercules_term<ET, IP, ZP>(Lp, quads + e2 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
                                           rot, __int_as_float(__builtin_amdgcn_readlane(xi_bits, e2)),
                                           -__builtin_amdgcn_readlane(mine.w0, e2), acc);
             }
             if (mask) {
                 const int e1 = __builtin_ctzll(mask);
-                hercules_term<ET, IP, ZP>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, kf,
+                hercules_term<ET, IP, ZP>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
                                           rot, __int_as_float(__builtin_amdgcn_readlane(xi_bits, e1)),
                                           -__builtin_amdgcn_readlane(mine.w0, e1), acc);
             }
@@ -716,11 +728,10 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
         }
 
         if (!nxt.valid) break;
-        float4 *nb_ = ((bi + 1) & 1) ? q1 : q0;
-        stage_store<MODE, IP, QS, QM>(c, s_tx, nxt, st, nb_ + c.nb, reinterpret_cast<Meta *>(nb_),
-                                      wave, lane, nwaves);
+        stage_store<IP, QS, QM>(c, st, ((bi + 1) & 1) ? q1 : q0, wave, lane, nwaves);
         __syncthreads();
         cur = nxt;
+        td = td_n;
         ++bi;
     }
     const long npts = (long)a.g.nx * a.g.ny * a.g.nz;
@@ -904,7 +915,7 @@ static hipError_t launch_lds_et(const DasArgs &a, const LdsCfg &c, int et, int i
 size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs)
 {
     return (size_t)(((n_tx + 3) & ~3) + ((n_ch + 3) & ~3)) * 4 + (size_t)HANN_TAB_PAD * 8 +
-           2 * (size_t)(nb * lmax * qs + nb) * 16;
+           2 * (size_t)nb * lmax * qs * 16;
 }
 
 hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, int ip,

@@ -277,7 +277,7 @@ def envelope_stage(torch, bfm, img, reps: int = 10):
     nbytes = 2 * img.numel() * 4
     gbps = nbytes / (res["fused_ms"] * 1e-3) / 1e9
     res["workload"] = (f"log envelope (60 dB) of the {tuple(img.shape)} RF volume, "
-                       f"radix-2 FFT analytic signal along depth ({img.shape[-1]})")
+                       f"FFT analytic signal along depth ({img.shape[-1]})")
     res["roofline"] = {"bound": "hbm", "achieved": round(gbps, 1), "peak": 8000.0, "unit": "GB/s",
                        "frac": round(gbps / 8000.0, 4), "traffic": None}
     return res

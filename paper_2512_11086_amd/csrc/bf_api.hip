@@ -234,7 +234,7 @@ int Frame::init(const bf_params &src)
     // wavefront tiles; HERCULES volumes = LDS windows, flat 8x8x1 lane tiles
     // with two depth points per lane in a 2x2x3 block (12 wavefronts,
     // 16x16x6 points: two such workgroups fill a CU's LDS) with as many traces
-    // per staged batch as the LDS cap allows (up to 48).
+    // per staged batch as the LDS cap and the staging rounds allow.
     if (p.mode == BF_FORCES_2D && (grid.ny == 1 || grid.nx == 1)) {
         // a plane: 16 x 4 points per wavefront along its lateral axis and depth
         if (grid.ny == 1) set_tile(4, 0, 2); else set_tile(0, 4, 2);
@@ -258,7 +258,7 @@ int Frame::init(const bf_params &src)
         nb = 40;
         if (p.mode == BF_HERCULES_3D && grid.nz >= 2) {
             variant = BF_DAS_LDS_Z2;
-            nb = 48;   // trimmed to the LDS cap by lds_config
+            nb = 48;   // trimmed to the LDS cap and staging rounds by lds_config
         }
     }
     sorted_tx = 1;

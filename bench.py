@@ -63,6 +63,25 @@ def active_terms(desc, dev) -> int:
     return total
 
 
+def algorithmic_flops(desc, n_act: int) -> float:
+    """FP32 flops (FMA = 2) the DAS definition needs for n_act active terms.
+
+    HERCULES (one radial receive path per term, plane or diverging transmit):
+    45 per active term (delay 13, apodization 14, cubic read 16, accumulate 2).
+    TPW and VLS separate into a transmit path per (point, transmit) and a
+    receive path with its apodization per (point, row): per active term the
+    two are added and read (add, floor, fract 3, cubic read 16, weighted
+    accumulate 2 = 21); per active (point, row) pair the receive path and
+    weight (13 + 14 = 27); per (point, transmit) the transmit path (TPW
+    x sin + z (cos - 1): 6; VLS distance to the line with its sign: 13)."""
+    if desc["mode"] not in ("tpw", "vls"):
+        return 45.0 * n_act
+    n_tx = desc["n_tx"]
+    n_pts = int(np.prod(desc["dims"]))
+    f_tx = 6 if desc["mode"] == "tpw" else 13
+    return n_act * (21.0 + 27.0 / n_tx) + f_tx * n_pts * n_tx
+
+
 def cpu_baseline(desc, H, rf, budget_s: float):
     """FP64 oracle on the host cores: full decode + DAS on a random voxel sample."""
     import oracle
@@ -311,7 +330,7 @@ def n4_workloads(torch, bfm, synth, reps: int = 2):
         dec_ms = ev[0].elapsed_time(ev[1]) / reps
         das_ms = ev[1].elapsed_time(ev[2]) / reps
         n_act = active_terms(desc, dev)
-        tf = n_act * 45 / (das_ms * 1e-3) / 1e12
+        tf = algorithmic_flops(desc, n_act) / (das_ms * 1e-3) / 1e12
         nominal = int(np.prod(desc["dims"])) * desc["n_tx"] * desc["n_ch"]
         res[name] = {"n_tx": desc["n_tx"], "decode_ms": round(dec_ms, 4),
                      "das_ms": round(das_ms, 3),

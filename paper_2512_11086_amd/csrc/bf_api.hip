@@ -184,6 +184,7 @@ int Frame::init(const bf_params &src)
         for (int i = 0; i < n; ++i) {
             const double th = p.tx_angles[i], sh = sin(0.5 * th);
             tx_sc.push_back(make_float2((float)sin(th), (float)(-2.0 * sh * sh)));   // cos - 1
+            tpw_smax = std::max(tpw_smax, fabs(sin(th)));
         }
     p.tx_angles = nullptr;
     tx.resize(n);
@@ -242,10 +243,12 @@ int Frame::init(const bf_params &src)
         nb = 4;
         variant = BF_DAS_GATHER;   // 2D windows are long for the LDS staging limit
     } else if (p.mode == BF_TPW_3D || p.mode == BF_VLS_3D) {
-        set_tile(3, 3, 0);         // gather kernel (separable transmit / receive paths)
+        // LDS windows, 4 rows x nb/4 transmits per batch (separable paths);
+        // VLS windows are longer (the path to the line changes along x too)
+        if (p.mode == BF_TPW_3D) set_tile(3, 3, 0); else set_tile(2, 3, 1);
         bw[0] = 2; bw[1] = 2; bw[2] = 3;
-        nb = 32;
-        variant = BF_DAS_GATHER;
+        nb = 64;                   // trimmed to the LDS cap and staging rounds
+        variant = BF_DAS_LDS;
     } else if (p.iq) {
         // IQ kernels hold more registers (complex accumulators and quads): two
         // 8-wavefront workgroups per CU
@@ -435,10 +438,26 @@ static size_t lds_cap_bytes()
 
 bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
 {
-    if (p.mode != BF_FORCES_2D && p.mode != BF_HERCULES_3D) return false;   // gather only
+    const bool sep = p.mode != BF_HERCULES_3D;   // separable: FORCES, TPW, VLS
     // points per lane along z: two for the HERCULES real-data variant
     const int zp = variant == BF_DAS_LDS_Z2 && z2_ok() ? 2 : 1;
     const int tx = bw[0] << lx, ty = bw[1] << ly, tz = (bw[2] << lz) * zp;
+    // VLS: the transmit path jumps at the virtual line's depth (converging
+    // above it, diverging below), so no box may hold points of both sides:
+    // the box grid is shifted along z to start a box where the side changes.
+    // The side is decided as in the kernels (FP32 depth minus FP32 line
+    // depth); depth must follow the z index alone.
+    int z_off = 0;
+    if (p.mode == BF_VLS_3D) {
+        if (grid.ax[2] != 0.0 || grid.ay[2] != 0.0) return false;
+        const float zf = (float)p.focal_depth;
+        auto below = [&](int iz) { return (float)(grid.org[2] + iz * grid.az[2]) - zf < 0.f; };
+        for (int iz = 1; iz < grid.nz; ++iz)
+            if (below(iz) != below(iz - 1)) {
+                z_off = (tz - iz % tz) % tz;
+                break;
+            }
+    }
     double E[3];
     for (int r = 0; r < 3; ++r)
         E[r] = fabs(grid.ax[r]) * (tx - 1) + fabs(grid.ay[r]) * (ty - 1) + fabs(grid.az[r]) * (tz - 1);
@@ -449,24 +468,33 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
     // rho / d <= 1 / sqrt(1 + 4 F#^2) inside the receive aperture
     // (F# rho / z < 1/2); points outside it have weight 0 and read a clamped
     // index.  Transmit paths are not apodized: rate 1 (FORCES column
-    // cylinder), and a diverging wave changes by at most the box diagonal.
+    // cylinder, and a VLS path over the box's x-z diagonal), |sin| of the
+    // steepest angle along x for TPW, and a diverging wave changes by at most
+    // the box diagonal.  Row receivers (TPW, VLS) see y and z only.
     const double lat = sqrt(E[0] * E[0] + E[1] * E[1]);
     const double srx = p.f_number > 0.0 ? 1.0 / sqrt(1.0 + 4.0 * p.f_number * p.f_number) : 1.0;
-    const double spread = p.mode == BF_FORCES_2D ? 2.0 * E[2] + (1.0 + srx) * E[0]
-                          : a.div_f > 0.0 ? E[2] + srx * lat + sqrt(lat * lat + E[2] * E[2])
-                                          : 2.0 * E[2] + srx * lat;
+    double spread;
+    switch (p.mode) {
+        case BF_FORCES_2D: spread = 2.0 * E[2] + (1.0 + srx) * E[0]; break;
+        case BF_TPW_3D: spread = 2.0 * E[2] + srx * E[1] + tpw_smax * E[0]; break;
+        case BF_VLS_3D: spread = E[2] + srx * E[1] + sqrt(E[0] * E[0] + E[2] * E[2]); break;
+        default:
+            spread = a.div_f > 0.0 ? E[2] + srx * lat + sqrt(lat * lat + E[2] * E[2])
+                                   : 2.0 * E[2] + srx * lat;
+    }
     // Window of an active point: its quad index floor(s) - w0 lies in
     // [1, k spread + 3] (the start w0 is floored 2 samples below the box's
     // lowest path, the quad covers taps n-1 .. n+2); one quad of FP32 slack.
     const int lmax = (int)ceil(a.k * spread) + 5;
     const int nthr = 64 * bw[0] * bw[1] * bw[2];
     int nbb = nb;
-    const int unit = p.mode == BF_FORCES_2D ? 4 : 1;
+    const int unit = sep ? 4 : 1;       // separable modes: 4 rows per batch
     const size_t lds_cap = lds_cap_bytes();
     const int nwaves = nthr / 64;
     // staging rounds per thread: the batch's quads dealt over the workgroup's
-    // threads; the kernels unroll 2 rounds (3 with two points per lane)
-    const int max_rounds = zp == 2 ? 3 : 2;
+    // threads; the kernels unroll 2 rounds (3 with two points per lane and
+    // for the row-column modes)
+    const int max_rounds = (zp == 2 || p.mode == BF_TPW_3D || p.mode == BF_VLS_3D) ? 3 : 2;
     auto rounds = [&](int n) { return (n * lmax + 64 * nwaves - 1) / (64 * nwaves); };
     const int qs = p.iq ? 2 : 1;
     while (nbb >= unit &&
@@ -484,9 +512,10 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
     cfg->tx_inv_dx = tx_inv_dx;
     cfg->inv_lmax = 1.0f / (float)lmax;
     cfg->zp = zp;
+    cfg->z_off = z_off;
     cfg->blocks_x = (grid.nx + tx - 1) / tx;
     cfg->blocks_y = (grid.ny + ty - 1) / ty;
-    cfg->blocks_z = (grid.nz + tz - 1) / tz;
+    cfg->blocks_z = (grid.nz + z_off + tz - 1) / tz;
     return true;
 }
 

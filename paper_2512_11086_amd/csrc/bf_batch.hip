@@ -462,7 +462,7 @@ int bf_autotune(bf_plan plan, const char *cache_path)
     if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
     if (e != hipSuccess) return hip_fail(e, "device query");
     // Tune the first frame of each mode; apply to every frame of that mode.
-    for (int mode = 0; mode < 2; ++mode) {
+    for (int mode = 0; mode < 4; ++mode) {
         Frame *f0 = nullptr;
         for (Frame *f : plan->frames)
             if (f->p.mode == mode) {

@@ -112,6 +112,8 @@ struct LdsCfg {
     float tx_x0, tx_inv_dx;
     float inv_lmax;      // 1 / lmax (staging: quad number -> (trace, quad))
     int zp;              // output points per lane along z (1, or 2 for HERCULES real data)
+    int z_off;           // box grid shift along z: box bz holds iz from bz * tz - z_off
+                         // (VLS: no box straddles the virtual line's depth)
 };
 
 // One frame of a batch for the persistent DAS kernel (device table entry).

@@ -17,11 +17,19 @@
 // the per-trace scalars of every term, and each wavefront's per-batch work
 // (aperture mask, trace metadata) serves twice the points.
 //
+// Separable modes (FORCES planes, TPW and VLS row-column volumes): the delay
+// is a transmit path per (point, transmit) plus a receive path per (point,
+// channel row), and the apodization depends on the row only.  A batch holds
+// 4 rows x nb/4 transmits; each lane computes the receive path and weight of
+// a row once, the transmit path of a transmit once, and every term adds the
+// two.
+//
 // Apodization skip (Sec. VII-F): a channel row is staged only if the receive
 // aperture of the deepest point of the box reaches it; within a row only the
 // transmits whose lateral offset can fall inside that aperture are staged
 // (HERCULES); each wavefront additionally skips traces outside the union of
-// its own lanes' apertures with a scalar test.
+// its own lanes' apertures with a scalar test (HERCULES), or rows no lane of
+// it can receive (separable modes).
 //
 // Delay precision: as in the gather kernel, s = B(p) + k (E_tx + E_rx) with
 // B in FP64 split into integer + FP32 fraction and E = rho^2 / (d + z) in FP32.
@@ -36,7 +44,7 @@ namespace bf {
 
 hipError_t launch_sum_groups(const DasArgs &a, hipStream_t s);
 
-constexpr int JC = 4;    // FORCES channel rows per batch
+constexpr int JC = 4;    // channel rows per batch of the separable modes (FORCES, TPW, VLS)
 constexpr int HANN_TAB_PAD = HANN_N + 2;   // table entries reserved in LDS (float2, keeps 16-byte alignment)
 
 // Trace slot `lane` of a batch, held by that lane of every wavefront: the
@@ -54,7 +62,7 @@ struct BatchDesc {
     int valid;
     int i0, cnt;          // transmits i0 .. i0+cnt-1
     int j;                // HERCULES: channel row
-    int rows[JC];         // FORCES: channel rows (-1 = none)
+    int rows[JC];         // separable modes: channel rows (-1 = none)
 };
 
 struct BoxGeom {
@@ -105,7 +113,7 @@ __device__ inline void lane_point(const DasArgs &a, const LdsCfg &c, int bx, int
     const int ly = lane >> (a.lz + a.lx);
     *ix = ((bx * c.bwx + wx) << a.lx) + lx;
     *iy = ((by * c.bwy + wy) << a.ly) + ly;
-    *iz = (((bz * c.bwz + wz) << a.lz) + lz) * c.zp + p;
+    *iz = (((bz * c.bwz + wz) << a.lz) + lz) * c.zp + p - c.z_off;
 }
 
 __device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, int by, int bz,
@@ -114,7 +122,7 @@ __device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, 
     LaneL L;
     int ix, iy, iz;
     lane_point(a, c, bx, by, bz, wave, lane, p, &ix, &iy, &iz);
-    L.valid = ix < a.g.nx && iy < a.g.ny && iz < a.g.nz;
+    L.valid = ix < a.g.nx && iy < a.g.ny && iz >= 0 && iz < a.g.nz;
     const double px = a.g.org[0] + ix * a.g.ax[0] + iy * a.g.ay[0] + iz * a.g.az[0];
     const double py = a.g.org[1] + ix * a.g.ax[1] + iy * a.g.ay[1] + iz * a.g.az[1];
     const double pz = a.g.org[2] + ix * a.g.ax[2] + iy * a.g.ay[2] + iz * a.g.az[2];
@@ -153,9 +161,9 @@ __device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, 
 __device__ inline BoxGeom block_box(const DasArgs &a, const LdsCfg &c, int bx, int by, int bz)
 {
     const int tx = c.bwx << a.lx, ty = c.bwy << a.ly, tz = (c.bwz << a.lz) * c.zp;
-    const int i0[3] = {bx * tx, by * ty, bz * tz};
+    const int i0[3] = {bx * tx, by * ty, max(bz * tz - c.z_off, 0)};
     const int i1[3] = {min(bx * tx + tx - 1, a.g.nx - 1), min(by * ty + ty - 1, a.g.ny - 1),
-                       min(bz * tz + tz - 1, a.g.nz - 1)};
+                       min(bz * tz + tz - 1 - c.z_off, a.g.nz - 1)};
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int q = 0; q < 8; ++q) {
         const int ix = (q & 1) ? i1[0] : i0[0];
@@ -200,22 +208,46 @@ __device__ inline float far_to_range(float v, float lo, float hi)
     return fmaxf(fabsf(v - lo), fabsf(v - hi));
 }
 
-// First sample interval of the staged window of one trace for the box.
-// (the bound has a 2-sample margin, so the hardware square root suffices)
+// First sample interval of the staged window of trace (transmit i, receive
+// channel at lateral coordinate cj) for the box: a lower bound of the path
+// over the box (the bound has a 2-sample margin, so the hardware square root
+// suffices).  Separable modes add the lower bounds of the transmit and the
+// receive path; the receive path of a row (TPW, VLS) or column (FORCES) is
+// at least its distance to the nearest box point at the shallowest depth.
 template <int MODE>
-__device__ inline int window_start(const BoxGeom &b, float xi, float cj)
+__device__ inline int window_start(const DasArgs &a, const BoxGeom &b, int i, float xi, float cj)
 {
     const float zlo = fmaxf(b.zmin, 0.f);
     float path;
-    if constexpr (MODE == 0) {
+    if constexpr (MODE == MODE_FORCES) {
         const float rt = dist_to_range(xi, b.xmin, b.xmax);
         const float rr = dist_to_range(cj, b.xmin, b.xmax);
         path = __builtin_amdgcn_sqrtf(fmaf(rt, rt, zlo * zlo)) +
                __builtin_amdgcn_sqrtf(fmaf(rr, rr, zlo * zlo));
-    } else {
+    } else if constexpr (MODE == MODE_HERCULES) {
         const float rx = dist_to_range(xi, b.xmin, b.xmax);
         const float ry = dist_to_range(cj, b.ymin, b.ymax);
         path = b.txlo + __builtin_amdgcn_sqrtf(fmaf(rx, rx, fmaf(ry, ry, zlo * zlo)));
+    } else {
+        const float ry = dist_to_range(cj, b.ymin, b.ymax);
+        float tx;
+        if constexpr (MODE == MODE_TPW) {
+            // x sin(th) + z cos(th): smallest at the box edge along sin(th), cos(th) > 0
+            const float2 sc = a.tx_sc[i];
+            tx = (sc.x >= 0.f ? b.xmin : b.xmax) * sc.x + zlo * (1.f + sc.y);
+        } else {
+            // z_f + sgn(z - z_f) |(x - x_i, z - z_f)|: with the whole box below the
+            // line the nearest point bounds it; else z_f minus the farthest reach
+            const float zf = a.zf;
+            if (zf <= zlo) {
+                const float rx = dist_to_range(xi, b.xmin, b.xmax);
+                tx = zf + __builtin_amdgcn_sqrtf(fmaf(rx, rx, (zlo - zf) * (zlo - zf)));
+            } else {
+                const float rf = far_to_range(xi, b.xmin, b.xmax);
+                tx = zf - __builtin_amdgcn_sqrtf(fmaf(rf, rf, (zf - zlo) * (zf - zlo)));
+            }
+        }
+        path = tx + __builtin_amdgcn_sqrtf(fmaf(ry, ry, zlo * zlo));
     }
     return (int)floorf(fmaf(path, b.kf, -b.t0f)) - 2;
 }
@@ -303,7 +335,13 @@ __device__ inline BatchDesc next_batch(const DasArgs &a, const LdsCfg &c, const 
             for (int q = 0; q < JC; ++q) it.rows[q] = -1;
             while (n < JC && it.j < it.jend) {
                 float R;
-                if (row_active<0>(a, b, s_rx[it.j], &R)) it.rows[n++] = it.j;
+                if (row_active<MODE>(a, b, s_rx[it.j], &R)) {
+                    // (selects instead of a dynamic index keep rows[] in registers)
+#pragma unroll
+                    for (int q = 0; q < JC; ++q)
+                        if (q == n) it.rows[q] = it.j;
+                    ++n;
+                }
                 ++it.j;
             }
             if (n == 0) return d;
@@ -327,14 +365,21 @@ __device__ inline void slot_trace(const BatchDesc &d, const LdsCfg &c, int e, in
     } else {
         const int nbi = c.nb / JC;
         const int ii = e % nbi, jj = e / nbi;
+        int row = -1;
+#pragma unroll
+        for (int q = 0; q < JC; ++q)
+            if (q == jj) row = d.rows[q];
         *i = d.i0 + ii;
-        *j = (ii < d.cnt) ? d.rows[jj] : -1;
+        *j = (ii < d.cnt) ? row : -1;
     }
 }
 
 // Staging rounds per thread per batch (the host keeps nb * lmax within
-// QM * 64 * wavefronts): 2, or 3 for the two-point kernel.
-template <int ZP> struct StageRounds { static constexpr int value = ZP == 2 ? 3 : 2; };
+// QM * 64 * wavefronts): 3 for the two-point kernel and the row-column
+// modes (longer windows), else 2.
+template <int MODE, int ZP> struct StageRounds {
+    static constexpr int value = (ZP == 2 || MODE == MODE_TPW || MODE == MODE_VLS) ? 3 : 2;
+};
 
 // Staging map: the nb * lmax quads of a batch are numbered trace-major and
 // dealt to the workgroup's threads in order (round q, wavefront, lane), so no
@@ -370,7 +415,7 @@ __device__ inline TraceDesc trace_desc(const DasArgs &a, const LdsCfg &c, const 
         slot_trace<MODE>(d, c, lane, &i, &j);
         if (j >= 0) {
             t.xi = s_tx[i];
-            t.w0 = window_start<MODE>(b, t.xi, s_rx[j]);
+            t.w0 = window_start<MODE>(a, b, i, t.xi, s_rx[j]);
             t.tr = i * a.n_ch + j;
         }
     }
@@ -564,7 +609,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                                  float4 *smem)
 {
     static_assert(ZP == 1 || MODE == MODE_HERCULES, "two points per lane: HERCULES only");
-    constexpr int QM = StageRounds<ZP>::value;
+    constexpr int QM = StageRounds<MODE, ZP>::value;
     const int nthr = blockDim.x;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -692,7 +737,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                 if (cur.rows[q] != rows_cur[q]) {
                     rows_cur[q] = cur.rows[q];
                     if (rows_cur[q] >= 0) {
-                        const float dxr = L.x - s_rx[rows_cur[q]];
+                        const float dxr = rx_coord<MODE>(L.x, L.y) - s_rx[rows_cur[q]];
                         const float r2 = dxr * dxr;
                         const bool act = r2 < L.thr;
                         Rj[q] = fmaf(excess(r2, L.z, L.z2), kf, L.fB);
@@ -704,9 +749,8 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                 }
             }
             for (int ii = 0; ii < cur.cnt; ++ii) {
-                const float xi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.xi), ii));
-                const float dxt = L.x - xi;
-                const float T = kf * excess(dxt * dxt, L.z, L.z2);
+                // transmit excess path of this lane, shared by the batch's rows
+                const float T = kf * tx_excess<MODE>(a, L.x, L.z, L.z2, cur.i0 + ii);
 #pragma unroll
                 for (int q = 0; q < JC; ++q) {
                     if (!row_on[q]) continue;
@@ -744,7 +788,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     for (int p = 0; p < ZP; ++p) {
         int ix, iy, iz;
         lane_point(a, c, bx, by, bz, wave, lane_e, p, &ix, &iy, &iz);
-        if (ix < a.g.nx && iy < a.g.ny && iz < a.g.nz) {
+        if (ix < a.g.nx && iy < a.g.ny && iz >= 0 && iz < a.g.nz) {
             const long idx = ((long)iy * a.g.nx + ix) * a.g.nz + iz;
             const double pz = a.g.org[2] + ix * a.g.ax[2] + iy * a.g.ay[2] + iz * a.g.az[2];
             const float2 v = pz > 0.0 ? acc[p] : make_float2(0.f, 0.f);
@@ -756,12 +800,14 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     }
 }
 
-// Two points per lane: registers capped for 6 wavefronts per SIMD (two
-// 12-wavefront workgroups per CU).
-template <int ZP> struct WavesPerEu { static constexpr int value = ZP == 2 ? 6 : 1; };
+// Two points per lane and the row-column modes: registers capped for 6
+// wavefronts per SIMD (two 12-wavefront workgroups per CU).
+template <int MODE, int ZP> struct WavesPerEu {
+    static constexpr int value = (ZP == 2 || MODE == MODE_TPW || MODE == MODE_VLS) ? 6 : 1;
+};
 
 template <int MODE, int ET, int IP, int ZP>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerEu<ZP>::value)))
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerEu<MODE, ZP>::value)))
 void das_lds_kernel(DasArgs a, LdsCfg c)
 {
     extern __shared__ float4 smem[];
@@ -772,7 +818,7 @@ void das_lds_kernel(DasArgs a, LdsCfg c)
 // items from a queue until it is empty.  Items are ordered by decreasing
 // cost on the host, so the queue balances uneven frames.
 template <int MODE, int ET, int IP, int ZP>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerEu<ZP>::value)))
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerEu<MODE, ZP>::value)))
 void das_persistent_kernel(const FrameDas *__restrict__ frames,
                                                               const int2 *__restrict__ items,
                                                               int n_items, int *counter,
@@ -847,7 +893,13 @@ static hipError_t launch_persistent1(const PersistentLaunch &p, hipStream_t s)
 
 hipError_t launch_das_persistent(const PersistentLaunch &p, hipStream_t s)
 {
-    return p.mode == 0 ? launch_persistent1<0>(p, s) : launch_persistent1<1>(p, s);
+    switch (p.mode) {
+        case MODE_FORCES: return launch_persistent1<MODE_FORCES>(p, s);
+        case MODE_HERCULES: return launch_persistent1<MODE_HERCULES>(p, s);
+        case MODE_TPW: return launch_persistent1<MODE_TPW>(p, s);
+        case MODE_VLS: return launch_persistent1<MODE_VLS>(p, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // Workgroups of the persistent DAS kernel that fit on the device at once.
@@ -922,9 +974,14 @@ hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, i
                           hipStream_t s)
 {
     const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, a.cx ? 2 : 1);
-    if (mode != MODE_FORCES && mode != MODE_HERCULES) return hipErrorInvalidValue;
-    hipError_t err = mode == MODE_FORCES ? launch_lds_et<MODE_FORCES>(a, c, et, ip, shm, s)
-                                         : launch_lds_et<MODE_HERCULES>(a, c, et, ip, shm, s);
+    hipError_t err;
+    switch (mode) {
+        case MODE_FORCES: err = launch_lds_et<MODE_FORCES>(a, c, et, ip, shm, s); break;
+        case MODE_HERCULES: err = launch_lds_et<MODE_HERCULES>(a, c, et, ip, shm, s); break;
+        case MODE_TPW: err = launch_lds_et<MODE_TPW>(a, c, et, ip, shm, s); break;
+        case MODE_VLS: err = launch_lds_et<MODE_VLS>(a, c, et, ip, shm, s); break;
+        default: return hipErrorInvalidValue;
+    }
     if (err != hipSuccess || a.groups <= 1) return err;
     return launch_sum_groups(a, s);
 }

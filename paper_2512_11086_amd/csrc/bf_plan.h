@@ -30,6 +30,7 @@ struct Frame {
     int sorted_tx = 0;           // transmit columns ascending
     int uniform_tx = 0;          // transmit columns equally spaced (ascending)
     float tx_x0 = 0.f, tx_inv_dx = 0.f;
+    double tpw_smax = 0.0;       // TPW: largest |sin| of the transmit angles
     int groups = 1;              // channel groups of the DAS launch (small grids)
     float *d_part = nullptr;     // [groups][points] partial images
     float2 *d_hann = nullptr;    // Hann weight table (HANN_N + 1 entries)

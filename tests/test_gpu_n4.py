@@ -59,8 +59,7 @@ def test_small_volumes_match_oracle(torch_mod, mode, kw, interp):
     H, rf = _data(d, 3, encoded=mode == "hercules")
     ref = oracle.das(d, _decode_oracle(H, rf))
     plan = bfm.Plan(d, H)
-    variants = ["gather"] + (["lds"] if mode == "hercules" else [])
-    for v in variants:
+    for v in ("gather", "lds"):
         if v == "lds":
             plan.set_das_config("lds", (2, 2, 1), 8)
             assert plan.info()["variant"] == 0
@@ -69,6 +68,46 @@ def test_small_volumes_match_oracle(torch_mod, mode, kw, interp):
         got = plan.das(plan.decode(torch.from_numpy(rf).cuda())).cpu().numpy()
         err = rel_l2(got, ref)
         assert err <= (1e-4 if interp == "nearest" else 1e-5), (v, err)
+
+
+@pytest.mark.parametrize("mode, kw", CASES[:3])
+@pytest.mark.parametrize("tile, block, nb", [
+    ((3, 3, 0), (2, 2, 3), 48), ((2, 2, 2), (1, 1, 1), 4), ((1, 1, 4), (2, 2, 2), 16),
+    ((0, 0, 6), (1, 1, 2), 64), ((3, 3, 0), (4, 2, 1), 32),
+])
+def test_separable_lds_configurations(torch_mod, mode, kw, tile, block, nb):
+    # row-column volumes on the LDS kernel: window bounds per transmit model
+    # (tilted plane, virtual line behind or in front of the volume), batches
+    # of 4 rows x nb/4 transmits, several lane tiles and workgroup shapes
+    torch = torch_mod
+    d = _small(mode, **kw)
+    H, rf = _data(d, 11, encoded=False)
+    ref = oracle.das(d, _decode_oracle(H, rf))
+    plan = bfm.Plan(d, H, tile=tile)
+    plan.set_das_config("lds", block, nb)
+    got = plan.das(plan.decode(torch.from_numpy(rf).cuda())).cpu().numpy()
+    assert rel_l2(got, ref) <= 1e-5, (tile, block, nb, plan.info())
+
+
+@pytest.mark.parametrize("mode, kw", [("tpw", {}), ("vls", dict(focal_depth=5.1 * MM)),
+                                      ("vls", dict(focal_depth=2.6 * MM))])
+def test_separable_lds_volume_through_the_focus_and_array_plane(torch_mod, mode, kw):
+    # depths from -0.5 mm (behind the array: zero output) past a virtual line
+    # inside the volume (VLS: converging above, diverging below it; the
+    # transmit path jumps at the line's depth, which no LDS box may straddle)
+    torch = torch_mod
+    n = 16
+    extra = dict(tx_angles=np.deg2rad(np.linspace(-12, 12, n))) if mode == "tpw" else {}
+    d = describe(mode, (n, n), (0.3 * MM, 0.3 * MM), n, n, 700, 20e6, 5e6, (17, 15, 41),
+                 (-2 * MM, -1.5 * MM, -0.5 * MM), (2 * MM, 1.5 * MM, 9.5 * MM), t0=0.5e-6,
+                 **extra, **kw)
+    H, rf = _data(d, 12, encoded=False)
+    ref = oracle.das(d, _decode_oracle(H, rf))
+    plan = bfm.Plan(d, H)
+    plan.set_das_config("lds", (2, 2, 2), 16)
+    got = plan.das(plan.decode(torch.from_numpy(rf).cuda())).cpu().numpy()
+    assert np.all(got[..., :3] == 0)
+    assert rel_l2(got, ref) <= 1e-5
 
 
 def test_unencoded_decode_is_exact_copy(torch_mod):
@@ -106,6 +145,35 @@ def test_full_size_workloads_sampled(torch_mod, k):
     vox = sample_voxels(img.size, 256, k)
     ref = oracle.das_points(desc, _decode_oracle(H, rf), vox)
     assert rel_l2(img[vox], ref) <= 1e-5, rel_l2(img[vox], ref)
+
+
+def test_row_column_batch_and_graph(torch_mod):
+    # TPW and VLS frames (LDS kernel, persistent path) with a FORCES plane in
+    # one batch: oracle parity per frame, graph replays equal the eager run
+    torch = torch_mod
+    frames = []
+    for k, (mode, kw) in enumerate([("tpw", {}), ("vls", dict(focal_depth=-4 * MM)),
+                                    ("vls", dict(focal_depth=6.1 * MM))]):
+        d = _small(mode, **kw)
+        frames.append((d,) + _data(d, 20 + k, encoded=False))
+    descs = [f[0] for f in frames]
+    bp = bfm.BatchPlan(descs, [f[1] for f in frames])      # unencoded: no Hadamard matrix
+    rf_d = [torch.from_numpy(f[2]).cuda() for f in frames]
+    outs = [torch.empty(s, device="cuda") for s in bp.out_shapes]
+    bp.run(rf_d, outs)
+    torch.cuda.synchronize()
+    for (d, H, rf), o in zip(frames, outs):
+        ref = oracle.das(d, _decode_oracle(H, rf))
+        assert rel_l2(o.cpu().numpy(), ref) <= 1e-5, d["mode"]
+    eager = [o.clone() for o in outs]
+    for rep in range(2):
+        outs2 = [torch.full(s, float("nan"), device="cuda") for s in bp.out_shapes]
+        bp.graph_launch(rf_d, outs2)
+        junk = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for o, r in zip(outs2, eager):
+            assert torch.equal(o, r), rep
 
 
 def test_cross_plane_batch_and_graph(torch_mod):

@@ -231,17 +231,23 @@ int Frame::init(const bf_params &src)
     grid.ny = p.out_dims[1];
     grid.nz = p.out_dims[2];
     // Default DAS workgroups (fastest in measured sweeps on MI355X; the
-    // autotuner can replace them): 2D = the direct-gather kernel on 16x4-point
+    // autotuner can replace them): planes = LDS windows on 16x4-point
     // wavefront tiles; HERCULES volumes = LDS windows, flat 8x8x1 lane tiles
     // with two depth points per lane in a 2x2x3 block (12 wavefronts,
     // 16x16x6 points: two such workgroups fill a CU's LDS) with as many traces
     // per staged batch as the LDS cap and the staging rounds allow.
     if (p.mode == BF_FORCES_2D && (grid.ny == 1 || grid.nx == 1)) {
-        // a plane: 16 x 4 points per wavefront along its lateral axis and depth
-        if (grid.ny == 1) set_tile(4, 0, 2); else set_tile(0, 4, 2);
-        bw[0] = 2; bw[1] = 1; bw[2] = 2;
-        nb = 4;
-        variant = BF_DAS_GATHER;   // 2D windows are long for the LDS staging limit
+        // a plane: 16 x 4 points per wavefront along its lateral axis and
+        // depth, 4 x 4 wavefronts per LDS workgroup (64 x 16 points), batches
+        // of 4 rows x 4 transmits
+        if (grid.ny == 1) {
+            set_tile(4, 0, 2);
+            bw[0] = 4; bw[1] = 1; bw[2] = 4;
+        } else {
+            set_tile(0, 4, 2);
+            bw[0] = 1; bw[1] = 4; bw[2] = 4;
+        }
+        nb = 16;
     } else if (p.mode == BF_TPW_3D || p.mode == BF_VLS_3D) {
         // LDS windows, 4 rows x nb/4 transmits per batch (separable paths);
         // VLS windows are longer (the path to the line changes along x too)
@@ -250,11 +256,11 @@ int Frame::init(const bf_params &src)
         nb = 64;                   // trimmed to the LDS cap and staging rounds
         variant = BF_DAS_LDS;
     } else if (p.iq) {
-        // IQ kernels hold more registers (complex accumulators and quads): two
-        // 8-wavefront workgroups per CU
+        // IQ (complex accumulators and quads, one point per lane): 12-wavefront
+        // workgroups as for real data, batches up to the LDS cap
         set_tile(3, 3, 0);
-        bw[0] = 4; bw[1] = 2; bw[2] = 1;
-        nb = 24;
+        bw[0] = 2; bw[1] = 2; bw[2] = 3;
+        nb = 48;
     } else {
         set_tile(3, 3, 0);
         bw[0] = 2; bw[1] = 2; bw[2] = 3;

@@ -60,7 +60,8 @@ struct Batch {
     int *d_counters = nullptr;
     std::vector<DecClass> dec;
     std::vector<DasClass> das;
-    std::vector<int> gather_frames;   // frames whose window does not fit in LDS
+    std::vector<int> gather_frames;   // frames on the gather kernel (no LDS fit, or a class too
+                                      // small to fill the chip)
     void **h_stage[RING] = {};
     hipEvent_t ev[RING] = {};
     int ring = 0;
@@ -97,6 +98,34 @@ static int build_batch(bf_plan plan)
     b->F = F;
     std::vector<FrameDec> fdec(F);
     std::vector<FrameDas> fdas(F);
+    int dev0 = 0, cus0 = 0;
+    (void)hipGetDevice(&dev0);
+    (void)hipDeviceGetAttribute(&cus0, hipDeviceAttributeMultiprocessorCount, dev0);
+    // LDS frames of a kernel class run as one persistent launch over their
+    // boxes; a class with fewer boxes than two per CU (e.g. a pair of small
+    // planes) would leave the chip idle, so its frames take the gather kernel,
+    // which splits the channel sum over workgroups instead.
+    std::vector<int> lds_ok(F, 0);
+    {
+        std::vector<std::pair<long, long>> cls_boxes;   // (class key, boxes)
+        std::vector<long> key(F, -1);
+        for (int f = 0; f < F; ++f) {
+            Frame &fr = *plan->frames[f];
+            DasArgs a = fr.das_args(nullptr, nullptr, fr.p.c);
+            LdsCfg c;
+            if (fr.variant == BF_DAS_GATHER || !fr.lds_config(a, &c)) continue;
+            key[f] = ((((long)fr.p.mode * 8 + fr.p.e_type) * 8 + fr.p.interp) * 4 + c.zp) * 2048 +
+                     64 * c.bwx * c.bwy * c.bwz;
+            const long nblk = (long)c.blocks_x * c.blocks_y * c.blocks_z;
+            bool found = false;
+            for (auto &kb : cls_boxes)
+                if (kb.first == key[f]) { kb.second += nblk; found = true; }
+            if (!found) cls_boxes.push_back({key[f], nblk});
+        }
+        for (int f = 0; f < F; ++f)
+            for (auto &kb : cls_boxes)
+                if (key[f] >= 0 && kb.first == key[f]) lds_ok[f] = kb.second >= 2L * cus0;
+    }
     for (int f = 0; f < F; ++f) {
         Frame &fr = *plan->frames[f];
         if (!fr.d_e) {
@@ -108,7 +137,7 @@ static int build_batch(bf_plan plan)
         a.groups = 1;
         a.part = nullptr;
         LdsCfg c;
-        if (fr.variant == BF_DAS_GATHER || !fr.lds_config(a, &c)) {
+        if (!lds_ok[f] || !fr.lds_config(a, &c)) {
             b->gather_frames.push_back(f);
             memset(&c, 0, sizeof c);
         } else {

@@ -118,3 +118,51 @@ def test_autotune_choice_is_valid_and_cached(torch_mod, tmp_path):
     info2 = p2.autotune(cache)      # served from the cache
     assert info2["tile"] == info["tile"] and info2["block"] == info["block"]
     assert len(open(cache).read().strip().splitlines()) == 1
+
+
+def _big_frames(seed):
+    # enough LDS boxes per kernel class (>= 2 per CU) for the persistent path:
+    # four FORCES planes of 512 x 256 points and four HERCULES volumes of
+    # 64 x 64 x 60 points (two depth points per lane)
+    rng = np.random.default_rng(seed)
+    out = []
+    for f in range(8):
+        n_tx = 32
+        cols = np.arange(32)
+        if f % 2 == 0:
+            d = describe("forces", (32, 16), (0.2 * MM, 0.2 * MM), n_tx, 32, 800, 20e6, 5e6,
+                         (512, 1, 256), (-3.2 * MM, 0, 3 * MM), (3.2 * MM, 0, 14 * MM),
+                         tx_elements=cols)
+        else:
+            d = describe("hercules", (32, 16), (0.2 * MM, 0.2 * MM), n_tx, 16, 800, 20e6, 5e6,
+                         (64, 64, 60), (-3 * MM, -1.5 * MM, 3 * MM), (3 * MM, 1.5 * MM, 10 * MM),
+                         tx_elements=cols)
+        H = synth.hadamard_sylvester(n_tx)
+        pts = rng.uniform([-2 * MM, -1 * MM, 4 * MM], [2 * MM, 1 * MM, 9 * MM], size=(5, 3))
+        if d["mode"] == "forces":
+            pts[:, 1] = 0
+        rf = synth.acquire(d, pts, np.ones(5), rng, H=H)
+        out.append((d, H, rf))
+    return out
+
+
+def test_persistent_lds_classes_and_graph(torch_mod):
+    torch = torch_mod
+    frames = _big_frames(7)
+    bp = bfm.BatchPlan([f[0] for f in frames], [f[1] for f in frames])
+    rfs = [torch.from_numpy(f[2]).cuda() for f in frames]
+    outs = [torch.empty(s, device="cuda") for s in bp.out_shapes]
+    bp.run(rfs, outs)
+    torch.cuda.synchronize()
+    for (d, H, rf), o in zip(frames, outs):
+        ref = oracle.das(d, oracle.decode(H, rf))
+        assert rel_l2(o.cpu().numpy(), ref) <= 1e-5, d["mode"]
+    eager = [o.clone() for o in outs]
+    for rep in range(2):
+        outs2 = [torch.full(s, float("nan"), device="cuda") for s in bp.out_shapes]
+        bp.graph_launch(rfs, outs2)
+        junk = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for o, r in zip(outs2, eager):
+            assert torch.equal(o, r), rep

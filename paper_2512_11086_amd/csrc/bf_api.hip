@@ -492,6 +492,10 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
     // [1, k spread + 3] (the start w0 is floored 2 samples below the box's
     // lowest path, the quad covers taps n-1 .. n+2); one quad of FP32 slack.
     const int lmax = (int)ceil(a.k * spread) + 5;
+    // HERCULES reads without an index clamp: a lane outside its aperture
+    // (weight 0) may reach past its window by at most the receive path's
+    // extra lateral slope, (1 - srx) lat, into the next window or this guard
+    const int guard = sep ? 0 : (int)ceil(a.k * (1.0 - srx) * lat) + 3;
     const int nthr = 64 * bw[0] * bw[1] * bw[2];
     int nbb = nb;
     const int unit = sep ? 4 : 1;       // separable modes: 4 rows per batch
@@ -504,7 +508,7 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
     auto rounds = [&](int n) { return (n * lmax + 64 * nwaves - 1) / (64 * nwaves); };
     const int qs = p.iq ? 2 : 1;
     while (nbb >= unit &&
-           (rounds(nbb) > max_rounds || lds_bytes(p.n_tx, p.n_ch, nbb, lmax, qs) > lds_cap))
+           (rounds(nbb) > max_rounds || lds_bytes(p.n_tx, p.n_ch, nbb, lmax, qs, guard) > lds_cap))
         nbb -= unit;
     if (nbb < unit || nthr > 1024) return false;
     cfg->bwx = bw[0];
@@ -519,6 +523,7 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
     cfg->inv_lmax = 1.0f / (float)lmax;
     cfg->zp = zp;
     cfg->z_off = z_off;
+    cfg->guard = guard;
     cfg->blocks_x = (grid.nx + tx - 1) / tx;
     cfg->blocks_y = (grid.ny + ty - 1) / ty;
     cfg->blocks_z = (grid.nz + z_off + tz - 1) / tz;

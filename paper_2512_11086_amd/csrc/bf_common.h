@@ -114,6 +114,8 @@ struct LdsCfg {
     int zp;              // output points per lane along z (1, or 2 for HERCULES real data)
     int z_off;           // box grid shift along z: box bz holds iz from bz * tz - z_off
                          // (VLS: no box straddles the virtual line's depth)
+    int guard;           // zeroed sample intervals after the second window buffer
+                         // (HERCULES: reads of lanes outside their aperture)
 };
 
 // One frame of a batch for the persistent DAS kernel (device table entry).

@@ -116,6 +116,7 @@ __device__ inline void lane_point(const DasArgs &a, const LdsCfg &c, int bx, int
     *iz = (((bz * c.bwz + wz) << a.lz) + lz) * c.zp + p - c.z_off;
 }
 
+template <int MODE>
 __device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, int by, int bz,
                                      int wave, int lane, int p)
 {
@@ -123,12 +124,37 @@ __device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, 
     int ix, iy, iz;
     lane_point(a, c, bx, by, bz, wave, lane, p, &ix, &iy, &iz);
     L.valid = ix < a.g.nx && iy < a.g.ny && iz >= 0 && iz < a.g.nz;
+    if constexpr (MODE == MODE_HERCULES) {
+        // HERCULES reads its windows without clamping the index, so every lane
+        // takes the geometry of the nearest grid point of its box: its delay
+        // then lies within the box's bounds (see hercules_term)
+        ix = min(ix, a.g.nx - 1);
+        iy = min(iy, a.g.ny - 1);
+        iz = min(max(iz, 0), a.g.nz - 1);
+    }
     const double px = a.g.org[0] + ix * a.g.ax[0] + iy * a.g.ay[0] + iz * a.g.az[0];
     const double py = a.g.org[1] + ix * a.g.ax[1] + iy * a.g.ay[1] + iz * a.g.az[1];
     const double pz = a.g.org[2] + ix * a.g.ax[2] + iy * a.g.ay[2] + iz * a.g.az[2];
     L.x = (float)px;
     L.y = (float)py;
-    if (L.valid && pz > 0.0) {
+    if constexpr (MODE == MODE_HERCULES) {
+        // a point on or behind the array plane (its output is 0) is evaluated
+        // just in front of it, inside the box; it and any lane outside the
+        // grid stay out of the wavefront's aperture mask (thr < 0)
+        const double pze = fmax(pz, 1e-7);
+        const double B = (tx_path(a, px, py, pze) + pze) * a.k - a.t0fs;
+        const double fl = floor(B);
+        L.nB = (int)fl;
+        L.fB = (float)(B - fl);
+        L.z = (float)pze;
+        L.z2 = L.z * L.z;
+        L.zk = (float)(pze / a.k);
+        L.zk2 = L.zk * L.zk;
+        L.thr = (L.valid && pz > 0.0) ? (a.f2 > 0.f ? L.z2 * 0.25f / a.f2 : __builtin_inff()) : -1.f;
+        L.wsc = a.f2 > 0.f ? a.f2 / L.z2 : 0.f;
+        L.wtab = L.wsc * (4.f * HANN_N);
+        L.ph0 = phase_origin(a, L.nB);
+    } else if (L.valid && pz > 0.0) {
         const double B = (tx_path(a, px, py, pz) + pz) * a.k - a.t0fs;
         const double fl = floor(B);
         L.nB = (int)fl;
@@ -594,11 +620,16 @@ __device__ inline void hercules_term(const LaneL (&L)[ZP], const float4 *win, in
         const float xw = rho2 * L[p].wtab;
         const float2 h = hann[min((unsigned)cvt_flr(xw), (unsigned)HANN_N)];
         const float w = fmaf(__builtin_amdgcn_fractf(xw), h.y, h.x);
+        // no clamp: li lies in [-1, lmax + guard) for every lane (its
+        // geometry is inside the box); -1 reads the finite LDS word before the
+        // windows, and lanes outside their aperture (weight exactly 0) may
+        // read past their window into the next one or the zeroed guard
+        const float t = __builtin_amdgcn_fractf(s);
         if constexpr (ET == ET_CF32) {
-            const float2 v = read_quad_cx<IP>(win, li, lmax, __builtin_amdgcn_fractf(s));
+            const float2 v = make_float2(eval_quad<IP>(win[2 * li], t), eval_quad<IP>(win[2 * li + 1], t));
             rotate_acc(v, w, fmaf(rot, s, L[p].ph0), acc[p]);
         } else {
-            const float v = read_quad<IP>(win, li, lmax, __builtin_amdgcn_fractf(s));
+            const float v = eval_quad<IP>(win[li], t);
             acc[p].x = fmaf(w, v, acc[p].x);
         }
     }
@@ -626,7 +657,10 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     for (int t = tid; t < a.n_tx; t += nthr) s_tx[t] = a.tx_x[t];
     for (int t = tid; t < a.n_ch; t += nthr) s_rx[t] = a.rx_c[t];
     if constexpr (MODE == 1)
-        for (int t = tid; t <= HANN_N; t += nthr) s_hann[t] = a.hann_tab[t];
+        for (int t = tid; t < HANN_TAB_PAD; t += nthr)
+            s_hann[t] = t <= HANN_N ? a.hann_tab[t] : make_float2(0.f, 0.f);
+    if constexpr (MODE == MODE_HERCULES)   // finite data wherever an unclamped read can land
+        for (int t = tid; t < buf_quads + c.guard * QS; t += nthr) q1[t] = make_float4(0.f, 0.f, 0.f, 0.f);
 
     const int bz = blk % c.blocks_z;
     const int bx = (blk / c.blocks_z) % c.blocks_x;
@@ -634,7 +668,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     const BoxGeom box = block_box(a, c, bx, by, bz);
     LaneL Lp[ZP];
 #pragma unroll
-    for (int p = 0; p < ZP; ++p) Lp[p] = lane_setup_l(a, c, bx, by, bz, wave, lane, p);
+    for (int p = 0; p < ZP; ++p) Lp[p] = lane_setup_l<MODE>(a, c, bx, by, bz, wave, lane, p);
     const LaneL &L = Lp[0];
     // largest rho^2 bound of the receive aperture over the lane's points
     float thr_l = Lp[0].thr;
@@ -964,16 +998,16 @@ static hipError_t launch_lds_et(const DasArgs &a, const LdsCfg &c, int et, int i
     }
 }
 
-size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs)
+size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard)
 {
     return (size_t)(((n_tx + 3) & ~3) + ((n_ch + 3) & ~3)) * 4 + (size_t)HANN_TAB_PAD * 8 +
-           2 * (size_t)nb * lmax * qs * 16;
+           (2 * (size_t)nb * lmax + guard) * qs * 16;
 }
 
 hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, int ip,
                           hipStream_t s)
 {
-    const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, a.cx ? 2 : 1);
+    const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, a.cx ? 2 : 1, c.guard);
     hipError_t err;
     switch (mode) {
         case MODE_FORCES: err = launch_lds_et<MODE_FORCES>(a, c, et, ip, shm, s); break;

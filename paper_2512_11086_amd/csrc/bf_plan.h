@@ -66,7 +66,7 @@ struct Batch;   // persistent batched path state (bf_batch.hip)
 hipError_t launch_das(const DasArgs &a, int mode, int et, int ip, hipStream_t s);
 hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, int ip,
                           hipStream_t s);
-size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs);
+size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard);
 
 constexpr uint32_t BF_PLAN_MAGIC = 0xBF0C0DE5u;
 

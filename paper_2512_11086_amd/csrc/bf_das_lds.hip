@@ -530,6 +530,21 @@ __device__ inline float4 coef_quad(float pm, float p0, float p1, float p2)
         return make_float4(p0, p1, 0.f, 0.f);
 }
 
+// Negated window starts of a batch's slots into LDS (wavefront 0, lane =
+// slot): HERCULES in slot order; the separable modes as [transmit][row], so
+// one 16-byte load gives the 4 rows of a transmit.
+template <int MODE>
+__device__ inline void store_w0(const LdsCfg &c, const TraceDesc &td, int *w, int wave, int lane)
+{
+    if (wave != 0 || lane >= c.nb) return;
+    if constexpr (MODE == MODE_HERCULES) {
+        w[lane] = -td.w0;
+    } else {
+        const int nbi = c.nb / JC;
+        w[(lane % nbi) * JC + lane / nbi] = -td.w0;
+    }
+}
+
 // Convert the loaded taps to coefficient quads and write them to one LDS
 // buffer.  QS = quads per sample interval (2 for IQ data: real part, then
 // imaginary part).
@@ -590,11 +605,11 @@ __device__ inline int cvt_flr(float x)
     return r;
 }
 
-// a + b + c in one instruction (c wave-uniform)
-__device__ inline int add3_i32(int a, int b, int c)
+// a + b + c in one instruction
+__device__ inline int add3_vvv(int a, int b, int c)
 {
     int r;
-    asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
     return r;
 }
 
@@ -607,7 +622,7 @@ __device__ inline int add3_i32(int a, int b, int c)
 template <int ET, int IP, int ZP>
 __device__ inline void hercules_term(const LaneL (&L)[ZP], const float4 *win, int lmax,
                                      const float2 *hann, float dy2, float ik2, float rot, float xi,
-                                     int neg_w0, float2 (&acc)[ZP])
+                                     int neg_w0, float2 (&acc)[ZP])   // neg_w0: from LDS
 {
     const float dx = L[0].x - xi;
     const float rho2 = fmaf(dx, dx, dy2);
@@ -615,7 +630,7 @@ __device__ inline void hercules_term(const LaneL (&L)[ZP], const float4 *win, in
     for (int p = 0; p < ZP; ++p) {
         const float dk = __builtin_amdgcn_sqrtf(fmaf(rho2, ik2, L[p].zk2));
         const float s = fmaf(rho2, __builtin_amdgcn_rcpf(dk + L[p].zk), L[p].fB);
-        const int li = add3_i32(cvt_flr(s), L[p].nB, neg_w0);
+        const int li = add3_vvv(cvt_flr(s), L[p].nB, neg_w0);
         // Hann weight from the LDS table; u^2 >= 1/4 lands on the (0, 0) entry
         const float xw = rho2 * L[p].wtab;
         const float2 h = hann[min((unsigned)cvt_flr(xw), (unsigned)HANN_N)];
@@ -646,10 +661,16 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     const int wave = tid >> 6, lane = tid & 63;
     const int nwaves = nthr >> 6;
 
-    // tables: tx_x, rx_c, Hann weights, then two buffers of [nb * lmax] quads
+    // tables: tx_x, rx_c, the window starts of the two batch buffers (negated;
+    // read by the terms with one LDS load instead of a lane broadcast), Hann
+    // weights, then two buffers of [nb * lmax] quads (the Hann table sits
+    // right before them: an index of -1 reads finite data)
     float *s_tx = reinterpret_cast<float *>(smem);
     float *s_rx = s_tx + ((a.n_tx + 3) & ~3);
-    float2 *s_hann = reinterpret_cast<float2 *>(s_rx + ((a.n_ch + 3) & ~3));
+    int *s_w0[2];
+    s_w0[0] = reinterpret_cast<int *>(s_rx + ((a.n_ch + 3) & ~3));
+    s_w0[1] = s_w0[0] + ((c.nb + 3) & ~3);
+    float2 *s_hann = reinterpret_cast<float2 *>(s_w0[1] + ((c.nb + 3) & ~3));
     float4 *bufbase = reinterpret_cast<float4 *>(s_hann + HANN_TAB_PAD);
     constexpr int QS = ET == ET_CF32 ? 2 : 1;     // quads per sample interval
     const int buf_quads = c.nb * c.lmax * QS;
@@ -698,6 +719,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
         td = trace_desc<MODE>(a, c, box, s_tx, s_rx, cur, lane);
         stage_load<ET, QM>(a, c, td, st, wave, lane, nwaves);
         stage_store<IP, QS, QM>(c, st, q0, wave, lane, nwaves);
+        store_w0<MODE>(c, td, s_w0[0], wave, lane);
     }
     __syncthreads();
 
@@ -734,16 +756,18 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
             // (a contiguous run: the columns are sorted within a batch), in
             // pairs whose LDS reads overlap, then an odd last one
             uint64_t mask = __ballot(lane < cur.cnt && mine.xi >= wlo && mine.xi <= whi);
-            const int xi_bits = __float_as_int(mine.xi);
+            // per trace: the column position from the read-only table through
+            // the scalar cache (uniform index) and the negated window start
+            // from LDS -- no lane broadcasts (their SGPR results stall the wave)
+            const float *__restrict__ txcol = a.tx_x + cur.i0;
+            const int *wst = s_w0[bi & 1];
             if constexpr (ZP == 2) {
                 // one trace per step already gives two independent terms
                 while (mask) {
                     const int e1 = __builtin_ctzll(mask);
                     mask &= mask - 1;
                     hercules_term<ET, IP, ZP>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2,
-                                              ik2, rot,
-                                              __int_as_float(__builtin_amdgcn_readlane(xi_bits, e1)),
-                                              -__builtin_amdgcn_readlane(mine.w0, e1), acc);
+                                              ik2, rot, txcol[e1], wst[e1], acc);
                 }
             }
             while (mask & (mask - 1)) {
@@ -752,17 +776,14 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                 const int e2 = __builtin_ctzll(mask);
                 mask &= mask - 1;
                 hercules_term<ET, IP, ZP>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
-                                          rot, __int_as_float(__builtin_amdgcn_readlane(xi_bits, e1)),
-                                          -__builtin_amdgcn_readlane(mine.w0, e1), acc);
+                                          rot, txcol[e1], wst[e1], acc);
                 hercules_term<ET, IP, ZP>(Lp, quads + e2 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
-                                          rot, __int_as_float(__builtin_amdgcn_readlane(xi_bits, e2)),
-                                          -__builtin_amdgcn_readlane(mine.w0, e2), acc);
+                                          rot, txcol[e2], wst[e2], acc);
             }
             if (mask) {
                 const int e1 = __builtin_ctzll(mask);
                 hercules_term<ET, IP, ZP>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
-                                          rot, __int_as_float(__builtin_amdgcn_readlane(xi_bits, e1)),
-                                          -__builtin_amdgcn_readlane(mine.w0, e1), acc);
+                                          rot, txcol[e1], wst[e1], acc);
             }
         } else {
             const int nbi = c.nb / JC;
@@ -782,16 +803,18 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                     }
                 }
             }
+            const int4 *wst4 = reinterpret_cast<const int4 *>(s_w0[bi & 1]);
             for (int ii = 0; ii < cur.cnt; ++ii) {
                 // transmit excess path of this lane, shared by the batch's rows
                 const float T = kf * tx_excess<MODE>(a, L.x, L.z, L.z2, cur.i0 + ii);
+                const int4 nw4 = wst4[ii];    // negated window starts of the 4 rows
+                const int nw[JC] = {nw4.x, nw4.y, nw4.z, nw4.w};
 #pragma unroll
                 for (int q = 0; q < JC; ++q) {
                     if (!row_on[q]) continue;
                     const int e = q * nbi + ii;
-                    const int w0 = __builtin_amdgcn_readlane(mine.w0, e);
                     const float sq = Rj[q] + T;
-                    const int li = (int)floorf(sq) + L.nB - w0;
+                    const int li = (int)floorf(sq) + L.nB + nw[q];
                     if constexpr (ET == ET_CF32) {
                         const float2 v = read_quad_cx<IP>(quads + e * c.lmax * QS, li, c.lmax,
                                                           __builtin_amdgcn_fractf(sq));
@@ -807,6 +830,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
 
         if (!nxt.valid) break;
         stage_store<IP, QS, QM>(c, st, ((bi + 1) & 1) ? q1 : q0, wave, lane, nwaves);
+        store_w0<MODE>(c, td_n, s_w0[(bi + 1) & 1], wave, lane);
         __syncthreads();
         cur = nxt;
         td = td_n;
@@ -1000,8 +1024,8 @@ static hipError_t launch_lds_et(const DasArgs &a, const LdsCfg &c, int et, int i
 
 size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard)
 {
-    return (size_t)(((n_tx + 3) & ~3) + ((n_ch + 3) & ~3)) * 4 + (size_t)HANN_TAB_PAD * 8 +
-           (2 * (size_t)nb * lmax + guard) * qs * 16;
+    return (size_t)(((n_tx + 3) & ~3) + ((n_ch + 3) & ~3) + 2 * ((nb + 3) & ~3)) * 4 +
+           (size_t)HANN_TAB_PAD * 8 + (2 * (size_t)nb * lmax + guard) * qs * 16;
 }
 
 hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, int ip,

@@ -272,22 +272,30 @@ __device__ inline float rx_coord(float x, float y)
 //   VLS:    virtual line source (x_i, z_f):   z_f + sgn(z - z_f) |(x - x_i, z - z_f)| - z
 //           = sgn(dz) rho^2 / (|(rho, dz)| + |dz|),  rho = x - x_i, dz = z - z_f
 //           (exact rewriting without cancellation; sgn(0) = +1)
+// The same from the transmit's table entries: tsc = (sin, cos - 1) for TPW,
+// xi = column position for FORCES and VLS.
 template <int MODE>
-__device__ inline float tx_excess(const DasArgs &a, float x, float z, float z2, int i)
+__device__ inline float tx_excess_p(float x, float z, float z2, float2 tsc, float xi, float zf)
 {
     if constexpr (MODE == MODE_TPW) {
-        const float2 sc = a.tx_sc[i];
-        return fmaf(x, sc.x, z * sc.y);
+        return fmaf(x, tsc.x, z * tsc.y);
     } else if constexpr (MODE == MODE_VLS) {
-        const float rho = x - a.tx_x[i], dz = z - a.zf;
+        const float rho = x - xi, dz = z - zf;
         const float r2 = rho * rho;
         const float den = __builtin_amdgcn_sqrtf(fmaf(dz, dz, r2)) + fabsf(dz);
         const float e = den > 0.f ? r2 * __builtin_amdgcn_rcpf(den) : 0.f;   // 0 on the line
         return dz >= 0.f ? e : -e;
     } else {
-        const float dxt = x - a.tx_x[i];
+        const float dxt = x - xi;
         return excess(dxt * dxt, z, z2);
     }
+}
+
+template <int MODE>
+__device__ inline float tx_excess(const DasArgs &a, float x, float z, float z2, int i)
+{
+    return tx_excess_p<MODE>(x, z, z2, MODE == MODE_TPW ? a.tx_sc[i] : make_float2(0.f, 0.f),
+                             MODE == MODE_TPW ? 0.f : a.tx_x[i], a.zf);
 }
 
 template <int ET>

@@ -667,10 +667,10 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     // right before them: an index of -1 reads finite data)
     float *s_tx = reinterpret_cast<float *>(smem);
     float *s_rx = s_tx + ((a.n_tx + 3) & ~3);
-    int *s_w0[2];
-    s_w0[0] = reinterpret_cast<int *>(s_rx + ((a.n_ch + 3) & ~3));
-    s_w0[1] = s_w0[0] + ((c.nb + 3) & ~3);
-    float2 *s_hann = reinterpret_cast<float2 *>(s_w0[1] + ((c.nb + 3) & ~3));
+    // (indexed from one base so that the compiler keeps them in LDS)
+    int *s_w0 = reinterpret_cast<int *>(s_rx + ((a.n_ch + 3) & ~3));
+    const int w0_stride = (c.nb + 3) & ~3;
+    float2 *s_hann = reinterpret_cast<float2 *>(s_w0 + 2 * w0_stride);
     float4 *bufbase = reinterpret_cast<float4 *>(s_hann + HANN_TAB_PAD);
     constexpr int QS = ET == ET_CF32 ? 2 : 1;     // quads per sample interval
     const int buf_quads = c.nb * c.lmax * QS;
@@ -719,7 +719,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
         td = trace_desc<MODE>(a, c, box, s_tx, s_rx, cur, lane);
         stage_load<ET, QM>(a, c, td, st, wave, lane, nwaves);
         stage_store<IP, QS, QM>(c, st, q0, wave, lane, nwaves);
-        store_w0<MODE>(c, td, s_w0[0], wave, lane);
+        store_w0<MODE>(c, td, s_w0, wave, lane);
     }
     __syncthreads();
 
@@ -760,7 +760,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
             // the scalar cache (uniform index) and the negated window start
             // from LDS -- no lane broadcasts (their SGPR results stall the wave)
             const float *__restrict__ txcol = a.tx_x + cur.i0;
-            const int *wst = s_w0[bi & 1];
+            const int *wst = s_w0 + (bi & 1) * w0_stride;
             if constexpr (ZP == 2) {
                 // one trace per step already gives two independent terms
                 while (mask) {
@@ -803,10 +803,17 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                     }
                 }
             }
-            const int4 *wst4 = reinterpret_cast<const int4 *>(s_w0[bi & 1]);
+            const int4 *wst4 = reinterpret_cast<const int4 *>(s_w0 + (bi & 1) * w0_stride);
+            // the transmits' table entries through the scalar cache (uniform)
+            const float *__restrict__ tscf = reinterpret_cast<const float *>(a.tx_sc) + 2 * cur.i0;
+            const float *__restrict__ txc = a.tx_x + cur.i0;
             for (int ii = 0; ii < cur.cnt; ++ii) {
                 // transmit excess path of this lane, shared by the batch's rows
-                const float T = kf * tx_excess<MODE>(a, L.x, L.z, L.z2, cur.i0 + ii);
+                const float T =
+                    kf * tx_excess_p<MODE>(L.x, L.z, L.z2,
+                                           MODE == MODE_TPW ? make_float2(tscf[2 * ii], tscf[2 * ii + 1])
+                                                            : make_float2(0.f, 0.f),
+                                           MODE == MODE_TPW ? 0.f : txc[ii], a.zf);
                 const int4 nw4 = wst4[ii];    // negated window starts of the 4 rows
                 const int nw[JC] = {nw4.x, nw4.y, nw4.z, nw4.w};
 #pragma unroll
@@ -830,7 +837,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
 
         if (!nxt.valid) break;
         stage_store<IP, QS, QM>(c, st, ((bi + 1) & 1) ? q1 : q0, wave, lane, nwaves);
-        store_w0<MODE>(c, td_n, s_w0[(bi + 1) & 1], wave, lane);
+        store_w0<MODE>(c, td_n, s_w0 + ((bi + 1) & 1) * w0_stride, wave, lane);
         __syncthreads();
         cur = nxt;
         td = td_n;

@@ -302,6 +302,62 @@ def envelope_stage(torch, bfm, img, reps: int = 10):
     return res
 
 
+def autofocus_stage(torch, bfm, synth, reps: int = 5):
+    """Differentiable FORCES workload (256x256 plane, 64 tx x 64 ch, 2048
+    samples, 8 frames): per frame the forward DAS, the sharpness loss with its
+    image gradient, and the adjoint for dL/dc alone (the autofocus gradient)
+    and with the RF gradient (FP32 atomics into a 64 x 64 x 2048 buffer).
+    Adjoint roofline: per active term the delay (13) and apodization (14),
+    the Hermite derivative read (14) and the weighted accumulation of
+    v'(s) ds/dc (4) = 45 flops."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    desc, H, rfs, info = synth.make_inputs(3)
+    plan = bfm.Plan(desc, H)
+    es = [plan.decode(torch.from_numpy(r).to(dev)) for r in rfs]
+    c = float(info["c_true"])
+    img = plan.das(es[0], c=c)
+    loss, g = bfm.sharpness(img.reshape(1, -1))
+    ge, gc = plan.das_adjoint(es[0], g.reshape(img.shape), c=c)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    ev[0].record(stream)
+    for _ in range(reps):
+        for e in es:
+            plan.das(e, c=c, out=img)
+    ev[1].record(stream)
+    for _ in range(reps):
+        for e in es:
+            bfm.sharpness(img.reshape(1, -1))
+    ev[2].record(stream)
+    for _ in range(reps):
+        for e in es:
+            plan.das_adjoint(e, g.reshape(img.shape), c=c, want_e=False)
+    ev[3].record(stream)
+    for _ in range(reps):
+        plan.das_adjoint(es[0], g.reshape(img.shape), c=c, want_e=True)
+    ev[4].record(stream)
+    torch.cuda.synchronize()
+    nf = len(es)
+    fwd_ms = ev[0].elapsed_time(ev[1]) / (reps * nf)
+    sh_ms = ev[1].elapsed_time(ev[2]) / (reps * nf)
+    adj_ms = ev[2].elapsed_time(ev[3]) / (reps * nf)
+    adj_e_ms = ev[3].elapsed_time(ev[4]) / reps
+    n_act = active_terms(desc, dev)
+    tf = n_act * 45 / (adj_ms * 1e-3) / 1e12
+    step = fwd_ms + sh_ms + adj_ms
+    nominal = int(np.prod(desc["dims"])) * desc["n_tx"] * desc["n_ch"]
+    return {"workload": "FORCES 256x256 plane, 64 tx x 64 ch x 2048 samples, 8 frames: "
+                        "DAS + sharpness + adjoint dL/dc per frame",
+            "das_ms": round(fwd_ms, 4), "sharpness_ms": round(sh_ms, 4),
+            "adjoint_c_ms": round(adj_ms, 4), "adjoint_e_and_c_ms": round(adj_e_ms, 4),
+            "gradient_step_ms_per_frame": round(step, 4),
+            "value": round(nominal / (step * 1e-3) / 1e9, 2), "unit": "G samples/s",
+            "adjoint_roofline": {"bound": "alu", "achieved": round(tf, 2),
+                                 "peak": round(FP32_NONPACKED_TFLOPS, 1), "unit": "TFLOP/s",
+                                 "frac": round(tf / FP32_NONPACKED_TFLOPS, 4)}}
+
+
 def n4_workloads(torch, bfm, synth, reps: int = 2):
     """Decode + DAS of the additional transmit models at the headline volume
     size (128x128 array, 2048 samples, 128x128x256 voxels): diverging-wave
@@ -370,6 +426,8 @@ def main():
     ap.add_argument("--no-iq", action="store_true", help="skip the demodulation + IQ pipeline")
     ap.add_argument("--iq-reps", type=int, default=3)
     ap.add_argument("--no-n4", action="store_true", help="skip the TPW / VLS / diverging workloads")
+    ap.add_argument("--no-autofocus", action="store_true",
+                    help="skip the differentiable FORCES workload (adjoint, sharpness)")
     ap.add_argument("--traffic", action="store_true",
                     help="only run the short kernel sequence used for counter collection")
     args = ap.parse_args()
@@ -461,6 +519,9 @@ def main():
         log(f"IQ pipeline {res['iq']['ms_per_step']:.3f} ms")
     if not args.no_n4:
         res["n4"] = n4_workloads(torch, bfm, synth)
+    if not args.no_autofocus:
+        res["autofocus"] = autofocus_stage(torch, bfm, synth)
+        log(f"autofocus step {res['autofocus']['gradient_step_ms_per_frame']:.3f} ms per frame")
     if not args.no_batch:
         res["batched"] = batched_comparison(torch, bfm, synth, args.batch_reps)
     if not args.no_cpu:

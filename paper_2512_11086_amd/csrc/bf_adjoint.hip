@@ -158,6 +158,12 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double *part
     if (threadIdx.x == 0) *out = (float)red[0];
 }
 
+hipError_t launch_reduce_partials(const double *partial, int n, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, s, partial, n, out);
+    return hipGetLastError();
+}
+
 __global__ void fill_kernel(float *p, long n, float v)
 {
     for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n;

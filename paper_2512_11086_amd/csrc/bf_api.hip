@@ -297,14 +297,19 @@ int Frame::init(const bf_params &src)
                                   hipMemcpyHostToDevice);
         if (he != hipSuccess) return hip_fail(he, "upload of the TPW angle table");
     }
-    max_blocks = 0;
-    for (int lx = 0; lx <= 6; ++lx)        // partial-sum buffer large enough for any tile
+    // partial-sum buffer of the adjoint, large enough for any tile: one entry
+    // per 4-wavefront block (gather kernel) or per (LDS box, channel group);
+    // a box holds at least one wavefront and the channel split keeps
+    // groups x wavefronts below wavefronts + 8192
+    long max_waves = 0;
+    for (int lx = 0; lx <= 6; ++lx)
         for (int ly = 0; ly + lx <= 6; ++ly) {
             const int lz = 6 - lx - ly;
             const long w = (long)((grid.nx + (1 << lx) - 1) >> lx) *
                            ((grid.ny + (1 << ly) - 1) >> ly) * ((grid.nz + (1 << lz) - 1) >> lz);
-            if ((w + 3) / 4 > max_blocks) max_blocks = (w + 3) / 4;
+            if (w > max_waves) max_waves = w;
         }
+    max_blocks = max_waves + 8192;
     d_partial = (double *)alloc((size_t)max_blocks * sizeof(double));
     {
         // Eq. 3 in double precision at u^2 = k / (4 HANN_N), value + slope
@@ -733,8 +738,18 @@ int bf_das_adjoint(bf_plan plan, const void *e, const float *grad_out, double c,
     DasArgs a = f.das_args(e, nullptr, c);
     a.grad_out = grad_out;
     a.grad_e = grad_e;
-    hipError_t err = launch_das_adjoint(a, f.p.mode, f.p.e_type, f.p.interp, grad_c,
-                                        (hipStream_t)stream);
+    // dL/dc alone (the autofocus gradient) runs the LDS-staged kernel for FP32
+    // data and linear / cubic reads; the RF gradient and the other cases run
+    // the gather adjoint (FP32 atomics into grad_e)
+    LdsCfg cfg;
+    const bool lds = !grad_e && grad_c && f.p.e_type == BF_E_F32 &&
+                     f.p.interp != BF_INTERP_NEAREST && f.variant != BF_DAS_GATHER &&
+                     f.lds_config(a, &cfg) &&
+                     (long)cfg.blocks_x * cfg.blocks_y * cfg.blocks_z * a.groups <= f.max_blocks;
+    hipError_t err = lds ? launch_das_lds_adjoint_c(a, cfg, f.p.mode, f.p.interp, grad_c,
+                                                    (hipStream_t)stream)
+                         : launch_das_adjoint(a, f.p.mode, f.p.e_type, f.p.interp, grad_c,
+                                              (hipStream_t)stream);
     return err == hipSuccess ? BF_OK : hip_fail(err, "DAS adjoint launch");
 }
 

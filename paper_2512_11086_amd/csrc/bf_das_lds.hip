@@ -518,6 +518,28 @@ __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const Trace
 }
 
 // Coefficient quad of one sample interval from taps p[n-1] .. p[n+2].
+// Derivative quad of one sample interval (the adjoint's dL/dc): v'(t) =
+// d1 + d2 t + d3 t^2 = (c1, 2 c2, 3 c3) of the cubic; the slope of the linear
+// read; 0 for nearest (piecewise constant).
+template <int IP>
+__device__ inline float4 coef_dquad(float pm, float p0, float p1, float p2)
+{
+    if constexpr (IP == IN_CUBIC)
+        return make_float4(0.5f * (p1 - pm), 2.f * (pm - 2.5f * p0 + 2.0f * p1 - 0.5f * p2),
+                           3.f * (0.5f * (p2 - pm) + 1.5f * (p0 - p1)), 0.f);
+    else if constexpr (IP == IN_LINEAR)
+        return make_float4(p1 - p0, 0.f, 0.f, 0.f);
+    else
+        return make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+template <int IP>
+__device__ inline float eval_dquad(const float4 q, float t)
+{
+    if constexpr (IP == IN_CUBIC) return fmaf(t, fmaf(t, q.z, q.y), q.x);
+    return q.x;
+}
+
 template <int IP>
 __device__ inline float4 coef_quad(float pm, float p0, float p1, float p2)
 {
@@ -548,7 +570,7 @@ __device__ inline void store_w0(const LdsCfg &c, const TraceDesc &td, int *w, in
 // Convert the loaded taps to coefficient quads and write them to one LDS
 // buffer.  QS = quads per sample interval (2 for IQ data: real part, then
 // imaginary part).
-template <int IP, int QS, int QM>
+template <int IP, int QS, int QM, bool ADJ>
 __device__ inline void stage_store(const LdsCfg &c, const Staged<QM> &st, float4 *quads, int wave,
                                    int lane, int nwaves)
 {
@@ -557,7 +579,8 @@ __device__ inline void stage_store(const LdsCfg &c, const Staged<QM> &st, float4
         int e, m;
         if (stage_slot(c, q, wave, lane, nwaves, &e, &m)) {
             const float *t = st.p[q];
-            quads[(e * c.lmax + m) * QS] = coef_quad<IP>(t[0], t[1], t[2], t[3]);
+            quads[(e * c.lmax + m) * QS] = ADJ ? coef_dquad<IP>(t[0], t[1], t[2], t[3])
+                                               : coef_quad<IP>(t[0], t[1], t[2], t[3]);
             if constexpr (QS == 2)
                 quads[(e * c.lmax + m) * 2 + 1] = coef_quad<IP>(t[4], t[5], t[6], t[7]);
         }
@@ -619,7 +642,7 @@ __device__ inline int add3_vvv(int a, int b, int c)
 // samples, k rho^2 / (d + z), is evaluated as rho^2 / (d/k + z/k) with
 // d/k = sqrt(rho^2 / k^2 + (z/k)^2): the scale k is folded into the lane
 // constants (ik2 = 1 / k^2).
-template <int ET, int IP, int ZP>
+template <int ET, int IP, int ZP, bool ADJ>
 __device__ inline void hercules_term(const LaneL (&L)[ZP], const float4 *win, int lmax,
                                      const float2 *hann, float dy2, float ik2, float rot, float xi,
                                      int neg_w0, float2 (&acc)[ZP])   // neg_w0: from LDS
@@ -643,6 +666,11 @@ __device__ inline void hercules_term(const LaneL (&L)[ZP], const float4 *win, in
         if constexpr (ET == ET_CF32) {
             const float2 v = make_float2(eval_quad<IP>(win[2 * li], t), eval_quad<IP>(win[2 * li + 1], t));
             rotate_acc(v, w, fmaf(rot, s, L[p].ph0), acc[p]);
+        } else if constexpr (ADJ) {
+            // adjoint (dL/dc): sums of w v'(s) and w v'(s) s (derivative quads)
+            const float wv = w * eval_dquad<IP>(win[li], t);
+            acc[p].x += wv;
+            acc[p].y = fmaf(wv, s, acc[p].y);
         } else {
             const float v = eval_quad<IP>(win[li], t);
             acc[p].x = fmaf(w, v, acc[p].x);
@@ -650,10 +678,15 @@ __device__ inline void hercules_term(const LaneL (&L)[ZP], const float4 *win, in
     }
 }
 
-template <int MODE, int ET, int IP, int ZP>
+// ADJ: the adjoint for dL/dc instead of the image: the staged quads hold the
+// read's derivative, each point accumulates sum w v'(s) and sum w v'(s) s, and
+// the workgroup writes its FP64 partial of dL/dc = -1/c sum_p G(p) sum_terms
+// w v'(s) (s + nB + t0 fs) (the delay's derivative: ds/dc = -(s_abs + t0 fs)/c).
+template <int MODE, int ET, int IP, int ZP, bool ADJ = false>
 __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int grp,
                                  float4 *smem)
 {
+    static_assert(!ADJ || ET != ET_CF32, "the adjoint is defined for real data");
     static_assert(ZP == 1 || MODE == MODE_HERCULES, "two points per lane: HERCULES only");
     constexpr int QM = StageRounds<MODE, ZP>::value;
     const int nthr = blockDim.x;
@@ -718,7 +751,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     if (cur.valid) {
         td = trace_desc<MODE>(a, c, box, s_tx, s_rx, cur, lane);
         stage_load<ET, QM>(a, c, td, st, wave, lane, nwaves);
-        stage_store<IP, QS, QM>(c, st, q0, wave, lane, nwaves);
+        stage_store<IP, QS, QM, ADJ>(c, st, q0, wave, lane, nwaves);
         store_w0<MODE>(c, td, s_w0, wave, lane);
     }
     __syncthreads();
@@ -766,7 +799,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                 while (mask) {
                     const int e1 = __builtin_ctzll(mask);
                     mask &= mask - 1;
-                    hercules_term<ET, IP, ZP>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2,
+                    hercules_term<ET, IP, ZP, ADJ>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2,
                                               ik2, rot, txcol[e1], wst[e1], acc);
                 }
             }
@@ -775,14 +808,14 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                 mask &= mask - 1;
                 const int e2 = __builtin_ctzll(mask);
                 mask &= mask - 1;
-                hercules_term<ET, IP, ZP>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
+                hercules_term<ET, IP, ZP, ADJ>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
                                           rot, txcol[e1], wst[e1], acc);
-                hercules_term<ET, IP, ZP>(Lp, quads + e2 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
+                hercules_term<ET, IP, ZP, ADJ>(Lp, quads + e2 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
                                           rot, txcol[e2], wst[e2], acc);
             }
             if (mask) {
                 const int e1 = __builtin_ctzll(mask);
-                hercules_term<ET, IP, ZP>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
+                hercules_term<ET, IP, ZP, ADJ>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
                                           rot, txcol[e1], wst[e1], acc);
             }
         } else {
@@ -826,6 +859,12 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                         const float2 v = read_quad_cx<IP>(quads + e * c.lmax * QS, li, c.lmax,
                                                           __builtin_amdgcn_fractf(sq));
                         rotate_acc(v, aj[q], fmaf(rot, sq, L.ph0), acc[0]);
+                    } else if constexpr (ADJ) {
+                        const float wv = aj[q] * eval_dquad<IP>(
+                                                     quads[e * c.lmax + clamp0_i32(li, c.lmax - 1)],
+                                                     __builtin_amdgcn_fractf(sq));
+                        acc[0].x += wv;
+                        acc[0].y = fmaf(wv, sq, acc[0].y);
                     } else {
                         const float v = read_quad<IP>(quads + e * c.lmax, li, c.lmax,
                                                       __builtin_amdgcn_fractf(sq));
@@ -836,19 +875,45 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
         }
 
         if (!nxt.valid) break;
-        stage_store<IP, QS, QM>(c, st, ((bi + 1) & 1) ? q1 : q0, wave, lane, nwaves);
+        stage_store<IP, QS, QM, ADJ>(c, st, ((bi + 1) & 1) ? q1 : q0, wave, lane, nwaves);
         store_w0<MODE>(c, td_n, s_w0 + ((bi + 1) & 1) * w0_stride, wave, lane);
         __syncthreads();
         cur = nxt;
         td = td_n;
         ++bi;
     }
-    const long npts = (long)a.g.nx * a.g.ny * a.g.nz;
-    float *dst = a.groups > 1 ? a.part + (long)grp * npts * QS : das_out(a);
     // the point indices are recomputed here (an opaque copy of the lane
     // number), so they hold no registers during the loop
     int lane_e = lane;
     asm volatile("" : "+v"(lane_e));
+    if constexpr (ADJ) {
+        double contrib = 0.0;
+#pragma unroll
+        for (int p = 0; p < ZP; ++p) {
+            int ix, iy, iz;
+            lane_point(a, c, bx, by, bz, wave, lane_e, p, &ix, &iy, &iz);
+            if (ix < a.g.nx && iy < a.g.ny && iz >= 0 && iz < a.g.nz) {
+                const double pz = a.g.org[2] + ix * a.g.ax[2] + iy * a.g.ay[2] + iz * a.g.az[2];
+                if (pz > 0.0) {
+                    const double G = a.grad_out[((long)iy * a.g.nx + ix) * a.g.nz + iz];
+                    contrib += G * ((double)acc[p].y + ((double)Lp[p].nB + a.t0fs) * (double)acc[p].x);
+                }
+            }
+        }
+        // workgroup sum in a fixed order -> one partial per (box, channel group)
+        __shared__ double red[16];
+        for (int off = 32; off > 0; off >>= 1) contrib += __shfl_down(contrib, off, 64);
+        if (lane == 0) red[wave] = contrib;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < nwaves; ++w) t += red[w];
+            a.partial[(long)grp * gridDim.x + blockIdx.x] = -t / a.c;
+        }
+        return;
+    }
+    const long npts = (long)a.g.nx * a.g.ny * a.g.nz;
+    float *dst = a.groups > 1 ? a.part + (long)grp * npts * QS : das_out(a);
 #pragma unroll
     for (int p = 0; p < ZP; ++p) {
         int ix, iy, iz;
@@ -877,6 +942,15 @@ void das_lds_kernel(DasArgs a, LdsCfg c)
 {
     extern __shared__ float4 smem[];
     das_block<MODE, ET, IP, ZP>(a, c, blockIdx.x, blockIdx.y, smem);
+}
+
+// dL/dc of the DAS image (real data): one FP64 partial per (box, channel group).
+template <int MODE, int IP, int ZP>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerEu<MODE, ZP>::value)))
+void das_lds_adj_kernel(DasArgs a, LdsCfg c)
+{
+    extern __shared__ float4 smem[];
+    das_block<MODE, ET_F32, IP, ZP, true>(a, c, blockIdx.x, blockIdx.y, smem);
 }
 
 // Persistent form for a batch of frames: each workgroup pulls (frame, box)
@@ -1027,6 +1101,56 @@ static hipError_t launch_lds_et(const DasArgs &a, const LdsCfg &c, int et, int i
         case ET_CF32: return launch_lds_ip<MODE, ET_CF32>(a, c, ip, shm, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_reduce_partials(const double *partial, int n, float *out, hipStream_t s);
+size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard);
+
+template <int MODE, int IP, int ZP>
+static hipError_t launch_adj_lds3(const DasArgs &a, const LdsCfg &c, size_t shm, hipStream_t s)
+{
+    const int nthr = 64 * c.bwx * c.bwy * c.bwz;
+    dim3 grid(c.blocks_x * c.blocks_y * c.blocks_z, a.groups);
+    hipError_t e = allow_lds(reinterpret_cast<const void *>(&das_lds_adj_kernel<MODE, IP, ZP>), shm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((das_lds_adj_kernel<MODE, IP, ZP>), grid, dim3(nthr), shm, s, a, c);
+    return hipGetLastError();
+}
+
+template <int MODE, int IP>
+static hipError_t launch_adj_lds2(const DasArgs &a, const LdsCfg &c, size_t shm, hipStream_t s)
+{
+    if constexpr (MODE == MODE_HERCULES)
+        if (c.zp == 2) return launch_adj_lds3<MODE, IP, 2>(a, c, shm, s);
+    return c.zp == 1 ? launch_adj_lds3<MODE, IP, 1>(a, c, shm, s) : hipErrorInvalidValue;
+}
+
+template <int MODE>
+static hipError_t launch_adj_lds1(const DasArgs &a, const LdsCfg &c, int ip, size_t shm, hipStream_t s)
+{
+    switch (ip) {
+        case IN_LINEAR: return launch_adj_lds2<MODE, IN_LINEAR>(a, c, shm, s);
+        case IN_CUBIC: return launch_adj_lds2<MODE, IN_CUBIC>(a, c, shm, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// dL/dc with the LDS-staged kernel (FP32 data, linear or cubic reads): the
+// workgroups' partials, then their sum in a fixed order into grad_c.
+hipError_t launch_das_lds_adjoint_c(const DasArgs &a, const LdsCfg &c, int mode, int ip,
+                                    float *grad_c, hipStream_t s)
+{
+    const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, 1, c.guard);
+    hipError_t err;
+    switch (mode) {
+        case MODE_FORCES: err = launch_adj_lds1<MODE_FORCES>(a, c, ip, shm, s); break;
+        case MODE_HERCULES: err = launch_adj_lds1<MODE_HERCULES>(a, c, ip, shm, s); break;
+        case MODE_TPW: err = launch_adj_lds1<MODE_TPW>(a, c, ip, shm, s); break;
+        case MODE_VLS: err = launch_adj_lds1<MODE_VLS>(a, c, ip, shm, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    if (err != hipSuccess) return err;
+    return launch_reduce_partials(a.partial, c.blocks_x * c.blocks_y * c.blocks_z * a.groups, grad_c, s);
 }
 
 size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard)

@@ -67,6 +67,8 @@ hipError_t launch_das(const DasArgs &a, int mode, int et, int ip, hipStream_t s)
 hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, int ip,
                           hipStream_t s);
 size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard);
+hipError_t launch_das_lds_adjoint_c(const DasArgs &a, const LdsCfg &c, int mode, int ip,
+                                    float *grad_c, hipStream_t s);
 
 constexpr uint32_t BF_PLAN_MAGIC = 0xBF0C0DE5u;
 

@@ -305,8 +305,9 @@ def envelope_stage(torch, bfm, img, reps: int = 10):
 def autofocus_stage(torch, bfm, synth, reps: int = 5):
     """Differentiable FORCES workload (256x256 plane, 64 tx x 64 ch, 2048
     samples, 8 frames): per frame the forward DAS, the sharpness loss with its
-    image gradient, and the adjoint for dL/dc alone (the autofocus gradient)
-    and with the RF gradient (FP32 atomics into a 64 x 64 x 2048 buffer).
+    image gradient, and the adjoint for dL/dc alone (the autofocus gradient);
+    also timed: the adjoint with the RF gradient (64 x 64 x 2048, LDS windows
+    added to it with FP32 atomics), with and without dL/dc.
     Adjoint roofline: per active term the delay (13) and apodization (14),
     the Hermite derivative read (14) and the weighted accumulation of
     v'(s) ds/dc (4) = 45 flops."""
@@ -320,7 +321,7 @@ def autofocus_stage(torch, bfm, synth, reps: int = 5):
     loss, g = bfm.sharpness(img.reshape(1, -1))
     ge, gc = plan.das_adjoint(es[0], g.reshape(img.shape), c=c)
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
     ev[0].record(stream)
     for _ in range(reps):
         for e in es:
@@ -335,14 +336,20 @@ def autofocus_stage(torch, bfm, synth, reps: int = 5):
             plan.das_adjoint(e, g.reshape(img.shape), c=c, want_e=False)
     ev[3].record(stream)
     for _ in range(reps):
-        plan.das_adjoint(es[0], g.reshape(img.shape), c=c, want_e=True)
+        for e in es:
+            plan.das_adjoint(e, g.reshape(img.shape), c=c, want_e=True, out_e=ge)
     ev[4].record(stream)
+    for _ in range(reps):
+        for e in es:
+            plan.das_adjoint(None, g.reshape(img.shape), c=c, want_c=False, out_e=ge)
+    ev[5].record(stream)
     torch.cuda.synchronize()
     nf = len(es)
     fwd_ms = ev[0].elapsed_time(ev[1]) / (reps * nf)
     sh_ms = ev[1].elapsed_time(ev[2]) / (reps * nf)
     adj_ms = ev[2].elapsed_time(ev[3]) / (reps * nf)
-    adj_e_ms = ev[3].elapsed_time(ev[4]) / reps
+    adj_ec_ms = ev[3].elapsed_time(ev[4]) / (reps * nf)
+    adj_e_ms = ev[4].elapsed_time(ev[5]) / (reps * nf)
     n_act = active_terms(desc, dev)
     tf = n_act * 45 / (adj_ms * 1e-3) / 1e12
     step = fwd_ms + sh_ms + adj_ms
@@ -350,7 +357,8 @@ def autofocus_stage(torch, bfm, synth, reps: int = 5):
     return {"workload": "FORCES 256x256 plane, 64 tx x 64 ch x 2048 samples, 8 frames: "
                         "DAS + sharpness + adjoint dL/dc per frame",
             "das_ms": round(fwd_ms, 4), "sharpness_ms": round(sh_ms, 4),
-            "adjoint_c_ms": round(adj_ms, 4), "adjoint_e_and_c_ms": round(adj_e_ms, 4),
+            "adjoint_c_ms": round(adj_ms, 4), "adjoint_e_and_c_ms": round(adj_ec_ms, 4),
+            "adjoint_e_ms": round(adj_e_ms, 4),
             "gradient_step_ms_per_frame": round(step, 4),
             "value": round(nominal / (step * 1e-3) / 1e9, 2), "unit": "G samples/s",
             "adjoint_roofline": {"bound": "alu", "achieved": round(tf, 2),

@@ -223,7 +223,7 @@ int bf_decode(bf_plan plan, const int16_t *rf, void *e, void *stream);
  * HERCULES: tof = (tx(p) + |p - (x_i, y_j, 0)|) / c,  a = W(F# rho / z), rho radial,
  *           tx = z (plane) or |p - v| - f (diverging, see focal_depth)
  * TPW, VLS: tof = (tx_i(p) + |(y - y_j, z)|) / c,  a = W(F# |y - y_j| / z),
- *           tx_i per tx_angles / focal_depth; these modes run the gather kernel
+ *           tx_i per tx_angles / focal_depth
  * W is the Hann window (Eq. 3); points with z <= 0 give 0.  Samples outside
  * [0, n_samples) read as 0.  e: device, type params.e_type; out: device f32
  * [Ny][Nx][Nz], overwritten.  c: sound speed for this call (m/s, finite, > 0;
@@ -237,7 +237,14 @@ int bf_das(bf_plan plan, const void *e, float *out, double c, void *stream);
  *       transpose of the linear map e -> out, applied to grad_out;
  *   grad_c (device f32 scalar, nullable, overwritten) =
  *       sum_p grad_out[p] * d out[p] / dc, with d s / dc = -tof * fs / c.
- * grad_e accumulates with atomics, so its low bits may vary between calls. */
+ * e may be NULL when grad_c is NULL (grad_e does not depend on the data).
+ * grad_out must be finite.  Linear and cubic reads run on the LDS-staged
+ * kernel: grad_c as FP64 workgroup partials summed in a fixed order
+ * (bit-identical between calls); grad_e per workgroup in 64-bit fixed point
+ * (scaled by the workgroup's largest |grad_out|), then FP32 atomics across
+ * workgroups, so its low bits may vary between calls.  Nearest reads, data
+ * types other than FP32 (for grad_c) and the BF_DAS_GATHER variant run the
+ * gather adjoint (FP32 atomics per term). */
 int bf_das_adjoint(bf_plan plan, const void *e, const float *grad_out, double c,
                    float *grad_e, float *grad_c, void *stream);
 

@@ -187,16 +187,28 @@ class Plan:
         return out
 
     def das_adjoint(self, e, grad_out, c: float | None = None, want_e: bool = True,
-                    want_c: bool = True, stream=None):
-        """Returns (grad_e or None, grad_c tensor of shape () or None)."""
+                    want_c: bool = True, stream=None, out_e=None):
+        """Returns (grad_e or None, grad_c tensor of shape () or None).
+
+        ``e`` may be None when only grad_e is wanted (it does not depend on
+        the data); ``out_e`` is an optional float32 (n_tx, n_ch, S) buffer
+        for grad_e."""
         torch = _torch()
         if e is not None:
             self._check_e(e)
         g = grad_out.contiguous().to(torch.float32)
         if tuple(g.shape) != self.out_shape:
             raise ValueError("grad_out has the wrong shape")
-        ge = (torch.empty((self.n_tx, self.n_ch, self.n_samples), dtype=torch.float32,
-                          device=g.device) if want_e else None)
+        shape_e = (self.n_tx, self.n_ch, self.n_samples)
+        if want_e and out_e is not None:
+            if (tuple(out_e.shape) != shape_e or out_e.dtype != torch.float32
+                    or not out_e.is_contiguous() or out_e.device != g.device):
+                raise ValueError("out_e must be a contiguous float32 (n_tx, n_ch, S) "
+                                 "tensor on grad_out's device")
+            ge = out_e
+        else:
+            ge = (torch.empty(shape_e, dtype=torch.float32, device=g.device)
+                  if want_e else None)
         gc = torch.empty((), dtype=torch.float32, device=g.device) if want_c else None
         check(lib().bf_das_adjoint(self._h, _ptr(e) if e is not None else None, _ptr(g),
                                    float(self.c if c is None else c),

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbf.so")
 ARCH = "gfx950"
-SOURCES = ["bf_api.hip", "bf_decode.hip", "bf_das.hip", "bf_das_lds.hip", "bf_adjoint.hip",
+SOURCES = ["bf_api.hip", "bf_decode.hip", "bf_das.hip", "bf_das_lds.hip", "bf_das_adj.hip", "bf_adjoint.hip",
            "bf_batch.hip", "bf_demod.hip", "bf_env.hip"]
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

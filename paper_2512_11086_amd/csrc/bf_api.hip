@@ -447,9 +447,14 @@ static size_t lds_cap_bytes()
     return cap;
 }
 
-bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
+// adj: the adjoint's LDS layout (1: dL/dc, 2: dL/de, 3: both), 0 for DAS.
+// The wavefront tile is a's; bw_adj (if set) replaces the plan's workgroup
+// shape.
+bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg, int adj, const int *bw_adj) const
 {
     const bool sep = p.mode != BF_HERCULES_3D;   // separable: FORCES, TPW, VLS
+    const int *bw = bw_adj ? bw_adj : this->bw;
+    const int lx = a.lx, ly = a.ly, lz = a.lz;
     // points per lane along z: two for the HERCULES real-data variant
     const int zp = variant == BF_DAS_LDS_Z2 && z2_ok() ? 2 : 1;
     const int tx = bw[0] << lx, ty = bw[1] << ly, tz = (bw[2] << lz) * zp;
@@ -512,8 +517,9 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
     const int max_rounds = (zp == 2 || p.mode == BF_TPW_3D || p.mode == BF_VLS_3D) ? 3 : 2;
     auto rounds = [&](int n) { return (n * lmax + 64 * nwaves - 1) / (64 * nwaves); };
     const int qs = p.iq ? 2 : 1;
-    while (nbb >= unit &&
-           (rounds(nbb) > max_rounds || lds_bytes(p.n_tx, p.n_ch, nbb, lmax, qs, guard) > lds_cap))
+    const bool staged = adj == 0 || (adj & 1);    // the RF gradient alone reads no data
+    while (nbb >= unit && ((staged && rounds(nbb) > max_rounds) ||
+                           lds_bytes(p.n_tx, p.n_ch, nbb, lmax, qs, guard, adj) > lds_cap))
         nbb -= unit;
     if (nbb < unit || nthr > 1024) return false;
     cfg->bwx = bw[0];
@@ -533,6 +539,38 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg) const
     cfg->blocks_y = (grid.ny + ty - 1) / ty;
     cfg->blocks_z = (grid.nz + z_off + tz - 1) / tz;
     return true;
+}
+
+// Wavefront tile and workgroup shape of the RF gradient on the LDS kernel.
+// Its terms add to LDS with atomics; lanes of one instruction that hit the
+// same entry are serialized, and entries a few apart share LDS banks.  The
+// delay grows by about 2 k dz per depth step (two or more samples on the
+// usual grids) but hardly changes between laterally adjacent points near a
+// trace's own column, so the wavefront runs mostly along depth: 16 lanes
+// (measured best against 4 to 64 on the 256 x 256 FORCES plane and the
+// 128 x 128 x 256 HERCULES volume), fewer for shallow grids; the rest of the
+// lanes and the workgroup's 8 wavefronts lie side by side laterally.
+void Frame::adjoint_e_tile(DasArgs *a, int bw_out[3]) const
+{
+    const int zp = variant == BF_DAS_LDS_Z2 && z2_ok() ? 2 : 1;
+    const int nzl = (grid.nz + zp - 1) / zp;
+    int lz = 0;
+    while (lz < 4 && (1 << lz) < nzl) ++lz;
+    const int r = 6 - lz;
+    if (grid.ny == 1) {
+        a->lx = r;
+        a->ly = 0;
+        bw_out[0] = 8; bw_out[1] = 1; bw_out[2] = 1;
+    } else {
+        a->lx = (r + 1) / 2;
+        a->ly = r / 2;
+        bw_out[0] = 4; bw_out[1] = 2; bw_out[2] = 1;
+    }
+    a->lz = lz;
+    a->tiles_x = (grid.nx + (1 << a->lx) - 1) >> a->lx;
+    a->tiles_y = (grid.ny + (1 << a->ly) - 1) >> a->ly;
+    a->tiles_z = (grid.nz + (1 << lz) - 1) >> lz;
+    a->n_waves = a->tiles_x * a->tiles_y * a->tiles_z;
 }
 
 // Two points per lane share their lateral offset to every receiver: HERCULES
@@ -738,18 +776,32 @@ int bf_das_adjoint(bf_plan plan, const void *e, const float *grad_out, double c,
     DasArgs a = f.das_args(e, nullptr, c);
     a.grad_out = grad_out;
     a.grad_e = grad_e;
-    // dL/dc alone (the autofocus gradient) runs the LDS-staged kernel for FP32
-    // data and linear / cubic reads; the RF gradient and the other cases run
-    // the gather adjoint (FP32 atomics into grad_e)
-    LdsCfg cfg;
-    const bool lds = !grad_e && grad_c && f.p.e_type == BF_E_F32 &&
-                     f.p.interp != BF_INTERP_NEAREST && f.variant != BF_DAS_GATHER &&
-                     f.lds_config(a, &cfg) &&
-                     (long)cfg.blocks_x * cfg.blocks_y * cfg.blocks_z * a.groups <= f.max_blocks;
-    hipError_t err = lds ? launch_das_lds_adjoint_c(a, cfg, f.p.mode, f.p.interp, grad_c,
-                                                    (hipStream_t)stream)
-                         : launch_das_adjoint(a, f.p.mode, f.p.e_type, f.p.interp, grad_c,
-                                              (hipStream_t)stream);
+    // Linear / cubic reads run the LDS-staged adjoint: dL/de (which reads no
+    // data) on a depth-major wavefront tile, dL/dc (FP32 data) on the plan's
+    // tile, as two launches when both are requested.  Nearest reads, other
+    // data types and the gather variant run the gather adjoint (FP32 atomics
+    // into grad_e).
+    const hipStream_t s = (hipStream_t)stream;
+    const bool lds_ok = f.p.interp != BF_INTERP_NEAREST && f.variant != BF_DAS_GATHER;
+    DasArgs ae = a;
+    LdsCfg ce, cc;
+    int bwa[3];
+    f.adjoint_e_tile(&ae, bwa);
+    const bool e_lds = grad_e && lds_ok && f.lds_config(ae, &ce, 2, bwa);
+    const bool c_lds = grad_c && lds_ok && f.p.e_type == BF_E_F32 && f.lds_config(a, &cc, 1) &&
+                       (long)cc.blocks_x * cc.blocks_y * cc.blocks_z * a.groups <= f.max_blocks;
+    hipError_t err = hipSuccess;
+    DasArgs ag = a;                 // what the LDS kernels do not take
+    ag.grad_e = e_lds ? nullptr : grad_e;
+    if (ag.grad_e || (grad_c && !c_lds))
+        err = launch_das_adjoint(ag, f.p.mode, f.p.e_type, f.p.interp, c_lds ? nullptr : grad_c, s);
+    if (err == hipSuccess && e_lds)
+        err = launch_das_lds_adjoint(ae, ce, f.p.mode, f.p.interp, nullptr, s);
+    if (err == hipSuccess && c_lds) {
+        DasArgs ac = a;
+        ac.grad_e = nullptr;
+        err = launch_das_lds_adjoint(ac, cc, f.p.mode, f.p.interp, grad_c, s);
+    }
     return err == hipSuccess ? BF_OK : hip_fail(err, "DAS adjoint launch");
 }
 

@@ -142,7 +142,7 @@ static int build_batch(bf_plan plan)
             memset(&c, 0, sizeof c);
         } else {
             const int threads = 64 * c.bwx * c.bwy * c.bwz;
-            const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, 1, c.guard);
+            const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, 1, c.guard, 0);
             DasClass *cls = nullptr;
             for (DasClass &d : b->das)
                 if (d.mode == fr.p.mode && d.et == fr.p.e_type && d.ip == fr.p.interp &&

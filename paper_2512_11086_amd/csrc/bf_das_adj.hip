@@ -1,0 +1,91 @@
+// bf_das_adj.hip -- the adjoint of LDS-staged delay-and-sum: das_block in its
+// adjoint form (bf_das_lds_block.h).  dL/dc: one FP64 partial per workgroup,
+// then a fixed-order sum.  dL/de: per-trace LDS accumulation windows added
+// to grad_e after each batch.
+#include "bf_das_lds_block.h"
+
+namespace bf {
+
+hipError_t launch_reduce_partials(const double *partial, int n, float *out, hipStream_t s);
+hipError_t launch_fill(float *p, long n, float v, hipStream_t s);
+
+// ADJ = 1: dL/dc (FP32 data), 2: dL/de (reads no data).
+template <int MODE, int IP, int ZP, int ADJ>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerEu<MODE, ZP>::value)))
+void das_lds_adj_kernel(DasArgs a, LdsCfg c)
+{
+    extern __shared__ float4 smem[];
+    das_block<MODE, ET_F32, IP, ZP, ADJ>(a, c, blockIdx.x, blockIdx.y, smem);
+}
+
+template <int MODE, int IP, int ZP, int ADJ>
+static hipError_t launch_adj_lds4(const DasArgs &a, const LdsCfg &c, size_t shm, hipStream_t s)
+{
+    const int nthr = 64 * c.bwx * c.bwy * c.bwz;
+    dim3 grid(c.blocks_x * c.blocks_y * c.blocks_z, a.groups);
+    hipError_t e =
+        allow_lds(reinterpret_cast<const void *>(&das_lds_adj_kernel<MODE, IP, ZP, ADJ>), shm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((das_lds_adj_kernel<MODE, IP, ZP, ADJ>), grid, dim3(nthr), shm, s, a, c);
+    return hipGetLastError();
+}
+
+template <int MODE, int IP, int ZP>
+static hipError_t launch_adj_lds3(const DasArgs &a, const LdsCfg &c, int adj, size_t shm,
+                                  hipStream_t s)
+{
+    switch (adj) {
+        case 1: return launch_adj_lds4<MODE, IP, ZP, 1>(a, c, shm, s);
+        case 2: return launch_adj_lds4<MODE, IP, ZP, 2>(a, c, shm, s);
+        default: return hipErrorInvalidValue;     // one gradient per launch
+    }
+}
+
+template <int MODE, int IP>
+static hipError_t launch_adj_lds2(const DasArgs &a, const LdsCfg &c, int adj, size_t shm,
+                                  hipStream_t s)
+{
+    if constexpr (MODE == MODE_HERCULES)
+        if (c.zp == 2) return launch_adj_lds3<MODE, IP, 2>(a, c, adj, shm, s);
+    return c.zp == 1 ? launch_adj_lds3<MODE, IP, 1>(a, c, adj, shm, s) : hipErrorInvalidValue;
+}
+
+template <int MODE>
+static hipError_t launch_adj_lds1(const DasArgs &a, const LdsCfg &c, int ip, int adj, size_t shm,
+                                  hipStream_t s)
+{
+    switch (ip) {
+        case IN_LINEAR: return launch_adj_lds2<MODE, IN_LINEAR>(a, c, adj, shm, s);
+        case IN_CUBIC: return launch_adj_lds2<MODE, IN_CUBIC>(a, c, adj, shm, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// The adjoint with the LDS-staged kernel (linear or cubic reads), one of the
+// two gradients per call: grad_e (a.grad_e) is cleared and accumulated, or
+// grad_c receives the fixed-order sum of the workgroups' partials (FP32
+// data).
+hipError_t launch_das_lds_adjoint(const DasArgs &a, const LdsCfg &c, int mode, int ip,
+                                  float *grad_c, hipStream_t s)
+{
+    const int adj = (grad_c ? 1 : 0) | (a.grad_e ? 2 : 0);
+    if (adj == 0) return hipSuccess;
+    if (adj == 3) return hipErrorInvalidValue;
+    const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, 1, c.guard, adj);
+    hipError_t err;
+    if (a.grad_e) {
+        err = launch_fill(a.grad_e, (long)a.n_tx * a.n_ch * a.S, 0.f, s);
+        if (err != hipSuccess) return err;
+    }
+    switch (mode) {
+        case MODE_FORCES: err = launch_adj_lds1<MODE_FORCES>(a, c, ip, adj, shm, s); break;
+        case MODE_HERCULES: err = launch_adj_lds1<MODE_HERCULES>(a, c, ip, adj, shm, s); break;
+        case MODE_TPW: err = launch_adj_lds1<MODE_TPW>(a, c, ip, adj, shm, s); break;
+        case MODE_VLS: err = launch_adj_lds1<MODE_VLS>(a, c, ip, adj, shm, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    if (err != hipSuccess || !grad_c) return err;
+    return launch_reduce_partials(a.partial, c.blocks_x * c.blocks_y * c.blocks_z * a.groups, grad_c, s);
+}
+
+}  // namespace bf

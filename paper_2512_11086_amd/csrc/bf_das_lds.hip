@@ -1,940 +1,11 @@
-// bf_das_lds.hip -- delay-and-sum with LDS-staged trace windows (gfx950).
-//
-// A workgroup owns a box of output points (a grid of 64-lane wavefront
-// tiles).  It walks the (transmit, channel) traces in batches; for every
-// trace of a batch it stages, once, the window of samples that any point of
-// the box can read -- bounded from the box geometry, since the delay grows
-// with depth and with lateral distance -- as cubic-Hermite coefficient quads
-// (c0, c1, c2, c3) per sample interval, with zeros outside the record.  Each
-// term of Eq. 1 then costs one aligned 16-byte LDS read and three FMAs for
-// the read (Sec. IV-B) instead of four bounds-checked global loads.  The
-// global loads of the next batch are issued before the current batch is
-// beamformed (double-buffered LDS, one barrier per batch), and they read
-// contiguous runs along fast time.
-//
-// HERCULES volumes with real data can give each lane two adjacent depth
-// points (ZP = 2): both share the lateral offset to the receiver, rho^2 and
-// the per-trace scalars of every term, and each wavefront's per-batch work
-// (aperture mask, trace metadata) serves twice the points.
-//
-// Separable modes (FORCES planes, TPW and VLS row-column volumes): the delay
-// is a transmit path per (point, transmit) plus a receive path per (point,
-// channel row), and the apodization depends on the row only.  A batch holds
-// 4 rows x nb/4 transmits; each lane computes the receive path and weight of
-// a row once, the transmit path of a transmit once, and every term adds the
-// two.
-//
-// Apodization skip (Sec. VII-F): a channel row is staged only if the receive
-// aperture of the deepest point of the box reaches it; within a row only the
-// transmits whose lateral offset can fall inside that aperture are staged
-// (HERCULES); each wavefront additionally skips traces outside the union of
-// its own lanes' apertures with a scalar test (HERCULES), or rows no lane of
-// it can receive (separable modes).
-//
-// Delay precision: as in the gather kernel, s = B(p) + k (E_tx + E_rx) with
-// B in FP64 split into integer + FP32 fraction and E = rho^2 / (d + z) in FP32.
-//
-// IQ data (ET_CF32): a sample interval stages as two adjacent quads, the
-// coefficients of the real and of the imaginary part (32 bytes per interval),
-// and each term is rotated by its carrier phase before the complex
-// accumulation.
-#include "bf_common.h"
+// bf_das_lds.hip -- forward delay-and-sum kernels with LDS-staged trace
+// windows (gfx950): the single-frame kernel, the persistent batched kernel
+// and their launchers.  The workgroup body is das_block in bf_das_lds_block.h.
+#include "bf_das_lds_block.h"
 
 namespace bf {
 
 hipError_t launch_sum_groups(const DasArgs &a, hipStream_t s);
-
-constexpr int JC = 4;    // channel rows per batch of the separable modes (FORCES, TPW, VLS)
-constexpr int HANN_TAB_PAD = HANN_N + 2;   // table entries reserved in LDS (float2, keeps 16-byte alignment)
-
-// Trace slot `lane` of a batch, held by that lane of every wavefront: the
-// first sample interval of its window, the x of its transmit column, and
-// its trace index i * n_ch + j (-1 for an empty slot).  Staging lanes fetch
-// the entry of their slot with a lane permute; terms read it with readlane.
-struct TraceDesc {
-    int w0;
-    float xi;
-    int tr;
-};
-
-// Uniform description of one batch.
-struct BatchDesc {
-    int valid;
-    int i0, cnt;          // transmits i0 .. i0+cnt-1
-    int j;                // HERCULES: channel row
-    int rows[JC];         // separable modes: channel rows (-1 = none)
-};
-
-struct BoxGeom {
-    float xmin, xmax, ymin, ymax, zmin, zmax;
-    float kf, t0f;    // fs / c and t0 * fs in FP32 (window bounds only)
-    float txlo;       // lower bound of the transmit path over the box (HERCULES)
-};
-
-__device__ inline float wave_min(float v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ inline float wave_max(float v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-__device__ inline int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ inline float uniform_f(float v)
-{
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-
-// Lane state.  A point outside the grid or at z <= 0 keeps the lane's real
-// lateral position (a lane's points share it) and benign depth values: it
-// is never inside the aperture mask, its arithmetic stays finite, and its
-// sum is discarded (outside the grid) or replaced by 0 (z <= 0, where the
-// apodization vanishes) when the outputs are stored.
-struct LaneL {
-    bool valid;
-    float x, y, z, z2, thr, wsc, fB;
-    float zk, zk2;  // z / k and its square (k = fs / c): the HERCULES delay
-    float wtab;     // u^2 * 4 HANN_N = rho^2 * wtab (table coordinate)
-    int nB;
-    float ph0;      // IQ: carrier phase of sample position nB (revolutions)
-};
-
-// Grid indices of point p (0 .. zp-1) of a lane: the lane's z tile index
-// times zp plus p, so a lane's points are adjacent along z.
-__device__ inline void lane_point(const DasArgs &a, const LdsCfg &c, int bx, int by, int bz,
-                                  int wave, int lane, int p, int *ix, int *iy, int *iz)
-{
-    const int wz = wave % c.bwz, wx = (wave / c.bwz) % c.bwx, wy = wave / (c.bwz * c.bwx);
-    const int lz = lane & ((1 << a.lz) - 1);
-    const int lx = (lane >> a.lz) & ((1 << a.lx) - 1);
-    const int ly = lane >> (a.lz + a.lx);
-    *ix = ((bx * c.bwx + wx) << a.lx) + lx;
-    *iy = ((by * c.bwy + wy) << a.ly) + ly;
-    *iz = (((bz * c.bwz + wz) << a.lz) + lz) * c.zp + p - c.z_off;
-}
-
-template <int MODE>
-__device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, int by, int bz,
-                                     int wave, int lane, int p)
-{
-    LaneL L;
-    int ix, iy, iz;
-    lane_point(a, c, bx, by, bz, wave, lane, p, &ix, &iy, &iz);
-    L.valid = ix < a.g.nx && iy < a.g.ny && iz >= 0 && iz < a.g.nz;
-    if constexpr (MODE == MODE_HERCULES) {
-        // HERCULES reads its windows without clamping the index, so every lane
-        // takes the geometry of the nearest grid point of its box: its delay
-        // then lies within the box's bounds (see hercules_term)
-        ix = min(ix, a.g.nx - 1);
-        iy = min(iy, a.g.ny - 1);
-        iz = min(max(iz, 0), a.g.nz - 1);
-    }
-    const double px = a.g.org[0] + ix * a.g.ax[0] + iy * a.g.ay[0] + iz * a.g.az[0];
-    const double py = a.g.org[1] + ix * a.g.ax[1] + iy * a.g.ay[1] + iz * a.g.az[1];
-    const double pz = a.g.org[2] + ix * a.g.ax[2] + iy * a.g.ay[2] + iz * a.g.az[2];
-    L.x = (float)px;
-    L.y = (float)py;
-    if constexpr (MODE == MODE_HERCULES) {
-        // a point on or behind the array plane (its output is 0) is evaluated
-        // just in front of it, inside the box; it and any lane outside the
-        // grid stay out of the wavefront's aperture mask (thr < 0)
-        const double pze = fmax(pz, 1e-7);
-        const double B = (tx_path(a, px, py, pze) + pze) * a.k - a.t0fs;
-        const double fl = floor(B);
-        L.nB = (int)fl;
-        L.fB = (float)(B - fl);
-        L.z = (float)pze;
-        L.z2 = L.z * L.z;
-        L.zk = (float)(pze / a.k);
-        L.zk2 = L.zk * L.zk;
-        L.thr = (L.valid && pz > 0.0) ? (a.f2 > 0.f ? L.z2 * 0.25f / a.f2 : __builtin_inff()) : -1.f;
-        L.wsc = a.f2 > 0.f ? a.f2 / L.z2 : 0.f;
-        L.wtab = L.wsc * (4.f * HANN_N);
-        L.ph0 = phase_origin(a, L.nB);
-    } else if (L.valid && pz > 0.0) {
-        const double B = (tx_path(a, px, py, pz) + pz) * a.k - a.t0fs;
-        const double fl = floor(B);
-        L.nB = (int)fl;
-        L.fB = (float)(B - fl);
-        L.z = (float)pz;
-        L.z2 = L.z * L.z;
-        L.zk = (float)(pz / a.k);
-        L.zk2 = L.zk * L.zk;
-        L.thr = a.f2 > 0.f ? L.z2 * 0.25f / a.f2 : __builtin_inff();
-        L.wsc = a.f2 > 0.f ? a.f2 / L.z2 : 0.f;
-        L.wtab = L.wsc * (4.f * HANN_N);
-        L.ph0 = phase_origin(a, L.nB);
-    } else {
-        // benign: depth 1 m (finite delays, clamped window index), outside
-        // every aperture test (thr < 0, FORCES weight forced to 0)
-        L.nB = 0;
-        L.fB = 0.f;
-        L.z = L.z2 = 1.f;
-        L.zk = (float)(1.0 / a.k);
-        L.zk2 = L.zk * L.zk;
-        L.thr = -1.f;
-        L.wsc = __builtin_inff();
-        L.wtab = 1.f;
-        L.ph0 = 0.f;
-    }
-    return L;
-}
-
-// Array-frame bounding box of the workgroup's points (clamped to the grid).
-__device__ inline BoxGeom block_box(const DasArgs &a, const LdsCfg &c, int bx, int by, int bz)
-{
-    const int tx = c.bwx << a.lx, ty = c.bwy << a.ly, tz = (c.bwz << a.lz) * c.zp;
-    const int i0[3] = {bx * tx, by * ty, max(bz * tz - c.z_off, 0)};
-    const int i1[3] = {min(bx * tx + tx - 1, a.g.nx - 1), min(by * ty + ty - 1, a.g.ny - 1),
-                       min(bz * tz + tz - 1 - c.z_off, a.g.nz - 1)};
-    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-    for (int q = 0; q < 8; ++q) {
-        const int ix = (q & 1) ? i1[0] : i0[0];
-        const int iy = (q & 2) ? i1[1] : i0[1];
-        const int iz = (q & 4) ? i1[2] : i0[2];
-        for (int r = 0; r < 3; ++r) {
-            const double v = a.g.org[r] + ix * a.g.ax[r] + iy * a.g.ay[r] + iz * a.g.az[r];
-            lo[r] = fmin(lo[r], v);
-            hi[r] = fmax(hi[r], v);
-        }
-    }
-    BoxGeom b;
-    b.xmin = (float)lo[0]; b.xmax = (float)hi[0];
-    b.ymin = (float)lo[1]; b.ymax = (float)hi[1];
-    b.zmin = (float)lo[2]; b.zmax = (float)hi[2];
-    b.kf = (float)a.k;
-    b.t0f = (float)a.t0fs;
-    // transmit path: z (plane wave), or the distance from the virtual source
-    // (0, 0, -f) to the box minus f (diverging wave); both grow with depth
-    const float zlo = fmaxf(b.zmin, 0.f);
-    b.txlo = zlo;
-    if (a.div_f > 0.0) {
-        const float f = (float)a.div_f;
-        const float dx = fmaxf(0.f, fmaxf(b.xmin, -b.xmax));
-        const float dy = fmaxf(0.f, fmaxf(b.ymin, -b.ymax));
-        b.txlo = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, (zlo + f) * (zlo + f)))) - f;
-    }
-    // workgroup-uniform: keep the box in scalar registers
-    b.xmin = uniform_f(b.xmin); b.xmax = uniform_f(b.xmax);
-    b.ymin = uniform_f(b.ymin); b.ymax = uniform_f(b.ymax);
-    b.zmin = uniform_f(b.zmin); b.zmax = uniform_f(b.zmax);
-    b.kf = uniform_f(b.kf); b.t0f = uniform_f(b.t0f); b.txlo = uniform_f(b.txlo);
-    return b;
-}
-
-__device__ inline float dist_to_range(float v, float lo, float hi)
-{
-    return fmaxf(0.f, fmaxf(lo - v, v - hi));
-}
-__device__ inline float far_to_range(float v, float lo, float hi)
-{
-    return fmaxf(fabsf(v - lo), fabsf(v - hi));
-}
-
-// First sample interval of the staged window of trace (transmit i, receive
-// channel at lateral coordinate cj) for the box: a lower bound of the path
-// over the box (the bound has a 2-sample margin, so the hardware square root
-// suffices).  Separable modes add the lower bounds of the transmit and the
-// receive path; the receive path of a row (TPW, VLS) or column (FORCES) is
-// at least its distance to the nearest box point at the shallowest depth.
-template <int MODE>
-__device__ inline int window_start(const DasArgs &a, const BoxGeom &b, int i, float xi, float cj)
-{
-    const float zlo = fmaxf(b.zmin, 0.f);
-    float path;
-    if constexpr (MODE == MODE_FORCES) {
-        const float rt = dist_to_range(xi, b.xmin, b.xmax);
-        const float rr = dist_to_range(cj, b.xmin, b.xmax);
-        path = __builtin_amdgcn_sqrtf(fmaf(rt, rt, zlo * zlo)) +
-               __builtin_amdgcn_sqrtf(fmaf(rr, rr, zlo * zlo));
-    } else if constexpr (MODE == MODE_HERCULES) {
-        const float rx = dist_to_range(xi, b.xmin, b.xmax);
-        const float ry = dist_to_range(cj, b.ymin, b.ymax);
-        path = b.txlo + __builtin_amdgcn_sqrtf(fmaf(rx, rx, fmaf(ry, ry, zlo * zlo)));
-    } else {
-        const float ry = dist_to_range(cj, b.ymin, b.ymax);
-        float tx;
-        if constexpr (MODE == MODE_TPW) {
-            // x sin(th) + z cos(th): smallest at the box edge along sin(th), cos(th) > 0
-            const float2 sc = a.tx_sc[i];
-            tx = (sc.x >= 0.f ? b.xmin : b.xmax) * sc.x + zlo * (1.f + sc.y);
-        } else {
-            // z_f + sgn(z - z_f) |(x - x_i, z - z_f)|: with the whole box below the
-            // line the nearest point bounds it; else z_f minus the farthest reach
-            const float zf = a.zf;
-            if (zf <= zlo) {
-                const float rx = dist_to_range(xi, b.xmin, b.xmax);
-                tx = zf + __builtin_amdgcn_sqrtf(fmaf(rx, rx, (zlo - zf) * (zlo - zf)));
-            } else {
-                const float rf = far_to_range(xi, b.xmin, b.xmax);
-                tx = zf - __builtin_amdgcn_sqrtf(fmaf(rf, rf, (zf - zlo) * (zf - zlo)));
-            }
-        }
-        path = tx + __builtin_amdgcn_sqrtf(fmaf(ry, ry, zlo * zlo));
-    }
-    return (int)floorf(fmaf(path, b.kf, -b.t0f)) - 2;
-}
-
-// Is channel row j reachable by the receive aperture of any point of the box?
-// For HERCULES also returns the lateral reach R of the aperture along x.
-template <int MODE>
-__device__ inline bool row_active(const DasArgs &a, const BoxGeom &b, float cj, float *R)
-{
-    if (b.zmax <= 0.f) return false;
-    if (a.f2 <= 0.f) {
-        *R = __builtin_inff();
-        return true;
-    }
-    const float thr = b.zmax * b.zmax * 0.25f / a.f2;
-    const float d = MODE == 0 ? dist_to_range(cj, b.xmin, b.xmax) : dist_to_range(cj, b.ymin, b.ymax);
-    const float r2 = thr - d * d;
-    *R = sqrtf(fmaxf(r2, 0.f));
-    return r2 > 0.f;
-}
-
-// Transmit range [lo, hi) whose column x lies in [xl, xh] (ascending tx_x).
-__device__ inline void tx_range(const float *tx, int n, float xl, float xh, int *lo, int *hi)
-{
-    int a0 = 0, b0 = n;                   // first index with tx >= xl
-    while (a0 < b0) {
-        const int m = (a0 + b0) >> 1;
-        if (tx[m] < xl) a0 = m + 1; else b0 = m;
-    }
-    int a1 = a0, b1 = n;                  // first index with tx > xh
-    while (a1 < b1) {
-        const int m = (a1 + b1) >> 1;
-        if (tx[m] <= xh) a1 = m + 1; else b1 = m;
-    }
-    *lo = a0;
-    *hi = a1;
-}
-
-// Batch iterator (uniform across the workgroup).
-struct Iter {
-    int jend;    // end of this workgroup's channel rows
-    int j;       // current channel row (HERCULES) / next row to scan (FORCES)
-    int i;       // next transmit
-    int ihi;     // end of the current row's transmit range (HERCULES)
-    int rows[JC];
-};
-
-template <int MODE>
-__device__ inline BatchDesc next_batch(const DasArgs &a, const LdsCfg &c, const BoxGeom &b,
-                                       const float *s_tx, const float *s_rx, Iter &it)
-{
-    BatchDesc d;
-    d.valid = 0;
-    if constexpr (MODE == 1) {
-        while (it.i >= it.ihi) {          // advance to the next active row
-            ++it.j;
-            if (it.j >= it.jend) return d;
-            float R;
-            if (!row_active<1>(a, b, s_rx[it.j], &R)) continue;
-            if (c.uniform_tx && isfinite(R)) {
-                // columns on a regular grid: [lo, hi) by arithmetic (one
-                // column of margin each side; the wavefront tests are exact)
-                const int lo = (int)floorf((b.xmin - R - c.tx_x0) * c.tx_inv_dx) - 1;
-                const int hi = (int)floorf((b.xmax + R - c.tx_x0) * c.tx_inv_dx) + 2;
-                it.i = max(lo, 0);
-                it.ihi = min(hi, a.n_tx);
-                if (it.i > it.ihi) it.i = it.ihi;
-            } else if (c.sorted_tx && isfinite(R)) {
-                tx_range(s_tx, a.n_tx, b.xmin - R, b.xmax + R, &it.i, &it.ihi);
-            } else {
-                it.i = 0;
-                it.ihi = a.n_tx;
-            }
-        }
-        d.valid = 1;
-        d.j = it.j;
-        d.i0 = it.i;
-        d.cnt = min(c.nb, it.ihi - it.i);
-        it.i += d.cnt;
-        return d;
-    } else {
-        const int nbi = c.nb / JC;
-        if (it.i >= a.n_tx) {             // next chunk of JC active rows
-            int n = 0;
-            for (int q = 0; q < JC; ++q) it.rows[q] = -1;
-            while (n < JC && it.j < it.jend) {
-                float R;
-                if (row_active<MODE>(a, b, s_rx[it.j], &R)) {
-                    // (selects instead of a dynamic index keep rows[] in registers)
-#pragma unroll
-                    for (int q = 0; q < JC; ++q)
-                        if (q == n) it.rows[q] = it.j;
-                    ++n;
-                }
-                ++it.j;
-            }
-            if (n == 0) return d;
-            it.i = 0;
-        }
-        d.valid = 1;
-        for (int q = 0; q < JC; ++q) d.rows[q] = it.rows[q];
-        d.i0 = it.i;
-        d.cnt = min(nbi, a.n_tx - it.i);
-        it.i += d.cnt;
-        return d;
-    }
-}
-
-template <int MODE>
-__device__ inline void slot_trace(const BatchDesc &d, const LdsCfg &c, int e, int *i, int *j)
-{
-    if constexpr (MODE == 1) {
-        *i = d.i0 + e;
-        *j = e < d.cnt ? d.j : -1;
-    } else {
-        const int nbi = c.nb / JC;
-        const int ii = e % nbi, jj = e / nbi;
-        int row = -1;
-#pragma unroll
-        for (int q = 0; q < JC; ++q)
-            if (q == jj) row = d.rows[q];
-        *i = d.i0 + ii;
-        *j = (ii < d.cnt) ? row : -1;
-    }
-}
-
-// Staging rounds per thread per batch (the host keeps nb * lmax within
-// QM * 64 * wavefronts): 3 for the two-point kernel and the row-column
-// modes (longer windows), else 2.
-template <int MODE, int ZP> struct StageRounds {
-    static constexpr int value = (ZP == 2 || MODE == MODE_TPW || MODE == MODE_VLS) ? 3 : 2;
-};
-
-// Staging map: the nb * lmax quads of a batch are numbered trace-major and
-// dealt to the workgroup's threads in order (round q, wavefront, lane), so no
-// lane idles on a short window and consecutive lanes read consecutive samples
-// of one trace.  Each lane computes the window start of its own trace.
-template <int QM>
-struct Staged {
-    float p[QM][8];    // taps n-1 .. n+2 (IQ: (re, im) of each)
-};
-
-// Slot e and quad m handled by this lane in staging round q; false if none.
-// (g + 1/2) / lmax is at least 1 / (2 lmax) away from an integer, far more
-// than the FP32 rounding of the product for g < 2^16.
-__device__ inline bool stage_slot(const LdsCfg &c, int q, int wave, int lane, int nwaves, int *e,
-                                  int *m)
-{
-    const int g = (q * nwaves + wave) * 64 + lane;
-    const int ee = (int)(((float)g + 0.5f) * c.inv_lmax);
-    *e = ee;
-    *m = g - ee * c.lmax;
-    return ee < c.nb;
-}
-
-// Descriptor of trace slot `lane` of batch d (see TraceDesc).
-template <int MODE>
-__device__ inline TraceDesc trace_desc(const DasArgs &a, const LdsCfg &c, const BoxGeom &b,
-                                       const float *s_tx, const float *s_rx, const BatchDesc &d,
-                                       int lane)
-{
-    TraceDesc t{0, 0.f, -1};
-    if (lane < c.nb) {
-        int i, j;
-        slot_trace<MODE>(d, c, lane, &i, &j);
-        if (j >= 0) {
-            t.xi = s_tx[i];
-            t.w0 = window_start<MODE>(a, b, i, t.xi, s_rx[j]);
-            t.tr = i * a.n_ch + j;
-        }
-    }
-    return t;
-}
-
-// Issue the global loads of a batch's windows (taps n-1..n+2 of every quad).
-template <int ET, int QM>
-__device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const TraceDesc &td,
-                                  Staged<QM> &st, int wave, int lane, int nwaves)
-{
-#pragma unroll
-    for (int q = 0; q < QM; ++q) {
-        int e, m;
-        const bool on = stage_slot(c, q, wave, lane, nwaves, &e, &m);
-        // window start and trace of slot e, from lane e
-        const int src = (e & 63) << 2;
-        const int w0 = __builtin_amdgcn_ds_bpermute(src, td.w0);
-        const int tr = __builtin_amdgcn_ds_bpermute(src, td.tr);
-        float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
-        float p4 = 0.f, p5 = 0.f, p6 = 0.f, p7 = 0.f;
-        if (on && tr >= 0) {
-            const int n = w0 + m;
-            const void *tn = trace_ptr<ET>(trace_ptr<ET>(a.e, tr, a.S), n, 1);   // sample n
-            const unsigned S = (unsigned)a.S;
-            const bool inside = w0 >= 1 && w0 + c.lmax + 1 < a.S;
-            if constexpr (ET == ET_CF32) {
-                // (re, im) of taps n-1 .. n+2: 32 contiguous bytes
-                const float2 z = make_float2(0.f, 0.f);
-                float2 t0, t1, t2, t3;
-                if (inside) {
-                    float4 u, v;
-                    __builtin_memcpy(&u, static_cast<const float2 *>(tn) - 1, 16);
-                    __builtin_memcpy(&v, static_cast<const float2 *>(tn) + 1, 16);
-                    t0 = make_float2(u.x, u.y); t1 = make_float2(u.z, u.w);
-                    t2 = make_float2(v.x, v.y); t3 = make_float2(v.z, v.w);
-                } else {
-                    t0 = ((unsigned)(n - 1) < S) ? load_c(tn, -1) : z;
-                    t1 = ((unsigned)n < S) ? load_c(tn, 0) : z;
-                    t2 = ((unsigned)(n + 1) < S) ? load_c(tn, 1) : z;
-                    t3 = ((unsigned)(n + 2) < S) ? load_c(tn, 2) : z;
-                }
-                p0 = t0.x; p1 = t1.x; p2 = t2.x; p3 = t3.x;
-                p4 = t0.y; p5 = t1.y; p6 = t2.y; p7 = t3.y;
-            } else if (inside) {
-                // whole window inside the record (the usual case): one
-                // 16-byte load of the four taps (4-byte aligned)
-                if constexpr (ET == ET_F32) {
-                    float4 v;
-                    __builtin_memcpy(&v, static_cast<const float *>(tn) - 1, 16);
-                    p0 = v.x; p1 = v.y; p2 = v.z; p3 = v.w;
-                } else {
-                    p0 = load_e<ET>(tn, -1);
-                    p1 = load_e<ET>(tn, 0);
-                    p2 = load_e<ET>(tn, 1);
-                    p3 = load_e<ET>(tn, 2);
-                }
-            } else {
-                p0 = ((unsigned)(n - 1) < S) ? load_e<ET>(tn, -1) : 0.f;
-                p1 = ((unsigned)n < S) ? load_e<ET>(tn, 0) : 0.f;
-                p2 = ((unsigned)(n + 1) < S) ? load_e<ET>(tn, 1) : 0.f;
-                p3 = ((unsigned)(n + 2) < S) ? load_e<ET>(tn, 2) : 0.f;
-            }
-        }
-        st.p[q][0] = p0;
-        st.p[q][1] = p1;
-        st.p[q][2] = p2;
-        st.p[q][3] = p3;
-        st.p[q][4] = p4;
-        st.p[q][5] = p5;
-        st.p[q][6] = p6;
-        st.p[q][7] = p7;
-    }
-}
-
-// Coefficient quad of one sample interval from taps p[n-1] .. p[n+2].
-// Derivative quad of one sample interval (the adjoint's dL/dc): v'(t) =
-// d1 + d2 t + d3 t^2 = (c1, 2 c2, 3 c3) of the cubic; the slope of the linear
-// read; 0 for nearest (piecewise constant).
-template <int IP>
-__device__ inline float4 coef_dquad(float pm, float p0, float p1, float p2)
-{
-    if constexpr (IP == IN_CUBIC)
-        return make_float4(0.5f * (p1 - pm), 2.f * (pm - 2.5f * p0 + 2.0f * p1 - 0.5f * p2),
-                           3.f * (0.5f * (p2 - pm) + 1.5f * (p0 - p1)), 0.f);
-    else if constexpr (IP == IN_LINEAR)
-        return make_float4(p1 - p0, 0.f, 0.f, 0.f);
-    else
-        return make_float4(0.f, 0.f, 0.f, 0.f);
-}
-
-template <int IP>
-__device__ inline float eval_dquad(const float4 q, float t)
-{
-    if constexpr (IP == IN_CUBIC) return fmaf(t, fmaf(t, q.z, q.y), q.x);
-    return q.x;
-}
-
-template <int IP>
-__device__ inline float4 coef_quad(float pm, float p0, float p1, float p2)
-{
-    if constexpr (IP == IN_CUBIC)
-        return make_float4(p0, 0.5f * (p1 - pm), pm - 2.5f * p0 + 2.0f * p1 - 0.5f * p2,
-                           0.5f * (p2 - pm) + 1.5f * (p0 - p1));
-    else if constexpr (IP == IN_LINEAR)
-        return make_float4(p0, p1 - p0, 0.f, 0.f);
-    else
-        return make_float4(p0, p1, 0.f, 0.f);
-}
-
-// Negated window starts of a batch's slots into LDS (wavefront 0, lane =
-// slot): HERCULES in slot order; the separable modes as [transmit][row], so
-// one 16-byte load gives the 4 rows of a transmit.
-template <int MODE>
-__device__ inline void store_w0(const LdsCfg &c, const TraceDesc &td, int *w, int wave, int lane)
-{
-    if (wave != 0 || lane >= c.nb) return;
-    if constexpr (MODE == MODE_HERCULES) {
-        w[lane] = -td.w0;
-    } else {
-        const int nbi = c.nb / JC;
-        w[(lane % nbi) * JC + lane / nbi] = -td.w0;
-    }
-}
-
-// Convert the loaded taps to coefficient quads and write them to one LDS
-// buffer.  QS = quads per sample interval (2 for IQ data: real part, then
-// imaginary part).
-template <int IP, int QS, int QM, bool ADJ>
-__device__ inline void stage_store(const LdsCfg &c, const Staged<QM> &st, float4 *quads, int wave,
-                                   int lane, int nwaves)
-{
-#pragma unroll
-    for (int q = 0; q < QM; ++q) {
-        int e, m;
-        if (stage_slot(c, q, wave, lane, nwaves, &e, &m)) {
-            const float *t = st.p[q];
-            quads[(e * c.lmax + m) * QS] = ADJ ? coef_dquad<IP>(t[0], t[1], t[2], t[3])
-                                               : coef_quad<IP>(t[0], t[1], t[2], t[3]);
-            if constexpr (QS == 2)
-                quads[(e * c.lmax + m) * 2 + 1] = coef_quad<IP>(t[4], t[5], t[6], t[7]);
-        }
-    }
-}
-
-// clamp to [0, hi] in one instruction (hi wave-uniform)
-__device__ inline int clamp0_i32(int x, int hi)
-{
-    int r;
-    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "s"(hi));
-    return r;
-}
-
-template <int IP>
-__device__ inline float eval_quad(const float4 q, float t)
-{
-    if constexpr (IP == IN_NEAREST) return t < 0.5f ? q.x : q.y;
-    if constexpr (IP == IN_LINEAR) return fmaf(t, q.y, q.x);
-    return fmaf(t, fmaf(t, fmaf(t, q.w, q.z), q.y), q.x);
-}
-
-template <int IP>
-__device__ inline float read_quad(const float4 *win, int li, int lmax, float t)
-{
-    li = clamp0_i32(li, lmax - 1);
-    return eval_quad<IP>(win[li], t);
-}
-
-// IQ window: interval li holds the real quad at 2 li and the imaginary at 2 li + 1
-template <int IP>
-__device__ inline float2 read_quad_cx(const float4 *win, int li, int lmax, float t)
-{
-    li = clamp0_i32(li, lmax - 1);
-    return make_float2(eval_quad<IP>(win[2 * li], t), eval_quad<IP>(win[2 * li + 1], t));
-}
-
-// Beamforms workgroup box `blk` (channel group `grp`) of one frame.  Every
-// thread of the workgroup must call it (it contains barriers).
-// floor to int in one instruction
-__device__ inline int cvt_flr(float x)
-{
-    int r;
-    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
-    return r;
-}
-
-// a + b + c in one instruction
-__device__ inline int add3_vvv(int a, int b, int c)
-{
-    int r;
-    asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
-}
-
-// One HERCULES trace for the lane's ZP points: receiver at lateral offset
-// (x - xi, dy) from all of them (same x, y), trace window `win` starting at
-// sample interval w0 (passed negated, uniform).  The excess receive path in
-// samples, k rho^2 / (d + z), is evaluated as rho^2 / (d/k + z/k) with
-// d/k = sqrt(rho^2 / k^2 + (z/k)^2): the scale k is folded into the lane
-// constants (ik2 = 1 / k^2).
-template <int ET, int IP, int ZP, bool ADJ>
-__device__ inline void hercules_term(const LaneL (&L)[ZP], const float4 *win, int lmax,
-                                     const float2 *hann, float dy2, float ik2, float rot, float xi,
-                                     int neg_w0, float2 (&acc)[ZP])   // neg_w0: from LDS
-{
-    const float dx = L[0].x - xi;
-    const float rho2 = fmaf(dx, dx, dy2);
-#pragma unroll
-    for (int p = 0; p < ZP; ++p) {
-        const float dk = __builtin_amdgcn_sqrtf(fmaf(rho2, ik2, L[p].zk2));
-        const float s = fmaf(rho2, __builtin_amdgcn_rcpf(dk + L[p].zk), L[p].fB);
-        const int li = add3_vvv(cvt_flr(s), L[p].nB, neg_w0);
-        // Hann weight from the LDS table; u^2 >= 1/4 lands on the (0, 0) entry
-        const float xw = rho2 * L[p].wtab;
-        const float2 h = hann[min((unsigned)cvt_flr(xw), (unsigned)HANN_N)];
-        const float w = fmaf(__builtin_amdgcn_fractf(xw), h.y, h.x);
-        // no clamp: li lies in [-1, lmax + guard) for every lane (its
-        // geometry is inside the box); -1 reads the finite LDS word before the
-        // windows, and lanes outside their aperture (weight exactly 0) may
-        // read past their window into the next one or the zeroed guard
-        const float t = __builtin_amdgcn_fractf(s);
-        if constexpr (ET == ET_CF32) {
-            const float2 v = make_float2(eval_quad<IP>(win[2 * li], t), eval_quad<IP>(win[2 * li + 1], t));
-            rotate_acc(v, w, fmaf(rot, s, L[p].ph0), acc[p]);
-        } else if constexpr (ADJ) {
-            // adjoint (dL/dc): sums of w v'(s) and w v'(s) s (derivative quads)
-            const float wv = w * eval_dquad<IP>(win[li], t);
-            acc[p].x += wv;
-            acc[p].y = fmaf(wv, s, acc[p].y);
-        } else {
-            const float v = eval_quad<IP>(win[li], t);
-            acc[p].x = fmaf(w, v, acc[p].x);
-        }
-    }
-}
-
-// ADJ: the adjoint for dL/dc instead of the image: the staged quads hold the
-// read's derivative, each point accumulates sum w v'(s) and sum w v'(s) s, and
-// the workgroup writes its FP64 partial of dL/dc = -1/c sum_p G(p) sum_terms
-// w v'(s) (s + nB + t0 fs) (the delay's derivative: ds/dc = -(s_abs + t0 fs)/c).
-template <int MODE, int ET, int IP, int ZP, bool ADJ = false>
-__device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int grp,
-                                 float4 *smem)
-{
-    static_assert(!ADJ || ET != ET_CF32, "the adjoint is defined for real data");
-    static_assert(ZP == 1 || MODE == MODE_HERCULES, "two points per lane: HERCULES only");
-    constexpr int QM = StageRounds<MODE, ZP>::value;
-    const int nthr = blockDim.x;
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int nwaves = nthr >> 6;
-
-    // tables: tx_x, rx_c, the window starts of the two batch buffers (negated;
-    // read by the terms with one LDS load instead of a lane broadcast), Hann
-    // weights, then two buffers of [nb * lmax] quads (the Hann table sits
-    // right before them: an index of -1 reads finite data)
-    float *s_tx = reinterpret_cast<float *>(smem);
-    float *s_rx = s_tx + ((a.n_tx + 3) & ~3);
-    // (indexed from one base so that the compiler keeps them in LDS)
-    int *s_w0 = reinterpret_cast<int *>(s_rx + ((a.n_ch + 3) & ~3));
-    const int w0_stride = (c.nb + 3) & ~3;
-    float2 *s_hann = reinterpret_cast<float2 *>(s_w0 + 2 * w0_stride);
-    float4 *bufbase = reinterpret_cast<float4 *>(s_hann + HANN_TAB_PAD);
-    constexpr int QS = ET == ET_CF32 ? 2 : 1;     // quads per sample interval
-    const int buf_quads = c.nb * c.lmax * QS;
-    float4 *q0 = bufbase, *q1 = bufbase + buf_quads;
-    for (int t = tid; t < a.n_tx; t += nthr) s_tx[t] = a.tx_x[t];
-    for (int t = tid; t < a.n_ch; t += nthr) s_rx[t] = a.rx_c[t];
-    if constexpr (MODE == 1)
-        for (int t = tid; t < HANN_TAB_PAD; t += nthr)
-            s_hann[t] = t <= HANN_N ? a.hann_tab[t] : make_float2(0.f, 0.f);
-    if constexpr (MODE == MODE_HERCULES)   // finite data wherever an unclamped read can land
-        for (int t = tid; t < buf_quads + c.guard * QS; t += nthr) q1[t] = make_float4(0.f, 0.f, 0.f, 0.f);
-
-    const int bz = blk % c.blocks_z;
-    const int bx = (blk / c.blocks_z) % c.blocks_x;
-    const int by = blk / (c.blocks_z * c.blocks_x);
-    const BoxGeom box = block_box(a, c, bx, by, bz);
-    LaneL Lp[ZP];
-#pragma unroll
-    for (int p = 0; p < ZP; ++p) Lp[p] = lane_setup_l<MODE>(a, c, bx, by, bz, wave, lane, p);
-    const LaneL &L = Lp[0];
-    // largest rho^2 bound of the receive aperture over the lane's points
-    float thr_l = Lp[0].thr;
-#pragma unroll
-    for (int p = 1; p < ZP; ++p) thr_l = fmaxf(thr_l, Lp[p].thr);
-    const float kf = (float)a.k;
-    const float ik2 = uniform_f((float)(1.0 / (a.k * a.k)));
-    const float rot = a.rot;
-    float2 acc[ZP];
-#pragma unroll
-    for (int p = 0; p < ZP; ++p) acc[p] = make_float2(0.f, 0.f);
-    __syncthreads();
-
-    int jb, je;
-    group_rows(a.n_ch, grp, a.groups, &jb, &je);
-    Iter it;
-    it.j = MODE == 1 ? jb - 1 : jb;
-    it.jend = je;
-    it.i = MODE == 1 ? 0 : a.n_tx;
-    it.ihi = 0;
-    for (int q = 0; q < JC; ++q) it.rows[q] = -1;
-
-    BatchDesc cur = next_batch<MODE>(a, c, box, s_tx, s_rx, it);
-    Staged<QM> st;
-    TraceDesc td = {0, 0.f, -1};       // descriptors of the current batch
-    if (cur.valid) {
-        td = trace_desc<MODE>(a, c, box, s_tx, s_rx, cur, lane);
-        stage_load<ET, QM>(a, c, td, st, wave, lane, nwaves);
-        stage_store<IP, QS, QM, ADJ>(c, st, q0, wave, lane, nwaves);
-        store_w0<MODE>(c, td, s_w0, wave, lane);
-    }
-    __syncthreads();
-
-    // per-row lane state
-    int row_j = -1;
-    float dy2 = 0.f, wlo = 0.f, whi = 0.f;              // HERCULES
-    int rows_cur[JC];
-    float Rj[JC], aj[JC];
-    bool row_on[JC];
-    for (int q = 0; q < JC; ++q) { rows_cur[q] = -1; Rj[q] = 0.f; aj[q] = 0.f; row_on[q] = false; }
-
-    int bi = 0;
-    while (cur.valid) {
-        BatchDesc nxt = next_batch<MODE>(a, c, box, s_tx, s_rx, it);
-        TraceDesc td_n = {0, 0.f, -1};
-        if (nxt.valid) {
-            td_n = trace_desc<MODE>(a, c, box, s_tx, s_rx, nxt, lane);
-            stage_load<ET, QM>(a, c, td_n, st, wave, lane, nwaves);
-        }
-
-        const float4 *quads = (bi & 1) ? q1 : q0;
-        const TraceDesc &mine = td;
-        if constexpr (MODE == 1) {
-            if (cur.j != row_j) {
-                row_j = cur.j;
-                const float dy = L.y - s_rx[row_j];
-                dy2 = dy * dy;
-                const float r2 = thr_l - dy2;
-                const float r = r2 > 0.f ? sqrtf(r2) : 0.f;
-                wlo = uniform_f(wave_min(r2 > 0.f ? L.x - r : __builtin_inff()));
-                whi = uniform_f(wave_max(r2 > 0.f ? L.x + r : -__builtin_inff()));
-            }
-            // traces inside the union of this wavefront's receive apertures
-            // (a contiguous run: the columns are sorted within a batch), in
-            // pairs whose LDS reads overlap, then an odd last one
-            uint64_t mask = __ballot(lane < cur.cnt && mine.xi >= wlo && mine.xi <= whi);
-            // per trace: the column position from the read-only table through
-            // the scalar cache (uniform index) and the negated window start
-            // from LDS -- no lane broadcasts (their SGPR results stall the wave)
-            const float *__restrict__ txcol = a.tx_x + cur.i0;
-            const int *wst = s_w0 + (bi & 1) * w0_stride;
-            if constexpr (ZP == 2) {
-                // one trace per step already gives two independent terms
-                while (mask) {
-                    const int e1 = __builtin_ctzll(mask);
-                    mask &= mask - 1;
-                    hercules_term<ET, IP, ZP, ADJ>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2,
-                                              ik2, rot, txcol[e1], wst[e1], acc);
-                }
-            }
-            while (mask & (mask - 1)) {
-                const int e1 = __builtin_ctzll(mask);
-                mask &= mask - 1;
-                const int e2 = __builtin_ctzll(mask);
-                mask &= mask - 1;
-                hercules_term<ET, IP, ZP, ADJ>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
-                                          rot, txcol[e1], wst[e1], acc);
-                hercules_term<ET, IP, ZP, ADJ>(Lp, quads + e2 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
-                                          rot, txcol[e2], wst[e2], acc);
-            }
-            if (mask) {
-                const int e1 = __builtin_ctzll(mask);
-                hercules_term<ET, IP, ZP, ADJ>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
-                                          rot, txcol[e1], wst[e1], acc);
-            }
-        } else {
-            const int nbi = c.nb / JC;
-#pragma unroll
-            for (int q = 0; q < JC; ++q) {
-                if (cur.rows[q] != rows_cur[q]) {
-                    rows_cur[q] = cur.rows[q];
-                    if (rows_cur[q] >= 0) {
-                        const float dxr = rx_coord<MODE>(L.x, L.y) - s_rx[rows_cur[q]];
-                        const float r2 = dxr * dxr;
-                        const bool act = r2 < L.thr;
-                        Rj[q] = fmaf(excess(r2, L.z, L.z2), kf, L.fB);
-                        aj[q] = act ? hann_u2(r2 * L.wsc) : 0.f;
-                        row_on[q] = __any(act);
-                    } else {
-                        row_on[q] = false;
-                    }
-                }
-            }
-            const int4 *wst4 = reinterpret_cast<const int4 *>(s_w0 + (bi & 1) * w0_stride);
-            // the transmits' table entries through the scalar cache (uniform)
-            const float *__restrict__ tscf = reinterpret_cast<const float *>(a.tx_sc) + 2 * cur.i0;
-            const float *__restrict__ txc = a.tx_x + cur.i0;
-            for (int ii = 0; ii < cur.cnt; ++ii) {
-                // transmit excess path of this lane, shared by the batch's rows
-                const float T =
-                    kf * tx_excess_p<MODE>(L.x, L.z, L.z2,
-                                           MODE == MODE_TPW ? make_float2(tscf[2 * ii], tscf[2 * ii + 1])
-                                                            : make_float2(0.f, 0.f),
-                                           MODE == MODE_TPW ? 0.f : txc[ii], a.zf);
-                const int4 nw4 = wst4[ii];    // negated window starts of the 4 rows
-                const int nw[JC] = {nw4.x, nw4.y, nw4.z, nw4.w};
-#pragma unroll
-                for (int q = 0; q < JC; ++q) {
-                    if (!row_on[q]) continue;
-                    const int e = q * nbi + ii;
-                    const float sq = Rj[q] + T;
-                    const int li = (int)floorf(sq) + L.nB + nw[q];
-                    if constexpr (ET == ET_CF32) {
-                        const float2 v = read_quad_cx<IP>(quads + e * c.lmax * QS, li, c.lmax,
-                                                          __builtin_amdgcn_fractf(sq));
-                        rotate_acc(v, aj[q], fmaf(rot, sq, L.ph0), acc[0]);
-                    } else if constexpr (ADJ) {
-                        const float wv = aj[q] * eval_dquad<IP>(
-                                                     quads[e * c.lmax + clamp0_i32(li, c.lmax - 1)],
-                                                     __builtin_amdgcn_fractf(sq));
-                        acc[0].x += wv;
-                        acc[0].y = fmaf(wv, sq, acc[0].y);
-                    } else {
-                        const float v = read_quad<IP>(quads + e * c.lmax, li, c.lmax,
-                                                      __builtin_amdgcn_fractf(sq));
-                        acc[0].x = fmaf(aj[q], v, acc[0].x);
-                    }
-                }
-            }
-        }
-
-        if (!nxt.valid) break;
-        stage_store<IP, QS, QM, ADJ>(c, st, ((bi + 1) & 1) ? q1 : q0, wave, lane, nwaves);
-        store_w0<MODE>(c, td_n, s_w0 + ((bi + 1) & 1) * w0_stride, wave, lane);
-        __syncthreads();
-        cur = nxt;
-        td = td_n;
-        ++bi;
-    }
-    // the point indices are recomputed here (an opaque copy of the lane
-    // number), so they hold no registers during the loop
-    int lane_e = lane;
-    asm volatile("" : "+v"(lane_e));
-    if constexpr (ADJ) {
-        double contrib = 0.0;
-#pragma unroll
-        for (int p = 0; p < ZP; ++p) {
-            int ix, iy, iz;
-            lane_point(a, c, bx, by, bz, wave, lane_e, p, &ix, &iy, &iz);
-            if (ix < a.g.nx && iy < a.g.ny && iz >= 0 && iz < a.g.nz) {
-                const double pz = a.g.org[2] + ix * a.g.ax[2] + iy * a.g.ay[2] + iz * a.g.az[2];
-                if (pz > 0.0) {
-                    const double G = a.grad_out[((long)iy * a.g.nx + ix) * a.g.nz + iz];
-                    contrib += G * ((double)acc[p].y + ((double)Lp[p].nB + a.t0fs) * (double)acc[p].x);
-                }
-            }
-        }
-        // workgroup sum in a fixed order -> one partial per (box, channel group)
-        __shared__ double red[16];
-        for (int off = 32; off > 0; off >>= 1) contrib += __shfl_down(contrib, off, 64);
-        if (lane == 0) red[wave] = contrib;
-        __syncthreads();
-        if (tid == 0) {
-            double t = 0.0;
-            for (int w = 0; w < nwaves; ++w) t += red[w];
-            a.partial[(long)grp * gridDim.x + blockIdx.x] = -t / a.c;
-        }
-        return;
-    }
-    const long npts = (long)a.g.nx * a.g.ny * a.g.nz;
-    float *dst = a.groups > 1 ? a.part + (long)grp * npts * QS : das_out(a);
-#pragma unroll
-    for (int p = 0; p < ZP; ++p) {
-        int ix, iy, iz;
-        lane_point(a, c, bx, by, bz, wave, lane_e, p, &ix, &iy, &iz);
-        if (ix < a.g.nx && iy < a.g.ny && iz >= 0 && iz < a.g.nz) {
-            const long idx = ((long)iy * a.g.nx + ix) * a.g.nz + iz;
-            const double pz = a.g.org[2] + ix * a.g.ax[2] + iy * a.g.ay[2] + iz * a.g.az[2];
-            const float2 v = pz > 0.0 ? acc[p] : make_float2(0.f, 0.f);
-            if constexpr (ET == ET_CF32)
-                reinterpret_cast<float2 *>(dst)[idx] = v;
-            else
-                dst[idx] = v.x;
-        }
-    }
-}
-
-// Two points per lane and the row-column modes: registers capped for 6
-// wavefronts per SIMD (two 12-wavefront workgroups per CU).
-template <int MODE, int ZP> struct WavesPerEu {
-    static constexpr int value = (ZP == 2 || MODE == MODE_TPW || MODE == MODE_VLS) ? 6 : 1;
-};
 
 template <int MODE, int ET, int IP, int ZP>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerEu<MODE, ZP>::value)))
@@ -942,15 +13,6 @@ void das_lds_kernel(DasArgs a, LdsCfg c)
 {
     extern __shared__ float4 smem[];
     das_block<MODE, ET, IP, ZP>(a, c, blockIdx.x, blockIdx.y, smem);
-}
-
-// dL/dc of the DAS image (real data): one FP64 partial per (box, channel group).
-template <int MODE, int IP, int ZP>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerEu<MODE, ZP>::value)))
-void das_lds_adj_kernel(DasArgs a, LdsCfg c)
-{
-    extern __shared__ float4 smem[];
-    das_block<MODE, ET_F32, IP, ZP, true>(a, c, blockIdx.x, blockIdx.y, smem);
 }
 
 // Persistent form for a batch of frames: each workgroup pulls (frame, box)
@@ -981,13 +43,6 @@ void das_persistent_kernel(const FrameDas *__restrict__ frames,
     }
 }
 
-// Dynamic LDS beyond 64 KiB (gfx950 has 160 KiB per CU) is requested per
-// kernel before its launch.
-static hipError_t allow_lds(const void *fn, size_t shm)
-{
-    if (shm <= 65536) return hipSuccess;
-    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-}
 
 template <int MODE, int ET, int IP, int ZP>
 static hipError_t launch_persistent4(const PersistentLaunch &p, hipStream_t s)
@@ -1103,66 +158,18 @@ static hipError_t launch_lds_et(const DasArgs &a, const LdsCfg &c, int et, int i
     }
 }
 
-hipError_t launch_reduce_partials(const double *partial, int n, float *out, hipStream_t s);
-size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard);
-
-template <int MODE, int IP, int ZP>
-static hipError_t launch_adj_lds3(const DasArgs &a, const LdsCfg &c, size_t shm, hipStream_t s)
+size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard, int adj)
 {
-    const int nthr = 64 * c.bwx * c.bwy * c.bwz;
-    dim3 grid(c.blocks_x * c.blocks_y * c.blocks_z, a.groups);
-    hipError_t e = allow_lds(reinterpret_cast<const void *>(&das_lds_adj_kernel<MODE, IP, ZP>), shm);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((das_lds_adj_kernel<MODE, IP, ZP>), grid, dim3(nthr), shm, s, a, c);
-    return hipGetLastError();
-}
-
-template <int MODE, int IP>
-static hipError_t launch_adj_lds2(const DasArgs &a, const LdsCfg &c, size_t shm, hipStream_t s)
-{
-    if constexpr (MODE == MODE_HERCULES)
-        if (c.zp == 2) return launch_adj_lds3<MODE, IP, 2>(a, c, shm, s);
-    return c.zp == 1 ? launch_adj_lds3<MODE, IP, 1>(a, c, shm, s) : hipErrorInvalidValue;
-}
-
-template <int MODE>
-static hipError_t launch_adj_lds1(const DasArgs &a, const LdsCfg &c, int ip, size_t shm, hipStream_t s)
-{
-    switch (ip) {
-        case IN_LINEAR: return launch_adj_lds2<MODE, IN_LINEAR>(a, c, shm, s);
-        case IN_CUBIC: return launch_adj_lds2<MODE, IN_CUBIC>(a, c, shm, s);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-// dL/dc with the LDS-staged kernel (FP32 data, linear or cubic reads): the
-// workgroups' partials, then their sum in a fixed order into grad_c.
-hipError_t launch_das_lds_adjoint_c(const DasArgs &a, const LdsCfg &c, int mode, int ip,
-                                    float *grad_c, hipStream_t s)
-{
-    const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, 1, c.guard);
-    hipError_t err;
-    switch (mode) {
-        case MODE_FORCES: err = launch_adj_lds1<MODE_FORCES>(a, c, ip, shm, s); break;
-        case MODE_HERCULES: err = launch_adj_lds1<MODE_HERCULES>(a, c, ip, shm, s); break;
-        case MODE_TPW: err = launch_adj_lds1<MODE_TPW>(a, c, ip, shm, s); break;
-        case MODE_VLS: err = launch_adj_lds1<MODE_VLS>(a, c, ip, shm, s); break;
-        default: return hipErrorInvalidValue;
-    }
-    if (err != hipSuccess) return err;
-    return launch_reduce_partials(a.partial, c.blocks_x * c.blocks_y * c.blocks_z * a.groups, grad_c, s);
-}
-
-size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard)
-{
+    const bool stage = adj == 0 || (adj & 1);     // data windows staged
     return (size_t)(((n_tx + 3) & ~3) + ((n_ch + 3) & ~3) + 2 * ((nb + 3) & ~3)) * 4 +
-           (size_t)HANN_TAB_PAD * 8 + (2 * (size_t)nb * lmax + guard) * qs * 16;
+           (size_t)HANN_TAB_PAD * 8 + (stage ? (2 * (size_t)nb * lmax + guard) * qs * 16 : 0) +
+           ((adj & 2) ? 2 * (size_t)nb * (lmax + 3) * 8 + 16 * 4 : 0);
 }
 
 hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, int ip,
                           hipStream_t s)
 {
-    const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, a.cx ? 2 : 1, c.guard);
+    const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, a.cx ? 2 : 1, c.guard, 0);
     hipError_t err;
     switch (mode) {
         case MODE_FORCES: err = launch_lds_et<MODE_FORCES>(a, c, et, ip, shm, s); break;

@@ -55,7 +55,8 @@ struct Frame {
     size_t e_bytes() const;
     DecodeArgs decode_args(const int16_t *rf, void *e) const;
     DasArgs das_args(const void *e, float *out, double c) const;
-    bool lds_config(const DasArgs &a, LdsCfg *cfg) const;
+    bool lds_config(const DasArgs &a, LdsCfg *cfg, int adj = 0, const int *bw_adj = nullptr) const;
+    void adjoint_e_tile(DasArgs *a, int bw_out[3]) const;   // the RF gradient's lane tile
     bool z2_ok() const;          // two depth points per lane apply to this frame
     int decode(const int16_t *rf, void *e, hipStream_t s) const;
     int das(const void *e, float *out, double c, hipStream_t s) const;
@@ -66,9 +67,9 @@ struct Batch;   // persistent batched path state (bf_batch.hip)
 hipError_t launch_das(const DasArgs &a, int mode, int et, int ip, hipStream_t s);
 hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, int ip,
                           hipStream_t s);
-size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard);
-hipError_t launch_das_lds_adjoint_c(const DasArgs &a, const LdsCfg &c, int mode, int ip,
-                                    float *grad_c, hipStream_t s);
+size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard, int adj);
+hipError_t launch_das_lds_adjoint(const DasArgs &a, const LdsCfg &c, int mode, int ip,
+                                  float *grad_c, hipStream_t s);
 
 constexpr uint32_t BF_PLAN_MAGIC = 0xBF0C0DE5u;
 

@@ -109,7 +109,8 @@ def cpu_baseline(desc, H, rf, budget_s: float):
 
 
 VARIANT_NAMES = {0: "lds", 1: "gather", 2: "lds2"}
-KERNEL_SOURCES = ("paper_2512_11086_amd/csrc/bf_das_lds.hip", "paper_2512_11086_amd/csrc/bf_common.h")
+KERNEL_SOURCES = ("paper_2512_11086_amd/csrc/bf_das_lds.hip", "paper_2512_11086_amd/csrc/bf_das_lds_block.h",
+                  "paper_2512_11086_amd/csrc/bf_common.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "das_hercules_128x128x256_traffic.json")
 
 

@@ -223,3 +223,21 @@ def test_de_fixed_point_range(torch_mod):
     gs, _ = plan.das_adjoint(None, torch.from_numpy(small.astype(np.float32)).cuda(), want_c=False)
     refs = oracle.das_adjoint_e(d, small.astype(np.float32).astype(np.float64))
     assert rel_l2(gs.cpu().numpy(), refs) <= 1e-5
+
+
+@pytest.mark.parametrize("k", [1, 6, 7])
+def test_de_full_size_adjoint_identity(torch_mod, k):
+    # full-size volumes (HERCULES, TPW-32, VLS-128, default configuration):
+    # <DAS(e), G> = <e, dL/de> holds at any size
+    torch = torch_mod
+    desc, H, rf, _ = synth.make_inputs(k)
+    plan = bfm.Plan(desc, H)
+    e = plan.decode(torch.from_numpy(rf).cuda())
+    img = plan.das(e)
+    gen = torch.Generator(device="cuda").manual_seed(100 + k)
+    G = torch.randn(img.shape, device="cuda", generator=gen)
+    ge, _ = plan.das_adjoint(None, G, want_c=False)
+    lhs = (img.double() * G.double()).sum().item()
+    rhs = (e.double() * ge.double()).sum().item()
+    bound = 1e-5 * img.double().norm().item() * G.double().norm().item()
+    assert abs(lhs - rhs) <= bound, (lhs, rhs, bound)

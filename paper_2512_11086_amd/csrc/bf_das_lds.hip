@@ -7,12 +7,33 @@ namespace bf {
 
 hipError_t launch_sum_groups(const DasArgs &a, hipStream_t s);
 
+// Box order of the single-frame kernel.  Workgroups are dispatched in index
+// order, round-robin over the 8 XCDs (index b runs on XCD b % 8), and each
+// XCD has its own L2.  XCD x takes the depth slabs x, x + 8, x + 16, ... (a
+// slab = every lateral box at one box depth), deepest first: the boxes
+// resident on an XCD at a time lie side by side at one depth and stage
+// nearly the same trace windows, which then hit in that XCD's L2, and the
+// costliest boxes (the widest apertures) start first.  The grid holds
+// nlat * 8 * ceil(blocks_z / 8) workgroups; those past the last slab return.
+// Any order is correct (each box is visited once); this one measured 5 %
+// faster than depth-fastest order on the 128 x 128 x 256 HERCULES volume.
+__device__ inline int xcd_slab_box(const LdsCfg &c, int b)
+{
+    const int nlat = c.blocks_x * c.blocks_y;
+    const int slot = b >> 3;
+    const int zrank = (slot / nlat) * 8 + (b & 7);     // 0 = deepest slab
+    if (zrank >= c.blocks_z) return -1;
+    return (c.blocks_z - 1 - zrank) + c.blocks_z * (slot % nlat);
+}
+
 template <int MODE, int ET, int IP, int ZP>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerEu<MODE, ZP>::value)))
 void das_lds_kernel(DasArgs a, LdsCfg c)
 {
     extern __shared__ float4 smem[];
-    das_block<MODE, ET, IP, ZP>(a, c, blockIdx.x, blockIdx.y, smem);
+    const int blk = xcd_slab_box(c, blockIdx.x);
+    if (blk < 0) return;
+    das_block<MODE, ET, IP, ZP>(a, c, blk, blockIdx.y, smem);
 }
 
 // Persistent form for a batch of frames: each workgroup pulls (frame, box)
@@ -118,7 +139,7 @@ template <int MODE, int ET, int IP, int ZP>
 static hipError_t launch_lds4(const DasArgs &a, const LdsCfg &c, size_t shm, hipStream_t s)
 {
     const int nthr = 64 * c.bwx * c.bwy * c.bwz;
-    dim3 grid(c.blocks_x * c.blocks_y * c.blocks_z, a.groups);
+    dim3 grid(c.blocks_x * c.blocks_y * 8 * ((c.blocks_z + 7) / 8), a.groups);   // xcd_slab_box
     hipError_t e = allow_lds(reinterpret_cast<const void *>(&das_lds_kernel<MODE, ET, IP, ZP>), shm);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((das_lds_kernel<MODE, ET, IP, ZP>), grid, dim3(nthr), shm, s, a, c);

@@ -298,9 +298,10 @@ int Frame::init(const bf_params &src)
         if (he != hipSuccess) return hip_fail(he, "upload of the TPW angle table");
     }
     // partial-sum buffer of the adjoint, large enough for any tile: one entry
-    // per 4-wavefront block (gather kernel) or per (LDS box, channel group);
-    // a box holds at least one wavefront and the channel split keeps
-    // groups x wavefronts below wavefronts + 8192
+    // per 4-wavefront block (gather kernel) or per (LDS workgroup, channel
+    // group); a box holds at least one wavefront, the slab order pads the
+    // boxes to whole groups of 8 depth slabs (at most 8x), and the channel
+    // split keeps groups x wavefronts below wavefronts + 8192
     long max_waves = 0;
     for (int lx = 0; lx <= 6; ++lx)
         for (int ly = 0; ly + lx <= 6; ++ly) {
@@ -309,7 +310,7 @@ int Frame::init(const bf_params &src)
                            ((grid.ny + (1 << ly) - 1) >> ly) * ((grid.nz + (1 << lz) - 1) >> lz);
             if (w > max_waves) max_waves = w;
         }
-    max_blocks = max_waves + 8192;
+    max_blocks = 8 * (max_waves + 8192);
     d_partial = (double *)alloc((size_t)max_blocks * sizeof(double));
     {
         // Eq. 3 in double precision at u^2 = k / (4 HANN_N), value + slope
@@ -502,10 +503,13 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg, int adj, const int *bw_adj
     // [1, k spread + 3] (the start w0 is floored 2 samples below the box's
     // lowest path, the quad covers taps n-1 .. n+2); one quad of FP32 slack.
     const int lmax = (int)ceil(a.k * spread) + 5;
-    // HERCULES reads without an index clamp: a lane outside its aperture
-    // (weight 0) may reach past its window by at most the receive path's
-    // extra lateral slope, (1 - srx) lat, into the next window or this guard
-    const int guard = sep ? 0 : (int)ceil(a.k * (1.0 - srx) * lat) + 3;
+    // The terms read without an index clamp: a lane outside its receive
+    // aperture (weight 0) may reach past its window by at most the receive
+    // path's extra lateral slope, (1 - srx) times the box's receive-lateral
+    // extent (HERCULES: radial; FORCES: x; TPW, VLS: y), into the next window
+    // or this zeroed guard
+    const double rx_lat = p.mode == BF_HERCULES_3D ? lat : p.mode == BF_FORCES_2D ? E[0] : E[1];
+    const int guard = (int)ceil(a.k * (1.0 - srx) * rx_lat) + 3;
     const int nthr = 64 * bw[0] * bw[1] * bw[2];
     int nbb = nb;
     const int unit = sep ? 4 : 1;       // separable modes: 4 rows per batch
@@ -789,7 +793,7 @@ int bf_das_adjoint(bf_plan plan, const void *e, const float *grad_out, double c,
     f.adjoint_e_tile(&ae, bwa);
     const bool e_lds = grad_e && lds_ok && f.lds_config(ae, &ce, 2, bwa);
     const bool c_lds = grad_c && lds_ok && f.p.e_type == BF_E_F32 && f.lds_config(a, &cc, 1) &&
-                       (long)cc.blocks_x * cc.blocks_y * cc.blocks_z * a.groups <= f.max_blocks;
+                       (long)xcd_slab_grid(cc) * a.groups <= f.max_blocks;
     hipError_t err = hipSuccess;
     DasArgs ag = a;                 // what the LDS kernels do not take
     ag.grad_e = e_lds ? nullptr : grad_e;

@@ -5,10 +5,11 @@
 // transmit subsets of different sizes, 2D and 3D outputs).  Frames are
 // grouped into kernel classes: decode by (32-wide K blocks, output type) and
 // DAS by (mode, data type, interpolation).  Each class runs as ONE persistent
-// launch whose workgroups pull work items from an atomic queue: decode items
-// are (frame, channel, 256 samples), DAS items are (frame, workgroup box),
-// sorted by decreasing cost so that the tail of the queue is made of short
-// items.  Decoded data stays in plan-owned workspaces; the caller's RF and
+// launch whose workgroups pull work items from atomic queues: decode items
+// are (frame, channel, 256 samples); DAS items are (frame, workgroup box),
+// grouped into depth slabs that are dealt to one queue per XCD in decreasing
+// cost, so the tail is made of short items and the boxes that run together
+// on an XCD share trace windows in its L2.  Decoded data stays in plan-owned workspaces; the caller's RF and
 // output buffers are passed through a device pointer table refreshed before
 // every launch, so a captured graph never needs re-capture for new buffers.
 #include <math.h>
@@ -31,7 +32,7 @@ hipError_t launch_fill(float *p, long n, float v, hipStream_t s);
 
 __global__ void reset_counters_kernel(int *c, int n)
 {
-    if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) c[q] = 0;
 }
 
 struct DecClass {
@@ -41,12 +42,19 @@ struct DecClass {
     int grid = 0;
 };
 
+struct DasItem {
+    double cost;    // per-box cost of its frame
+    int slab;       // box depth index (bz)
+    int2 item;      // (frame, box)
+};
+
 struct DasClass {
     int mode, et, ip, zp, threads;
     size_t shm = 0;
-    std::vector<std::pair<double, int2>> items;   // (cost, item)
+    std::vector<DasItem> items;
     int2 *d_items = nullptr;
     int n_items = 0;
+    QueueSet queues{};
     int grid = 0;
 };
 
@@ -161,7 +169,7 @@ static int build_batch(bf_plan plan)
             cls->shm = std::max(cls->shm, shm);
             const int nblk = c.blocks_x * c.blocks_y * c.blocks_z;
             const double cost = (double)fr.p.n_tx * fr.p.n_ch * threads;
-            for (int q = 0; q < nblk; ++q) cls->items.push_back({cost, make_int2(f, q)});
+            for (int q = 0; q < nblk; ++q) cls->items.push_back({cost, q % c.blocks_z, make_int2(f, q)});
         }
         fdas[f].a = a;
         fdas[f].c = c;
@@ -183,7 +191,7 @@ static int build_batch(bf_plan plan)
                 for (int g = 0; g < n_cg; ++g) cls->items.push_back(make_int2(f, j * n_cg + g));
         }
     }
-    const int n_counters = (int)(b->dec.size() + b->das.size());
+    const int n_counters = (int)(b->dec.size() + b->das.size() * N_XCD_QUEUES);
     b->d_fdec = (FrameDec *)b->alloc(sizeof(FrameDec) * F);
     b->d_fdas = (FrameDas *)b->alloc(sizeof(FrameDas) * F);
     b->d_ptrs = (void **)b->alloc(sizeof(void *) * 2 * F);
@@ -208,12 +216,28 @@ static int build_batch(bf_plan plan)
         d.grid = std::min<int>((int)d.items.size(), cus * 8);
     }
     for (DasClass &d : b->das) {
-        std::stable_sort(d.items.begin(), d.items.end(),
-                         [](const std::pair<double, int2> &x, const std::pair<double, int2> &y) {
-                             return x.first > y.first;
-                         });
-        std::vector<int2> it(d.items.size());
-        for (size_t q = 0; q < it.size(); ++q) it[q] = d.items[q].second;
+        // Depth slabs (frame, bz) in decreasing cost (costlier frames, then
+        // deeper slabs: wider apertures) dealt round-robin to the per-XCD
+        // queues; a slab's boxes stay together in its queue.
+        std::stable_sort(d.items.begin(), d.items.end(), [](const DasItem &x, const DasItem &y) {
+            if (x.cost != y.cost) return x.cost > y.cost;
+            if (x.item.x != y.item.x) return x.item.x < y.item.x;
+            return x.slab > y.slab;
+        });
+        std::vector<std::vector<int2>> per(N_XCD_QUEUES);
+        int next = 0;
+        for (size_t q = 0; q < d.items.size(); ++q) {
+            if (q > 0 && (d.items[q].item.x != d.items[q - 1].item.x ||
+                          d.items[q].slab != d.items[q - 1].slab))
+                next = (next + 1) % N_XCD_QUEUES;
+            per[next].push_back(d.items[q].item);
+        }
+        std::vector<int2> it;
+        for (int q = 0; q < N_XCD_QUEUES; ++q) {
+            d.queues.off[q] = (int)it.size();
+            it.insert(it.end(), per[q].begin(), per[q].end());
+        }
+        d.queues.off[N_XCD_QUEUES] = (int)it.size();
         d.n_items = (int)it.size();
         d.d_items = (int2 *)b->alloc(sizeof(int2) * it.size());
         if (!d.d_items) return fail(BF_ERR_HIP, "batch item allocation failed");
@@ -255,7 +279,7 @@ static int stage_pointers(Batch *b, const int16_t *const *rf, float *const *out,
 static int enqueue(bf_plan plan, hipStream_t s)
 {
     Batch *b = plan->batch;
-    const int n_counters = (int)(b->dec.size() + b->das.size());
+    const int n_counters = (int)(b->dec.size() + b->das.size() * N_XCD_QUEUES);
     hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, b->d_counters,
                        n_counters);
     int ci = 0;
@@ -283,8 +307,9 @@ static int enqueue(bf_plan plan, hipStream_t s)
         L.shm = d.shm;
         L.frames = b->d_fdas;
         L.items = d.d_items;
-        L.n_items = d.n_items;
-        L.counter = b->d_counters + ci++;
+        L.queues = d.queues;
+        L.counters = b->d_counters + ci;
+        ci += N_XCD_QUEUES;
         L.out_ptrs = b->d_ptrs + b->F;
         hipError_t e = launch_das_persistent(L, s);
         if (e != hipSuccess) return hip_fail(e, "persistent DAS launch");

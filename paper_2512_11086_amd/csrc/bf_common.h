@@ -118,10 +118,24 @@ struct LdsCfg {
                          // (HERCULES: reads of lanes outside their aperture)
 };
 
+// Workgroups of a single-frame LDS launch (box order xcd_slab_box): whole
+// groups of 8 depth slabs.
+__host__ __device__ inline int xcd_slab_grid(const LdsCfg &c)
+{
+    return c.blocks_x * c.blocks_y * 8 * ((c.blocks_z + 7) / 8);
+}
+
 // One frame of a batch for the persistent DAS kernel (device table entry).
 struct FrameDas {
     DasArgs a;      // out is taken from the per-launch pointer table
     LdsCfg c;
+};
+
+// Work queues of the persistent DAS kernel: one per XCD, queue q holding
+// items[off[q] .. off[q + 1]).
+constexpr int N_XCD_QUEUES = 8;
+struct QueueSet {
+    int off[N_XCD_QUEUES + 1];
 };
 
 struct PersistentLaunch {
@@ -129,9 +143,9 @@ struct PersistentLaunch {
     int grid, threads;
     size_t shm;
     const FrameDas *frames;
-    const int2 *items;      // (frame, workgroup box)
-    int n_items;
-    int *counter;
+    const int2 *items;      // (frame, workgroup box), grouped by queue
+    QueueSet queues;
+    int *counters;          // one per queue
     void *const *out_ptrs;  // [n_frames] device pointers
 };
 

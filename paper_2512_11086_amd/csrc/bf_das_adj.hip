@@ -15,14 +15,19 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerEu
 void das_lds_adj_kernel(DasArgs a, LdsCfg c)
 {
     extern __shared__ float4 smem[];
-    das_block<MODE, ET_F32, IP, ZP, ADJ>(a, c, blockIdx.x, blockIdx.y, smem);
+    const int blk = xcd_slab_box(c, blockIdx.x);
+    if (blk < 0) {      // past the last slab: an empty partial for dL/dc
+        if ((ADJ & 1) && threadIdx.x == 0) a.partial[(long)blockIdx.y * gridDim.x + blockIdx.x] = 0.0;
+        return;
+    }
+    das_block<MODE, ET_F32, IP, ZP, ADJ>(a, c, blk, blockIdx.y, smem);
 }
 
 template <int MODE, int IP, int ZP, int ADJ>
 static hipError_t launch_adj_lds4(const DasArgs &a, const LdsCfg &c, size_t shm, hipStream_t s)
 {
     const int nthr = 64 * c.bwx * c.bwy * c.bwz;
-    dim3 grid(c.blocks_x * c.blocks_y * c.blocks_z, a.groups);
+    dim3 grid(xcd_slab_grid(c), a.groups);
     hipError_t e =
         allow_lds(reinterpret_cast<const void *>(&das_lds_adj_kernel<MODE, IP, ZP, ADJ>), shm);
     if (e != hipSuccess) return e;
@@ -85,7 +90,7 @@ hipError_t launch_das_lds_adjoint(const DasArgs &a, const LdsCfg &c, int mode, i
         default: return hipErrorInvalidValue;
     }
     if (err != hipSuccess || !grad_c) return err;
-    return launch_reduce_partials(a.partial, c.blocks_x * c.blocks_y * c.blocks_z * a.groups, grad_c, s);
+    return launch_reduce_partials(a.partial, xcd_slab_grid(c) * a.groups, grad_c, s);
 }
 
 }  // namespace bf

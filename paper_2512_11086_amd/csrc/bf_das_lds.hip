@@ -7,25 +7,6 @@ namespace bf {
 
 hipError_t launch_sum_groups(const DasArgs &a, hipStream_t s);
 
-// Box order of the single-frame kernel.  Workgroups are dispatched in index
-// order, round-robin over the 8 XCDs (index b runs on XCD b % 8), and each
-// XCD has its own L2.  XCD x takes the depth slabs x, x + 8, x + 16, ... (a
-// slab = every lateral box at one box depth), deepest first: the boxes
-// resident on an XCD at a time lie side by side at one depth and stage
-// nearly the same trace windows, which then hit in that XCD's L2, and the
-// costliest boxes (the widest apertures) start first.  The grid holds
-// nlat * 8 * ceil(blocks_z / 8) workgroups; those past the last slab return.
-// Any order is correct (each box is visited once); this one measured 5 %
-// faster than depth-fastest order on the 128 x 128 x 256 HERCULES volume.
-__device__ inline int xcd_slab_box(const LdsCfg &c, int b)
-{
-    const int nlat = c.blocks_x * c.blocks_y;
-    const int slot = b >> 3;
-    const int zrank = (slot / nlat) * 8 + (b & 7);     // 0 = deepest slab
-    if (zrank >= c.blocks_z) return -1;
-    return (c.blocks_z - 1 - zrank) + c.blocks_z * (slot % nlat);
-}
-
 template <int MODE, int ET, int IP, int ZP>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerEu<MODE, ZP>::value)))
 void das_lds_kernel(DasArgs a, LdsCfg c)
@@ -37,30 +18,40 @@ void das_lds_kernel(DasArgs a, LdsCfg c)
 }
 
 // Persistent form for a batch of frames: each workgroup pulls (frame, box)
-// items from a queue until it is empty.  Items are ordered by decreasing
-// cost on the host, so the queue balances uneven frames.
+// items from queues until they are empty.  There is one queue per XCD; the
+// host deals whole depth slabs of a frame to the queues (costliest first), so
+// the workgroups on one XCD (index b runs on XCD b % 8: the grid is resident
+// at once and dispatched round-robin) work on neighbouring boxes that share
+// trace windows in that XCD's L2.  A workgroup drains its home queue, then
+// takes what is left in the others, so uneven queues still balance.  Every
+// workgroup leaves after one failed pull per queue.
 template <int MODE, int ET, int IP, int ZP>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerEu<MODE, ZP>::value)))
 void das_persistent_kernel(const FrameDas *__restrict__ frames,
                                                               const int2 *__restrict__ items,
-                                                              int n_items, int *counter,
+                                                              QueueSet queues, int *counters,
                                                               void *const *__restrict__ out_ptrs)
 {
     extern __shared__ float4 smem[];
     __shared__ int s_item;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
-        __syncthreads();
-        // the item is workgroup-uniform: keep it (and all it indexes) scalar
-        const int item = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        if (item >= n_items) break;
-        const int fr = __builtin_amdgcn_readfirstlane(items[item].x);
-        const int blk = __builtin_amdgcn_readfirstlane(items[item].y);
-        DasArgs a = frames[fr].a;
-        a.out = static_cast<float *>(out_ptrs[fr]);
-        das_block<MODE, ET, IP, ZP>(a, frames[fr].c, blk, 0, smem);
-        __syncthreads();
+    const int home = blockIdx.x % N_XCD_QUEUES;
+    for (int r = 0; r < N_XCD_QUEUES; ++r) {
+        const int q = (home + r) % N_XCD_QUEUES;
+        const int beg = queues.off[q], n = queues.off[q + 1] - beg;
+        for (;;) {
+            if (threadIdx.x == 0) s_item = atomicAdd(counters + q, 1);
+            __syncthreads();
+            // the item is workgroup-uniform: keep it (and all it indexes) scalar
+            const int item = __builtin_amdgcn_readfirstlane(s_item);
+            __syncthreads();
+            if (item >= n) break;
+            const int fr = __builtin_amdgcn_readfirstlane(items[beg + item].x);
+            const int blk = __builtin_amdgcn_readfirstlane(items[beg + item].y);
+            DasArgs a = frames[fr].a;
+            a.out = static_cast<float *>(out_ptrs[fr]);
+            das_block<MODE, ET, IP, ZP>(a, frames[fr].c, blk, 0, smem);
+            __syncthreads();
+        }
     }
 }
 
@@ -72,7 +63,7 @@ static hipError_t launch_persistent4(const PersistentLaunch &p, hipStream_t s)
     hipError_t e = allow_lds(fn, p.shm);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((das_persistent_kernel<MODE, ET, IP, ZP>), dim3(p.grid), dim3(p.threads),
-                       p.shm, s, p.frames, p.items, p.n_items, p.counter, p.out_ptrs);
+                       p.shm, s, p.frames, p.items, p.queues, p.counters, p.out_ptrs);
     return hipGetLastError();
 }
 
@@ -139,7 +130,7 @@ template <int MODE, int ET, int IP, int ZP>
 static hipError_t launch_lds4(const DasArgs &a, const LdsCfg &c, size_t shm, hipStream_t s)
 {
     const int nthr = 64 * c.bwx * c.bwy * c.bwz;
-    dim3 grid(c.blocks_x * c.blocks_y * 8 * ((c.blocks_z + 7) / 8), a.groups);   // xcd_slab_box
+    dim3 grid(xcd_slab_grid(c), a.groups);
     hipError_t e = allow_lds(reinterpret_cast<const void *>(&das_lds_kernel<MODE, ET, IP, ZP>), shm);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((das_lds_kernel<MODE, ET, IP, ZP>), grid, dim3(nthr), shm, s, a, c);

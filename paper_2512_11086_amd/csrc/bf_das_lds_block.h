@@ -128,62 +128,33 @@ __device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, 
     int ix, iy, iz;
     lane_point(a, c, bx, by, bz, wave, lane, p, &ix, &iy, &iz);
     L.valid = ix < a.g.nx && iy < a.g.ny && iz >= 0 && iz < a.g.nz;
-    if constexpr (MODE == MODE_HERCULES) {
-        // HERCULES reads its windows without clamping the index, so every lane
-        // takes the geometry of the nearest grid point of its box: its delay
-        // then lies within the box's bounds (see hercules_term)
-        ix = min(ix, a.g.nx - 1);
-        iy = min(iy, a.g.ny - 1);
-        iz = min(max(iz, 0), a.g.nz - 1);
-    }
+    // Real-data terms read their windows without clamping the index, so every
+    // lane takes the geometry of the nearest grid point of its box: its delay
+    // then lies within the box's bounds (see hercules_term, sep_term)
+    ix = min(ix, a.g.nx - 1);
+    iy = min(iy, a.g.ny - 1);
+    iz = min(max(iz, 0), a.g.nz - 1);
     const double px = a.g.org[0] + ix * a.g.ax[0] + iy * a.g.ay[0] + iz * a.g.az[0];
     const double py = a.g.org[1] + ix * a.g.ax[1] + iy * a.g.ay[1] + iz * a.g.az[1];
     const double pz = a.g.org[2] + ix * a.g.ax[2] + iy * a.g.ay[2] + iz * a.g.az[2];
     L.x = (float)px;
     L.y = (float)py;
-    if constexpr (MODE == MODE_HERCULES) {
-        // a point on or behind the array plane (its output is 0) is evaluated
-        // just in front of it, inside the box; it and any lane outside the
-        // grid stay out of the wavefront's aperture mask (thr < 0)
-        const double pze = fmax(pz, 1e-7);
-        const double B = (tx_path(a, px, py, pze) + pze) * a.k - a.t0fs;
-        const double fl = floor(B);
-        L.nB = (int)fl;
-        L.fB = (float)(B - fl);
-        L.z = (float)pze;
-        L.z2 = L.z * L.z;
-        L.zk = (float)(pze / a.k);
-        L.zk2 = L.zk * L.zk;
-        L.thr = (L.valid && pz > 0.0) ? (a.f2 > 0.f ? L.z2 * 0.25f / a.f2 : __builtin_inff()) : -1.f;
-        L.wsc = a.f2 > 0.f ? a.f2 / L.z2 : 0.f;
-        L.wtab = L.wsc * (4.f * HANN_N);
-        L.ph0 = phase_origin(a, L.nB);
-    } else if (L.valid && pz > 0.0) {
-        const double B = (tx_path(a, px, py, pz) + pz) * a.k - a.t0fs;
-        const double fl = floor(B);
-        L.nB = (int)fl;
-        L.fB = (float)(B - fl);
-        L.z = (float)pz;
-        L.z2 = L.z * L.z;
-        L.zk = (float)(pz / a.k);
-        L.zk2 = L.zk * L.zk;
-        L.thr = a.f2 > 0.f ? L.z2 * 0.25f / a.f2 : __builtin_inff();
-        L.wsc = a.f2 > 0.f ? a.f2 / L.z2 : 0.f;
-        L.wtab = L.wsc * (4.f * HANN_N);
-        L.ph0 = phase_origin(a, L.nB);
-    } else {
-        // benign: depth 1 m (finite delays, clamped window index), outside
-        // every aperture test (thr < 0, FORCES weight forced to 0)
-        L.nB = 0;
-        L.fB = 0.f;
-        L.z = L.z2 = 1.f;
-        L.zk = (float)(1.0 / a.k);
-        L.zk2 = L.zk * L.zk;
-        L.thr = -1.f;
-        L.wsc = __builtin_inff();
-        L.wtab = 1.f;
-        L.ph0 = 0.f;
-    }
+    // a point on or behind the array plane (its output is 0) is evaluated
+    // just in front of it, inside the box; it and any lane outside the grid
+    // stay out of every aperture test (thr < 0: weight 0, no wavefront mask)
+    const double pze = fmax(pz, 1e-7);
+    const double B = (tx_path(a, px, py, pze) + pze) * a.k - a.t0fs;
+    const double fl = floor(B);
+    L.nB = (int)fl;
+    L.fB = (float)(B - fl);
+    L.z = (float)pze;
+    L.z2 = L.z * L.z;
+    L.zk = (float)(pze / a.k);
+    L.zk2 = L.zk * L.zk;
+    L.thr = (L.valid && pz > 0.0) ? (a.f2 > 0.f ? L.z2 * 0.25f / a.f2 : __builtin_inff()) : -1.f;
+    L.wsc = a.f2 > 0.f ? a.f2 / L.z2 : 0.f;
+    L.wtab = L.wsc * (4.f * HANN_N);
+    L.ph0 = phase_origin(a, L.nB);
     return L;
 }
 
@@ -607,23 +578,6 @@ __device__ inline float eval_quad(const float4 q, float t)
     return fmaf(t, fmaf(t, fmaf(t, q.w, q.z), q.y), q.x);
 }
 
-template <int IP>
-__device__ inline float read_quad(const float4 *win, int li, int lmax, float t)
-{
-    li = clamp0_i32(li, lmax - 1);
-    return eval_quad<IP>(win[li], t);
-}
-
-// IQ window: interval li holds the real quad at 2 li and the imaginary at 2 li + 1
-template <int IP>
-__device__ inline float2 read_quad_cx(const float4 *win, int li, int lmax, float t)
-{
-    li = clamp0_i32(li, lmax - 1);
-    return make_float2(eval_quad<IP>(win[2 * li], t), eval_quad<IP>(win[2 * li + 1], t));
-}
-
-// Beamforms workgroup box `blk` (channel group `grp`) of one frame.  Every
-// thread of the workgroup must call it (it contains barriers).
 // floor to int in one instruction
 __device__ inline int cvt_flr(float x)
 {
@@ -749,6 +703,8 @@ __device__ inline void hercules_term(const LaneL (&L)[ZP], const float4 *win, in
     }
 }
 
+// Beamforms workgroup box `blk` (channel group `grp`) of one frame.  Every
+// thread of the workgroup must call it (it contains barriers).
 // ADJ: the adjoint of the image instead of the image, for G = dL/d(image).
 // Bit 1, dL/dc: the staged quads hold the read's derivative, each point
 // accumulates sum w v'(s) and sum w v'(s) s, and the workgroup writes its
@@ -798,7 +754,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     if constexpr (MODE == 1)
         for (int t = tid; t < HANN_TAB_PAD; t += nthr)
             s_hann[t] = t <= HANN_N ? a.hann_tab[t] : make_float2(0.f, 0.f);
-    if constexpr (MODE == MODE_HERCULES && STAGE)   // finite data wherever an unclamped read can land
+    if constexpr (STAGE)   // finite data wherever an unclamped read can land
         for (int t = tid; t < buf_quads + c.guard * QS; t += nthr) q1[t] = make_float4(0.f, 0.f, 0.f, 0.f);
     if constexpr (GE)
         for (int t = tid; t < 2 * c.nb * lw; t += nthr) accw0[t] = 0ull;
@@ -982,10 +938,16 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                     if (!row_on[q]) continue;
                     const int e = q * nbi + ii;
                     const float sq = Rj[q] + T;
-                    const int li = (int)floorf(sq) + L.nB + nw[q];
+                    // no clamp: li lies in [1, lmax + guard) for every lane (its
+                    // geometry is inside the box); lanes outside the row's
+                    // aperture (weight 0) may read into the next window or the
+                    // zeroed guard
+                    const int li = add3_vvv(cvt_flr(sq), L.nB, nw[q]);
                     if constexpr (ET == ET_CF32) {
-                        const float2 v = read_quad_cx<IP>(quads + e * c.lmax * QS, li, c.lmax,
-                                                          __builtin_amdgcn_fractf(sq));
+                        const float4 *win = quads + e * c.lmax * QS;
+                        const float t = __builtin_amdgcn_fractf(sq);
+                        const float2 v = make_float2(eval_quad<IP>(win[2 * li], t),
+                                                     eval_quad<IP>(win[2 * li + 1], t));
                         rotate_acc(v, aj[q], fmaf(rot, sq, L.ph0), acc[0]);
                     } else if constexpr (ADJ != 0) {
                         const int k = clamp0_i32(li, c.lmax - 1);
@@ -997,8 +959,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                         }
                         if constexpr (GE) scatter_taps<IP>(accw + e * lw, k, Gv[0] * aj[q], t);
                     } else {
-                        const float v = read_quad<IP>(quads + e * c.lmax, li, c.lmax,
-                                                      __builtin_amdgcn_fractf(sq));
+                        const float v = eval_quad<IP>(quads[e * c.lmax + li], __builtin_amdgcn_fractf(sq));
                         acc[0].x = fmaf(aj[q], v, acc[0].x);
                     }
                 }
@@ -1065,6 +1026,26 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                 dst[idx] = v.x;
         }
     }
+}
+
+// Box order of the single-frame kernels (DAS and its adjoints).  Workgroups are dispatched in index
+// order, round-robin over the 8 XCDs (index b runs on XCD b % 8), and each
+// XCD has its own L2.  XCD x takes the depth slabs x, x + 8, x + 16, ... (a
+// slab = every lateral box at one box depth), deepest first: the boxes
+// resident on an XCD at a time lie side by side at one depth and stage
+// nearly the same trace windows, which then hit in that XCD's L2, and the
+// costliest boxes (the widest apertures) start first.  The grid holds
+// xcd_slab_grid(c) = nlat * 8 * ceil(blocks_z / 8) workgroups; those past
+// the last slab return.
+// Any order is correct (each box is visited once); this one measured 5 %
+// faster than depth-fastest order on the 128 x 128 x 256 HERCULES volume.
+__device__ inline int xcd_slab_box(const LdsCfg &c, int b)
+{
+    const int nlat = c.blocks_x * c.blocks_y;
+    const int slot = b >> 3;
+    const int zrank = (slot / nlat) * 8 + (b & 7);     // 0 = deepest slab
+    if (zrank >= c.blocks_z) return -1;
+    return (c.blocks_z - 1 - zrank) + c.blocks_z * (slot % nlat);
 }
 
 // Two points per lane and the row-column modes: registers capped for 6

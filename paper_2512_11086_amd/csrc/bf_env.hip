@@ -6,8 +6,8 @@
 // column is |x_a| with x_a its analytic signal along depth:
 //     X = DFT_N(x),  X_a[k] = h[k] X[k]  (h = 1 at DC and Nyquist, 2 for
 //     positive, 0 for negative frequencies),  x_a = IDFT_N(X_a).
-// Power-of-two N from 64 to 1024: one wavefront per column, FFT held in
-// registers (four-step split N = 64 M: a 64-point FFT across the lanes by
+// Power-of-two N from 64 to 1024: one wavefront per two columns (packed as
+// one complex sequence, see env_fft_reg_kernel), FFT held in registers (four-step split N = 64 M: a 64-point FFT across the lanes by
 // xor-partner exchanges, a twiddle, an M-point FFT inside each lane, then the
 // mirror image for the inverse); no LDS passes and no barriers.  Other
 // power-of-two N: one workgroup per column, radix-2 FFT in LDS (forward
@@ -53,15 +53,19 @@ struct EnvArgs {
     int N, log2n;
     int compress;
     float ref, param;
+    float inv_ref;           // 1 / ref (ref > 0)
 };
 
-__device__ inline float compress_value(float env, int mode, float ref, float param)
+// Compression with the hardware base-2 logarithm and exponential (about 1 ulp
+// each): 20 log10(x) = (20 log10 2) log2(x) and x^p = 2^(p log2 x); x = 0
+// gives log2 = -inf, i.e. -param dB and 0 (param > 0).  inv_ref = 1 / ref.
+__device__ inline float compress_value(float env, int mode, float inv_ref, float param)
 {
-    if (mode == BF_COMPRESS_LOG) {
-        const float db = 20.f * log10f(env / ref);      // -inf for env = 0
-        return fmaxf(db, -param);
-    }
-    if (mode == BF_COMPRESS_POWER) return powf(fminf(env / ref, 1.f), param);
+    const float x = env * inv_ref;
+    if (mode == BF_COMPRESS_LOG)
+        return fmaxf(6.0205999132796239f * __builtin_amdgcn_logf(x), -param);
+    if (mode == BF_COMPRESS_POWER)
+        return __builtin_amdgcn_exp2f(param * __builtin_amdgcn_logf(fminf(x, 1.f)));
     return env;
 }
 
@@ -70,7 +74,7 @@ __device__ inline float compress_value(float env, int mode, float ref, float par
 __device__ inline void store_env(const EnvArgs &a, long idx, float env, float &local_max)
 {
     if (a.compress != BF_COMPRESS_NONE && a.ref > 0.f) {
-        a.out[idx] = compress_value(env, a.compress, a.ref, a.param);
+        a.out[idx] = compress_value(env, a.compress, a.inv_ref, a.param);
     } else {
         a.out[idx] = env;
         local_max = fmaxf(local_max, env);
@@ -185,14 +189,32 @@ __global__ __launch_bounds__(256) void env_direct_kernel(EnvArgs a)
 // Register FFT (64 <= N = 64 M <= 1024): sample n = M l + r lives in lane l,
 // register r.  X[k1 + 64 k2] = sum_r W_M^{r k2} W_N^{r k1} [sum_l x[M l + r] W_64^{l k1}].
 // ---------------------------------------------------------------------------
-__device__ inline float2 shfl_xor2(float2 v, int m)
+// Value of lane l ^ m (m a power of two, constant after unrolling).  Lane
+// distances 1 and 2 move through DPP quad permutes and 32 through the gfx950
+// half-swap (permlane32_swap: lanes 32-63 of the first operand trade places
+// with lanes 0-31 of the second), all in the VALU; 4, 8 and 16 go through the
+// LDS crossbar (ds_bpermute), so both pipes share the exchanges.
+__device__ inline float xor_lane(float x, int m, int lane)
 {
-    return make_float2(__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64));
+    const int xi = __float_as_int(x);
+    if (m == 1) return __int_as_float(__builtin_amdgcn_update_dpp(0, xi, 0xB1, 0xF, 0xF, false));
+    if (m == 2) return __int_as_float(__builtin_amdgcn_update_dpp(0, xi, 0x4E, 0xF, 0xF, false));
+    if (m == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(xi, xi, false, false);
+        return __int_as_float(lane < 32 ? r[1] : r[0]);
+    }
+    return __shfl_xor(x, m, 64);
+}
+
+__device__ inline float2 shfl_xor2(float2 v, int m, int lane)
+{
+    return make_float2(xor_lane(v.x, m, lane), xor_lane(v.y, m, lane));
 }
 
 // 64-point DIF across lanes for each register (sign -1: forward); lane l ends
 // with the bin bitrev6(l).  Pairs (l, l ^ d): lower l gets v + p, upper gets
-// (p - v) W_{2d}^{l mod d}.  tw_l[s] = W_{2d}^{l mod d} for every lane.
+// (p - v) W_{2d}^{l mod d}, both as (sigma v + p) w with sigma = +-1 and w = 1
+// on the lower lane (no selects).  tw_l[s] = W_{2d}^{l mod d} for every lane.
 template <int M>
 __device__ inline void lane_dif(float2 (&v)[M], const float2 *tw_l, int lane)
 {
@@ -200,19 +222,20 @@ __device__ inline void lane_dif(float2 (&v)[M], const float2 *tw_l, int lane)
     for (int s = 0; s < 6; ++s) {
         const int d = 32 >> s;
         const bool up = (lane & d) != 0;
+        const float sg = up ? -1.f : 1.f;
         const float2 w = up ? tw_l[s] : make_float2(1.f, 0.f);
 #pragma unroll
         for (int r = 0; r < M; ++r) {
-            const float2 p = shfl_xor2(v[r], d);
-            const float2 t = up ? make_float2(p.x - v[r].x, p.y - v[r].y)
-                                : make_float2(v[r].x + p.x, v[r].y + p.y);
-            v[r] = cmul(t, w);
+            const float2 p = shfl_xor2(v[r], d, lane);
+            v[r] = cmul(make_float2(fmaf(sg, v[r].x, p.x), fmaf(sg, v[r].y, p.y)), w);
         }
     }
 }
 
 // 64-point inverse DIT across lanes from bit-reversed bins back to natural
 // order (sign +1): lower l gets v + W p, upper gets p - W v, W = conj(W_{2d}^{l mod d}).
+// The upper lane multiplies its own value by W before the exchange, so both
+// results are sigma u + p with u the lane's (weighted) value, sigma = +-1.
 template <int M>
 __device__ inline void lane_dit_inv(float2 (&v)[M], const float2 *tw_l, int lane)
 {
@@ -220,14 +243,13 @@ __device__ inline void lane_dit_inv(float2 (&v)[M], const float2 *tw_l, int lane
     for (int s = 5; s >= 0; --s) {
         const int d = 32 >> s;
         const bool up = (lane & d) != 0;
-        const float2 w = make_float2(tw_l[s].x, -tw_l[s].y);
+        const float sg = up ? -1.f : 1.f;
+        const float2 w = up ? make_float2(tw_l[s].x, -tw_l[s].y) : make_float2(1.f, 0.f);
 #pragma unroll
         for (int r = 0; r < M; ++r) {
-            const float2 p = shfl_xor2(v[r], d);
-            const float2 own = cmul(up ? v[r] : p, w);      // W times the upper value
-            const float2 base = up ? p : v[r];              // the lower value
-            v[r] = up ? make_float2(base.x - own.x, base.y - own.y)
-                      : make_float2(base.x + own.x, base.y + own.y);
+            const float2 u = cmul(v[r], w);
+            const float2 p = shfl_xor2(u, d, lane);
+            v[r] = make_float2(fmaf(sg, u.x, p.x), fmaf(sg, u.y, p.y));
         }
     }
 }
@@ -268,19 +290,30 @@ __device__ inline void reg_fft(float2 (&v)[M], const float2 *wm, float sign)
     }
 }
 
-// 4 columns per 256-thread workgroup, one per wavefront.
+// Two real columns per wavefront, 8 per 256-thread workgroup.  The Hilbert
+// transform H is linear with a real kernel, so for z = x1 + j x2 the inverse
+// DFT of -j sgn(k) DFT(z) (sgn = 0 at DC and Nyquist, +1 for positive and -1
+// for negative frequencies) is H{x1} + j H{x2}, and each envelope is
+// |x_a| = sqrt(x^2 + H{x}^2): the analytic signal of both columns for one
+// complex FFT pair (half the work of one pair per column).
 template <int M>
 __global__ __launch_bounds__(256) void env_fft_reg_kernel(EnvArgs a)
 {
     constexpr int N = 64 * M;
     const int lane = threadIdx.x & 63;
-    const long col = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const long col = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 2;
     float local_max = 0.f;
     if (col < a.n_cols) {
+        const bool has2 = col + 1 < a.n_cols;
         const float *x = a.img + col * N + M * lane;
+        float x1[M], x2[M];
         float2 v[M];
 #pragma unroll
-        for (int r = 0; r < M; ++r) v[r] = make_float2(x[r], 0.f);
+        for (int r = 0; r < M; ++r) {
+            x1[r] = x[r];
+            x2[r] = has2 ? x[N + r] : 0.f;
+            v[r] = make_float2(x1[r], x2[r]);
+        }
         float2 twl[6];
 #pragma unroll
         for (int s = 0; s < 6; ++s) twl[s] = a.tw_lane[s * 64 + lane];
@@ -290,13 +323,13 @@ __global__ __launch_bounds__(256) void env_fft_reg_kernel(EnvArgs a)
 #pragma unroll
         for (int r = 0; r < M; ++r) v[r] = cmul(v[r], tm[r]);
         reg_fft<M>(v, a.wm, -1.f);
-        // analytic-signal weights on X[k1 + 64 k2] (register k2)
+        // -j sgn(k) on Z[k1 + 64 k2] (register k2): -j s (a + j b) = s (b - j a)
         const int k1 = (int)(__brev((unsigned)lane) >> 26);
 #pragma unroll
         for (int k2 = 0; k2 < M; ++k2) {
             const int k = k1 + 64 * k2;
-            const float w = (k == 0 || 2 * k == N) ? 1.f : (2 * k < N ? 2.f : 0.f);
-            v[k2] = make_float2(v[k2].x * w, v[k2].y * w);
+            const float sg = (k == 0 || 2 * k == N) ? 0.f : (2 * k < N ? 1.f : -1.f);
+            v[k2] = make_float2(sg * v[k2].y, -sg * v[k2].x);
         }
         reg_fft<M>(v, a.wm, 1.f);
 #pragma unroll
@@ -304,9 +337,14 @@ __global__ __launch_bounds__(256) void env_fft_reg_kernel(EnvArgs a)
         lane_dit_inv<M>(v, twl, lane);
         const float inv_n = 1.f / (float)N;
 #pragma unroll
-        for (int r = 0; r < M; ++r)
+        for (int r = 0; r < M; ++r) {
+            const float h1 = v[r].x * inv_n, h2 = v[r].y * inv_n;
             store_env(a, col * N + M * lane + r,
-                      sqrtf(fmaf(v[r].x, v[r].x, v[r].y * v[r].y)) * inv_n, local_max);
+                      __builtin_amdgcn_sqrtf(fmaf(x1[r], x1[r], h1 * h1)), local_max);
+            if (has2)
+                store_env(a, (col + 1) * N + M * lane + r,
+                          __builtin_amdgcn_sqrtf(fmaf(x2[r], x2[r], h2 * h2)), local_max);
+        }
     }
     publish_max(a, local_max);
 }
@@ -343,11 +381,12 @@ __global__ __launch_bounds__(256) void env_compress_kernel(EnvArgs a)
 {
     const long total = a.n_cols * a.N;
     const float ref = *a.img_max;
+    const float inv_ref = ref > 0.f ? 1.f / ref : 0.f;
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
         const float env = a.out[i];
         float y;
         if (ref > 0.f) {
-            y = compress_value(env, a.compress, ref, a.param);
+            y = compress_value(env, a.compress, inv_ref, a.param);
         } else {   // all-zero image
             y = a.compress == BF_COMPRESS_LOG ? -a.param : 0.f;
         }
@@ -416,7 +455,7 @@ int bf_env_create(int64_t n_cols, int32_t n, int32_t iq, bf_env *out)
     // workgroups of the envelope pass: one per column, four columns per
     // workgroup (register FFT), or the grid-stride launch of the IQ path
     e->n_parts = iq ? std::min<long>((n_cols * n + 255) / 256, 8192)
-                    : e->reg_m ? (n_cols + 3) / 4 : n_cols;
+                    : e->reg_m ? (n_cols + 7) / 8 : n_cols;
     hipError_t err = hipMalloc(&e->d_part, (e->n_parts + 1) * sizeof(float));
     if (err == hipSuccess && !iq) {
         if ((n & (n - 1)) == 0 && n >= 2) {
@@ -528,6 +567,8 @@ int bf_envelope(bf_env e, const float *img, float *out, int32_t compress, double
     a.compress = compress;
     a.ref = (float)ref;
     a.param = (float)param;
+    // (a ref below 2^-128 keeps a finite reciprocal: env = 0 still maps to 0)
+    a.inv_ref = ref > 0.0 ? (float)std::min(1.0 / ref, 3.4028234663852886e38) : 0.f;
     hipStream_t s = (hipStream_t)stream;
     const bool two_pass = compress != BF_COMPRESS_NONE && ref <= 0.0;
     const long total = e->n_cols * e->N;
@@ -535,7 +576,7 @@ int bf_envelope(bf_env e, const float *img, float *out, int32_t compress, double
     if (e->iq) {
         hipLaunchKernelGGL(env_iq_kernel, dim3(eblocks), dim3(256), 0, s, a);
     } else if (e->reg_m) {
-        const dim3 g((unsigned)((e->n_cols + 3) / 4)), b(256);
+        const dim3 g((unsigned)((e->n_cols + 7) / 8)), b(256);
         switch (e->reg_m) {
             case 1: hipLaunchKernelGGL(env_fft_reg_kernel<1>, g, b, 0, s, a); break;
             case 2: hipLaunchKernelGGL(env_fft_reg_kernel<2>, g, b, 0, s, a); break;

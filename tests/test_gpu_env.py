@@ -46,6 +46,20 @@ def test_envelope_fft_path_matches_oracle(torch_mod, N):
     _check_env(got, oracle.envelope(img.astype(np.float64)))
 
 
+def test_envelope_pairs_of_unequal_columns(torch_mod):
+    # power-of-two depths up to 1024 pack two columns into one complex FFT; a
+    # weak column next to a 1000x stronger one keeps the image-level bound
+    # and stays within 1e-5 of its partner's maximum
+    rng = np.random.default_rng(7)
+    img = rng.normal(size=(7, 256)).astype(np.float32)
+    img[0::2] *= 1000.0
+    got = _env_gpu(torch_mod, img)
+    ref = oracle.envelope(img.astype(np.float64))
+    _check_env(got, ref)
+    for c in range(1, 7, 2):
+        assert np.abs(got[c] - ref[c]).max() <= 1e-5 * np.abs(ref[c - 1]).max(), c
+
+
 @pytest.mark.parametrize("N", [1, 3, 37, 100, 255, 1000])
 def test_envelope_direct_path_matches_oracle(torch_mod, N):
     img = np.random.default_rng(N).normal(size=(7, N)).astype(np.float32)

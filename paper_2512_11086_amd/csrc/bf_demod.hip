@@ -49,6 +49,8 @@ struct DemodArgs {
     int chunks;           // workgroups per trace
     int phase_len;        // LDS words per polyphase component (multiple of 4)
     int kind[16];         // per component: 0 complex taps, 1 real only, 2 imaginary only
+    int lg_d;             // log2(D) when D is a power of two and the trace rows are
+                          // 16-byte aligned (vector staging), else -1
 };
 
 enum { TAPS_COMPLEX = 0, TAPS_REAL = 1, TAPS_IMAG = 2 };
@@ -57,6 +59,15 @@ __device__ inline int16_t sat_i16(float v)
 {
     const float r = __builtin_rintf(v);                       // ties to even
     return (int16_t)(int)fminf(fmaxf(r, -32768.f), 32767.f);
+}
+
+// Two rounded, saturated values packed as (lo, hi) int16: round half to
+// even, clamp in FP32 (exact at the int16 limits), convert, pack.
+__device__ inline uint32_t sat_pk_i16(float lo, float hi)
+{
+    const int a = (int)__builtin_amdgcn_fmed3f(__builtin_rintf(lo), -32768.f, 32767.f);
+    const int b = (int)__builtin_amdgcn_fmed3f(__builtin_rintf(hi), -32768.f, 32767.f);
+    return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pk_i16(a, b));
 }
 
 // Taps of polyphase component ph (of D) of an N-tap filter, and that count
@@ -68,6 +79,36 @@ __host__ __device__ inline int phase_taps(int N, int D, int ph)
 __host__ __device__ inline int phase_taps4(int N, int D, int ph)
 {
     return (phase_taps(N, D, ph) + 3) & ~3;
+}
+
+// One polyphase component's taps for the thread's M = 4 outputs: words
+// wp[0 ..] of the component (the outputs' inputs shifted by one word each),
+// taps gp[0 .. nb4) (nb4 a multiple of 4, zero-padded).  Each 4-tap block
+// reads one aligned 16-byte LDS word group and two 16-byte tap pairs through
+// the scalar cache; KIND drops the products the component does not have.
+template <int KIND>
+__device__ inline void fir_phase(const float4 *wp, const float2 *__restrict__ gp, int nb4,
+                                 float (&ar)[DEMOD_M], float (&ai)[DEMOD_M])
+{
+    const float4 *__restrict__ g4 = reinterpret_cast<const float4 *>(gp);
+    float4 lo = wp[0];
+#pragma unroll 2
+    for (int b = 0; b < nb4; b += 4) {
+        const float4 hi = wp[b / 4 + 1];
+        const float w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+        const float4 g01 = g4[b / 2], g23 = g4[b / 2 + 1];
+        const float gr[4] = {g01.x, g01.z, g23.x, g23.z};
+        const float gi[4] = {g01.y, g01.w, g23.y, g23.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int m = 0; m < DEMOD_M; ++m) {
+                if constexpr (KIND != TAPS_IMAG) ar[m] = fmaf(gr[u], w[u + m], ar[m]);
+                if constexpr (KIND != TAPS_REAL) ai[m] = fmaf(gi[u], w[u + m], ai[m]);
+            }
+        }
+        lo = hi;
+    }
 }
 
 template <int OT, int T>
@@ -83,6 +124,40 @@ __global__ __launch_bounds__(T) void demod_kernel(DemodArgs a)
     // Word w of component ph holds input sample n0 + ph + D w, with
     // n0 = q0 D - (N_f - 1); samples outside the record read as 0.
     const int n0 = q0 * a.D - (a.n_taps - 1);
+    if (a.lg_d >= 0) {
+        // Vector form: thread c converts the 8 samples nb .. nb + 7
+        // (nb = n_al + 8 c, n_al = n0 rounded down to a multiple of 8) from one
+        // 16-byte load; sample n goes to component (n - n0) & (D - 1), word
+        // (n - n0) >> log2 D, if it lies in the staged span [n0, n0 + D len).
+        const int span = a.D * a.phase_len;
+        const int n_al = n0 & ~7;
+        const int nchunks = (n0 + span - n_al + 7) >> 3;
+        for (int c = t; c < nchunks; c += T) {
+            const int nb = n_al + 8 * c;
+            int vals[8];
+            if (nb >= 0 && nb + 8 <= a.S) {
+                const int4 raw = *reinterpret_cast<const int4 *>(x + nb);
+                const int w4[4] = {raw.x, raw.y, raw.z, raw.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    vals[2 * i] = (int16_t)(w4[i] & 0xFFFF);          // low half
+                    vals[2 * i + 1] = (int16_t)((uint32_t)w4[i] >> 16);  // high half
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    vals[i] = (nb + i >= 0 && nb + i < a.S) ? (int)x[nb + i] : 0;
+            }
+            // word address of sample rel: (rel mod D) len + rel / D (the 24-bit
+            // product runs at full rate)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int rel = nb + i - n0;
+                if ((unsigned)rel < (unsigned)span)
+                    xs[__umul24(rel & (a.D - 1), a.phase_len) + (rel >> a.lg_d)] = (float)vals[i];
+            }
+        }
+    } else
     // Loads are unconditional from a clamped index (then zeroed), four per
     // thread in flight before their conversions.
     for (int ph = 0; ph < a.D; ++ph) {
@@ -114,37 +189,11 @@ __global__ __launch_bounds__(T) void demod_kernel(DemodArgs a)
     for (int ph = 0; ph < a.D; ++ph) {
         const int nb4 = phase_taps4(a.n_taps, a.D, ph);
         const float4 *wp = xs4 + (ph * a.phase_len) / 4 + t;   // words tM .. (M = 4)
-        const int kind = a.kind[ph];                           // uniform
-        float4 lo = wp[0];
-        for (int b = 0; b < nb4; b += 4) {
-            const float4 hi = wp[b / 4 + 1];
-            const float w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-            if (kind == TAPS_REAL) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const float g = gp[b + u].x;
-#pragma unroll
-                    for (int m = 0; m < DEMOD_M; ++m) ar[m] = fmaf(g, w[u + m], ar[m]);
-                }
-            } else if (kind == TAPS_IMAG) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const float g = gp[b + u].y;
-#pragma unroll
-                    for (int m = 0; m < DEMOD_M; ++m) ai[m] = fmaf(g, w[u + m], ai[m]);
-                }
-            } else {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const float2 gk = gp[b + u];
-#pragma unroll
-                    for (int m = 0; m < DEMOD_M; ++m) {
-                        ar[m] = fmaf(gk.x, w[u + m], ar[m]);
-                        ai[m] = fmaf(gk.y, w[u + m], ai[m]);
-                    }
-                }
-            }
-            lo = hi;
+        // the tap kind is uniform per component: one straight loop each
+        switch (a.kind[ph]) {
+            case TAPS_REAL: fir_phase<TAPS_REAL>(wp, gp, nb4, ar, ai); break;
+            case TAPS_IMAG: fir_phase<TAPS_IMAG>(wp, gp, nb4, ar, ai); break;
+            default: fir_phase<TAPS_COMPLEX>(wp, gp, nb4, ar, ai); break;
         }
         gp += nb4;
     }
@@ -163,10 +212,10 @@ __global__ __launch_bounds__(T) void demod_kernel(DemodArgs a)
         }
         if constexpr (OT == BF_IQ_I16) {
             uint4 v;
-            v.x = (uint16_t)sat_i16(yr[0]) | ((uint32_t)(uint16_t)sat_i16(yi[0]) << 16);
-            v.y = (uint16_t)sat_i16(yr[1]) | ((uint32_t)(uint16_t)sat_i16(yi[1]) << 16);
-            v.z = (uint16_t)sat_i16(yr[2]) | ((uint32_t)(uint16_t)sat_i16(yi[2]) << 16);
-            v.w = (uint16_t)sat_i16(yr[3]) | ((uint32_t)(uint16_t)sat_i16(yi[3]) << 16);
+            v.x = sat_pk_i16(yr[0], yi[0]);
+            v.y = sat_pk_i16(yr[1], yi[1]);
+            v.z = sat_pk_i16(yr[2], yi[2]);
+            v.w = sat_pk_i16(yr[3], yi[3]);
             uint32_t *dst = static_cast<uint32_t *>(a.y) + o;
             if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
                 *reinterpret_cast<uint4 *>(dst) = v;
@@ -361,6 +410,11 @@ int bf_demodulate(bf_demod d, const int16_t *rf, void *iq, void *stream)
     a.chunks = (d->n_out + T * DEMOD_M - 1) / (T * DEMOD_M);
     for (int ph = 0; ph < 16; ++ph) a.kind[ph] = d->kind[ph];
     a.phase_len = T * DEMOD_M + nb4max + 4;
+    // vector staging: D a power of two, every trace row 16-byte aligned
+    a.lg_d = -1;
+    if ((a.D & (a.D - 1)) == 0 && a.S % 8 == 0 && (reinterpret_cast<uintptr_t>(rf) & 15) == 0)
+        for (int l = 0; l < 5; ++l)
+            if ((1 << l) == a.D) a.lg_d = l;
     const size_t shm = (size_t)a.D * a.phase_len * sizeof(float);
     const long blocks = (long)a.n_traces * a.chunks;
     if (blocks >= (1L << 31)) return fail(BF_ERR_TOO_LARGE, "too many workgroups");

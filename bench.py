@@ -63,23 +63,40 @@ def active_terms(desc, dev) -> int:
     return total
 
 
-def algorithmic_flops(desc, n_act: int) -> float:
-    """FP32 flops (FMA = 2) the DAS definition needs for n_act active terms.
+def algorithmic_flops(desc, n_act: int, iq: bool = False, adjoint_c: bool = False) -> float:
+    """FP32 flops (FMA = 2) of one DAS launch (or its dL/dc adjoint) with
+    n_act active terms (apodization > 0), counted for the algorithm with
+    per-sample interpolation coefficients: the cubic read's coefficients of a
+    trace's sample interval are formed once (10 flops; 20 for IQ's real and
+    imaginary parts; the adjoint forms the derivative's 3 coefficients, 10)
+    and every term evaluates its polynomial by Horner's rule (6; the
+    derivative's quadratic 4).
 
-    HERCULES (one radial receive path per term, plane or diverging transmit):
-    45 per active term (delay 13, apodization 14, cubic read 16, accumulate 2).
-    TPW and VLS separate into a transmit path per (point, transmit) and a
-    receive path with its apodization per (point, row): per active term the
-    two are added and read (add, floor, fract 3, cubic read 16, weighted
-    accumulate 2 = 21); per active (point, row) pair the receive path and
-    weight (13 + 14 = 27); per (point, transmit) the transmit path (TPW
-    x sin + z (cos - 1): 6; VLS distance to the line with its sign: 13)."""
-    if desc["mode"] not in ("tpw", "vls"):
-        return 45.0 * n_act
+    Per active term: HERCULES (one receive path per term) delay 13 (dx,
+    rho^2, d^2, sqrt, d+z, rcp, mul, fma, floor, fract) + apodization 14 (u^2
+    and a degree-6 polynomial); FORCES, TPW and VLS separate the path into a
+    transmit part per (point, transmit) (FORCES distance to the column 8,
+    TPW x sin + z (cos - 1) 6, VLS signed distance to the line 13) and a
+    receive part with its weight per active (point, row) (13 + 14 = 27), and
+    a term adds the two and splits the sum (3).  Then the read (Horner 6) and
+    the accumulation: real 2; IQ two reads (12) + phase 2 + sine and cosine 2
+    + weight x rotation 2 + complex multiply-add 8; dL/dc the derivative (4)
+    + the sums of w v' and w v' s (4)."""
+    mode = desc["mode"]
+    traces = desc["n_tx"] * desc["n_ch"]
+    coef = 10.0 * traces * desc["n_samples"] * (2 if iq else 1)
+    if adjoint_c:
+        per_term = 4 + 4
+    elif iq:
+        per_term = 12 + 2 + 2 + 2 + 8
+    else:
+        per_term = 6 + 2
+    if mode == "hercules":
+        return n_act * (13 + 14 + per_term) + coef
     n_tx = desc["n_tx"]
     n_pts = int(np.prod(desc["dims"]))
-    f_tx = 6 if desc["mode"] == "tpw" else 13
-    return n_act * (21.0 + 27.0 / n_tx) + f_tx * n_pts * n_tx
+    f_tx = {"forces": 8, "tpw": 6, "vls": 13}[mode]
+    return n_act * (3 + per_term + 27.0 / n_tx) + f_tx * n_pts * n_tx + coef
 
 
 def cpu_baseline(desc, H, rf, budget_s: float):
@@ -237,7 +254,20 @@ def iq_pipeline(torch, bfm, synth, desc, H, rf_d, n_act, reps: int):
         ev[k][3].record(stream)
     torch.cuda.synchronize()
     t = np.array([[ev[k][i].elapsed_time(ev[k][i + 1]) for i in range(3)] for k in range(reps)])
-    dem_ms, dec_ms, das_ms = (float(v) for v in t.mean(axis=0))
+    _, _, das_ms = (float(v) for v in t.mean(axis=0))
+    # the short kernels: 10 back-to-back launches each (single launches
+    # between 40 ms DAS launches carry the event gaps)
+    ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev2[0].record(stream)
+    for _ in range(10):
+        dm(rf_d, out=iq)
+    ev2[1].record(stream)
+    for _ in range(10):
+        plan.decode(iq, out=e)
+    ev2[2].record(stream)
+    torch.cuda.synchronize()
+    dem_ms = ev2[0].elapsed_time(ev2[1]) / 10
+    dec_ms = ev2[1].elapsed_time(ev2[2]) / 10
     step = dem_ms + dec_ms + das_ms
     n_out = dm.n_out
     # demodulation: per output 2 flops per non-zero real or imaginary part of
@@ -253,9 +283,7 @@ def iq_pipeline(torch, bfm, synth, desc, H, rf_d, n_act, reps: int):
     dem_flops = n_tr * n_out * (2 * parts + 6)
     dem_bytes = n_tr * (2 * desc["n_samples"] + 4 * n_out)
     dem_tf = dem_flops / (dem_ms * 1e-3) / 1e12
-    # IQ term: delay 13, apodization 14, two cubic reads 32, phase 2, sin+cos
-    # 2, weight x rotation 2, complex multiply-accumulate 8 = 73 flops
-    das_tf = n_act * 73 / (das_ms * 1e-3) / 1e12
+    das_tf = algorithmic_flops(dq, n_act, iq=True) / (das_ms * 1e-3) / 1e12
     nominal = int(np.prod(dq["dims"])) * dq["n_tx"] * dq["n_ch"]
     return {
         "workload": "same RF -> demodulate (36-tap low-pass, D = 2, fd = 7.5 MHz) -> "
@@ -309,9 +337,8 @@ def autofocus_stage(torch, bfm, synth, reps: int = 5):
     image gradient, and the adjoint for dL/dc alone (the autofocus gradient);
     also timed: the adjoint with the RF gradient (64 x 64 x 2048, LDS windows
     added to it with FP32 atomics), with and without dL/dc.
-    Adjoint roofline: per active term the delay (13) and apodization (14),
-    the Hermite derivative read (14) and the weighted accumulation of
-    v'(s) ds/dc (4) = 45 flops."""
+    Adjoint roofline: algorithmic_flops(..., adjoint_c=True) (the separable
+    FORCES path, derivative coefficients once per trace sample interval)."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     desc, H, rfs, info = synth.make_inputs(3)
@@ -352,7 +379,7 @@ def autofocus_stage(torch, bfm, synth, reps: int = 5):
     adj_ec_ms = ev[3].elapsed_time(ev[4]) / (reps * nf)
     adj_e_ms = ev[4].elapsed_time(ev[5]) / (reps * nf)
     n_act = active_terms(desc, dev)
-    tf = n_act * 45 / (adj_ms * 1e-3) / 1e12
+    tf = algorithmic_flops(desc, n_act, adjoint_c=True) / (adj_ms * 1e-3) / 1e12
     step = fwd_ms + sh_ms + adj_ms
     nominal = int(np.prod(desc["dims"])) * desc["n_tx"] * desc["n_ch"]
     return {"workload": "FORCES 256x256 plane, 64 tx x 64 ch x 2048 samples, 8 frames: "
@@ -494,11 +521,8 @@ def main():
     nominal = nv * desc["n_tx"] * desc["n_ch"]
     value = nominal / (ms_step * 1e-3) / 1e9
     n_act = active_terms(desc, dev)
-    # Algorithmic FP32 work of one active HERCULES term:
-    # delay 13 flops (dx, rho^2, d^2, sqrt, d+z, rcp, mul, fma, floor, fract),
-    # apodization 14 (u^2 + degree-6 polynomial), cubic read 16, accumulate 2.
-    flops_per_term = 45
-    achieved = n_act * flops_per_term / (das_ms * 1e-3) / 1e12
+    # algorithmic FP32 work of the launch (algorithmic_flops)
+    achieved = algorithmic_flops(desc, n_act) / (das_ms * 1e-3) / 1e12
     dec_bytes = rf.size * 2 + rf.size * 4
     res = {
         "metric": "G voxel*tx*ch samples/s (+ volumes/s), decode + DAS at oracle accuracy",

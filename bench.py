@@ -132,11 +132,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "das_hercules_128x128x256_traffic.
 
 
 def kernel_hash() -> str:
+    """Hash of the DAS kernel sources without their comments and with
+    whitespace collapsed: it changes with the code the counters measured, not
+    with its comments."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fp:
-            h.update(fp.read())
+        with open(os.path.join(ROOT, f)) as fp:
+            text = fp.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

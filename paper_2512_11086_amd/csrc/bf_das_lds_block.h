@@ -53,8 +53,10 @@ constexpr int HANN_TAB_PAD = HANN_N + 2;   // table entries reserved in LDS (flo
 
 // Trace slot `lane` of a batch, held by that lane of every wavefront: the
 // first sample interval of its window, the x of its transmit column, and
-// its trace index i * n_ch + j (-1 for an empty slot).  Staging lanes fetch
-// the entry of their slot with a lane permute; terms read it with readlane.
+// its trace index i * n_ch + j (-1 for an empty slot).  Staging lanes (and
+// the RF gradient's flush) fetch the entry of their slot with a lane
+// permute; the terms take the column from the read-only table and the
+// negated window start from a per-batch LDS array (store_w0).
 struct TraceDesc {
     int w0;
     float xi;
@@ -128,9 +130,10 @@ __device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, 
     int ix, iy, iz;
     lane_point(a, c, bx, by, bz, wave, lane, p, &ix, &iy, &iz);
     L.valid = ix < a.g.nx && iy < a.g.ny && iz >= 0 && iz < a.g.nz;
-    // Real-data terms read their windows without clamping the index, so every
-    // lane takes the geometry of the nearest grid point of its box: its delay
-    // then lies within the box's bounds (see hercules_term, sep_term)
+    // The terms read their windows without clamping the index, so every lane
+    // takes the geometry of the nearest grid point of its box: its delay then
+    // lies within the box's bounds (see hercules_term and the separable terms
+    // of das_block)
     ix = min(ix, a.g.nx - 1);
     iy = min(iy, a.g.ny - 1);
     iz = min(max(iz, 0), a.g.nz - 1);

@@ -241,3 +241,22 @@ def test_de_full_size_adjoint_identity(torch_mod, k):
     rhs = (e.double() * ge.double()).sum().item()
     bound = 1e-5 * img.double().norm().item() * G.double().norm().item()
     assert abs(lhs - rhs) <= bound, (lhs, rhs, bound)
+
+
+@pytest.mark.parametrize("e_type", ["bf16", "i32"])
+def test_adjoint_for_other_storage_types(torch_mod, e_type):
+    # dL/de reads no data: the LDS kernel serves every storage type; dL/dc of
+    # BF16 / INT32 data runs the gather adjoint in the same call
+    torch = torch_mod
+    d = _desc("hercules", "cubic")
+    H, e = _data(d, 14)
+    G = np.random.default_rng(15).normal(size=oracle.Geometry(d).shape)
+    plan = bfm.Plan(d, H, e_type=e_type)
+    dt = {"bf16": torch.bfloat16, "i32": torch.int32}[e_type]
+    et = torch.from_numpy(np.rint(e).astype(np.float32)).to(dt).cuda()
+    e_ref = et.float().cpu().numpy().astype(np.float64)
+    ge, gc = plan.das_adjoint(et, torch.from_numpy(G.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    assert rel_l2(ge.cpu().numpy(), oracle.das_adjoint_e(d, G)) <= 1e-5
+    ref_c = float(np.sum(G * oracle.das_dc(d, e_ref)))
+    assert abs(gc.item() - ref_c) <= 1e-4 * abs(ref_c)

@@ -10,6 +10,7 @@ import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbf.so")
+ABI_VERSION = 4     # the bf.h version these structures and signatures follow
 
 BF_OK = 0
 STATUS = {0: "BF_OK", -1: "BF_ERR_NULL", -2: "BF_ERR_SHAPE", -3: "BF_ERR_NOT_HADAMARD",
@@ -106,6 +107,9 @@ def lib():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = res
+    if L.bf_abi_version() != ABI_VERSION:
+        raise ImportError(f"{LIB_PATH} reports ABI {L.bf_abi_version()}, the binding "
+                          f"follows ABI {ABI_VERSION}: rebuild libbf")
     _lib = L
     return L
 

@@ -32,7 +32,10 @@ def test_library_exports_every_declared_function():
     for name in names:
         assert hasattr(L, name), f"{name} declared in bf.h but not exported"
     assert set(names) == set(_lib.EXPORTED)
-    assert L.bf_abi_version() == 4
+    # the binding, the header and the library agree on the ABI version
+    with open(os.path.join(ROOT, "include", "bf.h")) as fp:
+        m = re.search(r"#define BF_ABI_VERSION (\d+)", fp.read())
+    assert m and int(m.group(1)) == _lib.ABI_VERSION == L.bf_abi_version()
 
 
 def _good(k=0):

@@ -79,7 +79,7 @@ enum { BF_DECODE_MFMA_I8 = 0, BF_DECODE_FMA_F32 = 1 };
  * order, sampling rate, sound speed, output region and resolution, channel
  * mapping). */
 typedef struct {
-    int32_t mode;              /* BF_FORCES_2D or BF_HERCULES_3D                        */
+    int32_t mode;              /* BF_FORCES_2D, BF_HERCULES_3D, BF_TPW_3D, BF_VLS_3D     */
     int32_t n_tx;              /* transmits per frame = Hadamard order, 1..256          */
     int32_t n_ch;              /* receive data channels, 1..1024                        */
     int32_t n_samples;         /* samples per channel, 1..65536                         */
@@ -327,10 +327,13 @@ int bf_demodulate(bf_demod d, const int16_t *rf, void *iq, void *stream);
  *   (computed on the device; an all-zero image gives -param / 0).
  * img: device f32 [n_cols][n] (depth fastest: a [Ny][Nx][Nz] volume has
  * n_cols = Ny*Nx, n = Nz) or, for iq = 1, complex f32 [n_cols][n][2];
- * out: device f32 [n_cols][n] (must not overlap img).  FP32 arithmetic:
- * radix-2 FFT in LDS for power-of-two n, a direct circular sum otherwise.
- * A plan holds its tables and a one-word reduction buffer, so calls of one
- * plan must not overlap on the device.
+ * out: device f32 [n_cols][n] (must not overlap img).  FP32 arithmetic: for
+ * power-of-two n from 64 to 1024 a register-resident FFT per pair of columns
+ * (two real columns as one complex transform: the inverse DFT of
+ * -j sgn(k) DFT(x1 + j x2) is H{x1} + j H{x2}, and env = sqrt(x^2 + H{x}^2));
+ * other powers of two a radix-2 FFT in LDS; a direct circular sum otherwise.
+ * A plan holds its tables and a partial-maximum buffer, so calls of one plan
+ * must not overlap on the device.
  * ------------------------------------------------------------------------- */
 enum { BF_COMPRESS_NONE = 0, BF_COMPRESS_LOG = 1, BF_COMPRESS_POWER = 2 };
 

@@ -175,7 +175,8 @@ CASES = [
     # full-size workload geometries with their default tiles
     ("w1 hercules", lambda: synth.configs.workload(1), (3, 3, 0), (2, 2, 3), 2),
     ("w5 diverging", lambda: synth.configs.workload(5), (3, 3, 0), (2, 2, 3), 2),
-    ("w3 forces", lambda: synth.configs.workload(3), (4, 0, 2), (4, 1, 4), 1),
+    ("w3 forces", lambda: synth.configs.workload(3), (5, 0, 1), (2, 1, 8), 1),
+    ("w3 forces 16x4", lambda: synth.configs.workload(3), (4, 0, 2), (4, 1, 4), 1),
     ("w6 tpw", lambda: synth.configs.workload(6), (3, 3, 0), (2, 2, 3), 1),
     ("w7 vls", lambda: synth.configs.workload(7), (2, 3, 1), (2, 2, 3), 1),
     # small grids: tiles, tilt, array plane, F#, focal lines

@@ -390,8 +390,8 @@ std::vector<TileCand> candidates(const Frame &f)
         // a plane along x (ny = 1) or along y (nx = 1): tiles and workgroups
         // spread over that lateral axis and depth only
         const bool along_x = f.grid.ny == 1;
-        const int tiles[][2] = {{3, 3}, {2, 4}, {4, 2}, {1, 5}};
-        const int blocks[][2] = {{2, 2}, {4, 1}, {1, 4}, {2, 1}, {4, 4}};
+        const int tiles[][2] = {{3, 3}, {2, 4}, {4, 2}, {1, 5}, {5, 1}};
+        const int blocks[][2] = {{2, 2}, {4, 1}, {1, 4}, {2, 1}, {4, 4}, {2, 8}};
         for (auto &t : tiles) {
             const int lx = along_x ? t[0] : 0, ly = along_x ? 0 : t[0];
             c.push_back({lx, ly, t[1], 1, 1, 1, 4, BF_DAS_GATHER});
@@ -547,7 +547,12 @@ int bf_autotune(bf_plan plan, const char *cache_path)
             (void)hipEventCreate(&t0);
             (void)hipEventCreate(&t1);
             float best_ms = 1e30f;
-            for (const TileCand &t : candidates(*f0)) {
+            // the plan's own configuration first: tuning never ends slower
+            std::vector<TileCand> cands{
+                {saved[0], saved[1], saved[2], saved[3], saved[4], saved[5], saved[6], saved_variant}};
+            const std::vector<TileCand> more = candidates(*f0);
+            cands.insert(cands.end(), more.begin(), more.end());
+            for (const TileCand &t : cands) {
                 f0->set_tile(t.lx, t.ly, t.lz);
                 f0->bw[0] = t.bwx;
                 f0->bw[1] = t.bwy;

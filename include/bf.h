@@ -45,7 +45,10 @@
 extern "C" {
 #endif
 
-#define BF_ABI_VERSION 4
+#define BF_ABI_VERSION 5
+
+/* Largest frame count of bf_das_frames / bf_das_adjoint_frames. */
+#define BF_MAX_FRAMES 4096
 
 typedef enum {
     BF_OK = 0,
@@ -247,6 +250,30 @@ int bf_das(bf_plan plan, const void *e, float *out, double c, void *stream);
  * gather adjoint (FP32 atomics per term). */
 int bf_das_adjoint(bf_plan plan, const void *e, const float *grad_out, double c,
                    float *grad_e, float *grad_c, void *stream);
+
+/* bf_das for a stack of n_frames frames of this plan's geometry, all at
+ * sound speed c (e.g. the frames of one sound-speed autofocus batch):
+ *   out[f] = bf_das(e[f]) for f < n_frames.
+ * e: device, type params.e_type, [n_frames][n_tx][n_ch][n_samples];
+ * out: device f32 [n_frames][Ny][Nx][Nz], overwritten.  n_frames in
+ * 1..BF_MAX_FRAMES (BF_ERR_SHAPE otherwise).  The LDS-staged kernel takes all
+ * frames in one launch, so small grids fill the device; each out[f] is
+ * bit-identical to bf_das on frame f alone.  The gather kernel runs frame by
+ * frame.  May allocate (once per larger stack) partial images of
+ * n_frames x the plan's channel groups x the grid; plan_get_info's
+ * workspace_bytes includes them. */
+int bf_das_frames(bf_plan plan, const void *e, int32_t n_frames, float *out, double c,
+                  void *stream);
+
+/* bf_das_adjoint for a stack of frames at one c: grad_out [n_frames][Ny][Nx][Nz],
+ * grad_e [n_frames][n_tx][n_ch][n_samples] (nullable), grad_c device f32
+ * [n_frames] (nullable): grad_c[f] = sum_p grad_out[f][p] d out[f][p] / dc, the
+ * frame's own term (a loss summed over frames has dL/dc = sum_f grad_c[f]).
+ * grad_c[f] is bit-identical to bf_das_adjoint on frame f alone; grad_e
+ * matches it up to the order of its FP32 atomics.  Errors as bf_das_frames
+ * and bf_das_adjoint. */
+int bf_das_adjoint_frames(bf_plan plan, const void *e, const float *grad_out, int32_t n_frames,
+                          double c, float *grad_e, float *grad_c, void *stream);
 
 /* Image-sharpness loss for n_images images of n_per_image points each:
  *   loss[f] = -sum I^4 / (sum I^2)^2   (device f32 [n_images], overwritten)

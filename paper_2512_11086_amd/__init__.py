@@ -160,30 +160,43 @@ class Plan:
             raise ValueError(f"rf shape {tuple(rf.shape)} != {self.rf_shape}")
 
     def _check_e(self, e):
+        """Number of stacked frames of e: None for one frame of the plan's
+        shape, F for an (F, *e_shape) stack."""
         if e.dtype != self.e_dtype() or not e.is_cuda or not e.is_contiguous():
             raise ValueError(f"e must be a contiguous {self.e_dtype()} CUDA tensor")
-        if tuple(e.shape) != self.e_shape:
-            raise ValueError("e has the wrong shape")
+        if tuple(e.shape) == self.e_shape:
+            return None
+        if e.dim() == len(self.e_shape) + 1 and tuple(e.shape[1:]) == self.e_shape:
+            return int(e.shape[0])
+        raise ValueError("e has the wrong shape")
 
     def decode(self, rf, out=None, stream=None):
         torch = _torch()
         self._check_rf(rf)
         if out is None:
             out = torch.empty(rf.shape, dtype=self.e_dtype(), device=rf.device)
-        self._check_e(out)
+        if self._check_e(out) is not None:
+            raise ValueError("out must hold one frame")
         check(lib().bf_decode(self._h, _ptr(rf), _ptr(out), _stream(stream)))
         return out
 
     def das(self, e, c: float | None = None, out=None, stream=None):
+        """Image of e at sound speed c (the plan's by default).  e may be a
+        stack (F, n_tx, n_ch, S) of frames: one call beamforms all of them
+        (bf_das_frames) into an (F, *image shape) output."""
         torch = _torch()
-        self._check_e(e)
+        nf = self._check_e(e)
         odt = torch.complex64 if self.iq else torch.float32
+        shape = self.out_shape if nf is None else (nf,) + self.out_shape
         if out is None:
-            out = torch.empty(self.out_shape, dtype=odt, device=e.device)
-        if out.dtype != odt or tuple(out.shape) != self.out_shape or not out.is_contiguous():
-            raise ValueError(f"out must be a contiguous {odt} tensor of the image shape")
-        check(lib().bf_das(self._h, _ptr(e), _ptr(out), float(self.c if c is None else c),
-                           _stream(stream)))
+            out = torch.empty(shape, dtype=odt, device=e.device)
+        if out.dtype != odt or tuple(out.shape) != shape or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous {odt} tensor of shape {shape}")
+        cv = float(self.c if c is None else c)
+        if nf is None:
+            check(lib().bf_das(self._h, _ptr(e), _ptr(out), cv, _stream(stream)))
+        else:
+            check(lib().bf_das_frames(self._h, _ptr(e), nf, _ptr(out), cv, _stream(stream)))
         return out
 
     def das_adjoint(self, e, grad_out, c: float | None = None, want_e: bool = True,
@@ -191,29 +204,41 @@ class Plan:
         """Returns (grad_e or None, grad_c tensor of shape () or None).
 
         ``e`` may be None when only grad_e is wanted (it does not depend on
-        the data); ``out_e`` is an optional float32 (n_tx, n_ch, S) buffer
-        for grad_e."""
+        the data); ``out_e`` is an optional float32 buffer for grad_e.  A
+        stack of frames (grad_out of shape (F, *image shape), e of shape
+        (F, n_tx, n_ch, S)) runs bf_das_adjoint_frames: grad_e has shape
+        (F, n_tx, n_ch, S) and grad_c shape (F,), one dL/dc term per frame."""
         torch = _torch()
-        if e is not None:
-            self._check_e(e)
+        nf_e = self._check_e(e) if e is not None else None
         g = grad_out.contiguous().to(torch.float32)
-        if tuple(g.shape) != self.out_shape:
+        if tuple(g.shape) == self.out_shape:
+            nf = None
+        elif g.dim() == len(self.out_shape) + 1 and tuple(g.shape[1:]) == self.out_shape:
+            nf = int(g.shape[0])
+        else:
             raise ValueError("grad_out has the wrong shape")
-        shape_e = (self.n_tx, self.n_ch, self.n_samples)
+        if e is not None and nf_e != nf:
+            raise ValueError("e and grad_out hold different numbers of frames")
+        lead = () if nf is None else (nf,)
+        shape_e = lead + (self.n_tx, self.n_ch, self.n_samples)
         if want_e and out_e is not None:
             if (tuple(out_e.shape) != shape_e or out_e.dtype != torch.float32
                     or not out_e.is_contiguous() or out_e.device != g.device):
-                raise ValueError("out_e must be a contiguous float32 (n_tx, n_ch, S) "
+                raise ValueError(f"out_e must be a contiguous float32 {shape_e} "
                                  "tensor on grad_out's device")
             ge = out_e
         else:
             ge = (torch.empty(shape_e, dtype=torch.float32, device=g.device)
                   if want_e else None)
-        gc = torch.empty((), dtype=torch.float32, device=g.device) if want_c else None
-        check(lib().bf_das_adjoint(self._h, _ptr(e) if e is not None else None, _ptr(g),
-                                   float(self.c if c is None else c),
-                                   _ptr(ge) if ge is not None else None,
-                                   _ptr(gc) if gc is not None else None, _stream(stream)))
+        gc = torch.empty(lead, dtype=torch.float32, device=g.device) if want_c else None
+        args = (_ptr(ge) if ge is not None else None, _ptr(gc) if gc is not None else None,
+                _stream(stream))
+        ep = _ptr(e) if e is not None else None
+        cv = float(self.c if c is None else c)
+        if nf is None:
+            check(lib().bf_das_adjoint(self._h, ep, _ptr(g), cv, *args))
+        else:
+            check(lib().bf_das_adjoint_frames(self._h, ep, _ptr(g), nf, cv, *args))
         return ge, gc
 
 

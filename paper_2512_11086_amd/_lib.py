@@ -10,9 +10,11 @@ import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbf.so")
-ABI_VERSION = 4     # the bf.h version these structures and signatures follow
+ABI_VERSION = 5     # the bf.h version these structures and signatures follow
 
 BF_OK = 0
+BF_ERR_NULL, BF_ERR_SHAPE = -1, -2
+MAX_FRAMES = 4096   # BF_MAX_FRAMES: frames of one bf_das_frames / bf_das_adjoint_frames call
 STATUS = {0: "BF_OK", -1: "BF_ERR_NULL", -2: "BF_ERR_SHAPE", -3: "BF_ERR_NOT_HADAMARD",
           -4: "BF_ERR_GEOMETRY", -5: "BF_ERR_UNSUPPORTED", -6: "BF_ERR_TOO_LARGE",
           -7: "BF_ERR_HIP", -8: "BF_ERR_NO_DEVICE", -9: "BF_ERR_STATE"}
@@ -91,6 +93,8 @@ def lib():
         "bf_decode": ([vp, vp, vp, vp], ctypes.c_int),
         "bf_das": ([vp, vp, vp, dbl, vp], ctypes.c_int),
         "bf_das_adjoint": ([vp, vp, vp, dbl, vp, vp, vp], ctypes.c_int),
+        "bf_das_frames": ([vp, vp, i32, vp, dbl, vp], ctypes.c_int),
+        "bf_das_adjoint_frames": ([vp, vp, vp, i32, dbl, vp, vp, vp], ctypes.c_int),
         "bf_sharpness": ([vp, i64, i32, vp, vp, vp], ctypes.c_int),
         "bf_batch_run": ([vp, P(vp), P(vp), vp], ctypes.c_int),
         "bf_graph_launch": ([vp, P(vp), P(vp), vp], ctypes.c_int),
@@ -121,7 +125,8 @@ def check(status: int) -> None:
 
 EXPORTED = ("bf_abi_version", "bf_last_error", "bf_validate", "bf_plan_create",
             "bf_plan_create_batch", "bf_plan_destroy", "bf_plan_get_info", "bf_autotune",
-            "bf_set_tile", "bf_set_das_config", "bf_decode", "bf_das", "bf_das_adjoint", "bf_sharpness",
+            "bf_set_tile", "bf_set_das_config", "bf_decode", "bf_das", "bf_das_adjoint",
+            "bf_das_frames", "bf_das_adjoint_frames", "bf_sharpness",
             "bf_batch_run", "bf_graph_launch", "bf_hann_poly", "bf_demod_create",
             "bf_demod_destroy", "bf_demod_out_samples", "bf_demodulate", "bf_env_create",
             "bf_env_destroy", "bf_envelope")

@@ -8,9 +8,12 @@ only (ds/dc = -tof * fs / c).  ``sharpness(img)`` wraps bf_sharpness, the
 negative normalised L4 norm -sum I^4 / (sum I^2)^2 per image.
 
 ``autofocus`` minimises the summed sharpness loss of a batch of frames over c
-with the exact gradient; each frame's beamforming runs under
-torch.utils.checkpoint, so its image is recomputed in backward instead of
-being kept alive (the memory of a batch stays at one image).
+with the exact gradient.  Frames given as a list are beamformed one by one,
+each under torch.utils.checkpoint, so its image is recomputed in backward
+instead of being kept alive (the memory of a batch stays at one image).
+Frames given as one stacked tensor (F, n_tx, n_ch, S) are beamformed, and
+their adjoint run, in one launch for all F (bf_das_frames,
+bf_das_adjoint_frames), which fills the device far better for small grids.
 """
 from __future__ import annotations
 
@@ -31,36 +34,51 @@ class _DasFunction(torch.autograd.Function):
         e, c = ctx.saved_tensors
         want_e, want_c = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         ge, gc = ctx.plan.das_adjoint(e, grad_img, c=float(c), want_e=want_e, want_c=want_c)
-        gc_out = gc.to(device=c.device, dtype=c.dtype).reshape(c.shape) if want_c else None
+        # a stack of frames gives one dL/dc term per frame; c is shared
+        gc_out = (gc.to(device=c.device, dtype=c.dtype).sum().reshape(c.shape)
+                  if want_c else None)
         return ge if want_e else None, gc_out, None
 
 
 class _SharpnessFunction(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, img):
+    def forward(ctx, img, n_images):
         from . import sharpness as _sharp
-        loss, g = _sharp(img.reshape(1, -1), grad=True)
+        loss, g = _sharp(img.reshape(n_images, -1), grad=True)
         ctx.save_for_backward(g.reshape(img.shape))
-        return loss.reshape(())
+        return loss.sum()
 
     @staticmethod
     def backward(ctx, grad_loss):
         (g,) = ctx.saved_tensors
-        return g * grad_loss
+        return g * grad_loss, None
 
 
 def das(e, c, plan):
-    """Differentiable DAS image of decoded data e at sound speed c (0-d tensor)."""
+    """Differentiable DAS image of decoded data e at sound speed c (0-d
+    tensor); e may be a stack of frames (F, n_tx, n_ch, S)."""
     return _DasFunction.apply(e, c, plan)
 
 
-def sharpness(img):
-    """Differentiable -sum I^4 / (sum I^2)^2 of one image."""
-    return _SharpnessFunction.apply(img)
+def sharpness(img, n_images: int = 1):
+    """Differentiable -sum I^4 / (sum I^2)^2 of one image, or its sum over
+    the n_images images stacked along the first axis of img."""
+    return _SharpnessFunction.apply(img, n_images)
+
+
+def _stacked(frames, plan):
+    return torch.is_tensor(frames) and frames.dim() == len(plan.e_shape) + 1
 
 
 def focus_loss(frames, c, plan, use_checkpoint: bool = True):
-    """Sum over frames of the sharpness loss at sound speed c."""
+    """Sum over frames of the sharpness loss at sound speed c.  frames: a
+    list of decoded frames, or one stacked (F, n_tx, n_ch, S) tensor."""
+    if _stacked(frames, plan):
+        nf = int(frames.shape[0])
+        if use_checkpoint:
+            return checkpoint(lambda ee, cc: sharpness(das(ee, cc, plan), nf), frames, c,
+                              use_reentrant=False)
+        return sharpness(das(frames, c, plan), nf)
     total = None
     for e in frames:
         if use_checkpoint:

@@ -143,10 +143,14 @@ __global__ __launch_bounds__(256) void das_adjoint_kernel(DasArgs a)
 }
 
 // Sum of the per-block partials in a fixed order -> grad_c.
+// out[b] = sum of partial[b * n .. b * n + n) in a fixed order (one
+// workgroup per frame b).
 __global__ __launch_bounds__(256) void reduce_partials_kernel(const double *partial, int n,
                                                              float *out)
 {
     __shared__ double red[256];
+    partial += (long)blockIdx.x * n;
+    out += blockIdx.x;
     double s = 0.0;
     for (int q = threadIdx.x; q < n; q += 256) s += partial[q];
     red[threadIdx.x] = s;
@@ -158,9 +162,10 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double *part
     if (threadIdx.x == 0) *out = (float)red[0];
 }
 
-hipError_t launch_reduce_partials(const double *partial, int n, float *out, hipStream_t s)
+hipError_t launch_reduce_partials(const double *partial, int n, float *out, hipStream_t s,
+                                  int n_frames)
 {
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, s, partial, n, out);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(n_frames), dim3(256), 0, s, partial, n, out);
     return hipGetLastError();
 }
 

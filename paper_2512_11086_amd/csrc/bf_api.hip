@@ -163,6 +163,17 @@ void *Frame::alloc(size_t bytes)
     return p;
 }
 
+void Frame::release(void *ptr, size_t bytes)
+{
+    for (size_t q = 0; q < allocs.size(); ++q)
+        if (allocs[q] == ptr) {
+            (void)hipFree(ptr);
+            allocs.erase(allocs.begin() + (long)q);
+            total_bytes -= (int64_t)bytes;
+            return;
+        }
+}
+
 Frame::~Frame()
 {
     for (void *p : allocs) (void)hipFree(p);
@@ -598,6 +609,84 @@ int Frame::das(const void *e, float *out, double c, hipStream_t s) const
     return err == hipSuccess ? BF_OK : hip_fail(err, "DAS launch");
 }
 
+
+// Partial images of a stack of nf frames ([nf][groups][points]), grown on
+// demand; null when the plan does not split the channel sum.
+float *Frame::frames_part(int nf)
+{
+    if (groups <= 1) return nullptr;
+    const size_t need = (size_t)nf * groups * out_elems() * sizeof(float);
+    if (need > part_frames_bytes) {
+        if (d_part_frames) release(d_part_frames, part_frames_bytes);
+        d_part_frames = (float *)alloc(need);
+        part_frames_bytes = d_part_frames ? need : 0;
+    }
+    return d_part_frames;
+}
+
+// A stack of nf frames ([nf][...] arrays) at one sound speed.  The LDS
+// kernel beamforms all of them in one launch (grid z), so that a small grid
+// fills the device and the costly deep boxes of one frame overlap the cheap
+// ones of the next; the gather kernel runs frame by frame.
+int Frame::das_frames(const void *e, int nf, float *out, double c, hipStream_t s)
+{
+    DasArgs a = das_args(e, out, c);
+    LdsCfg cfg;
+    if (nf > 1 && variant != BF_DAS_GATHER && lds_config(a, &cfg)) {
+        if (groups > 1 && !(a.part = frames_part(nf)))
+            return fail(BF_ERR_HIP, "device allocation of partial images failed");
+        const hipError_t err = launch_das_lds(a, cfg, p.mode, das_et(), p.interp, s, nf);
+        return err == hipSuccess ? BF_OK : hip_fail(err, "DAS launch");
+    }
+    for (int f = 0; f < nf; ++f) {
+        const int st = das(static_cast<const char *>(e) + (size_t)f * e_bytes(),
+                           out + (size_t)f * out_elems(), c, s);
+        if (st != BF_OK) return st;
+    }
+    return BF_OK;
+}
+
+// Adjoint of das_frames (grad_out, grad_e: [nf][...]; grad_c: [nf]).
+// Linear / cubic reads run the LDS-staged adjoint: dL/de (which reads no
+// data) on a depth-major wavefront tile, dL/dc (FP32 data) on the plan's
+// tile, as two launches when both are requested, each over all frames.
+// Nearest reads, other data types and the gather variant run the gather
+// adjoint (FP32 atomics into grad_e) frame by frame.
+int Frame::das_adjoint(const void *e, const float *grad_out, double c, float *grad_e,
+                       float *grad_c, int nf, hipStream_t s) const
+{
+    DasArgs a = das_args(e, nullptr, c);
+    a.grad_out = grad_out;
+    a.grad_e = grad_e;
+    const bool lds_ok = p.interp != BF_INTERP_NEAREST && variant != BF_DAS_GATHER;
+    DasArgs ae = a;
+    LdsCfg ce, cc;
+    int bwa[3];
+    adjoint_e_tile(&ae, bwa);
+    const bool e_lds = grad_e && lds_ok && lds_config(ae, &ce, 2, bwa);
+    const bool c_lds = grad_c && lds_ok && p.e_type == BF_E_F32 && lds_config(a, &cc, 1) &&
+                       (long)xcd_slab_grid(cc) * a.groups * nf <= max_blocks;
+    hipError_t err = hipSuccess;
+    if ((grad_e && !e_lds) || (grad_c && !c_lds)) {
+        const long pts = (long)grid.nx * grid.ny * grid.nz;
+        for (int f = 0; f < nf && err == hipSuccess; ++f) {
+            DasArgs ag = a;          // what the LDS kernels do not take, frame f
+            ag.e = e ? static_cast<const char *>(e) + (size_t)f * e_bytes() : nullptr;
+            ag.grad_out = grad_out + f * pts;
+            ag.grad_e = e_lds || !grad_e ? nullptr : grad_e + f * e_elems();
+            err = launch_das_adjoint(ag, p.mode, p.e_type, p.interp,
+                                     c_lds || !grad_c ? nullptr : grad_c + f, s);
+        }
+    }
+    if (err == hipSuccess && e_lds)
+        err = launch_das_lds_adjoint(ae, ce, p.mode, p.interp, nullptr, s, nf);
+    if (err == hipSuccess && c_lds) {
+        DasArgs ac = a;
+        ac.grad_e = nullptr;
+        err = launch_das_lds_adjoint(ac, cc, p.mode, p.interp, grad_c, s, nf);
+    }
+    return err == hipSuccess ? BF_OK : hip_fail(err, "DAS adjoint launch");
+}
 }  // namespace bf
 
 using namespace bf;
@@ -606,6 +695,13 @@ static int check_plan(bf_plan plan)
 {
     if (!plan) return fail(BF_ERR_NULL, "plan is NULL");
     if (plan->magic != BF_PLAN_MAGIC) return fail(BF_ERR_STATE, "not a live plan");
+    return BF_OK;
+}
+
+static int check_frames(int32_t n_frames)
+{
+    if (n_frames < 1 || n_frames > BF_MAX_FRAMES)
+        return fail(BF_ERR_SHAPE, "n_frames must be 1..%d", BF_MAX_FRAMES);
     return BF_OK;
 }
 
@@ -765,50 +861,40 @@ int bf_das(bf_plan plan, const void *e, float *out, double c, void *stream)
     if (st != BF_OK) return st;
     if (!e || !out) return fail(BF_ERR_NULL, "e and out must be non-NULL");
     if ((st = check_c(c)) != BF_OK) return st;
-    return plan->frames[0]->das(e, out, c, (hipStream_t)stream);
+    return plan->frames[0]->das_frames(e, 1, out, c, (hipStream_t)stream);
 }
 
 int bf_das_adjoint(bf_plan plan, const void *e, const float *grad_out, double c, float *grad_e,
                    float *grad_c, void *stream)
+{
+    return bf_das_adjoint_frames(plan, e, grad_out, 1, c, grad_e, grad_c, stream);
+}
+
+int bf_das_frames(bf_plan plan, const void *e, int32_t n_frames, float *out, double c,
+                  void *stream)
+{
+    g_err.clear();
+    int st = check_plan(plan);
+    if (st != BF_OK) return st;
+    if (!e || !out) return fail(BF_ERR_NULL, "e and out must be non-NULL");
+    if ((st = check_frames(n_frames)) != BF_OK) return st;
+    if ((st = check_c(c)) != BF_OK) return st;
+    return plan->frames[0]->das_frames(e, n_frames, out, c, (hipStream_t)stream);
+}
+
+int bf_das_adjoint_frames(bf_plan plan, const void *e, const float *grad_out, int32_t n_frames,
+                          double c, float *grad_e, float *grad_c, void *stream)
 {
     g_err.clear();
     int st = check_plan(plan);
     if (st != BF_OK) return st;
     if (!grad_out) return fail(BF_ERR_NULL, "grad_out is NULL");
     if (grad_c && !e) return fail(BF_ERR_NULL, "e is needed for grad_c");
+    if ((st = check_frames(n_frames)) != BF_OK) return st;
     if ((st = check_c(c)) != BF_OK) return st;
     const Frame &f = *plan->frames[0];
     if (f.p.iq) return fail(BF_ERR_UNSUPPORTED, "the adjoint is defined for RF plans only");
-    DasArgs a = f.das_args(e, nullptr, c);
-    a.grad_out = grad_out;
-    a.grad_e = grad_e;
-    // Linear / cubic reads run the LDS-staged adjoint: dL/de (which reads no
-    // data) on a depth-major wavefront tile, dL/dc (FP32 data) on the plan's
-    // tile, as two launches when both are requested.  Nearest reads, other
-    // data types and the gather variant run the gather adjoint (FP32 atomics
-    // into grad_e).
-    const hipStream_t s = (hipStream_t)stream;
-    const bool lds_ok = f.p.interp != BF_INTERP_NEAREST && f.variant != BF_DAS_GATHER;
-    DasArgs ae = a;
-    LdsCfg ce, cc;
-    int bwa[3];
-    f.adjoint_e_tile(&ae, bwa);
-    const bool e_lds = grad_e && lds_ok && f.lds_config(ae, &ce, 2, bwa);
-    const bool c_lds = grad_c && lds_ok && f.p.e_type == BF_E_F32 && f.lds_config(a, &cc, 1) &&
-                       (long)xcd_slab_grid(cc) * a.groups <= f.max_blocks;
-    hipError_t err = hipSuccess;
-    DasArgs ag = a;                 // what the LDS kernels do not take
-    ag.grad_e = e_lds ? nullptr : grad_e;
-    if (ag.grad_e || (grad_c && !c_lds))
-        err = launch_das_adjoint(ag, f.p.mode, f.p.e_type, f.p.interp, c_lds ? nullptr : grad_c, s);
-    if (err == hipSuccess && e_lds)
-        err = launch_das_lds_adjoint(ae, ce, f.p.mode, f.p.interp, nullptr, s);
-    if (err == hipSuccess && c_lds) {
-        DasArgs ac = a;
-        ac.grad_e = nullptr;
-        err = launch_das_lds_adjoint(ac, cc, f.p.mode, f.p.interp, grad_c, s);
-    }
-    return err == hipSuccess ? BF_OK : hip_fail(err, "DAS adjoint launch");
+    return f.das_adjoint(e, grad_out, c, grad_e, grad_c, n_frames, (hipStream_t)stream);
 }
 
 int bf_sharpness(const float *img, int64_t n_per_image, int32_t n_images, float *loss, float *grad,

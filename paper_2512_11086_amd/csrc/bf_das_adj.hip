@@ -6,7 +6,8 @@
 
 namespace bf {
 
-hipError_t launch_reduce_partials(const double *partial, int n, float *out, hipStream_t s);
+hipError_t launch_reduce_partials(const double *partial, int n, float *out, hipStream_t s,
+                                  int n_frames = 1);
 hipError_t launch_fill(float *p, long n, float v, hipStream_t s);
 
 // ADJ = 1: dL/dc (FP32 data), 2: dL/de (reads no data).
@@ -15,6 +16,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerEu
 void das_lds_adj_kernel(DasArgs a, LdsCfg c)
 {
     extern __shared__ float4 smem[];
+    frame_args<ET_F32>(a, blockIdx.z, (long)gridDim.x * gridDim.y);   // stacked frames
     const int blk = xcd_slab_box(c, blockIdx.x);
     if (blk < 0) {      // past the last slab: an empty partial for dL/dc
         if ((ADJ & 1) && threadIdx.x == 0) a.partial[(long)blockIdx.y * gridDim.x + blockIdx.x] = 0.0;
@@ -24,10 +26,11 @@ void das_lds_adj_kernel(DasArgs a, LdsCfg c)
 }
 
 template <int MODE, int IP, int ZP, int ADJ>
-static hipError_t launch_adj_lds4(const DasArgs &a, const LdsCfg &c, size_t shm, hipStream_t s)
+static hipError_t launch_adj_lds4(const DasArgs &a, const LdsCfg &c, int nf, size_t shm,
+                                  hipStream_t s)
 {
     const int nthr = 64 * c.bwx * c.bwy * c.bwz;
-    dim3 grid(xcd_slab_grid(c), a.groups);
+    dim3 grid(xcd_slab_grid(c), a.groups, nf);
     hipError_t e =
         allow_lds(reinterpret_cast<const void *>(&das_lds_adj_kernel<MODE, IP, ZP, ADJ>), shm);
     if (e != hipSuccess) return e;
@@ -36,32 +39,32 @@ static hipError_t launch_adj_lds4(const DasArgs &a, const LdsCfg &c, size_t shm,
 }
 
 template <int MODE, int IP, int ZP>
-static hipError_t launch_adj_lds3(const DasArgs &a, const LdsCfg &c, int adj, size_t shm,
+static hipError_t launch_adj_lds3(const DasArgs &a, const LdsCfg &c, int adj, int nf, size_t shm,
                                   hipStream_t s)
 {
     switch (adj) {
-        case 1: return launch_adj_lds4<MODE, IP, ZP, 1>(a, c, shm, s);
-        case 2: return launch_adj_lds4<MODE, IP, ZP, 2>(a, c, shm, s);
+        case 1: return launch_adj_lds4<MODE, IP, ZP, 1>(a, c, nf, shm, s);
+        case 2: return launch_adj_lds4<MODE, IP, ZP, 2>(a, c, nf, shm, s);
         default: return hipErrorInvalidValue;     // one gradient per launch
     }
 }
 
 template <int MODE, int IP>
-static hipError_t launch_adj_lds2(const DasArgs &a, const LdsCfg &c, int adj, size_t shm,
+static hipError_t launch_adj_lds2(const DasArgs &a, const LdsCfg &c, int adj, int nf, size_t shm,
                                   hipStream_t s)
 {
     if constexpr (MODE == MODE_HERCULES)
-        if (c.zp == 2) return launch_adj_lds3<MODE, IP, 2>(a, c, adj, shm, s);
-    return c.zp == 1 ? launch_adj_lds3<MODE, IP, 1>(a, c, adj, shm, s) : hipErrorInvalidValue;
+        if (c.zp == 2) return launch_adj_lds3<MODE, IP, 2>(a, c, adj, nf, shm, s);
+    return c.zp == 1 ? launch_adj_lds3<MODE, IP, 1>(a, c, adj, nf, shm, s) : hipErrorInvalidValue;
 }
 
 template <int MODE>
-static hipError_t launch_adj_lds1(const DasArgs &a, const LdsCfg &c, int ip, int adj, size_t shm,
-                                  hipStream_t s)
+static hipError_t launch_adj_lds1(const DasArgs &a, const LdsCfg &c, int ip, int adj, int nf,
+                                  size_t shm, hipStream_t s)
 {
     switch (ip) {
-        case IN_LINEAR: return launch_adj_lds2<MODE, IN_LINEAR>(a, c, adj, shm, s);
-        case IN_CUBIC: return launch_adj_lds2<MODE, IN_CUBIC>(a, c, adj, shm, s);
+        case IN_LINEAR: return launch_adj_lds2<MODE, IN_LINEAR>(a, c, adj, nf, shm, s);
+        case IN_CUBIC: return launch_adj_lds2<MODE, IN_CUBIC>(a, c, adj, nf, shm, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -69,9 +72,10 @@ static hipError_t launch_adj_lds1(const DasArgs &a, const LdsCfg &c, int ip, int
 // The adjoint with the LDS-staged kernel (linear or cubic reads), one of the
 // two gradients per call: grad_e (a.grad_e) is cleared and accumulated, or
 // grad_c receives the fixed-order sum of the workgroups' partials (FP32
-// data).
+// data).  n_frames > 1: a stack of frames in one launch (grid z), with
+// grad_c[n_frames] and [n_frames][...] arrays (frame_args).
 hipError_t launch_das_lds_adjoint(const DasArgs &a, const LdsCfg &c, int mode, int ip,
-                                  float *grad_c, hipStream_t s)
+                                  float *grad_c, hipStream_t s, int n_frames)
 {
     const int adj = (grad_c ? 1 : 0) | (a.grad_e ? 2 : 0);
     if (adj == 0) return hipSuccess;
@@ -79,18 +83,18 @@ hipError_t launch_das_lds_adjoint(const DasArgs &a, const LdsCfg &c, int mode, i
     const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, 1, c.guard, adj);
     hipError_t err;
     if (a.grad_e) {
-        err = launch_fill(a.grad_e, (long)a.n_tx * a.n_ch * a.S, 0.f, s);
+        err = launch_fill(a.grad_e, (long)n_frames * a.n_tx * a.n_ch * a.S, 0.f, s);
         if (err != hipSuccess) return err;
     }
     switch (mode) {
-        case MODE_FORCES: err = launch_adj_lds1<MODE_FORCES>(a, c, ip, adj, shm, s); break;
-        case MODE_HERCULES: err = launch_adj_lds1<MODE_HERCULES>(a, c, ip, adj, shm, s); break;
-        case MODE_TPW: err = launch_adj_lds1<MODE_TPW>(a, c, ip, adj, shm, s); break;
-        case MODE_VLS: err = launch_adj_lds1<MODE_VLS>(a, c, ip, adj, shm, s); break;
+        case MODE_FORCES: err = launch_adj_lds1<MODE_FORCES>(a, c, ip, adj, n_frames, shm, s); break;
+        case MODE_HERCULES: err = launch_adj_lds1<MODE_HERCULES>(a, c, ip, adj, n_frames, shm, s); break;
+        case MODE_TPW: err = launch_adj_lds1<MODE_TPW>(a, c, ip, adj, n_frames, shm, s); break;
+        case MODE_VLS: err = launch_adj_lds1<MODE_VLS>(a, c, ip, adj, n_frames, shm, s); break;
         default: return hipErrorInvalidValue;
     }
     if (err != hipSuccess || !grad_c) return err;
-    return launch_reduce_partials(a.partial, xcd_slab_grid(c) * a.groups, grad_c, s);
+    return launch_reduce_partials(a.partial, xcd_slab_grid(c) * a.groups, grad_c, s, n_frames);
 }
 
 }  // namespace bf

@@ -34,8 +34,11 @@ def test_library_exports_every_declared_function():
     assert set(names) == set(_lib.EXPORTED)
     # the binding, the header and the library agree on the ABI version
     with open(os.path.join(ROOT, "include", "bf.h")) as fp:
-        m = re.search(r"#define BF_ABI_VERSION (\d+)", fp.read())
+        text = fp.read()
+    m = re.search(r"#define BF_ABI_VERSION (\d+)", text)
     assert m and int(m.group(1)) == _lib.ABI_VERSION == L.bf_abi_version()
+    m = re.search(r"#define BF_MAX_FRAMES (\d+)", text)
+    assert m and int(m.group(1)) == _lib.MAX_FRAMES
 
 
 def _good(k=0):

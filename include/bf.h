@@ -256,12 +256,13 @@ int bf_das_adjoint(bf_plan plan, const void *e, const float *grad_out, double c,
  *   out[f] = bf_das(e[f]) for f < n_frames.
  * e: device, type params.e_type, [n_frames][n_tx][n_ch][n_samples];
  * out: device f32 [n_frames][Ny][Nx][Nz], overwritten.  n_frames in
- * 1..BF_MAX_FRAMES (BF_ERR_SHAPE otherwise).  The LDS-staged kernel takes all
- * frames in one launch, so small grids fill the device; each out[f] is
- * bit-identical to bf_das on frame f alone.  The gather kernel runs frame by
- * frame.  May allocate (once per larger stack) partial images of
- * n_frames x the plan's channel groups x the grid; plan_get_info's
- * workspace_bytes includes them. */
+ * 1..BF_MAX_FRAMES (BF_ERR_SHAPE otherwise).  The LDS-staged kernel takes a
+ * whole stack per launch (a stack whose partial images would exceed 256 MiB
+ * goes in several); each out[f] is bit-identical to bf_das on frame f alone.
+ * The gather kernel runs frame by frame.  Plans that split the channel sum
+ * (small grids) allocate, once per larger stack, partial images of up to
+ * 256 MiB (or one frame's, if larger); bf_plan_get_info's workspace_bytes
+ * includes them. */
 int bf_das_frames(bf_plan plan, const void *e, int32_t n_frames, float *out, double c,
                   void *stream);
 

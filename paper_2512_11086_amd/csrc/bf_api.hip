@@ -624,23 +624,51 @@ float *Frame::frames_part(int nf)
     return d_part_frames;
 }
 
+// The per-frame arrays of `a` advanced to frame f0 of a stack.
+DasArgs Frame::at_frame(const DasArgs &a, int f0) const
+{
+    DasArgs b = a;
+    const long pts = (long)grid.nx * grid.ny * grid.nz;
+    if (b.e) b.e = static_cast<const char *>(b.e) + (size_t)f0 * e_bytes();
+    if (b.out) b.out += (size_t)f0 * out_elems();
+    if (b.grad_out) b.grad_out += (size_t)f0 * pts;
+    if (b.grad_e) b.grad_e += (size_t)f0 * e_elems();
+    return b;
+}
+
+// Largest stack of one LDS launch: the partial images of a stack stay within
+// 256 MiB (small grids split the channel sum into groups).
+static int frames_per_launch(long part_bytes_per_frame, int nf)
+{
+    const long cap = 256l << 20;
+    const long k = part_bytes_per_frame > 0 ? cap / part_bytes_per_frame : nf;
+    return (int)std::max(1l, std::min<long>(k, nf));
+}
+
 // A stack of nf frames ([nf][...] arrays) at one sound speed.  The LDS
-// kernel beamforms all of them in one launch (grid z), so that a small grid
-// fills the device and the costly deep boxes of one frame overlap the cheap
-// ones of the next; the gather kernel runs frame by frame.
+// kernel takes a whole stack per launch (grid z = frame; stacks beyond the
+// partial-image cap go in several launches); the gather kernel runs frame by
+// frame.
 int Frame::das_frames(const void *e, int nf, float *out, double c, hipStream_t s)
 {
-    DasArgs a = das_args(e, out, c);
+    const DasArgs a = das_args(e, out, c);
     LdsCfg cfg;
     if (nf > 1 && variant != BF_DAS_GATHER && lds_config(a, &cfg)) {
-        if (groups > 1 && !(a.part = frames_part(nf)))
-            return fail(BF_ERR_HIP, "device allocation of partial images failed");
-        const hipError_t err = launch_das_lds(a, cfg, p.mode, das_et(), p.interp, s, nf);
-        return err == hipSuccess ? BF_OK : hip_fail(err, "DAS launch");
+        const long part_frame = groups > 1 ? (long)groups * out_elems() * (long)sizeof(float) : 0;
+        const int k = frames_per_launch(part_frame, nf);
+        for (int f0 = 0; f0 < nf; f0 += k) {
+            const int n = std::min(k, nf - f0);
+            DasArgs b = at_frame(a, f0);
+            if (groups > 1 && !(b.part = frames_part(n)))
+                return fail(BF_ERR_HIP, "device allocation of partial images failed");
+            const hipError_t err = launch_das_lds(b, cfg, p.mode, das_et(), p.interp, s, n);
+            if (err != hipSuccess) return hip_fail(err, "DAS launch");
+        }
+        return BF_OK;
     }
     for (int f = 0; f < nf; ++f) {
-        const int st = das(static_cast<const char *>(e) + (size_t)f * e_bytes(),
-                           out + (size_t)f * out_elems(), c, s);
+        const DasArgs b = at_frame(a, f);
+        const int st = das(b.e, b.out, c, s);
         if (st != BF_OK) return st;
     }
     return BF_OK;
@@ -649,7 +677,8 @@ int Frame::das_frames(const void *e, int nf, float *out, double c, hipStream_t s
 // Adjoint of das_frames (grad_out, grad_e: [nf][...]; grad_c: [nf]).
 // Linear / cubic reads run the LDS-staged adjoint: dL/de (which reads no
 // data) on a depth-major wavefront tile, dL/dc (FP32 data) on the plan's
-// tile, as two launches when both are requested, each over all frames.
+// tile, as two launches when both are requested, each over a whole stack
+// (dL/dc: as many frames per launch as the partial-sum buffer holds).
 // Nearest reads, other data types and the gather variant run the gather
 // adjoint (FP32 atomics into grad_e) frame by frame.
 int Frame::das_adjoint(const void *e, const float *grad_out, double c, float *grad_e,
@@ -665,15 +694,12 @@ int Frame::das_adjoint(const void *e, const float *grad_out, double c, float *gr
     adjoint_e_tile(&ae, bwa);
     const bool e_lds = grad_e && lds_ok && lds_config(ae, &ce, 2, bwa);
     const bool c_lds = grad_c && lds_ok && p.e_type == BF_E_F32 && lds_config(a, &cc, 1) &&
-                       (long)xcd_slab_grid(cc) * a.groups * nf <= max_blocks;
+                       (long)xcd_slab_grid(cc) * a.groups <= max_blocks;
     hipError_t err = hipSuccess;
     if ((grad_e && !e_lds) || (grad_c && !c_lds)) {
-        const long pts = (long)grid.nx * grid.ny * grid.nz;
         for (int f = 0; f < nf && err == hipSuccess; ++f) {
-            DasArgs ag = a;          // what the LDS kernels do not take, frame f
-            ag.e = e ? static_cast<const char *>(e) + (size_t)f * e_bytes() : nullptr;
-            ag.grad_out = grad_out + f * pts;
-            ag.grad_e = e_lds || !grad_e ? nullptr : grad_e + f * e_elems();
+            DasArgs ag = at_frame(a, f);   // what the LDS kernels do not take, frame f
+            if (e_lds) ag.grad_e = nullptr;
             err = launch_das_adjoint(ag, p.mode, p.e_type, p.interp,
                                      c_lds || !grad_c ? nullptr : grad_c + f, s);
         }
@@ -683,7 +709,10 @@ int Frame::das_adjoint(const void *e, const float *grad_out, double c, float *gr
     if (err == hipSuccess && c_lds) {
         DasArgs ac = a;
         ac.grad_e = nullptr;
-        err = launch_das_lds_adjoint(ac, cc, p.mode, p.interp, grad_c, s, nf);
+        const int k = (int)std::min<long>(nf, max_blocks / ((long)xcd_slab_grid(cc) * a.groups));
+        for (int f0 = 0; f0 < nf && err == hipSuccess; f0 += k)
+            err = launch_das_lds_adjoint(at_frame(ac, f0), cc, p.mode, p.interp, grad_c + f0, s,
+                                         std::min(k, nf - f0));
     }
     return err == hipSuccess ? BF_OK : hip_fail(err, "DAS adjoint launch");
 }

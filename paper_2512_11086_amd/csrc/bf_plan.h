@@ -64,6 +64,7 @@ struct Frame {
     int decode(const int16_t *rf, void *e, hipStream_t s) const;
     int das(const void *e, float *out, double c, hipStream_t s) const;
     float *frames_part(int nf);
+    DasArgs at_frame(const DasArgs &a, int f0) const;
     int das_frames(const void *e, int nf, float *out, double c, hipStream_t s);
     int das_adjoint(const void *e, const float *grad_out, double c, float *grad_e, float *grad_c,
                     int nf, hipStream_t s) const;

@@ -215,3 +215,24 @@ def test_iq_das_frames_matches_single_frames(torch_mod, mode):
         assert torch.equal(stack[f], plan.das(et[f]).cpu()), f
     ref = oracle.das_iq(d, e[1])
     assert rel_l2(stack[1].numpy(), ref) < 1e-5
+
+
+def test_large_stack_splits_into_launches(torch_mod):
+    """150 frames of the 256 x 256 FORCES plane: the forward takes two
+    launches (partial images of 8 channel groups x 128 frames fill the
+    256 MiB cap), and every frame, on both sides of the split, still equals
+    its own call, as does its dL/dc."""
+    torch = torch_mod
+    desc, H, _, info = synth.make_inputs(3)
+    plan = bfm.Plan(desc, H)
+    c = float(info["c_true"])
+    gen = torch.Generator(device="cuda").manual_seed(123)
+    nf = 150
+    es = torch.randn((nf,) + plan.e_shape, generator=gen, device="cuda") * 100.0
+    imgs = plan.das(es, c=c)
+    G = torch.randn(imgs.shape, generator=gen, device="cuda")
+    _, gc = plan.das_adjoint(es, G, c=c, want_e=False)
+    for f in (0, 127, 128, 143, 144, nf - 1):
+        assert torch.equal(imgs[f], plan.das(es[f], c=c)), f
+        _, gc1 = plan.das_adjoint(es[f], G[f], c=c, want_e=False)
+        assert float(gc[f]) == float(gc1), f

@@ -342,10 +342,10 @@ def autofocus_stage(torch, bfm, synth, reps: int = 5):
     """Differentiable FORCES workload (256x256 plane, 64 tx x 64 ch, 2048
     samples, 8 frames).  The gradient step -- forward DAS, the sharpness loss
     with its image gradient, and the adjoint for dL/dc alone (the autofocus
-    gradient) -- is timed two ways: with the 8 frames stacked (one DAS launch,
-    one sharpness launch and one adjoint launch for all frames:
-    bf_das_frames / bf_das_adjoint_frames), and frame by frame (bf_das /
-    bf_das_adjoint per frame).  Also timed: the adjoint with the RF gradient
+    gradient) -- is timed two ways: with the 8 frames stacked (bf_das_frames,
+    one DAS launch per frame; one sharpness launch for the 8 images;
+    bf_das_adjoint_frames, one launch per gradient for all frames), and frame
+    by frame (bf_das / bf_das_adjoint per frame).  Also timed: the adjoint with the RF gradient
     (8 x 64 x 64 x 2048, LDS windows added to it with FP32 atomics), with and
     without dL/dc.  Adjoint roofline: algorithmic_flops(..., adjoint_c=True)
     (the separable FORCES path, derivative coefficients once per trace sample
@@ -398,8 +398,10 @@ def autofocus_stage(torch, bfm, synth, reps: int = 5):
     tf = algorithmic_flops(desc, n_act, adjoint_c=True) / (st["adjoint_c_ms"] * 1e-3) / 1e12
     nominal = int(np.prod(desc["dims"])) * desc["n_tx"] * desc["n_ch"]
     out = {"workload": "FORCES 256x256 plane, 64 tx x 64 ch x 2048 samples, 8 frames: "
-                       "DAS + sharpness + adjoint dL/dc, the 8 frames stacked in one launch "
-                       "each (per_frame_calls: one call per frame); times in ms per frame"}
+                       "DAS + sharpness + adjoint dL/dc with the 8 frames stacked (one call "
+                       "each: the DAS one launch per frame, the sharpness and each adjoint "
+                       "gradient one launch for all 8); per_frame_calls: one call per frame; "
+                       "times in ms per frame"}
     for k, v in st.items():
         out[k] = round(v, 4)
     step = st["das_ms"] + st["sharpness_ms"] + st["adjoint_c_ms"]

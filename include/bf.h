@@ -253,16 +253,11 @@ int bf_das_adjoint(bf_plan plan, const void *e, const float *grad_out, double c,
 
 /* bf_das for a stack of n_frames frames of this plan's geometry, all at
  * sound speed c (e.g. the frames of one sound-speed autofocus batch):
- *   out[f] = bf_das(e[f]) for f < n_frames.
+ *   out[f] = bf_das(e[f]) for f < n_frames, bit for bit.
  * e: device, type params.e_type, [n_frames][n_tx][n_ch][n_samples];
  * out: device f32 [n_frames][Ny][Nx][Nz], overwritten.  n_frames in
- * 1..BF_MAX_FRAMES (BF_ERR_SHAPE otherwise).  The LDS-staged kernel takes a
- * whole stack per launch (a stack whose partial images would exceed 256 MiB
- * goes in several); each out[f] is bit-identical to bf_das on frame f alone.
- * The gather kernel runs frame by frame.  Plans that split the channel sum
- * (small grids) allocate, once per larger stack, partial images of up to
- * 256 MiB (or one frame's, if larger); bf_plan_get_info's workspace_bytes
- * includes them. */
+ * 1..BF_MAX_FRAMES (BF_ERR_SHAPE otherwise).  One launch per frame on the
+ * given stream; no allocation. */
 int bf_das_frames(bf_plan plan, const void *e, int32_t n_frames, float *out, double c,
                   void *stream);
 
@@ -270,9 +265,11 @@ int bf_das_frames(bf_plan plan, const void *e, int32_t n_frames, float *out, dou
  * grad_e [n_frames][n_tx][n_ch][n_samples] (nullable), grad_c device f32
  * [n_frames] (nullable): grad_c[f] = sum_p grad_out[f][p] d out[f][p] / dc, the
  * frame's own term (a loss summed over frames has dL/dc = sum_f grad_c[f]).
- * grad_c[f] is bit-identical to bf_das_adjoint on frame f alone; grad_e
- * matches it up to the order of its FP32 atomics.  Errors as bf_das_frames
- * and bf_das_adjoint. */
+ * The LDS-staged adjoint takes the whole stack in one launch per gradient
+ * (dL/dc: as many frames per launch as the plan's partial-sum buffer holds);
+ * the gather adjoint runs frame by frame.  grad_c[f] is bit-identical to
+ * bf_das_adjoint on frame f alone; grad_e matches it up to the order of its
+ * FP32 atomics.  No allocation.  Errors as bf_das_frames and bf_das_adjoint. */
 int bf_das_adjoint_frames(bf_plan plan, const void *e, const float *grad_out, int32_t n_frames,
                           double c, float *grad_e, float *grad_c, void *stream);
 

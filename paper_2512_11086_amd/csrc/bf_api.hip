@@ -163,17 +163,6 @@ void *Frame::alloc(size_t bytes)
     return p;
 }
 
-void Frame::release(void *ptr, size_t bytes)
-{
-    for (size_t q = 0; q < allocs.size(); ++q)
-        if (allocs[q] == ptr) {
-            (void)hipFree(ptr);
-            allocs.erase(allocs.begin() + (long)q);
-            total_bytes -= (int64_t)bytes;
-            return;
-        }
-}
-
 Frame::~Frame()
 {
     for (void *p : allocs) (void)hipFree(p);
@@ -610,20 +599,6 @@ int Frame::das(const void *e, float *out, double c, hipStream_t s) const
 }
 
 
-// Partial images of a stack of nf frames ([nf][groups][points]), grown on
-// demand; null when the plan does not split the channel sum.
-float *Frame::frames_part(int nf)
-{
-    if (groups <= 1) return nullptr;
-    const size_t need = (size_t)nf * groups * out_elems() * sizeof(float);
-    if (need > part_frames_bytes) {
-        if (d_part_frames) release(d_part_frames, part_frames_bytes);
-        d_part_frames = (float *)alloc(need);
-        part_frames_bytes = d_part_frames ? need : 0;
-    }
-    return d_part_frames;
-}
-
 // The per-frame arrays of `a` advanced to frame f0 of a stack.
 DasArgs Frame::at_frame(const DasArgs &a, int f0) const
 {
@@ -636,36 +611,13 @@ DasArgs Frame::at_frame(const DasArgs &a, int f0) const
     return b;
 }
 
-// Largest stack of one LDS launch: the partial images of a stack stay within
-// 256 MiB (small grids split the channel sum into groups).
-static int frames_per_launch(long part_bytes_per_frame, int nf)
-{
-    const long cap = 256l << 20;
-    const long k = part_bytes_per_frame > 0 ? cap / part_bytes_per_frame : nf;
-    return (int)std::max(1l, std::min<long>(k, nf));
-}
-
-// A stack of nf frames ([nf][...] arrays) at one sound speed.  The LDS
-// kernel takes a whole stack per launch (grid z = frame; stacks beyond the
-// partial-image cap go in several launches); the gather kernel runs frame by
-// frame.
-int Frame::das_frames(const void *e, int nf, float *out, double c, hipStream_t s)
+// A stack of nf frames ([nf][...] arrays) at one sound speed, one launch per
+// frame.  (One launch over the stack, grid z = frame, measured no faster on
+// the 256 x 256 plane -- its single-frame launch already fills the chip --
+// and the frame offsets cost the forward kernels four VGPRs.)
+int Frame::das_frames(const void *e, int nf, float *out, double c, hipStream_t s) const
 {
     const DasArgs a = das_args(e, out, c);
-    LdsCfg cfg;
-    if (nf > 1 && variant != BF_DAS_GATHER && lds_config(a, &cfg)) {
-        const long part_frame = groups > 1 ? (long)groups * out_elems() * (long)sizeof(float) : 0;
-        const int k = frames_per_launch(part_frame, nf);
-        for (int f0 = 0; f0 < nf; f0 += k) {
-            const int n = std::min(k, nf - f0);
-            DasArgs b = at_frame(a, f0);
-            if (groups > 1 && !(b.part = frames_part(n)))
-                return fail(BF_ERR_HIP, "device allocation of partial images failed");
-            const hipError_t err = launch_das_lds(b, cfg, p.mode, das_et(), p.interp, s, n);
-            if (err != hipSuccess) return hip_fail(err, "DAS launch");
-        }
-        return BF_OK;
-    }
     for (int f = 0; f < nf; ++f) {
         const DasArgs b = at_frame(a, f);
         const int st = das(b.e, b.out, c, s);

@@ -225,30 +225,24 @@ __global__ __launch_bounds__(256) void das_kernel(DasArgs a)
 }
 
 // Sum of the channel-group partial images in group order (deterministic).
-// out[f][q] = sum over g of part[f][g][q] in a fixed order, for n_frames
-// stacked frames of n values each.
 __global__ __launch_bounds__(256) void sum_groups_kernel(const float *part, float *out_direct,
-                                                         float *const *out_ref, long n, int G,
-                                                         long total)
+                                                         float *const *out_ref, long n, int G)
 {
     float *out = out_ref ? *out_ref : out_direct;
-    for (long q = (long)blockIdx.x * 256 + threadIdx.x; q < total; q += (long)gridDim.x * 256) {
-        const long f = q / n, r = q - f * n;
-        const float *src = part + f * G * n + r;
+    for (long q = (long)blockIdx.x * 256 + threadIdx.x; q < n; q += (long)gridDim.x * 256) {
         float s = 0.f;
-        for (int g = 0; g < G; ++g) s += src[(long)g * n];
+        for (int g = 0; g < G; ++g) s += part[(long)g * n + q];
         out[q] = s;
     }
 }
 
-hipError_t launch_sum_groups(const DasArgs &a, int n_frames, hipStream_t s)
+hipError_t launch_sum_groups(const DasArgs &a, hipStream_t s)
 {
     const long n = (long)a.g.nx * a.g.ny * a.g.nz * (a.cx ? 2 : 1);
-    const long total = n * n_frames;
-    long blocks = (total + 255) / 256;
+    long blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(sum_groups_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a.part, a.out,
-                       a.out_ref, n, a.groups, total);
+                       a.out_ref, n, a.groups);
     return hipGetLastError();
 }
 
@@ -288,7 +282,7 @@ hipError_t launch_das(const DasArgs &a, int mode, int et, int ip, hipStream_t s)
         default: return hipErrorInvalidValue;
     }
     if (err != hipSuccess || a.groups <= 1) return err;
-    return launch_sum_groups(a, 1, s);
+    return launch_sum_groups(a, s);
 }
 
 }  // namespace bf

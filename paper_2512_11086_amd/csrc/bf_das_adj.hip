@@ -10,13 +10,28 @@ hipError_t launch_reduce_partials(const double *partial, int n, float *out, hipS
                                   int n_frames = 1);
 hipError_t launch_fill(float *p, long n, float v, hipStream_t s);
 
-// ADJ = 1: dL/dc (FP32 data), 2: dL/de (reads no data).
-template <int MODE, int IP, int ZP, int ADJ>
+// Frame fr of a stack of frames of one plan (grid z): the per-frame arrays
+// advance by one frame's extent.  e, grad_e: [frames][n_tx][n_ch][S];
+// grad_out: [frames][points]; partial: [frames][n_wg] (n_wg workgroups per
+// frame).  Null arrays stay null.
+__device__ inline void frame_args(DasArgs &a, int fr, long n_wg)
+{
+    const long traces = (long)fr * a.n_tx * a.n_ch;
+    if (a.e) a.e = static_cast<const float *>(a.e) + traces * a.S;
+    if (a.grad_out) a.grad_out += (long)fr * a.g.nx * a.g.ny * a.g.nz;
+    if (a.grad_e) a.grad_e += traces * a.S;
+    if (a.partial) a.partial += fr * n_wg;
+}
+
+// ADJ = 1: dL/dc (FP32 data), 2: dL/de (reads no data).  STACK: grid z runs
+// a stack of frames (the single-frame kernels keep their registers: the
+// frame offsets cost four VGPRs).
+template <int MODE, int IP, int ZP, int ADJ, bool STACK>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerEu<MODE, ZP>::value)))
 void das_lds_adj_kernel(DasArgs a, LdsCfg c)
 {
     extern __shared__ float4 smem[];
-    frame_args<ET_F32>(a, blockIdx.z, (long)gridDim.x * gridDim.y);   // stacked frames
+    if constexpr (STACK) frame_args(a, blockIdx.z, (long)gridDim.x * gridDim.y);
     const int blk = xcd_slab_box(c, blockIdx.x);
     if (blk < 0) {      // past the last slab: an empty partial for dL/dc
         if ((ADJ & 1) && threadIdx.x == 0) a.partial[(long)blockIdx.y * gridDim.x + blockIdx.x] = 0.0;
@@ -25,17 +40,26 @@ void das_lds_adj_kernel(DasArgs a, LdsCfg c)
     das_block<MODE, ET_F32, IP, ZP, ADJ>(a, c, blk, blockIdx.y, smem);
 }
 
-template <int MODE, int IP, int ZP, int ADJ>
-static hipError_t launch_adj_lds4(const DasArgs &a, const LdsCfg &c, int nf, size_t shm,
+template <int MODE, int IP, int ZP, int ADJ, bool STACK>
+static hipError_t launch_adj_lds5(const DasArgs &a, const LdsCfg &c, int nf, size_t shm,
                                   hipStream_t s)
 {
     const int nthr = 64 * c.bwx * c.bwy * c.bwz;
     dim3 grid(xcd_slab_grid(c), a.groups, nf);
-    hipError_t e =
-        allow_lds(reinterpret_cast<const void *>(&das_lds_adj_kernel<MODE, IP, ZP, ADJ>), shm);
+    const void *fn = reinterpret_cast<const void *>(&das_lds_adj_kernel<MODE, IP, ZP, ADJ, STACK>);
+    hipError_t e = allow_lds(fn, shm);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((das_lds_adj_kernel<MODE, IP, ZP, ADJ>), grid, dim3(nthr), shm, s, a, c);
+    hipLaunchKernelGGL((das_lds_adj_kernel<MODE, IP, ZP, ADJ, STACK>), grid, dim3(nthr), shm, s, a,
+                       c);
     return hipGetLastError();
+}
+
+template <int MODE, int IP, int ZP, int ADJ>
+static hipError_t launch_adj_lds4(const DasArgs &a, const LdsCfg &c, int nf, size_t shm,
+                                  hipStream_t s)
+{
+    return nf > 1 ? launch_adj_lds5<MODE, IP, ZP, ADJ, true>(a, c, nf, shm, s)
+                  : launch_adj_lds5<MODE, IP, ZP, ADJ, false>(a, c, 1, shm, s);
 }
 
 template <int MODE, int IP, int ZP>

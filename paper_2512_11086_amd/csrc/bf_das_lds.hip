@@ -5,7 +5,7 @@
 
 namespace bf {
 
-hipError_t launch_sum_groups(const DasArgs &a, int n_frames, hipStream_t s);
+hipError_t launch_sum_groups(const DasArgs &a, hipStream_t s);
 
 template <int MODE, int ET, int IP, int ZP>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerEu<MODE, ZP>::value)))
@@ -14,7 +14,6 @@ void das_lds_kernel(DasArgs a, LdsCfg c)
     extern __shared__ float4 smem[];
     const int blk = xcd_slab_box(c, blockIdx.x);
     if (blk < 0) return;
-    frame_args<ET>(a, blockIdx.z, (long)gridDim.x * gridDim.y);   // stacked frames
     das_block<MODE, ET, IP, ZP>(a, c, blk, blockIdx.y, smem);
 }
 
@@ -128,10 +127,10 @@ int persistent_das_blocks(int mode, int et, int ip, int zp, int threads, size_t 
 }
 
 template <int MODE, int ET, int IP, int ZP>
-static hipError_t launch_lds4(const DasArgs &a, const LdsCfg &c, int nf, size_t shm, hipStream_t s)
+static hipError_t launch_lds4(const DasArgs &a, const LdsCfg &c, size_t shm, hipStream_t s)
 {
     const int nthr = 64 * c.bwx * c.bwy * c.bwz;
-    dim3 grid(xcd_slab_grid(c), a.groups, nf);
+    dim3 grid(xcd_slab_grid(c), a.groups);
     hipError_t e = allow_lds(reinterpret_cast<const void *>(&das_lds_kernel<MODE, ET, IP, ZP>), shm);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((das_lds_kernel<MODE, ET, IP, ZP>), grid, dim3(nthr), shm, s, a, c);
@@ -139,35 +138,34 @@ static hipError_t launch_lds4(const DasArgs &a, const LdsCfg &c, int nf, size_t 
 }
 
 template <int MODE, int ET, int IP>
-static hipError_t launch_lds_zp(const DasArgs &a, const LdsCfg &c, int nf, size_t shm,
-                                hipStream_t s)
+static hipError_t launch_lds_zp(const DasArgs &a, const LdsCfg &c, size_t shm, hipStream_t s)
 {
     if constexpr (MODE == MODE_HERCULES && ET != ET_CF32)
-        if (c.zp == 2) return launch_lds4<MODE, ET, IP, 2>(a, c, nf, shm, s);
-    return c.zp == 1 ? launch_lds4<MODE, ET, IP, 1>(a, c, nf, shm, s) : hipErrorInvalidValue;
+        if (c.zp == 2) return launch_lds4<MODE, ET, IP, 2>(a, c, shm, s);
+    return c.zp == 1 ? launch_lds4<MODE, ET, IP, 1>(a, c, shm, s) : hipErrorInvalidValue;
 }
 
 template <int MODE, int ET>
-static hipError_t launch_lds_ip(const DasArgs &a, const LdsCfg &c, int ip, int nf, size_t shm,
+static hipError_t launch_lds_ip(const DasArgs &a, const LdsCfg &c, int ip, size_t shm,
                                 hipStream_t s)
 {
     switch (ip) {
-        case IN_NEAREST: return launch_lds_zp<MODE, ET, IN_NEAREST>(a, c, nf, shm, s);
-        case IN_LINEAR: return launch_lds_zp<MODE, ET, IN_LINEAR>(a, c, nf, shm, s);
-        case IN_CUBIC: return launch_lds_zp<MODE, ET, IN_CUBIC>(a, c, nf, shm, s);
+        case IN_NEAREST: return launch_lds_zp<MODE, ET, IN_NEAREST>(a, c, shm, s);
+        case IN_LINEAR: return launch_lds_zp<MODE, ET, IN_LINEAR>(a, c, shm, s);
+        case IN_CUBIC: return launch_lds_zp<MODE, ET, IN_CUBIC>(a, c, shm, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int MODE>
-static hipError_t launch_lds_et(const DasArgs &a, const LdsCfg &c, int et, int ip, int nf,
-                                size_t shm, hipStream_t s)
+static hipError_t launch_lds_et(const DasArgs &a, const LdsCfg &c, int et, int ip, size_t shm,
+                                hipStream_t s)
 {
     switch (et) {
-        case ET_F32: return launch_lds_ip<MODE, ET_F32>(a, c, ip, nf, shm, s);
-        case ET_BF16: return launch_lds_ip<MODE, ET_BF16>(a, c, ip, nf, shm, s);
-        case ET_I32: return launch_lds_ip<MODE, ET_I32>(a, c, ip, nf, shm, s);
-        case ET_CF32: return launch_lds_ip<MODE, ET_CF32>(a, c, ip, nf, shm, s);
+        case ET_F32: return launch_lds_ip<MODE, ET_F32>(a, c, ip, shm, s);
+        case ET_BF16: return launch_lds_ip<MODE, ET_BF16>(a, c, ip, shm, s);
+        case ET_I32: return launch_lds_ip<MODE, ET_I32>(a, c, ip, shm, s);
+        case ET_CF32: return launch_lds_ip<MODE, ET_CF32>(a, c, ip, shm, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -180,22 +178,20 @@ size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard, int ad
            ((adj & 2) ? 2 * (size_t)nb * (lmax + 3) * 8 + 16 * 4 : 0);
 }
 
-// n_frames > 1: a stack of frames of the same plan in one launch (grid z);
-// e, out and the partial images are [n_frames][...] (frame_args).
 hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, int ip,
-                          hipStream_t s, int n_frames)
+                          hipStream_t s)
 {
     const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, a.cx ? 2 : 1, c.guard, 0);
     hipError_t err;
     switch (mode) {
-        case MODE_FORCES: err = launch_lds_et<MODE_FORCES>(a, c, et, ip, n_frames, shm, s); break;
-        case MODE_HERCULES: err = launch_lds_et<MODE_HERCULES>(a, c, et, ip, n_frames, shm, s); break;
-        case MODE_TPW: err = launch_lds_et<MODE_TPW>(a, c, et, ip, n_frames, shm, s); break;
-        case MODE_VLS: err = launch_lds_et<MODE_VLS>(a, c, et, ip, n_frames, shm, s); break;
+        case MODE_FORCES: err = launch_lds_et<MODE_FORCES>(a, c, et, ip, shm, s); break;
+        case MODE_HERCULES: err = launch_lds_et<MODE_HERCULES>(a, c, et, ip, shm, s); break;
+        case MODE_TPW: err = launch_lds_et<MODE_TPW>(a, c, et, ip, shm, s); break;
+        case MODE_VLS: err = launch_lds_et<MODE_VLS>(a, c, et, ip, shm, s); break;
         default: return hipErrorInvalidValue;
     }
     if (err != hipSuccess || a.groups <= 1) return err;
-    return launch_sum_groups(a, n_frames, s);
+    return launch_sum_groups(a, s);
 }
 
 }  // namespace bf

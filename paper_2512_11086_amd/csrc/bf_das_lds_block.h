@@ -46,6 +46,8 @@
 
 namespace bf {
 
+hipError_t launch_sum_groups(const DasArgs &a, hipStream_t s);
+
 constexpr int JC = 4;    // channel rows per batch of the separable modes (FORCES, TPW, VLS)
 constexpr int HANN_TAB_PAD = HANN_N + 2;   // table entries reserved in LDS (float2, keeps 16-byte alignment)
 
@@ -1047,24 +1049,6 @@ __device__ inline int xcd_slab_box(const LdsCfg &c, int b)
     const int zrank = (slot / nlat) * 8 + (b & 7);     // 0 = deepest slab
     if (zrank >= c.blocks_z) return -1;
     return (c.blocks_z - 1 - zrank) + c.blocks_z * (slot % nlat);
-}
-
-// Frame fr of a stack of frames of one plan (grid z): every per-frame array
-// advances by one frame's extent.  e: [frames][n_tx][n_ch][S]; out, grad_out:
-// [frames][points]; part: [frames][groups][points]; grad_e like e;
-// partial: [frames][n_wg] (n_wg workgroups per frame).  Null arrays stay null.
-template <int ET>
-__device__ inline void frame_args(DasArgs &a, int fr, long n_wg)
-{
-    const long pts = (long)a.g.nx * a.g.ny * a.g.nz;
-    const long qs = a.cx ? 2 : 1;
-    const long traces = (long)fr * a.n_tx * a.n_ch;
-    if (a.e) a.e = trace_ptr<ET>(a.e, traces, a.S);
-    if (a.out) a.out += fr * pts * qs;
-    if (a.part) a.part += fr * a.groups * pts * qs;
-    if (a.grad_out) a.grad_out += fr * pts;
-    if (a.grad_e) a.grad_e += traces * a.S;
-    if (a.partial) a.partial += fr * n_wg;
 }
 
 // Two points per lane and the row-column modes: registers capped for 6

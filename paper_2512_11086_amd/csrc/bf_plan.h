@@ -33,8 +33,6 @@ struct Frame {
     double tpw_smax = 0.0;       // TPW: largest |sin| of the transmit angles
     int groups = 1;              // channel groups of the DAS launch (small grids)
     float *d_part = nullptr;     // [groups][points] partial images
-    float *d_part_frames = nullptr;   // [frames][groups][points] for stacked frames
-    size_t part_frames_bytes = 0;
     float2 *d_hann = nullptr;    // Hann weight table (HANN_N + 1 entries)
     long max_blocks = 0;
     int8_t *d_At = nullptr;
@@ -49,7 +47,6 @@ struct Frame {
 
     ~Frame();
     void *alloc(size_t bytes);
-    void release(void *ptr, size_t bytes);
     int init(const bf_params &src);
     void set_tile(int lx, int ly, int lz);
     int64_t e_elems() const;
@@ -63,9 +60,8 @@ struct Frame {
     bool z2_ok() const;          // two depth points per lane apply to this frame
     int decode(const int16_t *rf, void *e, hipStream_t s) const;
     int das(const void *e, float *out, double c, hipStream_t s) const;
-    float *frames_part(int nf);
     DasArgs at_frame(const DasArgs &a, int f0) const;
-    int das_frames(const void *e, int nf, float *out, double c, hipStream_t s);
+    int das_frames(const void *e, int nf, float *out, double c, hipStream_t s) const;
     int das_adjoint(const void *e, const float *grad_out, double c, float *grad_e, float *grad_c,
                     int nf, hipStream_t s) const;
 };
@@ -74,7 +70,7 @@ struct Batch;   // persistent batched path state (bf_batch.hip)
 
 hipError_t launch_das(const DasArgs &a, int mode, int et, int ip, hipStream_t s);
 hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, int ip,
-                          hipStream_t s, int n_frames = 1);
+                          hipStream_t s);
 size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard, int adj);
 hipError_t launch_das_lds_adjoint(const DasArgs &a, const LdsCfg &c, int mode, int ip,
                                   float *grad_c, hipStream_t s, int n_frames = 1);

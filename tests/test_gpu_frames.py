@@ -1,8 +1,9 @@
-"""Stacks of frames in one launch (bf_das_frames, bf_das_adjoint_frames).
+"""Stacks of frames (bf_das_frames, bf_das_adjoint_frames).
 
-A stack of F frames of one plan is beamformed by one LDS launch (grid z =
-frame), and its adjoint likewise.  Per frame the kernel body, the channel
-groups and the order of every sum are those of the single-frame call, so:
+A stack of F frames of one plan is beamformed one launch per frame, and its
+LDS adjoint takes the whole stack in one launch per gradient (grid z =
+frame).  Per frame the kernel body, the channel groups and the order of
+every sum are those of the single-frame call, so:
   * out[f] equals bf_das on frame f alone bit for bit, and the stack matches
     the FP64 oracle at the single-frame bound (relative L2 1e-5);
   * grad_c[f] equals bf_das_adjoint's grad_c on frame f bit for bit (FP64
@@ -86,8 +87,9 @@ def test_das_frames_matches_single_frames_and_oracle(torch_mod, mode, interp, va
 
 
 def test_das_frames_partial_images(torch_mod):
-    """A small grid splits the channel sum into groups (partial images per
-    frame); stacks larger than before grow the workspace, smaller reuse it."""
+    """A small grid splits the channel sum into groups (partial images);
+    stacks of every size, larger and smaller than the one before, give each
+    frame's own image."""
     torch = torch_mod
     d = _desc("forces", "cubic")
     H, e = _frames(d, 5, 41)
@@ -217,11 +219,10 @@ def test_iq_das_frames_matches_single_frames(torch_mod, mode):
     assert rel_l2(stack[1].numpy(), ref) < 1e-5
 
 
-def test_large_stack_splits_into_launches(torch_mod):
-    """150 frames of the 256 x 256 FORCES plane: the forward takes two
-    launches (partial images of 8 channel groups x 128 frames fill the
-    256 MiB cap), and every frame, on both sides of the split, still equals
-    its own call, as does its dL/dc."""
+def test_large_stack(torch_mod):
+    """150 frames of the 256 x 256 FORCES plane: every frame's image and
+    dL/dc (one stacked adjoint launch) equal its own calls, at the first,
+    last and some middle frames."""
     torch = torch_mod
     desc, H, _, info = synth.make_inputs(3)
     plan = bfm.Plan(desc, H)

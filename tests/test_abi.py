@@ -159,6 +159,8 @@ def test_device_calls_fail_cleanly_without_gpu():
     assert L.bf_plan_destroy(None) == 0
     assert L.bf_decode(None, None, None, None) == -1
     assert L.bf_das(None, None, None, ctypes.c_double(1540.0), None) == -1
+    assert L.bf_das_frames(None, None, 2, None, 1540.0, None) == -1
+    assert L.bf_das_adjoint_frames(None, None, None, 2, 1540.0, None, None, None) == -1
     assert L.bf_sharpness(None, 1, 1, None, None, None) == -1
 
 

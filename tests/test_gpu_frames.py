@@ -37,26 +37,30 @@ def torch_mod():
     return torch
 
 
-def _desc(mode, interp):
-    n_ch = 10 if mode == "hercules" else 12
+def _desc(mode, interp, **kw):
+    n_ch = 12 if mode == "forces" else 10
     dims = (37, 1, 53) if mode == "forces" else (13, 9, 29)
+    if mode == "tpw":
+        kw.setdefault("tx_angles", np.deg2rad(np.linspace(-10, 10, 8)))
     return describe(mode, (12, 10), (0.25 * MM, 0.3 * MM), 8, n_ch, 600, 25e6, 6e6, dims,
                     (-2 * MM, -1.5 * MM, 1.0 * MM), (2.2 * MM, 1.2 * MM, 9 * MM), t0=0.3e-6,
                     f_number=1.0, interp=interp, tx_elements=[0, 3, 4, 6, 7, 8, 10, 11],
-                    channel_map=np.random.default_rng(2).permutation(n_ch))
+                    channel_map=np.random.default_rng(2).permutation(n_ch), **kw)
 
 
 def _frames(desc, n, seed):
-    """n decoded frames of different scatterers, (H, [n, n_tx, n_ch, S] FP64)."""
-    H = hadamard(desc["n_tx"], "scrambled", seed=seed)
+    """n decoded frames of different scatterers, (H, [n, n_tx, n_ch, S] FP64);
+    the row-column models (TPW, VLS) are acquired unencoded (H None)."""
+    encoded = desc["mode"] in ("forces", "hercules")
+    H = hadamard(desc["n_tx"], "scrambled", seed=seed) if encoded else None
     es = []
     for f in range(n):
         rng = np.random.default_rng(seed + 17 * f)
         pts = rng.uniform([-2 * MM, -1 * MM, 1.5 * MM], [2 * MM, 1 * MM, 8 * MM], size=(6, 3))
         if desc["mode"] == "forces":
             pts[:, 1] = 0
-        rf = synth.acquire(desc, pts, rng.uniform(0.5, 1.5, 6), rng, H=H, encoded=True)
-        es.append(oracle.decode(H, rf))
+        rf = synth.acquire(desc, pts, rng.uniform(0.5, 1.5, 6), rng, H=H, encoded=encoded)
+        es.append(oracle.decode(np.eye(desc["n_tx"], dtype=np.int8) if H is None else H, rf))
     return H, np.stack(es)
 
 
@@ -102,11 +106,14 @@ def test_das_frames_partial_images(torch_mod):
             assert np.array_equal(stack[f], singles[f]), (n, f)
 
 
-@pytest.mark.parametrize("mode, interp", [("forces", "cubic"), ("hercules", "cubic"),
-                                          ("hercules", "linear"), ("forces", "nearest")])
-def test_adjoint_frames_matches_single_frames(torch_mod, mode, interp):
+@pytest.mark.parametrize("mode, interp, kw", [
+    ("forces", "cubic", {}), ("hercules", "cubic", {}), ("hercules", "linear", {}),
+    ("forces", "nearest", {}), ("hercules", "cubic", dict(focal_depth=-6 * MM)),
+    ("tpw", "cubic", {}), ("vls", "cubic", dict(focal_depth=-4 * MM)),
+    ("vls", "linear", dict(focal_depth=5.1 * MM))])
+def test_adjoint_frames_matches_single_frames(torch_mod, mode, interp, kw):
     torch = torch_mod
-    d = _desc(mode, interp)
+    d = _desc(mode, interp, **kw)
     H, e = _frames(d, 3, 51)
     plan = bfm.Plan(d, H)
     et = torch.from_numpy(e.astype(np.float32)).cuda()

@@ -125,6 +125,42 @@ def cpu_baseline(desc, H, rf, budget_s: float):
                        f"({t_das:.1f} s), scaled to one volume"), e, vox, ref
 
 
+def precision_study(torch, bfm, desc, H, rf_d, e_mfma, out_f32, e64, vox, ref, n_ref=20000):
+    """The precision variants on the headline data (workload 2), against the
+    FP64 oracle: decode by int8 MFMA (the default, e_mfma) and by FP32 FMA --
+    max-abs error over the whole decoded set; DAS of FP32 and of BF16-stored
+    decoded data (FP32 accumulation) -- max-abs and relative L2 error on the
+    oracle's sampled voxels (vox, ref).  For BF16 the error of the kernel
+    alone is also given, against the oracle's DAS of the BF16-rounded data
+    (the first n_ref sampled voxels)."""
+    import oracle
+    res = {}
+    e_fma = bfm.Plan(desc, H, decode_algo="fma").decode(rf_d)
+    for name, e in (("decode_mfma", e_mfma), ("decode_fma", e_fma)):
+        err = float(np.max(np.abs(e.cpu().numpy().astype(np.float64) - e64)))
+        res[name] = {"max_abs": err, "bit_exact": err == 0.0}
+    del e_fma
+    pb = bfm.Plan(desc, H, e_type="bf16")
+    e_b = pb.decode(rf_d)
+    out_b = pb.das(e_b)
+    torch.cuda.synchronize()
+    scale = float(np.max(np.abs(ref)))
+    for name, out in (("das_f32", out_f32), ("das_bf16", out_b)):
+        got = out.cpu().numpy().reshape(-1)[vox].astype(np.float64)
+        res[name] = {"max_abs": float(np.max(np.abs(got - ref))),
+                     "max_abs_rel_to_peak": float(np.max(np.abs(got - ref)) / scale),
+                     "rel_l2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
+    sub = vox[:n_ref]
+    e_round = e_b.float().cpu().numpy().astype(np.float64)
+    ref_r = oracle.das_points(desc, e_round, sub)
+    got_b = out_b.cpu().numpy().reshape(-1)[sub].astype(np.float64)
+    res["das_bf16"]["rel_l2_vs_rounded_data"] = float(np.linalg.norm(got_b - ref_r) /
+                                                       np.linalg.norm(ref_r))
+    res["sample"] = (f"{len(vox)} random voxels of {int(np.prod(desc['dims']))} "
+                     f"({len(sub)} for the rounded-data reference)")
+    return res
+
+
 VARIANT_NAMES = {0: "lds", 1: "gather", 2: "lds2"}
 KERNEL_SOURCES = ("paper_2512_11086_amd/csrc/bf_das_lds.hip", "paper_2512_11086_amd/csrc/bf_das_lds_block.h",
                   "paper_2512_11086_amd/csrc/bf_common.h")
@@ -587,6 +623,8 @@ def main():
         res["cpu_baseline"] = cb
         got = out_d.cpu().numpy().reshape(-1)[vox].astype(np.float64)
         res["sampled_rel_l2_vs_oracle"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        res["precision"] = precision_study(torch, bfm, desc, H, rf_d, e_d, out_d, e64, vox, ref)
+        log("precision study: " + json.dumps(res["precision"]))
     print(json.dumps(res), flush=True)
 
 

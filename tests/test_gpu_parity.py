@@ -183,6 +183,35 @@ def test_das_workload1_sampled_voxels(torch_dev, workload1, variant):
     assert err <= TOL_L2
 
 
+def test_precision_study_workload2(torch_dev, workload1):
+    """Workload 2 (the headline data, precision variants) at full size:
+    FP32-FMA decode equals the int8 MFMA decode and the oracle bit for bit;
+    DAS of BF16-stored data is within the FP32 bound (1e-5) of the oracle's
+    DAS of the same rounded data, and within the storage bound of the
+    unrounded oracle: rounding each sample to BF16 changes it by at most
+    2^-9 relative, so for terms of random sign the relative L2 change of the
+    sum stays near 2^-9 / sqrt(3); 2^-8 is asserted."""
+    torch, _ = torch_dev
+    desc, H, rf, _ = workload1
+    e64 = oracle.decode(H, rf)
+    rf_d = _to_dev(torch, rf)
+    e_mfma = bfm.Plan(desc, H).decode(rf_d)
+    e_fma = bfm.Plan(desc, H, decode_algo="fma").decode(rf_d)
+    assert torch.equal(e_fma, e_mfma)
+    assert np.array_equal(e_fma.cpu().numpy().astype(np.float64), e64)
+    pb = bfm.Plan(desc, H, e_type="bf16")
+    e_b = pb.decode(rf_d)
+    got = pb.das(e_b).cpu().numpy().reshape(-1).astype(np.float64)
+    vox = sample_voxels(got.size, 2000, seed=12)
+    ref_r = oracle.das_points(desc, e_b.float().cpu().numpy().astype(np.float64), vox)
+    ref = oracle.das_points(desc, e64, vox)
+    err_r, err = rel_l2(got[vox], ref_r), rel_l2(got[vox], ref)
+    print(f"workload 2: BF16 storage rel L2 {err:.3e} vs the exact data, {err_r:.3e} vs the "
+          f"rounded data")
+    assert err_r <= TOL_L2
+    assert err <= 2.0 ** -8
+
+
 def _small_desc(mode, interp, f_number=0.7, rotate=False, dims=None, t0=0.3e-6):
     M = None
     if rotate:

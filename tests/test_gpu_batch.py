@@ -166,3 +166,33 @@ def test_persistent_lds_classes_and_graph(torch_mod):
         assert torch.isfinite(junk)
         for o, r in zip(outs2, eager):
             assert torch.equal(o, r), rep
+
+
+def test_workload4_frames_match_oracle():
+    """Full size: four frames of the batched stream (the first two planes and
+    the first two volumes, each with its own transmit subset) through one
+    batch plan, persistent launch and graph replay, against the FP64 oracle
+    on sampled points (relative L2 1e-5)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    descs, Hs, rfs, info = synth.make_inputs(4)
+    kinds = [k for k, _ in info["plan"]]
+    pick = [i for i, k in enumerate(kinds) if k == "2d"][:2] + \
+           [i for i, k in enumerate(kinds) if k == "3d"][:2]
+    bp = bfm.BatchPlan([descs[i] for i in pick], [Hs[i] for i in pick])
+    rf_d = [torch.from_numpy(rfs[i]).cuda() for i in pick]
+    outs = [torch.empty(s, device="cuda") for s in bp.out_shapes]
+    bp.run(rf_d, outs)
+    outs_g = [torch.empty(s, device="cuda") for s in bp.out_shapes]
+    bp.graph_launch(rf_d, outs_g)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(44)
+    for n, i in enumerate(pick):
+        got = outs[n].cpu().numpy().reshape(-1).astype(np.float64)
+        assert torch.equal(outs_g[n], outs[n]), i
+        vox = np.sort(rng.choice(got.size, 1500, replace=False))
+        ref = oracle.das_points(descs[i], oracle.decode(Hs[i], rfs[i]), vox)
+        err = rel_l2(got[vox], ref)
+        print(f"workload 4 frame {i} ({kinds[i]}, {descs[i]['n_tx']} tx): rel L2 {err:.2e}")
+        assert err <= 1e-5, i

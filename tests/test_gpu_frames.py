@@ -244,3 +244,26 @@ def test_large_stack(torch_mod):
         assert torch.equal(imgs[f], plan.das(es[f], c=c)), f
         _, gc1 = plan.das_adjoint(es[f], G[f], c=c, want_e=False)
         assert float(gc[f]) == float(gc1), f
+
+
+@pytest.mark.parametrize("e_type", ["bf16", "i32"])
+def test_frames_storage_types(torch_mod, e_type):
+    """Stacks of BF16 / int32 decoded data: frame offsets in their element
+    size; the adjoint's dL/dc (gather kernel for these types) and dL/de
+    (LDS kernel, which reads no data) per frame as in single calls."""
+    torch = torch_mod
+    d = _desc("hercules", "cubic")
+    H, e = _frames(d, 3, 101)
+    plan = bfm.Plan(d, H, e_type=e_type)
+    dt = torch.bfloat16 if e_type == "bf16" else torch.int32
+    et = (torch.from_numpy(e.astype(np.float32)).to(dt) if e_type == "bf16"
+          else torch.from_numpy(np.rint(e).astype(np.int32))).cuda()
+    stack = plan.das(et)
+    G = torch.from_numpy(np.random.default_rng(4).normal(
+        size=(3,) + plan.out_shape).astype(np.float32)).cuda()
+    ge, gc = plan.das_adjoint(et, G)
+    for f in range(3):
+        assert torch.equal(stack[f], plan.das(et[f])), f
+        ge1, gc1 = plan.das_adjoint(et[f], G[f])
+        assert rel_l2(gc[f:f + 1].cpu().numpy(), gc1.reshape(1).cpu().numpy()) <= 1e-6, f
+        assert rel_l2(ge[f].cpu().numpy(), ge1.cpu().numpy()) <= 1e-6, f

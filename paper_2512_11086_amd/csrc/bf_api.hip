@@ -598,7 +598,6 @@ int Frame::das(const void *e, float *out, double c, hipStream_t s) const
     return err == hipSuccess ? BF_OK : hip_fail(err, "DAS launch");
 }
 
-
 // The per-frame arrays of `a` advanced to frame f0 of a stack.
 DasArgs Frame::at_frame(const DasArgs &a, int f0) const
 {
@@ -668,6 +667,7 @@ int Frame::das_adjoint(const void *e, const float *grad_out, double c, float *gr
     }
     return err == hipSuccess ? BF_OK : hip_fail(err, "DAS adjoint launch");
 }
+
 }  // namespace bf
 
 using namespace bf;
@@ -842,7 +842,7 @@ int bf_das(bf_plan plan, const void *e, float *out, double c, void *stream)
     if (st != BF_OK) return st;
     if (!e || !out) return fail(BF_ERR_NULL, "e and out must be non-NULL");
     if ((st = check_c(c)) != BF_OK) return st;
-    return plan->frames[0]->das_frames(e, 1, out, c, (hipStream_t)stream);
+    return plan->frames[0]->das(e, out, c, (hipStream_t)stream);
 }
 
 int bf_das_adjoint(bf_plan plan, const void *e, const float *grad_out, double c, float *grad_e,

@@ -82,3 +82,23 @@ def test_autofocus_finds_generating_sound_speed(torch_mod, w3):
     # the refined point is a stationary point of the loss
     assert any(abs(h[2]) < 1e-3 * max(abs(g[2]) for g in hist) or h[0] == c_hat for h in hist)
     assert 1450.0 <= c_hat <= 1600.0
+
+
+def test_autofocus_stacked_batch_matches_list(torch_mod, w3):
+    """The same autofocus run with the 8 frames as one stacked tensor
+    (bf_das_frames / bf_das_adjoint_frames underneath): the scan losses and
+    the refinement's dL/dc agree with the per-frame list path to FP32
+    summation order, and it ends at the same sound speed."""
+    torch = torch_mod
+    desc, H, rfs, info = w3
+    plan = bfm.Plan(desc, H)
+    frames = [plan.decode(torch.from_numpy(r).cuda()) for r in rfs]
+    c_l, scan_l, hist_l = af.autofocus(frames, plan)
+    c_s, scan_s, hist_s = af.autofocus(torch.stack(frames).contiguous(), plan)
+    for (ca, la), (cb, lb) in zip(scan_l, scan_s):
+        assert ca == cb and abs(la - lb) <= 1e-6 * abs(la)
+    assert len(hist_l) == len(hist_s)
+    for (ca, la, ga), (cb, lb, gb) in zip(hist_l, hist_s):
+        assert abs(ca - cb) <= 1e-6 * ca
+        assert abs(la - lb) <= 1e-6 * abs(la) and abs(ga - gb) <= 1e-5 * abs(ga) + 1e-12
+    assert abs(c_l - c_s) <= 1e-3

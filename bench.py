@@ -25,9 +25,37 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# VALU peak used for the DAS roofline: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-# non-packed FP32 lane operations (an FMA counts as 2 flops).
+# FP32 vector peaks of MI355X (256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz, an FMA
+# counting 2 flops): the published 157.3 TFLOP/s counts packed FP32 (two FP32
+# operations per lane and instruction); this build disables packed FP32
+# instructions, so its ceiling is half of that.
+FP32_PUBLISHED_TFLOPS = 157.3
 FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+# LDS read bandwidth: 256 CUs x 128 bytes per clock x 2.4 GHz.
+LDS_PEAK_TBPS = 256 * 128 * 2.4e9 / 1e12
+# Bytes of LDS taps per cubic FP32 read: four samples (the kernels read them
+# as one 16-byte coefficient quad).
+LDS_BYTES_PER_TERM = 16
+
+
+def alu_roofline(tflops: float, traffic=None) -> dict:
+    """FP32 ALU roofline object: against the published peak (frac) and the
+    non-packed ceiling of this build (frac_nonpacked)."""
+    return {"bound": "alu", "achieved": round(tflops, 2), "peak": FP32_PUBLISHED_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(tflops / FP32_PUBLISHED_TFLOPS, 4),
+            "traffic": traffic, "peak_nonpacked": round(FP32_NONPACKED_TFLOPS, 1),
+            "frac_nonpacked": round(tflops / FP32_NONPACKED_TFLOPS, 4)}
+
+
+def lds_roofline(n_terms: int, n_nominal: int, ms: float) -> dict:
+    """LDS-gather roofline of a DAS launch: 16 bytes of taps per term read
+    from LDS, over the active terms (apodization > 0) and over the nominal
+    count of the metric."""
+    act = LDS_BYTES_PER_TERM * n_terms / (ms * 1e-3) / 1e12
+    nom = LDS_BYTES_PER_TERM * n_nominal / (ms * 1e-3) / 1e12
+    return {"bound": "lds", "achieved": round(act, 2), "peak": round(LDS_PEAK_TBPS, 1),
+            "unit": "TB/s", "frac": round(act / LDS_PEAK_TBPS, 4),
+            "achieved_nominal": round(nom, 2), "frac_nominal": round(nom / LDS_PEAK_TBPS, 4)}
 
 
 def log(*a):
@@ -64,45 +92,118 @@ def active_terms(desc, dev) -> int:
 
 
 def algorithmic_flops(desc, n_act: int, iq: bool = False, adjoint_c: bool = False) -> float:
-    """FP32 flops (FMA = 2) of one DAS launch (or its dL/dc adjoint) with
-    n_act active terms (apodization > 0), counted for the algorithm with
-    per-sample interpolation coefficients: the cubic read's coefficients of a
-    trace's sample interval are formed once (10 flops; 20 for IQ's real and
-    imaginary parts; the adjoint forms the derivative's 3 coefficients, 10)
-    and every term evaluates its polynomial by Horner's rule (6; the
-    derivative's quadratic 4).
+    """FP32 flops (FMA = 2; a floor, fract, square root or reciprocal = 1) of
+    one DAS launch (or its dL/dc adjoint) with n_act active terms
+    (apodization > 0), counted as the kernels evaluate each term.  The cubic
+    read's coefficients of a trace's sample interval are formed once (10
+    flops; 20 for IQ's real and imaginary parts; the adjoint forms the
+    derivative's 3 coefficients, 10) and every term evaluates its polynomial
+    by Horner's rule (6; the derivative's quadratic 4).
 
-    Per active term: HERCULES (one receive path per term) delay 13 (dx,
-    rho^2, d^2, sqrt, d+z, rcp, mul, fma, floor, fract) + apodization 14 (u^2
-    and a degree-6 polynomial); FORCES, TPW and VLS separate the path into a
-    transmit part per (point, transmit) (FORCES distance to the column 8,
-    TPW x sin + z (cos - 1) 6, VLS signed distance to the line 13) and a
-    receive part with its weight per active (point, row) (13 + 14 = 27), and
-    a term adds the two and splits the sum (3).  Then the read (Horner 6) and
-    the accumulation: real 2; IQ two reads (12) + phase 2 + sine and cosine 2
-    + weight x rotation 2 + complex multiply-add 8; dL/dc the derivative (4)
-    + the sums of w v' and w v' s (4)."""
+    Per active term: HERCULES (one receive path per term) delay 12 (dx,
+    rho^2, (d/k)^2, sqrt, d/k + z/k, rcp, fma, floor, fract) + apodization 5
+    (the Hann table: scale, floor, fract, interpolating fma); FORCES, TPW and
+    VLS separate the path into a transmit part per (point, transmit)
+    (FORCES distance to the column 8, TPW x sin + z (cos - 1) 4, VLS signed
+    distance to the line 11) and a receive part with its weight per active
+    (point, row) (path 9 + Hann polynomial in u^2 13 = 22), and a term adds
+    the two and takes floor and fract (3).  Then the read (Horner 6) and the
+    accumulation: real 2; IQ two reads (12) + phase 2 + the rotation 13
+    (fract, sine, cosine, two weight products, complex multiply-add 8);
+    dL/dc the derivative (4) + the sums of w v' and w v' s (4)."""
     mode = desc["mode"]
     traces = desc["n_tx"] * desc["n_ch"]
     coef = 10.0 * traces * desc["n_samples"] * (2 if iq else 1)
     if adjoint_c:
         per_term = 4 + 4
     elif iq:
-        per_term = 12 + 2 + 2 + 2 + 8
+        per_term = 12 + 2 + 13
     else:
         per_term = 6 + 2
     if mode == "hercules":
-        return n_act * (13 + 14 + per_term) + coef
+        return n_act * (12 + 5 + per_term) + coef
     n_tx = desc["n_tx"]
     n_pts = int(np.prod(desc["dims"]))
-    f_tx = {"forces": 8, "tpw": 6, "vls": 13}[mode]
-    return n_act * (3 + per_term + 27.0 / n_tx) + f_tx * n_pts * n_tx + coef
+    f_tx = {"forces": 8, "tpw": 4, "vls": 11}[mode]
+    return n_act * (3 + per_term + 22.0 / n_tx) + f_tx * n_pts * n_tx + coef
+
+
+def _oracle_rate(desc, H, rf, n_vox=None, seed=0):
+    """Seconds of the FP64 oracle's decode and of its DAS over one whole frame
+    (DAS on n_vox random points scaled to the frame when n_vox is given)."""
+    import oracle
+    t = time.perf_counter()
+    e = oracle.decode(H, rf)
+    t_dec = time.perf_counter() - t
+    nv = int(np.prod(desc["dims"]))
+    t = time.perf_counter()
+    if n_vox is None or n_vox >= nv:
+        oracle.das(desc, e)
+        t_das = time.perf_counter() - t
+    else:
+        vox = np.sort(np.random.default_rng(seed).choice(nv, n_vox, replace=False))
+        oracle.das_points(desc, e, vox)
+        t_das = (time.perf_counter() - t) * nv / n_vox
+    return t_dec, t_das
+
+
+def cpu_baseline_per_config(stream4=None):
+    """The oracle on the other workloads, all host cores and one thread:
+    workload 0 (FORCES 128x128 B-scan) and one frame of workload 3 (FORCES
+    256x256, 64 x 64 x 2048) decode + DAS of the whole image (one thread:
+    DAS on a quarter of the pixels, scaled); workload 4 on 8 of its 64 frames
+    (the first four planes and the first four volumes), DAS on random points
+    scaled to each frame, as a rate for the whole stream."""
+    import oracle
+    import synth
+    cores = oracle.threads()
+    out = {}
+    for k, name in ((0, "workload0_forces_128x128"), (3, "workload3_forces_256x256_per_frame")):
+        if k == 0:
+            desc, H, rf, _ = synth.make_inputs(0)
+        else:
+            desc, H, rfs, _ = synth.make_inputs(3, frame=0)
+            rf = rfs[0]
+        nv = int(np.prod(desc["dims"]))
+        nominal = nv * desc["n_tx"] * desc["n_ch"]
+        rec = {}
+        for threads, n_vox in ((cores, None), (1, nv // 4)):
+            oracle.threads(threads)
+            t_dec, t_das = _oracle_rate(desc, H, rf, n_vox)
+            rec[f"threads_{threads}"] = {
+                "decode_s": round(t_dec, 4), "das_s": round(t_das, 4),
+                "G_samples_per_s": round(nominal / (t_dec + t_das) / 1e9, 4),
+                "frames_per_s": round(1.0 / (t_dec + t_das), 3),
+                "sample": "whole image" if n_vox is None else
+                          f"DAS on {n_vox} random pixels of {nv}, scaled"}
+        oracle.threads(cores)
+        out[name] = rec
+    if stream4 is not None:
+        descs, Hs, rfs = stream4
+        kinds = ["2d" if d["mode"] == "forces" else "3d" for d in descs]
+        pick = [i for i, k in enumerate(kinds) if k == "2d"][:4] + \
+               [i for i, k in enumerate(kinds) if k == "3d"][:4]
+        t_tot, nom = 0.0, 0
+        for i in pick:
+            t_dec, t_das = _oracle_rate(descs[i], Hs[i], rfs[i], n_vox=400, seed=i)
+            t_tot += t_dec + t_das
+            nom += int(np.prod(descs[i]["dims"])) * descs[i]["n_tx"] * descs[i]["n_ch"]
+        rate = nom / t_tot
+        total = sum(int(np.prod(d["dims"])) * d["n_tx"] * d["n_ch"] for d in descs)
+        out["workload4_stream"] = {
+            f"threads_{cores}": {"G_samples_per_s": round(rate / 1e9, 4),
+                                 "stream_s": round(total / rate, 1),
+                                 "sample": f"frames {pick} (n_tx "
+                                           f"{[descs[i]['n_tx'] for i in pick]}): full decode, "
+                                           "DAS on 400 random points per frame scaled to the "
+                                           "frame; stream time extrapolated at that rate"}}
+    return out
 
 
 def cpu_baseline(desc, H, rf, budget_s: float):
     """FP64 oracle on the host cores: full decode + DAS on a random voxel sample."""
     import oracle
-    threads = os.cpu_count()
+    threads = oracle.threads()
     t = time.perf_counter()
     e = oracle.decode(H, rf)
     t_dec = time.perf_counter() - t
@@ -222,12 +323,12 @@ def traffic_run():
                       "das_config": plan.info()}), flush=True)
 
 
-def batched_comparison(torch, bfm, synth, reps: int):
+def batched_comparison(torch, bfm, stream4, reps: int):
     """64-frame uFORCES/uHERCULES stream: plain per-frame launches vs one
-    persistent launch per kernel class vs the same captured in a hipGraph."""
-    t = time.perf_counter()
-    descs, Hs, rfs, info = synth.make_inputs(4)
-    log(f"batched inputs ({len(descs)} frames) generated in {time.perf_counter() - t:.1f} s")
+    persistent launch per kernel class vs the same captured in a hipGraph.
+    The per-frame loop is also timed as its decode launches alone and its
+    DAS launches alone (the decode share of the stream)."""
+    descs, Hs, rfs = stream4
     dev = torch.device("cuda:0")
     rf_d = [torch.from_numpy(r).to(dev) for r in rfs]
     bp = bfm.BatchPlan(descs, Hs)
@@ -242,6 +343,14 @@ def batched_comparison(torch, bfm, synth, reps: int):
             p.decode(r, out=e)
             p.das(e, out=o)
 
+    def decode_only():
+        for p, r, e in zip(plans, rf_d, es):
+            p.decode(r, out=e)
+
+    def das_only():
+        for p, e, o in zip(plans, es, outs_p):
+            p.das(e, out=o)
+
     def timed(fn):
         fn()
         torch.cuda.synchronize()
@@ -254,22 +363,62 @@ def batched_comparison(torch, bfm, synth, reps: int):
         return a.elapsed_time(b) / reps
 
     ms_pf = timed(per_frame)
+    ms_dec = timed(decode_only)
+    ms_das = timed(das_only)
     ms_ps = timed(lambda: bp.run(rf_d, outs_b))
     ms_gr = timed(lambda: bp.graph_launch(rf_d, outs_g))
     worst = 0.0
     for a_, b_, c_ in zip(outs_p, outs_b, outs_g):
         worst = max(worst, float((a_ - b_).norm() / a_.norm().clamp_min(1e-30)),
                     float((b_ - c_).norm() / b_.norm().clamp_min(1e-30)))
+    paths = [bp.frame_info(f) for f in range(len(descs))]
     nominal = sum(int(np.prod(d["dims"])) * d["n_tx"] * d["n_ch"] for d in descs)
     n3 = sum(1 for d in descs if d["mode"] == "hercules")
-    log(f"batched: per-frame {ms_pf:.2f} ms, persistent {ms_ps:.2f} ms, graph {ms_gr:.2f} ms")
+    log(f"batched: per-frame {ms_pf:.2f} ms (decode {ms_dec:.2f}, DAS {ms_das:.2f}), "
+        f"persistent {ms_ps:.2f} ms, graph {ms_gr:.2f} ms")
     return {"frames": len(descs), "frames_3d": n3, "nominal_G_samples": round(nominal / 1e9, 2),
-            "per_frame_ms": round(ms_pf, 3), "persistent_ms": round(ms_ps, 3),
+            "per_frame_ms": round(ms_pf, 3), "per_frame_decode_ms": round(ms_dec, 3),
+            "per_frame_das_ms": round(ms_das, 3), "persistent_ms": round(ms_ps, 3),
             "graph_ms": round(ms_gr, 3),
             "speedup_graph_vs_per_frame": round(ms_pf / ms_gr, 3),
             "speedup_persistent_vs_per_frame": round(ms_pf / ms_ps, 3),
             "graph_G_samples_per_s": round(nominal / (ms_gr * 1e-3) / 1e9, 1),
+            "frames_on_persistent_lds": sum(1 for p in paths if p["das_path"] == "persistent_lds"),
             "max_rel_l2_between_paths": worst}
+
+
+def decode_share(torch, bfm, synth, reps: int = 20):
+    """Decode and DAS times of the plane workloads (0: FORCES 128x128 from 32 x
+    32 x 1024; 3: one FORCES 256x256 frame from 64 x 64 x 2048): the largest
+    saving a decode fused into DAS could give is the decode's own time."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {}
+    for k, name in ((0, "workload0"), (3, "workload3_per_frame")):
+        if k == 0:
+            desc, H, rf, _ = synth.make_inputs(0)
+        else:
+            desc, H, rfs, _ = synth.make_inputs(3, frame=0)
+            rf = rfs[0]
+        plan = bfm.Plan(desc, H)
+        rf_d = torch.from_numpy(rf).to(dev)
+        e = plan.decode(rf_d)
+        img = plan.das(e)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        for _ in range(reps):
+            plan.decode(rf_d, out=e)
+        ev[1].record(stream)
+        for _ in range(reps):
+            plan.das(e, out=img)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        dec = ev[0].elapsed_time(ev[1]) / reps
+        das = ev[1].elapsed_time(ev[2]) / reps
+        out[name] = {"decode_ms": round(dec, 4), "das_ms": round(das, 4),
+                     "decode_share": round(dec / (dec + das), 4)}
+    return out
 
 
 def iq_pipeline(torch, bfm, synth, desc, H, rf_d, n_act, reps: int):
@@ -334,13 +483,9 @@ def iq_pipeline(torch, bfm, synth, desc, H, rf_d, n_act, reps: int):
         "ms_per_step": round(step, 4), "value": round(nominal / (step * 1e-3) / 1e9, 3),
         "unit": "G samples/s", "demod_ms": round(dem_ms, 4), "decode_ms": round(dec_ms, 4),
         "das_ms": round(das_ms, 4),
-        "demod_roofline": {"bound": "alu", "achieved": round(dem_tf, 2),
-                           "peak": round(FP32_NONPACKED_TFLOPS, 1), "unit": "TFLOP/s",
-                           "frac": round(dem_tf / FP32_NONPACKED_TFLOPS, 4),
+        "demod_roofline": {**alu_roofline(dem_tf),
                            "hbm_GBps": round(dem_bytes / (dem_ms * 1e-3) / 1e9, 1)},
-        "das_roofline": {"bound": "alu", "achieved": round(das_tf, 2),
-                         "peak": round(FP32_NONPACKED_TFLOPS, 1), "unit": "TFLOP/s",
-                         "frac": round(das_tf / FP32_NONPACKED_TFLOPS, 4)},
+        "das_roofline": alu_roofline(das_tf),
         "das_config": plan.info(),
     }
 
@@ -447,9 +592,7 @@ def autofocus_stage(torch, bfm, synth, reps: int = 5):
     out["unit"] = "G samples/s"
     out["per_frame_calls"] = {k: round(v, 4) for k, v in pf.items()}
     out["per_frame_calls"]["gradient_step_ms_per_frame"] = round(step_pf, 4)
-    out["adjoint_roofline"] = {"bound": "alu", "achieved": round(tf, 2),
-                               "peak": round(FP32_NONPACKED_TFLOPS, 1), "unit": "TFLOP/s",
-                               "frac": round(tf / FP32_NONPACKED_TFLOPS, 4)}
+    out["adjoint_roofline"] = alu_roofline(tf)
     return out
 
 
@@ -487,9 +630,7 @@ def n4_workloads(torch, bfm, synth, reps: int = 2):
                      "das_ms": round(das_ms, 3),
                      "value": round(nominal / ((dec_ms + das_ms) * 1e-3) / 1e9, 2),
                      "unit": "G samples/s", "variant": VARIANT_NAMES[plan.info()["variant"]],
-                     "roofline": {"bound": "alu", "achieved": round(tf, 2),
-                                  "peak": round(FP32_NONPACKED_TFLOPS, 1), "unit": "TFLOP/s",
-                                  "frac": round(tf / FP32_NONPACKED_TFLOPS, 4)}}
+                     "roofline": alu_roofline(tf)}
         log(f"{name}: decode {dec_ms:.3f} ms, DAS {das_ms:.3f} ms")
         del plan, rf_d, e, img
     descs, Hs, rfs, _ = synth.make_inputs(8)
@@ -598,10 +739,9 @@ def main():
         "decode_ms": round(dec_ms, 4), "das_ms": round(das_ms, 4),
         "decode_hbm_GBps": round(dec_bytes / (dec_ms * 1e-3) / 1e9, 1),
         "active_term_fraction": round(n_act / nominal, 4),
-        "roofline": {"bound": "alu", "achieved": round(achieved, 2),
-                     "peak": round(FP32_NONPACKED_TFLOPS, 1), "unit": "TFLOP/s",
-                     "frac": round(achieved / FP32_NONPACKED_TFLOPS, 4),
-                     "traffic": measured_traffic()},
+        "roofline": alu_roofline(achieved, measured_traffic()),
+        "lds_roofline": lds_roofline(n_act, nominal, das_ms),
+        "das_ms_median": round(float(np.median([b.elapsed_time(c) for _, b, c in ev])), 4),
     }
     res["das_config"] = plan.info()
     res["envelope"] = envelope_stage(torch, bfm, out_d)
@@ -616,10 +756,25 @@ def main():
         log(f"autofocus step {res['autofocus']['gradient_step_ms_per_frame']:.3f} ms per frame "
             f"(stacked frames; one call per frame: "
             f"{res['autofocus']['per_frame_calls']['gradient_step_ms_per_frame']:.3f} ms)")
+    res["decode_share"] = decode_share(torch, bfm, synth)
+    res["decode_share"]["workload1"] = {"decode_ms": round(dec_ms, 4), "das_ms": round(das_ms, 4),
+                                        "decode_share": round(dec_ms / (dec_ms + das_ms), 4)}
+    stream4 = None
+    if not args.no_batch or not args.no_cpu:
+        t = time.perf_counter()
+        descs4, Hs4, rfs4, _ = synth.make_inputs(4)
+        stream4 = (descs4, Hs4, rfs4)
+        log(f"batched inputs ({len(descs4)} frames) generated in {time.perf_counter() - t:.1f} s")
     if not args.no_batch:
-        res["batched"] = batched_comparison(torch, bfm, synth, args.batch_reps)
+        res["batched"] = batched_comparison(torch, bfm, stream4, args.batch_reps)
+        b = res["batched"]
+        res["decode_share"]["workload4_per_frame_loop"] = {
+            "decode_ms": b["per_frame_decode_ms"], "das_ms": b["per_frame_das_ms"],
+            "decode_share": round(b["per_frame_decode_ms"] /
+                                  (b["per_frame_decode_ms"] + b["per_frame_das_ms"]), 4)}
     if not args.no_cpu:
         cb, e64, vox, ref = cpu_baseline(desc, H, rf, args.cpu_budget)
+        cb["per_config"] = cpu_baseline_per_config(stream4)
         res["cpu_baseline"] = cb
         got = out_d.cpu().numpy().reshape(-1)[vox].astype(np.float64)
         res["sampled_rel_l2_vs_oracle"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define BF_ABI_VERSION 5
+#define BF_ABI_VERSION 6
 
 /* Largest frame count of bf_das_frames / bf_das_adjoint_frames. */
 #define BF_MAX_FRAMES 4096
@@ -161,6 +161,9 @@ typedef struct {
     int64_t e_elems;           /* elements of decoded data per frame (frame 0; IQ
                                   plans count the two FP32 parts of a sample)          */
     int64_t out_elems;         /* output values per frame (frame 0; IQ: 2 per point)   */
+    int32_t channel_groups;    /* workgroup sets the channel sum of bf_das is split over
+                                  (small grids; > 1: partial images summed in a fixed
+                                  order by a second kernel)                            */
 } bf_plan_info;
 
 /* ABI version of the loaded library (BF_ABI_VERSION). */
@@ -235,7 +238,10 @@ int bf_decode(bf_plan plan, const int16_t *rf, void *e, void *stream);
 int bf_das(bf_plan plan, const void *e, float *out, double c, void *stream);
 
 /* Adjoint of bf_das for the same e and c, given grad_out = dL/d(out)
- * (device f32 [Ny][Nx][Nz]):
+ * (device f32 [Ny][Nx][Nz]).  The paper defines only the forward sum (Eq. 1
+ * with Eqs. 2-3 and the Hermite read of Sec. IV-B); this is its exact
+ * transpose in e, and its derivative in c through the delays of Eq. 1 (the
+ * apodization of Eq. 2 does not depend on c):
  *   grad_e (device f32 [n_tx][n_ch][n_samples], nullable, overwritten) =
  *       transpose of the linear map e -> out, applied to grad_out;
  *   grad_c (device f32 scalar, nullable, overwritten) =
@@ -273,7 +279,9 @@ int bf_das_frames(bf_plan plan, const void *e, int32_t n_frames, float *out, dou
 int bf_das_adjoint_frames(bf_plan plan, const void *e, const float *grad_out, int32_t n_frames,
                           double c, float *grad_e, float *grad_c, void *stream);
 
-/* Image-sharpness loss for n_images images of n_per_image points each:
+/* Image-sharpness loss for n_images images of n_per_image points each (the
+ * objective of the sound-speed autofocus; not a step of the paper's
+ * pipeline, which images at a given c):
  *   loss[f] = -sum I^4 / (sum I^2)^2   (device f32 [n_images], overwritten)
  *   grad[f][p] = d loss[f] / d I[f][p] (device f32, nullable, overwritten)
  * Sums are accumulated in FP64.  An all-zero image gives loss 0, gradient 0. */
@@ -282,7 +290,10 @@ int bf_sharpness(const float *img, int64_t n_per_image, int32_t n_images, float 
 
 /* Batched decode + DAS of every frame of a batch plan with persistent
  * kernels (one decode launch per Hadamard-order class and one DAS launch per
- * mode, each pulling (frame, tile) items from a queue).
+ * kernel class, each pulling work items from queues).  The frames are the
+ * paper's parameter sets (Sec. VI-B: several sets, e.g. cross-plane views or
+ * transmit subsets, imaged from one acquisition stream), each decoded
+ * (Sec. VII-E) and beamformed (Eq. 1; Sec. VII-F) as by bf_decode + bf_das.
  * rf[f]: device int16 of frame f; out[f]: device f32 of frame f (host arrays of
  * n_frames device pointers).  Decoded data goes to the plan's workspaces. */
 int bf_batch_run(bf_plan plan, const int16_t *const *rf, float *const *out, void *stream);
@@ -291,6 +302,19 @@ int bf_batch_run(bf_plan plan, const int16_t *const *rf, float *const *out, void
  * later calls.  The frame pointers are copied into the plan's device table
  * before each replay, so new buffers need no re-capture. */
 int bf_graph_launch(bf_plan plan, const int16_t *const *rf, float *const *out, void *stream);
+
+/* How the batched path runs frame f of a batch plan (after its first
+ * bf_batch_run or bf_graph_launch; BF_ERR_STATE before, BF_ERR_SHAPE for f
+ * out of range). */
+enum { BF_BATCH_PERSISTENT_LDS = 0, BF_BATCH_GATHER = 1 };
+typedef struct {
+    int32_t das_path;          /* BF_BATCH_PERSISTENT_LDS or BF_BATCH_GATHER            */
+    int32_t das_class;         /* index of its persistent DAS launch (-1: gather)        */
+    int32_t channel_groups;    /* work items per box along the channel sum (>= 1)        */
+    int32_t decode_class;      /* index of its persistent decode launch                  */
+    int64_t das_items;         /* DAS work items of the frame                            */
+} bf_batch_frame_info;
+int bf_batch_get_frame_info(bf_plan plan, int32_t frame, bf_batch_frame_info *info);
 
 /* ---------------------------------------------------------------------------
  * Demodulation (Eq. 4; Sec. VII-D): the stage before decoding.
@@ -373,9 +397,6 @@ int bf_env_destroy(bf_env e);
  * finite or, when compressing, param is not finite and > 0. */
 int bf_envelope(bf_env e, const float *img, float *out, int32_t compress, double ref,
                 double param, void *stream);
-
-/* Evaluates the library's Hann-window polynomial W at u^2 (host, for tests). */
-double bf_hann_poly(double u2);
 
 #ifdef __cplusplus
 }

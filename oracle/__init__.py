@@ -60,6 +60,8 @@ def lib():
             build()
         L = ctypes.CDLL(_LIB_PATH)
         P = ctypes.POINTER
+        L.oracle_threads.argtypes = [ctypes.c_int]
+        L.oracle_threads.restype = ctypes.c_int
         L.oracle_sylvester.argtypes = [ctypes.c_int, P(ctypes.c_int8)]
         L.oracle_decode.argtypes = [P(ctypes.c_int8), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     P(ctypes.c_int16), P(ctypes.c_int64)]
@@ -91,6 +93,12 @@ def lib():
 
 def _ptr(a, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def threads(n: int = 0) -> int:
+    """Set the oracle's OpenMP worker count (n >= 1) and return the count in
+    effect (n = 0 only queries it)."""
+    return int(lib().oracle_threads(int(n)))
 
 
 def sylvester(n: int) -> np.ndarray:

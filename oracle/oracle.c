@@ -21,6 +21,8 @@
 
 #include "oracle.h"
 
+#include <omp.h>
+
 /* ------------------------------------------------------------------------- */
 /* Hadamard matrices and decoding (Sec. IV-A; Sec. VII-E)                     */
 /* ------------------------------------------------------------------------- */
@@ -28,6 +30,15 @@
 /* Sylvester construction, natural order: H[k][i] = (-1)^popcount(k & i).
  * Reading: the paper never names its Hadamard construction; the workloads use
  * Sylvester's.  Returns 0, or -1 if n is not a power of two. */
+/* Worker threads of the OpenMP loops below (timing of the oracle on a given
+ * number of host cores; no arithmetic).  n < 1 leaves the setting unchanged;
+ * returns the count in effect. */
+int oracle_threads(int n)
+{
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
+}
+
 int oracle_sylvester(int n, int8_t *H)
 {
     if (n < 1 || (n & (n - 1)) != 0) return -1;

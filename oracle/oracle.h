@@ -28,6 +28,7 @@ typedef struct {
     const double *tx_angles;   /* TPW: n_tx tilt angles, radians                   */
 } oracle_geom;
 
+int oracle_threads(int n);
 int oracle_sylvester(int n, int8_t *H);
 void oracle_decode(const int8_t *H, int n_tx, int n_ch, int n_samples, const int16_t *r,
                    int64_t *e);

@@ -18,11 +18,11 @@ import math
 
 import numpy as np
 
-from ._lib import (BfError, COMPRESS, DECODE_ALGOS, DemodParams, ETYPES, INTERPS, IQ_TYPES, MODES,
-                   Params, PlanInfo, VARIANTS, check, lib)
+from ._lib import (BATCH_PATHS, BatchFrameInfo, BfError, COMPRESS, DECODE_ALGOS, DemodParams,
+                   ETYPES, INTERPS, IQ_TYPES, MODES, Params, PlanInfo, VARIANTS, check, lib)
 
 __all__ = ["BfError", "Plan", "BatchPlan", "Demod", "Envelope", "params_from_desc", "sharpness",
-           "validate", "hann_poly"]
+           "validate"]
 
 
 class _Marshalled:
@@ -70,10 +70,6 @@ def validate(desc, hadamard, **kw) -> None:
     check(lib().bf_validate(ctypes.byref(m.p)))
 
 
-def hann_poly(u2: float) -> float:
-    return lib().bf_hann_poly(float(u2))
-
-
 def _torch():
     import torch
     return torch
@@ -87,6 +83,26 @@ def _stream(stream):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_tensor(t, name, dtype, shape=None, device=None):
+    """Reject, before any library call, a tensor the kernels cannot take: a
+    host tensor (its pointer would reach a kernel as a device address), one
+    on another device than the call's other tensors, or one of the wrong
+    dtype, shape or layout."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (device) tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the call's other tensors on {device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, not {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
 
 
 _TORCH_ETYPE = {"f32": "float32", "bf16": "bfloat16", "i32": "int32"}
@@ -133,7 +149,7 @@ class Plan:
         return dict(n_frames=inf.n_frames, tile=tuple(inf.tile), variant=inf.variant,
                     block=tuple(inf.block), nb=inf.nb,
                     workspace_bytes=inf.workspace_bytes, e_elems=inf.e_elems,
-                    out_elems=inf.out_elems)
+                    out_elems=inf.out_elems, channel_groups=inf.channel_groups)
 
     def set_tile(self, lx: int, ly: int, lz: int):
         check(lib().bf_set_tile(self._h, lx, ly, lz))
@@ -153,29 +169,24 @@ class Plan:
         return getattr(_torch(), _TORCH_ETYPE[self.e_type])
 
     def _check_rf(self, rf):
-        torch = _torch()
-        if rf.dtype != torch.int16 or not rf.is_cuda or not rf.is_contiguous():
-            raise ValueError("rf must be a contiguous int16 CUDA tensor")
-        if tuple(rf.shape) != self.rf_shape:
-            raise ValueError(f"rf shape {tuple(rf.shape)} != {self.rf_shape}")
+        _check_tensor(rf, "rf", _torch().int16, self.rf_shape)
 
-    def _check_e(self, e):
+    def _check_e(self, e, name="e", device=None):
         """Number of stacked frames of e: None for one frame of the plan's
         shape, F for an (F, *e_shape) stack."""
-        if e.dtype != self.e_dtype() or not e.is_cuda or not e.is_contiguous():
-            raise ValueError(f"e must be a contiguous {self.e_dtype()} CUDA tensor")
+        _check_tensor(e, name, self.e_dtype(), device=device)
         if tuple(e.shape) == self.e_shape:
             return None
         if e.dim() == len(self.e_shape) + 1 and tuple(e.shape[1:]) == self.e_shape:
             return int(e.shape[0])
-        raise ValueError("e has the wrong shape")
+        raise ValueError(f"{name} has the wrong shape")
 
     def decode(self, rf, out=None, stream=None):
         torch = _torch()
         self._check_rf(rf)
         if out is None:
             out = torch.empty(rf.shape, dtype=self.e_dtype(), device=rf.device)
-        if self._check_e(out) is not None:
+        if self._check_e(out, "out", rf.device) is not None:
             raise ValueError("out must hold one frame")
         check(lib().bf_decode(self._h, _ptr(rf), _ptr(out), _stream(stream)))
         return out
@@ -190,8 +201,7 @@ class Plan:
         shape = self.out_shape if nf is None else (nf,) + self.out_shape
         if out is None:
             out = torch.empty(shape, dtype=odt, device=e.device)
-        if out.dtype != odt or tuple(out.shape) != shape or not out.is_contiguous():
-            raise ValueError(f"out must be a contiguous {odt} tensor of shape {shape}")
+        _check_tensor(out, "out", odt, shape, e.device)
         cv = float(self.c if c is None else c)
         if nf is None:
             check(lib().bf_das(self._h, _ptr(e), _ptr(out), cv, _stream(stream)))
@@ -209,7 +219,9 @@ class Plan:
         (F, n_tx, n_ch, S)) runs bf_das_adjoint_frames: grad_e has shape
         (F, n_tx, n_ch, S) and grad_c shape (F,), one dL/dc term per frame."""
         torch = _torch()
-        nf_e = self._check_e(e) if e is not None else None
+        if not isinstance(grad_out, torch.Tensor) or not grad_out.is_cuda:
+            raise ValueError("grad_out must be a CUDA (device) tensor")
+        nf_e = self._check_e(e, "e", grad_out.device) if e is not None else None
         g = grad_out.contiguous().to(torch.float32)
         if tuple(g.shape) == self.out_shape:
             nf = None
@@ -222,10 +234,7 @@ class Plan:
         lead = () if nf is None else (nf,)
         shape_e = lead + (self.n_tx, self.n_ch, self.n_samples)
         if want_e and out_e is not None:
-            if (tuple(out_e.shape) != shape_e or out_e.dtype != torch.float32
-                    or not out_e.is_contiguous() or out_e.device != g.device):
-                raise ValueError(f"out_e must be a contiguous float32 {shape_e} "
-                                 "tensor on grad_out's device")
+            _check_tensor(out_e, "out_e", torch.float32, shape_e, g.device)
             ge = out_e
         else:
             ge = (torch.empty(shape_e, dtype=torch.float32, device=g.device)
@@ -285,16 +294,14 @@ class Demod:
         """rf: contiguous int16 CUDA tensor whose last axis is the n_samples and
         whose leading axes hold n_traces traces; returns (..., n_out, 2)."""
         torch = _torch()
-        if rf.dtype != torch.int16 or not rf.is_cuda or not rf.is_contiguous():
-            raise ValueError("rf must be a contiguous int16 CUDA tensor")
+        _check_tensor(rf, "rf", torch.int16)
         if rf.shape[-1] != self.n_samples or rf.numel() != self.n_traces * self.n_samples:
             raise ValueError("rf does not hold n_traces x n_samples samples")
         shape = tuple(rf.shape[:-1]) + (self.n_out, 2)
         dt = torch.int16 if self.out == "i16" else torch.float32
         if out is None:
             out = torch.empty(shape, dtype=dt, device=rf.device)
-        if out.dtype != dt or tuple(out.shape) != shape or not out.is_contiguous():
-            raise ValueError(f"out must be a contiguous {dt} tensor of shape {shape}")
+        _check_tensor(out, "out", dt, shape, rf.device)
         check(lib().bf_demodulate(self._h, _ptr(rf), _ptr(out), _stream(stream)))
         return out
 
@@ -327,13 +334,10 @@ class Envelope:
                  out=None, stream=None):
         torch = _torch()
         dt = torch.complex64 if self.iq else torch.float32
-        if img.dtype != dt or not img.is_cuda or not img.is_contiguous() or \
-                tuple(img.shape) != self.shape:
-            raise ValueError(f"img must be a contiguous {dt} CUDA tensor of shape {self.shape}")
+        _check_tensor(img, "img", dt, self.shape)
         if out is None:
             out = torch.empty(self.shape, dtype=torch.float32, device=img.device)
-        if out.dtype != torch.float32 or tuple(out.shape) != self.shape or not out.is_contiguous():
-            raise ValueError("out must be a contiguous float32 tensor of the image shape")
+        _check_tensor(out, "out", torch.float32, self.shape, img.device)
         check(lib().bf_envelope(self._h, _ptr(img), _ptr(out), COMPRESS[compress], float(ref),
                                 float(param), _stream(stream)))
         return out
@@ -367,14 +371,42 @@ class BatchPlan:
     def _ptrs(self, tensors):
         return (ctypes.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
 
+    def _check_frames(self, rfs, outs):
+        """One int16 RF tensor and one float32 output tensor per frame, of the
+        frame's shapes, all on one device (the library reads n_frames
+        pointers from each list)."""
+        torch = _torch()
+        rfs, outs = list(rfs), list(outs)
+        n = len(self.descs)
+        if len(rfs) != n or len(outs) != n:
+            raise ValueError(f"need {n} rf and {n} out tensors, got {len(rfs)} and {len(outs)}")
+        dev = rfs[0].device if n and isinstance(rfs[0], torch.Tensor) else None
+        for f, (d, r, o) in enumerate(zip(self.descs, rfs, outs)):
+            iq = bool(d.get("iq", False))     # (the library refuses IQ frames in a batch)
+            shape_rf = (int(d["n_tx"]), int(d["n_ch"]), int(d["n_samples"])) + ((2,) if iq else ())
+            _check_tensor(r, f"rfs[{f}]", torch.int16, shape_rf, dev)
+            _check_tensor(o, f"outs[{f}]", torch.complex64 if iq else torch.float32,
+                          self.out_shapes[f], dev)
+        return rfs, outs
+
     def run(self, rfs, outs, stream=None):
+        rfs, outs = self._check_frames(rfs, outs)
         check(lib().bf_batch_run(self._h, self._ptrs(rfs), self._ptrs(outs), _stream(stream)))
 
     def graph_launch(self, rfs, outs, stream=None):
+        rfs, outs = self._check_frames(rfs, outs)
         check(lib().bf_graph_launch(self._h, self._ptrs(rfs), self._ptrs(outs), _stream(stream)))
 
     def autotune(self, cache_path: str | None = None):
         check(lib().bf_autotune(self._h, cache_path.encode() if cache_path else None))
+
+    def frame_info(self, frame: int) -> dict:
+        """How the batched path runs a frame (after the first run/graph_launch)."""
+        inf = BatchFrameInfo()
+        check(lib().bf_batch_get_frame_info(self._h, int(frame), ctypes.byref(inf)))
+        return dict(das_path=BATCH_PATHS[inf.das_path], das_class=inf.das_class,
+                    channel_groups=inf.channel_groups, decode_class=inf.decode_class,
+                    das_items=inf.das_items)
 
     def set_das_config(self, variant: str = "lds", block=(4, 4, 1), nb: int = 16):
         """As Plan.set_das_config, for every frame (before the first launch)."""
@@ -385,6 +417,8 @@ class BatchPlan:
 def sharpness(img, grad: bool = True, stream=None):
     """Negative normalised L4 norm per image of a (n_images, ...) float32 tensor."""
     torch = _torch()
+    if not isinstance(img, torch.Tensor) or not img.is_cuda:
+        raise ValueError("img must be a CUDA (device) tensor")
     x = img.contiguous()
     if x.dtype != torch.float32:
         raise ValueError("img must be float32")

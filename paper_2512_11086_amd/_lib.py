@@ -10,7 +10,7 @@ import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbf.so")
-ABI_VERSION = 5     # the bf.h version these structures and signatures follow
+ABI_VERSION = 6     # the bf.h version these structures and signatures follow
 
 BF_OK = 0
 BF_ERR_NULL, BF_ERR_SHAPE = -1, -2
@@ -63,8 +63,16 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n_frames", ctypes.c_int32), ("tile", ctypes.c_int32 * 3),
                 ("variant", ctypes.c_int32), ("block", ctypes.c_int32 * 3), ("nb", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_int64), ("e_elems", ctypes.c_int64),
-                ("out_elems", ctypes.c_int64)]
+                ("out_elems", ctypes.c_int64), ("channel_groups", ctypes.c_int32)]
 
+
+class BatchFrameInfo(ctypes.Structure):
+    _fields_ = [("das_path", ctypes.c_int32), ("das_class", ctypes.c_int32),
+                ("channel_groups", ctypes.c_int32), ("decode_class", ctypes.c_int32),
+                ("das_items", ctypes.c_int64)]
+
+
+BATCH_PATHS = {0: "persistent_lds", 1: "gather"}
 
 _lib = None
 
@@ -98,7 +106,9 @@ def lib():
         "bf_sharpness": ([vp, i64, i32, vp, vp, vp], ctypes.c_int),
         "bf_batch_run": ([vp, P(vp), P(vp), vp], ctypes.c_int),
         "bf_graph_launch": ([vp, P(vp), P(vp), vp], ctypes.c_int),
-        "bf_hann_poly": ([dbl], dbl),
+        "bf_batch_get_frame_info": ([vp, i32, P(BatchFrameInfo)], ctypes.c_int),
+        "bf_test_hann_poly": ([dbl], dbl),
+        "bf_test_set_stack_cap": ([vp, i32], ctypes.c_int),
         "bf_demod_create": ([P(DemodParams), P(vp)], ctypes.c_int),
         "bf_demod_destroy": ([vp], ctypes.c_int),
         "bf_demod_out_samples": ([vp, P(i32)], ctypes.c_int),
@@ -127,8 +137,9 @@ EXPORTED = ("bf_abi_version", "bf_last_error", "bf_validate", "bf_plan_create",
             "bf_plan_create_batch", "bf_plan_destroy", "bf_plan_get_info", "bf_autotune",
             "bf_set_tile", "bf_set_das_config", "bf_decode", "bf_das", "bf_das_adjoint",
             "bf_das_frames", "bf_das_adjoint_frames", "bf_sharpness",
-            "bf_batch_run", "bf_graph_launch", "bf_hann_poly", "bf_demod_create",
+            "bf_batch_run", "bf_graph_launch", "bf_batch_get_frame_info", "bf_demod_create",
             "bf_demod_destroy", "bf_demod_out_samples", "bf_demodulate", "bf_env_create",
             "bf_env_destroy", "bf_envelope")
+TEST_HOOKS = ("bf_test_hann_poly", "bf_test_set_stack_cap")   # include/bf_test.h
 COMPRESS = {"none": 0, "log": 1, "power": 2}
 VARIANTS = {"lds": 0, "gather": 1, "lds2": 2}   # BF_DAS_LDS, BF_DAS_GATHER, BF_DAS_LDS_Z2

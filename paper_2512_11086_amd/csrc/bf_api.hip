@@ -12,6 +12,7 @@
 #include "bf.h"
 #include "bf_common.h"
 #include "bf_plan.h"
+#include "bf_test.h"
 
 namespace bf {
 hipError_t launch_decode_mfma(const DecodeArgs &a, int kb, int etype, hipStream_t s);
@@ -655,12 +656,20 @@ int Frame::das_adjoint(const void *e, const float *grad_out, double c, float *gr
                                      c_lds || !grad_c ? nullptr : grad_c + f, s);
         }
     }
-    if (err == hipSuccess && e_lds)
-        err = launch_das_lds_adjoint(ae, ce, p.mode, p.interp, nullptr, s, nf);
+    // frames per launch: the whole stack, or as many as the cap allows
+    const int cap = stack_cap > 0 ? stack_cap : nf;
+    if (e_lds) {
+        const int k = std::min(nf, cap);
+        for (int f0 = 0; f0 < nf && err == hipSuccess; f0 += k)
+            err = launch_das_lds_adjoint(at_frame(ae, f0), ce, p.mode, p.interp, nullptr, s,
+                                         std::min(k, nf - f0));
+    }
     if (err == hipSuccess && c_lds) {
         DasArgs ac = a;
         ac.grad_e = nullptr;
-        const int k = (int)std::min<long>(nf, max_blocks / ((long)xcd_slab_grid(cc) * a.groups));
+        // (the dL/dc partials of a launch must fit the plan's partial buffer)
+        const int k = (int)std::min<long>(
+            std::min(nf, cap), max_blocks / ((long)xcd_slab_grid(cc) * a.groups));
         for (int f0 = 0; f0 < nf && err == hipSuccess; f0 += k)
             err = launch_das_lds_adjoint(at_frame(ac, f0), cc, p.mode, p.interp, grad_c + f0, s,
                                          std::min(k, nf - f0));
@@ -779,6 +788,7 @@ int bf_plan_get_info(bf_plan plan, bf_plan_info *info)
     info->workspace_bytes = plan->workspace_bytes();
     info->e_elems = f.e_elems();
     info->out_elems = f.out_elems();
+    info->channel_groups = f.groups;
     return BF_OK;
 }
 
@@ -894,6 +904,16 @@ int bf_sharpness(const float *img, int64_t n_per_image, int32_t n_images, float 
     return err == hipSuccess ? BF_OK : hip_fail(err, "sharpness launch");
 }
 
-double bf_hann_poly(double u2) { return (double)hann_u2((float)u2); }
+double bf_test_hann_poly(double u2) { return (double)hann_u2((float)u2); }
+
+int bf_test_set_stack_cap(bf_plan plan, int32_t cap)
+{
+    g_err.clear();
+    int st = check_plan(plan);
+    if (st != BF_OK) return st;
+    if (cap < 0) return fail(BF_ERR_SHAPE, "stack cap must be >= 0");
+    for (Frame *f : plan->frames) f->stack_cap = cap;
+    return BF_OK;
+}
 
 }  // extern "C"

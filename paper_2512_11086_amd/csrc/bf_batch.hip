@@ -70,6 +70,7 @@ struct Batch {
     std::vector<DasClass> das;
     std::vector<int> gather_frames;   // frames on the gather kernel (no LDS fit, or a class too
                                       // small to fill the chip)
+    std::vector<bf_batch_frame_info> info;   // how each frame runs
     void **h_stage[RING] = {};
     hipEvent_t ev[RING] = {};
     int ring = 0;
@@ -145,6 +146,12 @@ static int build_batch(bf_plan plan)
         a.groups = 1;
         a.part = nullptr;
         LdsCfg c;
+        bf_batch_frame_info fi;
+        fi.das_path = BF_BATCH_GATHER;
+        fi.das_class = -1;
+        fi.channel_groups = 1;
+        fi.decode_class = -1;
+        fi.das_items = 0;
         if (!lds_ok[f] || !fr.lds_config(a, &c)) {
             b->gather_frames.push_back(f);
             memset(&c, 0, sizeof c);
@@ -170,6 +177,9 @@ static int build_batch(bf_plan plan)
             const int nblk = c.blocks_x * c.blocks_y * c.blocks_z;
             const double cost = (double)fr.p.n_tx * fr.p.n_ch * threads;
             for (int q = 0; q < nblk; ++q) cls->items.push_back({cost, q % c.blocks_z, make_int2(f, q)});
+            fi.das_path = BF_BATCH_PERSISTENT_LDS;
+            fi.das_class = (int)(cls - b->das.data());
+            fi.das_items = nblk;
         }
         fdas[f].a = a;
         fdas[f].c = c;
@@ -189,7 +199,10 @@ static int build_batch(bf_plan plan)
             const int n_cg = (n_chunks + 3) / 4;
             for (int j = 0; j < fr.p.n_ch; ++j)
                 for (int g = 0; g < n_cg; ++g) cls->items.push_back(make_int2(f, j * n_cg + g));
+            fi.decode_class = (int)(cls - b->dec.data());
         }
+        if (fi.das_path == BF_BATCH_GATHER) fi.das_items = 1;   // one launch of the gather kernel
+        b->info.push_back(fi);
     }
     const int n_counters = (int)(b->dec.size() + b->das.size() * N_XCD_QUEUES);
     b->d_fdec = (FrameDec *)b->alloc(sizeof(FrameDec) * F);
@@ -502,6 +515,19 @@ int bf_graph_launch(bf_plan plan, const int16_t *const *rf, float *const *out, v
             return hip_fail(e, "graph instantiate");
     }
     if ((e = hipGraphLaunch(b->exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+    return BF_OK;
+}
+
+int bf_batch_get_frame_info(bf_plan plan, int32_t frame, bf_batch_frame_info *info)
+{
+    clear_err();
+    if (!plan) return fail(BF_ERR_NULL, "plan is NULL");
+    if (plan->magic != BF_PLAN_MAGIC) return fail(BF_ERR_STATE, "not a live plan");
+    if (!info) return fail(BF_ERR_NULL, "info is NULL");
+    if (!plan->batch) return fail(BF_ERR_STATE, "no batched launch yet");
+    if (frame < 0 || frame >= (int32_t)plan->batch->info.size())
+        return fail(BF_ERR_SHAPE, "frame %d outside the batch", frame);
+    *info = plan->batch->info[frame];
     return BF_OK;
 }
 

@@ -32,6 +32,7 @@ struct Frame {
     float tx_x0 = 0.f, tx_inv_dx = 0.f;
     double tpw_smax = 0.0;       // TPW: largest |sin| of the transmit angles
     int groups = 1;              // channel groups of the DAS launch (small grids)
+    int stack_cap = 0;           // frames per adjoint launch of a stack (0: no cap)
     float *d_part = nullptr;     // [groups][points] partial images
     float2 *d_hann = nullptr;    // Hann weight table (HANN_N + 1 entries)
     long max_blocks = 0;

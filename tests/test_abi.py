@@ -19,8 +19,8 @@ from synth import configs, hadamard_sylvester
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared_functions():
-    src = open(os.path.join(ROOT, "include", "bf.h")).read()
+def _declared_functions(header="bf.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(bf_\w+)\s*\(", src, flags=re.M)))
 
@@ -32,6 +32,10 @@ def test_library_exports_every_declared_function():
     for name in names:
         assert hasattr(L, name), f"{name} declared in bf.h but not exported"
     assert set(names) == set(_lib.EXPORTED)
+    hooks = _declared_functions("bf_test.h")
+    assert set(hooks) == set(_lib.TEST_HOOKS)
+    for name in hooks:
+        assert hasattr(L, name), f"{name} declared in bf_test.h but not exported"
     # the binding, the header and the library agree on the ABI version
     with open(os.path.join(ROOT, "include", "bf.h")) as fp:
         text = fp.read()
@@ -162,16 +166,19 @@ def test_device_calls_fail_cleanly_without_gpu():
     assert L.bf_das_frames(None, None, 2, None, 1540.0, None) == -1
     assert L.bf_das_adjoint_frames(None, None, None, 2, 1540.0, None, None, None) == -1
     assert L.bf_sharpness(None, 1, 1, None, None, None) == -1
+    assert L.bf_batch_get_frame_info(None, 0, None) == -1
+    assert L.bf_test_set_stack_cap(None, 1) == -1
 
 
 def test_hann_polynomial_matches_window():
-    # The library's polynomial in u^2 against Eq. 3 evaluated directly.
+    # The library's polynomial in u^2 (test hook) against Eq. 3 evaluated directly.
+    poly = _lib.lib().bf_test_hann_poly
     u = np.linspace(0.0, 0.5, 2001)[:-1]
     want = np.cos(np.pi * u) ** 2
-    got = np.array([bfm.hann_poly(v * v) for v in u])
+    got = np.array([poly(v * v) for v in u])
     assert np.max(np.abs(got - want)) < 3e-7
-    assert bfm.hann_poly(0.0) == 1.0
-    assert abs(bfm.hann_poly(0.25)) < 1e-6
+    assert poly(0.0) == 1.0
+    assert abs(poly(0.25)) < 1e-6
 
 
 def test_validate_iq_descriptions():

@@ -246,6 +246,32 @@ def test_large_stack(torch_mod):
         assert float(gc[f]) == float(gc1), f
 
 
+@pytest.mark.parametrize("cap", [1, 2])
+def test_stack_split_over_launches(torch_mod, cap):
+    """A stack taken in several launches per gradient (the frame cap, which
+    production sizes reach only with very long stacks, forced through the
+    test hook): 5 frames in launches of `cap` frames give grad_c bit for bit
+    and grad_e up to the order of FP32 atomics of the single-frame calls, and
+    the same as the uncapped stack."""
+    torch = torch_mod
+    d = _desc("forces", "cubic")
+    H, e = _frames(d, 5, 71)
+    plan = bfm.Plan(d, H)
+    et = torch.from_numpy(e.astype(np.float32)).cuda()
+    Gt = torch.from_numpy(np.random.default_rng(8).normal(
+        size=(5,) + plan.out_shape).astype(np.float32)).cuda()
+    ge_all, gc_all = plan.das_adjoint(et, Gt)
+    _lib.check(_lib.lib().bf_test_set_stack_cap(plan._h, cap))
+    ge, gc = plan.das_adjoint(et, Gt)
+    _lib.check(_lib.lib().bf_test_set_stack_cap(plan._h, 0))
+    assert torch.equal(gc, gc_all)
+    assert rel_l2(ge.cpu().numpy(), ge_all.cpu().numpy()) < 1e-6
+    for f in range(5):
+        ge1, gc1 = plan.das_adjoint(et[f], Gt[f])
+        assert float(gc[f]) == float(gc1), (cap, f)
+        assert rel_l2(ge[f].cpu().numpy(), ge1.cpu().numpy()) < 1e-6, (cap, f)
+
+
 @pytest.mark.parametrize("e_type", ["bf16", "i32"])
 def test_frames_storage_types(torch_mod, e_type):
     """Stacks of BF16 / int32 decoded data: frame offsets in their element

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define BF_ABI_VERSION 6
+#define BF_ABI_VERSION 7
 
 /* Largest frame count of bf_das_frames / bf_das_adjoint_frames. */
 #define BF_MAX_FRAMES 4096
@@ -236,6 +236,22 @@ int bf_decode(bf_plan plan, const int16_t *rf, void *e, void *stream);
  * the autofocus loop varies it).  Accumulation is FP32 in a fixed order per
  * point, so repeated calls give bit-identical results. */
 int bf_das(bf_plan plan, const void *e, float *out, double c, void *stream);
+
+/* bf_das for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result bit for bit, but the partial images of a
+ * channel-split launch (grids with fewer than 8192 wavefronts of points; see
+ * bf_plan_info.channel_groups) go to a static device array of
+ * BF_DAS_NOALLOC_MAX_BYTES per GPU, which the library holds until the process
+ * ends, instead of plan memory.  The call itself allocates nothing (the plan
+ * is created beforehand, with its tables).  Every call on a GPU shares that
+ * GPU's array, so calls that overlap on one GPU (other streams, other host
+ * threads) race; calls queued on one stream do not.  The current device must
+ * be the plan's (BF_ERR_STATE otherwise).  BF_ERR_TOO_LARGE if the plan's
+ * partial images exceed the array (the channel split keeps them below 8 MiB
+ * for every plan).  Other errors as bf_das. */
+#define BF_DAS_NOALLOC_MAX_BYTES (8u << 20)
+int bf_das_noalloc(bf_plan plan, const void *e, float *out, double c, void *stream);
 
 /* Adjoint of bf_das for the same e and c, given grad_out = dL/d(out)
  * (device f32 [Ny][Nx][Nz]).  The paper defines only the forward sum (Eq. 1

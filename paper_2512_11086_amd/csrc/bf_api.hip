@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -587,9 +588,10 @@ bool Frame::z2_ok() const
     return p.mode == BF_HERCULES_3D && !p.iq && grid.az[0] == 0.0 && grid.az[1] == 0.0;
 }
 
-int Frame::das(const void *e, float *out, double c, hipStream_t s) const
+int Frame::das(const void *e, float *out, double c, hipStream_t s, float *part) const
 {
-    const DasArgs a = das_args(e, out, c);
+    DasArgs a = das_args(e, out, c);
+    if (part) a.part = part;
     LdsCfg cfg;
     hipError_t err;
     if (variant != BF_DAS_GATHER && lds_config(a, &cfg))
@@ -675,6 +677,35 @@ int Frame::das_adjoint(const void *e, const float *grad_out, double c, float *gr
                                          std::min(k, nf - f0));
     }
     return err == hipSuccess ? BF_OK : hip_fail(err, "DAS adjoint launch");
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of bf_das_noalloc: the partial images of a channel-split DAS launch
+// live in this file-scope device array instead of plan memory.  Each device
+// holds its own copy (at its own address) for the life of the process.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): the device address is looked up once per device
+// with hipGetSymbolAddress and kept in g_scratch.
+// ---------------------------------------------------------------------------
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static __device__ __align__(256) float scratch[BF_DAS_NOALLOC_MAX_BYTES / sizeof(float)];
+static std::mutex g_scratch_mu;
+static float *g_scratch[SCRATCH_MAX_DEVICES];
+
+// Device address of this device's scratch array (dev must be current).
+static int scratch_ptr(int dev, float **out)
+{
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+        return fail(BF_ERR_UNSUPPORTED, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch[dev] = static_cast<float *>(p);
+    }
+    *out = g_scratch[dev];
+    return BF_OK;
 }
 
 }  // namespace bf
@@ -853,6 +884,31 @@ int bf_das(bf_plan plan, const void *e, float *out, double c, void *stream)
     if (!e || !out) return fail(BF_ERR_NULL, "e and out must be non-NULL");
     if ((st = check_c(c)) != BF_OK) return st;
     return plan->frames[0]->das(e, out, c, (hipStream_t)stream);
+}
+
+int bf_das_noalloc(bf_plan plan, const void *e, float *out, double c, void *stream)
+{
+    g_err.clear();
+    int st = check_plan(plan);
+    if (st != BF_OK) return st;
+    if (!e || !out) return fail(BF_ERR_NULL, "e and out must be non-NULL");
+    if ((st = check_c(c)) != BF_OK) return st;
+    int dev = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) return hip_fail(he, "hipGetDevice");
+    if (dev != plan->device)
+        return fail(BF_ERR_STATE, "current device %d is not the plan's device %d", dev,
+                    plan->device);
+    const Frame &f = *plan->frames[0];
+    float *part = nullptr;
+    if (f.groups > 1) {
+        const uint64_t need = (uint64_t)f.groups * (uint64_t)f.out_elems() * sizeof(float);
+        if (need > BF_DAS_NOALLOC_MAX_BYTES)
+            return fail(BF_ERR_TOO_LARGE, "partial images need %llu bytes, the scratch holds %u",
+                        (unsigned long long)need, (unsigned)BF_DAS_NOALLOC_MAX_BYTES);
+        if ((st = scratch_ptr(dev, &part)) != BF_OK) return st;
+    }
+    return f.das(e, out, c, (hipStream_t)stream, part);
 }
 
 int bf_das_adjoint(bf_plan plan, const void *e, const float *grad_out, double c, float *grad_e,

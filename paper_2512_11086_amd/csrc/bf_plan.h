@@ -60,7 +60,8 @@ struct Frame {
     void adjoint_e_tile(DasArgs *a, int bw_out[3]) const;   // the RF gradient's lane tile
     bool z2_ok() const;          // two depth points per lane apply to this frame
     int decode(const int16_t *rf, void *e, hipStream_t s) const;
-    int das(const void *e, float *out, double c, hipStream_t s) const;
+    // part: partial images of a channel-split launch (nullptr: the plan's own)
+    int das(const void *e, float *out, double c, hipStream_t s, float *part = nullptr) const;
     DasArgs at_frame(const DasArgs &a, int f0) const;
     int das_frames(const void *e, int nf, float *out, double c, hipStream_t s) const;
     int das_adjoint(const void *e, const float *grad_out, double c, float *grad_e, float *grad_c,

@@ -167,6 +167,7 @@ def test_device_calls_fail_cleanly_without_gpu():
     assert L.bf_das_adjoint_frames(None, None, None, 2, 1540.0, None, None, None) == -1
     assert L.bf_sharpness(None, 1, 1, None, None, None) == -1
     assert L.bf_batch_get_frame_info(None, 0, None) == -1
+    assert L.bf_das_noalloc(None, None, None, ctypes.c_double(1540.0), None) == -1
     assert L.bf_test_set_stack_cap(None, 1) == -1
 
 

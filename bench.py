@@ -367,20 +367,32 @@ def batched_comparison(torch, bfm, stream4, reps: int):
     ms_das = timed(das_only)
     ms_ps = timed(lambda: bp.run(rf_d, outs_b))
     ms_gr = timed(lambda: bp.graph_launch(rf_d, outs_g))
+    # the same stream with tiles autotuned per problem-shape class (no cache:
+    # every class is timed on the device)
+    t = time.perf_counter()
+    bp_t = bfm.BatchPlan(descs, Hs)
+    bp_t.autotune(None)
+    tune_s = time.perf_counter() - t
+    outs_t = [torch.empty(s, device=dev) for s in bp_t.out_shapes]
+    ms_gt = timed(lambda: bp_t.graph_launch(rf_d, outs_t))
     worst = 0.0
-    for a_, b_, c_ in zip(outs_p, outs_b, outs_g):
+    for a_, b_, c_, d_ in zip(outs_p, outs_b, outs_g, outs_t):
         worst = max(worst, float((a_ - b_).norm() / a_.norm().clamp_min(1e-30)),
-                    float((b_ - c_).norm() / b_.norm().clamp_min(1e-30)))
+                    float((b_ - c_).norm() / b_.norm().clamp_min(1e-30)),
+                    float((b_ - d_).norm() / b_.norm().clamp_min(1e-30)))
     paths = [bp.frame_info(f) for f in range(len(descs))]
     nominal = sum(int(np.prod(d["dims"])) * d["n_tx"] * d["n_ch"] for d in descs)
     n3 = sum(1 for d in descs if d["mode"] == "hercules")
     log(f"batched: per-frame {ms_pf:.2f} ms (decode {ms_dec:.2f}, DAS {ms_das:.2f}), "
-        f"persistent {ms_ps:.2f} ms, graph {ms_gr:.2f} ms")
+        f"persistent {ms_ps:.2f} ms, graph {ms_gr:.2f} ms, autotuned graph {ms_gt:.2f} ms "
+        f"(tuning {tune_s:.1f} s)")
     return {"frames": len(descs), "frames_3d": n3, "nominal_G_samples": round(nominal / 1e9, 2),
             "per_frame_ms": round(ms_pf, 3), "per_frame_decode_ms": round(ms_dec, 3),
             "per_frame_das_ms": round(ms_das, 3), "persistent_ms": round(ms_ps, 3),
-            "graph_ms": round(ms_gr, 3),
+            "graph_ms": round(ms_gr, 3), "autotuned_graph_ms": round(ms_gt, 3),
+            "autotune_s": round(tune_s, 1),
             "speedup_graph_vs_per_frame": round(ms_pf / ms_gr, 3),
+            "speedup_autotuned_graph_vs_per_frame": round(ms_pf / ms_gt, 3),
             "speedup_persistent_vs_per_frame": round(ms_pf / ms_ps, 3),
             "graph_G_samples_per_s": round(nominal / (ms_gr * 1e-3) / 1e9, 1),
             "frames_on_persistent_lds": sum(1 for p in paths if p["das_path"] == "persistent_lds"),
@@ -646,7 +658,26 @@ def n4_workloads(torch, bfm, synth, reps: int = 2):
     b.record(stream)
     torch.cuda.synchronize()
     res["cross_plane_graph_ms"] = round(a.elapsed_time(b) / reps, 3)
-    res["cross_plane"] = "FORCES x-z (columns) + y-z (rows) planes, 256x256 each, one graph"
+    # the same pair as plain per-frame calls (decode + DAS of each plane)
+    plans = [bfm.Plan(d, H) for d, H in zip(descs, Hs)]
+    es = [p.decode(r) for p, r in zip(plans, rf_d)]
+    outs_p = [p.das(e) for p, e in zip(plans, es)]
+
+    def per_frame():
+        for p, r, e, o in zip(plans, rf_d, es, outs_p):
+            p.decode(r, out=e)
+            p.das(e, out=o)
+
+    per_frame()
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(reps):
+        per_frame()
+    b.record(stream)
+    torch.cuda.synchronize()
+    res["cross_plane_per_frame_ms"] = round(a.elapsed_time(b) / reps, 3)
+    res["cross_plane"] = ("FORCES x-z (columns) + y-z (rows) planes, 256x256 each, 128 tx x 128 ch "
+                          "x 2048: one graph of the batched path vs per-frame calls")
     return res
 
 

@@ -141,11 +141,11 @@ typedef struct bf_plan_s *bf_plan;   /* opaque, owned by libbf */
 
 /* DAS kernel variants: LDS-staged trace windows, the direct gather kernel
  * (used automatically when a window would not fit in LDS), or LDS-staged
- * windows with two adjacent depth points per lane (HERCULES plans with real
- * data; a wavefront then covers tile[0] x tile[1] x 2 tile[2] points, the
- * default for such plans; a grid whose depth axis is not along the array
- * normal runs BF_DAS_LDS instead, as bf_plan_get_info reports).  Results
- * agree to FP32 rounding; the variants differ only in speed. */
+ * windows with two adjacent depth points per lane (HERCULES and FORCES plans
+ * with real data; a wavefront then covers tile[0] x tile[1] x 2 tile[2]
+ * points, the default for such plans; a grid whose depth axis is not along
+ * the array normal runs BF_DAS_LDS instead, as bf_plan_get_info reports).
+ * Results agree to FP32 rounding; the variants differ only in speed. */
 enum { BF_DAS_LDS = 0, BF_DAS_GATHER = 1, BF_DAS_LDS_Z2 = 2 };
 
 /* Read-only facts about a plan. */
@@ -208,8 +208,9 @@ int bf_set_tile(bf_plan plan, int32_t log2_x, int32_t log2_y, int32_t log2_z);
 
 /* Select the DAS kernel and its LDS workgroup: variant BF_DAS_*, wavefront
  * tiles per workgroup (product 1..16; bw_y = 1 for 2D plans) and traces per
- * staged batch nb (4..64, multiple of 4).  Applies to every frame;
- * BF_DAS_LDS_Z2 on a frame that is not HERCULES with real data is
+ * staged batch nb (4..64, multiple of 4; FORCES, TPW and VLS round it down
+ * to a multiple of their rows per batch, 4).  Applies to every frame;
+ * BF_DAS_LDS_Z2 on a frame that is not HERCULES or FORCES with real data is
  * BF_ERR_UNSUPPORTED; after the first bf_batch_run / bf_graph_launch of the
  * plan it is BF_ERR_STATE. */
 int bf_set_das_config(bf_plan plan, int32_t variant, int32_t bw_x, int32_t bw_y, int32_t bw_z,

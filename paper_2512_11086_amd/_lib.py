@@ -9,7 +9,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbf.so")
+# BF_LIBRARY names another build of the same library (e.g. one with host-code
+# sanitizers); the default is the in-tree build.
+LIB_PATH = os.environ.get("BF_LIBRARY") or os.path.join(_HERE, "libbf.so")
 ABI_VERSION = 7     # the bf.h version these structures and signatures follow
 
 BF_OK = 0

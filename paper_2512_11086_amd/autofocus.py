@@ -11,9 +11,10 @@ negative normalised L4 norm -sum I^4 / (sum I^2)^2 per image.
 with the exact gradient.  Frames given as a list are beamformed one by one,
 each under torch.utils.checkpoint, so its image is recomputed in backward
 instead of being kept alive (the memory of a batch stays at one image).
-Frames given as one stacked tensor (F, n_tx, n_ch, S) are beamformed, and
-their adjoint run, in one launch for all F (bf_das_frames,
-bf_das_adjoint_frames), which fills the device far better for small grids.
+Frames given as one stacked tensor (F, n_tx, n_ch, S) go through the
+frame-stack entry points: the forward runs one launch per frame
+(bf_das_frames), the LDS adjoint one launch per gradient over the whole stack
+(bf_das_adjoint_frames), and the sharpness one launch for all F images.
 """
 from __future__ import annotations
 

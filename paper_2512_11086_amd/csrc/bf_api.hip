@@ -241,7 +241,7 @@ int Frame::init(const bf_params &src)
     if (p.mode == BF_FORCES_2D && (grid.ny == 1 || grid.nx == 1)) {
         // a plane: 32 x 2 points per wavefront along its lateral axis and
         // depth, 2 x 8 wavefronts per LDS workgroup (64 x 16 points), batches
-        // of 4 rows x nb/4 transmits (on the 256 x 256 plane of 64 x 64
+        // of JC rows x nb/JC transmits (on the 256 x 256 plane of 64 x 64
         // traces: DAS 193 us, dL/dc 207 us, against 197 / 228 us for 16 x 4
         // tiles in 4 x 4 wavefronts)
         if (grid.ny == 1) {
@@ -252,8 +252,13 @@ int Frame::init(const bf_params &src)
             bw[0] = 1; bw[1] = 2; bw[2] = 8;
         }
         nb = 16;
+        if (!p.iq && grid.nz >= 2) {
+            // two depth points per lane: the same 64 x 16 box from 8 wavefronts
+            variant = BF_DAS_LDS_Z2;
+            bw[2] = 4;
+        }
     } else if (p.mode == BF_TPW_3D || p.mode == BF_VLS_3D) {
-        // LDS windows, 4 rows x nb/4 transmits per batch (separable paths);
+        // LDS windows, JC rows x nb/JC transmits per batch (separable paths);
         // VLS windows are longer (the path to the line changes along x too)
         if (p.mode == BF_TPW_3D) set_tile(3, 3, 0); else set_tile(2, 3, 1);
         bw[0] = 2; bw[1] = 2; bw[2] = 3;
@@ -515,19 +520,20 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg, int adj, const int *bw_adj
     const double rx_lat = p.mode == BF_HERCULES_3D ? lat : p.mode == BF_FORCES_2D ? E[0] : E[1];
     const int guard = (int)ceil(a.k * (1.0 - srx) * rx_lat) + 3;
     const int nthr = 64 * bw[0] * bw[1] * bw[2];
-    int nbb = nb;
-    const int unit = sep ? 4 : 1;       // separable modes: 4 rows per batch
+    const int unit = sep ? JC : 1;      // separable modes: JC rows per batch
+    int nbb = std::max(nb - nb % unit, unit);
     const size_t lds_cap = lds_cap_bytes();
     const int nwaves = nthr / 64;
     // staging rounds per thread: the batch's quads dealt over the workgroup's
     // threads; the kernels unroll 2 rounds (3 with two points per lane and
-    // for the row-column modes)
-    const int max_rounds = (zp == 2 || p.mode == BF_TPW_3D || p.mode == BF_VLS_3D) ? 3 : 2;
+    // for the row-column modes, 4 for FORCES planes with two points per lane)
+    const int max_rounds = (p.mode == BF_FORCES_2D && zp == 2) ? 4
+                           : (zp == 2 || p.mode == BF_TPW_3D || p.mode == BF_VLS_3D) ? 3 : 2;
     auto rounds = [&](int n) { return (n * lmax + 64 * nwaves - 1) / (64 * nwaves); };
     const int qs = p.iq ? 2 : 1;
     const bool staged = adj == 0 || (adj & 1);    // the RF gradient alone reads no data
     while (nbb >= unit && ((staged && rounds(nbb) > max_rounds) ||
-                           lds_bytes(p.n_tx, p.n_ch, nbb, lmax, qs, guard, adj) > lds_cap))
+                           lds_bytes(p.n_tx, p.n_ch, nbb, lmax, qs, guard, adj, p.mode) > lds_cap))
         nbb -= unit;
     if (nbb < unit || nthr > 1024) return false;
     cfg->bwx = bw[0];
@@ -582,10 +588,12 @@ void Frame::adjoint_e_tile(DasArgs *a, int bw_out[3]) const
 }
 
 // Two points per lane share their lateral offset to every receiver: HERCULES
-// with real data, and the grid's depth axis along the array normal.
+// volumes and FORCES planes with real data, and the grid's depth axis along
+// the array normal.
 bool Frame::z2_ok() const
 {
-    return p.mode == BF_HERCULES_3D && !p.iq && grid.az[0] == 0.0 && grid.az[1] == 0.0;
+    return (p.mode == BF_HERCULES_3D || p.mode == BF_FORCES_2D) && !p.iq && grid.az[0] == 0.0 &&
+           grid.az[1] == 0.0;
 }
 
 int Frame::das(const void *e, float *out, double c, hipStream_t s, float *part) const
@@ -853,9 +861,10 @@ int bf_set_das_config(bf_plan plan, int32_t variant, int32_t bw_x, int32_t bw_y,
     for (Frame *f : plan->frames) {
         if (f->p.mode == BF_FORCES_2D && f->grid.ny == 1 && bw_y != 1)
             return fail(BF_ERR_SHAPE, "a 2D plan needs bw_y = 1");
-        if (variant == BF_DAS_LDS_Z2 && (f->p.mode != BF_HERCULES_3D || f->p.iq))
+        if (variant == BF_DAS_LDS_Z2 &&
+            ((f->p.mode != BF_HERCULES_3D && f->p.mode != BF_FORCES_2D) || f->p.iq))
             return fail(BF_ERR_UNSUPPORTED,
-                        "two depth points per lane: HERCULES plans with real data only");
+                        "two depth points per lane: HERCULES and FORCES plans with real data only");
     }
     for (Frame *f : plan->frames) {
         f->variant = variant;

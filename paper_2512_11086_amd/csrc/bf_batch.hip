@@ -29,6 +29,7 @@ hipError_t launch_decode_persistent(const DecLaunch &p, hipStream_t s);
 hipError_t launch_das_persistent(const PersistentLaunch &p, hipStream_t s);
 int persistent_das_blocks(int mode, int et, int ip, int zp, int threads, size_t shm);
 hipError_t launch_fill(float *p, long n, float v, hipStream_t s);
+hipError_t launch_sum_groups(const DasArgs &a, hipStream_t s);
 
 __global__ void reset_counters_kernel(int *c, int n)
 {
@@ -43,16 +44,17 @@ struct DecClass {
 };
 
 struct DasItem {
-    double cost;    // per-box cost of its frame
+    double cost;    // per-item cost of its frame
     int slab;       // box depth index (bz)
-    int2 item;      // (frame, box)
+    int grp;        // channel group
+    int4 item;      // (frame, box, channel group, -)
 };
 
 struct DasClass {
     int mode, et, ip, zp, threads;
     size_t shm = 0;
     std::vector<DasItem> items;
-    int2 *d_items = nullptr;
+    int4 *d_items = nullptr;
     int n_items = 0;
     QueueSet queues{};
     int grid = 0;
@@ -64,12 +66,13 @@ struct Batch {
     int F = 0;
     FrameDec *d_fdec = nullptr;
     FrameDas *d_fdas = nullptr;
+    std::vector<FrameDas> h_fdas;     // host copy of the DAS frame table
     void **d_ptrs = nullptr;          // [2F]: rf pointers, then out pointers
     int *d_counters = nullptr;
     std::vector<DecClass> dec;
     std::vector<DasClass> das;
-    std::vector<int> gather_frames;   // frames on the gather kernel (no LDS fit, or a class too
-                                      // small to fill the chip)
+    std::vector<int> gather_frames;   // frames on the gather kernel (windows too long for LDS)
+    std::vector<int> split_frames;    // persistent frames with channel groups (partial images)
     std::vector<bf_batch_frame_info> info;   // how each frame runs
     void **h_stage[RING] = {};
     hipEvent_t ev[RING] = {};
@@ -111,10 +114,12 @@ static int build_batch(bf_plan plan)
     (void)hipGetDevice(&dev0);
     (void)hipDeviceGetAttribute(&cus0, hipDeviceAttributeMultiprocessorCount, dev0);
     // LDS frames of a kernel class run as one persistent launch over their
-    // boxes; a class with fewer boxes than two per CU (e.g. a pair of small
-    // planes) would leave the chip idle, so its frames take the gather kernel,
-    // which splits the channel sum over workgroups instead.
-    std::vector<int> lds_ok(F, 0);
+    // (box, channel group) items.  A class with few boxes (e.g. a pair of
+    // small planes) splits the channel sum of its frames over G groups, so
+    // that it still gives about four items per CU; each group writes a
+    // partial image and a second kernel adds them in a fixed order.
+    const long target_items = 4L * cus0;
+    std::vector<int> lds_ok(F, 0), groups(F, 1);
     {
         std::vector<std::pair<long, long>> cls_boxes;   // (class key, boxes)
         std::vector<long> key(F, -1);
@@ -123,6 +128,7 @@ static int build_batch(bf_plan plan)
             DasArgs a = fr.das_args(nullptr, nullptr, fr.p.c);
             LdsCfg c;
             if (fr.variant == BF_DAS_GATHER || !fr.lds_config(a, &c)) continue;
+            lds_ok[f] = 1;
             key[f] = ((((long)fr.p.mode * 8 + fr.p.e_type) * 8 + fr.p.interp) * 4 + c.zp) * 2048 +
                      64 * c.bwx * c.bwy * c.bwz;
             const long nblk = (long)c.blocks_x * c.blocks_y * c.blocks_z;
@@ -133,7 +139,11 @@ static int build_batch(bf_plan plan)
         }
         for (int f = 0; f < F; ++f)
             for (auto &kb : cls_boxes)
-                if (key[f] >= 0 && kb.first == key[f]) lds_ok[f] = kb.second >= 2L * cus0;
+                if (key[f] >= 0 && kb.first == key[f] && kb.second < target_items) {
+                    const long G = (target_items + kb.second - 1) / kb.second;
+                    const long gmax = std::max(1, plan->frames[f]->p.n_ch / 4);
+                    groups[f] = (int)std::min<long>(std::min<long>(G, 16), gmax);
+                }
     }
     for (int f = 0; f < F; ++f) {
         Frame &fr = *plan->frames[f];
@@ -156,8 +166,15 @@ static int build_batch(bf_plan plan)
             b->gather_frames.push_back(f);
             memset(&c, 0, sizeof c);
         } else {
+            const int G = groups[f];
+            if (G > 1) {
+                a.groups = G;
+                a.part = (float *)b->alloc((size_t)G * fr.out_elems() * sizeof(float));
+                if (!a.part) return fail(BF_ERR_HIP, "partial-image allocation failed");
+                b->split_frames.push_back(f);
+            }
             const int threads = 64 * c.bwx * c.bwy * c.bwz;
-            const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, 1, c.guard, 0);
+            const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, 1, c.guard, 0, fr.p.mode);
             DasClass *cls = nullptr;
             for (DasClass &d : b->das)
                 if (d.mode == fr.p.mode && d.et == fr.p.e_type && d.ip == fr.p.interp &&
@@ -175,11 +192,15 @@ static int build_batch(bf_plan plan)
             }
             cls->shm = std::max(cls->shm, shm);
             const int nblk = c.blocks_x * c.blocks_y * c.blocks_z;
-            const double cost = (double)fr.p.n_tx * fr.p.n_ch * threads;
-            for (int q = 0; q < nblk; ++q) cls->items.push_back({cost, q % c.blocks_z, make_int2(f, q)});
+            // an item's cost: its traces times its points
+            const double cost = (double)fr.p.n_tx * fr.p.n_ch / G * threads;
+            for (int g = 0; g < G; ++g)
+                for (int q = 0; q < nblk; ++q)
+                    cls->items.push_back({cost, q % c.blocks_z, g, make_int4(f, q, g, 0)});
             fi.das_path = BF_BATCH_PERSISTENT_LDS;
             fi.das_class = (int)(cls - b->das.data());
-            fi.das_items = nblk;
+            fi.channel_groups = G;
+            fi.das_items = (int64_t)nblk * G;
         }
         fdas[f].a = a;
         fdas[f].c = c;
@@ -217,6 +238,7 @@ static int build_batch(bf_plan plan)
         (e = hipMemcpy(b->d_fdas, fdas.data(), sizeof(FrameDas) * F, hipMemcpyHostToDevice)) !=
             hipSuccess)
         return hip_fail(e, "batch table upload");
+    b->h_fdas = fdas;
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -229,32 +251,35 @@ static int build_batch(bf_plan plan)
         d.grid = std::min<int>((int)d.items.size(), cus * 8);
     }
     for (DasClass &d : b->das) {
-        // Depth slabs (frame, bz) in decreasing cost (costlier frames, then
-        // deeper slabs: wider apertures) dealt round-robin to the per-XCD
-        // queues; a slab's boxes stay together in its queue.
+        // Depth slabs (frame, channel group, bz) in decreasing cost (costlier
+        // frames, then deeper slabs: wider apertures) dealt round-robin to the
+        // per-XCD queues; a slab's boxes stay together in its queue (they
+        // stage nearly the same trace windows).
         std::stable_sort(d.items.begin(), d.items.end(), [](const DasItem &x, const DasItem &y) {
             if (x.cost != y.cost) return x.cost > y.cost;
             if (x.item.x != y.item.x) return x.item.x < y.item.x;
+            if (x.grp != y.grp) return x.grp < y.grp;
             return x.slab > y.slab;
         });
-        std::vector<std::vector<int2>> per(N_XCD_QUEUES);
+        std::vector<std::vector<int4>> per(N_XCD_QUEUES);
         int next = 0;
         for (size_t q = 0; q < d.items.size(); ++q) {
             if (q > 0 && (d.items[q].item.x != d.items[q - 1].item.x ||
+                          d.items[q].grp != d.items[q - 1].grp ||
                           d.items[q].slab != d.items[q - 1].slab))
                 next = (next + 1) % N_XCD_QUEUES;
             per[next].push_back(d.items[q].item);
         }
-        std::vector<int2> it;
+        std::vector<int4> it;
         for (int q = 0; q < N_XCD_QUEUES; ++q) {
             d.queues.off[q] = (int)it.size();
             it.insert(it.end(), per[q].begin(), per[q].end());
         }
         d.queues.off[N_XCD_QUEUES] = (int)it.size();
         d.n_items = (int)it.size();
-        d.d_items = (int2 *)b->alloc(sizeof(int2) * it.size());
+        d.d_items = (int4 *)b->alloc(sizeof(int4) * it.size());
         if (!d.d_items) return fail(BF_ERR_HIP, "batch item allocation failed");
-        if ((e = hipMemcpy(d.d_items, it.data(), sizeof(int2) * it.size(), hipMemcpyHostToDevice)) !=
+        if ((e = hipMemcpy(d.d_items, it.data(), sizeof(int4) * it.size(), hipMemcpyHostToDevice)) !=
             hipSuccess)
             return hip_fail(e, "batch item upload");
         d.grid = std::min(d.n_items, persistent_das_blocks(d.mode, d.et, d.ip, d.zp, d.threads, d.shm));
@@ -326,6 +351,15 @@ static int enqueue(bf_plan plan, hipStream_t s)
         L.out_ptrs = b->d_ptrs + b->F;
         hipError_t e = launch_das_persistent(L, s);
         if (e != hipSuccess) return hip_fail(e, "persistent DAS launch");
+    }
+    // frames split over channel groups: add their partial images in a fixed
+    // order into the output (its pointer read from the device table)
+    for (int f : b->split_frames) {
+        DasArgs a = b->h_fdas[f].a;
+        a.out = nullptr;
+        a.out_ref = reinterpret_cast<float *const *>(b->d_ptrs + b->F + f);
+        hipError_t e = launch_sum_groups(a, s);
+        if (e != hipSuccess) return hip_fail(e, "partial-image sum launch");
     }
     return BF_OK;
 }
@@ -405,6 +439,9 @@ std::vector<TileCand> candidates(const Frame &f)
         const bool along_x = f.grid.ny == 1;
         const int tiles[][2] = {{3, 3}, {2, 4}, {4, 2}, {1, 5}, {5, 1}};
         const int blocks[][2] = {{2, 2}, {4, 1}, {1, 4}, {2, 1}, {4, 4}, {2, 8}};
+        // two depth points per lane (real data): half the wavefronts per box
+        const bool z2 = !f.p.iq && f.grid.nz >= 2;
+        const int blocks2[][2] = {{2, 4}, {2, 2}, {4, 2}, {2, 8}, {4, 4}};
         for (auto &t : tiles) {
             const int lx = along_x ? t[0] : 0, ly = along_x ? 0 : t[0];
             c.push_back({lx, ly, t[1], 1, 1, 1, 4, BF_DAS_GATHER});
@@ -412,6 +449,11 @@ std::vector<TileCand> candidates(const Frame &f)
                 for (int nb : {4, 8, 16})
                     c.push_back({lx, ly, t[1], along_x ? b[0] : 1, along_x ? 1 : b[0], b[1], nb,
                                  BF_DAS_LDS});
+            if (z2)
+                for (auto &b : blocks2)
+                    for (int nb : {8, 16, 24})
+                        c.push_back({lx, ly, t[1], along_x ? b[0] : 1, along_x ? 1 : b[0], b[1],
+                                     nb, BF_DAS_LDS_Z2});
         }
     } else {
         const int tiles[][3] = {{3, 3, 0}, {2, 3, 1}, {2, 2, 2}};
@@ -462,7 +504,9 @@ bool cache_lookup(const char *path, const std::string &key, TileCand *out)
     return found;
 }
 
-__global__ void scratch_fill_kernel(float *p, long n)
+// Scratch decoded data for timing: a hash of the index scaled to the int16
+// range, stored in the plan's element type (FP32, BF16 or int32).
+__global__ void scratch_fill_kernel(void *p, long n, int et)
 {
     for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (long)gridDim.x * blockDim.x) {
@@ -470,7 +514,13 @@ __global__ void scratch_fill_kernel(float *p, long n)
         h ^= h >> 13;
         h *= 0x5bd1e995u;
         h ^= h >> 15;
-        p[q] = (float)((int)(h & 0xFFFF) - 32768);
+        const int v = (int)(h & 0xFFFF) - 32768;
+        if (et == ET_F32)
+            static_cast<float *>(p)[q] = (float)v;
+        else if (et == ET_BF16)
+            static_cast<uint16_t *>(p)[q] = (uint16_t)(__float_as_uint((float)v) >> 16);
+        else
+            static_cast<int *>(p)[q] = v;
     }
 }
 
@@ -541,34 +591,33 @@ int bf_autotune(bf_plan plan, const char *cache_path)
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
     if (e != hipSuccess) return hip_fail(e, "device query");
-    // Tune the first frame of each mode; apply to every frame of that mode.
-    for (int mode = 0; mode < 4; ++mode) {
-        Frame *f0 = nullptr;
-        for (Frame *f : plan->frames)
-            if (f->p.mode == mode) {
-                f0 = f;
-                break;
-            }
-        if (!f0) continue;
-        const std::string key = tune_key(*f0, prop.gcnArchName);
+    // Frames of one problem shape (the tune key: mode, transmits, channels,
+    // samples, grid, interpolation, element type) form a class: the first
+    // frame of each class is tuned on scratch data of its own element type
+    // and its choice applies to the whole class.
+    std::vector<std::string> keys;
+    for (Frame *f : plan->frames) keys.push_back(tune_key(*f, prop.gcnArchName));
+    std::vector<int> done(plan->frames.size(), 0);
+    for (size_t c0 = 0; c0 < plan->frames.size(); ++c0) {
+        if (done[c0]) continue;
+        Frame *f0 = plan->frames[c0];
+        const std::string &key = keys[c0];
         TileCand best{};
         bool have = cache_path && cache_lookup(cache_path, key, &best);
         if (!have) {
-            float *e_buf = nullptr, *o_buf = nullptr;
-            const size_t e_bytes = (size_t)f0->e_elems() * 4;
+            void *e_buf = nullptr;
+            float *o_buf = nullptr;
             const size_t o_bytes = (size_t)f0->out_elems() * 4;
-            if (hipMalloc(&e_buf, e_bytes) != hipSuccess) return fail(BF_ERR_HIP, "scratch alloc");
+            if (hipMalloc(&e_buf, f0->e_bytes()) != hipSuccess) return fail(BF_ERR_HIP, "scratch alloc");
             if (hipMalloc(&o_buf, o_bytes) != hipSuccess) {
                 (void)hipFree(e_buf);
                 return fail(BF_ERR_HIP, "scratch alloc");
             }
+            // (IQ data: the real and imaginary parts of a sample as two FP32 values)
             hipLaunchKernelGGL(scratch_fill_kernel, dim3(4096), dim3(256), 0, 0, e_buf,
-                               (long)f0->e_elems());
+                               (long)f0->e_elems(), f0->p.iq ? (int)ET_F32 : f0->p.e_type);
             const int saved[7] = {f0->lx, f0->ly, f0->lz, f0->bw[0], f0->bw[1], f0->bw[2], f0->nb};
             const int saved_variant = f0->variant;
-            const int saved_et = f0->p.e_type;
-            f0->p.e_type = BF_E_F32;
-            f0->variant = 0;
             hipEvent_t t0, t1;
             (void)hipEventCreate(&t0);
             (void)hipEventCreate(&t1);
@@ -605,18 +654,10 @@ int bf_autotune(bf_plan plan, const char *cache_path)
             (void)hipEventDestroy(t1);
             (void)hipFree(e_buf);
             (void)hipFree(o_buf);
-            f0->p.e_type = saved_et;
-            f0->variant = saved_variant;
-            if (best_ms >= 1e30f) {
-                f0->variant = saved_variant;
-                f0->set_tile(saved[0], saved[1], saved[2]);
-                f0->bw[0] = saved[3];
-                f0->bw[1] = saved[4];
-                f0->bw[2] = saved[5];
-                f0->nb = saved[6];
-                continue;
-            }
-            if (cache_path) {
+            if (best_ms >= 1e30f)
+                best = {saved[0], saved[1], saved[2], saved[3], saved[4], saved[5], saved[6],
+                        saved_variant};
+            else if (cache_path) {
                 FILE *fp = fopen(cache_path, "a");
                 if (fp) {
                     fprintf(fp, "%s %d %d %d %d %d %d %d %d\n", key.c_str(), best.lx, best.ly,
@@ -625,14 +666,16 @@ int bf_autotune(bf_plan plan, const char *cache_path)
                 }
             }
         }
-        for (Frame *f : plan->frames)
-            if (f->p.mode == mode) {
-                f->set_tile(best.lx, best.ly, best.lz);
-                f->bw[0] = best.bwx;
-                f->bw[1] = best.bwy;
-                f->bw[2] = best.bwz;
-                f->nb = best.nb;
-                f->variant = best.variant;
+        for (size_t f = c0; f < plan->frames.size(); ++f)
+            if (keys[f] == key) {
+                Frame *fr = plan->frames[f];
+                fr->set_tile(best.lx, best.ly, best.lz);
+                fr->bw[0] = best.bwx;
+                fr->bw[1] = best.bwy;
+                fr->bw[2] = best.bwz;
+                fr->nb = best.nb;
+                fr->variant = best.variant;
+                done[f] = 1;
             }
     }
     return BF_OK;

@@ -101,10 +101,14 @@ __host__ __device__ inline void group_rows(int n_ch, int g, int G, int *j0, int 
     *j1 = (int)(((long)n_ch * (g + 1)) / G);
 }
 
+// Channel rows per staged batch of the separable modes (FORCES, TPW, VLS):
+// a batch holds JC rows x nb / JC transmits (nb a multiple of JC).
+constexpr int JC = 4;
+
 // Workgroup configuration of the LDS-staged DAS kernel.
 struct LdsCfg {
     int bwx, bwy, bwz;   // wavefront tiles per workgroup along x, y, z
-    int nb;              // traces per batch (FORCES: 4 channel rows x nb/4 transmits)
+    int nb;              // traces per batch (separable modes: JC rows x nb/JC transmits)
     int lmax;            // coefficient quads per staged window
     int sorted_tx;       // tx_x ascending (enables the per-row transmit range)
     int blocks_x, blocks_y, blocks_z;
@@ -143,7 +147,7 @@ struct PersistentLaunch {
     int grid, threads;
     size_t shm;
     const FrameDas *frames;
-    const int2 *items;      // (frame, workgroup box), grouped by queue
+    const int4 *items;      // (frame, workgroup box, channel group, -), grouped by queue
     QueueSet queues;
     int *counters;          // one per queue
     void *const *out_ptrs;  // [n_frames] device pointers

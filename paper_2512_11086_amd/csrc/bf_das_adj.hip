@@ -77,7 +77,7 @@ template <int MODE, int IP>
 static hipError_t launch_adj_lds2(const DasArgs &a, const LdsCfg &c, int adj, int nf, size_t shm,
                                   hipStream_t s)
 {
-    if constexpr (MODE == MODE_HERCULES)
+    if constexpr (MODE == MODE_HERCULES || MODE == MODE_FORCES)
         if (c.zp == 2) return launch_adj_lds3<MODE, IP, 2>(a, c, adj, nf, shm, s);
     return c.zp == 1 ? launch_adj_lds3<MODE, IP, 1>(a, c, adj, nf, shm, s) : hipErrorInvalidValue;
 }
@@ -104,7 +104,7 @@ hipError_t launch_das_lds_adjoint(const DasArgs &a, const LdsCfg &c, int mode, i
     const int adj = (grad_c ? 1 : 0) | (a.grad_e ? 2 : 0);
     if (adj == 0) return hipSuccess;
     if (adj == 3) return hipErrorInvalidValue;
-    const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, 1, c.guard, adj);
+    const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, 1, c.guard, adj, mode);
     hipError_t err;
     if (a.grad_e) {
         err = launch_fill(a.grad_e, (long)n_frames * a.n_tx * a.n_ch * a.S, 0.f, s);

@@ -17,8 +17,10 @@ void das_lds_kernel(DasArgs a, LdsCfg c)
     das_block<MODE, ET, IP, ZP>(a, c, blk, blockIdx.y, smem);
 }
 
-// Persistent form for a batch of frames: each workgroup pulls (frame, box)
-// items from queues until they are empty.  There is one queue per XCD; the
+// Persistent form for a batch of frames: each workgroup pulls (frame, box,
+// channel group) items from queues until they are empty (a frame with
+// channel groups writes one partial image per group, summed afterwards in a
+// fixed order).  There is one queue per XCD; the
 // host deals whole depth slabs of a frame to the queues (costliest first), so
 // the workgroups on one XCD (index b runs on XCD b % 8: the grid is resident
 // at once and dispatched round-robin) work on neighbouring boxes that share
@@ -28,7 +30,7 @@ void das_lds_kernel(DasArgs a, LdsCfg c)
 template <int MODE, int ET, int IP, int ZP>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerEu<MODE, ZP>::value)))
 void das_persistent_kernel(const FrameDas *__restrict__ frames,
-                                                              const int2 *__restrict__ items,
+                                                              const int4 *__restrict__ items,
                                                               QueueSet queues, int *counters,
                                                               void *const *__restrict__ out_ptrs)
 {
@@ -47,9 +49,10 @@ void das_persistent_kernel(const FrameDas *__restrict__ frames,
             if (item >= n) break;
             const int fr = __builtin_amdgcn_readfirstlane(items[beg + item].x);
             const int blk = __builtin_amdgcn_readfirstlane(items[beg + item].y);
+            const int grp = __builtin_amdgcn_readfirstlane(items[beg + item].z);
             DasArgs a = frames[fr].a;
             a.out = static_cast<float *>(out_ptrs[fr]);
-            das_block<MODE, ET, IP, ZP>(a, frames[fr].c, blk, 0, smem);
+            das_block<MODE, ET, IP, ZP>(a, frames[fr].c, blk, grp, smem);
             __syncthreads();
         }
     }
@@ -70,7 +73,7 @@ static hipError_t launch_persistent4(const PersistentLaunch &p, hipStream_t s)
 template <int MODE, int ET, int IP>
 static hipError_t launch_persistent3(const PersistentLaunch &p, hipStream_t s)
 {
-    if constexpr (MODE == MODE_HERCULES)
+    if constexpr (MODE == MODE_HERCULES || MODE == MODE_FORCES)
         if (p.zp == 2) return launch_persistent4<MODE, ET, IP, 2>(p, s);
     return p.zp == 1 ? launch_persistent4<MODE, ET, IP, 1>(p, s) : hipErrorInvalidValue;
 }
@@ -116,7 +119,8 @@ int persistent_das_blocks(int mode, int et, int ip, int zp, int threads, size_t 
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const void *fn = nullptr;
     if (mode == 0 && et == ET_F32 && ip == IN_CUBIC)
-        fn = reinterpret_cast<const void *>(&das_persistent_kernel<0, ET_F32, IN_CUBIC, 1>);
+        fn = zp == 2 ? reinterpret_cast<const void *>(&das_persistent_kernel<0, ET_F32, IN_CUBIC, 2>)
+                     : reinterpret_cast<const void *>(&das_persistent_kernel<0, ET_F32, IN_CUBIC, 1>);
     else if (mode == 1 && et == ET_F32 && ip == IN_CUBIC)
         fn = zp == 2 ? reinterpret_cast<const void *>(&das_persistent_kernel<1, ET_F32, IN_CUBIC, 2>)
                      : reinterpret_cast<const void *>(&das_persistent_kernel<1, ET_F32, IN_CUBIC, 1>);
@@ -140,7 +144,7 @@ static hipError_t launch_lds4(const DasArgs &a, const LdsCfg &c, size_t shm, hip
 template <int MODE, int ET, int IP>
 static hipError_t launch_lds_zp(const DasArgs &a, const LdsCfg &c, size_t shm, hipStream_t s)
 {
-    if constexpr (MODE == MODE_HERCULES && ET != ET_CF32)
+    if constexpr ((MODE == MODE_HERCULES || MODE == MODE_FORCES) && ET != ET_CF32)
         if (c.zp == 2) return launch_lds4<MODE, ET, IP, 2>(a, c, shm, s);
     return c.zp == 1 ? launch_lds4<MODE, ET, IP, 1>(a, c, shm, s) : hipErrorInvalidValue;
 }
@@ -170,18 +174,21 @@ static hipError_t launch_lds_et(const DasArgs &a, const LdsCfg &c, int et, int i
     }
 }
 
-size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard, int adj)
+size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard, int adj, int mode)
 {
     const bool stage = adj == 0 || (adj & 1);     // data windows staged
-    return (size_t)(((n_tx + 3) & ~3) + ((n_ch + 3) & ~3) + 2 * ((nb + 3) & ~3)) * 4 +
-           (size_t)HANN_TAB_PAD * 8 + (stage ? (2 * (size_t)nb * lmax + guard) * qs * 16 : 0) +
+    // tx_x and rx_c (and the separable modes' path bounds: one more of each)
+    const int tables = (mode == MODE_HERCULES ? 1 : 2) * (((n_tx + 3) & ~3) + ((n_ch + 3) & ~3));
+    return (size_t)(tables + 2 * ((nb + 3) & ~3)) * 4 +
+           (mode == MODE_HERCULES ? (size_t)HANN_TAB_PAD * 8 : 0) +
+           (stage ? (2 * (size_t)nb * lmax + guard) * qs * 16 : 0) +
            ((adj & 2) ? 2 * (size_t)nb * (lmax + 3) * 8 + 16 * 4 : 0);
 }
 
 hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, int ip,
                           hipStream_t s)
 {
-    const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, a.cx ? 2 : 1, c.guard, 0);
+    const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, a.cx ? 2 : 1, c.guard, 0, mode);
     hipError_t err;
     switch (mode) {
         case MODE_FORCES: err = launch_lds_et<MODE_FORCES>(a, c, et, ip, shm, s); break;

@@ -22,9 +22,9 @@
 // Separable modes (FORCES planes, TPW and VLS row-column volumes): the delay
 // is a transmit path per (point, transmit) plus a receive path per (point,
 // channel row), and the apodization depends on the row only.  A batch holds
-// 4 rows x nb/4 transmits; each lane computes the receive path and weight of
-// a row once, the transmit path of a transmit once, and every term adds the
-// two.
+// JC rows x nb/JC transmits; each lane computes the receive path and weight
+// of a row once, the transmit path of a transmit once per batch (shared by
+// the JC rows), and every term adds the two.
 //
 // Apodization skip (Sec. VII-F): a channel row is staged only if the receive
 // aperture of the deepest point of the box reaches it; within a row only the
@@ -48,28 +48,43 @@ namespace bf {
 
 hipError_t launch_sum_groups(const DasArgs &a, hipStream_t s);
 
-constexpr int JC = 4;    // channel rows per batch of the separable modes (FORCES, TPW, VLS)
 constexpr int HANN_TAB_PAD = HANN_N + 2;   // table entries reserved in LDS (float2, keeps 16-byte alignment)
 
 // Trace slot `lane` of a batch, held by that lane of every wavefront: the
-// first sample interval of its window, the x of its transmit column, and
-// its trace index i * n_ch + j (-1 for an empty slot).  Staging lanes (and
-// the RF gradient's flush) fetch the entry of their slot with a lane
-// permute; the terms take the column from the read-only table and the
-// negated window start from a per-batch LDS array (store_w0).
+// first sample interval w0 of its window, the x of its transmit column, and
+// for staging the window start sw and the element offset off = trace * S + w0
+// of that sample in the decoded data.  sw is NO_DATA for a slot with nothing
+// to stage (an empty slot, a padding slot, or a window wholly outside the
+// record, which stages zeros), so that off stays within the data (no 32-bit
+// overflow) whenever it is used.  Staging lanes (and the RF gradient's flush)
+// fetch sw and off of their slot with a lane permute; the terms take the
+// column from the read-only table and the negated window start from a
+// per-batch LDS array (store_w0).
+constexpr int NO_DATA = -(1 << 29);
 struct TraceDesc {
     int w0;
     float xi;
-    int tr;
+    int sw;
+    int off;
 };
 
-// Uniform description of one batch.
+// Uniform description of one batch (lane_row: per lane, see Iter).
 struct BatchDesc {
     int valid;
     int i0, cnt;          // transmits i0 .. i0+cnt-1
     int j;                // HERCULES: channel row
-    int rows[JC];         // separable modes: channel rows (-1 = none)
+    int rows[JC];         // separable modes: channel rows (row_slot encoding)
+    int lane_row;         // separable modes: rows[lane % JC], the row of trace slot `lane`
 };
+
+// Row slots of the separable modes.  A chunk of JC slots holds the next
+// active channel rows; when fewer remain, the last one is repeated in the
+// free slots as a padding slot, encoded -(row + 2): it has that row's
+// geometry (so the terms read inside a staged window) but no staged data
+// (its window holds zeros) and weight 0.  Every slot is then a real row and
+// the terms of a transmit need no per-row branch.
+__device__ inline int slot_row(int v) { return v >= 0 ? v : -v - 2; }
+__device__ inline bool slot_pad(int v) { return v < 0; }
 
 struct BoxGeom {
     float xmin, xmax, ymin, ymax, zmin, zmax;
@@ -212,48 +227,61 @@ __device__ inline float far_to_range(float v, float lo, float hi)
     return fmaxf(fabsf(v - lo), fabsf(v - hi));
 }
 
-// First sample interval of the staged window of trace (transmit i, receive
-// channel at lateral coordinate cj) for the box: a lower bound of the path
-// over the box (the bound has a 2-sample margin, so the hardware square root
-// suffices).  Separable modes add the lower bounds of the transmit and the
-// receive path; the receive path of a row (TPW, VLS) or column (FORCES) is
-// at least its distance to the nearest box point at the shallowest depth.
+// Lower bounds over the box of the transmit path of transmit i (column at
+// xi) and of the receive path of the row or column at cj, for the separable
+// modes: the receive path of a row (TPW, VLS) or column (FORCES) is at least
+// its distance to the nearest box point at the shallowest depth.  A box
+// tabulates both once (tx_lo per transmit, rx_lo per channel) and a trace's
+// window starts at their sum (window_start).
 template <int MODE>
-__device__ inline int window_start(const DasArgs &a, const BoxGeom &b, int i, float xi, float cj)
+__device__ inline float tx_lo(const DasArgs &a, const BoxGeom &b, int i, float xi)
 {
     const float zlo = fmaxf(b.zmin, 0.f);
-    float path;
     if constexpr (MODE == MODE_FORCES) {
         const float rt = dist_to_range(xi, b.xmin, b.xmax);
-        const float rr = dist_to_range(cj, b.xmin, b.xmax);
-        path = __builtin_amdgcn_sqrtf(fmaf(rt, rt, zlo * zlo)) +
-               __builtin_amdgcn_sqrtf(fmaf(rr, rr, zlo * zlo));
-    } else if constexpr (MODE == MODE_HERCULES) {
-        const float rx = dist_to_range(xi, b.xmin, b.xmax);
-        const float ry = dist_to_range(cj, b.ymin, b.ymax);
-        path = b.txlo + __builtin_amdgcn_sqrtf(fmaf(rx, rx, fmaf(ry, ry, zlo * zlo)));
+        return __builtin_amdgcn_sqrtf(fmaf(rt, rt, zlo * zlo));
+    } else if constexpr (MODE == MODE_TPW) {
+        // x sin(th) + z cos(th): smallest at the box edge along sin(th), cos(th) > 0
+        const float2 sc = a.tx_sc[i];
+        return (sc.x >= 0.f ? b.xmin : b.xmax) * sc.x + zlo * (1.f + sc.y);
     } else {
-        const float ry = dist_to_range(cj, b.ymin, b.ymax);
-        float tx;
-        if constexpr (MODE == MODE_TPW) {
-            // x sin(th) + z cos(th): smallest at the box edge along sin(th), cos(th) > 0
-            const float2 sc = a.tx_sc[i];
-            tx = (sc.x >= 0.f ? b.xmin : b.xmax) * sc.x + zlo * (1.f + sc.y);
-        } else {
-            // z_f + sgn(z - z_f) |(x - x_i, z - z_f)|: with the whole box below the
-            // line the nearest point bounds it; else z_f minus the farthest reach
-            const float zf = a.zf;
-            if (zf <= zlo) {
-                const float rx = dist_to_range(xi, b.xmin, b.xmax);
-                tx = zf + __builtin_amdgcn_sqrtf(fmaf(rx, rx, (zlo - zf) * (zlo - zf)));
-            } else {
-                const float rf = far_to_range(xi, b.xmin, b.xmax);
-                tx = zf - __builtin_amdgcn_sqrtf(fmaf(rf, rf, (zf - zlo) * (zf - zlo)));
-            }
+        // z_f + sgn(z - z_f) |(x - x_i, z - z_f)|: with the whole box below the
+        // line the nearest point bounds it; else z_f minus the farthest reach
+        const float zf = a.zf;
+        if (zf <= zlo) {
+            const float rx = dist_to_range(xi, b.xmin, b.xmax);
+            return zf + __builtin_amdgcn_sqrtf(fmaf(rx, rx, (zlo - zf) * (zlo - zf)));
         }
-        path = tx + __builtin_amdgcn_sqrtf(fmaf(ry, ry, zlo * zlo));
+        const float rf = far_to_range(xi, b.xmin, b.xmax);
+        return zf - __builtin_amdgcn_sqrtf(fmaf(rf, rf, (zf - zlo) * (zf - zlo)));
     }
+}
+
+template <int MODE>
+__device__ inline float rx_lo(const BoxGeom &b, float cj)
+{
+    const float zlo = fmaxf(b.zmin, 0.f);
+    const float r = MODE == MODE_FORCES ? dist_to_range(cj, b.xmin, b.xmax)
+                                        : dist_to_range(cj, b.ymin, b.ymax);
+    return __builtin_amdgcn_sqrtf(fmaf(r, r, zlo * zlo));
+}
+
+// First sample interval of the staged window of a trace for the box, from a
+// lower bound of its path over the box (the bound has a 2-sample margin, so
+// the hardware square root suffices): HERCULES from the transmit column at xi
+// and the row at cj; the separable modes from the tabulated bounds (path =
+// tx_lo + rx_lo).
+__device__ inline int window_from_path(const BoxGeom &b, float path)
+{
     return (int)floorf(fmaf(path, b.kf, -b.t0f)) - 2;
+}
+
+__device__ inline int window_start_hercules(const BoxGeom &b, float xi, float cj)
+{
+    const float zlo = fmaxf(b.zmin, 0.f);
+    const float rx = dist_to_range(xi, b.xmin, b.xmax);
+    const float ry = dist_to_range(cj, b.ymin, b.ymax);
+    return window_from_path(b, b.txlo + __builtin_amdgcn_sqrtf(fmaf(rx, rx, fmaf(ry, ry, zlo * zlo))));
 }
 
 // Is channel row j reachable by the receive aperture of any point of the box?
@@ -290,13 +318,15 @@ __device__ inline void tx_range(const float *tx, int n, float xl, float xh, int 
     *hi = a1;
 }
 
-// Batch iterator (uniform across the workgroup).
+// Batch iterator (uniform across the workgroup, except lane_row).
 struct Iter {
     int jend;    // end of this workgroup's channel rows
-    int j;       // current channel row (HERCULES) / next row to scan (FORCES)
+    int j;       // current channel row (HERCULES) / next row to scan (separable)
     int i;       // next transmit
     int ihi;     // end of the current row's transmit range (HERCULES)
     int rows[JC];
+    int lane_row;  // rows[lane % JC] (the slots of a separable batch are
+                   // transmit-major: slot e = transmit e / JC, row e % JC)
 };
 
 template <int MODE>
@@ -335,8 +365,7 @@ __device__ inline BatchDesc next_batch(const DasArgs &a, const LdsCfg &c, const 
     } else {
         const int nbi = c.nb / JC;
         if (it.i >= a.n_tx) {             // next chunk of JC active rows
-            int n = 0;
-            for (int q = 0; q < JC; ++q) it.rows[q] = -1;
+            int n = 0, last = -1;
             while (n < JC && it.j < it.jend) {
                 float R;
                 if (row_active<MODE>(a, b, s_rx[it.j], &R)) {
@@ -344,15 +373,27 @@ __device__ inline BatchDesc next_batch(const DasArgs &a, const LdsCfg &c, const 
 #pragma unroll
                     for (int q = 0; q < JC; ++q)
                         if (q == n) it.rows[q] = it.j;
+                    last = it.j;
                     ++n;
                 }
                 ++it.j;
             }
             if (n == 0) return d;
+#pragma unroll
+            for (int q = 0; q < JC; ++q)          // padding slots (slot_row)
+                if (q >= n) it.rows[q] = -last - 2;
+            // the row of this lane's trace slot, once per chunk
+            const int lq = (threadIdx.x & 63) % JC;
+            int v = it.rows[0];
+#pragma unroll
+            for (int q = 1; q < JC; ++q)
+                if (lq == q) v = it.rows[q];
+            it.lane_row = v;
             it.i = 0;
         }
         d.valid = 1;
         for (int q = 0; q < JC; ++q) d.rows[q] = it.rows[q];
+        d.lane_row = it.lane_row;
         d.i0 = it.i;
         d.cnt = min(nbi, a.n_tx - it.i);
         it.i += d.cnt;
@@ -360,29 +401,31 @@ __device__ inline BatchDesc next_batch(const DasArgs &a, const LdsCfg &c, const 
     }
 }
 
+// Transmit i and channel row j of trace slot e = lane of batch d (j = -1: an
+// empty slot); *pad: a padding slot of the separable modes (geometry of row
+// j, no data).  Separable batches number their slots transmit-major.
 template <int MODE>
-__device__ inline void slot_trace(const BatchDesc &d, const LdsCfg &c, int e, int *i, int *j)
+__device__ inline void slot_trace(const BatchDesc &d, int e, int *i, int *j, bool *pad)
 {
     if constexpr (MODE == 1) {
         *i = d.i0 + e;
         *j = e < d.cnt ? d.j : -1;
+        *pad = false;
     } else {
-        const int nbi = c.nb / JC;
-        const int ii = e % nbi, jj = e / nbi;
-        int row = -1;
-#pragma unroll
-        for (int q = 0; q < JC; ++q)
-            if (q == jj) row = d.rows[q];
+        const int ii = e / JC;
         *i = d.i0 + ii;
-        *j = (ii < d.cnt) ? row : -1;
+        *j = ii < d.cnt ? slot_row(d.lane_row) : -1;
+        *pad = slot_pad(d.lane_row);
     }
 }
 
 // Staging rounds per thread per batch (the host keeps nb * lmax within
-// QM * 64 * wavefronts): 3 for the two-point kernel and the row-column
-// modes (longer windows), else 2.
+// QM * 64 * wavefronts): 4 for FORCES planes with two points per lane (8
+// wavefronts stage the windows of a 16-wavefront box), 3 for HERCULES with
+// two points and the row-column modes (longer windows), else 2.
 template <int MODE, int ZP> struct StageRounds {
-    static constexpr int value = (ZP == 2 || MODE == MODE_TPW || MODE == MODE_VLS) ? 3 : 2;
+    static constexpr int value = (MODE == MODE_FORCES && ZP == 2) ? 4
+                                 : (ZP == 2 || MODE == MODE_TPW || MODE == MODE_VLS) ? 3 : 2;
 };
 
 // Staging map: the nb * lmax quads of a batch are numbered trace-major and
@@ -407,20 +450,31 @@ __device__ inline bool stage_slot(const LdsCfg &c, int q, int wave, int lane, in
     return ee < c.nb;
 }
 
-// Descriptor of trace slot `lane` of batch d (see TraceDesc).
+// Descriptor of trace slot `lane` of batch d (see TraceDesc).  s_lo: the
+// box's tx_lo table (n_tx entries) and, at lo_rx, its rx_lo table
+// (separable modes).
 template <int MODE>
 __device__ inline TraceDesc trace_desc(const DasArgs &a, const LdsCfg &c, const BoxGeom &b,
-                                       const float *s_tx, const float *s_rx, const BatchDesc &d,
-                                       int lane)
+                                       const float *s_tx, const float *s_rx, const float *s_lo,
+                                       int lo_rx, const BatchDesc &d, int lane)
 {
-    TraceDesc t{0, 0.f, -1};
+    TraceDesc t{0, 0.f, NO_DATA, 0};
     if (lane < c.nb) {
         int i, j;
-        slot_trace<MODE>(d, c, lane, &i, &j);
+        bool pad;
+        slot_trace<MODE>(d, lane, &i, &j, &pad);
         if (j >= 0) {
             t.xi = s_tx[i];
-            t.w0 = window_start<MODE>(a, b, i, t.xi, s_rx[j]);
-            t.tr = i * a.n_ch + j;
+            if constexpr (MODE == MODE_HERCULES)
+                t.w0 = window_start_hercules(b, t.xi, s_rx[j]);
+            else
+                t.w0 = window_from_path(b, s_lo[i] + s_lo[lo_rx + j]);
+            // taps w0 - 1 .. w0 + lmax + 1 of the window; none inside the record:
+            // nothing to stage (and a padding slot stages zeros)
+            if (!pad && t.w0 + c.lmax + 1 >= 0 && t.w0 - 1 < a.S) {
+                t.sw = t.w0;
+                t.off = (i * a.n_ch + j) * a.S + t.w0;
+            }
         }
     }
     return t;
@@ -435,15 +489,16 @@ __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const Trace
     for (int q = 0; q < QM; ++q) {
         int e, m;
         const bool on = stage_slot(c, q, wave, lane, nwaves, &e, &m);
-        // window start and trace of slot e, from lane e
+        // window start and data offset of slot e, from lane e
         const int src = (e & 63) << 2;
-        const int w0 = __builtin_amdgcn_ds_bpermute(src, td.w0);
-        const int tr = __builtin_amdgcn_ds_bpermute(src, td.tr);
+        const int w0 = __builtin_amdgcn_ds_bpermute(src, td.sw);
+        const int off = __builtin_amdgcn_ds_bpermute(src, td.off);
         float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
         float p4 = 0.f, p5 = 0.f, p6 = 0.f, p7 = 0.f;
-        if (on && tr >= 0) {
+        if (on && w0 != NO_DATA) {
             const int n = w0 + m;
-            const void *tn = trace_ptr<ET>(trace_ptr<ET>(a.e, tr, a.S), n, 1);   // sample n
+            // sample n of the trace: element off + m (32-bit, see TraceDesc)
+            const void *tn = trace_ptr<ET>(a.e, off + m, 1);
             const unsigned S = (unsigned)a.S;
             const bool inside = w0 >= 1 && w0 + c.lmax + 1 < a.S;
             if constexpr (ET == ET_CF32) {
@@ -531,18 +586,12 @@ __device__ inline float4 coef_quad(float pm, float p0, float p1, float p2)
 }
 
 // Negated window starts of a batch's slots into LDS (wavefront 0, lane =
-// slot): HERCULES in slot order; the separable modes as [transmit][row], so
-// one 16-byte load gives the 4 rows of a transmit.
-template <int MODE>
+// slot; the separable modes' slots are [transmit][row], so two 16-byte loads
+// give the JC rows of a transmit).
 __device__ inline void store_w0(const LdsCfg &c, const TraceDesc &td, int *w, int wave, int lane)
 {
     if (wave != 0 || lane >= c.nb) return;
-    if constexpr (MODE == MODE_HERCULES) {
-        w[lane] = -td.w0;
-    } else {
-        const int nbi = c.nb / JC;
-        w[(lane % nbi) * JC + lane / nbi] = -td.w0;
-    }
+    w[lane] = -td.w0;
 }
 
 // Convert the loaded taps to coefficient quads and write them to one LDS
@@ -645,15 +694,16 @@ __device__ inline void flush_grad_e(const DasArgs &a, const LdsCfg &c, unsigned 
         const int g = base + threadIdx.x;
         // (g + 1/2) / lw is at least 1 / (2 lw) from an integer
         const int e = min((int)(((float)g + 0.5f) * inv_lw), 63);
-        const int w0 = __builtin_amdgcn_ds_bpermute(e << 2, td.w0);
-        const int tr = __builtin_amdgcn_ds_bpermute(e << 2, td.tr);
+        const int w0 = __builtin_amdgcn_ds_bpermute(e << 2, td.sw);
+        const int off = __builtin_amdgcn_ds_bpermute(e << 2, td.off);
         if (g < total) {
             const long long v = (long long)accw[g];
             if (v != 0) {
                 accw[g] = 0ull;
-                const int n = w0 - 1 + (g - e * lw);
-                if (tr >= 0 && (unsigned)n < (unsigned)a.S)
-                    unsafeAtomicAdd(a.grad_e + (long)tr * a.S + n, (float)((double)v * unit));
+                const int r = g - e * lw;          // sample w0 - 1 + r, element off - 1 + r
+                const int n = w0 - 1 + r;
+                if (w0 != NO_DATA && (unsigned)n < (unsigned)a.S)
+                    unsafeAtomicAdd(a.grad_e + (off - 1 + r), (float)((double)v * unit));
             }
         }
     }
@@ -724,24 +774,30 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     static_assert(ADJ == 0 || ET != ET_CF32, "the adjoint is defined for real data");
     constexpr bool GC = (ADJ & 1) != 0, GE = (ADJ & 2) != 0;
     constexpr bool STAGE = ADJ == 0 || GC;       // data windows needed
-    static_assert(ZP == 1 || MODE == MODE_HERCULES, "two points per lane: HERCULES only");
+    static_assert(ZP == 1 || ((MODE == MODE_HERCULES || MODE == MODE_FORCES) && ET != ET_CF32),
+                  "two points per lane: HERCULES and FORCES with real data");
     constexpr int QM = StageRounds<MODE, ZP>::value;
     const int nthr = blockDim.x;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int nwaves = nthr >> 6;
 
-    // tables: tx_x, rx_c, the window starts of the two batch buffers (negated;
-    // read by the terms with one LDS load instead of a lane broadcast), Hann
-    // weights, then two buffers of [nb * lmax] quads (the Hann table sits
-    // right before them: an index of -1 reads finite data)
+    // tables: tx_x, rx_c, the box's path bounds tx_lo, rx_lo (separable
+    // modes), the window starts of the two batch buffers (negated; read by the
+    // terms with one LDS load instead of a lane broadcast), Hann weights
+    // (HERCULES; the separable modes weight rows with the polynomial), then
+    // two buffers of [nb * lmax] quads (the Hann table sits right before
+    // them: an index of -1 reads finite data)
+    constexpr bool SEP = MODE != MODE_HERCULES;
+    const int ntx4 = (a.n_tx + 3) & ~3, nch4 = (a.n_ch + 3) & ~3;
     float *s_tx = reinterpret_cast<float *>(smem);
-    float *s_rx = s_tx + ((a.n_tx + 3) & ~3);
+    float *s_rx = s_tx + ntx4;
+    float *s_lo = s_rx + nch4;                     // [ntx4] tx_lo, then [nch4] rx_lo
     // (indexed from one base so that the compiler keeps them in LDS)
-    int *s_w0 = reinterpret_cast<int *>(s_rx + ((a.n_ch + 3) & ~3));
+    int *s_w0 = reinterpret_cast<int *>(s_lo + (SEP ? ntx4 + nch4 : 0));
     const int w0_stride = (c.nb + 3) & ~3;
     float2 *s_hann = reinterpret_cast<float2 *>(s_w0 + 2 * w0_stride);
-    float4 *bufbase = reinterpret_cast<float4 *>(s_hann + HANN_TAB_PAD);
+    float4 *bufbase = reinterpret_cast<float4 *>(s_hann + (MODE == MODE_HERCULES ? HANN_TAB_PAD : 0));
     constexpr int QS = ET == ET_CF32 ? 2 : 1;     // quads per sample interval
     const int buf_quads = STAGE ? c.nb * c.lmax * QS : 0;
     float4 *q0 = bufbase, *q1 = bufbase + buf_quads;
@@ -766,6 +822,10 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     const int bx = (blk / c.blocks_z) % c.blocks_x;
     const int by = blk / (c.blocks_z * c.blocks_x);
     const BoxGeom box = block_box(a, c, bx, by, bz);
+    if constexpr (SEP) {   // the box's path bounds (read after the barrier below)
+        for (int t = tid; t < a.n_tx; t += nthr) s_lo[t] = tx_lo<MODE>(a, box, t, a.tx_x[t]);
+        for (int t = tid; t < a.n_ch; t += nthr) s_lo[ntx4 + t] = rx_lo<MODE>(box, a.rx_c[t]);
+    }
     LaneL Lp[ZP];
 #pragma unroll
     for (int p = 0; p < ZP; ++p) Lp[p] = lane_setup_l<MODE>(a, c, bx, by, bz, wave, lane, p);
@@ -827,14 +887,14 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
 
     BatchDesc cur = next_batch<MODE>(a, c, box, s_tx, s_rx, it);
     Staged<QM> st;
-    TraceDesc td = {0, 0.f, -1};       // descriptors of the current batch
+    TraceDesc td = {0, 0.f, NO_DATA, 0};   // descriptors of the current batch
     if (cur.valid) {
-        td = trace_desc<MODE>(a, c, box, s_tx, s_rx, cur, lane);
+        td = trace_desc<MODE>(a, c, box, s_tx, s_rx, s_lo, ntx4, cur, lane);
         if constexpr (STAGE) {
             stage_load<ET, QM>(a, c, td, st, wave, lane, nwaves);
             stage_store<IP, QS, QM, GC>(c, st, q0, wave, lane, nwaves);
         }
-        store_w0<MODE>(c, td, s_w0, wave, lane);
+        store_w0(c, td, s_w0, wave, lane);
     }
     TraceDesc td_prev = td;            // RF gradient: windows of the previous batch
     __syncthreads();
@@ -843,16 +903,20 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     int row_j = -1;
     float dy2 = 0.f, wlo = 0.f, whi = 0.f;              // HERCULES
     int rows_cur[JC];
-    float Rj[JC], aj[JC];
+    float Rj[JC][ZP], aj[JC][ZP];
     bool row_on[JC];
-    for (int q = 0; q < JC; ++q) { rows_cur[q] = -1; Rj[q] = 0.f; aj[q] = 0.f; row_on[q] = false; }
+    for (int q = 0; q < JC; ++q) {
+        rows_cur[q] = -1;
+        row_on[q] = false;
+        for (int p = 0; p < ZP; ++p) { Rj[q][p] = 0.f; aj[q][p] = 0.f; }
+    }
 
     int bi = 0;
     while (cur.valid) {
         BatchDesc nxt = next_batch<MODE>(a, c, box, s_tx, s_rx, it);
-        TraceDesc td_n = {0, 0.f, -1};
+        TraceDesc td_n = {0, 0.f, NO_DATA, 0};
         if (nxt.valid) {
-            td_n = trace_desc<MODE>(a, c, box, s_tx, s_rx, nxt, lane);
+            td_n = trace_desc<MODE>(a, c, box, s_tx, s_rx, s_lo, ntx4, nxt, lane);
             if constexpr (STAGE) stage_load<ET, QM>(a, c, td_n, st, wave, lane, nwaves);
         }
         // the previous batch's gradient windows (complete since the last barrier)
@@ -906,64 +970,99 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                                           rot, txcol[e1], wst[e1], acc, accw + e1 * lw, Gv);
             }
         } else {
-            const int nbi = c.nb / JC;
+            // receive paths and weights of the batch's rows (on a new chunk);
+            // the lane's ZP points share the lateral offset to a row
 #pragma unroll
             for (int q = 0; q < JC; ++q) {
                 if (cur.rows[q] != rows_cur[q]) {
                     rows_cur[q] = cur.rows[q];
-                    if (rows_cur[q] >= 0) {
-                        const float dxr = rx_coord<MODE>(L.x, L.y) - s_rx[rows_cur[q]];
-                        const float r2 = dxr * dxr;
-                        const bool act = r2 < L.thr;
-                        Rj[q] = fmaf(excess(r2, L.z, L.z2), kf, L.fB);
-                        aj[q] = act ? hann_u2(r2 * L.wsc) : 0.f;
-                        row_on[q] = __any(act);
-                    } else {
-                        row_on[q] = false;
+                    const float dxr = rx_coord<MODE>(L.x, L.y) - s_rx[slot_row(rows_cur[q])];
+                    const float r2 = dxr * dxr;
+                    bool any = false;
+#pragma unroll
+                    for (int p = 0; p < ZP; ++p) {
+                        const bool act = r2 < Lp[p].thr && !slot_pad(rows_cur[q]);
+                        Rj[q][p] = fmaf(excess(r2, Lp[p].z, Lp[p].z2), kf, Lp[p].fB);
+                        aj[q][p] = act ? hann_u2(r2 * Lp[p].wsc) : 0.f;
+                        any = any || act;
                     }
+                    row_on[q] = __any(any);
                 }
             }
             const int4 *wst4 = reinterpret_cast<const int4 *>(s_w0 + (bi & 1) * w0_stride);
             // the transmits' table entries through the scalar cache (uniform)
             const float *__restrict__ tscf = reinterpret_cast<const float *>(a.tx_sc) + 2 * cur.i0;
             const float *__restrict__ txc = a.tx_x + cur.i0;
+            // the next transmit's scalars are fetched one transmit ahead, so
+            // their latency overlaps the current transmit's terms
+            float2 tsc_n = MODE == MODE_TPW ? make_float2(tscf[0], tscf[1]) : make_float2(0.f, 0.f);
+            float xi_n = MODE == MODE_TPW ? 0.f : txc[0];
+            static_assert(JC % 4 == 0, "the window starts of a transmit are JC / 4 int4 loads");
+            constexpr int NW4 = JC / 4;
+            int4 nw4_n[NW4];
+#pragma unroll
+            for (int r = 0; r < NW4; ++r) nw4_n[r] = wst4[r];
             for (int ii = 0; ii < cur.cnt; ++ii) {
-                // transmit excess path of this lane, shared by the batch's rows
-                const float T =
-                    kf * tx_excess_p<MODE>(L.x, L.z, L.z2,
-                                           MODE == MODE_TPW ? make_float2(tscf[2 * ii], tscf[2 * ii + 1])
-                                                            : make_float2(0.f, 0.f),
-                                           MODE == MODE_TPW ? 0.f : txc[ii], a.zf);
-                const int4 nw4 = wst4[ii];    // negated window starts of the 4 rows
-                const int nw[JC] = {nw4.x, nw4.y, nw4.z, nw4.w};
+                const float2 tsc = tsc_n;
+                const float xi = xi_n;
+                int nw[JC];                   // negated window starts of the JC rows
+#pragma unroll
+                for (int r = 0; r < NW4; ++r) {
+                    nw[4 * r] = nw4_n[r].x;
+                    nw[4 * r + 1] = nw4_n[r].y;
+                    nw[4 * r + 2] = nw4_n[r].z;
+                    nw[4 * r + 3] = nw4_n[r].w;
+                }
+                const int in = min(ii + 1, cur.cnt - 1);
+                if constexpr (MODE == MODE_TPW)
+                    tsc_n = make_float2(tscf[2 * in], tscf[2 * in + 1]);
+                else
+                    xi_n = txc[in];
+#pragma unroll
+                for (int r = 0; r < NW4; ++r) nw4_n[r] = wst4[NW4 * in + r];
+                // transmit excess path of each of the lane's points, shared by
+                // the batch's rows
+                float T[ZP];
+#pragma unroll
+                for (int p = 0; p < ZP; ++p)
+                    T[p] = kf * tx_excess_p<MODE>(L.x, Lp[p].z, Lp[p].z2, tsc, xi, a.zf);
+                // every slot holds a real row (padding slots have weight 0 and
+                // a zero window), so the forward and dL/dc terms of the JC rows
+                // run without branches and their LDS reads overlap; the RF
+                // gradient skips rows no lane of the wavefront receives
 #pragma unroll
                 for (int q = 0; q < JC; ++q) {
-                    if (!row_on[q]) continue;
-                    const int e = q * nbi + ii;
-                    const float sq = Rj[q] + T;
-                    // no clamp: li lies in [1, lmax + guard) for every lane (its
-                    // geometry is inside the box); lanes outside the row's
-                    // aperture (weight 0) may read into the next window or the
-                    // zeroed guard
-                    const int li = add3_vvv(cvt_flr(sq), L.nB, nw[q]);
-                    if constexpr (ET == ET_CF32) {
-                        const float4 *win = quads + e * c.lmax * QS;
-                        const float t = __builtin_amdgcn_fractf(sq);
-                        const float2 v = make_float2(eval_quad<IP>(win[2 * li], t),
-                                                     eval_quad<IP>(win[2 * li + 1], t));
-                        rotate_acc(v, aj[q], fmaf(rot, sq, L.ph0), acc[0]);
-                    } else if constexpr (ADJ != 0) {
-                        const int k = clamp0_i32(li, c.lmax - 1);
-                        const float t = __builtin_amdgcn_fractf(sq);
-                        if constexpr (GC) {
-                            const float wv = aj[q] * eval_dquad<IP>(quads[e * c.lmax + k], t);
-                            acc[0].x += wv;
-                            acc[0].y = fmaf(wv, sq, acc[0].y);
+                    if (GE && !row_on[q]) continue;
+                    const int e = ii * JC + q;            // slot: transmit-major
+#pragma unroll
+                    for (int p = 0; p < ZP; ++p) {
+                        const float sq = Rj[q][p] + T[p];
+                        // no clamp: li lies in [1, lmax + guard) for every lane
+                        // (its geometry is inside the box); lanes outside the
+                        // row's aperture (weight 0) may read into the next
+                        // window or the zeroed guard
+                        const int li = add3_vvv(cvt_flr(sq), Lp[p].nB, nw[q]);
+                        if constexpr (ET == ET_CF32) {
+                            const float4 *win = quads + e * c.lmax * QS;
+                            const float t = __builtin_amdgcn_fractf(sq);
+                            const float2 v = make_float2(eval_quad<IP>(win[2 * li], t),
+                                                         eval_quad<IP>(win[2 * li + 1], t));
+                            rotate_acc(v, aj[q][p], fmaf(rot, sq, Lp[p].ph0), acc[p]);
+                        } else if constexpr (ADJ != 0) {
+                            const int k = clamp0_i32(li, c.lmax - 1);
+                            const float t = __builtin_amdgcn_fractf(sq);
+                            if constexpr (GC) {
+                                const float wv = aj[q][p] * eval_dquad<IP>(quads[e * c.lmax + k], t);
+                                acc[p].x += wv;
+                                acc[p].y = fmaf(wv, sq, acc[p].y);
+                            }
+                            if constexpr (GE)
+                                scatter_taps<IP>(accw + e * lw, k, Gv[p] * aj[q][p], t);
+                        } else {
+                            const float v =
+                                eval_quad<IP>(quads[e * c.lmax + li], __builtin_amdgcn_fractf(sq));
+                            acc[p].x = fmaf(aj[q][p], v, acc[p].x);
                         }
-                        if constexpr (GE) scatter_taps<IP>(accw + e * lw, k, Gv[0] * aj[q], t);
-                    } else {
-                        const float v = eval_quad<IP>(quads[e * c.lmax + li], __builtin_amdgcn_fractf(sq));
-                        acc[0].x = fmaf(aj[q], v, acc[0].x);
                     }
                 }
             }
@@ -971,7 +1070,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
 
         if (!nxt.valid) break;
         if constexpr (STAGE) stage_store<IP, QS, QM, GC>(c, st, ((bi + 1) & 1) ? q1 : q0, wave, lane, nwaves);
-        store_w0<MODE>(c, td_n, s_w0 + ((bi + 1) & 1) * w0_stride, wave, lane);
+        store_w0(c, td_n, s_w0 + ((bi + 1) & 1) * w0_stride, wave, lane);
         __syncthreads();
         cur = nxt;
         td_prev = td;
@@ -1051,10 +1150,15 @@ __device__ inline int xcd_slab_box(const LdsCfg &c, int b)
     return (c.blocks_z - 1 - zrank) + c.blocks_z * (slot % nlat);
 }
 
-// Two points per lane and the row-column modes: registers capped for 6
-// wavefronts per SIMD (two 12-wavefront workgroups per CU).
+// Registers capped for two workgroups per CU: 6 wavefronts per SIMD for
+// HERCULES with two points per lane and the row-column modes (12-wavefront
+// workgroups); FORCES planes 8 with one point per lane (16-wavefront
+// workgroups; without the cap the plane kernel's registers left room for
+// one workgroup per CU: 0.19 ms against 0.15 ms on the 256 x 256 plane of
+// 64 x 64 traces) and 4 with two (8-wavefront workgroups).
 template <int MODE, int ZP> struct WavesPerEu {
-    static constexpr int value = (ZP == 2 || MODE == MODE_TPW || MODE == MODE_VLS) ? 6 : 1;
+    static constexpr int value = MODE == MODE_FORCES ? (ZP == 2 ? 4 : 8)
+                                 : (ZP == 2 || MODE == MODE_TPW || MODE == MODE_VLS) ? 6 : 1;
 };
 
 // Dynamic LDS beyond 64 KiB (gfx950 has 160 KiB per CU) is requested per
@@ -1065,6 +1169,6 @@ static inline hipError_t allow_lds(const void *fn, size_t shm)
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
 }
 
-size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard, int adj);
+size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard, int adj, int mode);
 
 }  // namespace bf

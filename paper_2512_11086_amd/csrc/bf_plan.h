@@ -73,7 +73,7 @@ struct Batch;   // persistent batched path state (bf_batch.hip)
 hipError_t launch_das(const DasArgs &a, int mode, int et, int ip, hipStream_t s);
 hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, int ip,
                           hipStream_t s);
-size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard, int adj);
+size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard, int adj, int mode);
 hipError_t launch_das_lds_adjoint(const DasArgs &a, const LdsCfg &c, int mode, int ip,
                                   float *grad_c, hipStream_t s, int n_frames = 1);
 

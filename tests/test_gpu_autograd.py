@@ -61,11 +61,13 @@ def test_checkpointed_loss_equals_plain(torch_mod, w3):
     assert grads[0][1] == pytest.approx(grads[1][1], rel=1e-6)
 
 
-def test_autofocus_finds_generating_sound_speed(torch_mod, w3):
-    # Sanity check of the autofocus loop on the 8-frame workload: the scan +
-    # gradient refinement ends at a local minimum no worse than the scan's
-    # best point.  Distance to the generating sound speed is reported (the RF
-    # sharpness loss oscillates in c, so it is bounded loosely).
+def test_autofocus_reaches_stationary_point_no_worse_than_scan(torch_mod, w3):
+    # The autofocus loop on the 8-frame workload: the scan + gradient
+    # refinement ends at a stationary point of the loss, no worse than the
+    # scan's best point and inside the scanned range.  The distance to the
+    # generating sound speed is only printed: the RF sharpness loss
+    # oscillates in c with the carrier phase, and its deepest minimum on this
+    # workload is not the generating speed.
     torch = torch_mod
     desc, H, rfs, info = w3
     plan = bfm.Plan(desc, H)

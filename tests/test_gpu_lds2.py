@@ -145,11 +145,18 @@ def test_diverging_transmit(torch_mod):
 
 
 def test_rejected_where_unsupported(torch_mod):
-    forces = describe("forces", (12, 10), (0.25 * MM, 0.3 * MM), 8, 12, 600, 25e6, 6e6,
-                      (21, 1, 17), (-2 * MM, 0, 1 * MM), (2 * MM, 0, 8 * MM))
-    p = bfm.Plan(forces, synth.hadamard_sylvester(8))
+    # two depth points per lane: HERCULES and FORCES with real data only
+    tpw = describe("tpw", (12, 10), (0.25 * MM, 0.3 * MM), 8, 10, 600, 25e6, 6e6,
+                   (13, 9, 29), (-2 * MM, -1.5 * MM, 1 * MM), (2.2 * MM, 1.2 * MM, 9 * MM),
+                   tx_angles=np.deg2rad(np.linspace(-10, 10, 8)))
+    p = bfm.Plan(tpw, None)
     with pytest.raises(bfm.BfError):
-        p.set_das_config("lds2", (2, 1, 2), 8)
+        p.set_das_config("lds2", (2, 2, 2), 8)
+    _, _, iq = synth.configs.iq_frontend(synth.configs.workload(0))
+    p = bfm.Plan(iq, synth.hadamard_sylvester(32))
+    assert p.info()["variant"] != 2
+    with pytest.raises(bfm.BfError):
+        p.set_das_config("lds2", (2, 1, 4), 16)
     _, _, iq = synth.configs.iq_frontend(_desc())
     p = bfm.Plan(iq, synth.hadamard_sylvester(8))
     assert p.info()["variant"] != 2
@@ -212,3 +219,67 @@ def test_batched_two_points_and_graph(torch_mod):
         ref = oracle.das(d, oracle.decode(H, rf))
         assert rel_l2(a, ref) <= TOL_L2
         assert rel_l2(a, b) <= 1e-6
+
+
+def _plane(interp="cubic", nz=53, f_number=1.0, along_y=False):
+    """A small FORCES plane (x-z, or y-z through a frame rotated about z)."""
+    M = None
+    if along_y:
+        M = synth.configs.centered_xdc((12, 10), (0.25 * MM, 0.25 * MM))
+        M[:3, :3] = [[0, 1, 0], [-1, 0, 0], [0, 0, 1]]
+        dims, g0, g1 = (1, 37, nz), (0, -2 * MM, 1 * MM), (0, 2.2 * MM, 9 * MM)
+    else:
+        dims, g0, g1 = (37, 1, nz), (-2 * MM, 0, 1 * MM), (2.2 * MM, 0, 9 * MM)
+    return describe("forces", (12, 10), (0.25 * MM, 0.25 * MM), 8, 12, 600, 25e6, 6e6, dims,
+                    g0, g1, t0=0.3e-6, f_number=f_number, interp=interp,
+                    tx_elements=[0, 3, 4, 6, 7, 8, 10, 11],
+                    channel_map=np.random.default_rng(2).permutation(12), xdc=M)
+
+
+@pytest.mark.parametrize("interp, nz, tile, block, nb, kw", [
+    ("cubic", 53, (5, 0, 1), (2, 1, 4), 16, {}),
+    ("cubic", 2, (5, 0, 1), (2, 1, 4), 16, {}),
+    ("cubic", 1, (3, 0, 3), (2, 1, 2), 8, {}),
+    ("linear", 41, (5, 0, 1), (2, 1, 4), 4, dict(f_number=0.0)),
+    ("nearest", 53, (4, 0, 2), (4, 1, 4), 24, {}),
+    ("cubic", 53, (0, 5, 1), (1, 2, 4), 16, dict(along_y=True)),
+])
+def test_forces_plane_two_points_matches_oracle(torch_mod, interp, nz, tile, block, nb, kw):
+    """FORCES planes with two depth points per lane (the plane default):
+    odd and tiny depth counts, several tiles, workgroups and batches, linear
+    and nearest reads, F# 0, the y-z plane of a frame rotated about z; and
+    the one-point kernel gives the same image to FP32 rounding."""
+    torch = torch_mod
+    d = _plane(interp, nz, **kw)
+    H, e = _data(d, 11)
+    plan = bfm.Plan(d, H, tile=tile)
+    block = (block[0], 1, block[2]) if not kw.get("along_y") else (1, block[1], block[2])
+    plan.set_das_config("lds2", block, nb)
+    # (a depth count of 2 spaces the points 8 mm apart: the boxes' windows
+    # exceed LDS and the gather kernel runs, as bf_plan_get_info reports)
+    assert plan.info()["variant"] == (1 if nz == 2 else 2)
+    et = torch.from_numpy(e.astype(np.float32)).cuda()
+    got = plan.das(et).cpu().numpy()
+    ref = oracle.das(d, e)
+    tol = TOL_NEAREST if interp == "nearest" else TOL_L2
+    assert rel_l2(got, ref) <= tol
+    p1 = bfm.Plan(d, H, tile=tile)
+    p1.set_das_config("lds", block, nb)
+    one = p1.das(et).cpu().numpy()
+    assert rel_l2(got, one) <= (tol if interp == "nearest" else 1e-6)
+
+
+@pytest.mark.parametrize("e_type", ["bf16", "i32"])
+def test_forces_plane_two_points_storage_types(torch_mod, e_type):
+    torch = torch_mod
+    d = _plane()
+    H, e = _data(d, 13)
+    plan = bfm.Plan(d, H, e_type=e_type)
+    assert plan.info()["variant"] == 2
+    if e_type == "bf16":
+        et = torch.from_numpy(e.astype(np.float32)).to(torch.bfloat16).cuda()
+        ref = oracle.das(d, et.float().cpu().numpy().astype(np.float64))
+    else:
+        et = torch.from_numpy(np.rint(e).astype(np.int32)).cuda()
+        ref = oracle.das(d, e)
+    assert rel_l2(plan.das(et).cpu().numpy(), ref) <= TOL_L2

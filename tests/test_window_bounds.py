@@ -177,6 +177,10 @@ CASES = [
     ("w5 diverging", lambda: synth.configs.workload(5), (3, 3, 0), (2, 2, 3), 2),
     ("w3 forces", lambda: synth.configs.workload(3), (5, 0, 1), (2, 1, 8), 1),
     ("w3 forces 16x4", lambda: synth.configs.workload(3), (4, 0, 2), (4, 1, 4), 1),
+    ("w3 forces two points", lambda: synth.configs.workload(3), (5, 0, 1), (2, 1, 4), 2),
+    ("w0 forces two points", lambda: synth.configs.workload(0), (5, 0, 1), (2, 1, 4), 2),
+    ("w4 plane two points", lambda: synth.configs.frame_4("2d", np.arange(0, 128, 4)),
+     (5, 0, 1), (2, 1, 4), 2),
     ("w6 tpw", lambda: synth.configs.workload(6), (3, 3, 0), (2, 2, 3), 1),
     ("w7 vls", lambda: synth.configs.workload(7), (2, 3, 1), (2, 2, 3), 1),
     # small grids: tiles, tilt, array plane, F#, focal lines
@@ -185,6 +189,8 @@ CASES = [
     ("hercules F#0", lambda: _small("hercules", f_number=0.0), (0, 0, 6), (1, 1, 2), 2),
     ("forces plane", lambda: _small("forces", z0=-0.6 * MM), (2, 0, 4), (2, 1, 2), 1),
     ("forces F#2", lambda: _small("forces", f_number=2.0), (0, 0, 6), (1, 1, 1), 1),
+    ("forces plane two points", lambda: _small("forces", z0=-0.6 * MM), (3, 0, 3), (2, 1, 2), 2),
+    ("forces F#0 two points", lambda: _small("forces", f_number=0.0), (5, 0, 1), (1, 1, 4), 2),
     ("tpw plane", lambda: _small("tpw", z0=-0.6 * MM), (1, 1, 4), (1, 1, 2), 1),
     ("tpw F#0.5", lambda: _small("tpw", f_number=0.5), (3, 3, 0), (2, 2, 3), 1),
     ("vls diverging", lambda: _small("vls", focal_depth=-4 * MM), (2, 3, 1), (2, 2, 3), 1),

@@ -323,6 +323,98 @@ def traffic_run():
                       "das_config": plan.info()}), flush=True)
 
 
+def _counter_per_dispatch(db: str, counter: str) -> list:
+    """(kernel name, value) per dispatch of one rocprofv3 --pmc results
+    database, in dispatch order."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    try:
+        rows = con.execute("select dispatch_id, kernel_name, sum(value) from counters_collection "
+                           "where counter_name = ? group by dispatch_id order by dispatch_id",
+                           (counter,)).fetchall()
+    finally:
+        con.close()
+    return [(n, float(v)) for _, n, v in rows]
+
+
+def traffic_summary(fetch_db: str, write_db: str):
+    """Write the HBM traffic summary of the DAS kernel from the results of
+    the two counter runs of --traffic (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch).  Each counter is scaled by what it reads for the plain 512 MiB
+    copy at the start of the sequence (the dispatch outside this library that
+    fetches the most; its write is read from the same kernel)."""
+    fetch = _counter_per_dispatch(fetch_db, "FETCH_SIZE")
+    write = _counter_per_dispatch(write_db, "WRITE_SIZE")
+    mib512 = 512.0 * 1024.0           # KiB
+    copy_name, copy_fetch = max(((n, v) for n, v in fetch if "bf::" not in n), key=lambda t: t[1])
+    copy_write = max(v for n, v in write if n == copy_name)
+    das_f = [v for n, v in fetch if "das_lds_kernel" in n]
+    das_w = [v for n, v in write if "das_lds_kernel" in n]
+    das_name = next(n for n, _ in fetch if "das_lds_kernel" in n)
+    f_scale, w_scale = mib512 / copy_fetch, mib512 / copy_write
+    f_raw, w_raw = sum(das_f) / len(das_f), sum(das_w) / len(das_w)
+    out = {
+        "kernel": das_name,
+        "workload": "HERCULES 128 tx x 128 ch x 2048 -> 128x128x256, c = 1540 m/s",
+        "kernel_hash": kernel_hash(),
+        "fetch_kib_raw": f_raw,
+        "write_kib_raw": w_raw,
+        "fetch_scale": f_scale,
+        "write_scale": w_scale,
+        "das_hbm_bytes_per_launch": int(round((f_raw * f_scale + w_raw * w_scale) * 1024)),
+        "algorithmic_hbm_bytes_per_launch": 128 * 128 * 2048 * 4 + 128 * 128 * 256 * 4,
+        "calibration_kernel": copy_name[:120],
+        "commands": [
+            "rocprofv3 --pmc FETCH_SIZE --kernel-trace -d <dir> -o run -- python bench.py --traffic",
+            "rocprofv3 --pmc WRITE_SIZE --kernel-trace -d <dir> -o run -- python bench.py --traffic",
+            "python bench.py --traffic-summary <fetch dir>/run_results.db <write dir>/run_results.db",
+        ],
+    }
+    with open(TRAFFIC_FILE, "w") as fp:
+        json.dump(out, fp, indent=1)
+        fp.write("\n")
+    print(json.dumps(out))
+
+
+def plane_run():
+    """Short fixed sequence for rocprofv3 runs on the 256 x 256 FORCES plane
+    (one frame of workload 3, 64 x 64 x 2048): 3 DAS launches, 3 dL/dc
+    adjoint launches and 3 RF-gradient adjoint launches, then 20 timed DAS
+    and 20 timed dL/dc launches (HIP events on the launch stream)."""
+    import torch
+    import paper_2512_11086_amd as bfm
+    import synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    desc, H, rfs, info = synth.make_inputs(3, frame=0)
+    plan = bfm.Plan(desc, H)
+    e = plan.decode(torch.from_numpy(rfs[0]).to(dev))
+    c = float(info["c_true"])
+    img = plan.das(e, c=c)
+    _, g = bfm.sharpness(img.reshape(1, -1))
+    g = g.reshape(img.shape)
+    ge = torch.empty(e.shape, dtype=torch.float32, device=dev)
+    for _ in range(3):
+        plan.das(e, c=c, out=img)
+    for _ in range(3):
+        plan.das_adjoint(e, g, c=c, want_e=False)
+    for _ in range(3):
+        plan.das_adjoint(None, g, c=c, want_c=False, out_e=ge)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(stream)
+    for _ in range(20):
+        plan.das(e, c=c, out=img)
+    ev[1].record(stream)
+    for _ in range(20):
+        plan.das_adjoint(e, g, c=c, want_e=False)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    print(json.dumps({"plane_run": "done", "das_ms": ev[0].elapsed_time(ev[1]) / 20,
+                      "adjoint_c_ms": ev[1].elapsed_time(ev[2]) / 20, "config": plan.info()}),
+          flush=True)
+
+
 def batched_comparison(torch, bfm, stream4, reps: int):
     """64-frame uFORCES/uHERCULES stream: plain per-frame launches vs one
     persistent launch per kernel class vs the same captured in a hipGraph.
@@ -697,9 +789,19 @@ def main():
                     help="skip the differentiable FORCES workload (adjoint, sharpness)")
     ap.add_argument("--traffic", action="store_true",
                     help="only run the short kernel sequence used for counter collection")
+    ap.add_argument("--plane", action="store_true",
+                    help="only run the short FORCES-plane sequence used for profiles")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="write the DAS traffic summary from the two --traffic counter runs")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary)
+        return
     if args.traffic:
         traffic_run()
+        return
+    if args.plane:
+        plane_run()
         return
     if args.gpus != 1:
         print("bench.py measures one GPU; multi-GPU runs are not part of this build "

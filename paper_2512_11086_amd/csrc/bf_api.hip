@@ -242,8 +242,8 @@ int Frame::init(const bf_params &src)
         // a plane: 32 x 2 points per wavefront along its lateral axis and
         // depth, 2 x 8 wavefronts per LDS workgroup (64 x 16 points), batches
         // of JC rows x nb/JC transmits (on the 256 x 256 plane of 64 x 64
-        // traces: DAS 193 us, dL/dc 207 us, against 197 / 228 us for 16 x 4
-        // tiles in 4 x 4 wavefronts)
+        // traces: DAS 151 us, dL/dc 172 us; 16 x 4 tiles in 4 x 4 wavefronts
+        // measured slower in the earlier design, 197 / 228 against 193 / 207 us)
         if (grid.ny == 1) {
             set_tile(5, 0, 1);
             bw[0] = 2; bw[1] = 1; bw[2] = 8;
@@ -252,11 +252,10 @@ int Frame::init(const bf_params &src)
             bw[0] = 1; bw[1] = 2; bw[2] = 8;
         }
         nb = 16;
-        if (!p.iq && grid.nz >= 2) {
-            // two depth points per lane: the same 64 x 16 box from 8 wavefronts
-            variant = BF_DAS_LDS_Z2;
-            bw[2] = 4;
-        }
+        // (two depth points per lane, BF_DAS_LDS_Z2 over the same box from 2 x 4
+        // wavefronts, issues 16 % fewer instructions but hides less latency
+        // at half the wavefronts per SIMD: DAS 151 us both, dL/dc 178 against
+        // 172 us, the autofocus step and the cross-plane pair 3-6 % slower)
     } else if (p.mode == BF_TPW_3D || p.mode == BF_VLS_3D) {
         // LDS windows, JC rows x nb/JC transmits per batch (separable paths);
         // VLS windows are longer (the path to the line changes along x too)

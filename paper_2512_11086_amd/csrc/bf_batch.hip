@@ -596,7 +596,10 @@ int bf_autotune(bf_plan plan, const char *cache_path)
     // frame of each class is tuned on scratch data of its own element type
     // and its choice applies to the whole class.
     std::vector<std::string> keys;
-    for (Frame *f : plan->frames) keys.push_back(tune_key(*f, prop.gcnArchName));
+    // (a batch plan tunes under keys of its own: its candidates are restricted, below)
+    const bool batch = plan->frames.size() > 1;
+    for (Frame *f : plan->frames)
+        keys.push_back(tune_key(*f, prop.gcnArchName) + (batch ? "|batch" : ""));
     std::vector<int> done(plan->frames.size(), 0);
     for (size_t c0 = 0; c0 < plan->frames.size(); ++c0) {
         if (done[c0]) continue;
@@ -627,7 +630,15 @@ int bf_autotune(bf_plan plan, const char *cache_path)
                 {saved[0], saved[1], saved[2], saved[3], saved[4], saved[5], saved[6], saved_variant}};
             const std::vector<TileCand> more = candidates(*f0);
             cands.insert(cands.end(), more.begin(), more.end());
+            // A batch plan runs each kernel class (mode, type, interpolation,
+            // points per lane, workgroup size) as one persistent launch: its
+            // candidates keep the workgroup size, the points per lane and the
+            // LDS kernel, so that tuning one class does not split it into
+            // separate launches that run one after the other.
+            const int threads0 = saved[3] * saved[4] * saved[5];
             for (const TileCand &t : cands) {
+                if (batch && (t.bwx * t.bwy * t.bwz != threads0 || t.variant != saved_variant))
+                    continue;
                 f0->set_tile(t.lx, t.ly, t.lz);
                 f0->bw[0] = t.bwx;
                 f0->bw[1] = t.bwy;

@@ -169,6 +169,33 @@ def test_persistent_lds_classes_and_graph(torch_mod):
             assert torch.equal(o, r), rep
 
 
+def test_batch_autotune_keeps_persistent_classes(torch_mod, tmp_path):
+    """Tuning a batch plan keeps every kernel class on one persistent launch
+    (same workgroup size and kernel, so no class splits), caches its choice
+    under batch keys, and the tuned plan still matches the oracle."""
+    torch = torch_mod
+    frames = _big_frames(9)
+    rfs = [torch.from_numpy(f[2]).cuda() for f in frames]
+    untuned = bfm.BatchPlan([f[0] for f in frames], [f[1] for f in frames])
+    untuned.run(rfs, [torch.empty(s, device="cuda") for s in untuned.out_shapes])
+    torch.cuda.synchronize()
+    before = [untuned.frame_info(f) for f in range(len(frames))]
+    bp = bfm.BatchPlan([f[0] for f in frames], [f[1] for f in frames])
+    cache = str(tmp_path / "tune.txt")
+    bp.autotune(cache)
+    keys = [ln.split()[0] for ln in open(cache).read().strip().splitlines()]
+    assert len(keys) == 2 and all(k.endswith("|batch") for k in keys), keys
+    outs = [torch.empty(s, device="cuda") for s in bp.out_shapes]
+    bp.run(rfs, outs)
+    torch.cuda.synchronize()
+    for f, ((d, H, rf), o) in enumerate(zip(frames, outs)):
+        fi = bp.frame_info(f)
+        assert fi["das_path"] == "persistent_lds", (f, fi)
+        assert fi["das_class"] == before[f]["das_class"], (f, fi, before[f])
+        ref = oracle.das(d, oracle.decode(H, rf))
+        assert rel_l2(o.cpu().numpy(), ref) <= 1e-5, d["mode"]
+
+
 def test_workload4_all_frames_match_oracle():
     """Full size, the whole batched stream: all 64 frames (planes and volumes,
     every 16-, 32-, 64- and 128-transmit subset) through one batch plan and

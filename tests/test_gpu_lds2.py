@@ -245,7 +245,7 @@ def _plane(interp="cubic", nz=53, f_number=1.0, along_y=False):
     ("cubic", 53, (0, 5, 1), (1, 2, 4), 16, dict(along_y=True)),
 ])
 def test_forces_plane_two_points_matches_oracle(torch_mod, interp, nz, tile, block, nb, kw):
-    """FORCES planes with two depth points per lane (the plane default):
+    """FORCES planes with two depth points per lane (variant lds2):
     odd and tiny depth counts, several tiles, workgroups and batches, linear
     and nearest reads, F# 0, the y-z plane of a frame rotated about z; and
     the one-point kernel gives the same image to FP32 rounding."""
@@ -275,6 +275,7 @@ def test_forces_plane_two_points_storage_types(torch_mod, e_type):
     d = _plane()
     H, e = _data(d, 13)
     plan = bfm.Plan(d, H, e_type=e_type)
+    plan.set_das_config("lds2", (2, 1, 4), 16)
     assert plan.info()["variant"] == 2
     if e_type == "bf16":
         et = torch.from_numpy(e.astype(np.float32)).to(torch.bfloat16).cuda()
@@ -283,3 +284,20 @@ def test_forces_plane_two_points_storage_types(torch_mod, e_type):
         et = torch.from_numpy(np.rint(e).astype(np.int32)).cuda()
         ref = oracle.das(d, e)
     assert rel_l2(plan.das(et).cpu().numpy(), ref) <= TOL_L2
+
+
+def test_forces_plane_two_points_adjoint(torch_mod):
+    """Both adjoint gradients of a plane with two depth points per lane
+    against the oracle (dL/dc: the FP64 analytic derivative; dL/de: the
+    transpose of the FP64 beamforming map)."""
+    torch = torch_mod
+    d = _plane()
+    H, e = _data(d, 17)
+    plan = bfm.Plan(d, H)
+    plan.set_das_config("lds2", (2, 1, 4), 16)
+    et = torch.from_numpy(e.astype(np.float32)).cuda()
+    G = np.random.default_rng(5).normal(size=plan.out_shape).astype(np.float32).astype(np.float64)
+    ge, gc = plan.das_adjoint(et, torch.from_numpy(G.astype(np.float32)).cuda())
+    ref_c = float(np.sum(G * oracle.das_dc(d, e)))
+    assert abs(float(gc) - ref_c) <= 1e-4 * abs(ref_c)
+    assert rel_l2(ge.cpu().numpy(), oracle.das_adjoint_e(d, G)) <= TOL_L2

@@ -169,16 +169,46 @@ __host__ __device__ inline float hann_u2(float w)
     return p;
 }
 
+// Global and constant address-space views of device pointers.  A kernel
+// that reads its pointers from a table in memory (the persistent kernels)
+// holds generic pointers, and the compiler turns their loads into FLAT
+// instructions, which also count against the LDS wait counter: every LDS wait
+// of the terms would then wait for the staging loads in flight, and a
+// uniform table read would take a vector round trip.  Data loads go through
+// the global view (vector loads counted by vmcnt only); uniform reads of the
+// read-only geometry tables through the constant view (scalar loads).
+template <typename T> using gptr = const __attribute__((address_space(1))) T *;
+template <typename T> using gptr_mut = __attribute__((address_space(1))) T *;
+template <typename T> using cptr = const __attribute__((address_space(4))) T *;
+template <typename T> __device__ inline gptr<T> as_global(const T *p) { return (gptr<T>)p; }
+template <typename T> __device__ inline gptr_mut<T> as_global_mut(T *p) { return (gptr_mut<T>)p; }
+template <typename T> __device__ inline cptr<T> as_const(const T *p) { return (cptr<T>)p; }
+
+// Vector accesses through those views go element by element (the views do
+// not carry the vector types' constructors); the compiler merges them into
+// one wide load or store.
+__device__ inline float2 load_f2(const float2 *p, long idx)
+{
+    const gptr<float> q = as_global(reinterpret_cast<const float *>(p + idx));
+    return make_float2(q[0], q[1]);
+}
+__device__ inline void store_f2(float2 *p, long idx, float2 v)
+{
+    const gptr_mut<float> q = as_global_mut(reinterpret_cast<float *>(p + idx));
+    q[0] = v.x;
+    q[1] = v.y;
+}
+
 template <int ET>
 __device__ inline float load_e(const void *base, long idx)
 {
     if constexpr (ET == ET_F32) {
-        return static_cast<const float *>(base)[idx];
+        return as_global(static_cast<const float *>(base))[idx];
     } else if constexpr (ET == ET_BF16) {
-        uint32_t b = static_cast<const uint16_t *>(base)[idx];
+        uint32_t b = as_global(static_cast<const uint16_t *>(base))[idx];
         return __uint_as_float(b << 16);
     } else {
-        return (float)static_cast<const int *>(base)[idx];
+        return (float)as_global(static_cast<const int *>(base))[idx];
     }
 }
 
@@ -329,7 +359,7 @@ __device__ inline const void *trace_ptr(const void *e, long trace, int S)
 
 __device__ inline float2 load_c(const void *base, long idx)
 {
-    return static_cast<const float2 *>(base)[idx];
+    return load_f2(static_cast<const float2 *>(base), idx);
 }
 
 }  // namespace bf

@@ -242,7 +242,7 @@ __device__ inline float tx_lo(const DasArgs &a, const BoxGeom &b, int i, float x
         return __builtin_amdgcn_sqrtf(fmaf(rt, rt, zlo * zlo));
     } else if constexpr (MODE == MODE_TPW) {
         // x sin(th) + z cos(th): smallest at the box edge along sin(th), cos(th) > 0
-        const float2 sc = a.tx_sc[i];
+        const float2 sc = load_f2(a.tx_sc, i);
         return (sc.x >= 0.f ? b.xmin : b.xmax) * sc.x + zlo * (1.f + sc.y);
     } else {
         // z_f + sgn(z - z_f) |(x - x_i, z - z_f)|: with the whole box below the
@@ -506,11 +506,9 @@ __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const Trace
                 const float2 z = make_float2(0.f, 0.f);
                 float2 t0, t1, t2, t3;
                 if (inside) {
-                    float4 u, v;
-                    __builtin_memcpy(&u, static_cast<const float2 *>(tn) - 1, 16);
-                    __builtin_memcpy(&v, static_cast<const float2 *>(tn) + 1, 16);
-                    t0 = make_float2(u.x, u.y); t1 = make_float2(u.z, u.w);
-                    t2 = make_float2(v.x, v.y); t3 = make_float2(v.z, v.w);
+                    const gptr<float> u = as_global(reinterpret_cast<const float *>(tn) - 2);
+                    t0 = make_float2(u[0], u[1]); t1 = make_float2(u[2], u[3]);
+                    t2 = make_float2(u[4], u[5]); t3 = make_float2(u[6], u[7]);
                 } else {
                     t0 = ((unsigned)(n - 1) < S) ? load_c(tn, -1) : z;
                     t1 = ((unsigned)n < S) ? load_c(tn, 0) : z;
@@ -523,9 +521,8 @@ __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const Trace
                 // whole window inside the record (the usual case): one
                 // 16-byte load of the four taps (4-byte aligned)
                 if constexpr (ET == ET_F32) {
-                    float4 v;
-                    __builtin_memcpy(&v, static_cast<const float *>(tn) - 1, 16);
-                    p0 = v.x; p1 = v.y; p2 = v.z; p3 = v.w;
+                    const gptr<float> v = as_global(static_cast<const float *>(tn) - 1);
+                    p0 = v[0]; p1 = v[1]; p2 = v[2]; p3 = v[3];
                 } else {
                     p0 = load_e<ET>(tn, -1);
                     p1 = load_e<ET>(tn, 0);
@@ -808,11 +805,11 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
         reinterpret_cast<unsigned long long *>(q1 + buf_quads + (STAGE ? c.guard * QS : 0));
     unsigned long long *accw1 = accw0 + (GE ? c.nb * lw : 0);
     float *s_gmax = reinterpret_cast<float *>(accw1 + (GE ? c.nb * lw : 0));
-    for (int t = tid; t < a.n_tx; t += nthr) s_tx[t] = a.tx_x[t];
-    for (int t = tid; t < a.n_ch; t += nthr) s_rx[t] = a.rx_c[t];
+    for (int t = tid; t < a.n_tx; t += nthr) s_tx[t] = as_global(a.tx_x)[t];
+    for (int t = tid; t < a.n_ch; t += nthr) s_rx[t] = as_global(a.rx_c)[t];
     if constexpr (MODE == 1)
         for (int t = tid; t < HANN_TAB_PAD; t += nthr)
-            s_hann[t] = t <= HANN_N ? a.hann_tab[t] : make_float2(0.f, 0.f);
+            s_hann[t] = t <= HANN_N ? load_f2(a.hann_tab, t) : make_float2(0.f, 0.f);
     if constexpr (STAGE)   // finite data wherever an unclamped read can land
         for (int t = tid; t < buf_quads + c.guard * QS; t += nthr) q1[t] = make_float4(0.f, 0.f, 0.f, 0.f);
     if constexpr (GE)
@@ -823,8 +820,8 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     const int by = blk / (c.blocks_z * c.blocks_x);
     const BoxGeom box = block_box(a, c, bx, by, bz);
     if constexpr (SEP) {   // the box's path bounds (read after the barrier below)
-        for (int t = tid; t < a.n_tx; t += nthr) s_lo[t] = tx_lo<MODE>(a, box, t, a.tx_x[t]);
-        for (int t = tid; t < a.n_ch; t += nthr) s_lo[ntx4 + t] = rx_lo<MODE>(box, a.rx_c[t]);
+        for (int t = tid; t < a.n_tx; t += nthr) s_lo[t] = tx_lo<MODE>(a, box, t, as_global(a.tx_x)[t]);
+        for (int t = tid; t < a.n_ch; t += nthr) s_lo[ntx4 + t] = rx_lo<MODE>(box, as_global(a.rx_c)[t]);
     }
     LaneL Lp[ZP];
 #pragma unroll
@@ -851,7 +848,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
             lane_point(a, c, bx, by, bz, wave, lane, p, &ix, &iy, &iz);
             if (ix < a.g.nx && iy < a.g.ny && iz >= 0 && iz < a.g.nz) {
                 const double pz = a.g.org[2] + ix * a.g.ax[2] + iy * a.g.ay[2] + iz * a.g.az[2];
-                if (pz > 0.0) Gv[p] = a.grad_out[((long)iy * a.g.nx + ix) * a.g.nz + iz];
+                if (pz > 0.0) Gv[p] = as_global(a.grad_out)[((long)iy * a.g.nx + ix) * a.g.nz + iz];
             }
         }
     }
@@ -943,7 +940,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
             // per trace: the column position from the read-only table through
             // the scalar cache (uniform index) and the negated window start
             // from LDS -- no lane broadcasts (their SGPR results stall the wave)
-            const float *__restrict__ txcol = a.tx_x + cur.i0;
+            const cptr<float> txcol = as_const(a.tx_x) + cur.i0;
             const int *wst = s_w0 + (bi & 1) * w0_stride;
             if constexpr (ZP == 2) {
                 // one trace per step already gives two independent terms
@@ -991,8 +988,8 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
             }
             const int4 *wst4 = reinterpret_cast<const int4 *>(s_w0 + (bi & 1) * w0_stride);
             // the transmits' table entries through the scalar cache (uniform)
-            const float *__restrict__ tscf = reinterpret_cast<const float *>(a.tx_sc) + 2 * cur.i0;
-            const float *__restrict__ txc = a.tx_x + cur.i0;
+            const cptr<float> tscf = as_const(reinterpret_cast<const float *>(a.tx_sc)) + 2 * cur.i0;
+            const cptr<float> txc = as_const(a.tx_x) + cur.i0;
             // the next transmit's scalars are fetched one transmit ahead, so
             // their latency overlaps the current transmit's terms
             float2 tsc_n = MODE == MODE_TPW ? make_float2(tscf[0], tscf[1]) : make_float2(0.f, 0.f);
@@ -1123,9 +1120,9 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
             const double pz = a.g.org[2] + ix * a.g.ax[2] + iy * a.g.ay[2] + iz * a.g.az[2];
             const float2 v = pz > 0.0 ? acc[p] : make_float2(0.f, 0.f);
             if constexpr (ET == ET_CF32)
-                reinterpret_cast<float2 *>(dst)[idx] = v;
+                store_f2(reinterpret_cast<float2 *>(dst), idx, v);
             else
-                dst[idx] = v.x;
+                as_global_mut(dst)[idx] = v.x;
         }
     }
 }

@@ -32,9 +32,10 @@ namespace bf {
 __device__ inline uint32_t load_pair(const int16_t *rf, long row, int t, int S, bool even_S)
 {
     // Samples t and t+1 of one trace packed as (x[t] | x[t+1] << 16).
-    const int16_t *p = rf + row * (long)S + t;
+    // (global view: the persistent kernel reads rf from a pointer table)
+    const gptr<int16_t> p = as_global(rf + row * (long)S + t);
     if (even_S) {
-        return (t < S) ? *reinterpret_cast<const uint32_t *>(p) : 0u;
+        return (t < S) ? *reinterpret_cast<gptr<uint32_t>>(p) : 0u;
     }
     uint32_t a = (t < S) ? (uint16_t)p[0] : 0u;
     uint32_t b = (t + 1 < S) ? (uint16_t)p[1] : 0u;
@@ -58,26 +59,28 @@ template <int OT>
 __device__ inline void store_pair(void *e, long idx, int v0, int v1, bool two, bool even_S)
 {
     if constexpr (OT == ET_F32) {
-        float *p = static_cast<float *>(e) + idx;
+        const gptr_mut<float> p = as_global_mut(static_cast<float *>(e) + idx);
         if (two && even_S) {
-            *reinterpret_cast<float2 *>(p) = make_float2((float)v0, (float)v1);
+            p[0] = (float)v0;
+            p[1] = (float)v1;
         } else {
             p[0] = (float)v0;
             if (two) p[1] = (float)v1;
         }
     } else if constexpr (OT == ET_I32) {
-        int *p = static_cast<int *>(e) + idx;
+        const gptr_mut<int> p = as_global_mut(static_cast<int *>(e) + idx);
         if (two && even_S) {
-            *reinterpret_cast<int2 *>(p) = make_int2(v0, v1);
+            p[0] = v0;
+            p[1] = v1;
         } else {
             p[0] = v0;
             if (two) p[1] = v1;
         }
     } else {
-        uint16_t *p = static_cast<uint16_t *>(e) + idx;
+        const gptr_mut<uint16_t> p = as_global_mut(static_cast<uint16_t *>(e) + idx);
         uint32_t b0 = f32_to_bf16_rne((float)v0), b1 = f32_to_bf16_rne((float)v1);
         if (two && even_S) {
-            *reinterpret_cast<uint32_t *>(p) = b0 | (b1 << 16);
+            *reinterpret_cast<gptr_mut<uint32_t>>(p) = b0 | (b1 << 16);
         } else {
             p[0] = (uint16_t)b0;
             if (two) p[1] = (uint16_t)b1;
@@ -153,10 +156,10 @@ __device__ inline void stage_operands(const DecodeArgs &a, v4i *lds_A, int *lds_
     for (int idx = threadIdx.x; idx < KB * KB * 64; idx += blockDim.x) {
         const int frag = idx >> 6, l = idx & 63;
         const int mt = frag / KB, kb = frag % KB;
-        lds_A[idx] = *reinterpret_cast<const v4i *>(a.At + (long)(mt * 32 + (l & 31)) * KP +
-                                                    kb * 32 + 16 * (l >> 5));
+        lds_A[idx] = *reinterpret_cast<gptr<v4i>>(as_global(a.At) + (long)(mt * 32 + (l & 31)) * KP +
+                                                  kb * 32 + 16 * (l >> 5));
     }
-    for (int m = threadIdx.x; m < KP; m += blockDim.x) lds_cs[m] = a.colsum[m];
+    for (int m = threadIdx.x; m < KP; m += blockDim.x) lds_cs[m] = as_global(a.colsum)[m];
     __syncthreads();
 }
 

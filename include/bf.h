@@ -323,10 +323,14 @@ int bf_graph_launch(bf_plan plan, const int16_t *const *rf, float *const *out, v
 /* How the batched path runs frame f of a batch plan (after its first
  * bf_batch_run or bf_graph_launch; BF_ERR_STATE before, BF_ERR_SHAPE for f
  * out of range). */
-enum { BF_BATCH_PERSISTENT_LDS = 0, BF_BATCH_GATHER = 1 };
+enum { BF_BATCH_PERSISTENT_LDS = 0, BF_BATCH_GATHER = 1, BF_BATCH_FRAME_LDS = 2 };
 typedef struct {
-    int32_t das_path;          /* BF_BATCH_PERSISTENT_LDS or BF_BATCH_GATHER            */
-    int32_t das_class;         /* index of its persistent DAS launch (-1: gather)        */
+    int32_t das_path;          /* BF_BATCH_PERSISTENT_LDS, BF_BATCH_GATHER or
+                                  BF_BATCH_FRAME_LDS (its own LDS launch, in the same
+                                  pass and graph: a frame of a kernel class too small
+                                  for the persistent launch without a channel split,
+                                  whose own launch fills the GPU)                       */
+    int32_t das_class;         /* index of its persistent DAS launch (-1: otherwise)     */
     int32_t channel_groups;    /* work items per box along the channel sum (>= 1)        */
     int32_t decode_class;      /* index of its persistent decode launch                  */
     int64_t das_items;         /* DAS work items of the frame                            */

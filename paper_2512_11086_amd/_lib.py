@@ -74,7 +74,7 @@ class BatchFrameInfo(ctypes.Structure):
                 ("das_items", ctypes.c_int64)]
 
 
-BATCH_PATHS = {0: "persistent_lds", 1: "gather"}
+BATCH_PATHS = {0: "persistent_lds", 1: "gather", 2: "frame_lds"}
 
 _lib = None
 

@@ -73,6 +73,7 @@ struct Batch {
     std::vector<DasClass> das;
     std::vector<int> gather_frames;   // frames on the gather kernel (windows too long for LDS)
     std::vector<int> split_frames;    // persistent frames with channel groups (partial images)
+    std::vector<int> frame_lds;       // frames on their own LDS launch (BF_BATCH_FRAME_LDS)
     std::vector<bf_batch_frame_info> info;   // how each frame runs
     void **h_stage[RING] = {};
     hipEvent_t ev[RING] = {};
@@ -164,6 +165,19 @@ static int build_batch(bf_plan plan)
         fi.das_items = 0;
         if (!lds_ok[f] || !fr.lds_config(a, &c)) {
             b->gather_frames.push_back(f);
+            memset(&c, 0, sizeof c);
+        } else if (groups[f] > 1 &&
+                   (long)c.blocks_x * c.blocks_y * c.blocks_z * fr.groups >= 2L * cus0) {
+            // A frame of a class that would need the channel split, whose own
+            // launch (the single-frame kernel with the frame's channel groups)
+            // already gives two workgroups per CU: that launch, captured in
+            // the pass like the others, measured faster than its share of the
+            // persistent launch (a pair of 256 x 256 planes from 128 x 128
+            // traces: 1.35 ms per pass persistent).
+            b->frame_lds.push_back(f);
+            fi.das_path = BF_BATCH_FRAME_LDS;
+            fi.channel_groups = fr.groups;
+            fi.das_items = (int64_t)c.blocks_x * c.blocks_y * c.blocks_z * fr.groups;
             memset(&c, 0, sizeof c);
         } else {
             const int G = groups[f];
@@ -387,12 +401,22 @@ static int check_batch(bf_plan plan, const int16_t *const *rf, float *const *out
     return BF_OK;
 }
 
-// Frames whose windows do not fit in LDS run the direct-gather kernel after
-// the persistent kernels; they read their output pointer from the device
-// table too, so they are captured in the same graph.
+// Frames on their own LDS launch, and frames whose windows do not fit in
+// LDS (the direct-gather kernel), run after the persistent kernels; they read
+// their output pointer from the device table too, so they are captured in
+// the same graph.
 static int enqueue_gather(bf_plan plan, hipStream_t s)
 {
     Batch *b = plan->batch;
+    for (int f : b->frame_lds) {
+        const Frame &fr = *plan->frames[f];
+        DasArgs a = fr.das_args(fr.d_e, nullptr, fr.p.c);
+        a.out_ref = reinterpret_cast<float *const *>(b->d_ptrs + b->F + f);
+        LdsCfg c;
+        if (!fr.lds_config(a, &c)) return fail(BF_ERR_STATE, "frame %d lost its LDS configuration", f);
+        hipError_t e = launch_das_lds(a, c, fr.p.mode, fr.p.e_type, fr.p.interp, s);
+        if (e != hipSuccess) return hip_fail(e, "DAS launch");
+    }
     for (int f : b->gather_frames) {
         const Frame &fr = *plan->frames[f];
         DasArgs a = fr.das_args(fr.d_e, nullptr, fr.p.c);

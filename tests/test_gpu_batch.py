@@ -155,7 +155,11 @@ def test_persistent_lds_classes_and_graph(torch_mod):
     bp.run(rfs, outs)
     torch.cuda.synchronize()
     for f, ((d, H, rf), o) in enumerate(zip(frames, outs)):
-        assert bp.frame_info(f)["das_path"] == "persistent_lds", f
+        # the four volumes (80 boxes each) share a persistent launch with
+        # channel-group items; each plane's own launch (128 boxes x 4 channel
+        # groups) fills the GPU, so the planes run their own LDS launches
+        want = "frame_lds" if d["mode"] == "forces" else "persistent_lds"
+        assert bp.frame_info(f)["das_path"] == want, (f, bp.frame_info(f))
         ref = oracle.das(d, oracle.decode(H, rf))
         assert rel_l2(o.cpu().numpy(), ref) <= 1e-5, d["mode"]
     eager = [o.clone() for o in outs]
@@ -171,8 +175,9 @@ def test_persistent_lds_classes_and_graph(torch_mod):
 
 def test_batch_autotune_keeps_persistent_classes(torch_mod, tmp_path):
     """Tuning a batch plan keeps every kernel class on one persistent launch
-    (same workgroup size and kernel, so no class splits), caches its choice
-    under batch keys, and the tuned plan still matches the oracle."""
+    (same workgroup size and kernel, so no class splits) and every frame on
+    an LDS path, caches its choice under batch keys, and the tuned plan still
+    matches the oracle."""
     torch = torch_mod
     frames = _big_frames(9)
     rfs = [torch.from_numpy(f[2]).cuda() for f in frames]
@@ -190,8 +195,11 @@ def test_batch_autotune_keeps_persistent_classes(torch_mod, tmp_path):
     torch.cuda.synchronize()
     for f, ((d, H, rf), o) in enumerate(zip(frames, outs)):
         fi = bp.frame_info(f)
-        assert fi["das_path"] == "persistent_lds", (f, fi)
-        assert fi["das_class"] == before[f]["das_class"], (f, fi, before[f])
+        # (a tuned tile can change a frame's box count and with it whether its
+        # own launch fills the GPU: persistent <-> own LDS launch)
+        assert fi["das_path"] != "gather", (f, fi)
+        if fi["das_path"] == before[f]["das_path"] == "persistent_lds":
+            assert fi["das_class"] == before[f]["das_class"], (f, fi, before[f])
         ref = oracle.das(d, oracle.decode(H, rf))
         assert rel_l2(o.cpu().numpy(), ref) <= 1e-5, d["mode"]
 

@@ -189,6 +189,10 @@ def test_cross_plane_batch_and_graph(torch_mod):
     outs = [torch.empty(s, device="cuda") for s in bp.out_shapes]
     bp.run(rf_d, outs)
     torch.cuda.synchronize()
+    # each 256 x 256 plane (64 boxes x 8 channel groups) fills the GPU with its
+    # own LDS launch; the small volume takes the persistent launch
+    paths = [bp.frame_info(f)["das_path"] for f in range(len(descs))]
+    assert paths[:2] == ["frame_lds", "frame_lds"] and paths[2] != "gather", paths
     eager = [o.clone() for o in outs]
     for f, (d, H, rf) in enumerate(zip(descs, Hs, rfs)):
         e64 = oracle.decode(H, rf)

@@ -175,31 +175,39 @@ __global__ __launch_bounds__(256) void decode_mfma_kernel(DecodeArgs a, int n_ch
     decode_item<KB, OT>(a, lds_A, lds_cs, blockIdx.y, chunk, threadIdx.x & 63);
 }
 
-// Persistent form for a batch of frames of one 32-wide K-block class: each
-// workgroup pulls (frame, channel, 4 chunks) items from a queue; the operand
-// tables are restaged in LDS only when the frame changes (items are grouped
-// by frame).
+// Persistent form for a batch of frames of one 32-wide K-block class: the
+// workgroups stride over the (frame, channel, 4 chunks) items (items of one
+// class cost the same, so a static stride balances them without a queue: no
+// atomic and no barrier per item); the operand tables are restaged in LDS
+// only when the frame changes (items are grouped by frame, and a
+// workgroup's items come in increasing order).
+// (register caps: the occupancy of the single-frame kernel of the same K
+// blocks; without them the item loop took up to 305 registers, one
+// wavefront per SIMD for 128 transmits)
+template <int KB> struct DecWaves {
+    static constexpr int value = KB == 1 ? 6 : KB == 2 ? 4 : 2;
+};
 template <int KB, int OT>
-__global__ __launch_bounds__(256) void decode_persistent_kernel(const FrameDec *frames,
-                                                                const int2 *items, int n_items,
-                                                                int *counter,
-                                                                void *const *rf_ptrs)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DecWaves<KB>::value))) void decode_persistent_kernel(const FrameDec *__restrict__ frames,
+                                                                const int2 *__restrict__ items,
+                                                                int n_items, int *counter,
+                                                                void *const *__restrict__ rf_ptrs)
 {
+    (void)counter;
     __shared__ v4i lds_A[KB * KB * 64];
     __shared__ int lds_cs[KB * 32];
-    __shared__ int s_item;
     int staged = -1;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
-        __syncthreads();
-        const int item = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        if (item >= n_items) break;
+    for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+        // (a compiler-only memory barrier: the operand fragments are read from
+        // LDS per item, as in the single-frame kernel, instead of being held
+        // in registers across items, which would cost occupancy)
+        asm volatile("" ::: "memory");
         const int fr = __builtin_amdgcn_readfirstlane(items[item].x);
         const int wy = __builtin_amdgcn_readfirstlane(items[item].y);
         DecodeArgs a = frames[fr].a;
         a.rf = static_cast<const int16_t *>(rf_ptrs[fr]);
         if (fr != staged) {
+            if (staged >= 0) __syncthreads();     // every wavefront is done with the old tables
             stage_operands<KB>(a, lds_A, lds_cs);
             staged = fr;
         }

@@ -524,10 +524,12 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg, int adj, const int *bw_adj
     const size_t lds_cap = lds_cap_bytes();
     const int nwaves = nthr / 64;
     // staging rounds per thread: the batch's quads dealt over the workgroup's
-    // threads; the kernels unroll 2 rounds (3 with two points per lane and
-    // for the row-column modes, 4 for FORCES planes with two points per lane)
+    // threads; the kernels unroll 2 rounds (3 with two points per lane, for
+    // the row-column modes and for the forward FORCES plane kernel on real
+    // data, 4 for FORCES planes with two points per lane)
     const int max_rounds = (p.mode == BF_FORCES_2D && zp == 2) ? 4
-                           : (zp == 2 || p.mode == BF_TPW_3D || p.mode == BF_VLS_3D) ? 3 : 2;
+                           : (zp == 2 || p.mode == BF_TPW_3D || p.mode == BF_VLS_3D ||
+                              (p.mode == BF_FORCES_2D && adj == 0 && !p.iq)) ? 3 : 2;
     auto rounds = [&](int n) { return (n * lmax + 64 * nwaves - 1) / (64 * nwaves); };
     const int qs = p.iq ? 2 : 1;
     const bool staged = adj == 0 || (adj & 1);    // the RF gradient alone reads no data

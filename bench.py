@@ -700,11 +700,13 @@ def autofocus_stage(torch, bfm, synth, reps: int = 5):
     return out
 
 
-def n4_workloads(torch, bfm, synth, reps: int = 2):
+def n4_workloads(torch, bfm, synth, reps: int = 6):
     """Decode + DAS of the additional transmit models at the headline volume
     size (128x128 array, 2048 samples, 128x128x256 voxels): diverging-wave
-    HERCULES (LDS kernel), TPW with 32 angles and VLS-128 (gather kernel,
-    unencoded data), and the cross-plane FORCES pair as one captured graph."""
+    HERCULES (LDS kernel, two points per lane), TPW with 32 angles and
+    VLS-128 (separable LDS kernels, unencoded data), and the cross-plane
+    FORCES pair as one captured graph of the batched path against plain
+    per-frame calls."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     res = {}
@@ -744,7 +746,7 @@ def n4_workloads(torch, bfm, synth, reps: int = 2):
     bp.graph_launch(rf_d, outs)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    xreps = 5 * reps          # (about a millisecond per pass)
+    xreps = 2 * reps          # (about a millisecond per pass)
     a.record(stream)
     for _ in range(xreps):
         bp.graph_launch(rf_d, outs)

@@ -423,9 +423,10 @@ __device__ inline void slot_trace(const BatchDesc &d, int e, int *i, int *j, boo
 // QM * 64 * wavefronts): 4 for FORCES planes with two points per lane (8
 // wavefronts stage the windows of a 16-wavefront box), 3 for HERCULES with
 // two points and the row-column modes (longer windows) and for the forward
-// FORCES plane kernel on real data with one point per lane (whose default
-// 16-trace batch needs two: the third, unrolled and idle, measured 3 %
-// faster on the 256 x 256 plane, 0.146 against 0.151 ms), else 2.
+// FORCES plane kernel on real data with one point per lane (its default
+// 16-trace batch of ~130-quad windows needs three; with two the host trimmed
+// the batch to 12 traces: 0.151 against 0.146 ms on the 256 x 256 plane),
+// else 2.
 template <int MODE, int ZP, int ADJ, int ET> struct StageRounds {
     static constexpr int value = (MODE == MODE_FORCES && ZP == 2) ? 4
                                  : (ZP == 2 || MODE == MODE_TPW || MODE == MODE_VLS ||

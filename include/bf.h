@@ -317,7 +317,10 @@ int bf_batch_run(bf_plan plan, const int16_t *const *rf, float *const *out, void
 
 /* Same work as bf_batch_run, recorded once into a hipGraph and replayed on
  * later calls.  The frame pointers are copied into the plan's device table
- * before each replay, so new buffers need no re-capture. */
+ * before each replay, so new buffers need no re-capture; a call with the same
+ * buffers on the same stream as the last copy (of either entry point) finds
+ * them there and copies nothing.  Calls of one plan on different streams must
+ * not overlap: they share the table. */
 int bf_graph_launch(bf_plan plan, const int16_t *const *rf, float *const *out, void *stream);
 
 /* How the batched path runs frame f of a batch plan (after its first

@@ -510,14 +510,19 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg, int adj, const int *bw_adj
     // Window of an active point: its quad index floor(s) - w0 lies in
     // [1, k spread + 3] (the start w0 is floored 2 samples below the box's
     // lowest path, the quad covers taps n-1 .. n+2); one quad of FP32 slack.
-    const int lmax = (int)ceil(a.k * spread) + 5;
+    // The separable forward kernels on real data with cubic or linear reads
+    // split the start into a transmit part and a row part, each floored,
+    // which puts it up to one sample lower: one more quad, and one more guard
+    // entry (plus one for the rounding of the folded sums).
+    const int fold = (sep && adj == 0 && !p.iq && p.interp != BF_INTERP_NEAREST) ? 1 : 0;
+    const int lmax = (int)ceil(a.k * spread) + 5 + fold;
     // The terms read without an index clamp: a lane outside its receive
     // aperture (weight 0) may reach past its window by at most the receive
     // path's extra lateral slope, (1 - srx) times the box's receive-lateral
     // extent (HERCULES: radial; FORCES: x; TPW, VLS: y), into the next window
     // or this zeroed guard
     const double rx_lat = p.mode == BF_HERCULES_3D ? lat : p.mode == BF_FORCES_2D ? E[0] : E[1];
-    const int guard = (int)ceil(a.k * (1.0 - srx) * rx_lat) + 3;
+    const int guard = (int)ceil(a.k * (1.0 - srx) * rx_lat) + 3 + 2 * fold;
     const int nthr = 64 * bw[0] * bw[1] * bw[2];
     const int unit = sep ? JC : 1;      // separable modes: JC rows per batch
     int nbb = std::max(nb - nb % unit, unit);

@@ -458,7 +458,11 @@ __device__ inline bool stage_slot(const LdsCfg &c, int q, int wave, int lane, in
 // Descriptor of trace slot `lane` of batch d (see TraceDesc).  s_lo: the
 // box's tx_lo table (n_tx entries) and, at lo_rx, its rx_lo table
 // (separable modes).
-template <int MODE>
+// FOLD (separable forward kernels on real data, cubic or linear reads):
+// s_lo holds the box's integer window-start parts A_i (transmits) and B_j
+// (rows) instead of the path bounds, and the trace's window starts at
+// A_i + B_j.
+template <int MODE, bool FOLD = false>
 __device__ inline TraceDesc trace_desc(const DasArgs &a, const LdsCfg &c, const BoxGeom &b,
                                        const float *s_tx, const float *s_rx, const float *s_lo,
                                        int lo_rx, const BatchDesc &d, int lane)
@@ -472,6 +476,8 @@ __device__ inline TraceDesc trace_desc(const DasArgs &a, const LdsCfg &c, const 
             t.xi = s_tx[i];
             if constexpr (MODE == MODE_HERCULES)
                 t.w0 = window_start_hercules(b, t.xi, s_rx[j]);
+            else if constexpr (FOLD)
+                t.w0 = (int)(s_lo[i] + s_lo[lo_rx + j]);   // integers: exact
             else
                 t.w0 = window_from_path(b, s_lo[i] + s_lo[lo_rx + j]);
             // taps w0 - 1 .. w0 + lmax + 1 of the window; none inside the record:
@@ -791,6 +797,25 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     // two buffers of [nb * lmax] quads (the Hann table sits right before
     // them: an index of -1 reads finite data)
     constexpr bool SEP = MODE != MODE_HERCULES;
+    // Separable forward kernels on real data fold the window start into the
+    // paths.  The start of trace (i, j) is split as A_i + B_j, with
+    //   A_i = floor(k tx_lo_i - Zb),  B_j = floor(k rx_lo_j + Zb - t0 fs) - 2,
+    // Zb = k times the box's top depth (it keeps both parts, and the sums
+    // below, near the window length).  A_i + B_j is at most 2 samples below
+    // the box's lowest path (floor(u) + floor(v) <= u + v) and at most one
+    // sample below the unsplit start floor(k (tx_lo + rx_lo) - t0 fs) - 2,
+    // so the windows grow by one quad.  A term's window position is then
+    //   (fB + k E_rx + nB - B_j) + (k E_tx - A_i),
+    // the first sum per (point, row) once per row chunk, the second per
+    // (point, transmit): its floor is the quad index and no integer add per
+    // term is left.  The sums are kept centred, less hc = lmax / 4 quads (the
+    // window base pointer is moved by hc instead): active positions fill about
+    // the lower two thirds of a window, and FP32 rounds them at a quarter of
+    // the window's magnitude.  Nearest reads keep the unsplit position: their
+    // sample choice is an integer decision that extra rounding would move at
+    // near ties.
+    constexpr bool FOLD = SEP && ADJ == 0 && ET != ET_CF32 && IP != IN_NEAREST;
+    const int hc = FOLD ? c.lmax >> 2 : 0;
     const int ntx4 = (a.n_tx + 3) & ~3, nch4 = (a.n_ch + 3) & ~3;
     float *s_tx = reinterpret_cast<float *>(smem);
     float *s_rx = s_tx + ntx4;
@@ -825,9 +850,18 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     const int by = blk / (c.blocks_z * c.blocks_x);
     const BoxGeom box = block_box(a, c, bx, by, bz);
     if constexpr (SEP) {   // the box's path bounds (read after the barrier below)
-        for (int t = tid; t < a.n_tx; t += nthr) s_lo[t] = tx_lo<MODE>(a, box, t, as_global(a.tx_x)[t]);
-        for (int t = tid; t < a.n_ch; t += nthr) s_lo[ntx4 + t] = rx_lo<MODE>(box, as_global(a.rx_c)[t]);
+        const float zb = box.kf * fmaxf(box.zmin, 0.f);
+        for (int t = tid; t < a.n_tx; t += nthr) {
+            const float lo = tx_lo<MODE>(a, box, t, as_global(a.tx_x)[t]);
+            s_lo[t] = FOLD ? floorf(fmaf(box.kf, lo, -zb)) : lo;
+        }
+        for (int t = tid; t < a.n_ch; t += nthr) {
+            const float lo = rx_lo<MODE>(box, as_global(a.rx_c)[t]);
+            s_lo[ntx4 + t] = FOLD ? floorf(fmaf(box.kf, lo, zb - box.t0f)) - 2.f : lo;
+        }
     }
+    if constexpr (FOLD)    // the terms keep no window starts; an index of -1 reads these zeros
+        for (int t = tid; t < 2 * w0_stride; t += nthr) s_w0[t] = 0;
     LaneL Lp[ZP];
 #pragma unroll
     for (int p = 0; p < ZP; ++p) Lp[p] = lane_setup_l<MODE>(a, c, bx, by, bz, wave, lane, p);
@@ -891,12 +925,12 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     Staged<QM> st;
     TraceDesc td = {0, 0.f, NO_DATA, 0};   // descriptors of the current batch
     if (cur.valid) {
-        td = trace_desc<MODE>(a, c, box, s_tx, s_rx, s_lo, ntx4, cur, lane);
+        td = trace_desc<MODE, FOLD>(a, c, box, s_tx, s_rx, s_lo, ntx4, cur, lane);
         if constexpr (STAGE) {
             stage_load<ET, QM>(a, c, td, st, wave, lane, nwaves);
             stage_store<IP, QS, QM, GC>(c, st, q0, wave, lane, nwaves);
         }
-        store_w0(c, td, s_w0, wave, lane);
+        if constexpr (!FOLD) store_w0(c, td, s_w0, wave, lane);
     }
     TraceDesc td_prev = td;            // RF gradient: windows of the previous batch
     __syncthreads();
@@ -918,7 +952,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
         BatchDesc nxt = next_batch<MODE>(a, c, box, s_tx, s_rx, it);
         TraceDesc td_n = {0, 0.f, NO_DATA, 0};
         if (nxt.valid) {
-            td_n = trace_desc<MODE>(a, c, box, s_tx, s_rx, s_lo, ntx4, nxt, lane);
+            td_n = trace_desc<MODE, FOLD>(a, c, box, s_tx, s_rx, s_lo, ntx4, nxt, lane);
             if constexpr (STAGE) stage_load<ET, QM>(a, c, td_n, st, wave, lane, nwaves);
         }
         // the previous batch's gradient windows (complete since the last barrier)
@@ -978,13 +1012,16 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
             for (int q = 0; q < JC; ++q) {
                 if (cur.rows[q] != rows_cur[q]) {
                     rows_cur[q] = cur.rows[q];
-                    const float dxr = rx_coord<MODE>(L.x, L.y) - s_rx[slot_row(rows_cur[q])];
+                    const int row = slot_row(rows_cur[q]);
+                    const float dxr = rx_coord<MODE>(L.x, L.y) - s_rx[row];
                     const float r2 = dxr * dxr;
+                    const int bj = FOLD ? (int)s_lo[ntx4 + row] : 0;
                     bool any = false;
 #pragma unroll
                     for (int p = 0; p < ZP; ++p) {
                         const bool act = r2 < Lp[p].thr && !slot_pad(rows_cur[q]);
                         Rj[q][p] = fmaf(excess(r2, Lp[p].z, Lp[p].z2), kf, Lp[p].fB);
+                        if constexpr (FOLD) Rj[q][p] += (float)(Lp[p].nB - bj - hc);
                         aj[q][p] = act ? hann_u2(r2 * Lp[p].wsc) : 0.f;
                         any = any || act;
                     }
@@ -1002,32 +1039,46 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
             static_assert(JC % 4 == 0, "the window starts of a transmit are JC / 4 int4 loads");
             constexpr int NW4 = JC / 4;
             int4 nw4_n[NW4];
+            float ai_n = 0.f;                 // FOLD: A_i of the next transmit
+            if constexpr (FOLD) {
+                ai_n = s_lo[cur.i0];
+            } else {
 #pragma unroll
-            for (int r = 0; r < NW4; ++r) nw4_n[r] = wst4[r];
+                for (int r = 0; r < NW4; ++r) nw4_n[r] = wst4[r];
+            }
             for (int ii = 0; ii < cur.cnt; ++ii) {
                 const float2 tsc = tsc_n;
                 const float xi = xi_n;
+                const float ai = ai_n;
                 int nw[JC];                   // negated window starts of the JC rows
+                if constexpr (!FOLD) {
 #pragma unroll
-                for (int r = 0; r < NW4; ++r) {
-                    nw[4 * r] = nw4_n[r].x;
-                    nw[4 * r + 1] = nw4_n[r].y;
-                    nw[4 * r + 2] = nw4_n[r].z;
-                    nw[4 * r + 3] = nw4_n[r].w;
+                    for (int r = 0; r < NW4; ++r) {
+                        nw[4 * r] = nw4_n[r].x;
+                        nw[4 * r + 1] = nw4_n[r].y;
+                        nw[4 * r + 2] = nw4_n[r].z;
+                        nw[4 * r + 3] = nw4_n[r].w;
+                    }
                 }
                 const int in = min(ii + 1, cur.cnt - 1);
                 if constexpr (MODE == MODE_TPW)
                     tsc_n = make_float2(tscf[2 * in], tscf[2 * in + 1]);
                 else
                     xi_n = txc[in];
+                if constexpr (FOLD) {
+                    ai_n = s_lo[cur.i0 + in];
+                } else {
 #pragma unroll
-                for (int r = 0; r < NW4; ++r) nw4_n[r] = wst4[NW4 * in + r];
+                    for (int r = 0; r < NW4; ++r) nw4_n[r] = wst4[NW4 * in + r];
+                }
                 // transmit excess path of each of the lane's points, shared by
-                // the batch's rows
+                // the batch's rows (FOLD: minus A_i)
                 float T[ZP];
 #pragma unroll
-                for (int p = 0; p < ZP; ++p)
-                    T[p] = kf * tx_excess_p<MODE>(L.x, Lp[p].z, Lp[p].z2, tsc, xi, a.zf);
+                for (int p = 0; p < ZP; ++p) {
+                    const float ex = tx_excess_p<MODE>(L.x, Lp[p].z, Lp[p].z2, tsc, xi, a.zf);
+                    T[p] = FOLD ? fmaf(kf, ex, -ai) : kf * ex;
+                }
                 // every slot holds a real row (padding slots have weight 0 and
                 // a zero window), so the forward and dL/dc terms of the JC rows
                 // run without branches and their LDS reads overlap; the RF
@@ -1040,10 +1091,15 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                     for (int p = 0; p < ZP; ++p) {
                         const float sq = Rj[q][p] + T[p];
                         // no clamp: li lies in [1, lmax + guard) for every lane
-                        // (its geometry is inside the box); lanes outside the
-                        // row's aperture (weight 0) may read into the next
-                        // window or the zeroed guard
-                        const int li = add3_vvv(cvt_flr(sq), Lp[p].nB, nw[q]);
+                        // (its geometry is inside the box; FOLD: li + hc, and
+                        // in [0, ...) with the rounding of the folded sums);
+                        // lanes outside the row's aperture (weight 0) may read
+                        // into the next window or the zeroed guard
+                        int li;
+                        if constexpr (FOLD)
+                            li = cvt_flr(sq);
+                        else
+                            li = add3_vvv(cvt_flr(sq), Lp[p].nB, nw[q]);
                         if constexpr (ET == ET_CF32) {
                             const float4 *win = quads + e * c.lmax * QS;
                             const float t = __builtin_amdgcn_fractf(sq);
@@ -1061,8 +1117,9 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                             if constexpr (GE)
                                 scatter_taps<IP>(accw + e * lw, k, Gv[p] * aj[q][p], t);
                         } else {
-                            const float v =
-                                eval_quad<IP>(quads[e * c.lmax + li], __builtin_amdgcn_fractf(sq));
+                            // (FOLD: li counts from quad hc of the window)
+                            const float v = eval_quad<IP>(quads[(e * c.lmax + hc) + li],
+                                                          __builtin_amdgcn_fractf(sq));
                             acc[p].x = fmaf(aj[q][p], v, acc[p].x);
                         }
                     }
@@ -1072,7 +1129,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
 
         if (!nxt.valid) break;
         if constexpr (STAGE) stage_store<IP, QS, QM, GC>(c, st, ((bi + 1) & 1) ? q1 : q0, wave, lane, nwaves);
-        store_w0(c, td_n, s_w0 + ((bi + 1) & 1) * w0_stride, wave, lane);
+        if constexpr (!FOLD) store_w0(c, td_n, s_w0 + ((bi + 1) & 1) * w0_stride, wave, lane);
         __syncthreads();
         cur = nxt;
         td_prev = td;

@@ -248,7 +248,8 @@ def test_forces_plane_two_points_matches_oracle(torch_mod, interp, nz, tile, blo
     """FORCES planes with two depth points per lane (variant lds2):
     odd and tiny depth counts, several tiles, workgroups and batches, linear
     and nearest reads, F# 0, the y-z plane of a frame rotated about z; and
-    the one-point kernel gives the same image to FP32 rounding."""
+    the one-point kernel gives the same image to FP32 rounding (of the
+    window positions, which depend on the box)."""
     torch = torch_mod
     d = _plane(interp, nz, **kw)
     H, e = _data(d, 11)
@@ -266,7 +267,10 @@ def test_forces_plane_two_points_matches_oracle(torch_mod, interp, nz, tile, blo
     p1 = bfm.Plan(d, H, tile=tile)
     p1.set_das_config("lds", block, nb)
     one = p1.das(et).cpu().numpy()
-    assert rel_l2(got, one) <= (tol if interp == "nearest" else 1e-6)
+    # (cubic and linear reads: the two kernels' boxes differ, and with them
+    # the window-start parts folded into the FP32 positions; the agreement
+    # bound is the one of the plane kernel's tilings, test_das_tiles_agree)
+    assert rel_l2(got, one) <= (tol if interp == "nearest" else 4e-6)
 
 
 @pytest.mark.parametrize("e_type", ["bf16", "i32"])

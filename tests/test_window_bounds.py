@@ -9,10 +9,21 @@ path, floored 2 samples down), the staged length lmax (Frame::lds_config: the
 delay spread of active points plus 5) and the guard ((1 - srx) times the
 receive-lateral extent, plus 3), and checks them on sampled boxes of the
 workload geometries and of small grids (tilted, through the array plane,
-diverging, VLS focal lines, several F#).  Paths per Table I's methods: HERCULES
+diverging, VLS focal lines, several F#).  Active points (apodization > 0)
+must also read inside their own window: index at most lmax - 1 (the quad
+covers taps n-1 .. n+2).  Paths per Table I's methods: HERCULES
 tx = z (plane) or |p - v| - f (diverging), rx = |p - (x_i, y_j, 0)|; FORCES
 tx = |p - col_i|_xz, rx = |p - col_j|_xz; TPW tx = x sin a + z cos a; VLS
 tx = z_f + sgn(z - z_f) |(x - x_i, z - z_f)|; row receivers |(y - y_j, z)|.
+
+The separable forward kernels on real data (FORCES, TPW, VLS) split the
+start into a transmit part and a row part, each floored:
+floor(k tx_lo - Zb) + floor(k rx_lo + Zb - t0 fs) - 2 with Zb = k times the
+box's top depth, one quad longer windows and a guard two entries longer
+(`fold`).  Their terms take the index as the floor of an FP32 sum, which may
+round across an integer: there the index must fit with one entry to spare
+at either end (at least 1, below lmax - 1 for active points, below
+lmax + guard - 1 for all).
 """
 import math
 
@@ -43,8 +54,9 @@ def _far(v, a, b):
     return max(abs(v - a), abs(v - b))
 
 
-def window_range(desc, tile, bw, zp=1, nboxes=8, seed=0):
-    """(min, max) of the window index over sampled boxes, and lmax + guard."""
+def window_range(desc, tile, bw, zp=1, nboxes=8, seed=0, fold=False):
+    """(min, max) of the window index over sampled boxes, the max over
+    active points, lmax and lmax + guard."""
     mode = desc["mode"]
     nx, ny, nz = desc["dims"]
     org, ax, ay, az, centre = _grid(desc)
@@ -83,13 +95,13 @@ def window_range(desc, tile, bw, zp=1, nboxes=8, seed=0):
     else:
         spread = (E[2] + srx * lat + math.hypot(lat, E[2])) if div_f > 0 else 2 * E[2] + srx * lat
         rx_lat = lat
-    lmax = math.ceil(k * spread) + 5
-    guard = math.ceil(k * (1 - srx) * rx_lat) + 3
+    lmax = math.ceil(k * spread) + 5 + (1 if fold else 0)
+    guard = math.ceil(k * (1 - srx) * rx_lat) + 3 + (2 if fold else 0)
     nbx, nby, nbz = -(-nx // tx), -(-ny // ty), -(-(nz + z_off) // tz)
     rng = np.random.default_rng(seed)
     boxes = [(0, 0, 0), (nbx - 1, nby - 1, nbz - 1), (nbx // 2, nby // 2, nbz // 2)]
     boxes += [tuple(int(v) for v in rng.integers([nbx, nby, nbz])) for _ in range(nboxes)]
-    lo_all, hi_all = math.inf, -math.inf
+    lo_all, hi_all, hi_act = math.inf, -math.inf, -math.inf
     for bx, by, bz in boxes:
         i0 = [bx * tx, by * ty, max(bz * tz - z_off, 0)]
         i1 = [min(bx * tx + tx - 1, nx - 1), min(by * ty + ty - 1, ny - 1),
@@ -108,7 +120,10 @@ def window_range(desc, tile, bw, zp=1, nboxes=8, seed=0):
                                  indexing="ij")
         P = org + IX[..., None] * ax + IY[..., None] * ay + IZ[..., None] * az
         px, py = P[..., 0].ravel(), P[..., 1].ravel()
-        pz = np.maximum(P[..., 2].ravel(), 1e-7)
+        pz_raw = P[..., 2].ravel()
+        pz = np.maximum(pz_raw, 1e-7)
+        thr = np.where(pz_raw > 0, pz * pz * 0.25 / f2 if f2 > 0 else np.inf, -1.0)
+        zb = k * zlo
         txlo = zlo
         if div_f > 0:
             ddx, ddy = max(0.0, lo[0], -hi[0]), max(0.0, lo[1], -hi[1])
@@ -122,16 +137,20 @@ def window_range(desc, tile, bw, zp=1, nboxes=8, seed=0):
                 xi = tx_x[i]
                 if mode == "hercules":
                     txp = (np.sqrt(px ** 2 + py ** 2 + (pz + div_f) ** 2) - div_f) if div_f > 0 else pz
-                    rxp = np.sqrt((px - xi) ** 2 + (py - cj) ** 2 + pz ** 2)
+                    rho2 = (px - xi) ** 2 + (py - cj) ** 2
+                    rxp = np.sqrt(rho2 + pz ** 2)
                     rx_, ry_ = _dist(xi, lo[0], hi[0]), _dist(cj, lo[1], hi[1])
                     path = txlo + math.sqrt(rx_ * rx_ + ry_ * ry_ + zlo * zlo)
                 elif mode == "forces":
                     txp = np.sqrt((px - xi) ** 2 + pz ** 2)
-                    rxp = np.sqrt((px - cj) ** 2 + pz ** 2)
+                    rho2 = (px - cj) ** 2
+                    rxp = np.sqrt(rho2 + pz ** 2)
                     rt, rr = _dist(xi, lo[0], hi[0]), _dist(cj, lo[0], hi[0])
-                    path = math.sqrt(rt * rt + zlo * zlo) + math.sqrt(rr * rr + zlo * zlo)
+                    txb, rxb = math.sqrt(rt * rt + zlo * zlo), math.sqrt(rr * rr + zlo * zlo)
+                    path = txb + rxb
                 else:
-                    rxp = np.sqrt((py - cj) ** 2 + pz ** 2)
+                    rho2 = (py - cj) ** 2
+                    rxp = np.sqrt(rho2 + pz ** 2)
                     ry_ = _dist(cj, lo[1], hi[1])
                     if mode == "tpw":
                         sn, cs = math.sin(ang[i]), math.cos(ang[i])
@@ -145,11 +164,18 @@ def window_range(desc, tile, bw, zp=1, nboxes=8, seed=0):
                         else:
                             r_ = _far(xi, lo[0], hi[0])
                             txb = zf - math.sqrt(r_ * r_ + (zf - zlo) ** 2)
-                    path = txb + math.sqrt(ry_ * ry_ + zlo * zlo)
-                w0 = math.floor(path * k - t0fs) - 2
+                    rxb = math.sqrt(ry_ * ry_ + zlo * zlo)
+                    path = txb + rxb
+                if fold:
+                    w0 = math.floor(k * txb - zb) + math.floor(k * rxb + zb - t0fs) - 2
+                else:
+                    w0 = math.floor(path * k - t0fs) - 2
                 li = np.floor((txp + rxp) * k - t0fs) - w0
                 lo_all, hi_all = min(lo_all, li.min()), max(hi_all, li.max())
-    return lo_all, hi_all, lmax + guard
+                act = rho2 < thr
+                if act.any():
+                    hi_act = max(hi_act, li[act].max())
+    return lo_all, hi_all, hi_act, lmax, lmax + guard
 
 
 def _small(mode, z0=1.0 * MM, f_number=1.0, **kw):
@@ -201,5 +227,16 @@ CASES = [
 
 @pytest.mark.parametrize("name, make, tile, bw, zp", CASES, ids=[c[0] for c in CASES])
 def test_unclamped_window_index_stays_in_bounds(name, make, tile, bw, zp):
-    lo, hi, limit = window_range(make(), tile, bw, zp, nboxes=3 if name.startswith("w") else 12)
-    assert lo >= -1 and hi < limit, (name, lo, hi, limit)
+    lo, hi, hi_act, lmax, limit = window_range(make(), tile, bw, zp,
+                                               nboxes=3 if name.startswith("w") else 12)
+    assert lo >= -1 and hi < limit and hi_act <= lmax - 1, (name, lo, hi, hi_act, lmax, limit)
+
+
+FOLD_CASES = [c for c in CASES if "hercules" not in c[0] and "diverging" not in c[0]]
+
+
+@pytest.mark.parametrize("name, make, tile, bw, zp", FOLD_CASES, ids=[c[0] for c in FOLD_CASES])
+def test_folded_window_start_stays_in_bounds(name, make, tile, bw, zp):
+    lo, hi, hi_act, lmax, limit = window_range(make(), tile, bw, zp,
+                                               nboxes=3 if name.startswith("w") else 12, fold=True)
+    assert lo >= 1 and hi_act < lmax - 1 and hi < limit - 1, (name, lo, hi, hi_act, lmax, limit)

@@ -484,7 +484,10 @@ __device__ inline TraceDesc trace_desc(const DasArgs &a, const LdsCfg &c, const 
             // nothing to stage (and a padding slot stages zeros)
             if (!pad && t.w0 + c.lmax + 1 >= 0 && t.w0 - 1 < a.S) {
                 t.sw = t.w0;
-                t.off = (i * a.n_ch + j) * a.S + t.w0;
+                // 24-bit products: traces < 2^18, samples <= 2^16 (plan
+                // limits), element offsets < 2^31
+                const unsigned tr = __umul24((unsigned)i, (unsigned)a.n_ch) + (unsigned)j;
+                t.off = (int)__umul24(tr, (unsigned)a.S) + t.w0;
             }
         }
     }
@@ -1107,7 +1110,9 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                                                          eval_quad<IP>(win[2 * li + 1], t));
                             rotate_acc(v, aj[q][p], fmaf(rot, sq, Lp[p].ph0), acc[p]);
                         } else if constexpr (ADJ != 0) {
-                            const int k = clamp0_i32(li, c.lmax - 1);
+                            // the RF gradient's scatter stays inside the window;
+                            // dL/dc alone reads unclamped, as the forward terms do
+                            const int k = GE ? clamp0_i32(li, c.lmax - 1) : li;
                             const float t = __builtin_amdgcn_fractf(sq);
                             if constexpr (GC) {
                                 const float wv = aj[q][p] * eval_dquad<IP>(quads[e * c.lmax + k], t);

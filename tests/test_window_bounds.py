@@ -229,7 +229,11 @@ CASES = [
 def test_unclamped_window_index_stays_in_bounds(name, make, tile, bw, zp):
     lo, hi, hi_act, lmax, limit = window_range(make(), tile, bw, zp,
                                                nboxes=3 if name.startswith("w") else 12)
-    assert lo >= -1 and hi < limit and hi_act <= lmax - 1, (name, lo, hi, hi_act, lmax, limit)
+    # (the separable kernels, whose windows sit after integer tables, need
+    # an index of at least 0 after FP32 rounding: at least 1 here)
+    sep = "hercules" not in name and "diverging" not in name
+    assert lo >= (1 if sep else -1), (name, lo)
+    assert hi < limit and hi_act <= lmax - 1, (name, lo, hi, hi_act, lmax, limit)
 
 
 FOLD_CASES = [c for c in CASES if "hercules" not in c[0] and "diverging" not in c[0]]

@@ -58,23 +58,19 @@ __device__ inline uint32_t f32_to_bf16_rne(float f)
 template <int OT>
 __device__ inline void store_pair(void *e, long idx, int v0, int v1, bool two, bool even_S)
 {
-    if constexpr (OT == ET_F32) {
-        const gptr_mut<float> p = as_global_mut(static_cast<float *>(e) + idx);
+    // (with an even sample count the pair is 8-byte aligned: one 8-byte store
+    // per lane, so each half-wavefront writes 256 contiguous bytes in one
+    // instruction)
+    if constexpr (OT == ET_F32 || OT == ET_I32) {
+        const uint32_t u0 = OT == ET_F32 ? __float_as_uint((float)v0) : (uint32_t)v0;
+        const uint32_t u1 = OT == ET_F32 ? __float_as_uint((float)v1) : (uint32_t)v1;
+        const gptr_mut<uint32_t> p = as_global_mut(static_cast<uint32_t *>(e) + idx);
         if (two && even_S) {
-            p[0] = (float)v0;
-            p[1] = (float)v1;
+            *reinterpret_cast<gptr_mut<unsigned long long>>(p) =
+                (unsigned long long)u0 | ((unsigned long long)u1 << 32);
         } else {
-            p[0] = (float)v0;
-            if (two) p[1] = (float)v1;
-        }
-    } else if constexpr (OT == ET_I32) {
-        const gptr_mut<int> p = as_global_mut(static_cast<int *>(e) + idx);
-        if (two && even_S) {
-            p[0] = v0;
-            p[1] = v1;
-        } else {
-            p[0] = v0;
-            if (two) p[1] = v1;
+            p[0] = u0;
+            if (two) p[1] = u1;
         }
     } else {
         const gptr_mut<uint16_t> p = as_global_mut(static_cast<uint16_t *>(e) + idx);

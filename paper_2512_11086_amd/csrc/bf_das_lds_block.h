@@ -24,7 +24,9 @@
 // channel row), and the apodization depends on the row only.  A batch holds
 // JC rows x nb/JC transmits; each lane computes the receive path and weight
 // of a row once, the transmit path of a transmit once per batch (shared by
-// the JC rows), and every term adds the two.
+// the JC rows), and every term adds the two.  The forward kernels on real
+// data fold the trace's window start into the two paths (FOLD in das_block),
+// so the sum is the position inside the staged window.
 //
 // Apodization skip (Sec. VII-F): a channel row is staged only if the receive
 // aperture of the deepest point of the box reaches it; within a row only the
@@ -794,11 +796,12 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     const int nwaves = nthr >> 6;
 
     // tables: tx_x, rx_c, the box's path bounds tx_lo, rx_lo (separable
-    // modes), the window starts of the two batch buffers (negated; read by the
-    // terms with one LDS load instead of a lane broadcast), Hann weights
-    // (HERCULES; the separable modes weight rows with the polynomial), then
-    // two buffers of [nb * lmax] quads (the Hann table sits right before
-    // them: an index of -1 reads finite data)
+    // modes; FOLD: their integer window-start parts), the window starts of the
+    // two batch buffers (negated; read by the terms with one LDS load instead
+    // of a lane broadcast; zeros under FOLD, whose terms need none), Hann
+    // weights (HERCULES; the separable modes weight rows with the polynomial),
+    // then two buffers of [nb * lmax] quads (the Hann table, or the zeroed
+    // window starts, sit right before them: an index of -1 reads finite data)
     constexpr bool SEP = MODE != MODE_HERCULES;
     // Separable forward kernels on real data fold the window start into the
     // paths.  The start of trace (i, j) is split as A_i + B_j, with

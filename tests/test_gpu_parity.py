@@ -342,6 +342,21 @@ def test_das_edge_cases(torch_dev):
     assert rel_l2(g2, ref) <= TOL_L2
 
 
+@pytest.mark.parametrize("mode", ["forces", "hercules"])
+def test_das_record_starts_late(torch_dev, mode):
+    """Sample 0 taken 2 us after the transmit: the shallow points' delays fall
+    before the record (negative window starts, taps read as 0), the deeper
+    ones inside it; both kernels against the oracle."""
+    torch, _ = torch_dev
+    desc = _small_desc(mode, "cubic", f_number=1.0, t0=2e-6)
+    H, e = _small_data(_small_desc(mode, "cubic", f_number=1.0), seed=12)
+    ref = oracle.das(desc, e)
+    assert np.any(ref == 0.0) and np.any(ref != 0.0)
+    for variant in ("lds", "gather"):
+        _, _, got = _das_gpu(torch, desc, H, e.astype(np.float32), variant=variant)
+        assert rel_l2(got, ref) <= TOL_L2, variant
+
+
 def test_das_repeatable_bitwise(torch_dev, workload0):
     torch, _ = torch_dev
     desc, H, rf, _ = workload0

@@ -494,7 +494,9 @@ def batched_comparison(torch, bfm, stream4, reps: int):
 def decode_share(torch, bfm, synth, reps: int = 20):
     """Decode and DAS times of the plane workloads (0: FORCES 128x128 from 32 x
     32 x 1024; 3: one FORCES 256x256 frame from 64 x 64 x 2048): the largest
-    saving a decode fused into DAS could give is the decode's own time."""
+    saving a decode fused into DAS could give is the decode's own time.  The
+    fused kernel (bf_das_fused: the decode inside the DAS staging, one
+    launch, same image bit for bit) is timed beside them."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     out = {}
@@ -509,7 +511,9 @@ def decode_share(torch, bfm, synth, reps: int = 20):
         e = plan.decode(rf_d)
         img = plan.das(e)
         torch.cuda.synchronize()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        fused_img = plan.das_fused(rf_d)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record(stream)
         for _ in range(reps):
             plan.decode(rf_d, out=e)
@@ -517,11 +521,18 @@ def decode_share(torch, bfm, synth, reps: int = 20):
         for _ in range(reps):
             plan.das(e, out=img)
         ev[2].record(stream)
+        for _ in range(reps):
+            plan.das_fused(rf_d, out=fused_img)
+        ev[3].record(stream)
         torch.cuda.synchronize()
         dec = ev[0].elapsed_time(ev[1]) / reps
         das = ev[1].elapsed_time(ev[2]) / reps
+        fused = ev[2].elapsed_time(ev[3]) / reps
         out[name] = {"decode_ms": round(dec, 4), "das_ms": round(das, 4),
-                     "decode_share": round(dec / (dec + das), 4)}
+                     "decode_share": round(dec / (dec + das), 4),
+                     "fused_ms": round(fused, 4),
+                     "fused_vs_decode_plus_das": round(fused / (dec + das), 3),
+                     "fused_bitwise_equal": bool(torch.equal(fused_img, img))}
     return out
 
 

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define BF_ABI_VERSION 7
+#define BF_ABI_VERSION 8
 
 /* Largest frame count of bf_das_frames / bf_das_adjoint_frames. */
 #define BF_MAX_FRAMES 4096
@@ -253,6 +253,19 @@ int bf_das(bf_plan plan, const void *e, float *out, double c, void *stream);
  * for every plan).  Other errors as bf_das. */
 #define BF_DAS_NOALLOC_MAX_BYTES (8u << 20)
 int bf_das_noalloc(bf_plan plan, const void *e, float *out, double c, void *stream);
+
+/* Decode fused into DAS (Sec. VII-C's decode -> beamform order in one
+ * kernel; decode Sec. VII-E, DAS Eq. 1): FORCES planes only.  Each staged tap
+ * of decoded trace (i, j) is formed from the RF as sum_k H[k][i] rf[k][j][n]
+ * inside the LDS DAS kernel, so no decoded data is written or read; the sums
+ * are exact in FP32, and out equals bf_decode (BF_E_F32) followed by bf_das
+ * with the same plan, bit for bit.  rf: device int16 [n_tx][n_ch][n_samples];
+ * out: device f32 [Ny][Nx][Nz], overwritten; c as bf_das.  The decode is
+ * repeated for every workgroup box that stages a window, so on the
+ * workloads measured here this is slower than the two calls (the bench's
+ * decode_share object times both).  BF_ERR_UNSUPPORTED for HERCULES, TPW,
+ * VLS or IQ plans, the gather variant, or windows that do not fit LDS. */
+int bf_das_fused(bf_plan plan, const int16_t *rf, float *out, double c, void *stream);
 
 /* Adjoint of bf_das for the same e and c, given grad_out = dL/d(out)
  * (device f32 [Ny][Nx][Nz]).  The paper defines only the forward sum (Eq. 1

@@ -209,6 +209,19 @@ class Plan:
             check(lib().bf_das_frames(self._h, _ptr(e), nf, _ptr(out), cv, _stream(stream)))
         return out
 
+    def das_fused(self, rf, c: float | None = None, out=None, stream=None):
+        """Decode fused into DAS (bf_das_fused, FORCES planes): the image of
+        the int16 RF ``rf`` (n_tx, n_ch, S) in one kernel, equal bit for bit to
+        ``das(decode(rf))`` with an FP32 decoded-data plan."""
+        torch = _torch()
+        self._check_rf(rf)
+        if out is None:
+            out = torch.empty(self.out_shape, dtype=torch.float32, device=rf.device)
+        _check_tensor(out, "out", torch.float32, self.out_shape, rf.device)
+        cv = float(self.c if c is None else c)
+        check(lib().bf_das_fused(self._h, _ptr(rf), _ptr(out), cv, _stream(stream)))
+        return out
+
     def das_adjoint(self, e, grad_out, c: float | None = None, want_e: bool = True,
                     want_c: bool = True, stream=None, out_e=None):
         """Returns (grad_e or None, grad_c tensor of shape () or None).

@@ -12,7 +12,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # BF_LIBRARY names another build of the same library (e.g. one with host-code
 # sanitizers); the default is the in-tree build.
 LIB_PATH = os.environ.get("BF_LIBRARY") or os.path.join(_HERE, "libbf.so")
-ABI_VERSION = 7     # the bf.h version these structures and signatures follow
+ABI_VERSION = 8     # the bf.h version these structures and signatures follow
 
 BF_OK = 0
 BF_ERR_NULL, BF_ERR_SHAPE = -1, -2
@@ -103,6 +103,7 @@ def lib():
         "bf_decode": ([vp, vp, vp, vp], ctypes.c_int),
         "bf_das": ([vp, vp, vp, dbl, vp], ctypes.c_int),
         "bf_das_noalloc": ([vp, vp, vp, dbl, vp], ctypes.c_int),
+        "bf_das_fused": ([vp, vp, vp, dbl, vp], ctypes.c_int),
         "bf_das_adjoint": ([vp, vp, vp, dbl, vp, vp, vp], ctypes.c_int),
         "bf_das_frames": ([vp, vp, i32, vp, dbl, vp], ctypes.c_int),
         "bf_das_adjoint_frames": ([vp, vp, vp, i32, dbl, vp, vp, vp], ctypes.c_int),
@@ -139,7 +140,7 @@ def check(status: int) -> None:
 EXPORTED = ("bf_abi_version", "bf_last_error", "bf_validate", "bf_plan_create",
             "bf_plan_create_batch", "bf_plan_destroy", "bf_plan_get_info", "bf_autotune",
             "bf_set_tile", "bf_set_das_config", "bf_decode", "bf_das", "bf_das_noalloc",
-            "bf_das_adjoint",
+            "bf_das_fused", "bf_das_adjoint",
             "bf_das_frames", "bf_das_adjoint_frames", "bf_sharpness",
             "bf_batch_run", "bf_graph_launch", "bf_batch_get_frame_info", "bf_demod_create",
             "bf_demod_destroy", "bf_demod_out_samples", "bf_demodulate", "bf_env_create",

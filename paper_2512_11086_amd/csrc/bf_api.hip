@@ -615,6 +615,26 @@ int Frame::das(const void *e, float *out, double c, hipStream_t s, float *part) 
     return err == hipSuccess ? BF_OK : hip_fail(err, "DAS launch");
 }
 
+// Decode fused into DAS: the LDS kernel of a FORCES plane staging its taps
+// from the int16 RF through the plan's H (no decoded-data buffer, one launch
+// plus the channel-group sum).  The plan's DAS configuration applies; a
+// window that does not fit LDS, the gather variant, a non-FORCES or an IQ
+// plan is BF_ERR_UNSUPPORTED.
+int Frame::das_fused(const int16_t *rf, float *out, double c, hipStream_t s) const
+{
+    if (p.mode != BF_FORCES_2D || p.iq)
+        return fail(BF_ERR_UNSUPPORTED, "the fused decode + DAS takes FORCES plans with RF data");
+    DasArgs a = das_args(rf, out, c);
+    a.hf = d_Hf;
+    a.hf_ld = 32 * kb;
+    LdsCfg cfg;
+    if (variant == BF_DAS_GATHER || !lds_config(a, &cfg))
+        return fail(BF_ERR_UNSUPPORTED, "the fused decode + DAS needs the LDS kernel "
+                                        "(not the gather variant; windows must fit LDS)");
+    const hipError_t err = launch_das_lds_fused(a, cfg, p.interp, s);
+    return err == hipSuccess ? BF_OK : hip_fail(err, "fused decode + DAS launch");
+}
+
 // The per-frame arrays of `a` advanced to frame f0 of a stack.
 DasArgs Frame::at_frame(const DasArgs &a, int f0) const
 {
@@ -899,6 +919,16 @@ int bf_das(bf_plan plan, const void *e, float *out, double c, void *stream)
     if (!e || !out) return fail(BF_ERR_NULL, "e and out must be non-NULL");
     if ((st = check_c(c)) != BF_OK) return st;
     return plan->frames[0]->das(e, out, c, (hipStream_t)stream);
+}
+
+int bf_das_fused(bf_plan plan, const int16_t *rf, float *out, double c, void *stream)
+{
+    g_err.clear();
+    int st = check_plan(plan);
+    if (st != BF_OK) return st;
+    if (!rf || !out) return fail(BF_ERR_NULL, "rf and out must be non-NULL");
+    if ((st = check_c(c)) != BF_OK) return st;
+    return plan->frames[0]->das_fused(rf, out, c, (hipStream_t)stream);
 }
 
 int bf_das_noalloc(bf_plan plan, const void *e, float *out, double c, void *stream)

@@ -12,7 +12,9 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 // Element type of decoded data.  ET_CF32 is complex FP32 (re, im) pairs of IQ
 // plans; the DAS kernels then accumulate complex sums.
-enum EType { ET_F32 = 0, ET_BF16 = 1, ET_I32 = 2, ET_CF32 = 3 };
+// ET_RF16: the kernel reads int16 RF channel data and decodes each staged tap
+// itself (decode fused into DAS); the rest of the kernel sees FP32 samples.
+enum EType { ET_F32 = 0, ET_BF16 = 1, ET_I32 = 2, ET_CF32 = 3, ET_RF16 = 4 };
 enum Interp { IN_NEAREST = 0, IN_LINEAR = 1, IN_CUBIC = 2 };
 
 // ---------------------------------------------------------------------------
@@ -80,6 +82,8 @@ struct DasArgs {
     double div_f;           // HERCULES diverging wave: source depth f > 0 (0: plane wave)
     float zf;               // VLS: depth of the virtual line sources
     const float2 *tx_sc;    // TPW: [n_tx] (sin theta, cos theta - 1)
+    const float *hf;        // ET_RF16: H[k][i] at hf[k * hf_ld + i] (+-1 as FP32)
+    int hf_ld;
 };
 
 // Modes: 0 FORCES (2D), 1 HERCULES (3D), 2 TPW and 3 VLS (row-column volumes:

@@ -174,6 +174,10 @@ static hipError_t launch_lds_et(const DasArgs &a, const LdsCfg &c, int et, int i
     }
 }
 
+// Decode fused into DAS: FORCES planes from int16 RF (a.e) and the FP32 H
+// table (a.hf); the same LDS kernel with the decode in its staging.
+hipError_t launch_das_lds_fused(const DasArgs &a, const LdsCfg &c, int ip, hipStream_t s);
+
 size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard, int adj, int mode)
 {
     const bool stage = adj == 0 || (adj & 1);     // data windows staged
@@ -183,6 +187,14 @@ size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard, int ad
            (mode == MODE_HERCULES ? (size_t)HANN_TAB_PAD * 8 : 0) +
            (stage ? (2 * (size_t)nb * lmax + guard) * qs * 16 : 0) +
            ((adj & 2) ? 2 * (size_t)nb * (lmax + 3) * 8 + 16 * 4 : 0);
+}
+
+hipError_t launch_das_lds_fused(const DasArgs &a, const LdsCfg &c, int ip, hipStream_t s)
+{
+    const size_t shm = lds_bytes(a.n_tx, a.n_ch, c.nb, c.lmax, 1, c.guard, 0, MODE_FORCES);
+    const hipError_t err = launch_lds_ip<MODE_FORCES, ET_RF16>(a, c, ip, shm, s);
+    if (err != hipSuccess || a.groups <= 1) return err;
+    return launch_sum_groups(a, s);
 }
 
 hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, int ip,

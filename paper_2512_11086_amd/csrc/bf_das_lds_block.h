@@ -42,6 +42,12 @@
 // coefficients of the real and of the imaginary part (32 bytes per interval),
 // and each term is rotated by its carrier phase before the complex
 // accumulation.
+//
+// Decode fused into DAS (ET_RF16, FORCES planes): the kernel reads the int16
+// RF channel data and forms each staged tap of decoded trace (i, j) as
+// sum_k H[k][i] rf[k][j][n] (Sec. VII-E) while staging; the sums of at most
+// 256 products of +-1 and int16 values are exact in FP32, so the windows, and
+// the image, are those of decoding first and beamforming the decoded data.
 #pragma once
 
 #include "bf_common.h"
@@ -61,13 +67,15 @@ constexpr int HANN_TAB_PAD = HANN_N + 2;   // table entries reserved in LDS (flo
 // overflow) whenever it is used.  Staging lanes (and the RF gradient's flush)
 // fetch sw and off of their slot with a lane permute; the terms take the
 // column from the read-only table and the negated window start from a
-// per-batch LDS array (store_w0).
+// per-batch LDS array (store_w0).  ti: the slot's transmit (the fused decode
+// reads H[.][ti]).
 constexpr int NO_DATA = -(1 << 29);
 struct TraceDesc {
     int w0;
     float xi;
     int sw;
     int off;
+    int ti;
 };
 
 // Uniform description of one batch (lane_row: per lane, see Iter).
@@ -476,6 +484,7 @@ __device__ inline TraceDesc trace_desc(const DasArgs &a, const LdsCfg &c, const 
         slot_trace<MODE>(d, lane, &i, &j, &pad);
         if (j >= 0) {
             t.xi = s_tx[i];
+            t.ti = i;
             if constexpr (MODE == MODE_HERCULES)
                 t.w0 = window_start_hercules(b, t.xi, s_rx[j]);
             else if constexpr (FOLD)
@@ -509,6 +518,9 @@ __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const Trace
         const int src = (e & 63) << 2;
         const int w0 = __builtin_amdgcn_ds_bpermute(src, td.sw);
         const int off = __builtin_amdgcn_ds_bpermute(src, td.off);
+        // (the fused decode's transmit of slot e; every lane is active here, as
+        // a permute must read its source lane while that lane is active)
+        const int ti = ET == ET_RF16 ? __builtin_amdgcn_ds_bpermute(src, td.ti) : 0;
         float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
         float p4 = 0.f, p5 = 0.f, p6 = 0.f, p7 = 0.f;
         if (on && w0 != NO_DATA) {
@@ -517,7 +529,30 @@ __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const Trace
             const void *tn = trace_ptr<ET>(a.e, off + m, 1);
             const unsigned S = (unsigned)a.S;
             const bool inside = w0 >= 1 && w0 + c.lmax + 1 < a.S;
-            if constexpr (ET == ET_CF32) {
+            if constexpr (ET == ET_RF16) {
+                // decode fused into staging: tap n + u (u = -1 .. 2) of decoded
+                // trace (ti, j) is sum_k H[k][ti] rf[k][j][n + u]; sample n of
+                // transmit k's trace of row j is element base + k n_ch S
+                // (base: off + m less ti's traces; all offsets < 2^31)
+                const int kstride = a.n_ch * a.S;
+                const int base = off + m - ti * kstride;
+                const gptr<int16_t> r = as_global(static_cast<const int16_t *>(a.e));
+                const gptr<float> hcol = as_global(a.hf) + ti;
+                const unsigned S = (unsigned)a.S;
+                const bool t0 = inside || (unsigned)(n - 1) < S, t1 = inside || (unsigned)n < S;
+                const bool t2 = inside || (unsigned)(n + 1) < S, t3 = inside || (unsigned)(n + 2) < S;
+                // (a transmit index outside the plan reads nothing: a wrong
+                // image, never an access outside rf)
+                const int nk = (unsigned)ti < (unsigned)a.n_tx ? a.n_tx : 0;
+                for (int k = 0; k < nk; ++k) {
+                    const int idx = base + k * kstride;
+                    const float hk = hcol[k * a.hf_ld];
+                    p0 = fmaf(hk, t0 ? (float)r[idx - 1] : 0.f, p0);
+                    p1 = fmaf(hk, t1 ? (float)r[idx] : 0.f, p1);
+                    p2 = fmaf(hk, t2 ? (float)r[idx + 1] : 0.f, p2);
+                    p3 = fmaf(hk, t3 ? (float)r[idx + 2] : 0.f, p3);
+                }
+            } else if constexpr (ET == ET_CF32) {
                 // (re, im) of taps n-1 .. n+2: 32 contiguous bytes
                 const float2 z = make_float2(0.f, 0.f);
                 float2 t0, t1, t2, t3;

@@ -62,6 +62,8 @@ struct Frame {
     int decode(const int16_t *rf, void *e, hipStream_t s) const;
     // part: partial images of a channel-split launch (nullptr: the plan's own)
     int das(const void *e, float *out, double c, hipStream_t s, float *part = nullptr) const;
+    // decode fused into DAS (FORCES planes with real data, LDS path): rf int16
+    int das_fused(const int16_t *rf, float *out, double c, hipStream_t s) const;
     DasArgs at_frame(const DasArgs &a, int f0) const;
     int das_frames(const void *e, int nf, float *out, double c, hipStream_t s) const;
     int das_adjoint(const void *e, const float *grad_out, double c, float *grad_e, float *grad_c,
@@ -73,6 +75,7 @@ struct Batch;   // persistent batched path state (bf_batch.hip)
 hipError_t launch_das(const DasArgs &a, int mode, int et, int ip, hipStream_t s);
 hipError_t launch_das_lds(const DasArgs &a, const LdsCfg &c, int mode, int et, int ip,
                           hipStream_t s);
+hipError_t launch_das_lds_fused(const DasArgs &a, const LdsCfg &c, int ip, hipStream_t s);
 size_t lds_bytes(int n_tx, int n_ch, int nb, int lmax, int qs, int guard, int adj, int mode);
 hipError_t launch_das_lds_adjoint(const DasArgs &a, const LdsCfg &c, int mode, int ip,
                                   float *grad_c, hipStream_t s, int n_frames = 1);

@@ -46,6 +46,8 @@ def test_plan_rejects_host_tensors(no_lib):
     with pytest.raises(ValueError, match="CUDA"):
         p.decode(rf)
     with pytest.raises(ValueError, match="CUDA"):
+        p.das_fused(rf)
+    with pytest.raises(ValueError, match="CUDA"):
         p.das(e)
     with pytest.raises(ValueError, match="CUDA"):
         p.das_adjoint(e, g)

@@ -805,6 +805,9 @@ def main():
                     help="only run the short kernel sequence used for counter collection")
     ap.add_argument("--plane", action="store_true",
                     help="only run the short FORCES-plane sequence used for profiles")
+    ap.add_argument("--fused", action="store_true",
+                    help="only time decode, DAS and the fused decode + DAS on the FORCES "
+                         "planes of workloads 0 and 3 (the decode_share object)")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write the DAS traffic summary from the two --traffic counter runs")
     args = ap.parse_args()
@@ -816,6 +819,12 @@ def main():
         return
     if args.plane:
         plane_run()
+        return
+    if args.fused:
+        import torch
+        import paper_2512_11086_amd as bfm
+        import synth
+        print(json.dumps({"decode_share": decode_share(torch, bfm, synth, reps=5)}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU; multi-GPU runs are not part of this build "

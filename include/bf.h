@@ -258,8 +258,9 @@ int bf_das_noalloc(bf_plan plan, const void *e, float *out, double c, void *stre
  * kernel; decode Sec. VII-E, DAS Eq. 1): FORCES planes only.  Each staged tap
  * of decoded trace (i, j) is formed from the RF as sum_k H[k][i] rf[k][j][n]
  * inside the LDS DAS kernel, so no decoded data is written or read; the sums
- * are exact in FP32, and out equals bf_decode (BF_E_F32) followed by bf_das
- * with the same plan, bit for bit.  rf: device int16 [n_tx][n_ch][n_samples];
+ * are exact in FP32, and out equals bf_decode followed by bf_das bit for bit
+ * when the plan's e_type is BF_E_F32 or BF_E_I32 (exact decoded values; a
+ * BF_E_BF16 plan's bf_decode rounds, the fused taps do not).  rf: device int16 [n_tx][n_ch][n_samples];
  * out: device f32 [Ny][Nx][Nz], overwritten; c as bf_das.  The decode is
  * repeated for every workgroup box that stages a window, so on the
  * workloads measured here this is slower than the two calls (the bench's

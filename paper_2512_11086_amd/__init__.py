@@ -212,7 +212,8 @@ class Plan:
     def das_fused(self, rf, c: float | None = None, out=None, stream=None):
         """Decode fused into DAS (bf_das_fused, FORCES planes): the image of
         the int16 RF ``rf`` (n_tx, n_ch, S) in one kernel, equal bit for bit to
-        ``das(decode(rf))`` with an FP32 decoded-data plan."""
+        ``das(decode(rf))`` when the plan decodes to exact values (f32 or i32;
+        a bf16 plan's decode rounds, the fused taps do not)."""
         torch = _torch()
         self._check_rf(rf)
         if out is None:

@@ -758,12 +758,6 @@ def n4_workloads(torch, bfm, synth, reps: int = 6):
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     xreps = 2 * reps          # (about a millisecond per pass)
-    a.record(stream)
-    for _ in range(xreps):
-        bp.graph_launch(rf_d, outs)
-    b.record(stream)
-    torch.cuda.synchronize()
-    res["cross_plane_graph_ms"] = round(a.elapsed_time(b) / xreps, 3)
     # the same pair as plain per-frame calls (decode + DAS of each plane)
     plans = [bfm.Plan(d, H) for d, H in zip(descs, Hs)]
     es = [p.decode(r) for p, r in zip(plans, rf_d)]
@@ -774,14 +768,24 @@ def n4_workloads(torch, bfm, synth, reps: int = 6):
             p.decode(r, out=e)
             p.das(e, out=o)
 
+    def graph():
+        bp.graph_launch(rf_d, outs)
+
     per_frame()
     torch.cuda.synchronize()
-    a.record(stream)
-    for _ in range(xreps):
-        per_frame()
-    b.record(stream)
-    torch.cuda.synchronize()
-    res["cross_plane_per_frame_ms"] = round(a.elapsed_time(b) / xreps, 3)
+    # the two measured twice, alternating (the first pass after the other
+    # workloads runs at a different clock), the faster pass of each reported
+    times = {"graph": [], "per_frame": []}
+    for _ in range(2):
+        for name, fn in (("graph", graph), ("per_frame", per_frame)):
+            a.record(stream)
+            for _ in range(xreps):
+                fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            times[name].append(a.elapsed_time(b) / xreps)
+    res["cross_plane_graph_ms"] = round(min(times["graph"]), 3)
+    res["cross_plane_per_frame_ms"] = round(min(times["per_frame"]), 3)
     res["cross_plane"] = ("FORCES x-z (columns) + y-z (rows) planes, 256x256 each, 128 tx x 128 ch "
                           "x 2048: one graph of the batched path vs per-frame calls")
     return res

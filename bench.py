@@ -419,7 +419,9 @@ def batched_comparison(torch, bfm, stream4, reps: int):
     """64-frame uFORCES/uHERCULES stream: plain per-frame launches vs one
     persistent launch per kernel class vs the same captured in a hipGraph.
     The per-frame loop is also timed as its decode launches alone and its
-    DAS launches alone (the decode share of the stream)."""
+    DAS launches alone (the decode share of the stream).  Per-frame and graph
+    are timed twice, the second time after the others, and the faster pass
+    of each is reported."""
     descs, Hs, rfs = stream4
     dev = torch.device("cuda:0")
     rf_d = [torch.from_numpy(r).to(dev) for r in rfs]
@@ -459,6 +461,10 @@ def batched_comparison(torch, bfm, stream4, reps: int):
     ms_das = timed(das_only)
     ms_ps = timed(lambda: bp.run(rf_d, outs_b))
     ms_gr = timed(lambda: bp.graph_launch(rf_d, outs_g))
+    # a second, alternated pass of the two paths the speedup compares (the
+    # clock differs between the first and later passes); the faster of each
+    ms_pf = min(ms_pf, timed(per_frame))
+    ms_gr = min(ms_gr, timed(lambda: bp.graph_launch(rf_d, outs_g)))
     # the same stream with tiles autotuned per problem-shape class (no cache:
     # every class is timed on the device)
     t = time.perf_counter()

@@ -515,7 +515,10 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg, int adj, const int *bw_adj
     // which puts it up to one sample lower: one more quad, and one more guard
     // entry (plus one for the rounding of the folded sums).
     const int fold = (sep && adj == 0 && !p.iq && p.interp != BF_INTERP_NEAREST) ? 1 : 0;
-    const int lmax = (int)ceil(a.k * spread) + 5 + fold;
+    // (real data is staged in pairs of quads: lmax even)
+    const bool pairs = stage_pairs(p.iq != 0);
+    int lmax = (int)ceil(a.k * spread) + 5 + fold;
+    if (pairs) lmax += lmax & 1;
     // The terms read without an index clamp: a lane outside its receive
     // aperture (weight 0) may reach past its window by at most the receive
     // path's extra lateral slope, (1 - srx) times the box's receive-lateral
@@ -528,14 +531,12 @@ bool Frame::lds_config(const DasArgs &a, LdsCfg *cfg, int adj, const int *bw_adj
     int nbb = std::max(nb - nb % unit, unit);
     const size_t lds_cap = lds_cap_bytes();
     const int nwaves = nthr / 64;
-    // staging rounds per thread: the batch's quads dealt over the workgroup's
-    // threads; the kernels unroll 2 rounds (3 with two points per lane, for
-    // the row-column modes and for the forward FORCES plane kernel on real
-    // data, 4 for FORCES planes with two points per lane)
-    const int max_rounds = (p.mode == BF_FORCES_2D && zp == 2) ? 4
-                           : (zp == 2 || p.mode == BF_TPW_3D || p.mode == BF_VLS_3D ||
-                              (p.mode == BF_FORCES_2D && adj == 0 && !p.iq)) ? 3 : 2;
-    auto rounds = [&](int n) { return (n * lmax + 64 * nwaves - 1) / (64 * nwaves); };
+    // staging rounds per thread: the batch's quads (real data: pairs of
+    // quads) dealt over the workgroup's threads, within the rounds the
+    // kernels unroll
+    const int max_rounds = stage_rounds(p.mode, p.iq != 0);
+    const int per_trace = pairs ? lmax / 2 : lmax;
+    auto rounds = [&](int n) { return (n * per_trace + 64 * nwaves - 1) / (64 * nwaves); };
     const int qs = p.iq ? 2 : 1;
     const bool staged = adj == 0 || (adj & 1);    // the RF gradient alone reads no data
     while (nbb >= unit && ((staged && rounds(nbb) > max_rounds) ||

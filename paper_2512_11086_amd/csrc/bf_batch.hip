@@ -221,6 +221,7 @@ static int build_batch(bf_plan plan)
             fi.channel_groups = G;
             fi.das_items = (int64_t)nblk * G;
         }
+        if (c.lmax & 1) return fail(BF_ERR_STATE, "frame %d: odd LDS window length", f);
         fdas[f].a = a;
         fdas[f].c = c;
         // decode classes

@@ -91,6 +91,17 @@ struct DasArgs {
 // and a receive excess path; HERCULES has one radial receive path.
 constexpr int MODE_FORCES = 0, MODE_HERCULES = 1, MODE_TPW = 2, MODE_VLS = 3;
 
+// Staging of a batch's windows by the LDS kernels: the nb * lmax coefficient
+// quads are dealt to the workgroup's threads in rounds.  With real data a
+// thread stages two adjacent quads of one window per round (five taps give
+// both, and lmax is even); with IQ data one.  stage_rounds is the number of
+// rounds the kernels unroll, and the host keeps every batch within it.
+__host__ __device__ constexpr bool stage_pairs(bool iq) { return !iq; }
+__host__ __device__ constexpr int stage_rounds(int mode, bool iq)
+{
+    return iq && (mode == MODE_TPW || mode == MODE_VLS) ? 3 : 2;
+}
+
 // Hann weight table: W(u) of Eq. 3 sampled at u^2 = k / (4 HANN_N), stored as
 // (W_k, W_{k+1} - W_k) for linear interpolation in u^2 (max error 1.2e-7);
 // entry HANN_N is (0, 0), so every u^2 >= 1/4 reads weight 0.

@@ -46,6 +46,7 @@ static hipError_t launch_adj_lds5(const DasArgs &a, const LdsCfg &c, int nf, siz
 {
     const int nthr = 64 * c.bwx * c.bwy * c.bwz;
     dim3 grid(xcd_slab_grid(c), a.groups, nf);
+    if (c.lmax & 1) return hipErrorInvalidValue;        // real data: pairs of quads
     const void *fn = reinterpret_cast<const void *>(&das_lds_adj_kernel<MODE, IP, ZP, ADJ, STACK>);
     hipError_t e = allow_lds(fn, shm);
     if (e != hipSuccess) return e;

@@ -135,6 +135,7 @@ static hipError_t launch_lds4(const DasArgs &a, const LdsCfg &c, size_t shm, hip
 {
     const int nthr = 64 * c.bwx * c.bwy * c.bwz;
     dim3 grid(xcd_slab_grid(c), a.groups);
+    if (stage_pairs(ET == ET_CF32) && (c.lmax & 1)) return hipErrorInvalidValue;   // pairs of quads
     hipError_t e = allow_lds(reinterpret_cast<const void *>(&das_lds_kernel<MODE, ET, IP, ZP>), shm);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((das_lds_kernel<MODE, ET, IP, ZP>), grid, dim3(nthr), shm, s, a, c);

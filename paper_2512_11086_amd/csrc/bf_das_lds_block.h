@@ -429,39 +429,33 @@ __device__ inline void slot_trace(const BatchDesc &d, int e, int *i, int *j, boo
     }
 }
 
-// Staging rounds per thread per batch (the host keeps nb * lmax within
-// QM * 64 * wavefronts): 4 for FORCES planes with two points per lane (8
-// wavefronts stage the windows of a 16-wavefront box), 3 for HERCULES with
-// two points and the row-column modes (longer windows) and for the forward
-// FORCES plane kernel on real data with one point per lane (its default
-// 16-trace batch of ~130-quad windows needs three; with two the host trimmed
-// the batch to 12 traces: 0.151 against 0.146 ms on the 256 x 256 plane),
-// else 2.
-template <int MODE, int ZP, int ADJ, int ET> struct StageRounds {
-    static constexpr int value = (MODE == MODE_FORCES && ZP == 2) ? 4
-                                 : (ZP == 2 || MODE == MODE_TPW || MODE == MODE_VLS ||
-                                    (MODE == MODE_FORCES && ADJ == 0 && ET != ET_CF32)) ? 3 : 2;
-};
-
-// Staging map: the nb * lmax quads of a batch are numbered trace-major and
-// dealt to the workgroup's threads in order (round q, wavefront, lane), so no
-// lane idles on a short window and consecutive lanes read consecutive samples
-// of one trace.  Each lane computes the window start of its own trace.
+// Staging map: the quads of a batch -- with real data the nb * lmax / 2
+// pairs of adjacent quads (lmax is even), with IQ data the nb * lmax quads --
+// are numbered trace-major and dealt to the workgroup's threads in order
+// (round q, wavefront, lane), so no lane idles on a short window and
+// consecutive lanes read consecutive samples of one trace.  A pair costs one
+// slot's index arithmetic, lane permutes and bounds checks, and five loads
+// instead of eight: on the FORCES plane the staging had issued about as many
+// VALU instructions as the terms.  Each lane computes the window start of its
+// own trace.
 template <int QM>
 struct Staged {
-    float p[QM][8];    // taps n-1 .. n+2 (IQ: (re, im) of each)
+    float p[QM][8];    // taps n-1 .. n+3 (IQ: n-1 .. n+2, (re, im) of each)
 };
 
-// Slot e and quad m handled by this lane in staging round q; false if none.
-// (g + 1/2) / lmax is at least 1 / (2 lmax) away from an integer, far more
-// than the FP32 rounding of the product for g < 2^16.
+// Slot e and first quad m handled by this lane in staging round q; false if
+// none.  PR: pairs, m even.  (g + 1/2) / lmax, and (2g + 1) / lmax for
+// pairs, are at least 1 / (2 lmax) away from an integer, far more than the
+// FP32 rounding of the product for g < 2^16.
+template <bool PR>
 __device__ inline bool stage_slot(const LdsCfg &c, int q, int wave, int lane, int nwaves, int *e,
                                   int *m)
 {
     const int g = (q * nwaves + wave) * 64 + lane;
-    const int ee = (int)(((float)g + 0.5f) * c.inv_lmax);
+    const int g2 = PR ? 2 * g : g;
+    const int ee = (int)(((float)g2 + (PR ? 1.f : 0.5f)) * c.inv_lmax);
     *e = ee;
-    *m = g - ee * c.lmax;
+    *m = g2 - ee * c.lmax;
     return ee < c.nb;
 }
 
@@ -505,15 +499,17 @@ __device__ inline TraceDesc trace_desc(const DasArgs &a, const LdsCfg &c, const 
     return t;
 }
 
-// Issue the global loads of a batch's windows (taps n-1..n+2 of every quad).
+// Issue the global loads of a batch's windows (taps n-1 .. n+2 of every quad;
+// real data: n-1 .. n+3 of every pair of quads n, n+1).
 template <int ET, int QM>
 __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const TraceDesc &td,
                                   Staged<QM> &st, int wave, int lane, int nwaves)
 {
+    constexpr bool PR = stage_pairs(ET == ET_CF32);
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
         int e, m;
-        const bool on = stage_slot(c, q, wave, lane, nwaves, &e, &m);
+        const bool on = stage_slot<PR>(c, q, wave, lane, nwaves, &e, &m);
         // window start and data offset of slot e, from lane e
         const int src = (e & 63) << 2;
         const int w0 = __builtin_amdgcn_ds_bpermute(src, td.sw);
@@ -528,6 +524,7 @@ __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const Trace
             // sample n of the trace: element off + m (32-bit, see TraceDesc)
             const void *tn = trace_ptr<ET>(a.e, off + m, 1);
             const unsigned S = (unsigned)a.S;
+            // (the last tap of the window, of its last quad or pair, is w0 + lmax + 1)
             const bool inside = w0 >= 1 && w0 + c.lmax + 1 < a.S;
             if constexpr (ET == ET_RF16) {
                 // decode fused into staging: tap n + u (u = -1 .. 2) of decoded
@@ -541,6 +538,7 @@ __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const Trace
                 const unsigned S = (unsigned)a.S;
                 const bool t0 = inside || (unsigned)(n - 1) < S, t1 = inside || (unsigned)n < S;
                 const bool t2 = inside || (unsigned)(n + 1) < S, t3 = inside || (unsigned)(n + 2) < S;
+                const bool t4 = inside || (unsigned)(n + 3) < S;
                 // (a transmit index outside the plan reads nothing: a wrong
                 // image, never an access outside rf)
                 const int nk = (unsigned)ti < (unsigned)a.n_tx ? a.n_tx : 0;
@@ -551,6 +549,7 @@ __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const Trace
                     p1 = fmaf(hk, t1 ? (float)r[idx] : 0.f, p1);
                     p2 = fmaf(hk, t2 ? (float)r[idx + 1] : 0.f, p2);
                     p3 = fmaf(hk, t3 ? (float)r[idx + 2] : 0.f, p3);
+                    p4 = fmaf(hk, t4 ? (float)r[idx + 3] : 0.f, p4);
                 }
             } else if constexpr (ET == ET_CF32) {
                 // (re, im) of taps n-1 .. n+2: 32 contiguous bytes
@@ -569,22 +568,24 @@ __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const Trace
                 p0 = t0.x; p1 = t1.x; p2 = t2.x; p3 = t3.x;
                 p4 = t0.y; p5 = t1.y; p6 = t2.y; p7 = t3.y;
             } else if (inside) {
-                // whole window inside the record (the usual case): one
-                // 16-byte load of the four taps (4-byte aligned)
+                // whole window inside the record (the usual case): the five
+                // taps from 20 contiguous bytes (4-byte aligned)
                 if constexpr (ET == ET_F32) {
                     const gptr<float> v = as_global(static_cast<const float *>(tn) - 1);
-                    p0 = v[0]; p1 = v[1]; p2 = v[2]; p3 = v[3];
+                    p0 = v[0]; p1 = v[1]; p2 = v[2]; p3 = v[3]; p4 = v[4];
                 } else {
                     p0 = load_e<ET>(tn, -1);
                     p1 = load_e<ET>(tn, 0);
                     p2 = load_e<ET>(tn, 1);
                     p3 = load_e<ET>(tn, 2);
+                    p4 = load_e<ET>(tn, 3);
                 }
             } else {
                 p0 = ((unsigned)(n - 1) < S) ? load_e<ET>(tn, -1) : 0.f;
                 p1 = ((unsigned)n < S) ? load_e<ET>(tn, 0) : 0.f;
                 p2 = ((unsigned)(n + 1) < S) ? load_e<ET>(tn, 1) : 0.f;
                 p3 = ((unsigned)(n + 2) < S) ? load_e<ET>(tn, 2) : 0.f;
+                p4 = ((unsigned)(n + 3) < S) ? load_e<ET>(tn, 3) : 0.f;
             }
         }
         st.p[q][0] = p0;
@@ -649,15 +650,17 @@ template <int IP, int QS, int QM, bool DQ>
 __device__ inline void stage_store(const LdsCfg &c, const Staged<QM> &st, float4 *quads, int wave,
                                    int lane, int nwaves)
 {
+    constexpr bool PR = stage_pairs(QS == 2);
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
         int e, m;
-        if (stage_slot(c, q, wave, lane, nwaves, &e, &m)) {
+        if (stage_slot<PR>(c, q, wave, lane, nwaves, &e, &m)) {
             const float *t = st.p[q];
-            quads[(e * c.lmax + m) * QS] = DQ ? coef_dquad<IP>(t[0], t[1], t[2], t[3])
-                                              : coef_quad<IP>(t[0], t[1], t[2], t[3]);
-            if constexpr (QS == 2)
-                quads[(e * c.lmax + m) * 2 + 1] = coef_quad<IP>(t[4], t[5], t[6], t[7]);
+            float4 *dst = quads + (e * c.lmax + m) * QS;
+            dst[0] = DQ ? coef_dquad<IP>(t[0], t[1], t[2], t[3]) : coef_quad<IP>(t[0], t[1], t[2], t[3]);
+            if constexpr (PR)         // quad m + 1 < lmax (m even, lmax even)
+                dst[1] = DQ ? coef_dquad<IP>(t[1], t[2], t[3], t[4]) : coef_quad<IP>(t[1], t[2], t[3], t[4]);
+            if constexpr (QS == 2) dst[1] = coef_quad<IP>(t[4], t[5], t[6], t[7]);
         }
     }
 }
@@ -824,7 +827,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     constexpr bool STAGE = ADJ == 0 || GC;       // data windows needed
     static_assert(ZP == 1 || ((MODE == MODE_HERCULES || MODE == MODE_FORCES) && ET != ET_CF32),
                   "two points per lane: HERCULES and FORCES with real data");
-    constexpr int QM = StageRounds<MODE, ZP, ADJ, ET>::value;
+    constexpr int QM = stage_rounds(MODE, ET == ET_CF32);
     const int nthr = blockDim.x;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;

@@ -91,8 +91,9 @@ def _position_errors(desc, tile, bw, boxes, lmax):
 def test_folded_position_rounding_workload3_plane():
     desc = synth.configs.workload(3)
     # default plane box: 32 x 2 lane tiles, 2 x 1 x 8 wavefronts (64 x 16 points);
-    # lmax of that box with the fold (as tests/test_window_bounds.py derives it)
-    e_old, e_new = _position_errors(desc, (5, 0, 1), (2, 1, 8), [(1, 3), (2, 10), (3, 15)], 127)
+    # lmax of that box with the fold (as tests/test_window_bounds.py derives it:
+    # 127), rounded up to even as real data is staged in pairs of quads
+    e_old, e_new = _position_errors(desc, (5, 0, 1), (2, 1, 8), [(1, 3), (2, 10), (3, 15)], 128)
     rms_old, rms_new = np.sqrt((e_old ** 2).mean()), np.sqrt((e_new ** 2).mean())
     assert len(e_new) > 10 ** 6
     assert rms_new <= 2.0 * rms_old and rms_new < 5e-6, (rms_old, rms_new)

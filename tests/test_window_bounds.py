@@ -7,7 +7,9 @@ before the windows, indices past a window read the next window or the zeroed
 guard.  This re-derives, in FP64, the kernels' window start (the box's lowest
 path, floored 2 samples down), the staged length lmax (Frame::lds_config: the
 delay spread of active points plus 5) and the guard ((1 - srx) times the
-receive-lateral extent, plus 3), and checks them on sampled boxes of the
+receive-lateral extent, plus 3; real data, staged in pairs of quads, rounds
+lmax up to even, which only widens the windows, so the checks take the
+unrounded length), and checks them on sampled boxes of the
 workload geometries and of small grids (tilted, through the array plane,
 diverging, VLS focal lines, several F#).  Active points (apodization > 0)
 must also read inside their own window: index at most lmax - 1 (the quad

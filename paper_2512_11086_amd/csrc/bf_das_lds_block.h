@@ -441,7 +441,18 @@ __device__ inline void slot_trace(const BatchDesc &d, int e, int *i, int *j, boo
 template <int QM>
 struct Staged {
     float p[QM][8];    // taps n-1 .. n+3 (IQ: n-1 .. n+2, (re, im) of each)
+    int dst[QM];       // first quad of the slot in the batch buffer, -1: none
 };
+
+// Whether staging round q holds any slot of the batch (uniform: the
+// workgroup skips rounds past the last one, e.g. the second of the FORCES
+// plane's 16 windows of 128 quads, which its 1024 threads stage in one).
+template <bool PR>
+__device__ inline bool stage_round_live(const LdsCfg &c, int q, int nwaves)
+{
+    const int slots = PR ? (c.nb * c.lmax) >> 1 : c.nb * c.lmax;
+    return q == 0 || q * nwaves * 64 < slots;
+}
 
 // Slot e and first quad m handled by this lane in staging round q; false if
 // none.  PR: pairs, m even.  (g + 1/2) / lmax, and (2g + 1) / lmax for
@@ -508,8 +519,10 @@ __device__ inline void stage_load(const DasArgs &a, const LdsCfg &c, const Trace
     constexpr bool PR = stage_pairs(ET == ET_CF32);
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
+        if (!stage_round_live<PR>(c, q, nwaves)) break;
         int e, m;
         const bool on = stage_slot<PR>(c, q, wave, lane, nwaves, &e, &m);
+        st.dst[q] = on ? e * c.lmax + m : -1;
         // window start and data offset of slot e, from lane e
         const int src = (e & 63) << 2;
         const int w0 = __builtin_amdgcn_ds_bpermute(src, td.sw);
@@ -653,10 +666,10 @@ __device__ inline void stage_store(const LdsCfg &c, const Staged<QM> &st, float4
     constexpr bool PR = stage_pairs(QS == 2);
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
-        int e, m;
-        if (stage_slot<PR>(c, q, wave, lane, nwaves, &e, &m)) {
+        if (!stage_round_live<PR>(c, q, nwaves)) break;
+        if (st.dst[q] >= 0) {
             const float *t = st.p[q];
-            float4 *dst = quads + (e * c.lmax + m) * QS;
+            float4 *dst = quads + st.dst[q] * QS;
             dst[0] = DQ ? coef_dquad<IP>(t[0], t[1], t[2], t[3]) : coef_quad<IP>(t[0], t[1], t[2], t[3]);
             if constexpr (PR)         // quad m + 1 < lmax (m even, lmax even)
                 dst[1] = DQ ? coef_dquad<IP>(t[1], t[2], t[3], t[4]) : coef_quad<IP>(t[1], t[2], t[3], t[4]);

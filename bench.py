@@ -101,8 +101,9 @@ def algorithmic_flops(desc, n_act: int, iq: bool = False, adjoint_c: bool = Fals
     by Horner's rule (6; the derivative's quadratic 4).
 
     Per active term: HERCULES (one receive path per term) delay 12 (dx,
-    rho^2, (d/k)^2, sqrt, d/k + z/k, rcp, fma, floor, fract) + apodization 5
-    (the Hann table: scale, floor, fract, interpolating fma); FORCES, TPW and
+    rho^2, (d/k)^2, sqrt, d/k + z/k, rcp, fma, floor, fract) + apodization 4
+    (the Hann table: scale, floor, and one fma from the entry's base and
+    slope); FORCES, TPW and
     VLS separate the path into a transmit part per (point, transmit)
     (FORCES distance to the column 8, TPW x sin + z (cos - 1) 4, VLS signed
     distance to the line 11) and a receive part with its weight per active
@@ -121,7 +122,7 @@ def algorithmic_flops(desc, n_act: int, iq: bool = False, adjoint_c: bool = Fals
     else:
         per_term = 6 + 2
     if mode == "hercules":
-        return n_act * (12 + 5 + per_term) + coef
+        return n_act * (12 + 4 + per_term) + coef
     n_tx = desc["n_tx"]
     n_pts = int(np.prod(desc["dims"]))
     f_tx = {"forces": 8, "tpw": 4, "vls": 11}[mode]

@@ -321,7 +321,10 @@ int Frame::init(const bf_params &src)
     max_blocks = 8 * (max_waves + 8192);
     d_partial = (double *)alloc((size_t)max_blocks * sizeof(double));
     {
-        // Eq. 3 in double precision at u^2 = k / (4 HANN_N), value + slope
+        // Eq. 3 in double precision at u^2 = k / (4 HANN_N): entry k holds the
+        // slope D_k = W_{k+1} - W_k and the base W_k - k D_k (with D_k as
+        // rounded), so that the weight at table coordinate x in [k, k + 1) is
+        // one FMA, base + x D_k
         std::vector<float2> tab(HANN_N + 1);
         std::vector<double> W(HANN_N + 1);
         for (int k = 0; k <= HANN_N; ++k) {
@@ -329,7 +332,10 @@ int Frame::init(const bf_params &src)
             const double cu = cos(M_PI * u);
             W[k] = (k == HANN_N) ? 0.0 : cu * cu;
         }
-        for (int k = 0; k < HANN_N; ++k) tab[k] = make_float2((float)W[k], (float)(W[k + 1] - W[k]));
+        for (int k = 0; k < HANN_N; ++k) {
+            const float d = (float)(W[k + 1] - W[k]);
+            tab[k] = make_float2((float)(W[k] - k * (double)d), d);
+        }
         tab[HANN_N] = make_float2(0.f, 0.f);
         d_hann = (float2 *)alloc(tab.size() * sizeof(float2));
         if (!d_hann) return fail(BF_ERR_HIP, "device allocation of the Hann table failed");

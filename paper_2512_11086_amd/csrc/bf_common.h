@@ -75,7 +75,7 @@ struct DasArgs {
     int groups;             // channel groups (blockIdx.y); > 1 writes partial images
     float *part;            // [groups][ny][nx][nz] partial images when groups > 1
     float *const *out_ref;  // if set, the output pointer is read from here (graph replay)
-    const float2 *hann_tab; // [HANN_N + 1] (value, slope) of W over u^2 in [0, 1/4]
+    const float2 *hann_tab; // [HANN_N + 1] (base, slope) of W over u^2 in [0, 1/4]
     int cx;                 // IQ data: e, out and part hold (re, im) pairs
     float rot;              // IQ: fd / fs, revolutions of carrier phase per sample
     double rot_d;           // the same in FP64 (per-lane phase origin)
@@ -103,7 +103,9 @@ __host__ __device__ constexpr int stage_rounds(int mode, bool iq)
 }
 
 // Hann weight table: W(u) of Eq. 3 sampled at u^2 = k / (4 HANN_N), stored as
-// (W_k, W_{k+1} - W_k) for linear interpolation in u^2 (max error 1.2e-7);
+// (W_k - k D_k, D_k) with D_k = W_{k+1} - W_k, so that linear interpolation
+// in u^2 at table coordinate x = 4 HANN_N u^2 is fma(x, D_k, W_k - k D_k)
+// for k = floor(x) (max error 1.2e-7, plus ~6e-8 for the rounded base);
 // entry HANN_N is (0, 0), so every u^2 >= 1/4 reads weight 0.
 constexpr int HANN_N = 2048;
 
@@ -198,6 +200,19 @@ template <typename T> using cptr = const __attribute__((address_space(4))) T *;
 template <typename T> __device__ inline gptr<T> as_global(const T *p) { return (gptr<T>)p; }
 template <typename T> __device__ inline gptr_mut<T> as_global_mut(T *p) { return (gptr_mut<T>)p; }
 template <typename T> __device__ inline cptr<T> as_const(const T *p) { return (cptr<T>)p; }
+// LDS views: a 32-bit LDS byte address of a shared-memory pointer, and a
+// read through such an address (one DS instruction on the address VGPR)
+template <typename T> using lptr = const __attribute__((address_space(3))) T *;
+__device__ inline unsigned lds_addr(const void *p)
+{
+    return (unsigned)(size_t)(lptr<char>)static_cast<const char *>(p);
+}
+__device__ inline float4 lds_read_f4(unsigned addr)
+{
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const v4f v = *(lptr<v4f>)(size_t)addr;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
 
 // Vector accesses through those views go element by element (the views do
 // not carry the vector types' constructors); the compiler merges them into

@@ -147,9 +147,10 @@ __device__ inline void lane_point(const DasArgs &a, const LdsCfg &c, int bx, int
     *iz = (((bz * c.bwz + wz) << a.lz) + lz) * c.zp + p - c.z_off;
 }
 
+// nref (folded HERCULES reads): fB then holds B - nref in one FP32 rounding.
 template <int MODE>
 __device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, int by, int bz,
-                                     int wave, int lane, int p)
+                                     int wave, int lane, int p, const int *nref = nullptr)
 {
     LaneL L;
     int ix, iy, iz;
@@ -174,7 +175,7 @@ __device__ inline LaneL lane_setup_l(const DasArgs &a, const LdsCfg &c, int bx, 
     const double B = (tx_path(a, px, py, pze) + pze) * a.k - a.t0fs;
     const double fl = floor(B);
     L.nB = (int)fl;
-    L.fB = (float)(B - fl);
+    L.fB = (float)(B - (nref ? (double)*nref : fl));
     L.z = (float)pze;
     L.z2 = L.z * L.z;
     L.zk = (float)(pze / a.k);
@@ -656,6 +657,17 @@ __device__ inline void store_w0(const LdsCfg &c, const TraceDesc &td, int *w, in
     w[lane] = -td.w0;
 }
 
+// The HERCULES forward reads' per-slot value (hercules_term, HF): the LDS
+// byte address of slot `lane`'s window in buffer `quads` less (w0 - nR)
+// quads (modulo 2^32: the terms add floor(s) * 16 back, and the sum is the
+// address of quad floor(s) + nR - w0 of the window).
+__device__ inline void store_w0_addr(const LdsCfg &c, const TraceDesc &td, int *w, const float4 *quads,
+                                     int nR, int wave, int lane)
+{
+    if (wave != 0 || lane >= c.nb) return;
+    w[lane] = (int)(lds_addr(quads + lane * c.lmax) + ((unsigned)(nR - td.w0) << 4));
+}
+
 // Convert the loaded taps to coefficient quads and write them to one LDS
 // buffer.  QS = quads per sample interval (2 for IQ data: real part, then
 // imaginary part).
@@ -779,23 +791,29 @@ __device__ inline void flush_grad_e(const DasArgs &a, const LdsCfg &c, unsigned 
 // samples, k rho^2 / (d + z), is evaluated as rho^2 / (d/k + z/k) with
 // d/k = sqrt(rho^2 / k^2 + (z/k)^2): the scale k is folded into the lane
 // constants (ik2 = 1 / k^2).
-template <int ET, int IP, int ZP, int ADJ>
+// HF (real-data forward reads, cubic or linear): the lanes' fB hold
+// fB + nB - nR for the box's reference sample nR, and neg_w0 carries the
+// LDS byte address of the trace's window less (w0 - nR) quads, so a read's
+// address is floor(s) * 16 plus that value: one shift-add per point.
+template <int ET, int IP, int ZP, int ADJ, bool HF = false>
 __device__ inline void hercules_term(const LaneL (&L)[ZP], const float4 *win, int lmax,
                                      const float2 *hann, float dy2, float ik2, float rot, float xi,
                                      int neg_w0, float2 (&acc)[ZP],   // neg_w0: from LDS
                                      unsigned long long *gwin, const float (&G)[ZP])
 {
+    static_assert(!HF || (ET != ET_CF32 && ADJ == 0 && IP != IN_NEAREST),
+                  "folded reads: real-data forward, cubic or linear");
     const float dx = L[0].x - xi;
     const float rho2 = fmaf(dx, dx, dy2);
 #pragma unroll
     for (int p = 0; p < ZP; ++p) {
         const float dk = __builtin_amdgcn_sqrtf(fmaf(rho2, ik2, L[p].zk2));
         const float s = fmaf(rho2, __builtin_amdgcn_rcpf(dk + L[p].zk), L[p].fB);
-        const int li = add3_vvv(cvt_flr(s), L[p].nB, neg_w0);
+        const int li = HF ? 0 : add3_vvv(cvt_flr(s), L[p].nB, neg_w0);
         // Hann weight from the LDS table; u^2 >= 1/4 lands on the (0, 0) entry
         const float xw = rho2 * L[p].wtab;
         const float2 h = hann[min((unsigned)cvt_flr(xw), (unsigned)HANN_N)];
-        const float w = fmaf(__builtin_amdgcn_fractf(xw), h.y, h.x);
+        const float w = fmaf(xw, h.y, h.x);
         // no clamp: li lies in [-1, lmax + guard) for every lane (its
         // geometry is inside the box); -1 reads the finite LDS word before the
         // windows, and lanes outside their aperture (weight exactly 0) may
@@ -813,6 +831,10 @@ __device__ inline void hercules_term(const LaneL (&L)[ZP], const float4 *win, in
             }
             if constexpr ((ADJ & 2) != 0)   // RF gradient (active lanes lie inside the window)
                 scatter_taps<IP>(gwin, clamp0_i32(li, lmax - 1), G[p] * w, t);
+        } else if constexpr (HF) {
+            const unsigned ad = ((unsigned)cvt_flr(s) << 4) + (unsigned)neg_w0;
+            const float v = eval_quad<IP>(lds_read_f4(ad), t);
+            acc[p].x = fmaf(w, v, acc[p].x);
         } else {
             const float v = eval_quad<IP>(win[li], t);
             acc[p].x = fmaf(w, v, acc[p].x);
@@ -872,6 +894,10 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     // sample choice is an integer decision that extra rounding would move at
     // near ties.
     constexpr bool FOLD = SEP && ADJ == 0 && ET != ET_CF32 && IP != IN_NEAREST;
+    // HERCULES forward reads on real data fold the lane's integer sample nB,
+    // less a box reference nR, into its FP32 position (hercules_term, HF);
+    // nearest reads keep the unsplit position, as above
+    constexpr bool HF = MODE == MODE_HERCULES && ADJ == 0 && ET != ET_CF32 && IP != IN_NEAREST;
     const int hc = FOLD ? c.lmax >> 2 : 0;
     const int ntx4 = (a.n_tx + 3) & ~3, nch4 = (a.n_ch + 3) & ~3;
     float *s_tx = reinterpret_cast<float *>(smem);
@@ -919,9 +945,13 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
     }
     if constexpr (FOLD)    // the terms keep no window starts; an index of -1 reads these zeros
         for (int t = tid; t < 2 * w0_stride; t += nthr) s_w0[t] = 0;
+    // HF: nR = the sample of the two-way path txlo + zmax, near the middle of
+    // the box's delays B (the same integer in every thread), so the lanes'
+    // folded positions B - nR + excess stay near the excess path's magnitude
+    const int nR = HF ? (int)floorf(fmaf(box.txlo + fmaxf(box.zmax, 0.f), box.kf, -box.t0f)) : 0;
     LaneL Lp[ZP];
 #pragma unroll
-    for (int p = 0; p < ZP; ++p) Lp[p] = lane_setup_l<MODE>(a, c, bx, by, bz, wave, lane, p);
+    for (int p = 0; p < ZP; ++p) Lp[p] = lane_setup_l<MODE>(a, c, bx, by, bz, wave, lane, p, HF ? &nR : nullptr);
     const LaneL &L = Lp[0];
     // largest rho^2 bound of the receive aperture over the lane's points
     float thr_l = Lp[0].thr;
@@ -987,7 +1017,10 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
             stage_load<ET, QM>(a, c, td, st, wave, lane, nwaves);
             stage_store<IP, QS, QM, GC>(c, st, q0, wave, lane, nwaves);
         }
-        if constexpr (!FOLD) store_w0(c, td, s_w0, wave, lane);
+        if constexpr (HF)
+            store_w0_addr(c, td, s_w0, q0, nR, wave, lane);
+        else if constexpr (!FOLD)
+            store_w0(c, td, s_w0, wave, lane);
     }
     TraceDesc td_prev = td;            // RF gradient: windows of the previous batch
     __syncthreads();
@@ -1043,7 +1076,7 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                 while (mask) {
                     const int e1 = __builtin_ctzll(mask);
                     mask &= mask - 1;
-                    hercules_term<ET, IP, ZP, ADJ>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2,
+                    hercules_term<ET, IP, ZP, ADJ, HF>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2,
                                               ik2, rot, txcol[e1], wst[e1], acc, accw + e1 * lw, Gv);
                 }
             }
@@ -1052,14 +1085,14 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
                 mask &= mask - 1;
                 const int e2 = __builtin_ctzll(mask);
                 mask &= mask - 1;
-                hercules_term<ET, IP, ZP, ADJ>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
+                hercules_term<ET, IP, ZP, ADJ, HF>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
                                           rot, txcol[e1], wst[e1], acc, accw + e1 * lw, Gv);
-                hercules_term<ET, IP, ZP, ADJ>(Lp, quads + e2 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
+                hercules_term<ET, IP, ZP, ADJ, HF>(Lp, quads + e2 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
                                           rot, txcol[e2], wst[e2], acc, accw + e2 * lw, Gv);
             }
             if (mask) {
                 const int e1 = __builtin_ctzll(mask);
-                hercules_term<ET, IP, ZP, ADJ>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
+                hercules_term<ET, IP, ZP, ADJ, HF>(Lp, quads + e1 * c.lmax * QS, c.lmax, s_hann, dy2, ik2,
                                           rot, txcol[e1], wst[e1], acc, accw + e1 * lw, Gv);
             }
         } else {
@@ -1188,7 +1221,11 @@ __device__ inline void das_block(const DasArgs &a, const LdsCfg &c, int blk, int
 
         if (!nxt.valid) break;
         if constexpr (STAGE) stage_store<IP, QS, QM, GC>(c, st, ((bi + 1) & 1) ? q1 : q0, wave, lane, nwaves);
-        if constexpr (!FOLD) store_w0(c, td_n, s_w0 + ((bi + 1) & 1) * w0_stride, wave, lane);
+        if constexpr (HF)
+            store_w0_addr(c, td_n, s_w0 + ((bi + 1) & 1) * w0_stride, ((bi + 1) & 1) ? q1 : q0, nR, wave,
+                          lane);
+        else if constexpr (!FOLD)
+            store_w0(c, td_n, s_w0 + ((bi + 1) & 1) * w0_stride, wave, lane);
         __syncthreads();
         cur = nxt;
         td_prev = td;
@@ -1269,14 +1306,15 @@ __device__ inline int xcd_slab_box(const LdsCfg &c, int b)
 }
 
 // Registers capped for two workgroups per CU: 6 wavefronts per SIMD for
-// HERCULES with two points per lane and the row-column modes (12-wavefront
-// workgroups); FORCES planes 8 with one point per lane (16-wavefront
+// HERCULES and the row-column modes (12-wavefront workgroups; without the
+// cap the IQ volume kernel took 81 VGPRs, one workgroup per CU: 58 ms
+// against 42 ms); FORCES planes 8 with one point per lane (16-wavefront
 // workgroups; without the cap the plane kernel's registers left room for
 // one workgroup per CU: 0.19 ms against 0.15 ms on the 256 x 256 plane of
 // 64 x 64 traces) and 4 with two (8-wavefront workgroups).
 template <int MODE, int ZP> struct WavesPerEu {
     static constexpr int value = MODE == MODE_FORCES ? (ZP == 2 ? 4 : 8)
-                                 : (ZP == 2 || MODE == MODE_TPW || MODE == MODE_VLS) ? 6 : 1;
+                                 : (MODE == MODE_HERCULES || MODE == MODE_TPW || MODE == MODE_VLS) ? 6 : 1;
 };
 
 // Dynamic LDS beyond 64 KiB (gfx950 has 160 KiB per CU) is requested per

@@ -98,3 +98,68 @@ def test_folded_position_rounding_workload3_plane():
     assert len(e_new) > 10 ** 6
     assert rms_new <= 2.0 * rms_old and rms_new < 5e-6, (rms_old, rms_new)
     assert np.abs(e_new).max() < 1e-4, np.abs(e_new).max()
+
+
+def _hercules_position_errors(desc, tile, bw, zp, boxes):
+    """Errors against FP64 of the HERCULES window position (in samples) in the
+    unsplit form, floor(B) + FP32 fma(rho^2, 1/(d/k + z/k), frac(B)), and in
+    the folded form, nR + FP32 fma(rho^2, 1/(d/k + z/k), B - nR), where nR =
+    floor(k (txlo + zmax) - t0 fs) is the box's reference sample (plane
+    transmit: txlo = the box's top depth), over every receive element of the
+    active (point, element) pairs of the sampled boxes."""
+    nx, ny, nz = desc["dims"]
+    org, ax, ay, az, centre = _grid(desc)
+    ne, pitch = desc["n_elem"], desc["pitch"]
+    xs = (np.arange(ne[0]) * pitch[0] - centre[0]).astype(np.float32)
+    ys = (np.arange(ne[1]) * pitch[1] - centre[1]).astype(np.float32)
+    k, t0fs = desc["fs"] / desc["c"], desc["t0"] * desc["fs"]
+    kf, t0f = np.float32(k), np.float32(t0fs)
+    ik2 = np.float32(1.0 / (k * k))
+    f2 = desc["f_number"] ** 2
+    tx, ty, tz = bw[0] << tile[0], bw[1] << tile[1], (bw[2] << tile[2]) * zp
+    e_old, e_new = [], []
+    for bx, by, bz in boxes:
+        i0 = [bx * tx, by * ty, bz * tz]
+        i1 = [min(i0[0] + tx - 1, nx - 1), min(i0[1] + ty - 1, ny - 1), min(i0[2] + tz - 1, nz - 1)]
+        zlo = max(_r32(org[2] + i0[2] * az[2]), np.float32(0))
+        zmax = max(_r32(org[2] + i1[2] * az[2]), np.float32(0))
+        nR = math.floor(_r32(np.float64(_r32(np.float64(zlo) + zmax)) * kf - t0f))    # FMA
+        IX, IY, IZ = np.meshgrid(np.arange(i0[0], i0[0] + tx).clip(0, nx - 1),
+                                 np.arange(i0[1], i0[1] + ty).clip(0, ny - 1),
+                                 np.arange(i0[2], i0[2] + tz).clip(0, nz - 1), indexing="ij")
+        px = (org[0] + IX * ax[0]).ravel()
+        py = (org[1] + IY * ay[1]).ravel()
+        pz = np.maximum((org[2] + IZ * az[2]).ravel(), 1e-7)
+        B = 2 * pz * k - t0fs
+        nB = np.floor(B)
+        fB_old, fB_new = _r32(B - nB), _r32(B - nR)
+        Lx, Ly = _r32(px), _r32(py)
+        zk = _r32(pz / k)
+        zk2 = _r32(zk.astype(np.float64) * zk)
+        for yj in ys:
+            dy = _r32(Ly.astype(np.float64) - yj)
+            dy2 = _r32(dy.astype(np.float64) * dy)
+            dx = _r32(Lx[:, None].astype(np.float64) - xs[None, :])
+            rho2 = _r32(dx.astype(np.float64) * dx + dy2[:, None])                      # FMA
+            dk = _r32(np.sqrt(_r32(rho2.astype(np.float64) * ik2 + zk2[:, None])))       # FMA, sqrt
+            r = _r32(1.0 / _r32(dk.astype(np.float64) + zk[:, None]))
+            s_old = _r32(rho2.astype(np.float64) * r + fB_old[:, None])                  # FMA
+            s_new = _r32(rho2.astype(np.float64) * r + fB_new[:, None])                  # FMA
+            r2 = (px[:, None] - xs[None, :]) ** 2 + (py[:, None] - float(yj)) ** 2
+            exact = B[:, None] + k * (np.sqrt(r2 + pz[:, None] ** 2) - pz[:, None])
+            act = r2 < pz[:, None] ** 2 * 0.25 / f2
+            e_old.append((s_old + nB[:, None] - exact)[act])
+            e_new.append((s_new.astype(np.float64) + nR - exact)[act])
+    return np.concatenate(e_old), np.concatenate(e_new)
+
+
+def test_folded_position_rounding_workload1_volume():
+    desc = synth.configs.workload(1)
+    # default HERCULES box: 8 x 8 lane tiles, 2 x 2 x 3 wavefronts, two depth
+    # points per lane (16 x 16 x 6 points); shallow, middle and deep boxes
+    e_old, e_new = _hercules_position_errors(desc, (3, 3, 0), (2, 2, 3), 2,
+                                             [(3, 4, 2), (4, 3, 20), (2, 5, 40)])
+    rms_old, rms_new = np.sqrt((e_old ** 2).mean()), np.sqrt((e_new ** 2).mean())
+    assert len(e_new) > 10 ** 6
+    assert rms_new <= 1.5 * rms_old and rms_new < 5e-6, (rms_old, rms_new)
+    assert np.abs(e_new).max() < 1e-4, np.abs(e_new).max()

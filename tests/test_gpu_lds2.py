@@ -97,11 +97,15 @@ def test_configurations_agree(torch_mod, tile, block, nb):
     ref = oracle.das(desc, e)
     _, got = _run(torch_mod, desc, H, e.astype(np.float32), tile=tile, block=block, nb=nb)
     assert rel_l2(got, ref) <= TOL_L2, (tile, block, nb)
-    # one point per lane on the same tile: only terms at the very edge of the
-    # aperture (weight ~1e-7) may be visited differently
+    # one point per lane on the same tile: terms at the very edge of the
+    # aperture (weight ~1e-7) may be visited differently, and the read
+    # positions are rounded in FP32 around each box's reference sample, so
+    # two tilings round a point's positions differently (each stays within
+    # TOL_L2 of the oracle; tests/test_fold_precision.py bounds the rounding)
     _, one = _run(torch_mod, desc, H, e.astype(np.float32), variant="lds", tile=tile,
                   block=(4, 4, 1), nb=16)
-    assert rel_l2(got, one) <= 1e-6
+    assert rel_l2(one, ref) <= TOL_L2
+    assert rel_l2(got, one) <= 4e-6
 
 
 @pytest.mark.parametrize("e_type", ["bf16", "i32"])
